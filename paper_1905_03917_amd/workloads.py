@@ -1,0 +1,189 @@
+"""Seeded synthetic inputs shared by the GPU path's tests/benchmark and the CPU oracle.
+
+This module only builds initial fields: a level set (signed distance to the
+interface) and piecewise-constant primitive states per fluid.  It holds none
+of the method's arithmetic; both the oracle and the GPU library turn these
+primitives into cell contents themselves.
+
+Fluid 0 is the fluid where phi < 0, fluid 1 where phi >= 0.  Arrays are
+numpy float64 with x fastest: phi has shape (nz, ny, nx) squeezed to the
+active dimensions, prim has shape (2, D+2, cells) with components
+(rho, u_1..u_D, p).
+
+Workloads (sizes follow the paper's compressible test section, Sec. 4.1-4.2,
+re-posed with stiffened-gas water gamma=4.4, p_inf=6e8 Pa and air gamma=1.4):
+  tube_1d          gas-water shock tube, water at 1e9 Pa | air at 1e5 Pa
+  shock_bubble_2d  planar water shock (1e9 Pa) hitting an air bubble
+  shock_droplet_3d Mach-1.5 air shock hitting a water droplet
+  smooth_2d        Gaussian acoustic pulse in air crossing a flat interface
+  droplet_2d       periodic translation of a water droplet (Sec. 4.2 analogue)
+"""
+from __future__ import annotations
+
+import numpy as np
+
+WATER = (4.4, 6.0e8)
+AIR = (1.4, 0.0)
+
+# Post-shock states used as inputs.  They satisfy the stiffened-gas
+# Rankine-Hugoniot conditions; the oracle tests check that the exact Riemann
+# solver reproduces a single shock between them and the pre-shock states.
+WATER_SHOCK_1E9 = dict(rho=1230.377372836252, u=432.6921608084541, p=1.0e9)
+AIR_SHOCK_M15 = dict(rho=1.8620689655172413, u=259.83731852596816, p=245833.33333333334)
+
+
+def _rng(seed):
+    return np.random.Generator(np.random.PCG64(seed))
+
+
+def _grid(ndim, n):
+    h = 1.0 / n
+    x = (np.arange(n) + 0.5) * h
+    if ndim == 1:
+        return h, (x,)
+    if ndim == 2:
+        Y, X = np.meshgrid(x, x, indexing="ij")
+        return h, (X, Y)
+    Z, Y, X = np.meshgrid(x, x, x, indexing="ij")
+    return h, (X, Y, Z)
+
+
+def _case(ndim, n, bc, eos0, eos1, phi, prim, t_end, name, **extra):
+    h = 1.0 / n
+    d = dict(
+        name=name, ndim=ndim, n=[n if i < ndim else 1 for i in range(3)],
+        lo=[0.0, 0.0, 0.0], h=h, bc=[bc if i < ndim else 0 for i in range(3)],
+        gamma=[eos0[0], eos1[0]], pinf=[eos0[1], eos1[1]],
+        phi=np.ascontiguousarray(phi, dtype=np.float64).reshape(-1),
+        prim=np.ascontiguousarray(prim, dtype=np.float64),
+        t_end=t_end,
+    )
+    d.update(extra)
+    return d
+
+
+def _fill(ndim, ncell, state):
+    """primitive block (D+2, cells) of one constant state, or per-cell arrays"""
+    out = np.empty((ndim + 2, ncell))
+    out[0] = state["rho"]
+    for d in range(ndim):
+        out[1 + d] = state.get("u%d" % d, state.get("u", 0.0) if d == 0 else 0.0)
+    out[ndim + 1] = state["p"]
+    return out
+
+
+def tube_1d(n=400, seed=0, t_end=2.2e-4):
+    """Gas-water shock tube: water (fluid 0) left of x_I, air (fluid 1) right.
+
+    x_I = 0.5 + delta, delta ~ U(-1, 1) * h (seeded), phi = x - x_I.
+    """
+    h, (x,) = _grid(1, n)
+    xi = 0.5 + _rng(seed).uniform(-1.0, 1.0) * h
+    phi = x - xi
+    prim = np.stack([_fill(1, n, dict(rho=1000.0, u=0.0, p=1.0e9)),
+                     _fill(1, n, dict(rho=50.0, u=0.0, p=1.0e5))])
+    return _case(1, n, 0, WATER, AIR, phi, prim, t_end, "tube_1d", x_interface=xi)
+
+
+def tube_1d_single(n=200, seed=0, t_end=2e-4, left=None, right=None, eos=AIR):
+    """Shock tube of one fluid across a 'material' interface of identical EOS."""
+    h, (x,) = _grid(1, n)
+    xi = 0.5 + _rng(seed).uniform(-1.0, 1.0) * h
+    left = left or dict(rho=1.0, u=0.0, p=1.0e5)
+    right = right or dict(rho=0.125, u=0.0, p=1.0e4)
+    prim = np.stack([_fill(1, n, left), _fill(1, n, right)])
+    return _case(1, n, 0, eos, eos, x - xi, prim, t_end, "tube_1d_single", x_interface=xi)
+
+
+def shock_bubble_2d(n=1024, seed=0, radius=0.15, t_end=1.5e-4):
+    """Planar water shock (post-shock p=1e9) hitting an air bubble.
+
+    Air bubble (fluid 0, phi < 0 inside) of the given radius near (0.5, 0.5),
+    centre jittered by U(-0.5, 0.5) h per axis; water (fluid 1) outside, at
+    rest (rho=1000, p=1e5) ahead of the shock and in the post-shock state for
+    x < 96/1024 (face aligned).
+    """
+    h, (X, Y) = _grid(2, n)
+    r = _rng(seed)
+    cx, cy = 0.5 + r.uniform(-0.5, 0.5) * h, 0.5 + r.uniform(-0.5, 0.5) * h
+    phi = np.sqrt((X - cx) ** 2 + (Y - cy) ** 2) - radius
+    nc = n * n
+    air = _fill(2, nc, dict(rho=1.0, p=1.0e5))
+    water = _fill(2, nc, dict(rho=1000.0, p=1.0e5))
+    xs = 96.0 / 1024.0
+    post = (X.reshape(-1) < xs)
+    water[0, post] = WATER_SHOCK_1E9["rho"]
+    water[1, post] = WATER_SHOCK_1E9["u"]
+    water[3, post] = WATER_SHOCK_1E9["p"]
+    return _case(2, n, 0, AIR, WATER, phi, np.stack([air, water]), t_end,
+                 "shock_bubble_2d", centre=(cx, cy), radius=radius)
+
+
+def shock_droplet_3d(n=256, seed=0, radius=0.2, t_end=None):
+    """Mach-1.5 air shock hitting a water droplet (fluid 0 inside)."""
+    h, (X, Y, Z) = _grid(3, n)
+    r = _rng(seed)
+    c = [0.5 + r.uniform(-0.5, 0.5) * h for _ in range(3)]
+    phi = np.sqrt((X - c[0]) ** 2 + (Y - c[1]) ** 2 + (Z - c[2]) ** 2) - radius
+    nc = n ** 3
+    water = _fill(3, nc, dict(rho=1000.0, p=1.0e5))
+    air = _fill(3, nc, dict(rho=1.0, p=1.0e5))
+    post = (X.reshape(-1) < 51.0 / 256.0)
+    air[0, post] = AIR_SHOCK_M15["rho"]
+    air[1, post] = AIR_SHOCK_M15["u"]
+    air[4, post] = AIR_SHOCK_M15["p"]
+    return _case(3, n, 0, WATER, AIR, phi, np.stack([water, air]),
+                 t_end if t_end is not None else 1e30, "shock_droplet_3d", centre=c, radius=radius)
+
+
+def smooth_2d(n=512, seed=0, amp=1.0e3, width=0.05, t_end=None):
+    """Gaussian pressure pulse in air (x < 0.5, fluid 0) near a flat water
+    interface; isentropic density perturbation rho' = p'/c0^2, c0^2 = 1.4e5."""
+    h, (X, Y) = _grid(2, n)
+    xi = 0.5 + _rng(seed).uniform(-0.25, 0.25) * h
+    phi = X - xi
+    pp = amp * np.exp(-((X - 0.4) ** 2 + (Y - 0.5) ** 2) / width ** 2)
+    nc = n * n
+    air = _fill(2, nc, dict(rho=1.0, p=1.0e5))
+    air[0] += (pp / 1.4e5).reshape(-1)
+    air[3] += pp.reshape(-1)
+    water = _fill(2, nc, dict(rho=1000.0, p=1.0e5))
+    return _case(2, n, 0, AIR, WATER, phi, np.stack([air, water]),
+                 t_end if t_end is not None else 1e30, "smooth_2d", x_interface=xi)
+
+
+def droplet_2d(n=64, seed=0, radius=0.1, u=None, ndim=2):
+    """Periodic translation of a water droplet in air (Sec. 4.2 analogue):
+    water (fluid 0) inside radius R, both fluids moving with the same u."""
+    h, grid = _grid(ndim, n)
+    r = _rng(seed)
+    c = [0.5 + r.uniform(-0.5, 0.5) * h for _ in range(ndim)]
+    phi = np.sqrt(sum((g - ci) ** 2 for g, ci in zip(grid, c))) - radius
+    nc = n ** ndim
+    uu = 10.0 if u is None else u
+    water = _fill(ndim, nc, dict(rho=1000.0, u=uu, p=1.0e5))
+    air = _fill(ndim, nc, dict(rho=1.2, u=uu, p=1.0e5))
+    return _case(ndim, n, 1, WATER, AIR, phi, np.stack([water, air]), 1.0 / uu,
+                 "droplet_%dd" % ndim, centre=c, radius=radius)
+
+
+def entropy_wave_1d(n=64, amp=0.2, u=1.0, p=1.0, t_end=0.1):
+    """Single fluid (phi < 0 everywhere) smooth density wave on a periodic
+    domain: rho = 1 + amp sin(2 pi x), uniform u and p.  Exact solution is a
+    translation by u t."""
+    h, (x,) = _grid(1, n)
+    phi = -np.ones(n)
+    st = np.stack([np.ones(n), np.full(n, u), np.full(n, p)])
+    st[0] = 1.0 + amp * np.sin(2 * np.pi * x)
+    prim = np.stack([st, np.stack([np.ones(n), np.zeros(n), np.ones(n)])])
+    return _case(1, n, 1, (1.4, 0.0), (1.4, 0.0), phi, prim, t_end, "entropy_wave_1d")
+
+
+def CONFIGS():
+    """The named workloads and their sizes (used by the benchmark)."""
+    return {
+        "tube_1d": dict(fn=tube_1d, kw=dict(n=400)),
+        "shock_bubble_2d": dict(fn=shock_bubble_2d, kw=dict(n=1024)),
+        "shock_droplet_3d": dict(fn=shock_droplet_3d, kw=dict(n=256)),
+        "smooth_2d": dict(fn=smooth_2d, kw=dict(n=512)),
+    }

@@ -1,0 +1,121 @@
+"""Pins of the accelerated scheduler (Sec. 3.1): the truncation of n with the
+0.7 threshold, the fast-fluid sub-step sequence of Fig. 2, the speedup model
+Eq. (speedup_ratio) against Table 1, and the reduction of the generic cycle
+to the original method when n truncates to 1.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from paper_1905_03917_amd import workloads as WL
+
+GOLD = json.load(open(os.path.join(os.path.dirname(__file__), "golden", "paper_scheduler.json")))
+
+
+def test_fig2_substeps_rk2(oracle):
+    g = GOLD["fig2"]
+    dts, single = oracle.plan_cycle(g["dt_slow"], g["dt_fast"], 1e9, GOLD["n_threshold"])
+    assert not single and dts == g["dt_slow"]           # n = 2.8: fractional part 0.8 >= 0.7
+    tau, seq = 0.0, []
+    while True:
+        d, hh, fin = oracle.substep(tau, dts, g["dt_fast"], g["rk"], 0)
+        seq.append(d)
+        tau = dts if fin else tau + d
+        if fin:
+            break
+    np.testing.assert_allclose(seq, g["fast_substeps"], rtol=1e-14)
+
+
+def test_substeps_rk3_stop_at_half():
+    from oracle import oracle as O
+    tau, seq, half_done = 0.0, [], 0
+    while True:
+        d, hh, fin = O.substep(tau, 2.8, 1.0, 3, half_done)
+        seq.append(d)
+        if hh:
+            half_done, tau = 1, 1.4
+        elif fin:
+            break
+        else:
+            tau += d
+    np.testing.assert_allclose(seq, [1.0, 0.4, 1.0, 0.4], rtol=1e-14)
+
+
+@pytest.mark.parametrize("n,expect", [(2.8, 2.8), (3.5, 3.0), (3.7, 3.7), (3.69, 3.0),
+                                      (1.3, 1.0), (5.0, 5.0), (4.999, 4.999), (4.68, 4.0)])
+def test_threshold_truncation(oracle, n, expect):
+    dts, single = oracle.plan_cycle(n * 1e-6, 1e-6, 1.0, GOLD["n_threshold"])
+    assert dts == pytest.approx(expect * 1e-6, rel=1e-14)
+    assert single == (expect < 1.0 + 1e-9)
+
+
+def test_end_time_clamp(oracle):
+    dts, single = oracle.plan_cycle(3.5, 1.0, 2.2, 0.7)
+    assert dts == 2.2 and not single
+    dts, single = oracle.plan_cycle(3.5, 1.0, 0.6, 0.7)
+    assert dts == 0.6 and single
+
+
+def speedup_model(n, m):
+    """Eq. (speedup_ratio): r_s = n / ([n] - ([n] - 1) m), [.] = ceiling."""
+    c = math.ceil(n)
+    return n / (c - (c - 1) * m)
+
+
+def test_speedup_model_limits_and_table1():
+    assert speedup_model(4.0, 0.0) == pytest.approx(1.0)
+    assert speedup_model(4.0, 1.0) == pytest.approx(4.0)
+    assert speedup_model(2.8, 0.5) == pytest.approx(2.8 / 2.0)
+    for row in GOLD["table1"]:
+        assert row["original"] / row["modified"] == pytest.approx(row["rs"], abs=6e-4)
+        # the fluid-1 share m implied by n = 4 lies in [0, 1)
+        rs = row["rs"]
+        m = (4 - 4 / rs) / 3
+        assert 0.0 <= m < 1.0
+
+
+def test_generic_rk2_cycle_reduces_to_original_bitwise(oracle):
+    """With RK2 and n truncated to 1 the accelerated cycle is the original
+    step: the slow state interpolated at t2 = t1 is the future state and the
+    two correction terms cancel."""
+    c = WL.tube_1d_single(n=100, seed=3)
+    a = oracle.OracleSim(c, rk=2)
+    sa = a.advance(1e-3, mode=0, max_cycles=6)
+    b = oracle.OracleSim(c, rk=2, force_cycle=1)
+    sb = b.advance(1e-3, mode=1, max_cycles=6)
+    assert sa["steps"] == sb["steps"] == [6, 6]
+    for u, v in zip(a.state(), b.state()):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_generic_rk2_cycle_reduces_bitwise_2d(oracle):
+    c = WL.shock_bubble_2d(n=32, seed=6)
+    # same EOS for both fluids so that the time steps are close (n < 1.7)
+    c["gamma"] = [1.4, 1.4]
+    c["pinf"] = [0.0, 0.0]
+    c["prim"][1, 0] = 1.0
+    c["prim"][1, 1] = 0.0
+    c["prim"][1, 3] = 1e5
+    c["prim"][1, 3, :200] = 1.5e5
+    a = oracle.OracleSim(c, rk=2)
+    a.advance(1.0, mode=0, max_cycles=3)
+    b = oracle.OracleSim(c, rk=2, force_cycle=1)
+    sb = b.advance(1.0, mode=1, max_cycles=3)
+    assert sb["steps"] == [3, 3]
+    for u, v in zip(a.state(), b.state()):
+        np.testing.assert_array_equal(u, v)
+
+
+def test_multi_dt_takes_fewer_slow_steps(oracle):
+    c = WL.tube_1d(n=200, seed=0)
+    o = oracle.OracleSim(c)
+    st = o.advance(c["t_end"], mode=1)
+    # air (fluid 1) is slow: one step per cycle; water sub-steps n ~ 3 (+1 at t1/2)
+    assert st["steps"][1] == st["cycles"]
+    assert st["steps"][0] >= 3 * st["cycles"] - 2
+    o2 = oracle.OracleSim(c)
+    s2 = o2.advance(c["t_end"], mode=0)
+    assert st["steps"][1] < s2["steps"][1] / 2.5
