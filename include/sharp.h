@@ -1,0 +1,149 @@
+/*
+ * sharp.h -- C ABI of the gfx950 (MI355X) implementation of the accelerated
+ * sharp-interface method of Long, Cai & Pan, "An accelerated sharp-interface
+ * method for multiphase flows simulations".
+ *
+ * The library advances two compressible fluids separated by a level-set
+ * interface on a uniform Cartesian grid (1-D, 2-D or 3-D, FP64):
+ *   - each fluid's cut-cell finite-volume update, Eq. (Eulerdiscrete) of
+ *     Sec. 2.1, with a WENO5 flux (local Lax-Friedrichs splitting) and a
+ *     Shu-Osher Runge-Kutta stage (SSP-RK3 by default, the paper's TVD-RK2
+ *     on request, Sec. 3);
+ *   - the level-set geometry, interface interaction (exact two-material
+ *     stiffened-gas Riemann problem), ghost-fluid extension, small-cell
+ *     mixing, level-set advection Eq. (LS:linearadvection) and
+ *     reinitialisation (Sec. 2.2-2.3);
+ *   - the original method (one CFL time step for both fluids) or the
+ *     accelerated cycle of Sec. 3.1 (each fluid with its own CFL step, the
+ *     slow fluid's intermediate states by Eq. (interpolation), interfacial
+ *     flux correction by Eqs. (firstcorrection)/(secondcorrection)).
+ *
+ * Conventions.  Fluid 0 occupies phi < 0, fluid 1 phi >= 0.  Arrays are FP64
+ * structure-of-arrays with x fastest: cell c = i + n0*(j + n1*k).
+ *   phi[c]          level set (signed distance to the interface)
+ *   prim[k][q][c]   primitive state of fluid k, q = rho, u_1..u_D, p
+ *   cons[k][q][c]   cell content of fluid k per cell volume, alpha_k * U_k,
+ *                   q = rho, rho u_1..rho u_D, E
+ *   alpha[c]        volume fraction of fluid 0
+ * NV = D + 2 components.
+ *
+ * Ownership and errors.  The library allocates and owns every device buffer
+ * of a simulation.  Caller arrays are only read or written during a call;
+ * `on_device` tells whether they are device pointers (ordered on the
+ * simulation's stream) or host pointers.  Handles are not thread safe.  No
+ * exception crosses the ABI: every call returns a sim_status, and
+ * sim_last_error() returns a description of the last failure on this thread.
+ */
+#ifndef SHARP_H
+#define SHARP_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct sim sim_t;
+
+typedef enum {
+    SIM_OK = 0,
+    SIM_EINVAL = -1,    /* invalid argument */
+    SIM_ENOMEM = -2,    /* device allocation failed */
+    SIM_EDEVICE = -3,   /* HIP runtime error, or the interface band outran its tiles */
+    SIM_ENONPHYS = -4,  /* rho <= 0, p + p_inf <= 0, NaN, or no valid time step */
+    SIM_ESTATE = -5     /* call out of order (e.g. advance before set_state) */
+} sim_status;
+
+typedef enum { SIM_SINGLE_DT = 0, SIM_MULTI_DT = 1 } sim_mode;
+
+/* Uniform grid: n cells per direction on [lo, lo + n h]; unused directions
+ * have n = 1.  bc: 0 zero-gradient, 1 periodic (per direction). */
+typedef struct {
+    int ndim;
+    int64_t n[3];
+    double lo[3];
+    double h;
+    int bc[3];
+} sim_grid;
+
+/* Stiffened gas p = (gamma - 1) rho e - gamma p_inf (p_inf >= 0).  The
+ * paper's Tait water (Sec. 2.2) is the isentrope with p_inf = B - p0. */
+typedef struct {
+    double gamma;
+    double pinf;
+} sim_eos;
+
+/* Options; sim_default_opts() fills the values in brackets. */
+typedef struct {
+    double cfl;          /* CFL number [0.6] (Sec. 4) */
+    int rk;              /* 3: SSP-RK3 [3]; 2: the paper's TVD-RK2 */
+    double n_thr;        /* fractional-part threshold of n [0.7] (Sec. 3.1) */
+    double alpha_mix;    /* small-cell mixing threshold [0.5] */
+    double ls_band;      /* level-set band half width, cells [8] */
+    double ext_band;     /* extension depth, cells [5] */
+    double mix_band;     /* |phi| limit of mixing sources, cells [3] */
+    int ext_iters;       /* Jacobi sweeps of the extension [8] */
+    int reinit_iters;    /* reinitialisation sweeps per level-set step [2] */
+    double weno_eps;     /* WENO epsilon [1e-6] */
+    int force_cycle;     /* run the accelerated cycle even when n truncates to 1 [0] */
+    int no_correction;   /* skip the interfacial flux correction (diagnostic) [0] */
+} sim_opts;
+
+typedef struct {
+    int64_t cycles;          /* accelerated cycles, or original steps */
+    int64_t steps[2];        /* complete RK steps taken by each fluid */
+    int64_t cell_updates[2]; /* sum over those steps of the cells holding the fluid */
+    double t;                /* simulation time reached */
+    double last_n;           /* time-step ratio of the last cycle (1 for a single-dt step) */
+    double last_dt[2];       /* last CFL time step of each fluid */
+    double bflux[2][5];      /* time-integrated inflow through the domain boundary,
+                                per fluid and component (x dV units) */
+} sim_stats;
+
+/* Fill *o with the defaults listed above. */
+void sim_default_opts(sim_opts* o);
+
+/* Create a simulation.  eos[0] is fluid 0 (phi < 0), eos[1] fluid 1.
+ * stream: a hipStream_t to order all work on, or NULL for a private stream.
+ * Requires equal spacing in every direction (h), 1 <= ndim <= 3,
+ * n[d] >= 1, gamma > 1, p_inf >= 0, rk in {2, 3}.  Returns SIM_EINVAL on bad
+ * arguments, SIM_ENOMEM if device memory runs out. */
+sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts* opts,
+                      void* stream, sim_t** out);
+
+/* Set the state from a level set phi[cells] and primitives prim[2][NV][cells]
+ * (Sec. 2.1: the cut cells receive alpha_k * U_k of the given piecewise
+ * states).  The primitives given outside a fluid's region initialise that
+ * fluid's ghost states.  Resets time and the boundary-flux ledger. */
+sim_status sim_set_state(sim_t* s, const double* phi, const double* prim, int on_device);
+
+/* Advance to t_end with the original method (SIM_SINGLE_DT) or the
+ * accelerated cycle (SIM_MULTI_DT), stopping early after max_cycles
+ * cycles/steps when max_cycles > 0.  Statistics of this call go to *out
+ * (nullable).  On SIM_ENONPHYS the state is that of the failing step. */
+sim_status sim_advance(sim_t* s, double t_end, int mode, int64_t max_cycles, sim_stats* out);
+
+/* Copy the level set, contents cons[2][NV][cells] and fluid-0 volume
+ * fraction out (any pointer may be NULL). */
+sim_status sim_get_state(sim_t* s, double* phi, double* cons, double* alpha, int on_device);
+
+/* Total content sum_c dV cons[k][q][c] -> out[k*5 + q] (q < NV). */
+sim_status sim_totals(sim_t* s, double* out10);
+
+/* Kernel timing of the fused face-flux/RK stage kernel on bulk tiles: when
+ * enabled, sim_advance brackets every launch of it with HIP events on the
+ * simulation's stream.  sim_profile_read returns the summed duration (ms),
+ * the number of launches, and the algorithmic bytes those launches move
+ * (stage input and output, plus the step's base state after the first
+ * stage: 2 or 3 x NV doubles per cell).  Enabling resets the counters. */
+sim_status sim_profile(sim_t* s, int enable);
+sim_status sim_profile_read(sim_t* s, double* ms, int64_t* launches, int64_t* bytes);
+
+void sim_destroy(sim_t* s);
+const char* sim_strerror(sim_status st);
+const char* sim_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

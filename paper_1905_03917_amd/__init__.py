@@ -1,0 +1,206 @@
+"""Python binding of libsharp_hip.so, the gfx950 implementation of the
+accelerated sharp-interface method (Long, Cai & Pan).
+
+Argument marshalling only: every step of the method runs in the HIP kernels
+behind the C ABI declared in include/sharp.h.  PyTorch supplies device memory
+(float64 CUDA tensors) and the stream the library orders its work on.  If the
+library is missing this module raises; there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsharp_hip.so")
+
+SIM_SINGLE_DT = 0
+SIM_MULTI_DT = 1
+
+
+class Grid(C.Structure):
+    _fields_ = [("ndim", C.c_int), ("n", C.c_int64 * 3), ("lo", C.c_double * 3), ("h", C.c_double),
+                ("bc", C.c_int * 3)]
+
+
+class Eos(C.Structure):
+    _fields_ = [("gamma", C.c_double), ("pinf", C.c_double)]
+
+
+class Opts(C.Structure):
+    _fields_ = [("cfl", C.c_double), ("rk", C.c_int), ("n_thr", C.c_double), ("alpha_mix", C.c_double),
+                ("ls_band", C.c_double), ("ext_band", C.c_double), ("mix_band", C.c_double),
+                ("ext_iters", C.c_int), ("reinit_iters", C.c_int), ("weno_eps", C.c_double),
+                ("force_cycle", C.c_int), ("no_correction", C.c_int)]
+
+
+class Stats(C.Structure):
+    _fields_ = [("cycles", C.c_int64), ("steps", C.c_int64 * 2), ("cell_updates", C.c_int64 * 2),
+                ("t", C.c_double), ("last_n", C.c_double), ("last_dt", C.c_double * 2),
+                ("bflux", (C.c_double * 5) * 2)]
+
+    def as_dict(self):
+        return dict(cycles=self.cycles, steps=list(self.steps), cell_updates=list(self.cell_updates),
+                    t=self.t, last_n=self.last_n, last_dt=list(self.last_dt),
+                    bflux=np.array([list(r) for r in self.bflux]))
+
+
+EXPORTS = ["sim_default_opts", "sim_create", "sim_set_state", "sim_advance", "sim_get_state",
+           "sim_totals", "sim_profile", "sim_profile_read", "sim_destroy", "sim_strerror",
+           "sim_last_error"]
+
+_lib = None
+
+
+def lib():
+    """Load libsharp_hip.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libsharp_hip.so is not built: run __graft_entry__.build() "
+                               "or python paper_1905_03917_amd/build.py")
+        L = C.CDLL(LIB_PATH)
+        vp = C.c_void_p
+        L.sim_default_opts.argtypes = [C.POINTER(Opts)]
+        L.sim_default_opts.restype = None
+        L.sim_create.argtypes = [C.POINTER(Grid), C.POINTER(Eos), C.POINTER(Opts), vp, C.POINTER(vp)]
+        L.sim_set_state.argtypes = [vp, vp, vp, C.c_int]
+        L.sim_advance.argtypes = [vp, C.c_double, C.c_int, C.c_int64, C.POINTER(Stats)]
+        L.sim_get_state.argtypes = [vp, vp, vp, vp, C.c_int]
+        L.sim_totals.argtypes = [vp, vp]
+        L.sim_profile.argtypes = [vp, C.c_int]
+        L.sim_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.sim_destroy.argtypes = [vp]
+        L.sim_destroy.restype = None
+        L.sim_strerror.argtypes = [C.c_int]
+        L.sim_strerror.restype = C.c_char_p
+        L.sim_last_error.restype = C.c_char_p
+        for f in ("sim_create", "sim_set_state", "sim_advance", "sim_get_state", "sim_totals",
+                  "sim_profile", "sim_profile_read"):
+            getattr(L, f).restype = C.c_int
+        _lib = L
+    return _lib
+
+
+class SimError(RuntimeError):
+    def __init__(self, status, where):
+        L = lib()
+        super().__init__("%s: %s (%s)" % (where, L.sim_strerror(status).decode(), L.sim_last_error().decode()))
+        self.status = status
+
+
+def _check(rc, where):
+    if rc != 0:
+        raise SimError(rc, where)
+
+
+def default_opts(**over):
+    o = Opts()
+    lib().sim_default_opts(C.byref(o))
+    for k, v in over.items():
+        setattr(o, k, v)
+    return o
+
+
+def _ptr(a):
+    """device pointer of a contiguous float64 tensor, or host pointer of an ndarray"""
+    import torch
+    if isinstance(a, torch.Tensor):
+        assert a.dtype == torch.float64 and a.is_contiguous()
+        return C.c_void_p(a.data_ptr()), 1 if a.is_cuda else 0
+    a = np.ascontiguousarray(a, dtype=np.float64)
+    return C.c_void_p(a.ctypes.data), 0
+
+
+class Sim:
+    """One two-fluid simulation on the current CUDA (HIP) device.
+
+    case: dict with ndim, n, lo, h, bc, gamma, pinf (see workloads.py), or
+    explicit keyword arguments.  Options are sim_opts fields.
+    """
+
+    def __init__(self, case, stream=None, **opts):
+        import torch
+        self.case = case
+        self.D = int(case["ndim"])
+        self.NV = self.D + 2
+        self.nc = int(np.prod([case["n"][d] if d < self.D else 1 for d in range(3)]))
+        g = Grid()
+        g.ndim = self.D
+        for d in range(3):
+            g.n[d] = int(case["n"][d]) if d < self.D else 1
+            g.lo[d] = float(case["lo"][d])
+            g.bc[d] = int(case["bc"][d]) if d < self.D else 0
+        g.h = float(case["h"])
+        eos = (Eos * 2)(Eos(case["gamma"][0], case["pinf"][0]), Eos(case["gamma"][1], case["pinf"][1]))
+        self.opts = default_opts(**opts)
+        if stream is None:
+            stream = torch.cuda.current_stream()
+        self.stream = stream
+        h = C.c_void_p()
+        _check(lib().sim_create(C.byref(g), eos, C.byref(self.opts), C.c_void_p(stream.cuda_stream), C.byref(h)),
+               "sim_create")
+        self.h = h
+        if "phi" in case:
+            self.set_state(case["phi"], case["prim"])
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sim_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_state(self, phi, prim):
+        import torch
+        if isinstance(phi, torch.Tensor) and phi.is_cuda:
+            phi = phi.contiguous()
+            prim = prim.contiguous()
+        pp, dev = _ptr(phi)
+        pr, dev2 = _ptr(prim)
+        assert dev == dev2
+        self._keep = (phi, prim)
+        _check(lib().sim_set_state(self.h, pp, pr, dev), "sim_set_state")
+
+    def advance(self, t_end, mode=SIM_MULTI_DT, max_cycles=0):
+        st = Stats()
+        _check(lib().sim_advance(self.h, float(t_end), int(mode), int(max_cycles), C.byref(st)), "sim_advance")
+        return st.as_dict()
+
+    def state(self, device=True):
+        """(phi, cons[2][NV][cells], alpha) as float64 CUDA tensors (or numpy)."""
+        import torch
+        if device:
+            phi = torch.empty(self.nc, dtype=torch.float64, device="cuda")
+            cons = torch.empty((2, self.NV, self.nc), dtype=torch.float64, device="cuda")
+            alpha = torch.empty(self.nc, dtype=torch.float64, device="cuda")
+            _check(lib().sim_get_state(self.h, C.c_void_p(phi.data_ptr()), C.c_void_p(cons.data_ptr()),
+                                       C.c_void_p(alpha.data_ptr()), 1), "sim_get_state")
+            return phi, cons, alpha
+        phi = np.empty(self.nc)
+        cons = np.empty((2, self.NV, self.nc))
+        alpha = np.empty(self.nc)
+        _check(lib().sim_get_state(self.h, C.c_void_p(phi.ctypes.data), C.c_void_p(cons.ctypes.data),
+                                   C.c_void_p(alpha.ctypes.data), 0), "sim_get_state")
+        return phi, cons, alpha
+
+    def totals(self):
+        out = np.empty(10)
+        _check(lib().sim_totals(self.h, C.c_void_p(out.ctypes.data)), "sim_totals")
+        return out.reshape(2, 5)
+
+    def profile(self, enable=True):
+        _check(lib().sim_profile(self.h, int(enable)), "sim_profile")
+
+    def profile_read(self):
+        ms = C.c_double()
+        n = C.c_int64()
+        cells = C.c_int64()
+        _check(lib().sim_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(cells)), "sim_profile_read")
+        return ms.value, n.value, cells.value

@@ -1,0 +1,332 @@
+// sharp_capi.hip -- C ABI of the gfx950 sharp-interface library (include/sharp.h):
+// argument checking, device allocation, host/device staging.
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+
+#include "sharp_internal.h"
+
+struct sim {
+    sharp::Sim s;
+};
+
+namespace sharp {
+
+static thread_local char g_err[512] = "";
+
+void set_error(const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+}
+
+template <typename T>
+static sim_status dalloc(Sim& s, T** p, size_t n)
+{
+    void* q = nullptr;
+    if (n == 0) n = 1;
+    if (hipMalloc(&q, n * sizeof(T)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("device allocation of %zu bytes failed", n * sizeof(T));
+        return SIM_ENOMEM;
+    }
+    s.dev_allocs.push_back(q);
+    if (hipMemsetAsync(q, 0, n * sizeof(T), s.stream) != hipSuccess) {
+        set_error("hipMemsetAsync failed");
+        return SIM_EDEVICE;
+    }
+    *p = static_cast<T*>(q);
+    return SIM_OK;
+}
+
+static void release(Sim& s)
+{
+    for (void* p : s.dev_allocs) (void)hipFree(p);
+    s.dev_allocs.clear();
+    for (hipEvent_t e : s.ev_pool) (void)hipEventDestroy(e);
+    s.ev_pool.clear();
+    if (s.h_red) (void)hipHostFree(s.h_red);
+    s.h_red = nullptr;
+    if (s.own_stream && s.stream) (void)hipStreamDestroy(s.stream);
+    s.stream = nullptr;
+}
+
+}  // namespace sharp
+
+using namespace sharp;
+
+extern "C" {
+
+void sim_default_opts(sim_opts* o)
+{
+    if (!o) return;
+    memset(o, 0, sizeof(*o));
+    o->cfl = 0.6;
+    o->rk = 3;
+    o->n_thr = 0.7;
+    o->alpha_mix = 0.5;
+    o->ls_band = 8.0;
+    o->ext_band = 5.0;
+    o->mix_band = 3.0;
+    o->ext_iters = 8;
+    o->reinit_iters = 2;
+    o->weno_eps = 1e-6;
+}
+
+const char* sim_strerror(sim_status st)
+{
+    switch (st) {
+    case SIM_OK: return "ok";
+    case SIM_EINVAL: return "invalid argument";
+    case SIM_ENOMEM: return "out of device memory";
+    case SIM_EDEVICE: return "device error";
+    case SIM_ENONPHYS: return "non-physical state";
+    case SIM_ESTATE: return "invalid call order";
+    }
+    return "unknown status";
+}
+
+const char* sim_last_error(void) { return g_err; }
+
+sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts* opts, void* stream, sim_t** out)
+{
+    if (!grid || !eos || !out) { set_error("null argument"); return SIM_EINVAL; }
+    *out = nullptr;
+    int D = grid->ndim;
+    if (D < 1 || D > 3) { set_error("ndim must be 1, 2 or 3"); return SIM_EINVAL; }
+    if (!(grid->h > 0.0) || !std::isfinite(grid->h)) { set_error("h must be positive"); return SIM_EINVAL; }
+    long long nc = 1;
+    for (int d = 0; d < 3; d++) {
+        long long n = d < D ? grid->n[d] : 1;
+        if (n < 1 || (d >= D && grid->n[d] != 1 && grid->n[d] != 0)) { set_error("bad cell count in direction %d", d); return SIM_EINVAL; }
+        if (d < D && grid->bc[d] != 0 && grid->bc[d] != 1) { set_error("bc must be 0 or 1"); return SIM_EINVAL; }
+        if (d < D && grid->bc[d] == 1 && n < 6) { set_error("periodic direction needs >= 6 cells"); return SIM_EINVAL; }
+        nc *= n;
+    }
+    if (nc * 5 >= (1ll << 31)) { set_error("grid too large for 32-bit cell indexing"); return SIM_EINVAL; }
+    for (int k = 0; k < 2; k++)
+        if (!(eos[k].gamma > 1.0) || !(eos[k].pinf >= 0.0)) { set_error("eos %d: need gamma > 1, p_inf >= 0", k); return SIM_EINVAL; }
+    sim_opts o;
+    if (opts) o = *opts; else sim_default_opts(&o);
+    if (o.rk != 2 && o.rk != 3) { set_error("rk must be 2 or 3"); return SIM_EINVAL; }
+    if (!(o.cfl > 0.0) || o.ext_iters < 0 || o.reinit_iters < 0) { set_error("invalid options"); return SIM_EINVAL; }
+
+    sim_t* h = new sim_t();
+    Sim& s = h->s;
+    s.o = o;
+    if (stream) {
+        s.stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreate(&s.stream) != hipSuccess) { delete h; set_error("hipStreamCreate failed"); return SIM_EDEVICE; }
+        s.own_stream = true;
+    }
+    Dev& g = s.g;
+    memset(&g, 0, sizeof g);
+    g.D = D;
+    const int TT[3][3] = {{256, 1, 1}, {16, 16, 1}, {8, 8, 4}};
+    g.nc = 1;
+    g.nfc = 1;
+    g.ntiles = 1;
+    for (int d = 0; d < 3; d++) {
+        g.n[d] = d < D ? (int)grid->n[d] : 1;
+        g.nf[d] = d < D ? g.n[d] + 1 : 1;
+        g.bc[d] = d < D ? grid->bc[d] : 0;
+        g.T[d] = TT[D - 1][d];
+        g.nt[d] = (g.n[d] + g.T[d] - 1) / g.T[d];
+        g.nc *= g.n[d];
+        g.nfc *= g.nf[d];
+        g.ntiles *= g.nt[d];
+    }
+    g.h = grid->h;
+    for (int k = 0; k < 2; k++) { g.gam[k] = eos[k].gamma; g.pinf[k] = eos[k].pinf; }
+    g.amix = o.alpha_mix;
+    g.lsb = o.ls_band;
+    g.extb = o.ext_band;
+    g.mixb = o.mix_band;
+    g.eps = o.weno_eps;
+    // boundary faces: two sides per direction, product of the other extents
+    int off = 0;
+    for (int d = 0; d < 3; d++) {
+        int other = 1;
+        for (int e = 0; e < 3; e++)
+            if (e != d) other *= g.n[e];
+        for (int sd = 0; sd < 2; sd++) {
+            g.bface_off[d][sd] = off;
+            if (d < D) off += other;
+        }
+    }
+    g.nbface = off;
+
+    int NV = D + 2;
+    size_t nv = (size_t)NV * g.nc;
+    sim_status rc = SIM_OK;
+#define A(ptr, n) if (rc == SIM_OK) rc = dalloc(s, &(ptr), (n))
+    for (int k = 0; k < 2; k++) {
+        A(g.X[k], nv); A(g.Y[k], nv); A(g.Z[k], nv);
+        A(g.Wb[k][0], nv); A(g.Wb[k][1], nv);
+        A(g.ss[k], (size_t)g.nc);
+        A(g.bacc[k], (size_t)NV * (g.nbface > 0 ? g.nbface : 1));
+    }
+    A(g.T2, nv); A(g.Fh, nv); A(g.corr, nv); A(g.dmix, nv);
+    A(g.phiP, (size_t)g.nc);
+    for (int b = 0; b < 3; b++) A(g.phiB[b], (size_t)g.nc);
+    A(g.phiH, (size_t)g.nc);
+    A(g.alpha, (size_t)g.nc);
+    for (int d = 0; d < 3; d++) A(g.ap[d], d < D ? (size_t)g.nfc : 1);
+    A(g.ps, (size_t)g.nc); A(g.us, (size_t)g.nc);
+    for (int b = 0; b < 2; b++)
+        for (int d = 0; d < 3; d++) A(g.v[b][d], d < D ? (size_t)g.nc : 1);
+    A(g.M, (size_t)g.nc); A(g.nearif, (size_t)g.nc);
+    A(g.tcore, (size_t)g.ntiles); A(g.tflag, (size_t)g.ntiles); A(g.tsign, (size_t)g.ntiles);
+    A(g.lists, (size_t)5 * g.ntiles);
+    A(g.counts, 16);
+    A(g.red, 8);
+#undef A
+    if (rc == SIM_OK) {
+        std::vector<int> all(g.ntiles);
+        for (int t = 0; t < g.ntiles; t++) all[t] = t;
+        int cnt[16] = {0};
+        cnt[LIST_ALL] = g.ntiles;
+        if (hipMemcpyAsync(g.lists + (size_t)LIST_ALL * g.ntiles, all.data(), sizeof(int) * g.ntiles,
+                           hipMemcpyHostToDevice, s.stream) != hipSuccess ||
+            hipMemcpyAsync(g.counts, cnt, sizeof cnt, hipMemcpyHostToDevice, s.stream) != hipSuccess ||
+            hipStreamSynchronize(s.stream) != hipSuccess) {
+            set_error("initial upload failed");
+            rc = SIM_EDEVICE;
+        }
+    }
+    if (rc == SIM_OK && hipHostMalloc((void**)&s.h_red, 16 * sizeof(unsigned long long)) != hipSuccess) {
+        set_error("pinned host allocation failed");
+        rc = SIM_ENOMEM;
+    }
+    if (rc != SIM_OK) {
+        release(s);
+        delete h;
+        return rc;
+    }
+    *out = h;
+    return SIM_OK;
+}
+
+void sim_destroy(sim_t* h)
+{
+    if (!h) return;
+    (void)hipStreamSynchronize(h->s.stream);
+    release(h->s);
+    delete h;
+}
+
+static sim_status stage_in(Sim& s, const double* src, size_t n, int on_device, double** tmp)
+{
+    *tmp = nullptr;
+    if (on_device) return SIM_OK;
+    void* p = nullptr;
+    if (hipMalloc(&p, n * sizeof(double)) != hipSuccess) { (void)hipGetLastError(); set_error("staging allocation failed"); return SIM_ENOMEM; }
+    if (hipMemcpyAsync(p, src, n * sizeof(double), hipMemcpyHostToDevice, s.stream) != hipSuccess) {
+        (void)hipFree(p);
+        set_error("host-to-device copy failed");
+        return SIM_EDEVICE;
+    }
+    *tmp = (double*)p;
+    return SIM_OK;
+}
+
+sim_status sim_set_state(sim_t* h, const double* phi, const double* prim, int on_device)
+{
+    if (!h || !phi || !prim) { set_error("null argument"); return SIM_EINVAL; }
+    Sim& s = h->s;
+    int NV = s.g.D + 2;
+    double *tphi = nullptr, *tprim = nullptr;
+    sim_status rc = stage_in(s, phi, s.g.nc, on_device, &tphi);
+    if (rc == SIM_OK) rc = stage_in(s, prim, (size_t)2 * NV * s.g.nc, on_device, &tprim);
+    if (rc == SIM_OK) rc = engine_set_state(s, tphi ? tphi : phi, tprim ? tprim : prim);
+    (void)hipStreamSynchronize(s.stream);
+    if (tphi) (void)hipFree(tphi);
+    if (tprim) (void)hipFree(tprim);
+    return rc;
+}
+
+sim_status sim_advance(sim_t* h, double t_end, int mode, int64_t max_cycles, sim_stats* out)
+{
+    if (!h) { set_error("null handle"); return SIM_EINVAL; }
+    Sim& s = h->s;
+    if (!s.has_state) { set_error("sim_set_state has not been called"); return SIM_ESTATE; }
+    if (mode != SIM_SINGLE_DT && mode != SIM_MULTI_DT) { set_error("bad mode"); return SIM_EINVAL; }
+    if (!std::isfinite(t_end)) { set_error("t_end must be finite"); return SIM_EINVAL; }
+    sim_stats st;
+    memset(&st, 0, sizeof st);
+    sim_status rc = engine_advance(s, t_end, mode, (long long)max_cycles, &st);
+    if (rc == SIM_OK) rc = engine_bflux(s, st.bflux);
+    if (out) *out = st;
+    return rc;
+}
+
+sim_status sim_get_state(sim_t* h, double* phi, double* cons, double* alpha, int on_device)
+{
+    if (!h) { set_error("null handle"); return SIM_EINVAL; }
+    Sim& s = h->s;
+    if (!s.has_state) { set_error("no state"); return SIM_ESTATE; }
+    hipMemcpyKind kind = on_device ? hipMemcpyDeviceToDevice : hipMemcpyDeviceToHost;
+    size_t nc = s.g.nc, nv = (size_t)(s.g.D + 2) * nc;
+    SHARP_HIP(hipStreamSynchronize(s.stream));
+    if (phi) SHARP_HIP(hipMemcpyAsync(phi, s.g.phiP, nc * sizeof(double), kind, s.stream));
+    if (cons)
+        for (int k = 0; k < 2; k++) SHARP_HIP(hipMemcpyAsync(cons + k * nv, s.g.X[k], nv * sizeof(double), kind, s.stream));
+    if (alpha) SHARP_HIP(hipMemcpyAsync(alpha, s.g.alpha, nc * sizeof(double), kind, s.stream));
+    SHARP_HIP(hipStreamSynchronize(s.stream));
+    return SIM_OK;
+}
+
+sim_status sim_totals(sim_t* h, double* out10)
+{
+    if (!h || !out10) { set_error("null argument"); return SIM_EINVAL; }
+    Sim& s = h->s;
+    if (!s.has_state) { set_error("no state"); return SIM_ESTATE; }
+    int NV = s.g.D + 2;
+    size_t nc = s.g.nc;
+    std::vector<double> buf(nc);
+    double dv = std::pow(s.g.h, s.g.D);
+    SHARP_HIP(hipStreamSynchronize(s.stream));
+    for (int k = 0; k < 2; k++)
+        for (int q = 0; q < 5; q++) {
+            double sum = 0.0;
+            if (q < NV) {
+                SHARP_HIP(hipMemcpy(buf.data(), s.g.X[k] + q * nc, nc * sizeof(double), hipMemcpyDeviceToHost));
+                for (size_t c = 0; c < nc; c++) sum += buf[c];
+            }
+            out10[k * 5 + q] = sum * dv;
+        }
+    return SIM_OK;
+}
+
+sim_status sim_profile(sim_t* h, int enable)
+{
+    if (!h) { set_error("null handle"); return SIM_EINVAL; }
+    Sim& s = h->s;
+    s.prof = enable != 0;
+    if (s.prof && s.ev_pool.empty()) {
+        s.ev_pool.resize(4096);
+        for (auto& e : s.ev_pool) SHARP_HIP(hipEventCreate(&e));
+    }
+    s.prof_ms = 0.0;
+    s.prof_launches = 0;
+    s.prof_bytes = 0;
+    s.ev_used = 0;
+    s.prof_cells.clear();
+    return SIM_OK;
+}
+
+sim_status sim_profile_read(sim_t* h, double* ms, int64_t* launches, int64_t* bytes)
+{
+    if (!h) { set_error("null handle"); return SIM_EINVAL; }
+    Sim& s = h->s;
+    if (ms) *ms = s.prof_ms;
+    if (launches) *launches = s.prof_launches;
+    if (bytes) *bytes = s.prof_bytes;
+    return SIM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,270 @@
+// sharp_device.h -- device-side building blocks of the gfx950 path of the
+// accelerated sharp-interface method (Long, Cai & Pan, Sec. 2 and 3.1).
+//
+// Everything here is per-cell or per-face arithmetic used by the kernels in
+// sharp_kernels.hip: stiffened-gas EOS, WENO5 reconstruction, the exact
+// two-material Riemann problem of the interface interaction, and the
+// level-set geometry (vertex values, apertures, volume fraction).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#define SHARP_WG 256
+
+namespace sharp {
+
+// ---------------------------------------------------------------------------
+// Device view of one simulation: grid, tiling, parameters and buffers.
+// Passed by value to every kernel.
+// ---------------------------------------------------------------------------
+struct Dev {
+    int D;            // 1, 2, 3
+    int n[3];         // cells per direction (1 if unused)
+    int nf[3];        // padded face lattice (n+1 in active directions)
+    int nc;           // number of cells
+    int nfc;          // number of padded faces per direction array
+    int T[3];         // tile dims
+    int nt[3];        // tiles per direction
+    int ntiles;
+    int bc[3];        // 0 zero-gradient, 1 periodic
+    double h;
+    double gam[2], pinf[2];
+    double amix, lsb, extb, mixb, eps;
+    int bface_off[3][2];  // offsets of the boundary-face accumulators
+    int nbface;
+    // state
+    double* X[2];
+    double* Y[2];
+    double* Z[2];
+    double* T2;       // slow-fluid temporary (interpolated and mixed)
+    double* Fh;       // fast-fluid snapshot at t1/2
+    double* Wb[2][2]; // primitives, two Jacobi buffers per fluid
+    double* phiP;     // level set, base/current
+    double* phiB[3];  // level-set stage / reinitialisation buffers
+    double* phiH;     // level-set snapshot at t1/2
+    double* alpha;    // fluid-0 volume fraction
+    double* ap[3];    // fluid-0 aperture of the low face, padded index
+    double* ps;       // interface pressure (cut cells)
+    double* us;       // interface normal velocity (cut cells)
+    double* ss[2];    // star-state CFL speed per fluid (cut cells)
+    double* v[2][3];  // level-set velocity, two Jacobi buffers
+    uint8_t* M;       // band mask of the (sub)step
+    uint8_t* nearif;  // sign change within the 3^D neighbourhood (reinit)
+    double* corr;     // interfacial flux correction [NV][cells]
+    double* dmix;     // mixing increments [NV][cells]
+    double* bacc[2];  // boundary inflow accumulators [NV][nbface]
+    // tiles
+    int* tcore;       // tile holds band cells
+    int* tflag;       // bit0 band tile, bit1 candidate tile, bit2 ring tile
+    int* tsign;       // fluid of a tile outside the band
+    int* lists;       // [5][ntiles]: band, candidate, bulk0, bulk1, all
+    int* counts;      // [16]: tiles per list (0..4), cells per list (8..11)
+    // scalars
+    unsigned long long* red;   // [0..1] max speed bits, [2..3] active counts, [4] error flags
+};
+
+enum { LIST_BAND = 0, LIST_CAND = 1, LIST_BULK0 = 2, LIST_BULK1 = 3, LIST_ALL = 4 };
+enum { ERR_NONPHYS = 1, ERR_BAND_OVERFLOW = 2 };
+
+// ---------------------------------------------------------------------------
+// indexing
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int bcmap(int i, int n, int bc)
+{
+    if (bc == 1) { i %= n; return i < 0 ? i + n : i; }
+    return i < 0 ? 0 : (i >= n ? n - 1 : i);
+}
+
+__device__ __forceinline__ int cidx(const Dev& g, int i, int j, int k)
+{
+    i = bcmap(i, g.n[0], g.bc[0]);
+    j = g.D > 1 ? bcmap(j, g.n[1], g.bc[1]) : 0;
+    k = g.D > 2 ? bcmap(k, g.n[2], g.bc[2]) : 0;
+    return i + g.n[0] * (j + g.n[1] * k);
+}
+
+__device__ __forceinline__ int fidx(const Dev& g, int i, int j, int k)
+{
+    return i + g.nf[0] * (j + g.nf[1] * k);
+}
+
+__device__ __forceinline__ void coords(const Dev& g, int c, int& i, int& j, int& k)
+{
+    i = c % g.n[0];
+    j = (c / g.n[0]) % g.n[1];
+    k = c / (g.n[0] * g.n[1]);
+}
+
+__device__ __forceinline__ int nbr(const Dev& g, int c, int d, int off)
+{
+    int i, j, k;
+    coords(g, c, i, j, k);
+    if (d == 0) i += off; else if (d == 1) j += off; else k += off;
+    return cidx(g, i, j, k);
+}
+
+// level set of the (sub)step: band cells are read from the working buffer,
+// every other cell keeps its value in the base buffer
+__device__ __forceinline__ double phi_at(const Dev& g, const double* cur, int c)
+{
+    return g.M[c] ? cur[c] : g.phiP[c];
+}
+
+// ---------------------------------------------------------------------------
+// stiffened-gas EOS
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ void prim2cons(double gm, double pi, const double* W, double* U)
+{
+    double rho = W[0], ke = 0.0;
+    U[0] = rho;
+#pragma unroll
+    for (int d = 0; d < D; d++) { U[1 + d] = rho * W[1 + d]; ke += W[1 + d] * W[1 + d]; }
+    U[D + 1] = (W[D + 1] + gm * pi) / (gm - 1.0) + 0.5 * rho * ke;
+}
+
+template <int D>
+__device__ __forceinline__ bool cons2prim(double gm, double pi, const double* U, double* W)
+{
+    double rho = U[0], ir = 1.0 / rho, ke = 0.0;
+    W[0] = rho;
+#pragma unroll
+    for (int d = 0; d < D; d++) { W[1 + d] = U[1 + d] * ir; ke += W[1 + d] * W[1 + d]; }
+    double p = (gm - 1.0) * (U[D + 1] - 0.5 * rho * ke) - gm * pi;
+    W[D + 1] = p;
+    return (rho > 0.0) && (p + pi > 0.0) && isfinite(p);
+}
+
+__device__ __forceinline__ double csound(double gm, double pi, double rho, double p)
+{
+    return sqrt(gm * (p + pi) / rho);
+}
+
+// ---------------------------------------------------------------------------
+// WENO5 (Jiang & Shu), left-biased value at the right edge of v2, written
+// with a single division: the normalised nonlinear weights share the common
+// factor prod_r (eps + beta_r)^2.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double weno5(double v0, double v1, double v2, double v3, double v4, double eps)
+{
+    const double c13_12 = 13.0 / 12.0;
+    double q0 = (2.0 * v0 - 7.0 * v1 + 11.0 * v2) * (1.0 / 6.0);
+    double q1 = (-v1 + 5.0 * v2 + 2.0 * v3) * (1.0 / 6.0);
+    double q2 = (2.0 * v2 + 5.0 * v3 - v4) * (1.0 / 6.0);
+    double t0 = v0 - 2.0 * v1 + v2, u0 = v0 - 4.0 * v1 + 3.0 * v2;
+    double t1 = v1 - 2.0 * v2 + v3, u1 = v1 - v3;
+    double t2 = v2 - 2.0 * v3 + v4, u2 = 3.0 * v2 - 4.0 * v3 + v4;
+    double e0 = eps + c13_12 * t0 * t0 + 0.25 * u0 * u0;
+    double e1 = eps + c13_12 * t1 * t1 + 0.25 * u1 * u1;
+    double e2 = eps + c13_12 * t2 * t2 + 0.25 * u2 * u2;
+    double s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2;
+    double w0 = 0.1 * (s1 * s2), w1 = 0.6 * (s0 * s2), w2 = 0.3 * (s0 * s1);
+    return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
+}
+
+// ---------------------------------------------------------------------------
+// exact Riemann problem of two stiffened gases (wave curves in p + p_inf)
+// ---------------------------------------------------------------------------
+struct Side { double rho, u, p, g, pi; };
+
+__device__ __forceinline__ double wave_f(const Side& s, double p, double& df)
+{
+    double pk = s.p + s.pi, pb = p + s.pi;
+    if (p > s.p) {
+        double A = 2.0 / ((s.g + 1.0) * s.rho);
+        double B = (s.g - 1.0) / (s.g + 1.0) * pk;
+        double q = sqrt(A / (pb + B));
+        df = q * (1.0 - 0.5 * (p - s.p) / (pb + B));
+        return (p - s.p) * q;
+    }
+    double c = csound(s.g, s.pi, s.rho, s.p);
+    double r = pb / pk;
+    df = pow(r, -(s.g + 1.0) / (2.0 * s.g)) / (s.rho * c);
+    return 2.0 * c / (s.g - 1.0) * (pow(r, (s.g - 1.0) / (2.0 * s.g)) - 1.0);
+}
+
+__device__ __forceinline__ double star_rho(const Side& s, double ps)
+{
+    double pk = s.p + s.pi, pb = ps + s.pi;
+    if (pb <= 0.0) return 0.0;
+    if (ps > s.p) {
+        double m = (s.g - 1.0) / (s.g + 1.0);
+        return s.rho * (pb / pk + m) / (m * pb / pk + 1.0);
+    }
+    return s.rho * pow(pb / pk, 1.0 / s.g);
+}
+
+// out: p*, u*, rho*_L, rho*_R
+__device__ inline void riemann(const Side& L, const Side& R, double* out)
+{
+    double du = R.u - L.u, dfl, dfr;
+    double pfloor = -(L.pi < R.pi ? L.pi : R.pi);
+    double p;
+    double f0 = wave_f(L, pfloor, dfl) + wave_f(R, pfloor, dfr) + du;
+    if (f0 >= 0.0) {
+        p = pfloor;
+    } else {
+        double cL = csound(L.g, L.pi, L.rho, L.p), cR = csound(R.g, R.pi, R.rho, R.p);
+        p = 0.5 * (L.p + R.p) - 0.125 * du * (L.rho + R.rho) * (cL + cR);
+        double pmax = L.p > R.p ? L.p : R.p;
+        if (!(p > pfloor)) p = pfloor + 0.5 * (pmax - pfloor);
+        double lo = pfloor, hi = INFINITY;
+        double scale = fabs(L.pi) + fabs(R.pi) + 1e-300;
+        for (int it = 1; it <= 200; it++) {
+            double f = wave_f(L, p, dfl) + wave_f(R, p, dfr) + du;
+            if (f > 0.0) { if (p < hi) hi = p; }
+            else { if (p > lo) lo = p; }
+            double pn = p - f / (dfl + dfr);
+            if (!(pn > lo && pn < hi)) pn = isfinite(hi) ? 0.5 * (lo + hi) : lo + 2.0 * (p - lo);
+            double dp = pn - p;
+            p = pn;
+            if (fabs(dp) <= 1e-13 * (fabs(p) + scale)) break;
+        }
+    }
+    double fl = wave_f(L, p, dfl), fr = wave_f(R, p, dfr);
+    out[0] = p;
+    out[1] = 0.5 * (L.u + R.u) + 0.5 * (fr - fl);
+    out[2] = star_rho(L, p);
+    out[3] = star_rho(R, p);
+}
+
+// ---------------------------------------------------------------------------
+// geometry of the level set (vertex = mean of the adjacent cell centres,
+// interface linear along every cell edge)
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double edge_frac(double a, double b)
+{
+    bool na = a < 0.0, nb = b < 0.0;
+    if (na && nb) return 1.0;
+    if (!na && !nb) return 0.0;
+    double t = a / (a - b);
+    return na ? t : 1.0 - t;
+}
+
+// wetted area of the unit square with corner values v0..v3 at (0,0),(1,0),(1,1),(0,1)
+__device__ __forceinline__ double clip_area(const double* v)
+{
+    const double cx[4] = {0.0, 1.0, 1.0, 0.0}, cy[4] = {0.0, 0.0, 1.0, 1.0};
+    double px[8], py[8];
+    int m = 0;
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+        int a = e, b = (e + 1) & 3;
+        if (v[a] < 0.0) { px[m] = cx[a]; py[m] = cy[a]; m++; }
+        if ((v[a] < 0.0) != (v[b] < 0.0)) {
+            double t = v[a] / (v[a] - v[b]);
+            px[m] = cx[a] + t * (cx[b] - cx[a]);
+            py[m] = cy[a] + t * (cy[b] - cy[a]);
+            m++;
+        }
+    }
+    double area = 0.0;
+    for (int e = 0; e < m; e++) {
+        int f = (e + 1 == m) ? 0 : e + 1;
+        area += px[e] * py[f] - px[f] * py[e];
+    }
+    area = 0.5 * fabs(area);
+    return area > 1.0 ? 1.0 : area;
+}
+
+}  // namespace sharp

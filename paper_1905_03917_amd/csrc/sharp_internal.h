@@ -1,0 +1,53 @@
+// sharp_internal.h -- host-side simulation object shared by the engine
+// (sharp_kernels.hip) and the C ABI (sharp_capi.hip).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/sharp.h"
+#include "sharp_device.h"
+
+namespace sharp {
+
+struct Sim {
+    Dev g;                 // device view (pointers live in device memory)
+    sim_opts o;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int max_blocks = 2048; // grid-stride bound for tile-list kernels
+    bool has_state = false;
+    double t = 0.0;
+    int wcur = 0;          // Jacobi buffer holding the latest primitives
+    int vcur = 0;          // Jacobi buffer holding the latest level-set velocity
+    unsigned long long* h_red = nullptr;  // pinned readback of the reductions
+    std::vector<void*> dev_allocs;
+    // kernel timing of the bulk stage kernel
+    bool prof = false;
+    std::vector<hipEvent_t> ev_pool;
+    size_t ev_used = 0;
+    std::vector<long long> prof_cells;
+    double prof_ms = 0.0;
+    long long prof_launches = 0, prof_bytes = 0;
+    long long bulk_cells[2] = {0, 0};   // cells in the bulk lists (host copy)
+};
+
+void set_error(const char* fmt, ...);
+
+// engine entry points (sharp_kernels.hip)
+sim_status engine_set_state(Sim& s, const double* phi_dev, const double* prim_dev);
+sim_status engine_advance(Sim& s, double t_end, int mode, long long max_cycles, sim_stats* st);
+sim_status engine_bflux(Sim& s, double out[2][5]);
+
+#define SHARP_HIP(call)                                                              \
+    do {                                                                             \
+        hipError_t e_ = (call);                                                      \
+        if (e_ != hipSuccess) {                                                      \
+            ::sharp::set_error("%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                               __FILE__, __LINE__);                                  \
+            return SIM_EDEVICE;                                                      \
+        }                                                                            \
+    } while (0)
+
+}  // namespace sharp

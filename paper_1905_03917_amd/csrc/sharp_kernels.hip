@@ -1,0 +1,1419 @@
+// sharp_kernels.hip -- gfx950 kernels of the accelerated sharp-interface method
+// (Long, Cai & Pan): cut-cell WENO5-LLF finite-volume stages (Sec. 2.1,
+// Eq. Eulerdiscrete), level-set geometry, interface interaction, extension,
+// mixing, level-set advection and reinitialisation (Sec. 2.2-2.3), and the
+// bookkeeping of the accelerated cycle (Sec. 3.1: interpolation, Eq.
+// interpolation; interfacial flux correction, Eqs. firstcorrection and
+// secondcorrection).
+//
+// Work is organised in tiles of 256 cells (1-D 256, 2-D 16x16, 3-D 8x8x4).
+// Every kernel walks a device-resident tile list with a grid-stride loop, so
+// the host never reads list sizes back: bulk tiles of one fluid (no interface
+// within reach of the stencil) take the lean path, band tiles (the level-set
+// band, dilated by one tile) take the cut-cell path.  All per-cell state is
+// structure-of-arrays FP64 in HBM, x fastest, so a wavefront reads 64
+// consecutive doubles of one component.
+#include <cmath>
+#include <cstring>
+
+#include "sharp_internal.h"
+
+namespace sharp {
+
+template <int D> struct Tile;
+template <> struct Tile<1> { static constexpr int X = 256, Y = 1, Z = 1; };
+template <> struct Tile<2> { static constexpr int X = 16, Y = 16, Z = 1; };
+template <> struct Tile<3> { static constexpr int X = 8, Y = 8, Z = 4; };
+
+// origin of tile t and the cell handled by this thread; false if outside the domain
+template <int D>
+__device__ __forceinline__ bool tile_cell(const Dev& g, int t, int tid, int& i, int& j, int& k)
+{
+    int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1], tz = t / (g.nt[0] * g.nt[1]);
+    i = tx * Tile<D>::X + tid % Tile<D>::X;
+    j = ty * Tile<D>::Y + (tid / Tile<D>::X) % Tile<D>::Y;
+    k = tz * Tile<D>::Z + tid / (Tile<D>::X * Tile<D>::Y);
+    return i < g.n[0] && j < g.n[1] && k < g.n[2];
+}
+
+__device__ __forceinline__ int list_count(const Dev& g, int list) { return g.counts[list]; }
+__device__ __forceinline__ const int* list_ptr(const Dev& g, int list) { return g.lists + (size_t)list * g.ntiles; }
+
+__device__ __forceinline__ void flag_error(const Dev& g, unsigned long long bits)
+{
+    atomicOr(&g.red[4], bits);
+}
+
+// ---------------------------------------------------------------------------
+// band mask: a cell is in the band when it or an axis neighbour is closer
+// than ls_band cells to the interface; marks tiles holding band cells
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_mask(Dev g, int list, int check_ring)
+{
+    __shared__ int any;
+    const int* L = list_ptr(g, list);
+    double R = g.lsb * g.h;
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int t = L[ti];
+        if (threadIdx.x == 0) any = 0;
+        __syncthreads();
+        int i, j, k;
+        if (tile_cell<D>(g, t, threadIdx.x, i, j, k)) {
+            int c = i + g.n[0] * (j + g.n[1] * k);
+            double m = fabs(g.phiP[c]);
+#pragma unroll
+            for (int d = 0; d < D; d++) {
+                m = fmin(m, fabs(g.phiP[nbr(g, c, d, -1)]));
+                m = fmin(m, fabs(g.phiP[nbr(g, c, d, 1)]));
+            }
+            uint8_t in = m < R;
+            g.M[c] = in;
+            if (in) {
+                any = 1;
+                if (check_ring && (g.tflag[t] & 4)) flag_error(g, ERR_BAND_OVERFLOW);
+            }
+        }
+        __syncthreads();
+        if (threadIdx.x == 0) g.tcore[t] = any;
+        __syncthreads();
+    }
+}
+
+// tile classification: band = within one tile of a core tile, candidate =
+// within two, ring = band tile with a non-band neighbour
+__device__ __forceinline__ int tile_nbr(const Dev& g, int t, int dx, int dy, int dz)
+{
+    int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1], tz = t / (g.nt[0] * g.nt[1]);
+    int o[3] = {tx + dx, ty + dy, tz + dz};
+    for (int d = 0; d < 3; d++) {
+        if (o[d] < 0 || o[d] >= g.nt[d]) {
+            if (d < g.D && g.bc[d] == 1) o[d] = (o[d] + g.nt[d]) % g.nt[d];
+            else return -1;
+        }
+    }
+    return o[0] + g.nt[0] * (o[1] + g.nt[1] * o[2]);
+}
+
+template <int D>
+__global__ void k_tiles1(Dev g)
+{
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.ntiles; t += gridDim.x * blockDim.x) {
+        int band = 0, cand = 0;
+        int r2y = D > 1 ? 2 : 0, r2z = D > 2 ? 2 : 0;
+        for (int dz = -r2z; dz <= r2z; dz++)
+            for (int dy = -r2y; dy <= r2y; dy++)
+                for (int dx = -2; dx <= 2; dx++) {
+                    int u = tile_nbr(g, t, dx, dy, dz);
+                    if (u < 0 || !g.tcore[u]) continue;
+                    cand = 1;
+                    if (abs(dx) <= 1 && abs(dy) <= 1 && abs(dz) <= 1) band = 1;
+                }
+        g.tflag[t] = band | (cand << 1);
+        int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1], tz = t / (g.nt[0] * g.nt[1]);
+        int c = tx * Tile<D>::X + g.n[0] * (ty * Tile<D>::Y + g.n[1] * (tz * Tile<D>::Z));
+        g.tsign[t] = g.phiP[c] < 0.0 ? 0 : 1;
+    }
+}
+
+template <int D>
+__global__ void k_tiles2(Dev g)
+{
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.ntiles; t += gridDim.x * blockDim.x) {
+        int f = g.tflag[t];
+        if (!(f & 1)) continue;
+        int ring = 0;
+        int ry = D > 1 ? 1 : 0, rz = D > 2 ? 1 : 0;
+        for (int dz = -rz; dz <= rz; dz++)
+            for (int dy = -ry; dy <= ry; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    int u = tile_nbr(g, t, dx, dy, dz);
+                    if (u >= 0 && !(g.tflag[u] & 1)) ring = 1;
+                }
+        g.tflag[t] = f | (ring << 2);
+    }
+}
+
+// cells of tile t inside the domain
+__device__ __forceinline__ int tile_cells(const Dev& g, int t)
+{
+    int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1], tz = t / (g.nt[0] * g.nt[1]);
+    int o[3] = {tx * g.T[0], ty * g.T[1], tz * g.T[2]};
+    int n = 1;
+    for (int d = 0; d < 3; d++) n *= min(g.T[d], g.n[d] - o[d]);
+    return n;
+}
+
+// single-block compaction of the four tile lists (and their cell counts)
+__global__ void __launch_bounds__(1024) k_compact(Dev g)
+{
+    __shared__ int cnt[4][1024];
+    __shared__ int ccl[4][1024];
+    int nt = g.ntiles, tid = threadIdx.x, nth = blockDim.x;
+    int chunk = (nt + nth - 1) / nth;
+    int lo = tid * chunk, hi = min(nt, lo + chunk);
+    int c[4] = {0, 0, 0, 0}, cc[4] = {0, 0, 0, 0};
+    for (int t = lo; t < hi; t++) {
+        int f = g.tflag[t], nc = tile_cells(g, t);
+        if (f & 1) { c[0]++; cc[0] += nc; }
+        if (f & 2) { c[1]++; cc[1] += nc; }
+        if (!(f & 1)) { c[2 + g.tsign[t]]++; cc[2 + g.tsign[t]] += nc; }
+    }
+    for (int l = 0; l < 4; l++) { cnt[l][tid] = c[l]; ccl[l][tid] = cc[l]; }
+    __syncthreads();
+    for (int off = nth / 2; off > 0; off >>= 1) {
+        if (tid < off)
+            for (int l = 0; l < 4; l++) ccl[l][tid] += ccl[l][tid + off];
+        __syncthreads();
+    }
+    if (tid == 0)
+        for (int l = 0; l < 4; l++) g.counts[8 + l] = ccl[l][0];
+    // exclusive scan (Hillis-Steele on a copy)
+    for (int off = 1; off < nth; off <<= 1) {
+        int v[4];
+        for (int l = 0; l < 4; l++) v[l] = tid >= off ? cnt[l][tid - off] : 0;
+        __syncthreads();
+        for (int l = 0; l < 4; l++) cnt[l][tid] += v[l];
+        __syncthreads();
+    }
+    int base[4];
+    for (int l = 0; l < 4; l++) base[l] = cnt[l][tid] - c[l];
+    if (tid == nth - 1)
+        for (int l = 0; l < 4; l++) g.counts[l] = cnt[l][tid];
+    for (int t = lo; t < hi; t++) {
+        int f = g.tflag[t];
+        if (f & 1) g.lists[(size_t)LIST_BAND * nt + base[0]++] = t;
+        if (f & 2) g.lists[(size_t)LIST_CAND * nt + base[1]++] = t;
+        if (!(f & 1)) {
+            int l = 2 + g.tsign[t];
+            g.lists[(size_t)l * nt + base[l]++] = t;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// geometry: volume fraction and low-face apertures of every cell of the
+// listed tiles (plus the padded high faces on the domain boundary)
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ double vertex(const Dev& g, const double* cur, int i, int j, int k)
+{
+    double s = 0.0;
+#pragma unroll
+    for (int b = 0; b < (1 << D); b++) {
+        int ii = i - 1 + (b & 1);
+        int jj = D > 1 ? j - 1 + ((b >> 1) & 1) : 0;
+        int kk = D > 2 ? k - 1 + ((b >> 2) & 1) : 0;
+        s += phi_at(g, cur, cidx(g, ii, jj, kk));
+    }
+    return s / (double)(1 << D);
+}
+
+template <int D>
+__device__ __forceinline__ double aperture(const Dev& g, const double* cur, int d, int i, int j, int k)
+{
+    if (D == 1) return vertex<D>(g, cur, i, j, k) < 0.0 ? 1.0 : 0.0;
+    if (D == 2) {
+        if (d == 0) return edge_frac(vertex<D>(g, cur, i, j, k), vertex<D>(g, cur, i, j + 1, k));
+        return edge_frac(vertex<D>(g, cur, i, j, k), vertex<D>(g, cur, i + 1, j, k));
+    }
+    double v[4];
+    if (d == 0) {
+        v[0] = vertex<D>(g, cur, i, j, k);         v[1] = vertex<D>(g, cur, i, j + 1, k);
+        v[2] = vertex<D>(g, cur, i, j + 1, k + 1); v[3] = vertex<D>(g, cur, i, j, k + 1);
+    } else if (d == 1) {
+        v[0] = vertex<D>(g, cur, i, j, k);         v[1] = vertex<D>(g, cur, i + 1, j, k);
+        v[2] = vertex<D>(g, cur, i + 1, j, k + 1); v[3] = vertex<D>(g, cur, i, j, k + 1);
+    } else {
+        v[0] = vertex<D>(g, cur, i, j, k);         v[1] = vertex<D>(g, cur, i + 1, j, k);
+        v[2] = vertex<D>(g, cur, i + 1, j + 1, k); v[3] = vertex<D>(g, cur, i, j + 1, k);
+    }
+    return clip_area(v);
+}
+
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_geom(Dev g, int list, const double* cur)
+{
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, k;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, k)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * k);
+        int ii[3] = {i, j, k};
+        double alo[3], ahi[3];
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            alo[d] = aperture<D>(g, cur, d, i, j, k);
+            ahi[d] = aperture<D>(g, cur, d, i + (d == 0), j + (d == 1), k + (d == 2));
+            g.ap[d][fidx(g, i, j, k)] = alo[d];
+            if (ii[d] == g.n[d] - 1) g.ap[d][fidx(g, i + (d == 0), j + (d == 1), k + (d == 2))] = ahi[d];
+        }
+        double a;
+        if (D == 1) {
+            a = edge_frac(vertex<D>(g, cur, i, 0, 0), vertex<D>(g, cur, i + 1, 0, 0));
+        } else if (D == 2) {
+            double v[4] = {vertex<D>(g, cur, i, j, 0), vertex<D>(g, cur, i + 1, j, 0),
+                           vertex<D>(g, cur, i + 1, j + 1, 0), vertex<D>(g, cur, i, j + 1, 0)};
+            a = clip_area(v);
+        } else {
+            // divergence theorem on the wetted part of the unit cube, planar cut
+            double sumA = 0.0, g2 = 0.0;
+#pragma unroll
+            for (int d = 0; d < 3; d++) {
+                sumA += alo[d] + ahi[d];
+                double gd = alo[d] - ahi[d];
+                g2 += gd * gd;
+            }
+            a = (0.5 * sumA + sqrt(g2) * (-phi_at(g, cur, c) / g.h)) / 3.0;
+            a = a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a);
+        }
+        g.alpha[c] = a;
+    }
+}
+
+// interface segment per unit volume of fluid 0 (points into fluid 1)
+template <int D>
+__device__ __forceinline__ double iface(const Dev& g, int i, int j, int k, double* gv)
+{
+    double g2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        gv[d] = (g.ap[d][fidx(g, i, j, k)] - g.ap[d][fidx(g, i + (d == 0), j + (d == 1), k + (d == 2))]) / g.h;
+        g2 += gv[d] * gv[d];
+    }
+    return sqrt(g2);
+}
+
+__device__ __forceinline__ double alpha_k(const Dev& g, int k, int c)
+{
+    double a = g.alpha[c];
+    return k == 0 ? a : 1.0 - a;
+}
+
+template <int D>
+__device__ __forceinline__ double grad_phi(const Dev& g, const double* cur, int c, double* gr)
+{
+    double g2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        gr[d] = (phi_at(g, cur, nbr(g, c, d, 1)) - phi_at(g, cur, nbr(g, c, d, -1))) / (2.0 * g.h);
+        g2 += gr[d] * gr[d];
+    }
+    return sqrt(g2);
+}
+
+// ---------------------------------------------------------------------------
+// elementwise helpers over listed tiles
+// ---------------------------------------------------------------------------
+// dst = a1 * src1 + a2 * src2 on ncomp components
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_axpby(Dev g, int list, double a1, const double* s1, double a2,
+                                                   const double* s2, double* dst, int ncomp)
+{
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, k;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, k)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * k);
+        for (int q = 0; q < ncomp; q++) {
+            size_t e = (size_t)q * g.nc + c;
+            dst[e] = s2 ? a1 * s1[e] + a2 * s2[e] : s1[e];
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// small-cell mixing (Sec. 2.2): increments in gather form
+// ---------------------------------------------------------------------------
+template <int D>
+__device__ __forceinline__ bool mix_source(const Dev& g, const double* cur, int k, int c, double* beta, int* tgt)
+{
+    double as = alpha_k(g, k, c);
+    if (!(as < g.amix) || !(fabs(phi_at(g, cur, c)) <= g.mixb * g.h)) return false;
+    double gr[3];
+    double gm = grad_phi<D>(g, cur, c, gr);
+    if (!(gm > 0.0)) return false;
+    double dir[3] = {0.0, 0.0, 0.0};
+    int sx[3] = {1, 1, 1};
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        dir[d] = (k == 0 ? -1.0 : 1.0) * gr[d] / gm;
+        sx[d] = dir[d] < 0.0 ? -1 : 1;
+    }
+    const int nsub = (1 << D) - 1;
+    double bsum = 0.0;
+    for (int m = 1; m <= nsub; m++) {
+        int cnt = 0;
+        double prod = 1.0;
+        for (int d = 0; d < D; d++)
+            if (m & (1 << d)) { cnt++; prod *= fabs(dir[d]); }
+        double b = cnt == 1 ? prod * prod : (cnt == 2 ? prod : pow(prod, 2.0 / 3.0));
+        beta[m - 1] = b;
+        bsum += b;
+    }
+    int i, j, kk;
+    coords(g, c, i, j, kk);
+    for (int m = 1; m <= nsub; m++) {
+        beta[m - 1] /= bsum;
+        tgt[m - 1] = cidx(g, i + ((m & 1) ? sx[0] : 0), j + ((m & 2) ? sx[1] : 0), kk + ((m & 4) ? sx[2] : 0));
+    }
+    return true;
+}
+
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_mixdelta(Dev g, int list, int k, const double* cons, const double* cur)
+{
+    constexpr int NV = D + 2;
+    constexpr int NS = (1 << D) - 1;
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        if (!g.M[c]) continue;
+        double dl[NV];
+        for (int q = 0; q < NV; q++) dl[q] = 0.0;
+        double beta[7];
+        int tgt[7];
+        double ac = alpha_k(g, k, c);
+        // c as a source
+        if (mix_source<D>(g, cur, k, c, beta, tgt)) {
+            for (int m = 0; m < NS; m++) {
+                int t = tgt[m];
+                if (!(beta[m] > 0.0) || t == c) continue;
+                double at = alpha_k(g, k, t);
+                if (!(ac + at > 0.0)) continue;
+                for (int q = 0; q < NV; q++)
+                    dl[q] += beta[m] * (cons[(size_t)q * g.nc + t] * ac - cons[(size_t)q * g.nc + c] * at) / (ac + at);
+            }
+        }
+        // c as a target of its neighbours (distinct neighbour cells only)
+        int seen[26];
+        int ns = 0;
+        bool edge = false;
+        {
+            int ii[3] = {i, j, kk};
+            for (int d = 0; d < D; d++)
+                if (ii[d] == 0 || ii[d] == g.n[d] - 1) edge = true;
+        }
+        int rz = D > 2 ? 1 : 0, ry = D > 1 ? 1 : 0;
+        for (int oz = -rz; oz <= rz; oz++)
+            for (int oy = -ry; oy <= ry; oy++)
+                for (int ox = -1; ox <= 1; ox++) {
+                    if (!ox && !oy && !oz) continue;
+                    int s = cidx(g, i + ox, j + oy, kk + oz);
+                    if (s == c) continue;
+                    if (edge) {
+                        bool dup = false;
+                        for (int u = 0; u < ns; u++) dup |= (seen[u] == s);
+                        if (dup) continue;
+                        seen[ns++] = s;
+                    }
+                    if (!mix_source<D>(g, cur, k, s, beta, tgt)) continue;
+                    double as = alpha_k(g, k, s);
+                    if (!(as + ac > 0.0)) continue;
+                    for (int m = 0; m < NS; m++) {
+                        if (tgt[m] != c || !(beta[m] > 0.0)) continue;
+                        for (int q = 0; q < NV; q++)
+                            dl[q] -= beta[m] * (cons[(size_t)q * g.nc + c] * as - cons[(size_t)q * g.nc + s] * ac) / (as + ac);
+                    }
+                }
+        for (int q = 0; q < NV; q++) g.dmix[(size_t)q * g.nc + c] = dl[q];
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_mixapply(Dev g, int list, double* cons)
+{
+    constexpr int NV = D + 2;
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, k;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, k)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * k);
+        if (!g.M[c]) continue;
+        for (int q = 0; q < NV; q++) cons[(size_t)q * g.nc + c] += g.dmix[(size_t)q * g.nc + c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// primitive recovery on real band cells (alpha_k >= alpha_mix)
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_prims(Dev g, int list, int k, const double* src, int wb)
+{
+    constexpr int NV = D + 2;
+    const int* L = list_ptr(g, list);
+    double* W = g.Wb[k][wb];
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        if (!g.M[c]) continue;
+        double a = alpha_k(g, k, c);
+        if (a < g.amix) continue;
+        double U[NV], w[NV];
+        for (int q = 0; q < NV; q++) U[q] = src[(size_t)q * g.nc + c] / a;
+        if (!cons2prim<D>(g.gam[k], g.pinf[k], U, w)) flag_error(g, ERR_NONPHYS);
+        for (int q = 0; q < NV; q++) W[(size_t)q * g.nc + c] = w[q];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// extension: one Jacobi sweep of the upwind steady state of
+// dq/dtau + n.grad q = 0 for both fluids' primitives
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_extw(Dev g, int list, int in, int out, const double* cur)
+{
+    constexpr int NV = D + 2;
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        if (!g.M[c]) continue;
+        double ph = phi_at(g, cur, c);
+        double gr[3];
+        double gm = -1.0;
+        for (int k = 0; k < 2; k++) {
+            const double* Wi = g.Wb[k][in];
+            double* Wo = g.Wb[k][out];
+            double sk = k == 0 ? 1.0 : -1.0;
+            bool target = alpha_k(g, k, c) < g.amix && !(sk * ph > g.extb * g.h);
+            if (target && gm < 0.0) gm = grad_phi<D>(g, cur, c, gr);
+            if (!target || !(gm > 0.0)) {
+                for (int q = 0; q < NV; q++) Wo[(size_t)q * g.nc + c] = Wi[(size_t)q * g.nc + c];
+                continue;
+            }
+            int up[3];
+            double w[3], wsum = 0.0;
+            for (int d = 0; d < D; d++) {
+                double nd = sk * gr[d] / gm;
+                up[d] = nbr(g, c, d, nd > 0.0 ? -1 : 1);
+                w[d] = fabs(nd);
+                wsum += w[d];
+            }
+            for (int q = 0; q < NV; q++) {
+                double acc = 0.0;
+                for (int d = 0; d < D; d++) acc += w[d] * Wi[(size_t)q * g.nc + up[d]];
+                Wo[(size_t)q * g.nc + c] = acc / wsum;
+            }
+        }
+    }
+}
+
+// level-set velocity: from the cut cells to the rest of the band
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_extv(Dev g, int list, int in, int out, const double* cur)
+{
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        if (!g.M[c]) continue;
+        double gv[3];
+        bool cut = iface<D>(g, i, j, kk, gv) > 0.0;
+        double gr[3];
+        double gm = cut ? 0.0 : grad_phi<D>(g, cur, c, gr);
+        if (cut || !(gm > 0.0)) {
+            for (int e = 0; e < D; e++) g.v[out][e][c] = g.v[in][e][c];
+            continue;
+        }
+        double sg = phi_at(g, cur, c) < 0.0 ? -1.0 : 1.0;
+        int up[3];
+        double w[3], wsum = 0.0;
+        for (int d = 0; d < D; d++) {
+            double nd = sg * gr[d] / gm;
+            up[d] = nbr(g, c, d, nd > 0.0 ? -1 : 1);
+            w[d] = fabs(nd);
+            wsum += w[d];
+        }
+        for (int e = 0; e < D; e++) {
+            double acc = 0.0;
+            for (int d = 0; d < D; d++) acc += w[d] * g.v[in][e][up[d]];
+            g.v[out][e][c] = acc / wsum;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// interface interaction: exact Riemann problem per cut cell; exchange term of
+// fluid 0 per unit volume X/dV = (0, -p* g, -p* u* |g|); optionally books
+// wcorr * X_slow into the interfacial flux correction
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_interact(Dev g, int list, int wb, int vb, double wcorr, int S)
+{
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        double gv[3];
+        double gm = iface<D>(g, i, j, kk, gv);
+        if (!(gm > 0.0)) {
+            g.ps[c] = 0.0; g.us[c] = 0.0; g.ss[0][c] = 0.0; g.ss[1][c] = 0.0;
+            continue;
+        }
+        const double* W0 = g.Wb[0][wb];
+        const double* W1 = g.Wb[1][wb];
+        double un0 = 0.0, un1 = 0.0;
+        for (int d = 0; d < D; d++) {
+            un0 += W0[(size_t)(1 + d) * g.nc + c] * gv[d] / gm;
+            un1 += W1[(size_t)(1 + d) * g.nc + c] * gv[d] / gm;
+        }
+        Side Ls = {W0[c], un0, W0[(size_t)(D + 1) * g.nc + c], g.gam[0], g.pinf[0]};
+        Side Rs = {W1[c], un1, W1[(size_t)(D + 1) * g.nc + c], g.gam[1], g.pinf[1]};
+        double st[4];
+        riemann(Ls, Rs, st);
+        g.ps[c] = st[0];
+        g.us[c] = st[1];
+        for (int k = 0; k < 2; k++) {
+            double rs = st[2 + k];
+            double cs = rs > 0.0 ? csound(g.gam[k], g.pinf[k], rs, st[0]) : 0.0;
+            double sum = 0.0;
+            for (int d = 0; d < D; d++) sum += (fabs(st[1] * gv[d] / gm) + cs) / g.h;
+            g.ss[k][c] = sum;
+        }
+        for (int d = 0; d < D; d++) g.v[vb][d][c] = st[1] * gv[d] / gm;
+        if (wcorr != 0.0) {
+            double sg = S == 0 ? 1.0 : -1.0;
+            for (int d = 0; d < D; d++) g.corr[(size_t)(1 + d) * g.nc + c] += wcorr * (-sg * st[0] * gv[d]);
+            g.corr[(size_t)(D + 1) * g.nc + c] += wcorr * (-sg * st[0] * st[1] * gm);
+        }
+    }
+}
+
+// corr += w * X_slow from the stored interface solution (cycle start)
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_corr_add(Dev g, int list, double w, int S)
+{
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        double gv[3];
+        double gm = iface<D>(g, i, j, kk, gv);
+        if (!(gm > 0.0)) continue;
+        double sg = S == 0 ? 1.0 : -1.0, p = g.ps[c];
+        for (int d = 0; d < D; d++) g.corr[(size_t)(1 + d) * g.nc + c] += w * (-sg * p * gv[d]);
+        g.corr[(size_t)(D + 1) * g.nc + c] += w * (-sg * p * g.us[c] * gm);
+    }
+}
+
+// slow fluid += correction; the correction is reset for the next cycle
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_corr_apply(Dev g, int list, int S, int apply)
+{
+    constexpr int NV = D + 2;
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        for (int q = 1; q < NV; q++) {
+            size_t e = (size_t)q * g.nc + c;
+            if (apply) g.X[S][e] += g.corr[e];
+            g.corr[e] = 0.0;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// CFL: max over cells holding fluid k of sum_d (|u_d| + c)/dx, with the star
+// state of cut cells; also counts the cells holding the fluid
+// ---------------------------------------------------------------------------
+template <int D, bool BAND>
+__global__ void __launch_bounds__(SHARP_WG) k_cfl(Dev g, int list, int k, const double* cons, int wb)
+{
+    constexpr int NV = D + 2;
+    __shared__ double smax[SHARP_WG / 64];
+    __shared__ unsigned long long scnt[SHARP_WG / 64];
+    const int* L = list_ptr(g, list);
+    double mx = 0.0;
+    unsigned long long cnt = 0;
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        double a = BAND ? alpha_k(g, k, c) : 1.0;
+        if (!(a > 0.0)) continue;
+        cnt++;
+        double W[NV];
+        if (BAND && (g.M[c] || a < g.amix)) {
+            for (int q = 0; q < NV; q++) W[q] = g.Wb[k][wb][(size_t)q * g.nc + c];
+        } else {
+            double U[NV];
+            for (int q = 0; q < NV; q++) U[q] = cons[(size_t)q * g.nc + c] / a;
+            if (!cons2prim<D>(g.gam[k], g.pinf[k], U, W)) flag_error(g, ERR_NONPHYS);
+        }
+        double cs = csound(g.gam[k], g.pinf[k], W[0], W[D + 1]), s = 0.0;
+        for (int d = 0; d < D; d++) s += (fabs(W[1 + d]) + cs) / g.h;
+        mx = fmax(mx, s);
+        if (BAND) mx = fmax(mx, g.ss[k][c]);
+    }
+    // wavefront then block reduction (max is order independent)
+    for (int off = 32; off > 0; off >>= 1) {
+        mx = fmax(mx, __shfl_down(mx, off, 64));
+        cnt += __shfl_down(cnt, off, 64);
+    }
+    int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) { smax[wid] = mx; scnt[wid] = cnt; }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        for (int w = 1; w < SHARP_WG / 64; w++) { mx = fmax(mx, smax[w]); cnt += scnt[w]; }
+        if (!(mx >= 0.0) || isinf(mx)) { flag_error(g, ERR_NONPHYS); mx = 0.0; }
+        atomicMax(&g.red[k], (unsigned long long)__double_as_longlong(mx));
+        atomicAdd(&g.red[2 + k], cnt);
+    }
+}
+
+__global__ void k_zero_red(Dev g)
+{
+    if (threadIdx.x < 4) g.red[threadIdx.x] = 0ull;
+}
+
+// ---------------------------------------------------------------------------
+// one Shu-Osher stage of fluid k:
+//   out = a*base + (1-a)*(self + dt*L),  L = sum_d (A_lo F_lo - A_hi F_hi)/dx + X/dV
+// Face fluxes of a tile are computed once into LDS (the high faces of the
+// tile edge are recomputed by the neighbour tile), then combined per cell.
+// BAND: apertures, ghost states, exchange term, optional override `self2`
+// (read instead of `in` at band-mask cells: the slow fluid's mixed state).
+// ---------------------------------------------------------------------------
+template <int D> struct FaceCount;
+template <> struct FaceCount<1> { static constexpr int n0 = 257, n1 = 0, n2 = 0; };
+template <> struct FaceCount<2> { static constexpr int n0 = 17 * 16, n1 = 16 * 17, n2 = 0; };
+template <> struct FaceCount<3> { static constexpr int n0 = 9 * 8 * 4, n1 = 8 * 9 * 4, n2 = 8 * 8 * 5; };
+
+template <int D, bool BAND>
+__device__ __forceinline__ void load_state(const Dev& g, int k, const double* in, const double* self2, int wb,
+                                           int c, double* W, double* U)
+{
+    constexpr int NV = D + 2;
+    double a = BAND ? alpha_k(g, k, c) : 1.0;
+    if (BAND && a < g.amix) {
+        const double* Wg = g.Wb[k][wb];
+        for (int q = 0; q < NV; q++) W[q] = Wg[(size_t)q * g.nc + c];
+        prim2cons<D>(g.gam[k], g.pinf[k], W, U);
+        return;
+    }
+    const double* src = (BAND && self2 && g.M[c]) ? self2 : in;
+    if (BAND) {
+        for (int q = 0; q < NV; q++) U[q] = src[(size_t)q * g.nc + c] / a;
+    } else {
+        for (int q = 0; q < NV; q++) U[q] = src[(size_t)q * g.nc + c];
+    }
+    cons2prim<D>(g.gam[k], g.pinf[k], U, W);
+}
+
+template <int D, bool BAND>
+__global__ void __launch_bounds__(SHARP_WG) k_stage(Dev g, int list, int k, const double* in, const double* self2,
+                                                   const double* base, double* out, double a, double dt,
+                                                   double wflux, int wb)
+{
+    constexpr int NV = D + 2;
+    constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
+    constexpr int F0 = FaceCount<D>::n0, F1 = FaceCount<D>::n1, F2 = FaceCount<D>::n2;
+    constexpr int FT = F0 + F1 + F2;
+    __shared__ double sF[FT * NV];
+    const int* L = list_ptr(g, list);
+    const double gm = g.gam[k], pi = g.pinf[k];
+    const double farea = D == 1 ? 1.0 : (D == 2 ? g.h : g.h * g.h);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int t = L[ti];
+        int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1], tz = t / (g.nt[0] * g.nt[1]);
+        int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
+        // ---- face fluxes ----
+        for (int f = threadIdx.x; f < FT; f += SHARP_WG) {
+            int d, li, lj, lk;
+            if (f < F0) { d = 0; li = f % (TX + 1); lj = (f / (TX + 1)) % TY; lk = f / ((TX + 1) * TY); }
+            else if (f < F0 + F1) { int r = f - F0; d = 1; li = r % TX; lj = (r / TX) % (TY + 1); lk = r / (TX * (TY + 1)); }
+            else { int r = f - F0 - F1; d = 2; li = r % TX; lj = (r / TX) % TY; lk = r / (TX * TY); }
+            int i = ox + li, j = oy + lj, kk = oz + lk;
+            int fi[3] = {i, j, kk};
+            bool ok = true;
+            for (int e = 0; e < 3; e++) ok &= (e == d) ? fi[e] <= g.n[e] : fi[e] < g.n[e];
+            double* Fo = sF + (size_t)f * NV;
+            if (!ok) { for (int q = 0; q < NV; q++) Fo[q] = 0.0; continue; }
+            double A = 1.0;
+            if (BAND) {
+                A = g.ap[d][fidx(g, i, j, kk)];
+                if (k == 1) A = 1.0 - A;
+                if (!(A > 0.0)) { for (int q = 0; q < NV; q++) Fo[q] = 0.0; continue; }
+            }
+            // six-cell stencil i-3 .. i+2 along d; face between m = 2 and m = 3
+            double Us[6][NV], Fs[6][NV];
+            double amax = 0.0;
+#pragma unroll
+            for (int m = 0; m < 6; m++) {
+                int off = m - 3;
+                int c = cidx(g, i + (d == 0) * off, j + (d == 1) * off, kk + (d == 2) * off);
+                double W[NV];
+                load_state<D, BAND>(g, k, in, self2, wb, c, W, Us[m]);
+                double un = W[1 + d], p = W[D + 1];
+                Fs[m][0] = Us[m][0] * un;
+#pragma unroll
+                for (int e = 0; e < D; e++) Fs[m][1 + e] = Us[m][1 + e] * un;
+                Fs[m][1 + d] += p;
+                Fs[m][D + 1] = (Us[m][D + 1] + p) * un;
+                amax = fmax(amax, fabs(un) + csound(gm, pi, W[0], p));
+            }
+#pragma unroll
+            for (int q = 0; q < NV; q++) {
+                double fp[5], fm[5];
+#pragma unroll
+                for (int m = 0; m < 5; m++) {
+                    fp[m] = 0.5 * (Fs[m][q] + amax * Us[m][q]);
+                    fm[m] = 0.5 * (Fs[m + 1][q] - amax * Us[m + 1][q]);
+                }
+                double Fh = weno5(fp[0], fp[1], fp[2], fp[3], fp[4], g.eps)
+                          + weno5(fm[4], fm[3], fm[2], fm[1], fm[0], g.eps);
+                Fo[q] = A * Fh;
+            }
+            // boundary-face inflow bookkeeping (zero-gradient boundaries)
+            if (g.bc[d] == 0 && wflux != 0.0 && (fi[d] == 0 || fi[d] == g.n[d])) {
+                int side = fi[d] == 0 ? 0 : 1;
+                int o1 = d == 0 ? j : i, o2 = d == 2 ? j : kk;
+                int n1 = d == 0 ? g.n[1] : g.n[0];
+                int b = g.bface_off[d][side] + o1 + n1 * o2;
+                double sgn = side == 0 ? 1.0 : -1.0;
+                for (int q = 0; q < NV; q++) g.bacc[k][(size_t)q * g.nbface + b] += sgn * wflux * farea * Fo[q];
+            }
+        }
+        __syncthreads();
+        // ---- cell update ----
+        {
+            int li = threadIdx.x % TX, lj = (threadIdx.x / TX) % TY, lk = threadIdx.x / (TX * TY);
+            int i = ox + li, j = oy + lj, kk = oz + lk;
+            if (i < g.n[0] && j < g.n[1] && kk < g.n[2]) {
+                int c = i + g.n[0] * (j + g.n[1] * kk);
+                double Lr[NV];
+                for (int q = 0; q < NV; q++) Lr[q] = 0.0;
+#pragma unroll
+                for (int d = 0; d < D; d++) {
+                    int flo, fhi;
+                    if (d == 0) { flo = li + (TX + 1) * (lj + TY * lk); fhi = flo + 1; }
+                    else if (d == 1) { flo = F0 + li + TX * (lj + (TY + 1) * lk); fhi = flo + TX; }
+                    else { flo = F0 + F1 + li + TX * (lj + TY * lk); fhi = flo + TX * TY; }
+                    for (int q = 0; q < NV; q++) Lr[q] += (sF[(size_t)flo * NV + q] - sF[(size_t)fhi * NV + q]) / g.h;
+                }
+                if (BAND) {
+                    double gv[3];
+                    double gn = iface<D>(g, i, j, kk, gv);
+                    if (gn > 0.0) {
+                        double sg = k == 0 ? 1.0 : -1.0, p = g.ps[c];
+                        for (int d = 0; d < D; d++) Lr[1 + d] += -sg * p * gv[d];
+                        Lr[D + 1] += -sg * p * g.us[c] * gn;
+                    }
+                }
+                const double* sin_ = (BAND && self2 && g.M[c]) ? self2 : in;
+                for (int q = 0; q < NV; q++) {
+                    size_t e = (size_t)q * g.nc + c;
+                    double s = sin_[e] + dt * Lr[q];
+                    out[e] = (a == 0.0) ? s : a * base[e] + (1.0 - a) * s;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// level set: one Shu-Osher stage of Eq. (LS:linearadvection), WENO5 upwind
+// derivatives, band cells only
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_ls(Dev g, int list, double a, double dt, const double* in, double* out,
+                                                int vb)
+{
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        if (!g.M[c]) continue;
+        double rhs = 0.0;
+        for (int d = 0; d < D; d++) {
+            double vd = g.v[vb][d][c];
+            if (vd == 0.0) continue;
+            double p[7];
+            for (int m = 0; m < 7; m++) p[m] = phi_at(g, in, cidx(g, i + (d == 0) * (m - 3), j + (d == 1) * (m - 3), kk + (d == 2) * (m - 3)));
+            double D1[6];
+            for (int m = 0; m < 6; m++) D1[m] = (p[m + 1] - p[m]) / g.h;
+            double der = vd > 0.0 ? weno5(D1[0], D1[1], D1[2], D1[3], D1[4], g.eps)
+                                  : weno5(D1[5], D1[4], D1[3], D1[2], D1[1], g.eps);
+            rhs -= vd * der;
+        }
+        double s = in[c] + dt * rhs;
+        out[c] = (a == 0.0) ? s : a * g.phiP[c] + (1.0 - a) * s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// reinitialisation: Godunov sweeps of phi_tau + S(phi0)(|grad phi| - 1) = 0,
+// cells near a sign change of phi0 are kept
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_nearif(Dev g, int list, const double* phi0)
+{
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        int neg = 0, pos = 0;
+        int rz = D > 2 ? 1 : 0, ry = D > 1 ? 1 : 0;
+        for (int dz = -rz; dz <= rz; dz++)
+            for (int dy = -ry; dy <= ry; dy++)
+                for (int dx = -1; dx <= 1; dx++) {
+                    double v = phi_at(g, phi0, cidx(g, i + dx, j + dy, kk + dz));
+                    if (v < 0.0) neg = 1; else pos = 1;
+                }
+        g.nearif[c] = (uint8_t)(neg && pos);
+    }
+}
+
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_reinit(Dev g, int list, const double* phi0, const double* in, double* out)
+{
+    const int* L = list_ptr(g, list);
+    const double h = g.h, dtau = 0.5 * g.h;
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        if (!g.M[c]) continue;
+        double pc = in[c];
+        bool frz = false;
+        int rz = D > 2 ? 1 : 0, ry = D > 1 ? 1 : 0;
+        for (int dz = -rz; dz <= rz; dz++)
+            for (int dy = -ry; dy <= ry; dy++)
+                for (int dx = -1; dx <= 1; dx++) frz |= g.nearif[cidx(g, i + dx, j + dy, kk + dz)] != 0;
+        if (frz) { out[c] = pc; continue; }
+        double p0 = phi0[c];
+        double S = p0 / sqrt(p0 * p0 + h * h), g2 = 0.0;
+        for (int d = 0; d < D; d++) {
+            double am = (pc - phi_at(g, in, nbr(g, c, d, -1))) / h;
+            double bp = (phi_at(g, in, nbr(g, c, d, 1)) - pc) / h;
+            double x, y;
+            if (S > 0.0) { x = am > 0.0 ? am : 0.0; y = bp < 0.0 ? bp : 0.0; }
+            else { x = am < 0.0 ? am : 0.0; y = bp > 0.0 ? bp : 0.0; }
+            g2 += (x * x > y * y) ? x * x : y * y;
+        }
+        out[c] = pc - dtau * S * (sqrt(g2) - 1.0);
+    }
+}
+
+// copy a scalar field on the band-mask cells (reinitialisation disabled)
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_copy_masked(Dev g, int list, const double* src, double* dst)
+{
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        if (g.M[c]) dst[c] = src[c];
+    }
+}
+
+// ---------------------------------------------------------------------------
+// initial state: cell contents alpha_k U_k of the given primitives; the
+// given primitives also start every ghost state
+// ---------------------------------------------------------------------------
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_init(Dev g, const double* prim)
+{
+    constexpr int NV = D + 2;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x) {
+        for (int k = 0; k < 2; k++) {
+            double W[NV], U[NV];
+            for (int q = 0; q < NV; q++) W[q] = prim[((size_t)k * NV + q) * g.nc + c];
+            prim2cons<D>(g.gam[k], g.pinf[k], W, U);
+            double a = alpha_k(g, k, c);
+            for (int q = 0; q < NV; q++) {
+                size_t e = (size_t)q * g.nc + c;
+                g.X[k][e] = a * U[q];
+                g.Wb[k][0][e] = W[q];
+                g.Wb[k][1][e] = W[q];
+            }
+        }
+    }
+}
+
+// ===========================================================================
+// Engine: the host-side schedule of kernels for one dimension D.  It mirrors
+// the method step by step: the original single-dt step and the accelerated
+// cycle of Sec. 3.1 (generalised from RK2 to any Shu-Osher table).
+// ===========================================================================
+static const double RK3_A[3] = {0.0, 0.75, 1.0 / 3.0};
+static const double RK3_C[3] = {0.0, 1.0, 0.5};
+static const double RK3_B[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
+static const double RK2_A[2] = {0.0, 0.5};
+static const double RK2_C[2] = {0.0, 1.0};
+static const double RK2_B[2] = {0.5, 0.5};
+
+// truncation of the step ratio n (Sec. 3.1): if the fractional part of
+// n = dt_slow/dt_fast is below the threshold, dt_slow is cut to floor(n) dt_fast
+static void plan_cycle(double dt_slow, double dt_fast, double remaining, double thr, double* dts, int* single)
+{
+    double n = dt_slow / dt_fast;
+    double fl = floor(n);
+    double d = (n - fl < thr) ? fl * dt_fast : dt_slow;
+    if (d > remaining) d = remaining;
+    *dts = d;
+    *single = !(d > dt_fast * (1.0 + 1e-12));
+}
+
+// next fast sub-step: stops exactly at t1 (and, for RK3, at t1/2)
+static double next_substep(double tau, double t1, double dt_fast, int rk, int half_done, int* hh, int* fin)
+{
+    *hh = 0;
+    *fin = 0;
+    double half = 0.5 * t1;
+    if (rk == 3 && !half_done && tau < half) {
+        if (tau + dt_fast * (1.0 + 1e-9) >= half) { *hh = 1; return half - tau; }
+        return dt_fast;
+    }
+    if (tau + dt_fast * (1.0 + 1e-9) >= t1) { *fin = 1; return t1 - tau; }
+    return dt_fast;
+}
+
+template <int D>
+struct Engine {
+    static constexpr int NV = D + 2;
+    Sim& s;
+    Dev& g;
+    explicit Engine(Sim& sim) : s(sim), g(sim.g) {}
+
+    dim3 grid() const { return dim3(s.max_blocks < g.ntiles ? s.max_blocks : g.ntiles); }
+    dim3 wg() const { return dim3(SHARP_WG); }
+
+    // ---- tiles and masks ----
+    void mask(int list, int ring) { k_mask<D><<<grid(), wg(), 0, s.stream>>>(g, list, ring); }
+    void tiles()
+    {
+        int b = (g.ntiles + 255) / 256;
+        k_tiles1<D><<<b, 256, 0, s.stream>>>(g);
+        k_tiles2<D><<<b, 256, 0, s.stream>>>(g);
+        k_compact<<<1, 1024, 0, s.stream>>>(g);
+    }
+    void geom(const double* cur, int list = LIST_BAND) { k_geom<D><<<grid(), wg(), 0, s.stream>>>(g, list, cur); }
+
+    // ---- band physics ----
+    void prims(int k, const double* src) { k_prims<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, k, src, s.wcur); }
+    void extw(const double* cur)
+    {
+        for (int it = 0; it < s.o.ext_iters; it++) {
+            k_extw<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, s.wcur, 1 - s.wcur, cur);
+            s.wcur ^= 1;
+        }
+    }
+    void interact(double wcorr, int S) { k_interact<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, s.wcur, s.vcur, wcorr, S); }
+    void extv(const double* cur)
+    {
+        for (int it = 0; it < s.o.ext_iters; it++) {
+            k_extv<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, s.vcur, 1 - s.vcur, cur);
+            s.vcur ^= 1;
+        }
+    }
+    void interaction(const double* cur, double wcorr, int S)
+    {
+        extw(cur);
+        interact(wcorr, S);
+        extv(cur);
+    }
+    void corr_add(double w, int S) { k_corr_add<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, w, S); }
+    void mix(int k, double* cons, const double* cur)
+    {
+        k_mixdelta<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, cur);
+        k_mixapply<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, cons);
+    }
+    void axpby(double a1, const double* s1, double a2, const double* s2, double* dst, int ncomp)
+    {
+        k_axpby<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, a1, s1, a2, s2, dst, ncomp);
+    }
+
+    // ---- stages ----
+    void stage(int k, const double* in, const double* self2, const double* base, double* out, double a, double dt,
+               double wflux)
+    {
+        int bl = k == 0 ? LIST_BULK0 : LIST_BULK1;
+        size_t ev = 0;
+        if (s.prof) {
+            if (s.ev_used + 2 > s.ev_pool.size()) profile_flush();
+            ev = s.ev_used;
+            s.ev_used += 2;
+            (void)hipEventRecord(s.ev_pool[ev], s.stream);
+        }
+        k_stage<D, false><<<grid(), wg(), 0, s.stream>>>(g, bl, k, in, nullptr, base, out, a, dt, wflux, s.wcur);
+        if (s.prof) {
+            (void)hipEventRecord(s.ev_pool[ev + 1], s.stream);
+            // algorithmic bytes: read `in` (and `base` after the first stage), write `out`
+            s.prof_cells.push_back(s.bulk_cells[k] * (long long)((a == 0.0 ? 2 : 3) * NV * 8));
+        }
+        k_stage<D, true><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, k, in, self2, base, out, a, dt, wflux, s.wcur);
+    }
+    void profile_flush()
+    {
+        (void)hipStreamSynchronize(s.stream);
+        for (size_t e = 0; e + 1 < s.ev_used; e += 2) {
+            float ms = 0.f;
+            (void)hipEventElapsedTime(&ms, s.ev_pool[e], s.ev_pool[e + 1]);
+            s.prof_ms += ms;
+            s.prof_launches++;
+            s.prof_bytes += s.prof_cells[e / 2];
+        }
+        s.ev_used = 0;
+        s.prof_cells.clear();
+    }
+
+    // level-set stage buffers: stage outputs alternate B0, B1; reinitialisation
+    // iterates through the free buffers and ends in the base buffer P
+    double* phi_stage_out(int st) { return g.phiB[st % 2]; }
+    void reinit(double* phi0)
+    {
+        int K = s.o.reinit_iters;
+        if (K <= 0) {
+            k_copy_masked<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, phi0, g.phiP);
+            return;
+        }
+        k_nearif<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, phi0);
+        double* other = (phi0 == g.phiB[0]) ? g.phiB[1] : g.phiB[0];
+        const double* in = phi0;
+        for (int m = 1; m <= K; m++) {
+            double* out = (m == K) ? g.phiP : ((m % 2 == 1) ? g.phiB[2] : other);
+            k_reinit<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, phi0, in, out);
+            in = out;
+        }
+    }
+    void ls(double a, double dt, const double* in, double* out)
+    {
+        k_ls<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, a, dt, in, out, s.vcur);
+    }
+
+    // ---- CFL ----
+    void cfl_launch(int k, const double* cons)
+    {
+        int bl = k == 0 ? LIST_BULK0 : LIST_BULK1;
+        k_cfl<D, false><<<grid(), wg(), 0, s.stream>>>(g, bl, k, cons, s.wcur);
+        k_cfl<D, true><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, s.wcur);
+    }
+    // read back the reductions; fills dt and active-cell counts of the fluids in `which`
+    sim_status readback(int which, double* dt, long long* cnt)
+    {
+        SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s.stream));
+        SHARP_HIP(hipMemcpyAsync(s.h_red + 8, g.counts + 8, 4 * sizeof(int), hipMemcpyDeviceToHost, s.stream));
+        SHARP_HIP(hipStreamSynchronize(s.stream));
+        const int* cc = reinterpret_cast<const int*>(s.h_red + 8);
+        s.bulk_cells[0] = cc[2];
+        s.bulk_cells[1] = cc[3];
+        unsigned long long err = s.h_red[4];
+        if (err & ERR_NONPHYS) { set_error("non-physical state (rho <= 0, p + p_inf <= 0 or NaN)"); return SIM_ENONPHYS; }
+        if (err & ERR_BAND_OVERFLOW) { set_error("the interface band moved more than one tile within a cycle"); return SIM_EDEVICE; }
+        for (int k = 0; k < 2; k++) {
+            if (!(which & (1 << k))) continue;
+            double m = __longlong_as_double_host(s.h_red[k]);
+            cnt[k] = (long long)s.h_red[2 + k];
+            dt[k] = (cnt[k] > 0 && m > 0.0) ? s.o.cfl / m : INFINITY;
+        }
+        return SIM_OK;
+    }
+    static double __longlong_as_double_host(unsigned long long b)
+    {
+        double d;
+        std::memcpy(&d, &b, sizeof d);
+        return d;
+    }
+
+    // ---- (sub)step start: band mask, primitives, extension, interaction, CFL ----
+    sim_status prepare(bool cycle_start, double* dt, long long* cnt)
+    {
+        if (cycle_start) {
+            mask(LIST_CAND, 0);
+            tiles();
+        }
+        prims(0, g.X[0]);
+        prims(1, g.X[1]);
+        interaction(g.phiP, 0.0, 0);
+        k_zero_red<<<1, 64, 0, s.stream>>>(g);
+        cfl_launch(0, g.X[0]);
+        cfl_launch(1, g.X[1]);
+        return readback(3, dt, cnt);
+    }
+
+    // ---- the original method: one dt for both fluids and the level set ----
+    void step_single(double dt)
+    {
+        int ns = s.o.rk;
+        const double* A = ns == 3 ? RK3_A : RK2_A;
+        const double* B = ns == 3 ? RK3_B : RK2_B;
+        const double* in[2] = {g.X[0], g.X[1]};
+        const double* phin = g.phiP;
+        for (int st = 0; st < ns; st++) {
+            if (st > 0) {
+                prims(0, in[0]);
+                prims(1, in[1]);
+                interaction(phin, 0.0, 0);
+            }
+            double* out[2];
+            for (int k = 0; k < 2; k++) {
+                out[k] = (st == ns - 1) ? g.X[k] : (st == 0 ? g.Y[k] : g.Z[k]);
+                stage(k, in[k], nullptr, g.X[k], out[k], A[st], dt, B[st] * dt);
+            }
+            double* po = phi_stage_out(st);
+            ls(A[st], dt, phin, po);
+            const double* cur = po;
+            if (st == ns - 1) { reinit(po); cur = g.phiP; }
+            geom(cur);
+            mix(0, out[0], cur);
+            mix(1, out[1], cur);
+            in[0] = out[0];
+            in[1] = out[1];
+            phin = cur;
+        }
+        s.t += dt;
+    }
+
+    // slow fluid's intermediate state, Eq. (interpolation), mixed with the
+    // current geometry unless it is the (already mixed) previous state
+    void interp_slow(int S, double theta, const double* cur)
+    {
+        axpby(1.0 - theta, g.X[S], theta, g.Y[S], g.T2, NV);
+        if (theta != 0.0) mix(S, g.T2, cur);
+    }
+
+    // ---- the accelerated cycle (Sec. 3.1) ----
+    sim_status cycle(const double* dt, const long long* cnt, double t_end, sim_stats* st)
+    {
+        int ns = s.o.rk;
+        const double* A = ns == 3 ? RK3_A : RK2_A;
+        const double* C = ns == 3 ? RK3_C : RK2_C;
+        const double* B = ns == 3 ? RK3_B : RK2_B;
+        int S = dt[0] >= dt[1] ? 0 : 1, F = 1 - S;
+        double dtS, rem = t_end - s.t;
+        int single;
+        if (!std::isfinite(dt[F])) { S = F; F = 1 - S; }
+        if (!std::isfinite(dt[S]) || !std::isfinite(dt[F])) {
+            double d = dt[0] < dt[1] ? dt[0] : dt[1];
+            if (d > rem) d = rem;
+            single = 1;
+            dtS = d;
+        } else {
+            plan_cycle(dt[S], dt[F], rem, s.o.n_thr, &dtS, &single);
+            if (single && s.o.force_cycle && dtS >= dt[F] * (1.0 - 1e-12)) single = 0;
+        }
+        if (single) {
+            step_single(dtS);
+            st->cycles++;
+            for (int k = 0; k < 2; k++) { st->steps[k]++; st->cell_updates[k] += cnt[k]; }
+            st->last_n = 1.0;
+            return SIM_OK;
+        }
+        const bool corr = !s.o.no_correction;
+        double t1 = dtS;
+        st->last_n = t1 / dt[F];
+        // (1) slow fluid's first stage with dt_S on the cycle-start interaction
+        stage(S, g.X[S], nullptr, g.X[S], g.Y[S], A[0], t1, B[0] * t1);
+        double tau = 0.0, dtF = dt[F];
+        int first = 1, half_done = 0;
+        long long cntF = cnt[F];
+        for (;;) {
+            if (!first) {
+                double d2[2];
+                long long c2[2];
+                mask(LIST_BAND, 1);
+                interp_slow(S, tau / t1, g.phiP);
+                prims(S, g.T2);
+                prims(F, g.X[F]);
+                interaction(g.phiP, 0.0, S);
+                k_zero_red<<<1, 64, 0, s.stream>>>(g);
+                cfl_launch(F, g.X[F]);
+                sim_status rc = readback(1 << F, d2, c2);
+                if (rc != SIM_OK) return rc;
+                dtF = d2[F];
+                cntF = c2[F];
+                if (!std::isfinite(dtF) || !(dtF > 0.0)) {
+                    set_error("invalid fast-fluid time step");
+                    return SIM_ENONPHYS;
+                }
+            }
+            int hh, fin;
+            double dl = next_substep(tau, t1, dtF, ns, half_done, &hh, &fin);
+            if (first && corr) corr_add(-B[0] * t1 + B[0] * dl, S);
+            const double* in = g.X[F];
+            const double* phin = g.phiP;
+            for (int q = 0; q < ns; q++) {
+                if (q > 0) {
+                    double theta = (fin && C[q] == 1.0) ? 1.0 : (tau + C[q] * dl) / t1;
+                    interp_slow(S, theta, phin);
+                    prims(S, g.T2);
+                    prims(F, in);
+                    bool shared = fin && C[q] == 1.0;
+                    double w = !corr ? 0.0 : (shared ? -B[q] * t1 + B[q] * dl : B[q] * dl);
+                    interaction(phin, w, S);
+                    if (shared) {
+                        // shared with the slow fluid's second stage, Eq. (firstcorrection)
+                        stage(S, g.Y[S], g.T2, g.X[S], ns == 2 ? g.X[S] : g.Z[S], A[q], t1, B[q] * t1);
+                    }
+                } else if (!first && corr) {
+                    corr_add(B[0] * dl, S);   // Eq. (secondcorrection)
+                }
+                double* out = (q == ns - 1) ? g.X[F] : (q == 0 ? g.Y[F] : g.Z[F]);
+                stage(F, in, nullptr, g.X[F], out, A[q], dl, B[q] * dl);
+                double* po = phi_stage_out(q);
+                ls(A[q], dl, phin, po);
+                const double* cur = po;
+                if (q == ns - 1) { reinit(po); cur = g.phiP; }
+                geom(cur);
+                mix(F, out, cur);
+                in = out;
+                phin = cur;
+            }
+            st->steps[F]++;
+            st->cell_updates[F] += cntF;
+            tau = hh ? 0.5 * t1 : (fin ? t1 : tau + dl);
+            if (hh) {
+                half_done = 1;
+                axpby(1.0, g.X[F], 0.0, nullptr, g.Fh, NV);
+                axpby(1.0, g.phiP, 0.0, nullptr, g.phiH, 1);
+            }
+            first = 0;
+            if (fin) break;
+        }
+        if (ns == 3) {
+            // slow fluid's third stage at t1/2 against the snapshots
+            geom(g.phiH);
+            axpby(1.0, g.Z[S], 0.0, nullptr, g.T2, NV);
+            mix(S, g.T2, g.phiH);
+            prims(S, g.T2);
+            prims(F, g.Fh);
+            interaction(g.phiH, corr ? -B[2] * t1 : 0.0, S);
+            stage(S, g.Z[S], g.T2, g.X[S], g.X[S], A[2], t1, B[2] * t1);
+            geom(g.phiP);
+        }
+        // interfacial flux correction of the slow fluid, then mixing
+        k_corr_apply<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, S, corr ? 1 : 0);
+        mix(S, g.X[S], g.phiP);
+        s.t += t1;
+        st->cycles++;
+        st->steps[S]++;
+        st->cell_updates[S] += cnt[S];
+        return SIM_OK;
+    }
+
+    sim_status advance(double t_end, int mode, long long max_cycles, sim_stats* st)
+    {
+        long long done = 0;
+        sim_status rc = SIM_OK;
+        while (s.t < t_end && (max_cycles <= 0 || done < max_cycles)) {
+            double dt[2];
+            long long cnt[2];
+            rc = prepare(true, dt, cnt);
+            if (rc != SIM_OK) break;
+            st->last_dt[0] = dt[0];
+            st->last_dt[1] = dt[1];
+            if (!(fmin(dt[0], dt[1]) > 0.0)) { set_error("invalid time step"); rc = SIM_ENONPHYS; break; }
+            if (mode == SIM_SINGLE_DT) {
+                double d = dt[0] < dt[1] ? dt[0] : dt[1];
+                if (d > t_end - s.t) d = t_end - s.t;
+                step_single(d);
+                st->cycles++;
+                for (int k = 0; k < 2; k++) { st->steps[k]++; st->cell_updates[k] += cnt[k]; }
+                st->last_n = 1.0;
+            } else {
+                rc = cycle(dt, cnt, t_end, st);
+                if (rc != SIM_OK) break;
+            }
+            if (t_end - s.t <= 1e-14 * t_end) s.t = t_end;
+            done++;
+        }
+        if (rc == SIM_OK) {
+            // late non-physical flags (stages after the last readback)
+            SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s.stream));
+            SHARP_HIP(hipStreamSynchronize(s.stream));
+            if (s.h_red[4] & ERR_NONPHYS) { set_error("non-physical state"); rc = SIM_ENONPHYS; }
+        }
+        if (s.prof) profile_flush();
+        st->t = s.t;
+        return rc;
+    }
+
+    sim_status set_state(const double* phi, const double* prim)
+    {
+        SHARP_HIP(hipMemcpyAsync(g.phiP, phi, sizeof(double) * g.nc, hipMemcpyDeviceToDevice, s.stream));
+        SHARP_HIP(hipMemsetAsync(g.M, 0, g.nc, s.stream));
+        geom(g.phiP, LIST_ALL);
+        int b = (g.nc + 255) / 256;
+        if (b > 65535) b = 65535;
+        k_init<D><<<b, 256, 0, s.stream>>>(g, prim);
+        // band of the initial level set over every tile
+        mask(LIST_ALL, 0);
+        tiles();
+        for (int k = 0; k < 2; k++)
+            SHARP_HIP(hipMemsetAsync(g.bacc[k], 0, sizeof(double) * NV * (size_t)(g.nbface > 0 ? g.nbface : 1), s.stream));
+        SHARP_HIP(hipMemsetAsync(g.red, 0, 8 * sizeof(unsigned long long), s.stream));
+        SHARP_HIP(hipStreamSynchronize(s.stream));
+        SHARP_HIP(hipGetLastError());
+        s.t = 0.0;
+        s.wcur = 0;
+        s.vcur = 0;
+        s.has_state = true;
+        return SIM_OK;
+    }
+
+    sim_status bflux(double out[2][5])
+    {
+        std::vector<double> h((size_t)NV * (g.nbface > 0 ? g.nbface : 1));
+        for (int k = 0; k < 2; k++) {
+            SHARP_HIP(hipMemcpy(h.data(), g.bacc[k], sizeof(double) * h.size(), hipMemcpyDeviceToHost));
+            for (int q = 0; q < 5; q++) out[k][q] = 0.0;
+            for (int q = 0; q < NV; q++) {
+                double sum = 0.0;
+                for (int b = 0; b < g.nbface; b++) sum += h[(size_t)q * g.nbface + b];
+                out[k][q] = sum;
+            }
+        }
+        return SIM_OK;
+    }
+};
+
+sim_status engine_set_state(Sim& s, const double* phi, const double* prim)
+{
+    switch (s.g.D) {
+    case 1: return Engine<1>(s).set_state(phi, prim);
+    case 2: return Engine<2>(s).set_state(phi, prim);
+    default: return Engine<3>(s).set_state(phi, prim);
+    }
+}
+
+sim_status engine_advance(Sim& s, double t_end, int mode, long long max_cycles, sim_stats* st)
+{
+    sim_status rc;
+    switch (s.g.D) {
+    case 1: rc = Engine<1>(s).advance(t_end, mode, max_cycles, st); break;
+    case 2: rc = Engine<2>(s).advance(t_end, mode, max_cycles, st); break;
+    default: rc = Engine<3>(s).advance(t_end, mode, max_cycles, st); break;
+    }
+    hipError_t e = hipGetLastError();
+    if (rc == SIM_OK && e != hipSuccess) {
+        set_error("kernel launch failed: %s", hipGetErrorString(e));
+        return SIM_EDEVICE;
+    }
+    return rc;
+}
+
+sim_status engine_bflux(Sim& s, double out[2][5])
+{
+    switch (s.g.D) {
+    case 1: return Engine<1>(s).bflux(out);
+    case 2: return Engine<2>(s).bflux(out);
+    default: return Engine<3>(s).bflux(out);
+    }
+}
+
+}  // namespace sharp
