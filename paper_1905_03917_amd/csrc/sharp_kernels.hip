@@ -422,6 +422,94 @@ __global__ void __launch_bounds__(SHARP_WG) k_mixdelta(Dev g, int list, int k, c
     }
 }
 
+// LDS variant (1-D and 2-D): the source data (weights and targets) of every
+// cell of the tile and its one-cell halo is computed once, then gathered.
+template <int D> struct MixRegion;
+template <> struct MixRegion<1> { static constexpr int X = 256 + 2, Y = 1; };
+template <> struct MixRegion<2> { static constexpr int X = 16 + 2, Y = 16 + 2; };
+
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_mixdelta_lds(Dev g, int list, int k, const double* cons, const double* cur)
+{
+    static_assert(D <= 2, "LDS mixing is for 1-D and 2-D");
+    constexpr int NV = D + 2;
+    constexpr int NS = (1 << D) - 1;
+    constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
+    constexpr int RX = MixRegion<D>::X, RY = MixRegion<D>::Y, RN = RX * RY;
+    constexpr int HY = D == 2 ? 1 : 0;
+    __shared__ double sBeta[NS * RN];
+    __shared__ int sTgt[NS * RN];
+    __shared__ int sCell[RN];
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int t = L[ti];
+        int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
+        for (int r = threadIdx.x; r < RN; r += SHARP_WG) {
+            int rx = r % RX, ry = r / RX;
+            int c = cidx(g, ox - 1 + rx, oy - HY + ry, 0);
+            sCell[r] = c;
+            double beta[7];
+            int tgt[7];
+            bool src = mix_source<D>(g, cur, k, c, beta, tgt);
+            for (int m = 0; m < NS; m++) {
+                sBeta[m * RN + r] = src ? beta[m] : 0.0;
+                sTgt[m * RN + r] = src ? tgt[m] : -1;
+            }
+        }
+        __syncthreads();
+        int li = threadIdx.x % TX, lj = threadIdx.x / TX;
+        int i = ox + li, j = oy + lj;
+        if (i < g.n[0] && j < g.n[1]) {
+            int c = i + g.n[0] * j;
+            if (g.M[c]) {
+                int rc = (li + 1) + RX * (lj + HY);
+                double dl[NV];
+                for (int q = 0; q < NV; q++) dl[q] = 0.0;
+                double ac = alpha_k(g, k, c);
+                // c as a source
+                for (int m = 0; m < NS; m++) {
+                    int tt = sTgt[m * RN + rc];
+                    double b = sBeta[m * RN + rc];
+                    if (tt < 0 || !(b > 0.0) || tt == c) continue;
+                    double at = alpha_k(g, k, tt);
+                    if (!(ac + at > 0.0)) continue;
+                    for (int q = 0; q < NV; q++)
+                        dl[q] += b * (cons[(size_t)q * g.nc + tt] * ac - cons[(size_t)q * g.nc + c] * at) / (ac + at);
+                }
+                // c as a target of its (distinct) neighbours
+                bool edge = i == 0 || i == g.n[0] - 1 || (D == 2 && (j == 0 || j == g.n[1] - 1));
+                int seen[8];
+                int ns = 0;
+                for (int oy2 = -HY; oy2 <= HY; oy2++)
+                    for (int ox2 = -1; ox2 <= 1; ox2++) {
+                        if (!ox2 && !oy2) continue;
+                        int rs = rc + ox2 + RX * oy2;
+                        int sc = sCell[rs];
+                        if (sc == c) continue;
+                        if (edge) {
+                            bool dup = false;
+                            for (int u = 0; u < ns; u++) dup |= (seen[u] == sc);
+                            if (dup) continue;
+                            seen[ns++] = sc;
+                        }
+                        if (sTgt[rs] < 0) continue;     // not a source
+                        double as = alpha_k(g, k, sc);
+                        if (!(as + ac > 0.0)) continue;
+                        for (int m = 0; m < NS; m++) {
+                            if (sTgt[m * RN + rs] != c) continue;
+                            double b = sBeta[m * RN + rs];
+                            if (!(b > 0.0)) continue;
+                            for (int q = 0; q < NV; q++)
+                                dl[q] -= b * (cons[(size_t)q * g.nc + c] * as - cons[(size_t)q * g.nc + sc] * ac) / (as + ac);
+                        }
+                    }
+                for (int q = 0; q < NV; q++) g.dmix[(size_t)q * g.nc + c] = dl[q];
+            }
+        }
+        __syncthreads();
+    }
+}
+
 template <int D>
 __global__ void __launch_bounds__(SHARP_WG) k_mixapply(Dev g, int list, double* cons)
 {
@@ -535,6 +623,201 @@ __global__ void __launch_bounds__(SHARP_WG) k_extv(Dev g, int list, int in, int 
             for (int d = 0; d < D; d++) acc += w[d] * g.v[in][e][up[d]];
             g.v[out][e][c] = acc / wsum;
         }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Temporally blocked extension (1-D and 2-D): the tile and a halo of EXT_H
+// cells are staged in LDS and all Jacobi sweeps run there; a cell at depth e
+// inside the halo is exact for e sweeps, so the tile itself is exact after up
+// to EXT_H sweeps.  Same arithmetic as k_prims followed by k_extw / k_extv.
+// ---------------------------------------------------------------------------
+constexpr int EXT_H = 8;
+template <int D> struct ExtRegion;
+template <> struct ExtRegion<1> { static constexpr int X = 256 + 2 * EXT_H, Y = 1; };
+template <> struct ExtRegion<2> { static constexpr int X = 16 + 2 * EXT_H, Y = 16 + 2 * EXT_H; };
+
+// fused primitive recovery (real band cells of both fluids) + extension of
+// both fluids' primitives; reads Wb[.][in], writes the band cells of Wb[.][out]
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_extw_tb(Dev g, int list, const double* src0, const double* src1,
+                                                     int in, int out, int iters, const double* cur)
+{
+    static_assert(D <= 2, "temporally blocked extension is for 1-D and 2-D");
+    constexpr int NV = D + 2;
+    constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
+    constexpr int RX = ExtRegion<D>::X, RY = ExtRegion<D>::Y, RN = RX * RY;
+    constexpr int CPT = (RN + SHARP_WG - 1) / SHARP_WG;
+    constexpr int HY = D == 2 ? EXT_H : 0;
+    __shared__ double sA[NV * RN], sB[NV * RN];
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int t = L[ti];
+        int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
+        for (int k = 0; k < 2; k++) {
+            const double* src = k == 0 ? src0 : src1;
+            const double* Wi = g.Wb[k][in];
+            double sk = k == 0 ? 1.0 : -1.0;
+            bool tgt[CPT];
+            int up[CPT][2];
+            double w[CPT][2], wsum[CPT];
+#pragma unroll
+            for (int m = 0; m < CPT; m++) {
+                int r = threadIdx.x + m * SHARP_WG;
+                tgt[m] = false;
+                if (r >= RN) continue;
+                int rx = r % RX, ry = r / RX;
+                int c = cidx(g, ox - EXT_H + rx, oy - HY + ry, 0);
+                double a = alpha_k(g, k, c);
+                bool inM = g.M[c] != 0;
+                if (inM && a >= g.amix) {
+                    double U[NV], W[NV];
+                    for (int q = 0; q < NV; q++) U[q] = src[(size_t)q * g.nc + c] / a;
+                    if (!cons2prim<D>(g.gam[k], g.pinf[k], U, W)) flag_error(g, ERR_NONPHYS);
+                    for (int q = 0; q < NV; q++) sA[q * RN + r] = W[q];
+                } else {
+                    for (int q = 0; q < NV; q++) sA[q * RN + r] = Wi[(size_t)q * g.nc + c];
+                }
+                if (!inM || !(a < g.amix) || sk * phi_at(g, cur, c) > g.extb * g.h) continue;
+                double gr[3];
+                double gm = grad_phi<D>(g, cur, c, gr);
+                if (!(gm > 0.0)) continue;
+                bool inside = true;
+                wsum[m] = 0.0;
+                for (int d = 0; d < D; d++) {
+                    double nd = sk * gr[d] / gm;
+                    int o = nd > 0.0 ? -1 : 1;
+                    int qx = rx + (d == 0 ? o : 0), qy = ry + (d == 1 ? o : 0);
+                    inside &= qx >= 0 && qx < RX && qy >= 0 && qy < RY;
+                    up[m][d] = qx + RX * qy;
+                    w[m][d] = fabs(nd);
+                    wsum[m] += w[m][d];
+                }
+                tgt[m] = inside;   // cells whose upwind stencil leaves the region stay frozen
+            }
+            __syncthreads();
+            double* A = sA;
+            double* B = sB;
+            for (int it = 0; it < iters; it++) {
+#pragma unroll
+                for (int m = 0; m < CPT; m++) {
+                    int r = threadIdx.x + m * SHARP_WG;
+                    if (r >= RN) continue;
+                    for (int q = 0; q < NV; q++) {
+                        double v;
+                        if (tgt[m]) {
+                            double acc = 0.0;
+                            for (int d = 0; d < D; d++) acc += w[m][d] * A[q * RN + up[m][d]];
+                            v = acc / wsum[m];
+                        } else {
+                            v = A[q * RN + r];
+                        }
+                        B[q * RN + r] = v;
+                    }
+                }
+                __syncthreads();
+                double* tmp = A; A = B; B = tmp;
+            }
+            // band cells of the tile
+            {
+                int li = threadIdx.x % TX, lj = threadIdx.x / TX;
+                int i = ox + li, j = oy + lj;
+                if (i < g.n[0] && j < g.n[1]) {
+                    int c = i + g.n[0] * j;
+                    if (g.M[c]) {
+                        int r = (li + EXT_H) + RX * (lj + HY);
+                        for (int q = 0; q < NV; q++) g.Wb[k][out][(size_t)q * g.nc + c] = A[q * RN + r];
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+}
+
+// level-set velocity extension, temporally blocked
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_extv_tb(Dev g, int list, int in, int out, int iters, const double* cur)
+{
+    static_assert(D <= 2, "temporally blocked extension is for 1-D and 2-D");
+    constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
+    constexpr int RX = ExtRegion<D>::X, RY = ExtRegion<D>::Y, RN = RX * RY;
+    constexpr int CPT = (RN + SHARP_WG - 1) / SHARP_WG;
+    constexpr int HY = D == 2 ? EXT_H : 0;
+    __shared__ double sA[D * RN], sB[D * RN];
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int t = L[ti];
+        int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
+        bool tgt[CPT];
+        int up[CPT][2];
+        double w[CPT][2], wsum[CPT];
+#pragma unroll
+        for (int m = 0; m < CPT; m++) {
+            int r = threadIdx.x + m * SHARP_WG;
+            tgt[m] = false;
+            if (r >= RN) continue;
+            int rx = r % RX, ry = r / RX;
+            int gi = ox - EXT_H + rx, gj = oy - HY + ry;
+            int c = cidx(g, gi, gj, 0);
+            for (int e = 0; e < D; e++) sA[e * RN + r] = g.v[in][e][c];
+            if (!g.M[c]) continue;
+            int ci, cj, ck;
+            coords(g, c, ci, cj, ck);
+            double gv[3];
+            if (iface<D>(g, ci, cj, ck, gv) > 0.0) continue;
+            double gr[3];
+            double gm = grad_phi<D>(g, cur, c, gr);
+            if (!(gm > 0.0)) continue;
+            double sg = phi_at(g, cur, c) < 0.0 ? -1.0 : 1.0;
+            bool inside = true;
+            wsum[m] = 0.0;
+            for (int d = 0; d < D; d++) {
+                double nd = sg * gr[d] / gm;
+                int o = nd > 0.0 ? -1 : 1;
+                int qx = rx + (d == 0 ? o : 0), qy = ry + (d == 1 ? o : 0);
+                inside &= qx >= 0 && qx < RX && qy >= 0 && qy < RY;
+                up[m][d] = qx + RX * qy;
+                w[m][d] = fabs(nd);
+                wsum[m] += w[m][d];
+            }
+            tgt[m] = inside;
+        }
+        __syncthreads();
+        double* A = sA;
+        double* B = sB;
+        for (int it = 0; it < iters; it++) {
+#pragma unroll
+            for (int m = 0; m < CPT; m++) {
+                int r = threadIdx.x + m * SHARP_WG;
+                if (r >= RN) continue;
+                for (int e = 0; e < D; e++) {
+                    double v;
+                    if (tgt[m]) {
+                        double acc = 0.0;
+                        for (int d = 0; d < D; d++) acc += w[m][d] * A[e * RN + up[m][d]];
+                        v = acc / wsum[m];
+                    } else {
+                        v = A[e * RN + r];
+                    }
+                    B[e * RN + r] = v;
+                }
+            }
+            __syncthreads();
+            double* tmp = A; A = B; B = tmp;
+        }
+        {
+            int li = threadIdx.x % TX, lj = threadIdx.x / TX;
+            int i = ox + li, j = oy + lj;
+            if (i < g.n[0] && j < g.n[1]) {
+                int c = i + g.n[0] * j;
+                if (g.M[c]) {
+                    int r = (li + EXT_H) + RX * (lj + HY);
+                    for (int e = 0; e < D; e++) g.v[out][e][c] = A[e * RN + r];
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -823,6 +1106,158 @@ __global__ void __launch_bounds__(SHARP_WG) k_stage(Dev g, int list, int k, cons
 }
 
 // ---------------------------------------------------------------------------
+// LDS-staged stage kernel (1-D and 2-D): the primitives of the tile and its
+// three-cell halo are computed once per cell into LDS (SoA), every face flux
+// of the tile is computed once from LDS, then each cell combines its faces.
+// Same arithmetic as k_stage above.
+// ---------------------------------------------------------------------------
+template <int D> struct Region;
+template <> struct Region<1> { static constexpr int X = 256 + 6, Y = 1; };
+template <> struct Region<2> { static constexpr int X = 16 + 6, Y = 16 + 6; };
+
+template <int D, bool BAND>
+__global__ void __launch_bounds__(SHARP_WG) k_stage_lds(Dev g, int list, int k, const double* in, const double* self2,
+                                                       const double* base, double* out, double a, double dt,
+                                                       double wflux, int wb)
+{
+    static_assert(D <= 2, "LDS stage kernel is for 1-D and 2-D");
+    constexpr int NV = D + 2;
+    constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
+    constexpr int RX = Region<D>::X, RY = Region<D>::Y, RN = RX * RY;
+    constexpr int F0 = FaceCount<D>::n0, F1 = FaceCount<D>::n1;
+    constexpr int FT = F0 + F1;
+    __shared__ double sR[RN], sU[RN], sV[D > 1 ? RN : 1], sE[RN], sP[RN], sC[RN];
+    __shared__ double sF[FT * NV];
+    const int* L = list_ptr(g, list);
+    const double gm = g.gam[k], pi = g.pinf[k];
+    const double farea = D == 1 ? 1.0 : g.h;
+    const double ih = 1.0 / g.h;
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int t = L[ti];
+        int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1];
+        int ox = tx * TX, oy = ty * TY;
+        // ---- primitives of the tile and its halo (corners are never used) ----
+        for (int r = threadIdx.x; r < RN; r += SHARP_WG) {
+            int rx = r % RX, ry = r / RX;
+            if (D == 2 && (rx < 3 || rx >= TX + 3) && (ry < 3 || ry >= TY + 3)) continue;
+            int c = cidx(g, ox - 3 + rx, D == 2 ? oy - 3 + ry : 0, 0);
+            double W[NV], U[NV];
+            load_state<D, BAND>(g, k, in, self2, wb, c, W, U);
+            sR[r] = W[0];
+            sU[r] = W[1];
+            if (D == 2) sV[r] = W[2];
+            sE[r] = U[NV - 1];
+            sP[r] = W[NV - 1];
+            sC[r] = csound(gm, pi, W[0], W[NV - 1]);
+        }
+        __syncthreads();
+        // ---- face fluxes ----
+        for (int f = threadIdx.x; f < FT; f += SHARP_WG) {
+            int d, li, lj;
+            if (f < F0) { d = 0; li = f % (TX + 1); lj = f / (TX + 1); }
+            else { int r = f - F0; d = 1; li = r % TX; lj = r / TX; }
+            int i = ox + li, j = oy + lj;
+            bool ok = d == 0 ? (i <= g.n[0] && j < g.n[1]) : (i < g.n[0] && j <= g.n[1]);
+            double* Fo = sF + (size_t)f * NV;
+            double A = 1.0;
+            if (ok && BAND) {
+                A = g.ap[d][fidx(g, i, j, 0)];
+                if (k == 1) A = 1.0 - A;
+                ok = A > 0.0;
+            }
+            if (!ok) {
+#pragma unroll
+                for (int q = 0; q < NV; q++) Fo[q] = 0.0;
+                continue;
+            }
+            // stencil m = 0..5 <-> cells i-3 .. i+2 along d (region coordinates)
+            int r0 = d == 0 ? (li + RX * (D == 2 ? lj + 3 : 0)) : (li + 3 + RX * lj);
+            int st = d == 0 ? 1 : RX;
+            double rho[6], un[6], ut[6], E[6], p[6];
+            double amax = 0.0;
+#pragma unroll
+            for (int m = 0; m < 6; m++) {
+                int r = r0 + m * st;
+                rho[m] = sR[r];
+                double uu = sU[r], vv = D == 2 ? sV[r] : 0.0;
+                un[m] = d == 0 ? uu : vv;
+                ut[m] = d == 0 ? vv : uu;
+                E[m] = sE[r];
+                p[m] = sP[r];
+                amax = fmax(amax, fabs(un[m]) + sC[r]);
+            }
+#pragma unroll
+            for (int q = 0; q < NV; q++) {
+                double fp[6], fm[6];
+#pragma unroll
+                for (int m = 0; m < 6; m++) {
+                    // conserved value and physical flux of component q
+                    double Uq, Fq;
+                    if (q == 0) { Uq = rho[m]; Fq = rho[m] * un[m]; }
+                    else if (q == NV - 1) { Uq = E[m]; Fq = (E[m] + p[m]) * un[m]; }
+                    else {
+                        // momentum component q-1 (x for q = 1, y for q = 2)
+                        bool normal = (q - 1) == d;
+                        double uq = normal ? un[m] : ut[m];
+                        Uq = rho[m] * uq;
+                        Fq = Uq * un[m] + (normal ? p[m] : 0.0);
+                    }
+                    fp[m] = 0.5 * (Fq + amax * Uq);
+                    fm[m] = 0.5 * (Fq - amax * Uq);
+                }
+                double Fh = weno5(fp[0], fp[1], fp[2], fp[3], fp[4], g.eps)
+                          + weno5(fm[5], fm[4], fm[3], fm[2], fm[1], g.eps);
+                Fo[q] = A * Fh;
+            }
+            if (g.bc[d] == 0 && wflux != 0.0) {
+                int fi = d == 0 ? i : j;
+                if (fi == 0 || fi == g.n[d]) {
+                    int side = fi == 0 ? 0 : 1;
+                    int b = g.bface_off[d][side] + (d == 0 ? j : i);
+                    double sgn = side == 0 ? 1.0 : -1.0;
+                    for (int q = 0; q < NV; q++) g.bacc[k][(size_t)q * g.nbface + b] += sgn * wflux * farea * Fo[q];
+                }
+            }
+        }
+        __syncthreads();
+        // ---- cell update ----
+        {
+            int li = threadIdx.x % TX, lj = threadIdx.x / TX;
+            int i = ox + li, j = oy + lj;
+            if (i < g.n[0] && j < g.n[1]) {
+                int c = i + g.n[0] * j;
+                double Lr[NV];
+                int fxl = li + (TX + 1) * lj;
+#pragma unroll
+                for (int q = 0; q < NV; q++) Lr[q] = (sF[(size_t)fxl * NV + q] - sF[(size_t)(fxl + 1) * NV + q]) * ih;
+                if (D == 2) {
+                    int fyl = F0 + li + TX * lj;
+#pragma unroll
+                    for (int q = 0; q < NV; q++) Lr[q] += (sF[(size_t)fyl * NV + q] - sF[(size_t)(fyl + TX) * NV + q]) * ih;
+                }
+                if (BAND) {
+                    double gv[3];
+                    double gn = iface<D>(g, i, j, 0, gv);
+                    if (gn > 0.0) {
+                        double sg = k == 0 ? 1.0 : -1.0, p = g.ps[c];
+                        for (int d = 0; d < D; d++) Lr[1 + d] += -sg * p * gv[d];
+                        Lr[D + 1] += -sg * p * g.us[c] * gn;
+                    }
+                }
+                const double* sin_ = (BAND && self2 && g.M[c]) ? self2 : in;
+#pragma unroll
+                for (int q = 0; q < NV; q++) {
+                    size_t e = (size_t)q * g.nc + c;
+                    double s = sin_[e] + dt * Lr[q];
+                    out[e] = (a == 0.0) ? s : a * base[e] + (1.0 - a) * s;
+                }
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // level set: one Shu-Osher stage of Eq. (LS:linearadvection), WENO5 upwind
 // derivatives, band cells only
 // ---------------------------------------------------------------------------
@@ -1021,16 +1456,46 @@ struct Engine {
             s.vcur ^= 1;
         }
     }
-    void interaction(const double* cur, double wcorr, int S)
+    // primitives of both fluids on the band (real cells from src, ghost cells
+    // by extension), then the interaction and the level-set velocity
+    void band_state(const double* src0, const double* src1, const double* cur)
     {
+        if constexpr (D <= 2) {
+            if (s.o.ext_iters <= EXT_H) {
+                k_extw_tb<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, src0, src1, s.wcur, 1 - s.wcur,
+                                                            s.o.ext_iters, cur);
+                s.wcur ^= 1;
+                return;
+            }
+        }
+        prims(0, src0);
+        prims(1, src1);
         extw(cur);
-        interact(wcorr, S);
+    }
+    void velocity(const double* cur)
+    {
+        if constexpr (D <= 2) {
+            if (s.o.ext_iters <= EXT_H) {
+                k_extv_tb<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, s.vcur, 1 - s.vcur, s.o.ext_iters, cur);
+                s.vcur ^= 1;
+                return;
+            }
+        }
         extv(cur);
+    }
+    void interaction(const double* src0, const double* src1, const double* cur, double wcorr, int S)
+    {
+        band_state(src0, src1, cur);
+        interact(wcorr, S);
+        velocity(cur);
     }
     void corr_add(double w, int S) { k_corr_add<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, w, S); }
     void mix(int k, double* cons, const double* cur)
     {
-        k_mixdelta<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, cur);
+        if constexpr (D <= 2)
+            k_mixdelta_lds<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, cur);
+        else
+            k_mixdelta<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, cur);
         k_mixapply<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, cons);
     }
     void axpby(double a1, const double* s1, double a2, const double* s2, double* dst, int ncomp)
@@ -1050,13 +1515,22 @@ struct Engine {
             s.ev_used += 2;
             (void)hipEventRecord(s.ev_pool[ev], s.stream);
         }
-        k_stage<D, false><<<grid(), wg(), 0, s.stream>>>(g, bl, k, in, nullptr, base, out, a, dt, wflux, s.wcur);
+        launch_stage<false>(bl, k, in, nullptr, base, out, a, dt, wflux);
         if (s.prof) {
             (void)hipEventRecord(s.ev_pool[ev + 1], s.stream);
             // algorithmic bytes: read `in` (and `base` after the first stage), write `out`
             s.prof_cells.push_back(s.bulk_cells[k] * (long long)((a == 0.0 ? 2 : 3) * NV * 8));
         }
-        k_stage<D, true><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, k, in, self2, base, out, a, dt, wflux, s.wcur);
+        launch_stage<true>(LIST_BAND, k, in, self2, base, out, a, dt, wflux);
+    }
+    template <bool BAND>
+    void launch_stage(int list, int k, const double* in, const double* self2, const double* base, double* out,
+                      double a, double dt, double wflux)
+    {
+        if constexpr (D <= 2)
+            k_stage_lds<D, BAND><<<grid(), wg(), 0, s.stream>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
+        else
+            k_stage<D, BAND><<<grid(), wg(), 0, s.stream>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
     }
     void profile_flush()
     {
@@ -1137,9 +1611,7 @@ struct Engine {
             mask(LIST_CAND, 0);
             tiles();
         }
-        prims(0, g.X[0]);
-        prims(1, g.X[1]);
-        interaction(g.phiP, 0.0, 0);
+        interaction(g.X[0], g.X[1], g.phiP, 0.0, 0);
         k_zero_red<<<1, 64, 0, s.stream>>>(g);
         cfl_launch(0, g.X[0]);
         cfl_launch(1, g.X[1]);
@@ -1155,11 +1627,7 @@ struct Engine {
         const double* in[2] = {g.X[0], g.X[1]};
         const double* phin = g.phiP;
         for (int st = 0; st < ns; st++) {
-            if (st > 0) {
-                prims(0, in[0]);
-                prims(1, in[1]);
-                interaction(phin, 0.0, 0);
-            }
+            if (st > 0) interaction(in[0], in[1], phin, 0.0, 0);
             double* out[2];
             for (int k = 0; k < 2; k++) {
                 out[k] = (st == ns - 1) ? g.X[k] : (st == 0 ? g.Y[k] : g.Z[k]);
@@ -1228,9 +1696,7 @@ struct Engine {
                 long long c2[2];
                 mask(LIST_BAND, 1);
                 interp_slow(S, tau / t1, g.phiP);
-                prims(S, g.T2);
-                prims(F, g.X[F]);
-                interaction(g.phiP, 0.0, S);
+                interaction(S == 0 ? g.T2 : g.X[F], S == 0 ? g.X[F] : g.T2, g.phiP, 0.0, S);
                 k_zero_red<<<1, 64, 0, s.stream>>>(g);
                 cfl_launch(F, g.X[F]);
                 sim_status rc = readback(1 << F, d2, c2);
@@ -1251,11 +1717,9 @@ struct Engine {
                 if (q > 0) {
                     double theta = (fin && C[q] == 1.0) ? 1.0 : (tau + C[q] * dl) / t1;
                     interp_slow(S, theta, phin);
-                    prims(S, g.T2);
-                    prims(F, in);
                     bool shared = fin && C[q] == 1.0;
                     double w = !corr ? 0.0 : (shared ? -B[q] * t1 + B[q] * dl : B[q] * dl);
-                    interaction(phin, w, S);
+                    interaction(S == 0 ? g.T2 : in, S == 0 ? in : g.T2, phin, w, S);
                     if (shared) {
                         // shared with the slow fluid's second stage, Eq. (firstcorrection)
                         stage(S, g.Y[S], g.T2, g.X[S], ns == 2 ? g.X[S] : g.Z[S], A[q], t1, B[q] * t1);
@@ -1290,9 +1754,7 @@ struct Engine {
             geom(g.phiH);
             axpby(1.0, g.Z[S], 0.0, nullptr, g.T2, NV);
             mix(S, g.T2, g.phiH);
-            prims(S, g.T2);
-            prims(F, g.Fh);
-            interaction(g.phiH, corr ? -B[2] * t1 : 0.0, S);
+            interaction(S == 0 ? g.T2 : g.Fh, S == 0 ? g.Fh : g.T2, g.phiH, corr ? -B[2] * t1 : 0.0, S);
             stage(S, g.Z[S], g.T2, g.X[S], g.X[S], A[2], t1, B[2] * t1);
             geom(g.phiP);
         }
