@@ -100,9 +100,9 @@ static double wave_f(const side_t* s, double p, double* df)
     } else {                                         /* rarefaction */
         double c = sound(s->g, s->pi, s->rho, s->p);
         double z = (s->g - 1.0) / (2.0 * s->g);
-        double r = pb / pk;
-        *df = pow(r, -(s->g + 1.0) / (2.0 * s->g)) / (s->rho * c);
-        return 2.0 * c / (s->g - 1.0) * (pow(r, z) - 1.0);
+        double r = pb / pk, rz = pow(r, z);
+        *df = rz / r / (s->rho * c);            /* r^(z-1) / (rho c) */
+        return 2.0 * c / (s->g - 1.0) * (rz - 1.0);
     }
 }
 
@@ -131,11 +131,18 @@ int or_riemann(const double* WL, const double* WR, double gL, double piL,
     if (fl0 + fr0 + du >= 0.0) {
         p = pfloor;
     } else {
-        double cL = sound(gL, piL, L.rho, L.p), cR = sound(gR, piR, R.rho, R.p);
-        p = 0.5 * (L.p + R.p) - 0.125 * du * (L.rho + R.rho) * (cL + cR);
-        /* the side with the smaller p_inf has p > pfloor; the other side may not */
-        double pmax = (L.p > R.p ? L.p : R.p);
-        if (!(p > pfloor)) p = pfloor + 0.5 * (pmax - pfloor);
+        /* start from the geometric mean of the side pressures measured from
+         * the floor; a side below the floor (possible for the larger p_inf)
+         * falls back to the linearised (PVRS) estimate */
+        if (L.p > pfloor && R.p > pfloor) {
+            p = pfloor + sqrt((L.p - pfloor) * (R.p - pfloor));
+        } else {
+            double cL = sound(gL, piL, L.rho, L.p), cR = sound(gR, piR, R.rho, R.p);
+            p = 0.5 * (L.p + R.p) - 0.125 * du * (L.rho + R.rho) * (cL + cR);
+            /* the side with the smaller p_inf has p > pfloor; the other side may not */
+            double pmax = (L.p > R.p ? L.p : R.p);
+            if (!(p > pfloor)) p = pfloor + 0.5 * (pmax - pfloor);
+        }
         double lo = pfloor, hi = INFINITY;
         double scale = fabs(piL) + fabs(piR) + 1e-300;
         for (it = 1; it <= 200; it++) {

@@ -178,9 +178,9 @@ __device__ __forceinline__ double wave_f(const Side& s, double p, double& df)
         return (p - s.p) * q;
     }
     double c = csound(s.g, s.pi, s.rho, s.p);
-    double r = pb / pk;
-    df = pow(r, -(s.g + 1.0) / (2.0 * s.g)) / (s.rho * c);
-    return 2.0 * c / (s.g - 1.0) * (pow(r, (s.g - 1.0) / (2.0 * s.g)) - 1.0);
+    double r = pb / pk, rz = pow(r, (s.g - 1.0) / (2.0 * s.g));
+    df = rz / r / (s.rho * c);
+    return 2.0 * c / (s.g - 1.0) * (rz - 1.0);
 }
 
 __device__ __forceinline__ double star_rho(const Side& s, double ps)
@@ -204,10 +204,14 @@ __device__ inline void riemann(const Side& L, const Side& R, double* out)
     if (f0 >= 0.0) {
         p = pfloor;
     } else {
-        double cL = csound(L.g, L.pi, L.rho, L.p), cR = csound(R.g, R.pi, R.rho, R.p);
-        p = 0.5 * (L.p + R.p) - 0.125 * du * (L.rho + R.rho) * (cL + cR);
-        double pmax = L.p > R.p ? L.p : R.p;
-        if (!(p > pfloor)) p = pfloor + 0.5 * (pmax - pfloor);
+        if (L.p > pfloor && R.p > pfloor) {
+            p = pfloor + sqrt((L.p - pfloor) * (R.p - pfloor));
+        } else {
+            double cL = csound(L.g, L.pi, L.rho, L.p), cR = csound(R.g, R.pi, R.rho, R.p);
+            p = 0.5 * (L.p + R.p) - 0.125 * du * (L.rho + R.rho) * (cL + cR);
+            double pmax = L.p > R.p ? L.p : R.p;
+            if (!(p > pfloor)) p = pfloor + 0.5 * (pmax - pfloor);
+        }
         double lo = pfloor, hi = INFINITY;
         double scale = fabs(L.pi) + fabs(R.pi) + 1e-300;
         for (int it = 1; it <= 200; it++) {
