@@ -31,6 +31,7 @@ struct Sim {
     double prof_ms = 0.0;
     long long prof_launches = 0, prof_bytes = 0;
     long long bulk_cells[2] = {0, 0};   // cells in the bulk lists (host copy)
+    int lcount[5] = {1, 1, 1, 1, 1};    // tiles per list (host copy, sizes the grids)
 };
 
 void set_error(const char* fmt, ...);

@@ -271,6 +271,96 @@ __global__ void __launch_bounds__(SHARP_WG) k_geom(Dev g, int list, const double
     }
 }
 
+// LDS variant: the vertex values of the tile are computed once
+template <int D> struct GeoRegion;
+template <> struct GeoRegion<1> { static constexpr int X = 256 + 2, Y = 1, Z = 1; };
+template <> struct GeoRegion<2> { static constexpr int X = 16 + 2, Y = 16 + 2, Z = 1; };
+template <> struct GeoRegion<3> { static constexpr int X = 8 + 2, Y = 8 + 2, Z = 4 + 2; };
+
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_geom_lds(Dev g, int list, const double* cur)
+{
+    constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
+    constexpr int CX = GeoRegion<D>::X, CY = GeoRegion<D>::Y, CZ = GeoRegion<D>::Z, CN = CX * CY * CZ;
+    constexpr int VX = TX + 1, VY = D > 1 ? TY + 1 : 1, VZ = D > 2 ? TZ + 1 : 1, VN = VX * VY * VZ;
+    __shared__ double sP[CN];
+    __shared__ double sV[VN];
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int t = L[ti];
+        int ox = (t % g.nt[0]) * TX, oy = ((t / g.nt[0]) % g.nt[1]) * TY, oz = (t / (g.nt[0] * g.nt[1])) * TZ;
+        // cells (ox-1 .. ox+TX) x ...
+        for (int r = threadIdx.x; r < CN; r += SHARP_WG) {
+            int cx = r % CX, cy = (r / CX) % CY, cz = r / (CX * CY);
+            sP[r] = phi_at(g, cur, cidx(g, ox - 1 + cx, D > 1 ? oy - 1 + cy : 0, D > 2 ? oz - 1 + cz : 0));
+        }
+        __syncthreads();
+        // vertex (vx, vy, vz) <-> corner (ox+vx, ...): mean of cells (vx-1 .. vx) in region offset +1
+        for (int r = threadIdx.x; r < VN; r += SHARP_WG) {
+            int vx = r % VX, vy = (r / VX) % VY, vz = r / (VX * VY);
+            double sum = 0.0;
+#pragma unroll
+            for (int b = 0; b < (1 << D); b++) {
+                int cx = vx + (b & 1);
+                int cy = D > 1 ? vy + ((b >> 1) & 1) : 0;
+                int cz = D > 2 ? vz + ((b >> 2) & 1) : 0;
+                sum += sP[cx + CX * (cy + CY * cz)];
+            }
+            sV[r] = sum / (double)(1 << D);
+        }
+        __syncthreads();
+        int li = threadIdx.x % TX, lj = (threadIdx.x / TX) % TY, lk = threadIdx.x / (TX * TY);
+        int i = ox + li, j = oy + lj, k = oz + lk;
+        if (i < g.n[0] && j < g.n[1] && k < g.n[2]) {
+            int c = i + g.n[0] * (j + g.n[1] * k);
+            auto V = [&](int a, int b2, int c2) { return sV[(li + a) + VX * ((lj + b2) + VY * (lk + c2))]; };
+            int ii[3] = {i, j, k};
+            double alo[3], ahi[3];
+#pragma unroll
+            for (int d = 0; d < D; d++) {
+#pragma unroll
+                for (int side = 0; side < 2; side++) {
+                    int sx = d == 0 ? side : 0, sy = d == 1 ? side : 0, sz = d == 2 ? side : 0;
+                    double A;
+                    if (D == 1) {
+                        A = V(sx, 0, 0) < 0.0 ? 1.0 : 0.0;
+                    } else if (D == 2) {
+                        A = d == 0 ? edge_frac(V(sx, 0, 0), V(sx, 1, 0)) : edge_frac(V(0, sy, 0), V(1, sy, 0));
+                    } else {
+                        double v[4];
+                        if (d == 0) { v[0] = V(sx, 0, 0); v[1] = V(sx, 1, 0); v[2] = V(sx, 1, 1); v[3] = V(sx, 0, 1); }
+                        else if (d == 1) { v[0] = V(0, sy, 0); v[1] = V(1, sy, 0); v[2] = V(1, sy, 1); v[3] = V(0, sy, 1); }
+                        else { v[0] = V(0, 0, sz); v[1] = V(1, 0, sz); v[2] = V(1, 1, sz); v[3] = V(0, 1, sz); }
+                        A = clip_area(v);
+                    }
+                    if (side == 0) alo[d] = A; else ahi[d] = A;
+                }
+                g.ap[d][fidx(g, i, j, k)] = alo[d];
+                if (ii[d] == g.n[d] - 1) g.ap[d][fidx(g, i + (d == 0), j + (d == 1), k + (d == 2))] = ahi[d];
+            }
+            double a;
+            if (D == 1) {
+                a = edge_frac(V(0, 0, 0), V(1, 0, 0));
+            } else if (D == 2) {
+                double v[4] = {V(0, 0, 0), V(1, 0, 0), V(1, 1, 0), V(0, 1, 0)};
+                a = clip_area(v);
+            } else {
+                double sumA = 0.0, g2 = 0.0;
+#pragma unroll
+                for (int d = 0; d < 3; d++) {
+                    sumA += alo[d] + ahi[d];
+                    double gd = alo[d] - ahi[d];
+                    g2 += gd * gd;
+                }
+                a = (0.5 * sumA + sqrt(g2) * (-sP[(li + 1) + CX * ((lj + 1) + CY * (lk + 1))] / g.h)) / 3.0;
+                a = a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a);
+            }
+            g.alpha[c] = a;
+        }
+        __syncthreads();
+    }
+}
+
 // interface segment per unit volume of fluid 0 (points into fluid 1)
 template <int D>
 __device__ __forceinline__ double iface(const Dev& g, int i, int j, int k, double* gv)
@@ -637,8 +727,9 @@ template <int D> struct ExtRegion;
 template <> struct ExtRegion<1> { static constexpr int X = 256 + 2 * EXT_H, Y = 1; };
 template <> struct ExtRegion<2> { static constexpr int X = 16 + 2 * EXT_H, Y = 16 + 2 * EXT_H; };
 
-// fused primitive recovery (real band cells of both fluids) + extension of
-// both fluids' primitives; reads Wb[.][in], writes the band cells of Wb[.][out]
+// fused primitive recovery (real band cells) + extension of one fluid's
+// primitives per block (block b handles tile b/2, fluid b%2); reads
+// Wb[k][in], writes the band cells of Wb[k][out]
 template <int D>
 __global__ void __launch_bounds__(SHARP_WG) k_extw_tb(Dev g, int list, const double* src0, const double* src1,
                                                      int in, int out, int iters, const double* cur)
@@ -647,91 +738,103 @@ __global__ void __launch_bounds__(SHARP_WG) k_extw_tb(Dev g, int list, const dou
     constexpr int NV = D + 2;
     constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
     constexpr int RX = ExtRegion<D>::X, RY = ExtRegion<D>::Y, RN = RX * RY;
+    constexpr int PX = RX + 2, PY = D == 2 ? RY + 2 : 1, PN = PX * PY;   // level set with one more cell
     constexpr int CPT = (RN + SHARP_WG - 1) / SHARP_WG;
     constexpr int HY = D == 2 ? EXT_H : 0;
     __shared__ double sA[NV * RN], sB[NV * RN];
+    __shared__ double sPhi[PN];
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
-        int t = L[ti];
+    for (int wi = blockIdx.x; wi < 2 * list_count(g, list); wi += gridDim.x) {
+        int t = L[wi >> 1], k = wi & 1;
         int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
-        for (int k = 0; k < 2; k++) {
-            const double* src = k == 0 ? src0 : src1;
-            const double* Wi = g.Wb[k][in];
-            double sk = k == 0 ? 1.0 : -1.0;
-            bool tgt[CPT];
-            int up[CPT][2];
-            double w[CPT][2], wsum[CPT];
+        const double* src = k == 0 ? src0 : src1;
+        const double* Wi = g.Wb[k][in];
+        double sk = k == 0 ? 1.0 : -1.0;
+        for (int r = threadIdx.x; r < PN; r += SHARP_WG) {
+            int px = r % PX, py = r / PX;
+            sPhi[r] = phi_at(g, cur, cidx(g, ox - EXT_H - 1 + px, D == 2 ? oy - HY - 1 + py : 0, 0));
+        }
+        __syncthreads();
+        bool tgt[CPT];
+        int up[CPT][2];
+        double w[CPT][2];
+#pragma unroll
+        for (int m = 0; m < CPT; m++) {
+            int r = threadIdx.x + m * SHARP_WG;
+            tgt[m] = false;
+            if (r >= RN) continue;
+            int rx = r % RX, ry = r / RX;
+            int c = cidx(g, ox - EXT_H + rx, oy - HY + ry, 0);
+            double a = alpha_k(g, k, c);
+            bool inM = g.M[c] != 0;
+            if (inM && a >= g.amix) {
+                double U[NV], W[NV];
+                for (int q = 0; q < NV; q++) U[q] = src[(size_t)q * g.nc + c] / a;
+                if (!cons2prim<D>(g.gam[k], g.pinf[k], U, W)) flag_error(g, ERR_NONPHYS);
+                for (int q = 0; q < NV; q++) sA[q * RN + r] = W[q];
+            } else {
+                for (int q = 0; q < NV; q++) sA[q * RN + r] = Wi[(size_t)q * g.nc + c];
+            }
+            int pc = (rx + 1) + PX * (D == 2 ? ry + 1 : 0);
+            if (!inM || !(a < g.amix) || sk * sPhi[pc] > g.extb * g.h) continue;
+            double gr[2], g2 = 0.0;
+            gr[0] = (sPhi[pc + 1] - sPhi[pc - 1]) / (2.0 * g.h);
+            g2 += gr[0] * gr[0];
+            if (D == 2) {
+                gr[1] = (sPhi[pc + PX] - sPhi[pc - PX]) / (2.0 * g.h);
+                g2 += gr[1] * gr[1];
+            }
+            double gm = sqrt(g2);
+            if (!(gm > 0.0)) continue;
+            bool inside = true;
+            double wsum = 0.0;
+            for (int d = 0; d < D; d++) {
+                double nd = sk * gr[d] / gm;
+                int o = nd > 0.0 ? -1 : 1;
+                int qx = rx + (d == 0 ? o : 0), qy = ry + (d == 1 ? o : 0);
+                inside &= qx >= 0 && qx < RX && qy >= 0 && qy < RY;
+                up[m][d] = qx + RX * qy;
+                w[m][d] = fabs(nd);
+                wsum += w[m][d];
+            }
+            double iw = 1.0 / wsum;
+            for (int d = 0; d < D; d++) w[m][d] *= iw;
+            tgt[m] = inside;   // cells whose upwind stencil leaves the region stay frozen
+        }
+        __syncthreads();
+        double* A = sA;
+        double* B = sB;
+        for (int it = 0; it < iters; it++) {
 #pragma unroll
             for (int m = 0; m < CPT; m++) {
                 int r = threadIdx.x + m * SHARP_WG;
-                tgt[m] = false;
                 if (r >= RN) continue;
-                int rx = r % RX, ry = r / RX;
-                int c = cidx(g, ox - EXT_H + rx, oy - HY + ry, 0);
-                double a = alpha_k(g, k, c);
-                bool inM = g.M[c] != 0;
-                if (inM && a >= g.amix) {
-                    double U[NV], W[NV];
-                    for (int q = 0; q < NV; q++) U[q] = src[(size_t)q * g.nc + c] / a;
-                    if (!cons2prim<D>(g.gam[k], g.pinf[k], U, W)) flag_error(g, ERR_NONPHYS);
-                    for (int q = 0; q < NV; q++) sA[q * RN + r] = W[q];
-                } else {
-                    for (int q = 0; q < NV; q++) sA[q * RN + r] = Wi[(size_t)q * g.nc + c];
-                }
-                if (!inM || !(a < g.amix) || sk * phi_at(g, cur, c) > g.extb * g.h) continue;
-                double gr[3];
-                double gm = grad_phi<D>(g, cur, c, gr);
-                if (!(gm > 0.0)) continue;
-                bool inside = true;
-                wsum[m] = 0.0;
-                for (int d = 0; d < D; d++) {
-                    double nd = sk * gr[d] / gm;
-                    int o = nd > 0.0 ? -1 : 1;
-                    int qx = rx + (d == 0 ? o : 0), qy = ry + (d == 1 ? o : 0);
-                    inside &= qx >= 0 && qx < RX && qy >= 0 && qy < RY;
-                    up[m][d] = qx + RX * qy;
-                    w[m][d] = fabs(nd);
-                    wsum[m] += w[m][d];
-                }
-                tgt[m] = inside;   // cells whose upwind stencil leaves the region stay frozen
-            }
-            __syncthreads();
-            double* A = sA;
-            double* B = sB;
-            for (int it = 0; it < iters; it++) {
-#pragma unroll
-                for (int m = 0; m < CPT; m++) {
-                    int r = threadIdx.x + m * SHARP_WG;
-                    if (r >= RN) continue;
-                    for (int q = 0; q < NV; q++) {
-                        double v;
-                        if (tgt[m]) {
-                            double acc = 0.0;
-                            for (int d = 0; d < D; d++) acc += w[m][d] * A[q * RN + up[m][d]];
-                            v = acc / wsum[m];
-                        } else {
-                            v = A[q * RN + r];
-                        }
-                        B[q * RN + r] = v;
+                for (int q = 0; q < NV; q++) {
+                    double v;
+                    if (tgt[m]) {
+                        v = w[m][0] * A[q * RN + up[m][0]];
+                        if (D == 2) v += w[m][1] * A[q * RN + up[m][1]];
+                    } else {
+                        v = A[q * RN + r];
                     }
-                }
-                __syncthreads();
-                double* tmp = A; A = B; B = tmp;
-            }
-            // band cells of the tile
-            {
-                int li = threadIdx.x % TX, lj = threadIdx.x / TX;
-                int i = ox + li, j = oy + lj;
-                if (i < g.n[0] && j < g.n[1]) {
-                    int c = i + g.n[0] * j;
-                    if (g.M[c]) {
-                        int r = (li + EXT_H) + RX * (lj + HY);
-                        for (int q = 0; q < NV; q++) g.Wb[k][out][(size_t)q * g.nc + c] = A[q * RN + r];
-                    }
+                    B[q * RN + r] = v;
                 }
             }
             __syncthreads();
+            double* tmp = A; A = B; B = tmp;
         }
+        {
+            int li = threadIdx.x % TX, lj = threadIdx.x / TX;
+            int i = ox + li, j = oy + lj;
+            if (i < g.n[0] && j < g.n[1]) {
+                int c = i + g.n[0] * j;
+                if (g.M[c]) {
+                    int r = (li + EXT_H) + RX * (lj + HY);
+                    for (int q = 0; q < NV; q++) g.Wb[k][out][(size_t)q * g.nc + c] = A[q * RN + r];
+                }
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -916,6 +1019,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_cfl(Dev g, int list, int k, const 
     __shared__ double smax[SHARP_WG / 64];
     __shared__ unsigned long long scnt[SHARP_WG / 64];
     const int* L = list_ptr(g, list);
+    if (blockIdx.x >= list_count(g, list)) return;   // idle block: nothing to reduce
     double mx = 0.0;
     unsigned long long cnt = 0;
     for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
@@ -1425,11 +1529,19 @@ struct Engine {
     Dev& g;
     explicit Engine(Sim& sim) : s(sim), g(sim.g) {}
 
-    dim3 grid() const { return dim3(s.max_blocks < g.ntiles ? s.max_blocks : g.ntiles); }
+    // grid of a tile-list kernel: one block per listed tile (capped); the
+    // kernels loop over the device-side count, so any grid size is correct
+    dim3 grid(int list, int per_tile = 1) const
+    {
+        long long c = (long long)s.lcount[list] * per_tile;
+        if (c < 1) c = 1;
+        if (c > s.max_blocks) c = s.max_blocks;
+        return dim3((unsigned)c);
+    }
     dim3 wg() const { return dim3(SHARP_WG); }
 
     // ---- tiles and masks ----
-    void mask(int list, int ring) { k_mask<D><<<grid(), wg(), 0, s.stream>>>(g, list, ring); }
+    void mask(int list, int ring) { k_mask<D><<<grid(list), wg(), 0, s.stream>>>(g, list, ring); }
     void tiles()
     {
         int b = (g.ntiles + 255) / 256;
@@ -1437,22 +1549,22 @@ struct Engine {
         k_tiles2<D><<<b, 256, 0, s.stream>>>(g);
         k_compact<<<1, 1024, 0, s.stream>>>(g);
     }
-    void geom(const double* cur, int list = LIST_BAND) { k_geom<D><<<grid(), wg(), 0, s.stream>>>(g, list, cur); }
+    void geom(const double* cur, int list = LIST_BAND) { k_geom_lds<D><<<grid(list), wg(), 0, s.stream>>>(g, list, cur); }
 
     // ---- band physics ----
-    void prims(int k, const double* src) { k_prims<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, k, src, s.wcur); }
+    void prims(int k, const double* src) { k_prims<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, k, src, s.wcur); }
     void extw(const double* cur)
     {
         for (int it = 0; it < s.o.ext_iters; it++) {
-            k_extw<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, s.wcur, 1 - s.wcur, cur);
+            k_extw<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, s.wcur, 1 - s.wcur, cur);
             s.wcur ^= 1;
         }
     }
-    void interact(double wcorr, int S) { k_interact<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, s.wcur, s.vcur, wcorr, S); }
+    void interact(double wcorr, int S) { k_interact<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, s.wcur, s.vcur, wcorr, S); }
     void extv(const double* cur)
     {
         for (int it = 0; it < s.o.ext_iters; it++) {
-            k_extv<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, s.vcur, 1 - s.vcur, cur);
+            k_extv<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, s.vcur, 1 - s.vcur, cur);
             s.vcur ^= 1;
         }
     }
@@ -1462,7 +1574,7 @@ struct Engine {
     {
         if constexpr (D <= 2) {
             if (s.o.ext_iters <= EXT_H) {
-                k_extw_tb<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, src0, src1, s.wcur, 1 - s.wcur,
+                k_extw_tb<D><<<grid(LIST_BAND, 2), wg(), 0, s.stream>>>(g, LIST_BAND, src0, src1, s.wcur, 1 - s.wcur,
                                                             s.o.ext_iters, cur);
                 s.wcur ^= 1;
                 return;
@@ -1476,7 +1588,7 @@ struct Engine {
     {
         if constexpr (D <= 2) {
             if (s.o.ext_iters <= EXT_H) {
-                k_extv_tb<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, s.vcur, 1 - s.vcur, s.o.ext_iters, cur);
+                k_extv_tb<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, s.vcur, 1 - s.vcur, s.o.ext_iters, cur);
                 s.vcur ^= 1;
                 return;
             }
@@ -1489,18 +1601,18 @@ struct Engine {
         interact(wcorr, S);
         velocity(cur);
     }
-    void corr_add(double w, int S) { k_corr_add<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, w, S); }
+    void corr_add(double w, int S) { k_corr_add<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, w, S); }
     void mix(int k, double* cons, const double* cur)
     {
         if constexpr (D <= 2)
-            k_mixdelta_lds<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, cur);
+            k_mixdelta_lds<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, cur);
         else
-            k_mixdelta<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, cur);
-        k_mixapply<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, cons);
+            k_mixdelta<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, cur);
+        k_mixapply<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, cons);
     }
     void axpby(double a1, const double* s1, double a2, const double* s2, double* dst, int ncomp)
     {
-        k_axpby<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, a1, s1, a2, s2, dst, ncomp);
+        k_axpby<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, a1, s1, a2, s2, dst, ncomp);
     }
 
     // ---- stages ----
@@ -1528,9 +1640,9 @@ struct Engine {
                       double a, double dt, double wflux)
     {
         if constexpr (D <= 2)
-            k_stage_lds<D, BAND><<<grid(), wg(), 0, s.stream>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
+            k_stage_lds<D, BAND><<<grid(list), wg(), 0, s.stream>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
         else
-            k_stage<D, BAND><<<grid(), wg(), 0, s.stream>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
+            k_stage<D, BAND><<<grid(list), wg(), 0, s.stream>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
     }
     void profile_flush()
     {
@@ -1553,39 +1665,37 @@ struct Engine {
     {
         int K = s.o.reinit_iters;
         if (K <= 0) {
-            k_copy_masked<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, phi0, g.phiP);
+            k_copy_masked<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, phi0, g.phiP);
             return;
         }
-        k_nearif<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, phi0);
+        k_nearif<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, phi0);
         double* other = (phi0 == g.phiB[0]) ? g.phiB[1] : g.phiB[0];
         const double* in = phi0;
         for (int m = 1; m <= K; m++) {
             double* out = (m == K) ? g.phiP : ((m % 2 == 1) ? g.phiB[2] : other);
-            k_reinit<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, phi0, in, out);
+            k_reinit<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, phi0, in, out);
             in = out;
         }
     }
     void ls(double a, double dt, const double* in, double* out)
     {
-        k_ls<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, a, dt, in, out, s.vcur);
+        k_ls<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, a, dt, in, out, s.vcur);
     }
 
     // ---- CFL ----
     void cfl_launch(int k, const double* cons)
     {
         int bl = k == 0 ? LIST_BULK0 : LIST_BULK1;
-        k_cfl<D, false><<<grid(), wg(), 0, s.stream>>>(g, bl, k, cons, s.wcur);
-        k_cfl<D, true><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, s.wcur);
+        k_cfl<D, false><<<grid(bl), wg(), 0, s.stream>>>(g, bl, k, cons, s.wcur);
+        k_cfl<D, true><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, s.wcur);
     }
     // read back the reductions; fills dt and active-cell counts of the fluids in `which`
     sim_status readback(int which, double* dt, long long* cnt)
     {
         SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s.stream));
-        SHARP_HIP(hipMemcpyAsync(s.h_red + 8, g.counts + 8, 4 * sizeof(int), hipMemcpyDeviceToHost, s.stream));
+        SHARP_HIP(hipMemcpyAsync(s.h_red + 8, g.counts, 16 * sizeof(int), hipMemcpyDeviceToHost, s.stream));
         SHARP_HIP(hipStreamSynchronize(s.stream));
-        const int* cc = reinterpret_cast<const int*>(s.h_red + 8);
-        s.bulk_cells[0] = cc[2];
-        s.bulk_cells[1] = cc[3];
+        take_counts();
         unsigned long long err = s.h_red[4];
         if (err & ERR_NONPHYS) { set_error("non-physical state (rho <= 0, p + p_inf <= 0 or NaN)"); return SIM_ENONPHYS; }
         if (err & ERR_BAND_OVERFLOW) { set_error("the interface band moved more than one tile within a cycle"); return SIM_EDEVICE; }
@@ -1596,6 +1706,14 @@ struct Engine {
             dt[k] = (cnt[k] > 0 && m > 0.0) ? s.o.cfl / m : INFINITY;
         }
         return SIM_OK;
+    }
+    void take_counts()
+    {
+        const int* cc = reinterpret_cast<const int*>(s.h_red + 8);
+        for (int l = 0; l < 4; l++) s.lcount[l] = cc[l];
+        s.lcount[LIST_ALL] = g.ntiles;
+        s.bulk_cells[0] = cc[8 + 2];
+        s.bulk_cells[1] = cc[8 + 3];
     }
     static double __longlong_as_double_host(unsigned long long b)
     {
@@ -1759,7 +1877,7 @@ struct Engine {
             geom(g.phiP);
         }
         // interfacial flux correction of the slow fluid, then mixing
-        k_corr_apply<D><<<grid(), wg(), 0, s.stream>>>(g, LIST_BAND, S, corr ? 1 : 0);
+        k_corr_apply<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, S, corr ? 1 : 0);
         mix(S, g.X[S], g.phiP);
         s.t += t1;
         st->cycles++;
@@ -1807,6 +1925,7 @@ struct Engine {
 
     sim_status set_state(const double* phi, const double* prim)
     {
+        s.lcount[LIST_ALL] = g.ntiles;
         SHARP_HIP(hipMemcpyAsync(g.phiP, phi, sizeof(double) * g.nc, hipMemcpyDeviceToDevice, s.stream));
         SHARP_HIP(hipMemsetAsync(g.M, 0, g.nc, s.stream));
         geom(g.phiP, LIST_ALL);
@@ -1819,8 +1938,10 @@ struct Engine {
         for (int k = 0; k < 2; k++)
             SHARP_HIP(hipMemsetAsync(g.bacc[k], 0, sizeof(double) * NV * (size_t)(g.nbface > 0 ? g.nbface : 1), s.stream));
         SHARP_HIP(hipMemsetAsync(g.red, 0, 8 * sizeof(unsigned long long), s.stream));
+        SHARP_HIP(hipMemcpyAsync(s.h_red + 8, g.counts, 16 * sizeof(int), hipMemcpyDeviceToHost, s.stream));
         SHARP_HIP(hipStreamSynchronize(s.stream));
         SHARP_HIP(hipGetLastError());
+        take_counts();
         s.t = 0.0;
         s.wcur = 0;
         s.vcur = 0;
