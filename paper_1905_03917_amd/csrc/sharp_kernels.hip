@@ -600,6 +600,95 @@ __global__ void __launch_bounds__(SHARP_WG) k_mixdelta_lds(Dev g, int list, int 
     }
 }
 
+// Slow fluid's temporary state: dst = v + mixing increment of v, where
+// v = a1*s1 + a2*s2 (Eq. interpolation) is formed on the fly; the inputs are
+// read only, so one kernel suffices (the increments use pre-mixing values).
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_mixinterp_lds(Dev g, int list, int k, double a1, const double* s1,
+                                                           double a2, const double* s2, double* dst, int do_mix,
+                                                           const double* cur)
+{
+    static_assert(D <= 2, "LDS mixing is for 1-D and 2-D");
+    constexpr int NV = D + 2;
+    constexpr int NS = (1 << D) - 1;
+    constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
+    constexpr int RX = MixRegion<D>::X, RY = MixRegion<D>::Y, RN = RX * RY;
+    constexpr int HY = D == 2 ? 1 : 0;
+    __shared__ double sBeta[NS * RN];
+    __shared__ int sTgt[NS * RN];
+    __shared__ int sCell[RN];
+    const int* L = list_ptr(g, list);
+    auto val = [&](int q, int c) {
+        size_t e = (size_t)q * g.nc + c;
+        return s2 ? a1 * s1[e] + a2 * s2[e] : s1[e];
+    };
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int t = L[ti];
+        int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
+        if (do_mix) {
+            for (int r = threadIdx.x; r < RN; r += SHARP_WG) {
+                int rx = r % RX, ry = r / RX;
+                int c = cidx(g, ox - 1 + rx, oy - HY + ry, 0);
+                sCell[r] = c;
+                double beta[7];
+                int tgt[7];
+                bool src = mix_source<D>(g, cur, k, c, beta, tgt);
+                for (int m = 0; m < NS; m++) {
+                    sBeta[m * RN + r] = src ? beta[m] : 0.0;
+                    sTgt[m * RN + r] = src ? tgt[m] : -1;
+                }
+            }
+        }
+        __syncthreads();
+        int li = threadIdx.x % TX, lj = threadIdx.x / TX;
+        int i = ox + li, j = oy + lj;
+        if (i < g.n[0] && j < g.n[1]) {
+            int c = i + g.n[0] * j;
+            double vc[NV], dl[NV];
+            for (int q = 0; q < NV; q++) { vc[q] = val(q, c); dl[q] = 0.0; }
+            if (do_mix && g.M[c]) {
+                int rc = (li + 1) + RX * (lj + HY);
+                double ac = alpha_k(g, k, c);
+                for (int m = 0; m < NS; m++) {
+                    int tt = sTgt[m * RN + rc];
+                    double b = sBeta[m * RN + rc];
+                    if (tt < 0 || !(b > 0.0) || tt == c) continue;
+                    double at = alpha_k(g, k, tt);
+                    if (!(ac + at > 0.0)) continue;
+                    for (int q = 0; q < NV; q++) dl[q] += b * (val(q, tt) * ac - vc[q] * at) / (ac + at);
+                }
+                bool edge = i == 0 || i == g.n[0] - 1 || (D == 2 && (j == 0 || j == g.n[1] - 1));
+                int seen[8];
+                int ns = 0;
+                for (int oy2 = -HY; oy2 <= HY; oy2++)
+                    for (int ox2 = -1; ox2 <= 1; ox2++) {
+                        if (!ox2 && !oy2) continue;
+                        int rs = rc + ox2 + RX * oy2;
+                        int sc = sCell[rs];
+                        if (sc == c) continue;
+                        if (edge) {
+                            bool dup = false;
+                            for (int u = 0; u < ns; u++) dup |= (seen[u] == sc);
+                            if (dup) continue;
+                            seen[ns++] = sc;
+                        }
+                        if (sTgt[rs] < 0) continue;
+                        double as = alpha_k(g, k, sc);
+                        if (!(as + ac > 0.0)) continue;
+                        for (int m = 0; m < NS; m++) {
+                            if (sTgt[m * RN + rs] != c) continue;
+                            double b = sBeta[m * RN + rs];
+                            if (!(b > 0.0)) continue;
+                            for (int q = 0; q < NV; q++) dl[q] -= b * (vc[q] * as - val(q, sc) * ac) / (as + ac);
+                        }
+                    }
+            }
+            for (int q = 0; q < NV; q++) dst[(size_t)q * g.nc + c] = vc[q] + dl[q];
+        }
+        __syncthreads();
+    }
+}
+
 template <int D>
 __global__ void __launch_bounds__(SHARP_WG) k_mixapply(Dev g, int list, double* cons)
 {
@@ -1222,8 +1311,11 @@ template <> struct Region<2> { static constexpr int X = 16 + 6, Y = 16 + 6; };
 template <int D, bool BAND>
 __global__ void __launch_bounds__(SHARP_WG) k_stage_lds(Dev g, int list, int k, const double* in, const double* self2,
                                                        const double* base, double* out, double a, double dt,
-                                                       double wflux, int wb)
+                                                       double wflux, int wb, int cfl)
 {
+    __shared__ double sMax[SHARP_WG / 64];
+    double cmax = 0.0;          // CFL speed of this thread's output cells (bulk, when cfl != 0)
+    unsigned long long ccnt = 0;
     static_assert(D <= 2, "LDS stage kernel is for 1-D and 2-D");
     constexpr int NV = D + 2;
     constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
@@ -1349,15 +1441,42 @@ __global__ void __launch_bounds__(SHARP_WG) k_stage_lds(Dev g, int list, int k, 
                     }
                 }
                 const double* sin_ = (BAND && self2 && g.M[c]) ? self2 : in;
+                double Uo[NV];
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     size_t e = (size_t)q * g.nc + c;
                     double s = sin_[e] + dt * Lr[q];
-                    out[e] = (a == 0.0) ? s : a * base[e] + (1.0 - a) * s;
+                    Uo[q] = (a == 0.0) ? s : a * base[e] + (1.0 - a) * s;
+                    out[e] = Uo[q];
+                }
+                if (!BAND && cfl) {
+                    double W[NV];
+                    if (!cons2prim<D>(gm, pi, Uo, W)) flag_error(g, ERR_NONPHYS);
+                    double cs = csound(gm, pi, W[0], W[D + 1]), sp = 0.0;
+                    for (int d = 0; d < D; d++) sp += (fabs(W[1 + d]) + cs) / g.h;
+                    cmax = fmax(cmax, sp);
+                    ccnt++;
                 }
             }
         }
         __syncthreads();
+    }
+    if (!BAND && cfl) {
+        if (blockIdx.x >= list_count(g, list)) return;
+        for (int off = 32; off > 0; off >>= 1) {
+            cmax = fmax(cmax, __shfl_down(cmax, off, 64));
+            ccnt += __shfl_down(ccnt, off, 64);
+        }
+        __shared__ unsigned long long sCnt[SHARP_WG / 64];
+        int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+        if (lane == 0) { sMax[wid] = cmax; sCnt[wid] = ccnt; }
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < SHARP_WG / 64; w++) { cmax = fmax(cmax, sMax[w]); ccnt += sCnt[w]; }
+            if (!(cmax >= 0.0) || isinf(cmax)) { flag_error(g, ERR_NONPHYS); cmax = 0.0; }
+            atomicMax(&g.red[k], (unsigned long long)__double_as_longlong(cmax));
+            atomicAdd(&g.red[2 + k], ccnt);
+        }
     }
 }
 
@@ -1617,9 +1736,10 @@ struct Engine {
 
     // ---- stages ----
     void stage(int k, const double* in, const double* self2, const double* base, double* out, double a, double dt,
-               double wflux)
+               double wflux, int cfl = 0)
     {
         int bl = k == 0 ? LIST_BULK0 : LIST_BULK1;
+        if (cfl) k_zero_red<<<1, 64, 0, s.stream>>>(g);
         size_t ev = 0;
         if (s.prof) {
             if (s.ev_used + 2 > s.ev_pool.size()) profile_flush();
@@ -1627,20 +1747,23 @@ struct Engine {
             s.ev_used += 2;
             (void)hipEventRecord(s.ev_pool[ev], s.stream);
         }
-        launch_stage<false>(bl, k, in, nullptr, base, out, a, dt, wflux);
+        launch_stage<false>(bl, k, in, nullptr, base, out, a, dt, wflux, cfl);
         if (s.prof) {
             (void)hipEventRecord(s.ev_pool[ev + 1], s.stream);
             // algorithmic bytes: read `in` (and `base` after the first stage), write `out`
             s.prof_cells.push_back(s.bulk_cells[k] * (long long)((a == 0.0 ? 2 : 3) * NV * 8));
         }
-        launch_stage<true>(LIST_BAND, k, in, self2, base, out, a, dt, wflux);
+        launch_stage<true>(LIST_BAND, k, in, self2, base, out, a, dt, wflux, 0);
+        fused_cfl = cfl && D <= 2;
     }
+    bool fused_cfl = false;    // the last bulk stage already reduced the fast fluid's CFL speed
     template <bool BAND>
     void launch_stage(int list, int k, const double* in, const double* self2, const double* base, double* out,
-                      double a, double dt, double wflux)
+                      double a, double dt, double wflux, int cfl)
     {
         if constexpr (D <= 2)
-            k_stage_lds<D, BAND><<<grid(list), wg(), 0, s.stream>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
+            k_stage_lds<D, BAND><<<grid(list), wg(), 0, s.stream>>>(g, list, k, in, self2, base, out, a, dt, wflux,
+                                                                    s.wcur, cfl);
         else
             k_stage<D, BAND><<<grid(list), wg(), 0, s.stream>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
     }
@@ -1769,8 +1892,24 @@ struct Engine {
     // current geometry unless it is the (already mixed) previous state
     void interp_slow(int S, double theta, const double* cur)
     {
+        if constexpr (D <= 2) {
+            k_mixinterp_lds<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, S, 1.0 - theta, g.X[S], theta,
+                                                                        g.Y[S], g.T2, theta != 0.0, cur);
+            return;
+        }
         axpby(1.0 - theta, g.X[S], theta, g.Y[S], g.T2, NV);
         if (theta != 0.0) mix(S, g.T2, cur);
+    }
+    // copy of src mixed with the current geometry
+    void mixed_copy(int S, const double* src, const double* cur)
+    {
+        if constexpr (D <= 2) {
+            k_mixinterp_lds<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, S, 1.0, src, 0.0, nullptr,
+                                                                        g.T2, 1, cur);
+            return;
+        }
+        axpby(1.0, src, 0.0, nullptr, g.T2, NV);
+        mix(S, g.T2, cur);
     }
 
     // ---- the accelerated cycle (Sec. 3.1) ----
@@ -1815,8 +1954,14 @@ struct Engine {
                 mask(LIST_BAND, 1);
                 interp_slow(S, tau / t1, g.phiP);
                 interaction(S == 0 ? g.T2 : g.X[F], S == 0 ? g.X[F] : g.T2, g.phiP, 0.0, S);
-                k_zero_red<<<1, 64, 0, s.stream>>>(g);
-                cfl_launch(F, g.X[F]);
+                if (fused_cfl) {
+                    // bulk tiles were reduced by the previous sub-step's last stage
+                    k_cfl<D, true><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, F, g.X[F], s.wcur);
+                } else {
+                    k_zero_red<<<1, 64, 0, s.stream>>>(g);
+                    cfl_launch(F, g.X[F]);
+                }
+                fused_cfl = false;
                 sim_status rc = readback(1 << F, d2, c2);
                 if (rc != SIM_OK) return rc;
                 dtF = d2[F];
@@ -1846,7 +1991,7 @@ struct Engine {
                     corr_add(B[0] * dl, S);   // Eq. (secondcorrection)
                 }
                 double* out = (q == ns - 1) ? g.X[F] : (q == 0 ? g.Y[F] : g.Z[F]);
-                stage(F, in, nullptr, g.X[F], out, A[q], dl, B[q] * dl);
+                stage(F, in, nullptr, g.X[F], out, A[q], dl, B[q] * dl, (q == ns - 1 && !fin) ? 1 : 0);
                 double* po = phi_stage_out(q);
                 ls(A[q], dl, phin, po);
                 const double* cur = po;
@@ -1870,8 +2015,7 @@ struct Engine {
         if (ns == 3) {
             // slow fluid's third stage at t1/2 against the snapshots
             geom(g.phiH);
-            axpby(1.0, g.Z[S], 0.0, nullptr, g.T2, NV);
-            mix(S, g.T2, g.phiH);
+            mixed_copy(S, g.Z[S], g.phiH);
             interaction(S == 0 ? g.T2 : g.Fh, S == 0 ? g.Fh : g.T2, g.phiH, corr ? -B[2] * t1 : 0.0, S);
             stage(S, g.Z[S], g.T2, g.X[S], g.X[S], A[2], t1, B[2] * t1);
             geom(g.phiP);
