@@ -816,19 +816,26 @@ template <int D> struct ExtRegion;
 template <> struct ExtRegion<1> { static constexpr int X = 256 + 2 * EXT_H, Y = 1; };
 template <> struct ExtRegion<2> { static constexpr int X = 16 + 2 * EXT_H, Y = 16 + 2 * EXT_H; };
 
+// block sizes of the temporally blocked kernels: one thread per region cell
+// for the extension of primitives, two for the interaction + velocity kernel
+template <int D> struct ExtWG;
+template <> struct ExtWG<1> { static constexpr int W = 256, V = 256; };
+template <> struct ExtWG<2> { static constexpr int W = 1024, V = 512; };
+
 // fused primitive recovery (real band cells) + extension of one fluid's
 // primitives per block (block b handles tile b/2, fluid b%2); reads
 // Wb[k][in], writes the band cells of Wb[k][out]
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_extw_tb(Dev g, int list, const double* src0, const double* src1,
-                                                     int in, int out, int iters, const double* cur)
+__global__ void __launch_bounds__(ExtWG<D>::W) k_extw_tb(Dev g, int list, const double* src0, const double* src1,
+                                                        int in, int out, int iters, const double* cur)
 {
     static_assert(D <= 2, "temporally blocked extension is for 1-D and 2-D");
     constexpr int NV = D + 2;
+    constexpr int WGS = ExtWG<D>::W;
     constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
     constexpr int RX = ExtRegion<D>::X, RY = ExtRegion<D>::Y, RN = RX * RY;
     constexpr int PX = RX + 2, PY = D == 2 ? RY + 2 : 1, PN = PX * PY;   // level set with one more cell
-    constexpr int CPT = (RN + SHARP_WG - 1) / SHARP_WG;
+    constexpr int CPT = (RN + WGS - 1) / WGS;
     constexpr int HY = D == 2 ? EXT_H : 0;
     __shared__ double sA[NV * RN], sB[NV * RN];
     __shared__ double sPhi[PN];
@@ -839,7 +846,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_extw_tb(Dev g, int list, const dou
         const double* src = k == 0 ? src0 : src1;
         const double* Wi = g.Wb[k][in];
         double sk = k == 0 ? 1.0 : -1.0;
-        for (int r = threadIdx.x; r < PN; r += SHARP_WG) {
+        for (int r = threadIdx.x; r < PN; r += WGS) {
             int px = r % PX, py = r / PX;
             sPhi[r] = phi_at(g, cur, cidx(g, ox - EXT_H - 1 + px, D == 2 ? oy - HY - 1 + py : 0, 0));
         }
@@ -849,7 +856,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_extw_tb(Dev g, int list, const dou
         double w[CPT][2];
 #pragma unroll
         for (int m = 0; m < CPT; m++) {
-            int r = threadIdx.x + m * SHARP_WG;
+            int r = threadIdx.x + m * WGS;
             tgt[m] = false;
             if (r >= RN) continue;
             int rx = r % RX, ry = r / RX;
@@ -896,7 +903,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_extw_tb(Dev g, int list, const dou
         for (int it = 0; it < iters; it++) {
 #pragma unroll
             for (int m = 0; m < CPT; m++) {
-                int r = threadIdx.x + m * SHARP_WG;
+                int r = threadIdx.x + m * WGS;
                 if (r >= RN) continue;
                 for (int q = 0; q < NV; q++) {
                     double v;
@@ -912,8 +919,8 @@ __global__ void __launch_bounds__(SHARP_WG) k_extw_tb(Dev g, int list, const dou
             __syncthreads();
             double* tmp = A; A = B; B = tmp;
         }
-        {
-            int li = threadIdx.x % TX, lj = threadIdx.x / TX;
+        for (int u = threadIdx.x; u < TX * TY; u += WGS) {
+            int li = u % TX, lj = u / TX;
             int i = ox + li, j = oy + lj;
             if (i < g.n[0] && j < g.n[1]) {
                 int c = i + g.n[0] * j;
@@ -927,52 +934,125 @@ __global__ void __launch_bounds__(SHARP_WG) k_extw_tb(Dev g, int list, const dou
     }
 }
 
-// level-set velocity extension, temporally blocked
+// Riemann problem of cut cell c with fluid states from Wb[.][wb]:
+// st = {p*, u*, rho*_0, rho*_1}
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_extv_tb(Dev g, int list, int in, int out, int iters, const double* cur)
+__device__ __forceinline__ void interface_solve(const Dev& g, int c, const double* gv, double gm, int wb, double* st)
+{
+    const double* W0 = g.Wb[0][wb];
+    const double* W1 = g.Wb[1][wb];
+    double un0 = 0.0, un1 = 0.0;
+    for (int d = 0; d < D; d++) {
+        un0 += W0[(size_t)(1 + d) * g.nc + c] * gv[d] / gm;
+        un1 += W1[(size_t)(1 + d) * g.nc + c] * gv[d] / gm;
+    }
+    Side Ls = {W0[c], un0, W0[(size_t)(D + 1) * g.nc + c], g.gam[0], g.pinf[0]};
+    Side Rs = {W1[c], un1, W1[(size_t)(D + 1) * g.nc + c], g.gam[1], g.pinf[1]};
+    riemann(Ls, Rs, st);
+}
+
+// store the interface solution of the tile's own cut cell c (and book the
+// correction); non-cut cells get zeros
+template <int D>
+__device__ __forceinline__ void interface_store(const Dev& g, int c, const double* gv, double gm, const double* st,
+                                                double wcorr, int S)
+{
+    if (!(gm > 0.0)) {
+        g.ps[c] = 0.0; g.us[c] = 0.0; g.ss[0][c] = 0.0; g.ss[1][c] = 0.0;
+        return;
+    }
+    g.ps[c] = st[0];
+    g.us[c] = st[1];
+    for (int k = 0; k < 2; k++) {
+        double rs = st[2 + k];
+        double cs = rs > 0.0 ? csound(g.gam[k], g.pinf[k], rs, st[0]) : 0.0;
+        double sum = 0.0;
+        for (int d = 0; d < D; d++) sum += (fabs(st[1] * gv[d] / gm) + cs) / g.h;
+        g.ss[k][c] = sum;
+    }
+    if (wcorr != 0.0) {
+        double sg = S == 0 ? 1.0 : -1.0;
+        for (int d = 0; d < D; d++) g.corr[(size_t)(1 + d) * g.nc + c] += wcorr * (-sg * st[0] * gv[d]);
+        g.corr[(size_t)(D + 1) * g.nc + c] += wcorr * (-sg * st[0] * st[1] * gm);
+    }
+}
+
+// interface interaction + level-set velocity extension, temporally blocked:
+// every cut cell of the region is solved (redundantly across blocks), the
+// tile's own cut cells store p*, u*, star speeds and the correction, and the
+// velocity u* n is extended over the region
+template <int D>
+__global__ void __launch_bounds__(ExtWG<D>::V) k_intv_tb(Dev g, int list, int wb, int in, int out, int iters,
+                                                        const double* cur, double wcorr, int S)
 {
     static_assert(D <= 2, "temporally blocked extension is for 1-D and 2-D");
+    constexpr int WGS = ExtWG<D>::V;
     constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
     constexpr int RX = ExtRegion<D>::X, RY = ExtRegion<D>::Y, RN = RX * RY;
-    constexpr int CPT = (RN + SHARP_WG - 1) / SHARP_WG;
+    constexpr int PX = RX + 2, PY = D == 2 ? RY + 2 : 1, PN = PX * PY;
+    constexpr int CPT = (RN + WGS - 1) / WGS;
     constexpr int HY = D == 2 ? EXT_H : 0;
     __shared__ double sA[D * RN], sB[D * RN];
+    __shared__ double sPhi[PN];
     const int* L = list_ptr(g, list);
     for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
         int t = L[ti];
         int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
+        for (int r = threadIdx.x; r < PN; r += WGS) {
+            int px = r % PX, py = r / PX;
+            sPhi[r] = phi_at(g, cur, cidx(g, ox - EXT_H - 1 + px, D == 2 ? oy - HY - 1 + py : 0, 0));
+        }
+        __syncthreads();
         bool tgt[CPT];
         int up[CPT][2];
-        double w[CPT][2], wsum[CPT];
+        double w[CPT][2];
 #pragma unroll
         for (int m = 0; m < CPT; m++) {
-            int r = threadIdx.x + m * SHARP_WG;
+            int r = threadIdx.x + m * WGS;
             tgt[m] = false;
             if (r >= RN) continue;
             int rx = r % RX, ry = r / RX;
             int gi = ox - EXT_H + rx, gj = oy - HY + ry;
             int c = cidx(g, gi, gj, 0);
-            for (int e = 0; e < D; e++) sA[e * RN + r] = g.v[in][e][c];
-            if (!g.M[c]) continue;
             int ci, cj, ck;
             coords(g, c, ci, cj, ck);
             double gv[3];
-            if (iface<D>(g, ci, cj, ck, gv) > 0.0) continue;
-            double gr[3];
-            double gm = grad_phi<D>(g, cur, c, gr);
-            if (!(gm > 0.0)) continue;
-            double sg = phi_at(g, cur, c) < 0.0 ? -1.0 : 1.0;
+            double gm = iface<D>(g, ci, cj, ck, gv);
+            bool own = rx >= EXT_H && rx < EXT_H + TX && ry >= HY && ry < HY + TY && gi < g.n[0] && gj < g.n[1];
+            if (gm > 0.0) {
+                double st[4];
+                interface_solve<D>(g, c, gv, gm, wb, st);
+                for (int e = 0; e < D; e++) sA[e * RN + r] = st[1] * gv[e] / gm;
+                if (own) interface_store<D>(g, c, gv, gm, st, wcorr, S);
+                continue;
+            }
+            if (own) interface_store<D>(g, c, gv, gm, nullptr, 0.0, S);
+            for (int e = 0; e < D; e++) sA[e * RN + r] = g.v[in][e][c];
+            if (!g.M[c]) continue;
+            int pc = (rx + 1) + PX * (D == 2 ? ry + 1 : 0);
+            double gr[2], g2 = 0.0;
+            gr[0] = (sPhi[pc + 1] - sPhi[pc - 1]) / (2.0 * g.h);
+            g2 += gr[0] * gr[0];
+            if (D == 2) {
+                gr[1] = (sPhi[pc + PX] - sPhi[pc - PX]) / (2.0 * g.h);
+                g2 += gr[1] * gr[1];
+            }
+            double gmp = sqrt(g2);
+            if (!(gmp > 0.0)) continue;
+            double sg = sPhi[pc] < 0.0 ? -1.0 : 1.0;
             bool inside = true;
-            wsum[m] = 0.0;
+            double wsum = 0.0;
             for (int d = 0; d < D; d++) {
-                double nd = sg * gr[d] / gm;
+                double nd = sg * gr[d] / gmp;
                 int o = nd > 0.0 ? -1 : 1;
                 int qx = rx + (d == 0 ? o : 0), qy = ry + (d == 1 ? o : 0);
                 inside &= qx >= 0 && qx < RX && qy >= 0 && qy < RY;
                 up[m][d] = qx + RX * qy;
                 w[m][d] = fabs(nd);
-                wsum[m] += w[m][d];
+                wsum += w[m][d];
             }
+            double iw = 1.0 / wsum;
+            for (int d = 0; d < D; d++) w[m][d] *= iw;
             tgt[m] = inside;
         }
         __syncthreads();
@@ -981,14 +1061,13 @@ __global__ void __launch_bounds__(SHARP_WG) k_extv_tb(Dev g, int list, int in, i
         for (int it = 0; it < iters; it++) {
 #pragma unroll
             for (int m = 0; m < CPT; m++) {
-                int r = threadIdx.x + m * SHARP_WG;
+                int r = threadIdx.x + m * WGS;
                 if (r >= RN) continue;
                 for (int e = 0; e < D; e++) {
                     double v;
                     if (tgt[m]) {
-                        double acc = 0.0;
-                        for (int d = 0; d < D; d++) acc += w[m][d] * A[e * RN + up[m][d]];
-                        v = acc / wsum[m];
+                        v = w[m][0] * A[e * RN + up[m][0]];
+                        if (D == 2) v += w[m][1] * A[e * RN + up[m][1]];
                     } else {
                         v = A[e * RN + r];
                     }
@@ -998,8 +1077,8 @@ __global__ void __launch_bounds__(SHARP_WG) k_extv_tb(Dev g, int list, int in, i
             __syncthreads();
             double* tmp = A; A = B; B = tmp;
         }
-        {
-            int li = threadIdx.x % TX, lj = threadIdx.x / TX;
+        for (int u = threadIdx.x; u < TX * TY; u += WGS) {
+            int li = u % TX, lj = u / TX;
             int i = ox + li, j = oy + lj;
             if (i < g.n[0] && j < g.n[1]) {
                 int c = i + g.n[0] * j;
@@ -1693,7 +1772,7 @@ struct Engine {
     {
         if constexpr (D <= 2) {
             if (s.o.ext_iters <= EXT_H) {
-                k_extw_tb<D><<<grid(LIST_BAND, 2), wg(), 0, s.stream>>>(g, LIST_BAND, src0, src1, s.wcur, 1 - s.wcur,
+                k_extw_tb<D><<<grid(LIST_BAND, 2), ExtWG<D>::W, 0, s.stream>>>(g, LIST_BAND, src0, src1, s.wcur, 1 - s.wcur,
                                                             s.o.ext_iters, cur);
                 s.wcur ^= 1;
                 return;
@@ -1703,20 +1782,18 @@ struct Engine {
         prims(1, src1);
         extw(cur);
     }
-    void velocity(const double* cur)
+    void velocity(const double* cur) { extv(cur); }
+    void interaction(const double* src0, const double* src1, const double* cur, double wcorr, int S)
     {
+        band_state(src0, src1, cur);
         if constexpr (D <= 2) {
             if (s.o.ext_iters <= EXT_H) {
-                k_extv_tb<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, s.vcur, 1 - s.vcur, s.o.ext_iters, cur);
+                k_intv_tb<D><<<grid(LIST_BAND), ExtWG<D>::V, 0, s.stream>>>(g, LIST_BAND, s.wcur, s.vcur, 1 - s.vcur,
+                                                                            s.o.ext_iters, cur, wcorr, S);
                 s.vcur ^= 1;
                 return;
             }
         }
-        extv(cur);
-    }
-    void interaction(const double* src0, const double* src1, const double* cur, double wcorr, int S)
-    {
-        band_state(src0, src1, cur);
         interact(wcorr, S);
         velocity(cur);
     }
