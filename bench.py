@@ -37,6 +37,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run a plain 256 MiB device copy (scale reference for HBM byte counters)")
     return ap.parse_args()
 
 
@@ -78,6 +80,13 @@ def main():
     from paper_1905_03917_amd import workloads as WL
 
     torch.cuda.set_device(0)
+    if a.copy_probe:
+        # a device-to-device copy of exactly 256 MiB read + 256 MiB written
+        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     case = WL.shock_bubble_2d(n=a.n, seed=0)
     D = case["ndim"]
     print("bench: shock_bubble_2d %dx%d, warmup %d, steps %d" % (a.n, a.n, a.warmup, a.steps), flush=True)

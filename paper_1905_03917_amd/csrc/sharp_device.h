@@ -162,6 +162,37 @@ __device__ __forceinline__ double weno5(double v0, double v1, double v2, double 
     return (w0 * q0 + w1 * q1 + w2 * q2) / (w0 + w1 + w2);
 }
 
+// Reciprocal: hardware estimate refined by two Newton steps (within a few
+// ulp of the correctly rounded quotient).
+__device__ __forceinline__ double rcp_nr(double d)
+{
+    double r = __builtin_amdgcn_rcp(d);
+    r = fma(fma(-d, r, 1.0), r, r);
+    r = fma(fma(-d, r, 1.0), r, r);
+    return r;
+}
+
+// WENO5 of the face flux in the form used by the stage kernels: for
+// v = F +- a U (the LLF split flux without its factor 1/2) returns num/den
+// with value = num / (6 den); eps4 = 4 eps keeps the weights identical to
+// weno5(v/2, eps), since the smoothness indicators are quadratic in v.
+__device__ __forceinline__ double weno5_q(double v0, double v1, double v2, double v3, double v4, double eps4)
+{
+    const double c13_12 = 13.0 / 12.0;
+    double P0 = 2.0 * v0 - 7.0 * v1 + 11.0 * v2;
+    double P1 = -v1 + 5.0 * v2 + 2.0 * v3;
+    double P2 = 2.0 * v2 + 5.0 * v3 - v4;
+    double t0 = v0 - 2.0 * v1 + v2, u0 = v0 - 4.0 * v1 + 3.0 * v2;
+    double t1 = v1 - 2.0 * v2 + v3, u1 = v1 - v3;
+    double t2 = v2 - 2.0 * v3 + v4, u2 = 3.0 * v2 - 4.0 * v3 + v4;
+    double e0 = fma(c13_12 * t0, t0, fma(0.25 * u0, u0, eps4));
+    double e1 = fma(c13_12 * t1, t1, fma(0.25 * u1, u1, eps4));
+    double e2 = fma(c13_12 * t2, t2, fma(0.25 * u2, u2, eps4));
+    double s0 = e0 * e0, s1 = e1 * e1, s2 = e2 * e2;
+    double w0 = s1 * s2, w1 = 6.0 * (s0 * s2), w2 = 3.0 * (s0 * s1);
+    return (w0 * P0 + w1 * P1 + w2 * P2) * rcp_nr(w0 + w1 + w2);
+}
+
 // ---------------------------------------------------------------------------
 // exact Riemann problem of two stiffened gases (wave curves in p + p_inf)
 // ---------------------------------------------------------------------------

@@ -1407,6 +1407,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_stage_lds(Dev g, int list, int k, 
     const double gm = g.gam[k], pi = g.pinf[k];
     const double farea = D == 1 ? 1.0 : g.h;
     const double ih = 1.0 / g.h;
+    const double eps4 = 4.0 * g.eps;
     for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
         int t = L[ti];
         int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1];
@@ -1461,12 +1462,13 @@ __global__ void __launch_bounds__(SHARP_WG) k_stage_lds(Dev g, int list, int k, 
                 p[m] = sP[r];
                 amax = fmax(amax, fabs(un[m]) + sC[r]);
             }
-#pragma unroll
+ #pragma unroll
             for (int q = 0; q < NV; q++) {
+                // split fluxes F +- a U of component q (the factor 1/2 and the
+                // 1/6 of the candidate stencils are applied once at the end)
                 double fp[6], fm[6];
 #pragma unroll
                 for (int m = 0; m < 6; m++) {
-                    // conserved value and physical flux of component q
                     double Uq, Fq;
                     if (q == 0) { Uq = rho[m]; Fq = rho[m] * un[m]; }
                     else if (q == NV - 1) { Uq = E[m]; Fq = (E[m] + p[m]) * un[m]; }
@@ -1477,12 +1479,12 @@ __global__ void __launch_bounds__(SHARP_WG) k_stage_lds(Dev g, int list, int k, 
                         Uq = rho[m] * uq;
                         Fq = Uq * un[m] + (normal ? p[m] : 0.0);
                     }
-                    fp[m] = 0.5 * (Fq + amax * Uq);
-                    fm[m] = 0.5 * (Fq - amax * Uq);
+                    fp[m] = fma(amax, Uq, Fq);
+                    fm[m] = fma(-amax, Uq, Fq);
                 }
-                double Fh = weno5(fp[0], fp[1], fp[2], fp[3], fp[4], g.eps)
-                          + weno5(fm[5], fm[4], fm[3], fm[2], fm[1], g.eps);
-                Fo[q] = A * Fh;
+                double Fh = weno5_q(fp[0], fp[1], fp[2], fp[3], fp[4], eps4)
+                          + weno5_q(fm[5], fm[4], fm[3], fm[2], fm[1], eps4);
+                Fo[q] = (A * (1.0 / 12.0)) * Fh;
             }
             if (g.bc[d] == 0 && wflux != 0.0) {
                 int fi = d == 0 ? i : j;
