@@ -87,6 +87,9 @@ typedef struct {
     double weno_eps;     /* WENO epsilon [1e-6] */
     int force_cycle;     /* run the accelerated cycle even when n truncates to 1 [0] */
     int no_correction;   /* skip the interfacial flux correction (diagnostic) [0] */
+    int serial;          /* run every kernel on the simulation's stream instead of
+                            overlapping the bulk-tile stages with the band work on
+                            two library-owned streams; results are identical [0] */
 } sim_opts;
 
 typedef struct {
@@ -105,6 +108,9 @@ void sim_default_opts(sim_opts* o);
 
 /* Create a simulation.  eos[0] is fluid 0 (phi < 0), eos[1] fluid 1.
  * stream: a hipStream_t to order all work on, or NULL for a private stream.
+ * Unless opts->serial is set, the library also creates two non-blocking
+ * streams for the bulk-tile stages; every call joins them back into `stream`
+ * before it returns, so callers see all work ordered on `stream`.
  * Requires equal spacing in every direction (h), 1 <= ndim <= 3,
  * n[d] >= 1, gamma > 1, p_inf >= 0, rk in {2, 3}.  Returns SIM_EINVAL on bad
  * arguments, SIM_ENOMEM if device memory runs out. */

@@ -33,7 +33,8 @@ class Opts(C.Structure):
     _fields_ = [("cfl", C.c_double), ("rk", C.c_int), ("n_thr", C.c_double), ("alpha_mix", C.c_double),
                 ("ls_band", C.c_double), ("ext_band", C.c_double), ("mix_band", C.c_double),
                 ("ext_iters", C.c_int), ("reinit_iters", C.c_int), ("weno_eps", C.c_double),
-                ("force_cycle", C.c_int), ("no_correction", C.c_int)]
+                ("force_cycle", C.c_int), ("no_correction", C.c_int),
+                ("serial", C.c_int)]
 
 
 class Stats(C.Structure):

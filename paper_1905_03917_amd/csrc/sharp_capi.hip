@@ -50,6 +50,13 @@ static void release(Sim& s)
     s.ev_pool.clear();
     if (s.h_red) (void)hipHostFree(s.h_red);
     s.h_red = nullptr;
+    for (int k = 0; k < 2; k++) {
+        if (s.side[k]) (void)hipStreamDestroy(s.side[k]);
+        if (s.ev_band[k]) (void)hipEventDestroy(s.ev_band[k]);
+        if (s.ev_bulk[k]) (void)hipEventDestroy(s.ev_bulk[k]);
+        s.side[k] = nullptr;
+        s.ev_band[k] = s.ev_bulk[k] = nullptr;
+    }
     if (s.own_stream && s.stream) (void)hipStreamDestroy(s.stream);
     s.stream = nullptr;
 }
@@ -122,6 +129,18 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     } else {
         if (hipStreamCreate(&s.stream) != hipSuccess) { delete h; set_error("hipStreamCreate failed"); return SIM_EDEVICE; }
         s.own_stream = true;
+    }
+    if (!o.serial) {
+        for (int k = 0; k < 2; k++) {
+            if (hipStreamCreateWithFlags(&s.side[k], hipStreamNonBlocking) != hipSuccess ||
+                hipEventCreateWithFlags(&s.ev_band[k], hipEventDisableTiming) != hipSuccess ||
+                hipEventCreateWithFlags(&s.ev_bulk[k], hipEventDisableTiming) != hipSuccess) {
+                release(s);
+                delete h;
+                set_error("stream/event creation failed");
+                return SIM_EDEVICE;
+            }
+        }
     }
     Dev& g = s.g;
     memset(&g, 0, sizeof g);
@@ -215,6 +234,8 @@ void sim_destroy(sim_t* h)
 {
     if (!h) return;
     (void)hipStreamSynchronize(h->s.stream);
+    for (int k = 0; k < 2; k++)
+        if (h->s.side[k]) (void)hipStreamSynchronize(h->s.side[k]);
     release(h->s);
     delete h;
 }

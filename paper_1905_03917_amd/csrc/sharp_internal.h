@@ -16,6 +16,13 @@ struct Sim {
     sim_opts o;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    // bulk-tile stages run on one side stream per fluid, ordered against the
+    // band work on `stream` by events (none when o.serial is set)
+    hipStream_t side[2] = {nullptr, nullptr};
+    hipEvent_t ev_band[2] = {nullptr, nullptr};   // on stream: latest band stage of fluid k
+    hipEvent_t ev_bulk[2] = {nullptr, nullptr};   // on side[k]: latest bulk stage of fluid k
+    bool band_rec[2] = {false, false};
+    bool bulk_pending[2] = {false, false};        // stream has not yet waited for side[k]
     int max_blocks = 2048; // grid-stride bound for tile-list kernels
     bool has_state = false;
     double t = 0.0;

@@ -1814,41 +1814,73 @@ struct Engine {
     }
 
     // ---- stages ----
+    // A bulk tile lies at least one tile away from every band-mask cell, so
+    // its stencil (three cells) reads only bulk and ring-tile cells, which no
+    // band kernel writes except the band stage.  The bulk stage of fluid k
+    // therefore waits only for the previous band stage of k, and the band
+    // stage only for the previous bulk stage of k (it reads that output in
+    // its halo); everything in between (extension, interaction, level set,
+    // geometry, mixing) overlaps with the bulk stage on its side stream.
     void stage(int k, const double* in, const double* self2, const double* base, double* out, double a, double dt,
                double wflux, int cfl = 0)
     {
         int bl = k == 0 ? LIST_BULK0 : LIST_BULK1;
-        if (cfl) k_zero_red<<<1, 64, 0, s.stream>>>(g);
+        const bool ov = s.side[k] != nullptr;
+        hipStream_t bs = ov ? s.side[k] : s.stream;
+        if (ov) {
+            if (s.bulk_pending[k]) (void)hipStreamWaitEvent(s.stream, s.ev_bulk[k], 0);
+            if (s.band_rec[k]) (void)hipStreamWaitEvent(bs, s.ev_band[k], 0);
+        }
+        if (cfl) k_zero_red<<<1, 64, 0, bs>>>(g);
         size_t ev = 0;
         if (s.prof) {
             if (s.ev_used + 2 > s.ev_pool.size()) profile_flush();
             ev = s.ev_used;
             s.ev_used += 2;
-            (void)hipEventRecord(s.ev_pool[ev], s.stream);
+            (void)hipEventRecord(s.ev_pool[ev], bs);
         }
-        launch_stage<false>(bl, k, in, nullptr, base, out, a, dt, wflux, cfl);
+        launch_stage<false>(bs, bl, k, in, nullptr, base, out, a, dt, wflux, cfl);
         if (s.prof) {
-            (void)hipEventRecord(s.ev_pool[ev + 1], s.stream);
+            (void)hipEventRecord(s.ev_pool[ev + 1], bs);
             // algorithmic bytes: read `in` (and `base` after the first stage), write `out`
             s.prof_cells.push_back(s.bulk_cells[k] * (long long)((a == 0.0 ? 2 : 3) * NV * 8));
         }
-        launch_stage<true>(LIST_BAND, k, in, self2, base, out, a, dt, wflux, 0);
+        if (ov) {
+            (void)hipEventRecord(s.ev_bulk[k], bs);
+            s.bulk_pending[k] = true;
+        }
+        launch_stage<true>(s.stream, LIST_BAND, k, in, self2, base, out, a, dt, wflux, 0);
+        if (ov) {
+            (void)hipEventRecord(s.ev_band[k], s.stream);
+            s.band_rec[k] = true;
+        }
         fused_cfl = cfl && D <= 2;
+    }
+    // order the outstanding bulk stages before what follows on the stream
+    void join()
+    {
+        for (int k = 0; k < 2; k++)
+            if (s.bulk_pending[k]) {
+                (void)hipStreamWaitEvent(s.stream, s.ev_bulk[k], 0);
+                s.bulk_pending[k] = false;
+            }
     }
     bool fused_cfl = false;    // the last bulk stage already reduced the fast fluid's CFL speed
     template <bool BAND>
-    void launch_stage(int list, int k, const double* in, const double* self2, const double* base, double* out,
-                      double a, double dt, double wflux, int cfl)
+    void launch_stage(hipStream_t st, int list, int k, const double* in, const double* self2, const double* base,
+                      double* out, double a, double dt, double wflux, int cfl)
     {
         if constexpr (D <= 2)
-            k_stage_lds<D, BAND><<<grid(list), wg(), 0, s.stream>>>(g, list, k, in, self2, base, out, a, dt, wflux,
-                                                                    s.wcur, cfl);
+            k_stage_lds<D, BAND><<<grid(list), wg(), 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux,
+                                                              s.wcur, cfl);
         else
-            k_stage<D, BAND><<<grid(list), wg(), 0, s.stream>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
+            k_stage<D, BAND><<<grid(list), wg(), 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
     }
     void profile_flush()
     {
         (void)hipStreamSynchronize(s.stream);
+        for (int k = 0; k < 2; k++)
+            if (s.side[k]) (void)hipStreamSynchronize(s.side[k]);
         for (size_t e = 0; e + 1 < s.ev_used; e += 2) {
             float ms = 0.f;
             (void)hipEventElapsedTime(&ms, s.ev_pool[e], s.ev_pool[e + 1]);
@@ -1964,6 +1996,7 @@ struct Engine {
             in[1] = out[1];
             phin = cur;
         }
+        join();
         s.t += dt;
     }
 
@@ -2033,6 +2066,7 @@ struct Engine {
                 mask(LIST_BAND, 1);
                 interp_slow(S, tau / t1, g.phiP);
                 interaction(S == 0 ? g.T2 : g.X[F], S == 0 ? g.X[F] : g.T2, g.phiP, 0.0, S);
+                join();
                 if (fused_cfl) {
                     // bulk tiles were reduced by the previous sub-step's last stage
                     k_cfl<D, true><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, F, g.X[F], s.wcur);
@@ -2102,6 +2136,7 @@ struct Engine {
         // interfacial flux correction of the slow fluid, then mixing
         k_corr_apply<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, S, corr ? 1 : 0);
         mix(S, g.X[S], g.phiP);
+        join();
         s.t += t1;
         st->cycles++;
         st->steps[S]++;
@@ -2135,6 +2170,7 @@ struct Engine {
             if (t_end - s.t <= 1e-14 * t_end) s.t = t_end;
             done++;
         }
+        join();
         if (rc == SIM_OK) {
             // late non-physical flags (stages after the last readback)
             SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s.stream));

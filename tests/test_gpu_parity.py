@@ -136,6 +136,30 @@ def test_gpu_rk2_cycle_reduces_bitwise():
         np.testing.assert_array_equal(u, v)
 
 
+@pytest.mark.parametrize("name,n,mode,cycles", [
+    ("shock_bubble_2d", 256, 1, 3),
+    ("shock_bubble_2d", 250, 0, 3),
+    ("shock_bubble_2d", 1024, 1, 1),
+    ("shock_droplet_3d", 48, 1, 2),
+    ("tube_1d", 2000, 1, 3),
+])
+def test_overlapped_bulk_stages_equal_serial(name, n, mode, cycles):
+    """Bulk-tile stages on their own streams (the default) give results
+    bit-identical to every kernel on one stream: no kernel reads what a
+    concurrently running one writes."""
+    fn = getattr(WL, name)
+    c = fn(n=n, seed=0)
+    print("overlap case=%s n=%d mode=%d cycles=%d" % (name, n, mode, cycles), flush=True)
+    a = _gpu(c, serial=1)
+    sa = a.advance(1.0, mode=mode, max_cycles=cycles)
+    b = _gpu(c)
+    sb = b.advance(1.0, mode=mode, max_cycles=cycles)
+    assert sa["steps"] == sb["steps"] and sa["t"] == sb["t"]
+    np.testing.assert_array_equal(sa["bflux"], sb["bflux"])
+    for u, v in zip(a.state(device=False), b.state(device=False)):
+        np.testing.assert_array_equal(u, v)
+
+
 def test_full_size_shock_bubble_properties():
     """1024^2 shock-bubble, one accelerated cycle at the benchmark's launch
     configuration: conservation, and the far field untouched."""
