@@ -200,7 +200,7 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
         for (int d = 0; d < 3; d++) A(g.v[b][d], d < D ? (size_t)g.nc : 1);
     A(g.M, (size_t)g.nc); A(g.nearif, (size_t)g.nc);
     A(g.tcore, (size_t)g.ntiles); A(g.tflag, (size_t)g.ntiles); A(g.tsign, (size_t)g.ntiles);
-    A(g.lists, (size_t)5 * g.ntiles);
+    A(g.lists, (size_t)NLISTS * g.ntiles);
     A(g.counts, 16);
     A(g.red, 8);
 #undef A

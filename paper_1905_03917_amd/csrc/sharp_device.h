@@ -57,13 +57,16 @@ struct Dev {
     int* tcore;       // tile holds band cells
     int* tflag;       // bit0 band tile, bit1 candidate tile, bit2 ring tile
     int* tsign;       // fluid of a tile outside the band
-    int* lists;       // [5][ntiles]: band, candidate, bulk0, bulk1, all
-    int* counts;      // [16]: tiles per list (0..4), cells per list (8..11)
+    int* lists;       // [6][ntiles]: band, candidate, bulk0, bulk1, all, inner
+    int* counts;      // [16]: tiles per list (0..5), cells per list (8 + list, lists 0..3 and 5)
     // scalars
     unsigned long long* red;   // [0..1] max speed bits, [2..3] active counts, [4] error flags
 };
 
-enum { LIST_BAND = 0, LIST_CAND = 1, LIST_BULK0 = 2, LIST_BULK1 = 3, LIST_ALL = 4 };
+// band: tiles within one tile of a band-mask tile; inner: band tiles all of
+// whose neighbours are band tiles (every band-mask cell of a cycle lies in
+// one, or the cycle fails with a band overflow)
+enum { LIST_BAND = 0, LIST_CAND = 1, LIST_BULK0 = 2, LIST_BULK1 = 3, LIST_ALL = 4, LIST_INNER = 5, NLISTS = 6 };
 enum { ERR_NONPHYS = 1, ERR_BAND_OVERFLOW = 2 };
 
 // ---------------------------------------------------------------------------
@@ -225,37 +228,52 @@ __device__ __forceinline__ double star_rho(const Side& s, double ps)
     return s.rho * pow(pb / pk, 1.0 / s.g);
 }
 
-// out: p*, u*, rho*_L, rho*_R
-__device__ inline void riemann(const Side& L, const Side& R, double* out)
+// Exact two-material Riemann problem: the root p* of
+//   f(p) = f_L(p) + f_R(p) + (u_R - u_L),
+// which is increasing in p, by safeguarded Newton iteration; p* is the floor
+// -min(p_inf) when f(floor) >= 0.  out: p*, u*, rho*_L, rho*_R.
+// p0 is a start value (the cell's previous solution); when it does not lie
+// above the floor, the geometric mean of the side pressures (relative to the
+// floor) starts the iteration.  The floor value f(floor) is evaluated only
+// when an iterate would leave the bracket through the floor: if the root lies
+// above the floor the iterates never depend on it, and if it does not, every
+// Newton step moves down until one reaches the floor.
+__device__ inline void riemann(const Side& L, const Side& R, double p0, double* out)
 {
     double du = R.u - L.u, dfl, dfr;
     double pfloor = -(L.pi < R.pi ? L.pi : R.pi);
     double p;
-    double f0 = wave_f(L, pfloor, dfl) + wave_f(R, pfloor, dfr) + du;
-    if (f0 >= 0.0) {
-        p = pfloor;
+    if (p0 > pfloor && p0 < INFINITY) {
+        p = p0;
+    } else if (L.p > pfloor && R.p > pfloor) {
+        p = pfloor + sqrt((L.p - pfloor) * (R.p - pfloor));
     } else {
-        if (L.p > pfloor && R.p > pfloor) {
-            p = pfloor + sqrt((L.p - pfloor) * (R.p - pfloor));
-        } else {
-            double cL = csound(L.g, L.pi, L.rho, L.p), cR = csound(R.g, R.pi, R.rho, R.p);
-            p = 0.5 * (L.p + R.p) - 0.125 * du * (L.rho + R.rho) * (cL + cR);
-            double pmax = L.p > R.p ? L.p : R.p;
-            if (!(p > pfloor)) p = pfloor + 0.5 * (pmax - pfloor);
-        }
-        double lo = pfloor, hi = INFINITY;
-        double scale = fabs(L.pi) + fabs(R.pi) + 1e-300;
-        for (int it = 1; it <= 200; it++) {
-            double f = wave_f(L, p, dfl) + wave_f(R, p, dfr) + du;
-            if (f > 0.0) { if (p < hi) hi = p; }
-            else { if (p > lo) lo = p; }
-            double pn = p - f / (dfl + dfr);
-            if (!(pn > lo && pn < hi)) pn = isfinite(hi) ? 0.5 * (lo + hi) : lo + 2.0 * (p - lo);
-            double dp = pn - p;
-            p = pn;
-            if (fabs(dp) <= 1e-13 * (fabs(p) + scale)) break;
-        }
+        double cL = csound(L.g, L.pi, L.rho, L.p), cR = csound(R.g, R.pi, R.rho, R.p);
+        p = 0.5 * (L.p + R.p) - 0.125 * du * (L.rho + R.rho) * (cL + cR);
+        double pmax = L.p > R.p ? L.p : R.p;
+        if (!(p > pfloor)) p = pfloor + 0.5 * (pmax - pfloor);
     }
+    double lo = pfloor, hi = INFINITY;
+    double scale = fabs(L.pi) + fabs(R.pi) + 1e-300;
+    bool floor_known = false, at_floor = false;
+    for (int it = 1; it <= 200; it++) {
+        double f = wave_f(L, p, dfl) + wave_f(R, p, dfr) + du;
+        if (f > 0.0) { if (p < hi) hi = p; }
+        else { if (p > lo) lo = p; }
+        double pn = p - f / (dfl + dfr);
+        if (!(pn > lo && pn < hi)) {
+            if (!floor_known && !(pn > lo) && lo == pfloor) {
+                floor_known = true;
+                double d0l, d0r;
+                if (wave_f(L, pfloor, d0l) + wave_f(R, pfloor, d0r) + du >= 0.0) { at_floor = true; break; }
+            }
+            pn = isfinite(hi) ? 0.5 * (lo + hi) : lo + 2.0 * (p - lo);
+        }
+        double dp = pn - p;
+        p = pn;
+        if (fabs(dp) <= 1e-13 * (fabs(p) + scale)) break;
+    }
+    if (at_floor) p = pfloor;
     double fl = wave_f(L, p, dfl), fr = wave_f(R, p, dfr);
     out[0] = p;
     out[1] = 0.5 * (L.u + R.u) + 0.5 * (fr - fl);

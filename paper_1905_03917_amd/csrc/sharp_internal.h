@@ -9,6 +9,12 @@
 #include "../../include/sharp.h"
 #include "sharp_device.h"
 
+// grid bound of the bulk-tile stage kernels: below the tile count it leaves
+// room on the chip for the band kernels that run beside them
+#ifndef SHARP_BULK_BLOCKS
+#define SHARP_BULK_BLOCKS 2048
+#endif
+
 namespace sharp {
 
 struct Sim {
@@ -24,6 +30,7 @@ struct Sim {
     bool band_rec[2] = {false, false};
     bool bulk_pending[2] = {false, false};        // stream has not yet waited for side[k]
     int max_blocks = 2048; // grid-stride bound for tile-list kernels
+    int bulk_blocks = SHARP_BULK_BLOCKS;  // the same bound for the bulk-tile stages
     bool has_state = false;
     double t = 0.0;
     int wcur = 0;          // Jacobi buffer holding the latest primitives
@@ -38,7 +45,7 @@ struct Sim {
     double prof_ms = 0.0;
     long long prof_launches = 0, prof_bytes = 0;
     long long bulk_cells[2] = {0, 0};   // cells in the bulk lists (host copy)
-    int lcount[5] = {1, 1, 1, 1, 1};    // tiles per list (host copy, sizes the grids)
+    int lcount[NLISTS] = {1, 1, 1, 1, 1, 1};   // tiles per list (host copy, sizes the grids)
 };
 
 void set_error(const char* fmt, ...);

@@ -7,10 +7,12 @@
 // secondcorrection).
 //
 // Work is organised in tiles of 256 cells (1-D 256, 2-D 16x16, 3-D 8x8x4).
-// Every kernel walks a device-resident tile list with a grid-stride loop, so
-// the host never reads list sizes back: bulk tiles of one fluid (no interface
-// within reach of the stencil) take the lean path, band tiles (the level-set
-// band, dilated by one tile) take the cut-cell path.  All per-cell state is
+// Every kernel walks a device-resident tile list with a grid-stride loop over
+// the device-side count (the host reads the counts back at its CFL readbacks
+// only to size the grids): bulk tiles of one fluid (no interface within reach
+// of the stencil) take the lean path, band tiles (the level-set band, dilated
+// by one tile) take the cut-cell path, and kernels that touch band-mask cells
+// only walk the inner band tiles.  All per-cell state is
 // structure-of-arrays FP64 in HBM, x fastest, so a wavefront reads 64
 // consecutive doubles of one component.
 #include <cmath>
@@ -144,42 +146,49 @@ __device__ __forceinline__ int tile_cells(const Dev& g, int t)
     return n;
 }
 
-// single-block compaction of the four tile lists (and their cell counts)
+// single-block compaction of the tile lists (band, candidate, bulk of each
+// fluid, inner) and their cell counts
 __global__ void __launch_bounds__(1024) k_compact(Dev g)
 {
-    __shared__ int cnt[4][1024];
-    __shared__ int ccl[4][1024];
+    constexpr int NL = 5;   // list slot 4 holds LIST_INNER
+    __shared__ int cnt[NL][1024];
+    __shared__ int ccl[NL][1024];
     int nt = g.ntiles, tid = threadIdx.x, nth = blockDim.x;
     int chunk = (nt + nth - 1) / nth;
     int lo = tid * chunk, hi = min(nt, lo + chunk);
-    int c[4] = {0, 0, 0, 0}, cc[4] = {0, 0, 0, 0};
+    int c[NL] = {0, 0, 0, 0, 0}, cc[NL] = {0, 0, 0, 0, 0};
     for (int t = lo; t < hi; t++) {
         int f = g.tflag[t], nc = tile_cells(g, t);
         if (f & 1) { c[0]++; cc[0] += nc; }
         if (f & 2) { c[1]++; cc[1] += nc; }
         if (!(f & 1)) { c[2 + g.tsign[t]]++; cc[2 + g.tsign[t]] += nc; }
+        if ((f & 1) && !(f & 4)) { c[4]++; cc[4] += nc; }
     }
-    for (int l = 0; l < 4; l++) { cnt[l][tid] = c[l]; ccl[l][tid] = cc[l]; }
+    for (int l = 0; l < NL; l++) { cnt[l][tid] = c[l]; ccl[l][tid] = cc[l]; }
     __syncthreads();
     for (int off = nth / 2; off > 0; off >>= 1) {
         if (tid < off)
-            for (int l = 0; l < 4; l++) ccl[l][tid] += ccl[l][tid + off];
+            for (int l = 0; l < NL; l++) ccl[l][tid] += ccl[l][tid + off];
         __syncthreads();
     }
-    if (tid == 0)
+    if (tid == 0) {
         for (int l = 0; l < 4; l++) g.counts[8 + l] = ccl[l][0];
+        g.counts[8 + LIST_INNER] = ccl[4][0];
+    }
     // exclusive scan (Hillis-Steele on a copy)
     for (int off = 1; off < nth; off <<= 1) {
-        int v[4];
-        for (int l = 0; l < 4; l++) v[l] = tid >= off ? cnt[l][tid - off] : 0;
+        int v[NL];
+        for (int l = 0; l < NL; l++) v[l] = tid >= off ? cnt[l][tid - off] : 0;
         __syncthreads();
-        for (int l = 0; l < 4; l++) cnt[l][tid] += v[l];
+        for (int l = 0; l < NL; l++) cnt[l][tid] += v[l];
         __syncthreads();
     }
-    int base[4];
-    for (int l = 0; l < 4; l++) base[l] = cnt[l][tid] - c[l];
-    if (tid == nth - 1)
+    int base[NL];
+    for (int l = 0; l < NL; l++) base[l] = cnt[l][tid] - c[l];
+    if (tid == nth - 1) {
         for (int l = 0; l < 4; l++) g.counts[l] = cnt[l][tid];
+        g.counts[LIST_INNER] = cnt[4][tid];
+    }
     for (int t = lo; t < hi; t++) {
         int f = g.tflag[t];
         if (f & 1) g.lists[(size_t)LIST_BAND * nt + base[0]++] = t;
@@ -188,6 +197,7 @@ __global__ void __launch_bounds__(1024) k_compact(Dev g)
             int l = 2 + g.tsign[t];
             g.lists[(size_t)l * nt + base[l]++] = t;
         }
+        if ((f & 1) && !(f & 4)) g.lists[(size_t)LIST_INNER * nt + base[4]++] = t;
     }
 }
 
@@ -817,17 +827,19 @@ template <> struct ExtRegion<1> { static constexpr int X = 256 + 2 * EXT_H, Y = 
 template <> struct ExtRegion<2> { static constexpr int X = 16 + 2 * EXT_H, Y = 16 + 2 * EXT_H; };
 
 // block sizes of the temporally blocked kernels: one thread per region cell
-// for the extension of primitives, two for the interaction + velocity kernel
+// (2-D), one per tile cell (1-D)
 template <int D> struct ExtWG;
 template <> struct ExtWG<1> { static constexpr int W = 256, V = 256; };
-template <> struct ExtWG<2> { static constexpr int W = 1024, V = 512; };
+template <> struct ExtWG<2> { static constexpr int W = 1024, V = 1024; };
 
 // fused primitive recovery (real band cells) + extension of one fluid's
 // primitives per block (block b handles tile b/2, fluid b%2); reads
 // Wb[k][in], writes the band cells of Wb[k][out]
+// (at most 64 VGPRs, so that two 1024-thread blocks share a CU)
 template <int D>
-__global__ void __launch_bounds__(ExtWG<D>::W) k_extw_tb(Dev g, int list, const double* src0, const double* src1,
-                                                        int in, int out, int iters, const double* cur)
+__global__ void __launch_bounds__(ExtWG<D>::W, 2 * ExtWG<D>::W / 256) k_extw_tb(Dev g, int list, const double* src0,
+                                                                              const double* src1, int in, int out,
+                                                                              int iters, const double* cur)
 {
     static_assert(D <= 2, "temporally blocked extension is for 1-D and 2-D");
     constexpr int NV = D + 2;
@@ -934,11 +946,12 @@ __global__ void __launch_bounds__(ExtWG<D>::W) k_extw_tb(Dev g, int list, const 
     }
 }
 
-// Riemann problem of cut cell c with fluid states from Wb[.][wb]:
-// st = {p*, u*, rho*_0, rho*_1}
+// Riemann problem of cut cell c with fluid states from Wb[.][wb], started
+// from the cell's previous p*: st = {p*, u*, rho*_0, rho*_1}
 template <int D>
 __device__ __forceinline__ void interface_solve(const Dev& g, int c, const double* gv, double gm, int wb, double* st)
 {
+    const double p0 = g.ps[c];
     const double* W0 = g.Wb[0][wb];
     const double* W1 = g.Wb[1][wb];
     double un0 = 0.0, un1 = 0.0;
@@ -948,7 +961,7 @@ __device__ __forceinline__ void interface_solve(const Dev& g, int c, const doubl
     }
     Side Ls = {W0[c], un0, W0[(size_t)(D + 1) * g.nc + c], g.gam[0], g.pinf[0]};
     Side Rs = {W1[c], un1, W1[(size_t)(D + 1) * g.nc + c], g.gam[1], g.pinf[1]};
-    riemann(Ls, Rs, st);
+    riemann(Ls, Rs, p0, st);
 }
 
 // store the interface solution of the tile's own cut cell c (and book the
@@ -977,13 +990,37 @@ __device__ __forceinline__ void interface_store(const Dev& g, int c, const doubl
     }
 }
 
-// interface interaction + level-set velocity extension, temporally blocked:
-// every cut cell of the region is solved (redundantly across blocks), the
-// tile's own cut cells store p*, u*, star speeds and the correction, and the
-// velocity u* n is extended over the region
+// interface interaction of the tile's own band-mask cells: every cut cell
+// solves its Riemann problem once and stores p*, u*, the star-state speeds,
+// the correction share, and u* n as the source of the velocity extension;
+// the other band-mask cells get zeros
 template <int D>
-__global__ void __launch_bounds__(ExtWG<D>::V) k_intv_tb(Dev g, int list, int wb, int in, int out, int iters,
-                                                        const double* cur, double wcorr, int S)
+__global__ void __launch_bounds__(SHARP_WG) k_riemann(Dev g, int list, int wb, int vb, double wcorr, int S)
+{
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        if (!g.M[c]) continue;   // a cut cell is a band-mask cell
+        double gv[3];
+        double gm = iface<D>(g, i, j, kk, gv);
+        if (!(gm > 0.0)) {
+            interface_store<D>(g, c, gv, gm, nullptr, 0.0, S);
+            continue;
+        }
+        double st[4];
+        interface_solve<D>(g, c, gv, gm, wb, st);
+        interface_store<D>(g, c, gv, gm, st, wcorr, S);
+        for (int e = 0; e < D; e++) g.v[vb][e][c] = st[1] * gv[e] / gm;
+    }
+}
+
+// level-set velocity extension, temporally blocked: u* n of the cut cells
+// (from k_riemann, in v[in]) is extended over the tile's region in LDS
+template <int D>
+__global__ void __launch_bounds__(ExtWG<D>::V, 2 * ExtWG<D>::V / 256) k_vext_tb(Dev g, int list, int in, int out,
+                                                                              int iters, const double* cur)
 {
     static_assert(D <= 2, "temporally blocked extension is for 1-D and 2-D");
     constexpr int WGS = ExtWG<D>::V;
@@ -1014,21 +1051,12 @@ __global__ void __launch_bounds__(ExtWG<D>::V) k_intv_tb(Dev g, int list, int wb
             int rx = r % RX, ry = r / RX;
             int gi = ox - EXT_H + rx, gj = oy - HY + ry;
             int c = cidx(g, gi, gj, 0);
+            for (int e = 0; e < D; e++) sA[e * RN + r] = g.v[in][e][c];
+            if (!g.M[c]) continue;
             int ci, cj, ck;
             coords(g, c, ci, cj, ck);
             double gv[3];
-            double gm = iface<D>(g, ci, cj, ck, gv);
-            bool own = rx >= EXT_H && rx < EXT_H + TX && ry >= HY && ry < HY + TY && gi < g.n[0] && gj < g.n[1];
-            if (gm > 0.0) {
-                double st[4];
-                interface_solve<D>(g, c, gv, gm, wb, st);
-                for (int e = 0; e < D; e++) sA[e * RN + r] = st[1] * gv[e] / gm;
-                if (own) interface_store<D>(g, c, gv, gm, st, wcorr, S);
-                continue;
-            }
-            if (own) interface_store<D>(g, c, gv, gm, nullptr, 0.0, S);
-            for (int e = 0; e < D; e++) sA[e * RN + r] = g.v[in][e][c];
-            if (!g.M[c]) continue;
+            if (iface<D>(g, ci, cj, ck, gv) > 0.0) continue;   // cut cells are the sources
             int pc = (rx + 1) + PX * (D == 2 ? ry + 1 : 0);
             double gr[2], g2 = 0.0;
             gr[0] = (sPhi[pc + 1] - sPhi[pc - 1]) / (2.0 * g.h);
@@ -1121,7 +1149,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_interact(Dev g, int list, int wb, 
         Side Ls = {W0[c], un0, W0[(size_t)(D + 1) * g.nc + c], g.gam[0], g.pinf[0]};
         Side Rs = {W1[c], un1, W1[(size_t)(D + 1) * g.nc + c], g.gam[1], g.pinf[1]};
         double st[4];
-        riemann(Ls, Rs, st);
+        riemann(Ls, Rs, g.ps[c], st);
         g.ps[c] = st[0];
         g.us[c] = st[1];
         for (int k = 0; k < 2; k++) {
@@ -1208,7 +1236,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_cfl(Dev g, int list, int k, const 
         double cs = csound(g.gam[k], g.pinf[k], W[0], W[D + 1]), s = 0.0;
         for (int d = 0; d < D; d++) s += (fabs(W[1 + d]) + cs) / g.h;
         mx = fmax(mx, s);
-        if (BAND) mx = fmax(mx, g.ss[k][c]);
+        if (BAND && g.M[c]) mx = fmax(mx, g.ss[k][c]);   // star speeds live on the band-mask cells
     }
     // wavefront then block reduction (max is order independent)
     for (int off = 32; off > 0; off >>= 1) {
@@ -1731,11 +1759,12 @@ struct Engine {
 
     // grid of a tile-list kernel: one block per listed tile (capped); the
     // kernels loop over the device-side count, so any grid size is correct
-    dim3 grid(int list, int per_tile = 1) const
+    dim3 grid(int list, int per_tile = 1, int cap = 0) const
     {
         long long c = (long long)s.lcount[list] * per_tile;
+        if (cap <= 0) cap = s.max_blocks;
         if (c < 1) c = 1;
-        if (c > s.max_blocks) c = s.max_blocks;
+        if (c > cap) c = cap;
         return dim3((unsigned)c);
     }
     dim3 wg() const { return dim3(SHARP_WG); }
@@ -1752,19 +1781,19 @@ struct Engine {
     void geom(const double* cur, int list = LIST_BAND) { k_geom_lds<D><<<grid(list), wg(), 0, s.stream>>>(g, list, cur); }
 
     // ---- band physics ----
-    void prims(int k, const double* src) { k_prims<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, k, src, s.wcur); }
+    void prims(int k, const double* src) { k_prims<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, k, src, s.wcur); }
     void extw(const double* cur)
     {
         for (int it = 0; it < s.o.ext_iters; it++) {
-            k_extw<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, s.wcur, 1 - s.wcur, cur);
+            k_extw<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, s.wcur, 1 - s.wcur, cur);
             s.wcur ^= 1;
         }
     }
-    void interact(double wcorr, int S) { k_interact<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, s.wcur, s.vcur, wcorr, S); }
+    void interact(double wcorr, int S) { k_interact<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, s.wcur, s.vcur, wcorr, S); }
     void extv(const double* cur)
     {
         for (int it = 0; it < s.o.ext_iters; it++) {
-            k_extv<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, s.vcur, 1 - s.vcur, cur);
+            k_extv<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, s.vcur, 1 - s.vcur, cur);
             s.vcur ^= 1;
         }
     }
@@ -1774,7 +1803,7 @@ struct Engine {
     {
         if constexpr (D <= 2) {
             if (s.o.ext_iters <= EXT_H) {
-                k_extw_tb<D><<<grid(LIST_BAND, 2), ExtWG<D>::W, 0, s.stream>>>(g, LIST_BAND, src0, src1, s.wcur, 1 - s.wcur,
+                k_extw_tb<D><<<grid(LIST_INNER, 2), ExtWG<D>::W, 0, s.stream>>>(g, LIST_INNER, src0, src1, s.wcur, 1 - s.wcur,
                                                             s.o.ext_iters, cur);
                 s.wcur ^= 1;
                 return;
@@ -1790,8 +1819,9 @@ struct Engine {
         band_state(src0, src1, cur);
         if constexpr (D <= 2) {
             if (s.o.ext_iters <= EXT_H) {
-                k_intv_tb<D><<<grid(LIST_BAND), ExtWG<D>::V, 0, s.stream>>>(g, LIST_BAND, s.wcur, s.vcur, 1 - s.vcur,
-                                                                            s.o.ext_iters, cur, wcorr, S);
+                k_riemann<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, s.wcur, s.vcur, wcorr, S);
+                k_vext_tb<D><<<grid(LIST_INNER), ExtWG<D>::V, 0, s.stream>>>(g, LIST_INNER, s.vcur, 1 - s.vcur,
+                                                                            s.o.ext_iters, cur);
                 s.vcur ^= 1;
                 return;
             }
@@ -1799,18 +1829,18 @@ struct Engine {
         interact(wcorr, S);
         velocity(cur);
     }
-    void corr_add(double w, int S) { k_corr_add<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, w, S); }
+    void corr_add(double w, int S) { k_corr_add<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, w, S); }
     void mix(int k, double* cons, const double* cur)
     {
         if constexpr (D <= 2)
-            k_mixdelta_lds<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, cur);
+            k_mixdelta_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, k, cons, cur);
         else
-            k_mixdelta<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, cur);
-        k_mixapply<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, cons);
+            k_mixdelta<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, k, cons, cur);
+        k_mixapply<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, cons);
     }
     void axpby(double a1, const double* s1, double a2, const double* s2, double* dst, int ncomp)
     {
-        k_axpby<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, a1, s1, a2, s2, dst, ncomp);
+        k_axpby<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, a1, s1, a2, s2, dst, ncomp);
     }
 
     // ---- stages ----
@@ -1870,11 +1900,11 @@ struct Engine {
     void launch_stage(hipStream_t st, int list, int k, const double* in, const double* self2, const double* base,
                       double* out, double a, double dt, double wflux, int cfl)
     {
+        dim3 gr = grid(list, 1, BAND ? 0 : s.bulk_blocks);
         if constexpr (D <= 2)
-            k_stage_lds<D, BAND><<<grid(list), wg(), 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux,
-                                                              s.wcur, cfl);
+            k_stage_lds<D, BAND><<<gr, wg(), 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur, cfl);
         else
-            k_stage<D, BAND><<<grid(list), wg(), 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
+            k_stage<D, BAND><<<gr, wg(), 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
     }
     void profile_flush()
     {
@@ -1899,7 +1929,7 @@ struct Engine {
     {
         int K = s.o.reinit_iters;
         if (K <= 0) {
-            k_copy_masked<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, phi0, g.phiP);
+            k_copy_masked<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, phi0, g.phiP);
             return;
         }
         k_nearif<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, phi0);
@@ -1907,13 +1937,13 @@ struct Engine {
         const double* in = phi0;
         for (int m = 1; m <= K; m++) {
             double* out = (m == K) ? g.phiP : ((m % 2 == 1) ? g.phiB[2] : other);
-            k_reinit<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, phi0, in, out);
+            k_reinit<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, phi0, in, out);
             in = out;
         }
     }
     void ls(double a, double dt, const double* in, double* out)
     {
-        k_ls<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, a, dt, in, out, s.vcur);
+        k_ls<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, a, dt, in, out, s.vcur);
     }
 
     // ---- CFL ----
@@ -1945,6 +1975,7 @@ struct Engine {
     {
         const int* cc = reinterpret_cast<const int*>(s.h_red + 8);
         for (int l = 0; l < 4; l++) s.lcount[l] = cc[l];
+        s.lcount[LIST_INNER] = cc[LIST_INNER];
         s.lcount[LIST_ALL] = g.ntiles;
         s.bulk_cells[0] = cc[8 + 2];
         s.bulk_cells[1] = cc[8 + 3];
@@ -2005,7 +2036,7 @@ struct Engine {
     void interp_slow(int S, double theta, const double* cur)
     {
         if constexpr (D <= 2) {
-            k_mixinterp_lds<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, S, 1.0 - theta, g.X[S], theta,
+            k_mixinterp_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, S, 1.0 - theta, g.X[S], theta,
                                                                         g.Y[S], g.T2, theta != 0.0, cur);
             return;
         }
@@ -2016,7 +2047,7 @@ struct Engine {
     void mixed_copy(int S, const double* src, const double* cur)
     {
         if constexpr (D <= 2) {
-            k_mixinterp_lds<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, S, 1.0, src, 0.0, nullptr,
+            k_mixinterp_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, S, 1.0, src, 0.0, nullptr,
                                                                         g.T2, 1, cur);
             return;
         }
@@ -2134,7 +2165,7 @@ struct Engine {
             geom(g.phiP);
         }
         // interfacial flux correction of the slow fluid, then mixing
-        k_corr_apply<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, S, corr ? 1 : 0);
+        k_corr_apply<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, S, corr ? 1 : 0);
         mix(S, g.X[S], g.phiP);
         join();
         s.t += t1;
