@@ -16,6 +16,7 @@ stream), the time of the original single-dt method over the same simulated
 interval, and the CPU oracle's rate on a bounded sample.
 """
 import argparse
+import hashlib
 import json
 import os
 import sys
@@ -25,7 +26,11 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
-FP64_VECTOR_TFLOPS = 78.6      # MI355X FP64 vector peak
+# FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
+FP64_VECTOR_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
+COUNTERS = os.path.join(ROOT, "profiles", "stage_bulk_shock_bubble_2d_1024_counters.json")
+COPY_PROBE_BYTES = 1 << 30
+KERNEL_SOURCES = ["paper_1905_03917_amd/csrc/sharp_kernels.hip", "paper_1905_03917_amd/csrc/sharp_device.h"]
 
 
 def parse():
@@ -38,15 +43,103 @@ def parse():
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--copy-probe", action="store_true",
-                    help="also run a plain 256 MiB device copy (scale reference for HBM byte counters)")
+                    help="also run a plain 1 GiB device copy (scale reference for HBM byte counters)")
+    ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="reduce two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
+                         "'bench.py --copy-probe' into the committed traffic record, then exit")
     return ap.parse_args()
 
 
-def stage_bytes_per_cell(D):
-    # stage 1 reads its input and writes its output (2 NV doubles), stages 2
-    # and 3 also read the step's base state (3 NV doubles)
+def stage_bytes(D, first):
+    """Algorithmic HBM bytes of one bulk cell through one stage: the stage
+    input and output (NV doubles each), plus the step's base state after the
+    first stage."""
     NV = D + 2
-    return {1: 2 * NV * 8, 2: 3 * NV * 8}
+    return (2 if first else 3) * NV * 8
+
+
+def stage_flops(D, first):
+    """Algorithmic FP64 operations of one bulk cell through one stage (an FMA
+    counts two, a division or square root one).
+
+    Per face and component: the split fluxes F +- aU at the six stencil cells
+    (24), two WENO5-JS reconstructions (66 each: candidate stencils 15,
+    smoothness indicators 33, nonlinear weights 9, weighted sum 9) and the
+    combination (2).  Per face: the physical fluxes (D + 4), momenta (D) and
+    wave speed (1) at the six stencil cells.  Per cell: D faces, the
+    primitives and sound speed (3D + 9), and per component the flux
+    difference (2D) and the Shu-Osher update (2, or 5 after the first stage).
+    2-D: 1411 (first stage) / 1423."""
+    NV = D + 2
+    face = NV * (24 + 2 * 66 + 2) + 6 * (D + 4) + 6 * D + 6
+    return D * face + (3 * D + 9) + NV * (2 * D + (2 if first else 5))
+
+
+def source_digest():
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()
+
+
+def reduce_counters(fetch_dir, write_dir):
+    """HBM traffic of the bulk stage kernel from FETCH_SIZE and WRITE_SIZE
+    (KiB per dispatch), each scaled by what the same counter reads for the
+    1 GiB device copy of --copy-probe (the largest copy dispatch)."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        rows = []
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                rows += [r for r in csv.DictReader(fh) if r["Counter_Name"] == counter]
+        per = {}
+        for r in rows:
+            key = (r["Dispatch_Id"], r["Kernel_Name"])
+            per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+        return per
+
+    copy_kib = COPY_PROBE_BYTES / 1024.0
+    out = {}
+    for name, d, counter in (("fetch", fetch_dir, "FETCH_SIZE"), ("write", write_dir, "WRITE_SIZE")):
+        per = read(d, counter)
+        copies = [v for (i, k), v in per.items() if "copybuffer" in k.lower()]
+        if not copies or max(copies) < 0.25 * copy_kib:
+            raise SystemExit("no 1 GiB copy dispatch found in %s" % d)
+        scale = copy_kib / max(copies)
+        stage = [v for (i, k), v in per.items() if "k_stage_lds<2, false>" in k]
+        if not stage:
+            raise SystemExit("no bulk stage dispatch found in %s" % d)
+        out[name] = dict(counter=counter, copy_kib_read=max(copies), scale=scale, dispatches=len(stage),
+                         kib_per_dispatch=sum(stage) / len(stage))
+    traffic = (out["fetch"]["kib_per_dispatch"] * out["fetch"]["scale"]
+               + out["write"]["kib_per_dispatch"] * out["write"]["scale"]) * 1024.0
+    rec = dict(kernel="k_stage_lds<2, false>", workload="shock_bubble_2d 1024x1024 multi_dt",
+               source_sha256=source_digest(), sources=KERNEL_SOURCES, counters=out,
+               traffic_bytes_per_launch=traffic,
+               commands=["timeout -s KILL 60 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <FETCH_DIR> -o run "
+                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --copy-probe",
+                         "timeout -s KILL 60 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <WRITE_DIR> -o run "
+                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --copy-probe",
+                         "python bench.py --reduce-counters <FETCH_DIR> <WRITE_DIR>"])
+    with open(COUNTERS, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
+def measured_traffic():
+    """bytes per launch from the committed counter record, or None when the
+    kernel sources changed since the counters were taken"""
+    try:
+        with open(COUNTERS) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    if rec.get("source_sha256") != source_digest():
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def cpu_baseline(case_fn, seconds):
@@ -72,6 +165,9 @@ def cpu_baseline(case_fn, seconds):
 
 def main():
     a = parse()
+    if a.reduce_counters:
+        reduce_counters(*a.reduce_counters)
+        return
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % a.gpus, file=sys.stderr)
         sys.exit(2)
@@ -81,12 +177,15 @@ def main():
 
     torch.cuda.set_device(0)
     if a.copy_probe:
-        # a device-to-device copy of exactly 256 MiB read + 256 MiB written
-        src = torch.ones(32 * 1024 * 1024, dtype=torch.float64, device="cuda")
+        # a device-to-device copy of exactly 1 GiB read + 1 GiB written; a
+        # 1 GiB fill in between evicts the source from the 256 MB last-level
+        # cache, so the copy's reads come from HBM
+        src = torch.ones(COPY_PROBE_BYTES // 8, dtype=torch.float64, device="cuda")
+        flush = torch.zeros_like(src)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
-        del src, dst
+        del src, flush, dst
     case = WL.shock_bubble_2d(n=a.n, seed=0)
     D = case["ndim"]
     print("bench: shock_bubble_2d %dx%d, warmup %d, steps %d" % (a.n, a.n, a.warmup, a.steps), flush=True)
@@ -102,7 +201,7 @@ def main():
     st = sim.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=a.steps)
     torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    ms_k, launches, bytes_k = sim.profile_read()
+    ms_k, launches, cells_k, first_k = sim.profile_read()
     sim.profile(False)
     t_end = st["t"]
     updates = sum(st["cell_updates"])
@@ -126,10 +225,22 @@ def main():
               flush=True)
         s2.close()
 
-    ach_gbs = bytes_k / (ms_k * 1e-3) / 1e9 if ms_k > 0 else 0.0
-    roof = dict(bound="hbm", achieved=round(ach_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(ach_gbs / HBM_PEAK_GBS, 4), traffic=None,
-                kernel="k_stage<2,bulk>", launches=launches, avg_ms=round(ms_k / max(launches, 1), 4))
+    # dominant kernel: the bulk-tile stage (FP64 VALU-bound, so its roofline is
+    # the FP64 vector peak; the HBM view of the same launches rides along)
+    flops_k = first_k * stage_flops(D, True) + (cells_k - first_k) * stage_flops(D, False)
+    bytes_k = first_k * stage_bytes(D, True) + (cells_k - first_k) * stage_bytes(D, False)
+    sec_k = ms_k * 1e-3
+    ach_tf = flops_k / sec_k / 1e12 if sec_k > 0 else 0.0
+    ach_gbs = bytes_k / sec_k / 1e9 if sec_k > 0 else 0.0
+    traffic = measured_traffic()
+    roof = dict(bound="alu", achieved=round(ach_tf, 2), peak=round(FP64_VECTOR_TFLOPS, 1), unit="TFLOP/s",
+                frac=round(ach_tf / FP64_VECTOR_TFLOPS, 4),
+                traffic=round(traffic) if traffic else None,
+                kernel="k_stage_lds<2, false>", launches=launches, avg_ms=round(ms_k / max(launches, 1), 4),
+                flops_per_launch=round(flops_k / max(launches, 1)),
+                algorithmic_bytes_per_launch=round(bytes_k / max(launches, 1)),
+                hbm=dict(achieved=round(ach_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(ach_gbs / HBM_PEAK_GBS, 4)))
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(WL.shock_bubble_2d, a.cpu_seconds)

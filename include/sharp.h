@@ -138,12 +138,12 @@ sim_status sim_totals(sim_t* s, double* out10);
 
 /* Kernel timing of the fused face-flux/RK stage kernel on bulk tiles: when
  * enabled, sim_advance brackets every launch of it with HIP events on the
- * simulation's stream.  sim_profile_read returns the summed duration (ms),
- * the number of launches, and the algorithmic bytes those launches move
- * (stage input and output, plus the step's base state after the first
- * stage: 2 or 3 x NV doubles per cell).  Enabling resets the counters. */
+ * stream the kernel runs on.  sim_profile_read returns the summed duration
+ * (ms), the number of launches, the cells those launches advanced by one
+ * stage (summed over launches), and how many of them were first stages of a
+ * step (which read no base state).  Enabling resets the counters. */
 sim_status sim_profile(sim_t* s, int enable);
-sim_status sim_profile_read(sim_t* s, double* ms, int64_t* launches, int64_t* bytes);
+sim_status sim_profile_read(sim_t* s, double* ms, int64_t* launches, int64_t* cells, int64_t* first_cells);
 
 void sim_destroy(sim_t* s);
 const char* sim_strerror(sim_status st);

@@ -72,7 +72,8 @@ def lib():
         L.sim_get_state.argtypes = [vp, vp, vp, vp, C.c_int]
         L.sim_totals.argtypes = [vp, vp]
         L.sim_profile.argtypes = [vp, C.c_int]
-        L.sim_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.sim_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
+                                       C.POINTER(C.c_int64)]
         L.sim_destroy.argtypes = [vp]
         L.sim_destroy.restype = None
         L.sim_strerror.argtypes = [C.c_int]
@@ -200,8 +201,11 @@ class Sim:
         _check(lib().sim_profile(self.h, int(enable)), "sim_profile")
 
     def profile_read(self):
+        """(ms, launches, cell_stages, first_stage_cells) of the bulk stage kernel"""
         ms = C.c_double()
         n = C.c_int64()
         cells = C.c_int64()
-        _check(lib().sim_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(cells)), "sim_profile_read")
-        return ms.value, n.value, cells.value
+        first = C.c_int64()
+        _check(lib().sim_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(cells), C.byref(first)),
+               "sim_profile_read")
+        return ms.value, n.value, cells.value, first.value

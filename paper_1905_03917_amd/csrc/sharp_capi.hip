@@ -334,19 +334,21 @@ sim_status sim_profile(sim_t* h, int enable)
     }
     s.prof_ms = 0.0;
     s.prof_launches = 0;
-    s.prof_bytes = 0;
+    s.prof_cell_stages = 0;
+    s.prof_first_stages = 0;
     s.ev_used = 0;
     s.prof_cells.clear();
     return SIM_OK;
 }
 
-sim_status sim_profile_read(sim_t* h, double* ms, int64_t* launches, int64_t* bytes)
+sim_status sim_profile_read(sim_t* h, double* ms, int64_t* launches, int64_t* cells, int64_t* first_cells)
 {
     if (!h) { set_error("null handle"); return SIM_EINVAL; }
     Sim& s = h->s;
     if (ms) *ms = s.prof_ms;
     if (launches) *launches = s.prof_launches;
-    if (bytes) *bytes = s.prof_bytes;
+    if (cells) *cells = s.prof_cell_stages;
+    if (first_cells) *first_cells = s.prof_first_stages;
     return SIM_OK;
 }
 

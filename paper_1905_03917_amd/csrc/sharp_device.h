@@ -201,31 +201,63 @@ __device__ __forceinline__ double weno5_q(double v0, double v1, double v2, doubl
 // ---------------------------------------------------------------------------
 struct Side { double rho, u, p, g, pi; };
 
-__device__ __forceinline__ double wave_f(const Side& s, double p, double& df)
+// One side of the two-material Riemann problem with its p-independent
+// constants: shock branch f = (p - p_s) sqrt(A / (p + p_inf + B)),
+// rarefaction branch f = 2c/(g-1) (((p + p_inf)/(p_s + p_inf))^((g-1)/(2g)) - 1).
+struct WaveSide {
+    double p, pi, g, rho;
+    double A, B;          // shock
+    double e, cf, irc, ipk;   // rarefaction: exponent, 2c/(g-1), 1/(rho c), 1/(p_s + p_inf)
+};
+
+__device__ __forceinline__ WaveSide wave_side(const Side& s)
 {
-    double pk = s.p + s.pi, pb = p + s.pi;
-    if (p > s.p) {
-        double A = 2.0 / ((s.g + 1.0) * s.rho);
-        double B = (s.g - 1.0) / (s.g + 1.0) * pk;
-        double q = sqrt(A / (pb + B));
-        df = q * (1.0 - 0.5 * (p - s.p) / (pb + B));
-        return (p - s.p) * q;
-    }
-    double c = csound(s.g, s.pi, s.rho, s.p);
-    double r = pb / pk, rz = pow(r, (s.g - 1.0) / (2.0 * s.g));
-    df = rz / r / (s.rho * c);
-    return 2.0 * c / (s.g - 1.0) * (rz - 1.0);
+    WaveSide w;
+    double pk = s.p + s.pi, c = csound(s.g, s.pi, s.rho, s.p);
+    w.p = s.p;
+    w.pi = s.pi;
+    w.g = s.g;
+    w.rho = s.rho;
+    w.A = 2.0 / ((s.g + 1.0) * s.rho);
+    w.B = (s.g - 1.0) / (s.g + 1.0) * pk;
+    w.e = (s.g - 1.0) / (2.0 * s.g);
+    w.cf = 2.0 * c / (s.g - 1.0);
+    w.irc = 1.0 / (s.rho * c);
+    w.ipk = 1.0 / pk;
+    return w;
 }
 
-__device__ __forceinline__ double star_rho(const Side& s, double ps)
+// f and f' of one side at p; both branches are evaluated (independent
+// chains, no divergence) and the one for p is selected.  rz returns the
+// rarefaction factor ((p + p_inf)/(p_s + p_inf))^((g-1)/(2g)).
+__device__ __forceinline__ double wave_fs(const WaveSide& w, double p, double& df, double& rz)
 {
-    double pk = s.p + s.pi, pb = ps + s.pi;
+    double pb = p + w.pi;
+    double t = 1.0 / (pb + w.B);
+    double q = sqrt(w.A * t);
+    double fs = (p - w.p) * q;
+    double dfs = q * (1.0 - 0.5 * (p - w.p) * t);
+    double r = pb * w.ipk;
+    rz = pow(r, w.e);
+    double fr = w.cf * (rz - 1.0);
+    double dfr = rz * w.irc / r;
+    bool shock = p > w.p;
+    df = shock ? dfs : dfr;
+    return shock ? fs : fr;
+}
+
+// star-state density behind the wave of side w at p (rz from wave_fs at p):
+// shock Hugoniot, or the isentrope rho (r)^(1/g) = rho r / rz^2
+__device__ __forceinline__ double star_rho_w(const WaveSide& w, double p, double rz)
+{
+    double pb = p + w.pi;
     if (pb <= 0.0) return 0.0;
-    if (ps > s.p) {
-        double m = (s.g - 1.0) / (s.g + 1.0);
-        return s.rho * (pb / pk + m) / (m * pb / pk + 1.0);
+    double r = pb * w.ipk;
+    if (p > w.p) {
+        double m = (w.g - 1.0) / (w.g + 1.0);
+        return w.rho * (r + m) / (m * r + 1.0);
     }
-    return s.rho * pow(pb / pk, 1.0 / s.g);
+    return w.rho * r / (rz * rz);
 }
 
 // Exact two-material Riemann problem: the root p* of
@@ -240,7 +272,8 @@ __device__ __forceinline__ double star_rho(const Side& s, double ps)
 // Newton step moves down until one reaches the floor.
 __device__ inline void riemann(const Side& L, const Side& R, double p0, double* out)
 {
-    double du = R.u - L.u, dfl, dfr;
+    const WaveSide wl = wave_side(L), wr = wave_side(R);
+    double du = R.u - L.u, dfl, dfr, rzl, rzr;
     double pfloor = -(L.pi < R.pi ? L.pi : R.pi);
     double p;
     if (p0 > pfloor && p0 < INFINITY) {
@@ -257,15 +290,17 @@ __device__ inline void riemann(const Side& L, const Side& R, double p0, double* 
     double scale = fabs(L.pi) + fabs(R.pi) + 1e-300;
     bool floor_known = false, at_floor = false;
     for (int it = 1; it <= 200; it++) {
-        double f = wave_f(L, p, dfl) + wave_f(R, p, dfr) + du;
+        double f = wave_fs(wl, p, dfl, rzl) + wave_fs(wr, p, dfr, rzr) + du;
         if (f > 0.0) { if (p < hi) hi = p; }
         else { if (p > lo) lo = p; }
         double pn = p - f / (dfl + dfr);
         if (!(pn > lo && pn < hi)) {
             if (!floor_known && !(pn > lo) && lo == pfloor) {
                 floor_known = true;
-                double d0l, d0r;
-                if (wave_f(L, pfloor, d0l) + wave_f(R, pfloor, d0r) + du >= 0.0) { at_floor = true; break; }
+                if (wave_fs(wl, pfloor, dfl, rzl) + wave_fs(wr, pfloor, dfr, rzr) + du >= 0.0) {
+                    at_floor = true;
+                    break;
+                }
             }
             pn = isfinite(hi) ? 0.5 * (lo + hi) : lo + 2.0 * (p - lo);
         }
@@ -274,11 +309,11 @@ __device__ inline void riemann(const Side& L, const Side& R, double p0, double* 
         if (fabs(dp) <= 1e-13 * (fabs(p) + scale)) break;
     }
     if (at_floor) p = pfloor;
-    double fl = wave_f(L, p, dfl), fr = wave_f(R, p, dfr);
+    double fl = wave_fs(wl, p, dfl, rzl), fr = wave_fs(wr, p, dfr, rzr);
     out[0] = p;
     out[1] = 0.5 * (L.u + R.u) + 0.5 * (fr - fl);
-    out[2] = star_rho(L, p);
-    out[3] = star_rho(R, p);
+    out[2] = star_rho_w(wl, p, rzl);
+    out[3] = star_rho_w(wr, p, rzr);
 }
 
 // ---------------------------------------------------------------------------

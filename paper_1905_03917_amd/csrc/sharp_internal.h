@@ -41,9 +41,9 @@ struct Sim {
     bool prof = false;
     std::vector<hipEvent_t> ev_pool;
     size_t ev_used = 0;
-    std::vector<long long> prof_cells;
+    std::vector<long long> prof_cells;    // cells of each pending timed launch (negative: first stage)
     double prof_ms = 0.0;
-    long long prof_launches = 0, prof_bytes = 0;
+    long long prof_launches = 0, prof_cell_stages = 0, prof_first_stages = 0;
     long long bulk_cells[2] = {0, 0};   // cells in the bulk lists (host copy)
     int lcount[NLISTS] = {1, 1, 1, 1, 1, 1};   // tiles per list (host copy, sizes the grids)
 };

@@ -1872,8 +1872,9 @@ struct Engine {
         launch_stage<false>(bs, bl, k, in, nullptr, base, out, a, dt, wflux, cfl);
         if (s.prof) {
             (void)hipEventRecord(s.ev_pool[ev + 1], bs);
-            // algorithmic bytes: read `in` (and `base` after the first stage), write `out`
-            s.prof_cells.push_back(s.bulk_cells[k] * (long long)((a == 0.0 ? 2 : 3) * NV * 8));
+            // cells this launch advances by one stage; the first stage of a
+            // step (a == 0) reads no base state
+            s.prof_cells.push_back(a == 0.0 ? -s.bulk_cells[k] : s.bulk_cells[k]);
         }
         if (ov) {
             (void)hipEventRecord(s.ev_bulk[k], bs);
@@ -1916,7 +1917,9 @@ struct Engine {
             (void)hipEventElapsedTime(&ms, s.ev_pool[e], s.ev_pool[e + 1]);
             s.prof_ms += ms;
             s.prof_launches++;
-            s.prof_bytes += s.prof_cells[e / 2];
+            long long c = s.prof_cells[e / 2];
+            s.prof_cell_stages += c < 0 ? -c : c;
+            if (c < 0) s.prof_first_stages += -c;
         }
         s.ev_used = 0;
         s.prof_cells.clear();
