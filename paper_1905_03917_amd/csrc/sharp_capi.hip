@@ -131,15 +131,16 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
         s.own_stream = true;
     }
     if (!o.serial) {
-        for (int k = 0; k < 2; k++) {
-            if (hipStreamCreateWithFlags(&s.side[k], hipStreamNonBlocking) != hipSuccess ||
-                hipEventCreateWithFlags(&s.ev_band[k], hipEventDisableTiming) != hipSuccess ||
-                hipEventCreateWithFlags(&s.ev_bulk[k], hipEventDisableTiming) != hipSuccess) {
-                release(s);
-                delete h;
-                set_error("stream/event creation failed");
-                return SIM_EDEVICE;
-            }
+        bool ok = true;
+        for (int k = 0; k < 2 && ok; k++)
+            ok = hipStreamCreateWithFlags(&s.side[k], hipStreamNonBlocking) == hipSuccess &&
+                 hipEventCreateWithFlags(&s.ev_band[k], hipEventDisableTiming) == hipSuccess &&
+                 hipEventCreateWithFlags(&s.ev_bulk[k], hipEventDisableTiming) == hipSuccess;
+        if (!ok) {
+            release(s);
+            delete h;
+            set_error("stream/event creation failed");
+            return SIM_EDEVICE;
         }
     }
     Dev& g = s.g;
@@ -195,6 +196,8 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     A(g.phiH, (size_t)g.nc);
     A(g.alpha, (size_t)g.nc);
     for (int d = 0; d < 3; d++) A(g.ap[d], d < D ? (size_t)g.nfc : 1);
+    A(s.alpha_alt, (size_t)g.nc);
+    for (int d = 0; d < 3; d++) A(s.ap_alt[d], d < D ? (size_t)g.nfc : 1);
     A(g.ps, (size_t)g.nc); A(g.us, (size_t)g.nc);
     for (int b = 0; b < 2; b++)
         for (int d = 0; d < 3; d++) A(g.v[b][d], d < D ? (size_t)g.nc : 1);

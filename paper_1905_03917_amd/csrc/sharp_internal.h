@@ -29,6 +29,10 @@ struct Sim {
     hipEvent_t ev_bulk[2] = {nullptr, nullptr};   // on side[k]: latest bulk stage of fluid k
     bool band_rec[2] = {false, false};
     bool bulk_pending[2] = {false, false};        // stream has not yet waited for side[k]
+    // second geometry buffer set: a new geometry is written there while
+    // kernels (and other blocks of the writing kernel) read the current one
+    double* alpha_alt = nullptr;
+    double* ap_alt[3] = {nullptr, nullptr, nullptr};
     int max_blocks = 2048; // grid-stride bound for tile-list kernels
     int bulk_blocks = SHARP_BULK_BLOCKS;  // the same bound for the bulk-tile stages
     bool has_state = false;

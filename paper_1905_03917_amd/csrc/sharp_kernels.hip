@@ -17,6 +17,7 @@
 // consecutive doubles of one component.
 #include <cmath>
 #include <cstring>
+#include <utility>
 
 #include "sharp_internal.h"
 
@@ -832,6 +833,17 @@ template <int D> struct ExtWG;
 template <> struct ExtWG<1> { static constexpr int W = 256, V = 256; };
 template <> struct ExtWG<2> { static constexpr int W = 1024, V = 1024; };
 
+// Region position whose stencil a region position evaluates: along a
+// zero-gradient direction the cells beyond the wall read the wall cell, so a
+// position there repeats the wall cell's update (o: global coordinate of
+// region position 0, x: global coordinate of the position).  Periodic
+// directions wrap, which commutes with the stencils, so positions stay.
+__device__ __forceinline__ int src_pos(const Dev& g, int d, int o, int x)
+{
+    if (g.bc[d] == 0) x = x < 0 ? 0 : (x >= g.n[d] ? g.n[d] - 1 : x);
+    return x - o;
+}
+
 // fused primitive recovery (real band cells) + extension of one fluid's
 // primitives per block (block b handles tile b/2, fluid b%2); reads
 // Wb[k][in], writes the band cells of Wb[k][out]
@@ -873,6 +885,7 @@ __global__ void __launch_bounds__(ExtWG<D>::W, 2 * ExtWG<D>::W / 256) k_extw_tb(
             if (r >= RN) continue;
             int rx = r % RX, ry = r / RX;
             int c = cidx(g, ox - EXT_H + rx, oy - HY + ry, 0);
+            int sx = src_pos(g, 0, ox - EXT_H, ox - EXT_H + rx), sy = D == 2 ? src_pos(g, 1, oy - HY, oy - HY + ry) : 0;
             double a = alpha_k(g, k, c);
             bool inM = g.M[c] != 0;
             if (inM && a >= g.amix) {
@@ -883,7 +896,7 @@ __global__ void __launch_bounds__(ExtWG<D>::W, 2 * ExtWG<D>::W / 256) k_extw_tb(
             } else {
                 for (int q = 0; q < NV; q++) sA[q * RN + r] = Wi[(size_t)q * g.nc + c];
             }
-            int pc = (rx + 1) + PX * (D == 2 ? ry + 1 : 0);
+            int pc = (sx + 1) + PX * (D == 2 ? sy + 1 : 0);
             if (!inM || !(a < g.amix) || sk * sPhi[pc] > g.extb * g.h) continue;
             double gr[2], g2 = 0.0;
             gr[0] = (sPhi[pc + 1] - sPhi[pc - 1]) / (2.0 * g.h);
@@ -899,7 +912,7 @@ __global__ void __launch_bounds__(ExtWG<D>::W, 2 * ExtWG<D>::W / 256) k_extw_tb(
             for (int d = 0; d < D; d++) {
                 double nd = sk * gr[d] / gm;
                 int o = nd > 0.0 ? -1 : 1;
-                int qx = rx + (d == 0 ? o : 0), qy = ry + (d == 1 ? o : 0);
+                int qx = sx + (d == 0 ? o : 0), qy = sy + (d == 1 ? o : 0);
                 inside &= qx >= 0 && qx < RX && qy >= 0 && qy < RY;
                 up[m][d] = qx + RX * qy;
                 w[m][d] = fabs(nd);
@@ -1051,13 +1064,14 @@ __global__ void __launch_bounds__(ExtWG<D>::V, 2 * ExtWG<D>::V / 256) k_vext_tb(
             int rx = r % RX, ry = r / RX;
             int gi = ox - EXT_H + rx, gj = oy - HY + ry;
             int c = cidx(g, gi, gj, 0);
+            int sx = src_pos(g, 0, ox - EXT_H, gi), sy = D == 2 ? src_pos(g, 1, oy - HY, gj) : 0;
             for (int e = 0; e < D; e++) sA[e * RN + r] = g.v[in][e][c];
             if (!g.M[c]) continue;
             int ci, cj, ck;
             coords(g, c, ci, cj, ck);
             double gv[3];
             if (iface<D>(g, ci, cj, ck, gv) > 0.0) continue;   // cut cells are the sources
-            int pc = (rx + 1) + PX * (D == 2 ? ry + 1 : 0);
+            int pc = (sx + 1) + PX * (D == 2 ? sy + 1 : 0);
             double gr[2], g2 = 0.0;
             gr[0] = (sPhi[pc + 1] - sPhi[pc - 1]) / (2.0 * g.h);
             g2 += gr[0] * gr[0];
@@ -1073,7 +1087,7 @@ __global__ void __launch_bounds__(ExtWG<D>::V, 2 * ExtWG<D>::V / 256) k_vext_tb(
             for (int d = 0; d < D; d++) {
                 double nd = sg * gr[d] / gmp;
                 int o = nd > 0.0 ? -1 : 1;
-                int qx = rx + (d == 0 ? o : 0), qy = ry + (d == 1 ? o : 0);
+                int qx = sx + (d == 0 ? o : 0), qy = sy + (d == 1 ? o : 0);
                 inside &= qx >= 0 && qx < RX && qy >= 0 && qy < RY;
                 up[m][d] = qx + RX * qy;
                 w[m][d] = fabs(nd);
@@ -1689,6 +1703,280 @@ __global__ void __launch_bounds__(SHARP_WG) k_copy_masked(Dev g, int list, const
 }
 
 // ---------------------------------------------------------------------------
+// The level-set chain of one stage for one tile in one kernel (1-D and 2-D),
+// temporally blocked: extension of the interface velocity from the cut cells'
+// u* n (k_vext_tb), one Shu-Osher stage of Eq. (LS:linearadvection) (k_ls),
+// on the last stage of a step K reinitialisation sweeps (k_nearif, k_reinit),
+// and the geometry of the resulting level set (k_geom_lds).  Each step runs
+// on a region that shrinks by the reach of the next one, so the tile's values
+// are those of the separate kernels:
+//   geometry          tile + 1
+//   reinit sweep m    tile + K - m + 1, sign-change flags tile + K + 1
+//   level-set stage   tile + HL  (HL = K + 2 on the last stage, else 1)
+//   velocity          tile + HL + EXT_H (exact at tile + HL after EXT_H sweeps)
+//   input level set   tile + HL + EXT_H + 1
+// Writes v[vout] and, on the band-mask cells of the tile, the stage output
+// (K < 0: not the last stage) or the reinitialised level set to `po`; the
+// geometry goes to alpha_out / ap_out (the second buffer set).  The
+// reinitialised level set is not written to phiP here: other blocks still
+// read phiP in their halos (base of the Shu-Osher stage).
+
+// ---------------------------------------------------------------------------
+template <int D, int HL>
+__global__ void __launch_bounds__(ExtWG<D>::V)
+k_lsgeo_tb(Dev g, int list, int vin, int vout, int iters, const double* phin, double a, double dt, double* po,
+           int K, double* alpha_out, double* ap_out0, double* ap_out1)
+{
+    static_assert(D <= 2, "temporally blocked level-set chain is for 1-D and 2-D");
+    constexpr int WGS = ExtWG<D>::V;
+    constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
+    constexpr int LX = TX + 2 * HL, LY = D == 2 ? TY + 2 * HL : 1, LN = LX * LY;
+    constexpr int VH = HL + EXT_H;
+    constexpr int VX = TX + 2 * VH, VY = D == 2 ? TY + 2 * VH : 1, VN = VX * VY;
+    constexpr int PX = VX + 2, PY = D == 2 ? VY + 2 : 1, PN = PX * PY;
+    constexpr int CPT = (VN + WGS - 1) / WGS;
+    constexpr int GX = TX + 1, GY = D == 2 ? TY + 1 : 1;
+    constexpr bool REUSE = 2 * LN <= D * VN;   // reinitialisation buffers fit in the free velocity buffer
+    __shared__ double sQR[REUSE ? 1 : 2 * LN];
+    __shared__ double sPhi[PN];
+    __shared__ double sA[D * VN], sB[D * VN];
+    __shared__ double sL[LN];
+    __shared__ uint8_t sM[LN], sN[LN];
+    __shared__ double sV[GX * GY];
+    const int* L = list_ptr(g, list);
+    const bool last = K >= 0;
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        int t = L[ti];
+        int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
+        const int vox = ox - VH, voy = D == 2 ? oy - VH : 0;     // velocity region origin
+        const int lox = ox - HL, loy = D == 2 ? oy - HL : 0;     // level-set region origin
+        // ---- input level set ----
+        for (int r = threadIdx.x; r < PN; r += WGS) {
+            int px = r % PX, py = r / PX;
+            sPhi[r] = phi_at(g, phin, cidx(g, vox - 1 + px, D == 2 ? voy - 1 + py : 0, 0));
+        }
+        __syncthreads();
+        // ---- velocity extension: sources (cut cells), targets, upwind weights ----
+        bool tgt[CPT];
+        int up[CPT][2];
+        double w[CPT][2];
+#pragma unroll
+        for (int m = 0; m < CPT; m++) {
+            int r = threadIdx.x + m * WGS;
+            tgt[m] = false;
+            if (r >= VN) continue;
+            int rx = r % VX, ry = r / VX;
+            int gi = vox + rx, gj = voy + ry;
+            int c = cidx(g, gi, gj, 0);
+            int sx = src_pos(g, 0, vox, gi), sy = D == 2 ? src_pos(g, 1, voy, gj) : 0;
+            for (int e = 0; e < D; e++) sA[e * VN + r] = g.v[vin][e][c];
+            if (!g.M[c]) continue;
+            int ci, cj, ck;
+            coords(g, c, ci, cj, ck);
+            double gv[3];
+            if (iface<D>(g, ci, cj, ck, gv) > 0.0) continue;
+            int pc = (sx + 1) + PX * (D == 2 ? sy + 1 : 0);
+            double gr[2], g2 = 0.0;
+            gr[0] = (sPhi[pc + 1] - sPhi[pc - 1]) / (2.0 * g.h);
+            g2 += gr[0] * gr[0];
+            if (D == 2) {
+                gr[1] = (sPhi[pc + PX] - sPhi[pc - PX]) / (2.0 * g.h);
+                g2 += gr[1] * gr[1];
+            }
+            double gmp = sqrt(g2);
+            if (!(gmp > 0.0)) continue;
+            double sg = sPhi[pc] < 0.0 ? -1.0 : 1.0;
+            bool inside = true;
+            double wsum = 0.0;
+            for (int d = 0; d < D; d++) {
+                double nd = sg * gr[d] / gmp;
+                int o = nd > 0.0 ? -1 : 1;
+                int qx = sx + (d == 0 ? o : 0), qy = sy + (d == 1 ? o : 0);
+                inside &= qx >= 0 && qx < VX && qy >= 0 && qy < VY;
+                up[m][d] = qx + VX * qy;
+                w[m][d] = fabs(nd);
+                wsum += w[m][d];
+            }
+            double iw = 1.0 / wsum;
+            for (int d = 0; d < D; d++) w[m][d] *= iw;
+            tgt[m] = inside;
+        }
+        __syncthreads();
+        double* A = sA;
+        double* B = sB;
+        for (int it = 0; it < iters; it++) {
+#pragma unroll
+            for (int m = 0; m < CPT; m++) {
+                int r = threadIdx.x + m * WGS;
+                if (r >= VN) continue;
+                for (int e = 0; e < D; e++) {
+                    double v;
+                    if (tgt[m]) {
+                        v = w[m][0] * A[e * VN + up[m][0]];
+                        if (D == 2) v += w[m][1] * A[e * VN + up[m][1]];
+                    } else {
+                        v = A[e * VN + r];
+                    }
+                    B[e * VN + r] = v;
+                }
+            }
+            __syncthreads();
+            double* tmp = A; A = B; B = tmp;
+        }
+        // ---- level-set stage on tile + HL (WENO5 upwind derivatives) ----
+        for (int r = threadIdx.x; r < LN; r += WGS) {
+            int lx = r % LX, ly = r / LX;
+            int gi = lox + lx, gj = loy + ly;
+            int c = cidx(g, gi, gj, 0);
+            int sx = src_pos(g, 0, lox, gi), sy = D == 2 ? src_pos(g, 1, loy, gj) : 0;
+            int vs = (sx + EXT_H) + VX * (D == 2 ? sy + EXT_H : 0);
+            int ps = (sx + EXT_H + 1) + PX * (D == 2 ? sy + EXT_H + 1 : 0);
+            bool inM = g.M[c] != 0;
+            sM[r] = inM;
+            double phi0 = sPhi[ps];
+            if (inM) {
+                double rhs = 0.0;
+                for (int d = 0; d < D; d++) {
+                    double vd = A[d * VN + vs];
+                    if (vd == 0.0) continue;
+                    int st = d == 0 ? 1 : PX;
+                    double p[7];
+                    for (int q = 0; q < 7; q++) p[q] = sPhi[ps + (q - 3) * st];
+                    double D1[6];
+                    for (int q = 0; q < 6; q++) D1[q] = (p[q + 1] - p[q]) / g.h;
+                    double der = vd > 0.0 ? weno5(D1[0], D1[1], D1[2], D1[3], D1[4], g.eps)
+                                          : weno5(D1[5], D1[4], D1[3], D1[2], D1[1], g.eps);
+                    rhs -= vd * der;
+                }
+                double s1 = phi0 + dt * rhs;
+                phi0 = (a == 0.0) ? s1 : a * g.phiP[c] + (1.0 - a) * s1;
+            }
+            sL[r] = phi0;
+            bool own = lx >= HL && lx < HL + TX && (D == 1 || (ly >= HL && ly < HL + TY)) && gi < g.n[0] &&
+                       (D == 1 || gj < g.n[1]);
+            if (own && inM) {
+                for (int e = 0; e < D; e++) g.v[vout][e][c] = A[e * VN + vs];
+                if (!last) po[c] = phi0;
+            }
+        }
+        __syncthreads();
+        // ---- reinitialisation on the last stage ----
+        const double* fin = sL;
+        if (last && K > 0) {
+            double* Q = REUSE ? ((A == sA) ? sB : sA) : sQR;
+            double* R = Q + LN;
+            const double h = g.h, dtau = 0.5 * g.h;
+            // sign changes of the stage output around tile + K + 1
+            for (int r = threadIdx.x; r < LN; r += WGS) {
+                int lx = r % LX, ly = r / LX;
+                int ex = lx < HL ? HL - lx : (lx >= HL + TX ? lx - (HL + TX - 1) : 0);
+                int ey = D == 2 ? (ly < HL ? HL - ly : (ly >= HL + TY ? ly - (HL + TY - 1) : 0)) : 0;
+                sN[r] = 0;
+                if (ex > K + 1 || ey > K + 1) continue;
+                int sx = src_pos(g, 0, lox, lox + lx), sy = D == 2 ? src_pos(g, 1, loy, loy + ly) : 0;
+                int neg = 0, pos = 0;
+                for (int dy = -(D == 2); dy <= (D == 2); dy++)
+                    for (int dx = -1; dx <= 1; dx++) {
+                        double v = sL[(sx + dx) + LX * (sy + dy)];
+                        if (v < 0.0) neg = 1; else pos = 1;
+                    }
+                sN[r] = (uint8_t)(neg && pos);
+            }
+            __syncthreads();
+            const double* in = sL;
+            for (int m = 1; m <= K; m++) {
+                double* out = (m % 2 == 1) ? Q : R;
+                int reach = K - m + 1;
+                for (int r = threadIdx.x; r < LN; r += WGS) {
+                    int lx = r % LX, ly = r / LX;
+                    int ex = lx < HL ? HL - lx : (lx >= HL + TX ? lx - (HL + TX - 1) : 0);
+                    int ey = D == 2 ? (ly < HL ? HL - ly : (ly >= HL + TY ? ly - (HL + TY - 1) : 0)) : 0;
+                    if (ex > reach || ey > reach) continue;
+                    int sx = src_pos(g, 0, lox, lox + lx), sy = D == 2 ? src_pos(g, 1, loy, loy + ly) : 0;
+                    int rs = sx + LX * sy;
+                    double pc = in[rs];
+                    if (!sM[rs]) { out[r] = pc; continue; }
+                    bool frz = false;
+                    for (int dy = -(D == 2); dy <= (D == 2); dy++)
+                        for (int dx = -1; dx <= 1; dx++) frz |= sN[rs + dx + LX * dy] != 0;
+                    if (frz) { out[r] = pc; continue; }
+                    double p0 = sL[rs];
+                    double S = p0 / sqrt(p0 * p0 + h * h), g2 = 0.0;
+                    for (int d = 0; d < D; d++) {
+                        int st = d == 0 ? 1 : LX;
+                        double am = (pc - in[rs - st]) / h;
+                        double bp = (in[rs + st] - pc) / h;
+                        double x, y;
+                        if (S > 0.0) { x = am > 0.0 ? am : 0.0; y = bp < 0.0 ? bp : 0.0; }
+                        else { x = am < 0.0 ? am : 0.0; y = bp > 0.0 ? bp : 0.0; }
+                        g2 += (x * x > y * y) ? x * x : y * y;
+                    }
+                    out[r] = pc - dtau * S * (sqrt(g2) - 1.0);
+                }
+                __syncthreads();
+                in = out;
+            }
+            fin = in;
+        }
+        if (last) {
+            for (int u = threadIdx.x; u < TX * TY; u += WGS) {
+                int li = u % TX, lj = u / TX;
+                int i = ox + li, j = oy + lj;
+                int r = (li + HL) + LX * (D == 2 ? lj + HL : 0);
+                if (i < g.n[0] && (D == 1 || j < g.n[1]) && sM[r]) po[i + g.n[0] * j] = fin[r];
+            }
+        }
+        // ---- geometry of the new level set (tile cells, padded high faces) ----
+        for (int r = threadIdx.x; r < GX * GY; r += WGS) {
+            int vx = r % GX, vy = r / GX;
+            double sum = 0.0;
+#pragma unroll
+            for (int b = 0; b < (1 << D); b++) {
+                int cx = HL - 1 + vx + (b & 1);
+                int cy = D == 2 ? HL - 1 + vy + ((b >> 1) & 1) : 0;
+                sum += fin[cx + LX * cy];
+            }
+            sV[r] = sum / (double)(1 << D);
+        }
+        __syncthreads();
+        for (int u = threadIdx.x; u < TX * TY; u += WGS) {
+            int li = u % TX, lj = u / TX;
+            int i = ox + li, j = oy + lj;
+            if (i >= g.n[0] || (D == 2 && j >= g.n[1])) continue;
+            int c = i + g.n[0] * j;
+            auto V = [&](int x, int y) { return sV[(li + x) + GX * (D == 2 ? lj + y : 0)]; };
+            double* apo[2] = {ap_out0, ap_out1};
+            int ii[2] = {i, j};
+#pragma unroll
+            for (int d = 0; d < D; d++) {
+                double alo, ahi;
+                if (D == 1) {
+                    alo = V(0, 0) < 0.0 ? 1.0 : 0.0;
+                    ahi = V(1, 0) < 0.0 ? 1.0 : 0.0;
+                } else if (d == 0) {
+                    alo = edge_frac(V(0, 0), V(0, 1));
+                    ahi = edge_frac(V(1, 0), V(1, 1));
+                } else {
+                    alo = edge_frac(V(0, 0), V(1, 0));
+                    ahi = edge_frac(V(0, 1), V(1, 1));
+                }
+                apo[d][fidx(g, i, j, 0)] = alo;
+                if (ii[d] == g.n[d] - 1) apo[d][fidx(g, i + (d == 0), j + (d == 1), 0)] = ahi;
+            }
+            double al;
+            if (D == 1) {
+                al = edge_frac(V(0, 0), V(1, 0));
+            } else {
+                double v4[4] = {V(0, 0), V(1, 0), V(1, 1), V(0, 1)};
+                al = clip_area(v4);
+            }
+            alpha_out[c] = al;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
 // initial state: cell contents alpha_k U_k of the given primitives; the
 // given primitives also start every ghost state
 // ---------------------------------------------------------------------------
@@ -1778,7 +2066,53 @@ struct Engine {
         k_tiles2<D><<<b, 256, 0, s.stream>>>(g);
         k_compact<<<1, 1024, 0, s.stream>>>(g);
     }
-    void geom(const double* cur, int list = LIST_BAND) { k_geom_lds<D><<<grid(list), wg(), 0, s.stream>>>(g, list, cur); }
+    // geometry of the level set `cur` into the second buffer set, which then
+    // becomes current (kernels launched before keep reading the old one)
+    void geom(const double* cur, int list = LIST_BAND)
+    {
+        Dev go = g;
+        go.alpha = s.alpha_alt;
+        for (int d = 0; d < 3; d++) go.ap[d] = s.ap_alt[d];
+        k_geom_lds<D><<<grid(list), wg(), 0, s.stream>>>(go, list, cur);
+        std::swap(g.alpha, s.alpha_alt);
+        for (int d = 0; d < 3; d++) std::swap(g.ap[d], s.ap_alt[d]);
+    }
+    template <int HL>
+    void launch_lsgeo(const double* phin, double a, double dt, double* po, int K)
+    {
+        if constexpr (D <= 2)
+            k_lsgeo_tb<D, HL><<<grid(LIST_INNER), ExtWG<D>::V, 0, s.stream>>>(
+                g, LIST_INNER, s.vcur, 1 - s.vcur, s.o.ext_iters, phin, a, dt, po, K, s.alpha_alt, s.ap_alt[0],
+                s.ap_alt[1]);
+    }
+    // level-set stage q (Shu-Osher coefficient a, step dt) from phin; the
+    // last stage of a step reinitialises.  Returns the new level set.
+    const double* ls_chain(int q, bool last, double a, double dt, const double* phin)
+    {
+        if constexpr (D <= 2) {
+            if (fused_ls()) {
+                int K = last ? s.o.reinit_iters : -1;
+                double* po = last ? g.phiB[2] : phi_stage_out(q);
+                switch (K >= 1 ? K + 2 : 1) {
+                case 1: launch_lsgeo<1>(phin, a, dt, po, K); break;
+                case 3: launch_lsgeo<3>(phin, a, dt, po, K); break;
+                default: launch_lsgeo<4>(phin, a, dt, po, K); break;
+                }
+                s.vcur ^= 1;
+                std::swap(g.alpha, s.alpha_alt);
+                for (int d = 0; d < 3; d++) std::swap(g.ap[d], s.ap_alt[d]);
+                if (!last) return po;
+                k_copy_masked<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, po, g.phiP);
+                return g.phiP;
+            }
+        }
+        double* po = phi_stage_out(q);
+        ls(a, dt, phin, po);
+        const double* cur = po;
+        if (last) { reinit(po); cur = g.phiP; }
+        geom(cur);
+        return cur;
+    }
 
     // ---- band physics ----
     void prims(int k, const double* src) { k_prims<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, k, src, s.wcur); }
@@ -1814,12 +2148,18 @@ struct Engine {
         extw(cur);
     }
     void velocity(const double* cur) { extv(cur); }
-    void interaction(const double* src0, const double* src1, const double* cur, double wcorr, int S)
+    // the velocity extension runs inside the fused level-set kernel
+    bool fused_ls() const { return D <= 2 && s.o.ext_iters <= EXT_H && s.o.reinit_iters <= 2; }
+    // interface interaction: ghost states, Riemann problems, and (unless a
+    // fused level-set stage follows and extends it) the level-set velocity
+    void interaction(const double* src0, const double* src1, const double* cur, double wcorr, int S,
+                     bool ls_follows = true)
     {
         band_state(src0, src1, cur);
         if constexpr (D <= 2) {
             if (s.o.ext_iters <= EXT_H) {
                 k_riemann<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, s.wcur, s.vcur, wcorr, S);
+                if (ls_follows && fused_ls()) return;
                 k_vext_tb<D><<<grid(LIST_INNER), ExtWG<D>::V, 0, s.stream>>>(g, LIST_INNER, s.vcur, 1 - s.vcur,
                                                                             s.o.ext_iters, cur);
                 s.vcur ^= 1;
@@ -2019,11 +2359,7 @@ struct Engine {
                 out[k] = (st == ns - 1) ? g.X[k] : (st == 0 ? g.Y[k] : g.Z[k]);
                 stage(k, in[k], nullptr, g.X[k], out[k], A[st], dt, B[st] * dt);
             }
-            double* po = phi_stage_out(st);
-            ls(A[st], dt, phin, po);
-            const double* cur = po;
-            if (st == ns - 1) { reinit(po); cur = g.phiP; }
-            geom(cur);
+            const double* cur = ls_chain(st, st == ns - 1, A[st], dt, phin);
             mix(0, out[0], cur);
             mix(1, out[1], cur);
             in[0] = out[0];
@@ -2124,26 +2460,23 @@ struct Engine {
             const double* in = g.X[F];
             const double* phin = g.phiP;
             for (int q = 0; q < ns; q++) {
+                bool shared = false;
                 if (q > 0) {
                     double theta = (fin && C[q] == 1.0) ? 1.0 : (tau + C[q] * dl) / t1;
                     interp_slow(S, theta, phin);
-                    bool shared = fin && C[q] == 1.0;
+                    shared = fin && C[q] == 1.0;
                     double w = !corr ? 0.0 : (shared ? -B[q] * t1 + B[q] * dl : B[q] * dl);
                     interaction(S == 0 ? g.T2 : in, S == 0 ? in : g.T2, phin, w, S);
-                    if (shared) {
-                        // shared with the slow fluid's second stage, Eq. (firstcorrection)
-                        stage(S, g.Y[S], g.T2, g.X[S], ns == 2 ? g.X[S] : g.Z[S], A[q], t1, B[q] * t1);
-                    }
                 } else if (!first && corr) {
                     corr_add(B[0] * dl, S);   // Eq. (secondcorrection)
                 }
+                if (shared) {
+                    // shared with the slow fluid's second stage, Eq. (firstcorrection)
+                    stage(S, g.Y[S], g.T2, g.X[S], ns == 2 ? g.X[S] : g.Z[S], A[q], t1, B[q] * t1);
+                }
                 double* out = (q == ns - 1) ? g.X[F] : (q == 0 ? g.Y[F] : g.Z[F]);
                 stage(F, in, nullptr, g.X[F], out, A[q], dl, B[q] * dl, (q == ns - 1 && !fin) ? 1 : 0);
-                double* po = phi_stage_out(q);
-                ls(A[q], dl, phin, po);
-                const double* cur = po;
-                if (q == ns - 1) { reinit(po); cur = g.phiP; }
-                geom(cur);
+                const double* cur = ls_chain(q, q == ns - 1, A[q], dl, phin);
                 mix(F, out, cur);
                 in = out;
                 phin = cur;
@@ -2163,7 +2496,7 @@ struct Engine {
             // slow fluid's third stage at t1/2 against the snapshots
             geom(g.phiH);
             mixed_copy(S, g.Z[S], g.phiH);
-            interaction(S == 0 ? g.T2 : g.Fh, S == 0 ? g.Fh : g.T2, g.phiH, corr ? -B[2] * t1 : 0.0, S);
+            interaction(S == 0 ? g.T2 : g.Fh, S == 0 ? g.Fh : g.T2, g.phiH, corr ? -B[2] * t1 : 0.0, S, false);
             stage(S, g.Z[S], g.T2, g.X[S], g.X[S], A[2], t1, B[2] * t1);
             geom(g.phiP);
         }
@@ -2222,6 +2555,7 @@ struct Engine {
         SHARP_HIP(hipMemcpyAsync(g.phiP, phi, sizeof(double) * g.nc, hipMemcpyDeviceToDevice, s.stream));
         SHARP_HIP(hipMemsetAsync(g.M, 0, g.nc, s.stream));
         geom(g.phiP, LIST_ALL);
+        geom(g.phiP, LIST_ALL);   // both geometry buffers start from the initial level set
         int b = (g.nc + 255) / 256;
         if (b > 65535) b = 65535;
         k_init<D><<<b, 256, 0, s.stream>>>(g, prim);

@@ -167,6 +167,20 @@ def droplet_2d(n=64, seed=0, radius=0.1, u=None, ndim=2):
                  "droplet_%dd" % ndim, centre=c, radius=radius)
 
 
+def wall_bubble_2d(n=64, seed=0, radius=0.2):
+    """Air bubble (fluid 0) cut by the zero-gradient wall x = 0, at a higher
+    pressure than the surrounding water: the interface band touches the wall,
+    so extension, level set and mixing all meet the boundary."""
+    h, (X, Y) = _grid(2, n)
+    r = _rng(seed)
+    cx, cy = r.uniform(-0.5, 0.5) * h, 0.5 + r.uniform(-0.5, 0.5) * h
+    phi = np.sqrt((X - cx) ** 2 + (Y - cy) ** 2) - radius
+    nc = n * n
+    air = _fill(2, nc, dict(rho=5.0, p=5.0e5))
+    water = _fill(2, nc, dict(rho=1000.0, p=1.0e5))
+    return _case(2, n, 0, AIR, WATER, phi, np.stack([air, water]), 1e30, "wall_bubble_2d", centre=(cx, cy))
+
+
 def entropy_wave_1d(n=64, amp=0.2, u=1.0, p=1.0, t_end=0.1):
     """Single fluid (phi < 0 everywhere) smooth density wave on a periodic
     domain: rho = 1 + amp sin(2 pi x), uniform u and p.  Exact solution is a

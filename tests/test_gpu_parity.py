@@ -99,6 +99,14 @@ def test_droplet_periodic_2d(mode):
     _compare(WL.droplet_2d(n=40, seed=3), mode, 2)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("n", [64, 100])
+def test_band_at_zero_gradient_wall(n, mode):
+    """the interface band crosses a zero-gradient wall: temporally blocked
+    sweeps must evaluate positions beyond the wall as the wall cell"""
+    _compare(WL.wall_bubble_2d(n=n, seed=2), mode, 2)
+
+
 def test_smooth_2d(mode=1):
     _compare(WL.smooth_2d(n=48, seed=1), mode, 3)
 
