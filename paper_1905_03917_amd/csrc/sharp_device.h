@@ -201,6 +201,69 @@ __device__ __forceinline__ double weno5_q(double v0, double v1, double v2, doubl
 // ---------------------------------------------------------------------------
 struct Side { double rho, u, p, g, pi; };
 
+// Positive powers x^y (x >= 0, |y log x| moderate) for the rarefaction
+// branches, as exp(y log x) with short, branch-free evaluations:
+//  - log: x = m 2^e, m in [sqrt(1/2), sqrt(2)); log m = 2 atanh(s) with
+//    s = (m - 1)/(m + 1), |s| <= 0.172, summed as its Taylor series in s^2
+//    through s^21 (truncation below 1e-18 relative);
+//  - exp: y = k ln 2 + r, |r| <= ln 2 / 2, by Cody-Waite reduction with ln 2
+//    split into a 29-bit head (k * head exact) and a tail; exp r by its
+//    Taylor series through r^13 (truncation below 1e-17 relative).
+// A few ulp against a correctly rounded power; the Riemann solver only needs
+// its root to 1e-13.
+constexpr double LN2_HI = 0x1.62e42ffp-1;                 // 29 significant bits
+constexpr double LN2_LO = -4.2009150726810846e-11;        // ln 2 - LN2_HI
+constexpr double INV_LN2 = 1.4426950408889634;
+
+__host__ __device__ __forceinline__ double log_pos(double x)
+{
+    int e;
+    double m = frexp(x, &e);
+    if (m < 0.70710678118654752) { m *= 2.0; e -= 1; }
+    double s = (m - 1.0) / (m + 1.0);
+    double z = s * s;
+    double p = 1.0 / 21.0;
+    p = fma(p, z, 1.0 / 19.0);
+    p = fma(p, z, 1.0 / 17.0);
+    p = fma(p, z, 1.0 / 15.0);
+    p = fma(p, z, 1.0 / 13.0);
+    p = fma(p, z, 1.0 / 11.0);
+    p = fma(p, z, 1.0 / 9.0);
+    p = fma(p, z, 1.0 / 7.0);
+    p = fma(p, z, 1.0 / 5.0);
+    p = fma(p, z, 1.0 / 3.0);
+    p = fma(p, z, 1.0);
+    double de = (double)e;
+    return fma(de, LN2_HI, fma(de, LN2_LO, 2.0 * s * p));
+}
+
+__host__ __device__ __forceinline__ double exp_fin(double y)
+{
+    double k = rint(y * INV_LN2);
+    double r = fma(-k, LN2_HI, y);
+    r = fma(-k, LN2_LO, r);
+    double p = 1.0 / 6227020800.0;           // 1/13!
+    p = fma(p, r, 1.0 / 479001600.0);
+    p = fma(p, r, 1.0 / 39916800.0);
+    p = fma(p, r, 1.0 / 3628800.0);
+    p = fma(p, r, 1.0 / 362880.0);
+    p = fma(p, r, 1.0 / 40320.0);
+    p = fma(p, r, 1.0 / 5040.0);
+    p = fma(p, r, 1.0 / 720.0);
+    p = fma(p, r, 1.0 / 120.0);
+    p = fma(p, r, 1.0 / 24.0);
+    p = fma(p, r, 1.0 / 6.0);
+    p = fma(p, r, 0.5);
+    p = fma(p, r, 1.0);
+    p = fma(p, r, 1.0);
+    return ldexp(p, (int)k);
+}
+
+__host__ __device__ __forceinline__ double pow_pos(double x, double y)
+{
+    return x > 0.0 ? exp_fin(y * log_pos(x)) : 0.0;
+}
+
 // One side of the two-material Riemann problem with its p-independent
 // constants: shock branch f = (p - p_s) sqrt(A / (p + p_inf + B)),
 // rarefaction branch f = 2c/(g-1) (((p + p_inf)/(p_s + p_inf))^((g-1)/(2g)) - 1).
@@ -238,7 +301,7 @@ __device__ __forceinline__ double wave_fs(const WaveSide& w, double p, double& d
     double fs = (p - w.p) * q;
     double dfs = q * (1.0 - 0.5 * (p - w.p) * t);
     double r = pb * w.ipk;
-    rz = pow(r, w.e);
+    rz = pow_pos(r, w.e);
     double fr = w.cf * (rz - 1.0);
     double dfr = rz * w.irc / r;
     bool shock = p > w.p;
