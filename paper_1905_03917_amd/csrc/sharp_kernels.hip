@@ -1429,12 +1429,17 @@ template <int D> struct Region;
 template <> struct Region<1> { static constexpr int X = 256 + 6, Y = 1; };
 template <> struct Region<2> { static constexpr int X = 16 + 6, Y = 16 + 6; };
 
+// threads per block of the LDS stage kernel (one per tile cell: blocks with
+// a fifth wavefront share a SIMD between two of theirs and run slower)
+template <int D> struct StageWG { static constexpr int N = SHARP_WG; };
+
 template <int D, bool BAND>
-__global__ void __launch_bounds__(SHARP_WG) k_stage_lds(Dev g, int list, int k, const double* in, const double* self2,
-                                                       const double* base, double* out, double a, double dt,
-                                                       double wflux, int wb, int cfl)
+__global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, int k, const double* in,
+                                                            const double* self2, const double* base, double* out,
+                                                            double a, double dt, double wflux, int wb, int cfl)
 {
-    __shared__ double sMax[SHARP_WG / 64];
+    constexpr int NT = StageWG<D>::N;
+    __shared__ double sMax[NT / 64];
     double cmax = 0.0;          // CFL speed of this thread's output cells (bulk, when cfl != 0)
     unsigned long long ccnt = 0;
     static_assert(D <= 2, "LDS stage kernel is for 1-D and 2-D");
@@ -1454,10 +1459,27 @@ __global__ void __launch_bounds__(SHARP_WG) k_stage_lds(Dev g, int list, int k, 
         int t = L[ti];
         int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1];
         int ox = tx * TX, oy = ty * TY;
-        // ---- primitives of the tile and its halo (corners are never used) ----
-        for (int r = threadIdx.x; r < RN; r += SHARP_WG) {
-            int rx = r % RX, ry = r / RX;
-            if (D == 2 && (rx < 3 || rx >= TX + 3) && (ry < 3 || ry >= TY + 3)) continue;
+        // ---- primitives of the tile and its halo (the corners are never used:
+        // in 2-D the 448 other region cells are enumerated densely) ----
+        constexpr int NL = D == 2 ? RN - 4 * 9 : RN;
+        for (int q = threadIdx.x; q < NL; q += NT) {
+            int rx, ry;
+            if (D == 1) {
+                rx = q;
+                ry = 0;
+            } else if (q < 3 * TX) {
+                ry = q / TX;
+                rx = 3 + q % TX;
+            } else if (q < 3 * TX + TY * RX) {
+                int u = q - 3 * TX;
+                ry = 3 + u / RX;
+                rx = u % RX;
+            } else {
+                int u = q - 3 * TX - TY * RX;
+                ry = TY + 3 + u / TX;
+                rx = 3 + u % TX;
+            }
+            int r = rx + RX * ry;
             int c = cidx(g, ox - 3 + rx, D == 2 ? oy - 3 + ry : 0, 0);
             double W[NV], U[NV];
             load_state<D, BAND>(g, k, in, self2, wb, c, W, U);
@@ -1470,7 +1492,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_stage_lds(Dev g, int list, int k, 
         }
         __syncthreads();
         // ---- face fluxes ----
-        for (int f = threadIdx.x; f < FT; f += SHARP_WG) {
+        for (int f = threadIdx.x; f < FT; f += NT) {
             int d, li, lj;
             if (f < F0) { d = 0; li = f % (TX + 1); lj = f / (TX + 1); }
             else { int r = f - F0; d = 1; li = r % TX; lj = r / TX; }
@@ -1540,7 +1562,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_stage_lds(Dev g, int list, int k, 
         }
         __syncthreads();
         // ---- cell update ----
-        {
+        if (threadIdx.x < TX * TY) {
             int li = threadIdx.x % TX, lj = threadIdx.x / TX;
             int i = ox + li, j = oy + lj;
             if (i < g.n[0] && j < g.n[1]) {
@@ -1590,12 +1612,12 @@ __global__ void __launch_bounds__(SHARP_WG) k_stage_lds(Dev g, int list, int k, 
             cmax = fmax(cmax, __shfl_down(cmax, off, 64));
             ccnt += __shfl_down(ccnt, off, 64);
         }
-        __shared__ unsigned long long sCnt[SHARP_WG / 64];
+        __shared__ unsigned long long sCnt[NT / 64];
         int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
         if (lane == 0) { sMax[wid] = cmax; sCnt[wid] = ccnt; }
         __syncthreads();
         if (threadIdx.x == 0) {
-            for (int w = 1; w < SHARP_WG / 64; w++) { cmax = fmax(cmax, sMax[w]); ccnt += sCnt[w]; }
+            for (int w = 1; w < NT / 64; w++) { cmax = fmax(cmax, sMax[w]); ccnt += sCnt[w]; }
             if (!(cmax >= 0.0) || isinf(cmax)) { flag_error(g, ERR_NONPHYS); cmax = 0.0; }
             atomicMax(&g.red[k], (unsigned long long)__double_as_longlong(cmax));
             atomicAdd(&g.red[2 + k], ccnt);
@@ -2243,7 +2265,8 @@ struct Engine {
     {
         dim3 gr = grid(list, 1, BAND ? 0 : s.bulk_blocks);
         if constexpr (D <= 2)
-            k_stage_lds<D, BAND><<<gr, wg(), 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur, cfl);
+            k_stage_lds<D, BAND><<<gr, StageWG<D>::N, 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur,
+                                                               cfl);
         else
             k_stage<D, BAND><<<gr, wg(), 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
     }
