@@ -191,6 +191,7 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
         A(g.bacc[k], (size_t)NV * (g.nbface > 0 ? g.nbface : 1));
     }
     A(g.T2, nv); A(g.Fh, nv); A(g.corr, nv); A(g.dmix, nv);
+    A(g.Tm[0], nv); A(g.Tm[1], nv);
     A(g.phiP, (size_t)g.nc);
     for (int b = 0; b < 3; b++) A(g.phiB[b], (size_t)g.nc);
     A(g.phiH, (size_t)g.nc);

@@ -37,6 +37,7 @@ struct Dev {
     double* Y[2];
     double* Z[2];
     double* T2;       // slow-fluid temporary (interpolated and mixed)
+    double* Tm[2];    // per fluid: band-stage output of the inner tiles, before mixing
     double* Fh;       // fast-fluid snapshot at t1/2
     double* Wb[2][2]; // primitives, two Jacobi buffers per fluid
     double* phiP;     // level set, base/current

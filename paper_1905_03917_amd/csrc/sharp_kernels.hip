@@ -611,92 +611,144 @@ __global__ void __launch_bounds__(SHARP_WG) k_mixdelta_lds(Dev g, int list, int 
     }
 }
 
-// Slow fluid's temporary state: dst = v + mixing increment of v, where
-// v = a1*s1 + a2*s2 (Eq. interpolation) is formed on the fly; the inputs are
-// read only, so one kernel suffices (the increments use pre-mixing values).
+// Mixed copy of one tile: dst = v + mixing increment of v, where
+// v = a1*s1 + a2*s2 (s2 may be null: v = s1) is formed on the fly from
+// inputs that are only read, so one pass suffices (the increments use
+// pre-mixing values).  Used for the slow fluid's temporary state (Eq.
+// interpolation, then mixing with the current geometry) and for the mixing
+// of a stage output written out of place.
+struct MixPart {
+    int k;                // fluid
+    double a1;
+    const double* s1;
+    double a2;
+    const double* s2;
+    double* dst;
+    int do_mix;
+};
+
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_mixinterp_lds(Dev g, int list, int k, double a1, const double* s1,
-                                                           double a2, const double* s2, double* dst, int do_mix,
-                                                           const double* cur)
+__device__ __forceinline__ void mix_tile(const Dev& g, int t, const MixPart& P, const double* cur, double* sBeta,
+                                         int* sTgt, int* sCell)
 {
-    static_assert(D <= 2, "LDS mixing is for 1-D and 2-D");
     constexpr int NV = D + 2;
     constexpr int NS = (1 << D) - 1;
     constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
     constexpr int RX = MixRegion<D>::X, RY = MixRegion<D>::Y, RN = RX * RY;
     constexpr int HY = D == 2 ? 1 : 0;
-    __shared__ double sBeta[NS * RN];
-    __shared__ int sTgt[NS * RN];
-    __shared__ int sCell[RN];
-    const int* L = list_ptr(g, list);
+    const int k = P.k;
+    const double a1 = P.a1, a2 = P.a2;
+    const double* s1 = P.s1;
+    const double* s2 = P.s2;
     auto val = [&](int q, int c) {
         size_t e = (size_t)q * g.nc + c;
         return s2 ? a1 * s1[e] + a2 * s2[e] : s1[e];
     };
+    int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
+    if (P.do_mix) {
+        for (int r = threadIdx.x; r < RN; r += SHARP_WG) {
+            int rx = r % RX, ry = r / RX;
+            int c = cidx(g, ox - 1 + rx, oy - HY + ry, 0);
+            sCell[r] = c;
+            double beta[7];
+            int tgt[7];
+            bool src = mix_source<D>(g, cur, k, c, beta, tgt);
+            for (int m = 0; m < NS; m++) {
+                sBeta[m * RN + r] = src ? beta[m] : 0.0;
+                sTgt[m * RN + r] = src ? tgt[m] : -1;
+            }
+        }
+    }
+    __syncthreads();
+    int li = threadIdx.x % TX, lj = threadIdx.x / TX;
+    int i = ox + li, j = oy + lj;
+    if (i < g.n[0] && j < g.n[1]) {
+        int c = i + g.n[0] * j;
+        double vc[NV], dl[NV];
+        for (int q = 0; q < NV; q++) { vc[q] = val(q, c); dl[q] = 0.0; }
+        if (P.do_mix && g.M[c]) {
+            int rc = (li + 1) + RX * (lj + HY);
+            double ac = alpha_k(g, k, c);
+            for (int m = 0; m < NS; m++) {
+                int tt = sTgt[m * RN + rc];
+                double b = sBeta[m * RN + rc];
+                if (tt < 0 || !(b > 0.0) || tt == c) continue;
+                double at = alpha_k(g, k, tt);
+                if (!(ac + at > 0.0)) continue;
+                for (int q = 0; q < NV; q++) dl[q] += b * (val(q, tt) * ac - vc[q] * at) / (ac + at);
+            }
+            bool edge = i == 0 || i == g.n[0] - 1 || (D == 2 && (j == 0 || j == g.n[1] - 1));
+            int seen[8];
+            int ns = 0;
+            for (int oy2 = -HY; oy2 <= HY; oy2++)
+                for (int ox2 = -1; ox2 <= 1; ox2++) {
+                    if (!ox2 && !oy2) continue;
+                    int rs = rc + ox2 + RX * oy2;
+                    int sc = sCell[rs];
+                    if (sc == c) continue;
+                    if (edge) {
+                        bool dup = false;
+                        for (int u = 0; u < ns; u++) dup |= (seen[u] == sc);
+                        if (dup) continue;
+                        seen[ns++] = sc;
+                    }
+                    if (sTgt[rs] < 0) continue;
+                    double as = alpha_k(g, k, sc);
+                    if (!(as + ac > 0.0)) continue;
+                    for (int m = 0; m < NS; m++) {
+                        if (sTgt[m * RN + rs] != c) continue;
+                        double b = sBeta[m * RN + rs];
+                        if (!(b > 0.0)) continue;
+                        for (int q = 0; q < NV; q++) dl[q] -= b * (vc[q] * as - val(q, sc) * ac) / (as + ac);
+                    }
+                }
+        }
+        for (int q = 0; q < NV; q++) P.dst[(size_t)q * g.nc + c] = vc[q] + dl[q];
+    }
+    __syncthreads();
+}
+
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_mixinterp_lds(Dev g, int list, MixPart P, const double* cur)
+{
+    static_assert(D <= 2, "LDS mixing is for 1-D and 2-D");
+    constexpr int NS = (1 << D) - 1;
+    constexpr int RN = MixRegion<D>::X * MixRegion<D>::Y;
+    __shared__ double sBeta[NS * RN];
+    __shared__ int sTgt[NS * RN];
+    __shared__ int sCell[RN];
+    const int* L = list_ptr(g, list);
+    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x)
+        mix_tile<D>(g, L[ti], P, cur, sBeta, sTgt, sCell);
+}
+
+// Several mixed copies of the same tiles in one launch (the parts read no
+// buffer another part writes), and optionally phi_dst = phi_src on the
+// band-mask cells (the mixing reads the level set through phi_src).
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_mix_parts(Dev g, int list, MixPart A, MixPart B, int nparts,
+                                                       const double* cur, const double* phi_src, double* phi_dst)
+{
+    static_assert(D <= 2, "LDS mixing is for 1-D and 2-D");
+    constexpr int NS = (1 << D) - 1;
+    constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
+    constexpr int RN = MixRegion<D>::X * MixRegion<D>::Y;
+    __shared__ double sBeta[NS * RN];
+    __shared__ int sTgt[NS * RN];
+    __shared__ int sCell[RN];
+    const int* L = list_ptr(g, list);
     for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
         int t = L[ti];
-        int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
-        if (do_mix) {
-            for (int r = threadIdx.x; r < RN; r += SHARP_WG) {
-                int rx = r % RX, ry = r / RX;
-                int c = cidx(g, ox - 1 + rx, oy - HY + ry, 0);
-                sCell[r] = c;
-                double beta[7];
-                int tgt[7];
-                bool src = mix_source<D>(g, cur, k, c, beta, tgt);
-                for (int m = 0; m < NS; m++) {
-                    sBeta[m * RN + r] = src ? beta[m] : 0.0;
-                    sTgt[m * RN + r] = src ? tgt[m] : -1;
-                }
+        mix_tile<D>(g, t, A, cur, sBeta, sTgt, sCell);
+        if (nparts > 1) mix_tile<D>(g, t, B, cur, sBeta, sTgt, sCell);
+        if (phi_dst) {
+            int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
+            int i = ox + (int)threadIdx.x % TX, j = oy + (int)threadIdx.x / TX;
+            if (i < g.n[0] && j < g.n[1]) {
+                int c = i + g.n[0] * j;
+                if (g.M[c]) phi_dst[c] = phi_src[c];
             }
         }
-        __syncthreads();
-        int li = threadIdx.x % TX, lj = threadIdx.x / TX;
-        int i = ox + li, j = oy + lj;
-        if (i < g.n[0] && j < g.n[1]) {
-            int c = i + g.n[0] * j;
-            double vc[NV], dl[NV];
-            for (int q = 0; q < NV; q++) { vc[q] = val(q, c); dl[q] = 0.0; }
-            if (do_mix && g.M[c]) {
-                int rc = (li + 1) + RX * (lj + HY);
-                double ac = alpha_k(g, k, c);
-                for (int m = 0; m < NS; m++) {
-                    int tt = sTgt[m * RN + rc];
-                    double b = sBeta[m * RN + rc];
-                    if (tt < 0 || !(b > 0.0) || tt == c) continue;
-                    double at = alpha_k(g, k, tt);
-                    if (!(ac + at > 0.0)) continue;
-                    for (int q = 0; q < NV; q++) dl[q] += b * (val(q, tt) * ac - vc[q] * at) / (ac + at);
-                }
-                bool edge = i == 0 || i == g.n[0] - 1 || (D == 2 && (j == 0 || j == g.n[1] - 1));
-                int seen[8];
-                int ns = 0;
-                for (int oy2 = -HY; oy2 <= HY; oy2++)
-                    for (int ox2 = -1; ox2 <= 1; ox2++) {
-                        if (!ox2 && !oy2) continue;
-                        int rs = rc + ox2 + RX * oy2;
-                        int sc = sCell[rs];
-                        if (sc == c) continue;
-                        if (edge) {
-                            bool dup = false;
-                            for (int u = 0; u < ns; u++) dup |= (seen[u] == sc);
-                            if (dup) continue;
-                            seen[ns++] = sc;
-                        }
-                        if (sTgt[rs] < 0) continue;
-                        double as = alpha_k(g, k, sc);
-                        if (!(as + ac > 0.0)) continue;
-                        for (int m = 0; m < NS; m++) {
-                            if (sTgt[m * RN + rs] != c) continue;
-                            double b = sBeta[m * RN + rs];
-                            if (!(b > 0.0)) continue;
-                            for (int q = 0; q < NV; q++) dl[q] -= b * (vc[q] * as - val(q, sc) * ac) / (as + ac);
-                        }
-                    }
-            }
-            for (int q = 0; q < NV; q++) dst[(size_t)q * g.nc + c] = vc[q] + dl[q];
-        }
-        __syncthreads();
     }
 }
 
@@ -1433,10 +1485,13 @@ template <> struct Region<2> { static constexpr int X = 16 + 6, Y = 16 + 6; };
 // a fifth wavefront share a SIMD between two of theirs and run slower)
 template <int D> struct StageWG { static constexpr int N = SHARP_WG; };
 
+// `tmp` (band tiles, may be null): the output of inner band tiles goes there
+// instead of `out`, to be mixed into `out` out of place
 template <int D, bool BAND>
 __global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, int k, const double* in,
                                                             const double* self2, const double* base, double* out,
-                                                            double a, double dt, double wflux, int wb, int cfl)
+                                                            double a, double dt, double wflux, int wb, int cfl,
+                                                            double* tmp)
 {
     constexpr int NT = StageWG<D>::N;
     __shared__ double sMax[NT / 64];
@@ -1586,13 +1641,14 @@ __global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, in
                     }
                 }
                 const double* sin_ = (BAND && self2 && g.M[c]) ? self2 : in;
+                double* dst = (BAND && tmp && !(g.tflag[t] & 4)) ? tmp : out;
                 double Uo[NV];
 #pragma unroll
                 for (int q = 0; q < NV; q++) {
                     size_t e = (size_t)q * g.nc + c;
                     double s = sin_[e] + dt * Lr[q];
                     Uo[q] = (a == 0.0) ? s : a * base[e] + (1.0 - a) * s;
-                    out[e] = Uo[q];
+                    dst[e] = Uo[q];
                 }
                 if (!BAND && cfl) {
                     double W[NV];
@@ -2108,9 +2164,14 @@ struct Engine {
                 s.ap_alt[1]);
     }
     // level-set stage q (Shu-Osher coefficient a, step dt) from phin; the
-    // last stage of a step reinitialises.  Returns the new level set.
-    const double* ls_chain(int q, bool last, double a, double dt, const double* phin)
+    // last stage of a step reinitialises.  Returns the new level set.  With
+    // `commit`, the fused path leaves the reinitialised values in phiB[2],
+    // returns that buffer (read through phi_at it is the new level set) and
+    // sets *commit: the caller copies it to phiP on the band-mask cells.
+    const double* ls_chain(int q, bool last, double a, double dt, const double* phin,
+                           const double** commit = nullptr)
     {
+        if (commit) *commit = nullptr;
         if constexpr (D <= 2) {
             if (fused_ls()) {
                 int K = last ? s.o.reinit_iters : -1;
@@ -2124,6 +2185,7 @@ struct Engine {
                 std::swap(g.alpha, s.alpha_alt);
                 for (int d = 0; d < 3; d++) std::swap(g.ap[d], s.ap_alt[d]);
                 if (!last) return po;
+                if (commit) { *commit = po; return po; }
                 k_copy_masked<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, po, g.phiP);
                 return g.phiP;
             }
@@ -2200,6 +2262,22 @@ struct Engine {
             k_mixdelta<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, k, cons, cur);
         k_mixapply<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, cons);
     }
+    // 1-D/2-D: the band stage writes the inner tiles' output to Tm and one
+    // launch mixes it into the stage buffer, optionally together with a
+    // second mixed copy (the other fluid, or the slow fluid's interpolated
+    // state for the next stage) and the level-set commit
+    static constexpr bool fmix = D <= 2;
+    void mix_fused(const MixPart& A, const MixPart* B, const double* cur, const double* commit)
+    {
+        if constexpr (D <= 2)
+            k_mix_parts<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, A, B ? *B : A, B ? 2 : 1, cur,
+                                                                    commit, commit ? g.phiP : nullptr);
+    }
+    MixPart tm_part(int k, double* out) const
+    {
+        MixPart P = {k, 1.0, g.Tm[k], 0.0, nullptr, out, 1};
+        return P;
+    }
     void axpby(double a1, const double* s1, double a2, const double* s2, double* dst, int ncomp)
     {
         k_axpby<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, a1, s1, a2, s2, dst, ncomp);
@@ -2214,7 +2292,7 @@ struct Engine {
     // its halo); everything in between (extension, interaction, level set,
     // geometry, mixing) overlaps with the bulk stage on its side stream.
     void stage(int k, const double* in, const double* self2, const double* base, double* out, double a, double dt,
-               double wflux, int cfl = 0)
+               double wflux, int cfl = 0, double* tmp = nullptr)
     {
         int bl = k == 0 ? LIST_BULK0 : LIST_BULK1;
         const bool ov = s.side[k] != nullptr;
@@ -2231,7 +2309,7 @@ struct Engine {
             s.ev_used += 2;
             (void)hipEventRecord(s.ev_pool[ev], bs);
         }
-        launch_stage<false>(bs, bl, k, in, nullptr, base, out, a, dt, wflux, cfl);
+        launch_stage<false>(bs, bl, k, in, nullptr, base, out, a, dt, wflux, cfl, nullptr);
         if (s.prof) {
             (void)hipEventRecord(s.ev_pool[ev + 1], bs);
             // cells this launch advances by one stage; the first stage of a
@@ -2242,7 +2320,7 @@ struct Engine {
             (void)hipEventRecord(s.ev_bulk[k], bs);
             s.bulk_pending[k] = true;
         }
-        launch_stage<true>(s.stream, LIST_BAND, k, in, self2, base, out, a, dt, wflux, 0);
+        launch_stage<true>(s.stream, LIST_BAND, k, in, self2, base, out, a, dt, wflux, 0, tmp);
         if (ov) {
             (void)hipEventRecord(s.ev_band[k], s.stream);
             s.band_rec[k] = true;
@@ -2261,12 +2339,12 @@ struct Engine {
     bool fused_cfl = false;    // the last bulk stage already reduced the fast fluid's CFL speed
     template <bool BAND>
     void launch_stage(hipStream_t st, int list, int k, const double* in, const double* self2, const double* base,
-                      double* out, double a, double dt, double wflux, int cfl)
+                      double* out, double a, double dt, double wflux, int cfl, double* tmp)
     {
         dim3 gr = grid(list, 1, BAND ? 0 : s.bulk_blocks);
         if constexpr (D <= 2)
             k_stage_lds<D, BAND><<<gr, StageWG<D>::N, 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur,
-                                                               cfl);
+                                                               cfl, tmp);
         else
             k_stage<D, BAND><<<gr, wg(), 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
     }
@@ -2380,11 +2458,18 @@ struct Engine {
             double* out[2];
             for (int k = 0; k < 2; k++) {
                 out[k] = (st == ns - 1) ? g.X[k] : (st == 0 ? g.Y[k] : g.Z[k]);
-                stage(k, in[k], nullptr, g.X[k], out[k], A[st], dt, B[st] * dt);
+                stage(k, in[k], nullptr, g.X[k], out[k], A[st], dt, B[st] * dt, 0, fmix ? g.Tm[k] : nullptr);
             }
-            const double* cur = ls_chain(st, st == ns - 1, A[st], dt, phin);
-            mix(0, out[0], cur);
-            mix(1, out[1], cur);
+            const double* commit = nullptr;
+            const double* cur = ls_chain(st, st == ns - 1, A[st], dt, phin, fmix ? &commit : nullptr);
+            if (fmix) {
+                MixPart m1 = tm_part(1, out[1]);
+                mix_fused(tm_part(0, out[0]), &m1, cur, commit);
+                if (commit) cur = g.phiP;
+            } else {
+                mix(0, out[0], cur);
+                mix(1, out[1], cur);
+            }
             in[0] = out[0];
             in[1] = out[1];
             phin = cur;
@@ -2395,11 +2480,15 @@ struct Engine {
 
     // slow fluid's intermediate state, Eq. (interpolation), mixed with the
     // current geometry unless it is the (already mixed) previous state
+    MixPart interp_part(int S, double theta) const
+    {
+        MixPart P = {S, 1.0 - theta, g.X[S], theta, g.Y[S], g.T2, theta != 0.0};
+        return P;
+    }
     void interp_slow(int S, double theta, const double* cur)
     {
         if constexpr (D <= 2) {
-            k_mixinterp_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, S, 1.0 - theta, g.X[S], theta,
-                                                                        g.Y[S], g.T2, theta != 0.0, cur);
+            k_mixinterp_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, interp_part(S, theta), cur);
             return;
         }
         axpby(1.0 - theta, g.X[S], theta, g.Y[S], g.T2, NV);
@@ -2409,8 +2498,8 @@ struct Engine {
     void mixed_copy(int S, const double* src, const double* cur)
     {
         if constexpr (D <= 2) {
-            k_mixinterp_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, S, 1.0, src, 0.0, nullptr,
-                                                                        g.T2, 1, cur);
+            MixPart P = {S, 1.0, src, 0.0, nullptr, g.T2, 1};
+            k_mixinterp_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, P, cur);
             return;
         }
         axpby(1.0, src, 0.0, nullptr, g.T2, NV);
@@ -2486,7 +2575,7 @@ struct Engine {
                 bool shared = false;
                 if (q > 0) {
                     double theta = (fin && C[q] == 1.0) ? 1.0 : (tau + C[q] * dl) / t1;
-                    interp_slow(S, theta, phin);
+                    if (!fmix) interp_slow(S, theta, phin);   // else done with the previous stage's mixing
                     shared = fin && C[q] == 1.0;
                     double w = !corr ? 0.0 : (shared ? -B[q] * t1 + B[q] * dl : B[q] * dl);
                     interaction(S == 0 ? g.T2 : in, S == 0 ? in : g.T2, phin, w, S);
@@ -2498,9 +2587,23 @@ struct Engine {
                     stage(S, g.Y[S], g.T2, g.X[S], ns == 2 ? g.X[S] : g.Z[S], A[q], t1, B[q] * t1);
                 }
                 double* out = (q == ns - 1) ? g.X[F] : (q == 0 ? g.Y[F] : g.Z[F]);
-                stage(F, in, nullptr, g.X[F], out, A[q], dl, B[q] * dl, (q == ns - 1 && !fin) ? 1 : 0);
-                const double* cur = ls_chain(q, q == ns - 1, A[q], dl, phin);
-                mix(F, out, cur);
+                stage(F, in, nullptr, g.X[F], out, A[q], dl, B[q] * dl, (q == ns - 1 && !fin) ? 1 : 0,
+                      fmix ? g.Tm[F] : nullptr);
+                const double* commit = nullptr;
+                const double* cur = ls_chain(q, q == ns - 1, A[q], dl, phin, fmix ? &commit : nullptr);
+                if (fmix) {
+                    if (q + 1 < ns) {
+                        // the slow fluid's state for the next stage, Eq. (interpolation)
+                        double theta1 = (fin && C[q + 1] == 1.0) ? 1.0 : (tau + C[q + 1] * dl) / t1;
+                        MixPart ms = interp_part(S, theta1);
+                        mix_fused(tm_part(F, out), &ms, cur, commit);
+                    } else {
+                        mix_fused(tm_part(F, out), nullptr, cur, commit);
+                    }
+                    if (commit) cur = g.phiP;
+                } else {
+                    mix(F, out, cur);
+                }
                 in = out;
                 phin = cur;
             }
