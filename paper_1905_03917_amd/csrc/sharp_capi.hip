@@ -205,8 +205,11 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     A(g.M, (size_t)g.nc); A(g.nearif, (size_t)g.nc);
     A(g.tcore, (size_t)g.ntiles); A(g.tflag, (size_t)g.ntiles); A(g.tsign, (size_t)g.ntiles);
     A(g.lists, (size_t)NLISTS * g.ntiles);
-    A(g.counts, 16);
-    A(g.red, 8);
+    // reductions (8 words) and list counts (16 ints) share one block, read
+    // back with one copy; the counts, read by every grid-stride loop, sit
+    // 256 bytes away from the words the reductions update atomically
+    A(g.red, RED_WORDS);
+    if (rc == SIM_OK) g.counts = reinterpret_cast<int*>(g.red + RED_COUNTS);
 #undef A
     if (rc == SIM_OK) {
         std::vector<int> all(g.ntiles);
@@ -221,7 +224,7 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
             rc = SIM_EDEVICE;
         }
     }
-    if (rc == SIM_OK && hipHostMalloc((void**)&s.h_red, 16 * sizeof(unsigned long long)) != hipSuccess) {
+    if (rc == SIM_OK && hipHostMalloc((void**)&s.h_red, RED_WORDS * sizeof(unsigned long long)) != hipSuccess) {
         set_error("pinned host allocation failed");
         rc = SIM_ENOMEM;
     }

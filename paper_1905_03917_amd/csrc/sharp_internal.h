@@ -17,6 +17,11 @@
 
 namespace sharp {
 
+// layout of the reduction block (64-bit words): reductions at 0..7, the list
+// counts (16 ints) from word RED_COUNTS on
+constexpr int RED_COUNTS = 32;
+constexpr int RED_WORDS = RED_COUNTS + 8;
+
 struct Sim {
     Dev g;                 // device view (pointers live in device memory)
     sim_opts o;
@@ -39,7 +44,7 @@ struct Sim {
     double t = 0.0;
     int wcur = 0;          // Jacobi buffer holding the latest primitives
     int vcur = 0;          // Jacobi buffer holding the latest level-set velocity
-    unsigned long long* h_red = nullptr;  // pinned readback of the reductions
+    unsigned long long* h_red = nullptr;  // pinned readback of the reductions and list counts
     std::vector<void*> dev_allocs;
     // kernel timing of the bulk stage kernel
     bool prof = false;

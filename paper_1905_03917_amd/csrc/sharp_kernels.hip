@@ -2400,8 +2400,8 @@ struct Engine {
     // read back the reductions; fills dt and active-cell counts of the fluids in `which`
     sim_status readback(int which, double* dt, long long* cnt)
     {
-        SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s.stream));
-        SHARP_HIP(hipMemcpyAsync(s.h_red + 8, g.counts, 16 * sizeof(int), hipMemcpyDeviceToHost, s.stream));
+        SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, RED_WORDS * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                 s.stream));
         SHARP_HIP(hipStreamSynchronize(s.stream));
         take_counts();
         unsigned long long err = s.h_red[4];
@@ -2417,7 +2417,7 @@ struct Engine {
     }
     void take_counts()
     {
-        const int* cc = reinterpret_cast<const int*>(s.h_red + 8);
+        const int* cc = reinterpret_cast<const int*>(s.h_red + RED_COUNTS);
         for (int l = 0; l < 4; l++) s.lcount[l] = cc[l];
         s.lcount[LIST_INNER] = cc[LIST_INNER];
         s.lcount[LIST_ALL] = g.ntiles;
@@ -2579,8 +2579,6 @@ struct Engine {
                     shared = fin && C[q] == 1.0;
                     double w = !corr ? 0.0 : (shared ? -B[q] * t1 + B[q] * dl : B[q] * dl);
                     interaction(S == 0 ? g.T2 : in, S == 0 ? in : g.T2, phin, w, S);
-                } else if (!first && corr) {
-                    corr_add(B[0] * dl, S);   // Eq. (secondcorrection)
                 }
                 if (shared) {
                     // shared with the slow fluid's second stage, Eq. (firstcorrection)
@@ -2589,6 +2587,9 @@ struct Engine {
                 double* out = (q == ns - 1) ? g.X[F] : (q == 0 ? g.Y[F] : g.Z[F]);
                 stage(F, in, nullptr, g.X[F], out, A[q], dl, B[q] * dl, (q == ns - 1 && !fin) ? 1 : 0,
                       fmix ? g.Tm[F] : nullptr);
+                // Eq. (secondcorrection); booked after the stage launch (the stage does not
+                // read the correction) so that the GPU gets work soon after the readback
+                if (q == 0 && !first && corr) corr_add(B[0] * dl, S);
                 const double* commit = nullptr;
                 const double* cur = ls_chain(q, q == ns - 1, A[q], dl, phin, fmix ? &commit : nullptr);
                 if (fmix) {
@@ -2691,7 +2692,8 @@ struct Engine {
         for (int k = 0; k < 2; k++)
             SHARP_HIP(hipMemsetAsync(g.bacc[k], 0, sizeof(double) * NV * (size_t)(g.nbface > 0 ? g.nbface : 1), s.stream));
         SHARP_HIP(hipMemsetAsync(g.red, 0, 8 * sizeof(unsigned long long), s.stream));
-        SHARP_HIP(hipMemcpyAsync(s.h_red + 8, g.counts, 16 * sizeof(int), hipMemcpyDeviceToHost, s.stream));
+        SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, RED_WORDS * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                 s.stream));
         SHARP_HIP(hipStreamSynchronize(s.stream));
         SHARP_HIP(hipGetLastError());
         take_counts();
