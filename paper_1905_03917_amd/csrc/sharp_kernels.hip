@@ -42,6 +42,21 @@ __device__ __forceinline__ bool tile_cell(const Dev& g, int t, int tid, int& i, 
 __device__ __forceinline__ int list_count(const Dev& g, int list) { return g.counts[list]; }
 __device__ __forceinline__ const int* list_ptr(const Dev& g, int list) { return g.lists + (size_t)list * g.ntiles; }
 
+// XCD-aware assignment of list positions to the blocks of a grid-stride
+// loop.  Workgroup b runs on XCD b % 8, and each XCD has its own L2; giving
+// every XCD a contiguous range of the (row-major) tile list keeps tiles whose
+// halos overlap in the same L2.  Grids that are not a multiple of 8 use the
+// plain stride.
+struct ListRange { int begin, end, step; };
+__device__ __forceinline__ ListRange xcd_range(int count)
+{
+    const int G = gridDim.x;
+    if (G < 8 || (G & 7)) return {(int)blockIdx.x, count, G};
+    const int x = blockIdx.x & 7, j = blockIdx.x >> 3, chunk = (count + 7) >> 3;
+    const int b = x * chunk;
+    return {b + j, min(count, b + chunk), G >> 3};
+}
+
 __device__ __forceinline__ void flag_error(const Dev& g, unsigned long long bits)
 {
     atomicOr(&g.red[4], bits);
@@ -1372,7 +1387,8 @@ __global__ void __launch_bounds__(SHARP_WG) k_stage(Dev g, int list, int k, cons
     const int* L = list_ptr(g, list);
     const double gm = g.gam[k], pi = g.pinf[k];
     const double farea = D == 1 ? 1.0 : (D == 2 ? g.h : g.h * g.h);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    const ListRange lr = xcd_range(list_count(g, list));
+    for (int ti = lr.begin; ti < lr.end; ti += lr.step) {
         int t = L[ti];
         int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1], tz = t / (g.nt[0] * g.nt[1]);
         int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
@@ -1510,7 +1526,8 @@ __global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, in
     const double farea = D == 1 ? 1.0 : g.h;
     const double ih = 1.0 / g.h;
     const double eps4 = 4.0 * g.eps;
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    const ListRange lr = xcd_range(list_count(g, list));
+    for (int ti = lr.begin; ti < lr.end; ti += lr.step) {
         int t = L[ti];
         int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1];
         int ox = tx * TX, oy = ty * TY;
@@ -1663,7 +1680,7 @@ __global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, in
         __syncthreads();
     }
     if (!BAND && cfl) {
-        if (blockIdx.x >= list_count(g, list)) return;
+        if (lr.begin >= lr.end) return;   // idle block: nothing to reduce
         for (int off = 32; off > 0; off >>= 1) {
             cmax = fmax(cmax, __shfl_down(cmax, off, 64));
             ccnt += __shfl_down(ccnt, off, 64);
