@@ -50,6 +50,8 @@ static void release(Sim& s)
     s.ev_pool.clear();
     if (s.h_red) (void)hipHostFree(s.h_red);
     s.h_red = nullptr;
+    if (s.ev_rb) (void)hipEventDestroy(s.ev_rb);
+    s.ev_rb = nullptr;
     for (int k = 0; k < 2; k++) {
         if (s.side[k]) (void)hipStreamDestroy(s.side[k]);
         if (s.ev_band[k]) (void)hipEventDestroy(s.ev_band[k]);
@@ -209,7 +211,15 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     // back with one copy; the counts, read by every grid-stride loop, sit
     // 256 bytes away from the words the reductions update atomically
     A(g.red, RED_WORDS);
-    if (rc == SIM_OK) g.counts = reinterpret_cast<int*>(g.red + RED_COUNTS);
+    if (rc == SIM_OK) {
+        g.counts = reinterpret_cast<int*>(g.red + RED_COUNTS);
+        g.sched = reinterpret_cast<double*>(g.red + RED_SCHED);
+        g.use_sched = 0;
+    }
+    if (rc == SIM_OK && hipEventCreateWithFlags(&s.ev_rb, hipEventDisableTiming) != hipSuccess) {
+        set_error("event creation failed");
+        rc = SIM_EDEVICE;
+    }
 #undef A
     if (rc == SIM_OK) {
         std::vector<int> all(g.ntiles);

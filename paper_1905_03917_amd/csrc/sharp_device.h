@@ -62,7 +62,13 @@ struct Dev {
     int* counts;      // [16]: tiles per list (0..5), cells per list (8 + list, lists 0..3 and 5)
     // scalars
     unsigned long long* red;   // [0..1] max speed bits, [2..3] active counts, [4] error flags
+    // schedule of a fast sub-step planned on the device (SCHED_* slots); with
+    // use_sched set, the kernels of its first stage take dt and the weights
+    // from there instead of their arguments
+    double* sched;
+    int use_sched;
 };
+enum { SCHED_DT = 0, SCHED_W0 = 1, SCHED_TH1 = 2, SCHED_HH = 3, SCHED_FIN = 4, SCHED_DTF = 5, SCHED_CNT = 6 };
 
 // band: tiles within one tile of a band-mask tile; inner: band tiles all of
 // whose neighbours are band tiles (every band-mask cell of a cycle lies in

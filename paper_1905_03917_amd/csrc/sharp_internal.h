@@ -17,8 +17,10 @@
 
 namespace sharp {
 
-// layout of the reduction block (64-bit words): reductions at 0..7, the list
-// counts (16 ints) from word RED_COUNTS on
+// layout of the reduction block (64-bit words): reductions at 0..7, the
+// device-planned sub-step (doubles) from word RED_SCHED, the list counts
+// (16 ints) from word RED_COUNTS; each group on its own cache line
+constexpr int RED_SCHED = 16;
 constexpr int RED_COUNTS = 32;
 constexpr int RED_WORDS = RED_COUNTS + 8;
 
@@ -44,7 +46,8 @@ struct Sim {
     double t = 0.0;
     int wcur = 0;          // Jacobi buffer holding the latest primitives
     int vcur = 0;          // Jacobi buffer holding the latest level-set velocity
-    unsigned long long* h_red = nullptr;  // pinned readback of the reductions and list counts
+    unsigned long long* h_red = nullptr;  // pinned readback of the reduction block
+    hipEvent_t ev_rb = nullptr;           // readback of a device-planned sub-step
     std::vector<void*> dev_allocs;
     // kernel timing of the bulk stage kernel
     bool prof = false;

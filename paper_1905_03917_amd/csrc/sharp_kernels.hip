@@ -640,6 +640,7 @@ struct MixPart {
     const double* s2;
     double* dst;
     int do_mix;
+    int sched_theta;      // interpolation weight from the device plan: a1 = 1 - th, a2 = th
 };
 
 template <int D>
@@ -652,7 +653,14 @@ __device__ __forceinline__ void mix_tile(const Dev& g, int t, const MixPart& P, 
     constexpr int RX = MixRegion<D>::X, RY = MixRegion<D>::Y, RN = RX * RY;
     constexpr int HY = D == 2 ? 1 : 0;
     const int k = P.k;
-    const double a1 = P.a1, a2 = P.a2;
+    double a1 = P.a1, a2 = P.a2;
+    int do_mix = P.do_mix;
+    if (P.sched_theta) {
+        double th = g.sched[SCHED_TH1];
+        a1 = 1.0 - th;
+        a2 = th;
+        do_mix = th != 0.0;
+    }
     const double* s1 = P.s1;
     const double* s2 = P.s2;
     auto val = [&](int q, int c) {
@@ -660,7 +668,7 @@ __device__ __forceinline__ void mix_tile(const Dev& g, int t, const MixPart& P, 
         return s2 ? a1 * s1[e] + a2 * s2[e] : s1[e];
     };
     int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
-    if (P.do_mix) {
+    if (do_mix) {
         for (int r = threadIdx.x; r < RN; r += SHARP_WG) {
             int rx = r % RX, ry = r / RX;
             int c = cidx(g, ox - 1 + rx, oy - HY + ry, 0);
@@ -681,7 +689,7 @@ __device__ __forceinline__ void mix_tile(const Dev& g, int t, const MixPart& P, 
         int c = i + g.n[0] * j;
         double vc[NV], dl[NV];
         for (int q = 0; q < NV; q++) { vc[q] = val(q, c); dl[q] = 0.0; }
-        if (P.do_mix && g.M[c]) {
+        if (do_mix && g.M[c]) {
             int rc = (li + 1) + RX * (lj + HY);
             double ac = alpha_k(g, k, c);
             for (int m = 0; m < NS; m++) {
@@ -1253,6 +1261,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_interact(Dev g, int list, int wb, 
 template <int D>
 __global__ void __launch_bounds__(SHARP_WG) k_corr_add(Dev g, int list, double w, int S)
 {
+    if (g.use_sched) w = g.sched[SCHED_W0];
     const int* L = list_ptr(g, list);
     for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
         int i, j, kk;
@@ -1526,6 +1535,7 @@ __global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, in
     const double farea = D == 1 ? 1.0 : g.h;
     const double ih = 1.0 / g.h;
     const double eps4 = 4.0 * g.eps;
+    if (g.use_sched) { dt = g.sched[SCHED_DT]; wflux = g.sched[SCHED_W0]; }
     const ListRange lr = xcd_range(list_count(g, list));
     for (int ti = lr.begin; ti < lr.end; ti += lr.step) {
         int t = L[ti];
@@ -1840,6 +1850,7 @@ k_lsgeo_tb(Dev g, int list, int vin, int vout, int iters, const double* phin, do
     __shared__ double sV[GX * GY];
     const int* L = list_ptr(g, list);
     const bool last = K >= 0;
+    if (g.use_sched) dt = g.sched[SCHED_DT];
     for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
         int t = L[ti];
         int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
@@ -2119,9 +2130,13 @@ static void plan_cycle(double dt_slow, double dt_fast, double remaining, double 
     *single = !(d > dt_fast * (1.0 + 1e-12));
 }
 
-// next fast sub-step: stops exactly at t1 (and, for RK3, at t1/2)
-static double next_substep(double tau, double t1, double dt_fast, int rk, int half_done, int* hh, int* fin)
+// next fast sub-step: stops exactly at t1 (and, for RK3, at t1/2).  Shared
+// by the host and the device planner; no contraction, so both take the
+// decisions with the same operations.
+__host__ __device__ static double next_substep(double tau, double t1, double dt_fast, int rk, int half_done, int* hh,
+                                               int* fin)
 {
+#pragma clang fp contract(off)
     *hh = 0;
     *fin = 0;
     double half = 0.5 * t1;
@@ -2131,6 +2146,34 @@ static double next_substep(double tau, double t1, double dt_fast, int rk, int ha
     }
     if (tau + dt_fast * (1.0 + 1e-9) >= t1) { *fin = 1; return t1 - tau; }
     return dt_fast;
+}
+
+// Device planner of a fast sub-step, run right after its CFL reduction: the
+// fast fluid's dt from the reduced speed, the sub-step length (truncated at
+// t1/2 and t1), and the values the sub-step's first stage needs (dl, b_1 dl,
+// and the slow fluid's interpolation weight for the second stage).  The host
+// enqueues that first stage before it has read the plan back.
+__global__ void k_plan(Dev g, int F, double tau, double t1, int rk, int half_done, double cfl, double b0, double c1)
+{
+#pragma clang fp contract(off)
+    if (threadIdx.x != 0) return;
+    double m = __longlong_as_double((long long)g.red[F]);
+    unsigned long long cnt = g.red[2 + F];
+    double dtf = (cnt > 0 && m > 0.0) ? cfl / m : INFINITY;
+    int hh = 0, fin = 0;
+    double dl = NAN, th1 = NAN;
+    if (isfinite(dtf) && dtf > 0.0) {
+        dl = next_substep(tau, t1, dtf, rk, half_done, &hh, &fin);
+        th1 = (fin && c1 == 1.0) ? 1.0 : (tau + c1 * dl) / t1;
+    }
+    double* sc = g.sched;
+    sc[SCHED_DT] = dl;
+    sc[SCHED_W0] = b0 * dl;
+    sc[SCHED_TH1] = th1;
+    sc[SCHED_HH] = hh;
+    sc[SCHED_FIN] = fin;
+    sc[SCHED_DTF] = dtf;
+    sc[SCHED_CNT] = (double)cnt;
 }
 
 template <int D>
@@ -2292,7 +2335,7 @@ struct Engine {
     }
     MixPart tm_part(int k, double* out) const
     {
-        MixPart P = {k, 1.0, g.Tm[k], 0.0, nullptr, out, 1};
+        MixPart P = {k, 1.0, g.Tm[k], 0.0, nullptr, out, 1, 0};
         return P;
     }
     void axpby(double a1, const double* s1, double a2, const double* s2, double* dst, int ncomp)
@@ -2316,6 +2359,12 @@ struct Engine {
         hipStream_t bs = ov ? s.side[k] : s.stream;
         if (ov) {
             if (s.bulk_pending[k]) (void)hipStreamWaitEvent(s.stream, s.ev_bulk[k], 0);
+            if (g.use_sched) {
+                // a planned stage: the bulk kernel reads its step from the plan,
+                // so it also waits for everything enqueued so far (the planner)
+                (void)hipEventRecord(s.ev_band[k], s.stream);
+                s.band_rec[k] = true;
+            }
             if (s.band_rec[k]) (void)hipStreamWaitEvent(bs, s.ev_band[k], 0);
         }
         if (cfl) k_zero_red<<<1, 64, 0, bs>>>(g);
@@ -2415,15 +2464,22 @@ struct Engine {
         k_cfl<D, true><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, s.wcur);
     }
     // read back the reductions; fills dt and active-cell counts of the fluids in `which`
+    // list counts and error flags of a completed readback
+    sim_status check_flags()
+    {
+        take_counts();
+        unsigned long long err = s.h_red[4];
+        if (err & ERR_NONPHYS) { set_error("non-physical state (rho <= 0, p + p_inf <= 0 or NaN)"); return SIM_ENONPHYS; }
+        if (err & ERR_BAND_OVERFLOW) { set_error("the interface band moved more than one tile within a cycle"); return SIM_EDEVICE; }
+        return SIM_OK;
+    }
     sim_status readback(int which, double* dt, long long* cnt)
     {
         SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, RED_WORDS * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                  s.stream));
         SHARP_HIP(hipStreamSynchronize(s.stream));
-        take_counts();
-        unsigned long long err = s.h_red[4];
-        if (err & ERR_NONPHYS) { set_error("non-physical state (rho <= 0, p + p_inf <= 0 or NaN)"); return SIM_ENONPHYS; }
-        if (err & ERR_BAND_OVERFLOW) { set_error("the interface band moved more than one tile within a cycle"); return SIM_EDEVICE; }
+        sim_status rc = check_flags();
+        if (rc != SIM_OK) return rc;
         for (int k = 0; k < 2; k++) {
             if (!(which & (1 << k))) continue;
             double m = __longlong_as_double_host(s.h_red[k]);
@@ -2499,7 +2555,7 @@ struct Engine {
     // current geometry unless it is the (already mixed) previous state
     MixPart interp_part(int S, double theta) const
     {
-        MixPart P = {S, 1.0 - theta, g.X[S], theta, g.Y[S], g.T2, theta != 0.0};
+        MixPart P = {S, 1.0 - theta, g.X[S], theta, g.Y[S], g.T2, theta != 0.0, 0};
         return P;
     }
     void interp_slow(int S, double theta, const double* cur)
@@ -2515,7 +2571,7 @@ struct Engine {
     void mixed_copy(int S, const double* src, const double* cur)
     {
         if constexpr (D <= 2) {
-            MixPart P = {S, 1.0, src, 0.0, nullptr, g.T2, 1};
+            MixPart P = {S, 1.0, src, 0.0, nullptr, g.T2, 1, 0};
             k_mixinterp_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, P, cur);
             return;
         }
@@ -2558,10 +2614,57 @@ struct Engine {
         double tau = 0.0, dtF = dt[F];
         int first = 1, half_done = 0;
         long long cntF = cnt[F];
+        // One stage q of a fast sub-step of length dl.  With `planned` (the
+        // first stage of a sub-step planned on the device), dl, b_1 dl and the
+        // next interpolation weight are read by the kernels from the device
+        // plan (Dev::use_sched) and the host arguments are placeholders.
+        auto fast_stage = [&](int q, const double*& in, const double*& phin, double dl, int fin, bool planned) {
+            bool shared = false;
+            if (q > 0) {
+                double theta = (fin && C[q] == 1.0) ? 1.0 : (tau + C[q] * dl) / t1;
+                if (!fmix) interp_slow(S, theta, phin);   // else done with the previous stage's mixing
+                shared = fin && C[q] == 1.0;
+                double w = !corr ? 0.0 : (shared ? -B[q] * t1 + B[q] * dl : B[q] * dl);
+                interaction(S == 0 ? g.T2 : in, S == 0 ? in : g.T2, phin, w, S);
+            }
+            if (shared) {
+                // shared with the slow fluid's second stage, Eq. (firstcorrection)
+                stage(S, g.Y[S], g.T2, g.X[S], ns == 2 ? g.X[S] : g.Z[S], A[q], t1, B[q] * t1);
+            }
+            double* out = (q == ns - 1) ? g.X[F] : (q == 0 ? g.Y[F] : g.Z[F]);
+            stage(F, in, nullptr, g.X[F], out, A[q], dl, B[q] * dl, (q == ns - 1 && !fin) ? 1 : 0,
+                  fmix ? g.Tm[F] : nullptr);
+            // Eq. (secondcorrection); booked after the stage launch (the stage does not
+            // read the correction) so that the GPU gets work soon after the readback
+            if (q == 0 && !first && corr) corr_add(B[0] * dl, S);
+            const double* commit = nullptr;
+            const double* cur = ls_chain(q, q == ns - 1, A[q], dl, phin, fmix ? &commit : nullptr);
+            if (fmix) {
+                if (q + 1 < ns) {
+                    // the slow fluid's state for the next stage, Eq. (interpolation)
+                    double theta1 = (fin && C[q + 1] == 1.0) ? 1.0 : (tau + C[q + 1] * dl) / t1;
+                    MixPart ms = interp_part(S, theta1);
+                    ms.sched_theta = planned ? 1 : 0;
+                    mix_fused(tm_part(F, out), &ms, cur, commit);
+                } else {
+                    mix_fused(tm_part(F, out), nullptr, cur, commit);
+                }
+                if (commit) cur = g.phiP;
+            } else {
+                mix(F, out, cur);
+            }
+            in = out;
+            phin = cur;
+        };
+        // sub-steps after the first are planned on the device when every
+        // kernel of a stage can take its step from there
+        const bool plan_dev = fmix && fused_ls();
         for (;;) {
+            int hh = 0, fin = 0, q0 = 0;
+            double dl = 0.0;
+            const double* in = g.X[F];
+            const double* phin = g.phiP;
             if (!first) {
-                double d2[2];
-                long long c2[2];
                 mask(LIST_BAND, 1);
                 interp_slow(S, tau / t1, g.phiP);
                 interaction(S == 0 ? g.T2 : g.X[F], S == 0 ? g.X[F] : g.T2, g.phiP, 0.0, S);
@@ -2574,57 +2677,44 @@ struct Engine {
                     cfl_launch(F, g.X[F]);
                 }
                 fused_cfl = false;
-                sim_status rc = readback(1 << F, d2, c2);
-                if (rc != SIM_OK) return rc;
-                dtF = d2[F];
-                cntF = c2[F];
+                if (plan_dev) {
+                    // plan on the device, read the plan back, and enqueue the
+                    // first stage before waiting for it
+                    k_plan<<<1, 64, 0, s.stream>>>(g, F, tau, t1, ns, half_done, s.o.cfl, B[0], C[1]);
+                    SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, RED_WORDS * sizeof(unsigned long long),
+                                             hipMemcpyDeviceToHost, s.stream));
+                    SHARP_HIP(hipEventRecord(s.ev_rb, s.stream));
+                    g.use_sched = 1;
+                    fast_stage(0, in, phin, 0.0, 0, true);
+                    g.use_sched = 0;
+                    SHARP_HIP(hipEventSynchronize(s.ev_rb));
+                    sim_status rc = check_flags();
+                    if (rc != SIM_OK) return rc;
+                    const double* sc = reinterpret_cast<const double*>(s.h_red + RED_SCHED);
+                    dtF = sc[SCHED_DTF];
+                    cntF = (long long)sc[SCHED_CNT];
+                    dl = sc[SCHED_DT];
+                    hh = sc[SCHED_HH] != 0.0;
+                    fin = sc[SCHED_FIN] != 0.0;
+                    q0 = 1;
+                } else {
+                    double d2[2];
+                    long long c2[2];
+                    sim_status rc = readback(1 << F, d2, c2);
+                    if (rc != SIM_OK) return rc;
+                    dtF = d2[F];
+                    cntF = c2[F];
+                }
                 if (!std::isfinite(dtF) || !(dtF > 0.0)) {
                     set_error("invalid fast-fluid time step");
                     return SIM_ENONPHYS;
                 }
             }
-            int hh, fin;
-            double dl = next_substep(tau, t1, dtF, ns, half_done, &hh, &fin);
-            if (first && corr) corr_add(-B[0] * t1 + B[0] * dl, S);
-            const double* in = g.X[F];
-            const double* phin = g.phiP;
-            for (int q = 0; q < ns; q++) {
-                bool shared = false;
-                if (q > 0) {
-                    double theta = (fin && C[q] == 1.0) ? 1.0 : (tau + C[q] * dl) / t1;
-                    if (!fmix) interp_slow(S, theta, phin);   // else done with the previous stage's mixing
-                    shared = fin && C[q] == 1.0;
-                    double w = !corr ? 0.0 : (shared ? -B[q] * t1 + B[q] * dl : B[q] * dl);
-                    interaction(S == 0 ? g.T2 : in, S == 0 ? in : g.T2, phin, w, S);
-                }
-                if (shared) {
-                    // shared with the slow fluid's second stage, Eq. (firstcorrection)
-                    stage(S, g.Y[S], g.T2, g.X[S], ns == 2 ? g.X[S] : g.Z[S], A[q], t1, B[q] * t1);
-                }
-                double* out = (q == ns - 1) ? g.X[F] : (q == 0 ? g.Y[F] : g.Z[F]);
-                stage(F, in, nullptr, g.X[F], out, A[q], dl, B[q] * dl, (q == ns - 1 && !fin) ? 1 : 0,
-                      fmix ? g.Tm[F] : nullptr);
-                // Eq. (secondcorrection); booked after the stage launch (the stage does not
-                // read the correction) so that the GPU gets work soon after the readback
-                if (q == 0 && !first && corr) corr_add(B[0] * dl, S);
-                const double* commit = nullptr;
-                const double* cur = ls_chain(q, q == ns - 1, A[q], dl, phin, fmix ? &commit : nullptr);
-                if (fmix) {
-                    if (q + 1 < ns) {
-                        // the slow fluid's state for the next stage, Eq. (interpolation)
-                        double theta1 = (fin && C[q + 1] == 1.0) ? 1.0 : (tau + C[q + 1] * dl) / t1;
-                        MixPart ms = interp_part(S, theta1);
-                        mix_fused(tm_part(F, out), &ms, cur, commit);
-                    } else {
-                        mix_fused(tm_part(F, out), nullptr, cur, commit);
-                    }
-                    if (commit) cur = g.phiP;
-                } else {
-                    mix(F, out, cur);
-                }
-                in = out;
-                phin = cur;
+            if (q0 == 0) {
+                dl = next_substep(tau, t1, dtF, ns, half_done, &hh, &fin);
+                if (first && corr) corr_add(-B[0] * t1 + B[0] * dl, S);
             }
+            for (int q = q0; q < ns; q++) fast_stage(q, in, phin, dl, fin, false);
             st->steps[F]++;
             st->cell_updates[F] += cntF;
             tau = hh ? 0.5 * t1 : (fin ? t1 : tau + dl);
