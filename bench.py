@@ -42,6 +42,7 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--no-l1", action="store_true", help="skip the matched-L1 comparison on the 1-D tube ladder")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -140,6 +141,108 @@ def measured_traffic():
     if rec.get("source_sha256") != source_digest():
         return None
     return rec.get("traffic_bytes_per_launch")
+
+
+def exact_tube_1d(case, x, t):
+    """Exact solution (rho, u, p) at points x and time t of the 1-D two-fluid
+    stiffened-gas Riemann problem posed by a tube_1d case (the reference of
+    the matched-L1 comparison): p* from f_L(p) + f_R(p) + u_R - u_L = 0 by
+    bisection on the increasing function f, then the wave pattern sampled
+    at x/t."""
+    import numpy as np
+    g, pi = case["gamma"], case["pinf"]
+    sides = [(case["prim"][0, 0, 0], case["prim"][0, 1, 0], case["prim"][0, 2, 0], g[0], pi[0]),
+             (case["prim"][1, 0, -1], case["prim"][1, 1, -1], case["prim"][1, 2, -1], g[1], pi[1])]
+
+    def f(side, p):
+        r, u, pk, gm, pinf = side
+        a = pk + pinf
+        if p > pk:   # shock
+            A, B = 2.0 / ((gm + 1.0) * r), (gm - 1.0) / (gm + 1.0) * a
+            return (p - pk) * np.sqrt(A / (p + pinf + B))
+        c = np.sqrt(gm * a / r)
+        return 2.0 * c / (gm - 1.0) * (((p + pinf) / a) ** ((gm - 1.0) / (2.0 * gm)) - 1.0)
+
+    L, R = sides
+    du = R[1] - L[1]
+    lo, hi = -min(L[4], R[4]) + 1e-12, max(L[2], R[2]) * 10.0
+    for _ in range(200):
+        mid = 0.5 * (lo + hi)
+        if f(L, mid) + f(R, mid) + du > 0.0:
+            hi = mid
+        else:
+            lo = mid
+    ps = 0.5 * (lo + hi)
+    us = 0.5 * (L[1] + R[1]) + 0.5 * (f(R, ps) - f(L, ps))
+    out = np.empty((len(x), 3))
+    for i, xx in enumerate(x):
+        xi = (xx - case["x_interface"]) / t
+        left = xi <= us
+        r, u, pk, gm, pinf = L if left else R
+        sgn = -1.0 if left else 1.0
+        a = pk + pinf
+        c = np.sqrt(gm * a / r)
+        if ps > pk:   # shock
+            m = (gm - 1.0) / (gm + 1.0)
+            rs = r * ((ps + pinf) / a + m) / (m * (ps + pinf) / a + 1.0)
+            shock = u + sgn * c * np.sqrt((gm + 1.0) / (2.0 * gm) * (ps + pinf) / a + (gm - 1.0) / (2.0 * gm))
+            out[i] = (rs, us, ps) if sgn * (xi - shock) < 0.0 else (r, u, pk)
+        else:          # rarefaction
+            rs = r * ((ps + pinf) / a) ** (1.0 / gm)
+            cs = np.sqrt(gm * (ps + pinf) / rs)
+            head, tail = u + sgn * c, us + sgn * cs
+            if sgn * (xi - head) >= 0.0:
+                out[i] = (r, u, pk)
+            elif sgn * (xi - tail) <= 0.0:
+                out[i] = (rs, us, ps)
+            else:
+                uf = 2.0 / (gm + 1.0) * (-sgn * c + (gm - 1.0) / 2.0 * u + xi)
+                cf = -sgn * (uf - xi)
+                rf = r * (cf / c) ** (2.0 / (gm - 1.0))
+                pf = a * (cf / c) ** (2.0 * gm / (gm - 1.0)) - pinf
+                out[i] = (rf, uf, pf)
+    return out
+
+
+def matched_l1(P, WL, ladder=(400, 800, 1600, 3200, 6400)):
+    """The 1-D gas-water tube over a resolution ladder in both modes: GPU time
+    to t_end and the relative L1 error of the density against the exact
+    solution on x in [0.25, 1]; then the time of the original method
+    divided by the accelerated cycle's at equal error (log-log interpolation
+    of time against error along each mode's ladder)."""
+    import numpy as np
+    import torch
+    rows = {0: [], 1: []}
+    for n in ladder:
+        case = WL.tube_1d(n=n, seed=0)
+        x = (np.arange(n) + 0.5) / n
+        ex = exact_tube_1d(case, x, case["t_end"])
+        sel = x >= 0.25
+        for mode in (0, 1):
+            sim = P.Sim(case)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = sim.advance(case["t_end"], mode=mode)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            _, cons, alpha = sim.state(device=False)
+            a0 = alpha
+            rho = np.where(a0 >= 0.5, cons[0, 0] / np.maximum(a0, 1e-300), cons[1, 0] / np.maximum(1.0 - a0, 1e-300))
+            l1 = np.abs(rho - ex[:, 0])[sel].sum() / np.abs(ex[:, 0])[sel].sum()
+            rows[mode].append(dict(n=n, seconds=el, l1_rho=l1, cycles=st["cycles"]))
+            sim.close()
+    ratios = []
+    ls = np.log([r["l1_rho"] for r in rows[0]])
+    ts = np.log([r["seconds"] for r in rows[0]])
+    order = np.argsort(ls)
+    for r in rows[1]:
+        l = np.log(r["l1_rho"])
+        if ls.min() <= l <= ls.max():
+            ratios.append(float(np.exp(np.interp(l, ls[order], ts[order])) / r["seconds"]))
+    return dict(workload="tube_1d ladder %s, t_end 2.2e-4 s" % list(ladder),
+                single_dt=rows[0], multi_dt=rows[1],
+                time_ratio_single_over_multi_at_matched_l1=ratios,
+                geomean=float(np.exp(np.mean(np.log(ratios)))) if ratios else None)
 
 
 def cpu_baseline(case_fn, seconds):
@@ -241,6 +344,11 @@ def main():
                 algorithmic_bytes_per_launch=round(bytes_k / max(launches, 1)),
                 hbm=dict(achieved=round(ach_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                          frac=round(ach_gbs / HBM_PEAK_GBS, 4)))
+    ml1 = None
+    if not a.no_l1:
+        ml1 = matched_l1(P, WL)
+        print("bench: matched L1 (1-D tube ladder): single/multi time ratios %s"
+              % ml1["time_ratio_single_over_multi_at_matched_l1"], flush=True)
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(WL.shock_bubble_2d, a.cpu_seconds)
@@ -263,6 +371,7 @@ def main():
                       "water_cell_updates_per_s": st["cell_updates"][1] / el,
                       "steps": st["steps"]},
         "single_dt": single,
+        "matched_l1": ml1,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -64,14 +64,19 @@ __device__ __forceinline__ void flag_error(const Dev& g, unsigned long long bits
 
 // ---------------------------------------------------------------------------
 // band mask: a cell is in the band when it or an axis neighbour is closer
-// than ls_band cells to the interface; marks tiles holding band cells
+// than ls_band cells to the interface.  A tile is marked as a core tile when
+// a cell is within ls_band + 2 cells.  The level set changes only on inner
+// tiles, so a cell of a ring tile can join the band only through its inner
+// neighbour, whose |phi| must then fall by the margin within one cycle; the
+// interface moves by about CFL < 1 cell per cycle, so two cells keep the
+// band off the ring tiles however close to a tile edge it starts.
 // ---------------------------------------------------------------------------
 template <int D>
 __global__ void __launch_bounds__(SHARP_WG) k_mask(Dev g, int list, int check_ring)
 {
     __shared__ int any;
     const int* L = list_ptr(g, list);
-    double R = g.lsb * g.h;
+    const double R = g.lsb * g.h, Rc = (g.lsb + 2.0) * g.h;
     for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
         int t = L[ti];
         if (threadIdx.x == 0) any = 0;
@@ -87,10 +92,8 @@ __global__ void __launch_bounds__(SHARP_WG) k_mask(Dev g, int list, int check_ri
             }
             uint8_t in = m < R;
             g.M[c] = in;
-            if (in) {
-                any = 1;
-                if (check_ring && (g.tflag[t] & 4)) flag_error(g, ERR_BAND_OVERFLOW);
-            }
+            if (m < Rc) any = 1;
+            if (in && check_ring && (g.tflag[t] & 4)) flag_error(g, ERR_BAND_OVERFLOW);
         }
         __syncthreads();
         if (threadIdx.x == 0) g.tcore[t] = any;
@@ -2469,8 +2472,8 @@ struct Engine {
     {
         take_counts();
         unsigned long long err = s.h_red[4];
+        if (err & ERR_BAND_OVERFLOW) { set_error("the interface band left its tile set within a cycle"); return SIM_EDEVICE; }
         if (err & ERR_NONPHYS) { set_error("non-physical state (rho <= 0, p + p_inf <= 0 or NaN)"); return SIM_ENONPHYS; }
-        if (err & ERR_BAND_OVERFLOW) { set_error("the interface band moved more than one tile within a cycle"); return SIM_EDEVICE; }
         return SIM_OK;
     }
     sim_status readback(int which, double* dt, long long* cnt)

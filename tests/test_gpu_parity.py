@@ -76,6 +76,33 @@ def test_tube_1d_full_run_l1(mode):
     _compare(c, mode, 0, t_end=c["t_end"], tol=1e-8, l1=True)
 
 
+@pytest.mark.parametrize("mode", [0, 1])
+def test_tube_1d_fine_run_to_end(mode):
+    """6400 cells to t_end (about 2000 accelerated cycles): the band never
+    leaves the tiles classified at a cycle start, mass is conserved, and the
+    density is close to the exact two-material Riemann solution (relative L1
+    of the oracle at this resolution: 2.0e-4 to 2.1e-4)."""
+    from oracle import oracle as O
+    c = WL.tube_1d(n=6400, seed=0)
+    print("fine tube case n=6400 mode=%d" % mode, flush=True)
+    g = _gpu(c)
+    tot0 = g.totals()
+    st = g.advance(c["t_end"], mode=mode)
+    assert st["t"] == pytest.approx(c["t_end"], rel=1e-14)
+    tot1 = g.totals()
+    steps = max(st["steps"])
+    mass = np.abs(tot1[:, 0] - tot0[:, 0] - st["bflux"][:, 0]) / np.abs(tot0[:, 0])
+    assert np.all(mass <= 1e-12 * steps), mass
+    _, cons, alpha = g.state(device=False)
+    x = (np.arange(6400) + 0.5) / 6400
+    ex = O.exact_tube(c, x, c["t_end"])[:, 0]
+    rho = np.where(alpha >= 0.5, cons[0, 0] / np.maximum(alpha, 1e-300),
+                   cons[1, 0] / np.maximum(1 - alpha, 1e-300))
+    sel = x >= 0.25
+    l1 = np.abs(rho - ex)[sel].sum() / np.abs(ex)[sel].sum()
+    assert l1 < 3e-4, l1
+
+
 @pytest.mark.parametrize("rk", [2, 3])
 @pytest.mark.parametrize("mode", [0, 1])
 @pytest.mark.parametrize("n", [64, 50])
