@@ -120,10 +120,10 @@ def reduce_counters(fetch_dir, write_dir):
     rec = dict(kernel="k_stage_lds<2, false>", workload="shock_bubble_2d 1024x1024 multi_dt",
                source_sha256=source_digest(), sources=KERNEL_SOURCES, counters=out,
                traffic_bytes_per_launch=traffic,
-               commands=["timeout -s KILL 60 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <FETCH_DIR> -o run "
-                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --copy-probe",
-                         "timeout -s KILL 60 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <WRITE_DIR> -o run "
-                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --copy-probe",
+               commands=["timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <FETCH_DIR> -o run "
+                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --copy-probe",
+                         "timeout -s KILL 150 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <WRITE_DIR> -o run "
+                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --copy-probe",
                          "python bench.py --reduce-counters <FETCH_DIR> <WRITE_DIR>"])
     with open(COUNTERS, "w") as fh:
         json.dump(rec, fh, indent=1)

@@ -19,6 +19,8 @@
 #include <cstring>
 #include <utility>
 
+#include <hip/hip_ext.h>
+
 #include "sharp_internal.h"
 
 namespace sharp {
@@ -2376,11 +2378,10 @@ struct Engine {
             if (s.ev_used + 2 > s.ev_pool.size()) profile_flush();
             ev = s.ev_used;
             s.ev_used += 2;
-            (void)hipEventRecord(s.ev_pool[ev], bs);
         }
-        launch_stage<false>(bs, bl, k, in, nullptr, base, out, a, dt, wflux, cfl, nullptr);
+        launch_stage<false>(bs, bl, k, in, nullptr, base, out, a, dt, wflux, cfl, nullptr,
+                            s.prof ? s.ev_pool[ev] : nullptr, s.prof ? s.ev_pool[ev + 1] : nullptr);
         if (s.prof) {
-            (void)hipEventRecord(s.ev_pool[ev + 1], bs);
             // cells this launch advances by one stage; the first stage of a
             // step (a == 0) reads no base state
             s.prof_cells.push_back(a == 0.0 ? -s.bulk_cells[k] : s.bulk_cells[k]);
@@ -2407,15 +2408,19 @@ struct Engine {
     }
     bool fused_cfl = false;    // the last bulk stage already reduced the fast fluid's CFL speed
     template <bool BAND>
+    // e0, e1 (optional): events stamped by the dispatch itself at the start
+    // and end of the kernel's execution
     void launch_stage(hipStream_t st, int list, int k, const double* in, const double* self2, const double* base,
-                      double* out, double a, double dt, double wflux, int cfl, double* tmp)
+                      double* out, double a, double dt, double wflux, int cfl, double* tmp,
+                      hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
     {
         dim3 gr = grid(list, 1, BAND ? 0 : s.bulk_blocks);
         if constexpr (D <= 2)
-            k_stage_lds<D, BAND><<<gr, StageWG<D>::N, 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur,
-                                                               cfl, tmp);
+            hipExtLaunchKernelGGL(k_stage_lds<D, BAND>, gr, dim3(StageWG<D>::N), 0, st, e0, e1, 0, g, list, k, in,
+                                  self2, base, out, a, dt, wflux, s.wcur, cfl, tmp);
         else
-            k_stage<D, BAND><<<gr, wg(), 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur);
+            hipExtLaunchKernelGGL(k_stage<D, BAND>, gr, dim3(wg()), 0, st, e0, e1, 0, g, list, k, in, self2, base,
+                                  out, a, dt, wflux, s.wcur);
     }
     void profile_flush()
     {
