@@ -481,149 +481,122 @@ __device__ __forceinline__ bool mix_source(const Dev& g, const double* cur, int 
     return true;
 }
 
+// LDS variant: the source data (weights and targets) of every cell of the
+// tile and its one-cell halo is computed once, then gathered.
+template <int D> struct MixRegion;
+template <> struct MixRegion<1> { static constexpr int X = 256 + 2, Y = 1, Z = 1, N = X; };
+template <> struct MixRegion<2> { static constexpr int X = 16 + 2, Y = 16 + 2, Z = 1, N = X * Y; };
+template <> struct MixRegion<3> { static constexpr int X = 8 + 2, Y = 8 + 2, Z = 4 + 2, N = X * Y * Z; };
+
+// tile t's origin and the cell of thread `tid` (local coordinates)
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_mixdelta(Dev g, int list, int k, const double* cons, const double* cur)
+__device__ __forceinline__ void tile_origin(const Dev& g, int t, int& ox, int& oy, int& oz)
+{
+    ox = (t % g.nt[0]) * Tile<D>::X;
+    oy = D >= 2 ? ((t / g.nt[0]) % g.nt[1]) * Tile<D>::Y : 0;
+    oz = D == 3 ? (t / (g.nt[0] * g.nt[1])) * Tile<D>::Z : 0;
+}
+
+// Mixing increment of cell c (local coordinates li, lj, lk in the tile) from
+// the sources tabulated for the tile's region: c as a source, then c as a
+// target of each distinct neighbour (z, y, x order).  val(q, cell) gives the
+// pre-mixing values.
+template <int D, typename Val>
+__device__ __forceinline__ void mix_gather(const Dev& g, int k, int c, int i, int j, int kk, int li, int lj, int lk,
+                                           const double* sBeta, const int* sTgt, const int* sCell, Val val,
+                                           const double* vc, double* dl)
 {
     constexpr int NV = D + 2;
     constexpr int NS = (1 << D) - 1;
-    const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
-        int i, j, kk;
-        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
-        int c = i + g.n[0] * (j + g.n[1] * kk);
-        if (!g.M[c]) continue;
-        double dl[NV];
-        for (int q = 0; q < NV; q++) dl[q] = 0.0;
-        double beta[7];
-        int tgt[7];
-        double ac = alpha_k(g, k, c);
-        // c as a source
-        if (mix_source<D>(g, cur, k, c, beta, tgt)) {
-            for (int m = 0; m < NS; m++) {
-                int t = tgt[m];
-                if (!(beta[m] > 0.0) || t == c) continue;
-                double at = alpha_k(g, k, t);
-                if (!(ac + at > 0.0)) continue;
-                for (int q = 0; q < NV; q++)
-                    dl[q] += beta[m] * (cons[(size_t)q * g.nc + t] * ac - cons[(size_t)q * g.nc + c] * at) / (ac + at);
-            }
-        }
-        // c as a target of its neighbours (distinct neighbour cells only)
-        int seen[26];
-        int ns = 0;
-        bool edge = false;
-        {
-            int ii[3] = {i, j, kk};
-            for (int d = 0; d < D; d++)
-                if (ii[d] == 0 || ii[d] == g.n[d] - 1) edge = true;
-        }
-        int rz = D > 2 ? 1 : 0, ry = D > 1 ? 1 : 0;
-        for (int oz = -rz; oz <= rz; oz++)
-            for (int oy = -ry; oy <= ry; oy++)
-                for (int ox = -1; ox <= 1; ox++) {
-                    if (!ox && !oy && !oz) continue;
-                    int s = cidx(g, i + ox, j + oy, kk + oz);
-                    if (s == c) continue;
-                    if (edge) {
-                        bool dup = false;
-                        for (int u = 0; u < ns; u++) dup |= (seen[u] == s);
-                        if (dup) continue;
-                        seen[ns++] = s;
-                    }
-                    if (!mix_source<D>(g, cur, k, s, beta, tgt)) continue;
-                    double as = alpha_k(g, k, s);
-                    if (!(as + ac > 0.0)) continue;
-                    for (int m = 0; m < NS; m++) {
-                        if (tgt[m] != c || !(beta[m] > 0.0)) continue;
-                        for (int q = 0; q < NV; q++)
-                            dl[q] -= beta[m] * (cons[(size_t)q * g.nc + c] * as - cons[(size_t)q * g.nc + s] * ac) / (as + ac);
-                    }
-                }
-        for (int q = 0; q < NV; q++) g.dmix[(size_t)q * g.nc + c] = dl[q];
+    constexpr int RX = MixRegion<D>::X, RY = MixRegion<D>::Y, RN = MixRegion<D>::N;
+    constexpr int HY = D >= 2 ? 1 : 0, HZ = D == 3 ? 1 : 0;
+    const int rc = (li + 1) + RX * ((lj + HY) + RY * (lk + HZ));
+    double ac = alpha_k(g, k, c);
+    for (int m = 0; m < NS; m++) {
+        int tt = sTgt[m * RN + rc];
+        double b = sBeta[m * RN + rc];
+        if (tt < 0 || !(b > 0.0) || tt == c) continue;
+        double at = alpha_k(g, k, tt);
+        if (!(ac + at > 0.0)) continue;
+        for (int q = 0; q < NV; q++) dl[q] += b * (val(q, tt) * ac - vc[q] * at) / (ac + at);
     }
+    bool edge = i == 0 || i == g.n[0] - 1 || (D >= 2 && (j == 0 || j == g.n[1] - 1)) ||
+                (D == 3 && (kk == 0 || kk == g.n[2] - 1));
+    int seen[26];
+    int ns = 0;
+    for (int oz2 = -HZ; oz2 <= HZ; oz2++)
+        for (int oy2 = -HY; oy2 <= HY; oy2++)
+            for (int ox2 = -1; ox2 <= 1; ox2++) {
+                if (!ox2 && !oy2 && !oz2) continue;
+                int rs = rc + ox2 + RX * (oy2 + RY * oz2);
+                int sc = sCell[rs];
+                if (sc == c) continue;
+                if (edge) {
+                    bool dup = false;
+                    for (int u = 0; u < ns; u++) dup |= (seen[u] == sc);
+                    if (dup) continue;
+                    seen[ns++] = sc;
+                }
+                if (sTgt[rs] < 0) continue;     // not a source
+                double as = alpha_k(g, k, sc);
+                if (!(as + ac > 0.0)) continue;
+                for (int m = 0; m < NS; m++) {
+                    if (sTgt[m * RN + rs] != c) continue;
+                    double b = sBeta[m * RN + rs];
+                    if (!(b > 0.0)) continue;
+                    for (int q = 0; q < NV; q++) dl[q] -= b * (vc[q] * as - val(q, sc) * ac) / (as + ac);
+                }
+            }
 }
 
-// LDS variant (1-D and 2-D): the source data (weights and targets) of every
-// cell of the tile and its one-cell halo is computed once, then gathered.
-template <int D> struct MixRegion;
-template <> struct MixRegion<1> { static constexpr int X = 256 + 2, Y = 1; };
-template <> struct MixRegion<2> { static constexpr int X = 16 + 2, Y = 16 + 2; };
+// tabulate the mixing sources of the tile's region (cells outside the grid
+// map to their boundary images)
+template <int D>
+__device__ __forceinline__ void mix_sources(const Dev& g, int k, int ox, int oy, int oz, const double* cur,
+                                            double* sBeta, int* sTgt, int* sCell)
+{
+    constexpr int NS = (1 << D) - 1;
+    constexpr int RX = MixRegion<D>::X, RY = MixRegion<D>::Y, RN = MixRegion<D>::N;
+    constexpr int HY = D >= 2 ? 1 : 0, HZ = D == 3 ? 1 : 0;
+    for (int r = threadIdx.x; r < RN; r += SHARP_WG) {
+        int rx = r % RX, ry = (r / RX) % RY, rz = r / (RX * RY);
+        int c = cidx(g, ox - 1 + rx, oy - HY + ry, oz - HZ + rz);
+        sCell[r] = c;
+        double beta[7];
+        int tgt[7];
+        bool src = mix_source<D>(g, cur, k, c, beta, tgt);
+        for (int m = 0; m < NS; m++) {
+            sBeta[m * RN + r] = src ? beta[m] : 0.0;
+            sTgt[m * RN + r] = src ? tgt[m] : -1;
+        }
+    }
+}
 
 template <int D>
 __global__ void __launch_bounds__(SHARP_WG) k_mixdelta_lds(Dev g, int list, int k, const double* cons, const double* cur)
 {
-    static_assert(D <= 2, "LDS mixing is for 1-D and 2-D");
     constexpr int NV = D + 2;
     constexpr int NS = (1 << D) - 1;
     constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
-    constexpr int RX = MixRegion<D>::X, RY = MixRegion<D>::Y, RN = RX * RY;
-    constexpr int HY = D == 2 ? 1 : 0;
+    constexpr int RN = MixRegion<D>::N;
     __shared__ double sBeta[NS * RN];
     __shared__ int sTgt[NS * RN];
     __shared__ int sCell[RN];
     const int* L = list_ptr(g, list);
+    auto val = [&](int q, int c) { return cons[(size_t)q * g.nc + c]; };
     for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
-        int t = L[ti];
-        int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
-        for (int r = threadIdx.x; r < RN; r += SHARP_WG) {
-            int rx = r % RX, ry = r / RX;
-            int c = cidx(g, ox - 1 + rx, oy - HY + ry, 0);
-            sCell[r] = c;
-            double beta[7];
-            int tgt[7];
-            bool src = mix_source<D>(g, cur, k, c, beta, tgt);
-            for (int m = 0; m < NS; m++) {
-                sBeta[m * RN + r] = src ? beta[m] : 0.0;
-                sTgt[m * RN + r] = src ? tgt[m] : -1;
-            }
-        }
+        int ox, oy, oz;
+        tile_origin<D>(g, L[ti], ox, oy, oz);
+        mix_sources<D>(g, k, ox, oy, oz, cur, sBeta, sTgt, sCell);
         __syncthreads();
-        int li = threadIdx.x % TX, lj = threadIdx.x / TX;
-        int i = ox + li, j = oy + lj;
-        if (i < g.n[0] && j < g.n[1]) {
-            int c = i + g.n[0] * j;
+        int li = threadIdx.x % TX, lj = (threadIdx.x / TX) % TY, lk = threadIdx.x / (TX * TY);
+        int i = ox + li, j = oy + lj, kk = oz + lk;
+        if (i < g.n[0] && j < g.n[1] && kk < g.n[2]) {
+            int c = i + g.n[0] * (j + g.n[1] * kk);
             if (g.M[c]) {
-                int rc = (li + 1) + RX * (lj + HY);
-                double dl[NV];
-                for (int q = 0; q < NV; q++) dl[q] = 0.0;
-                double ac = alpha_k(g, k, c);
-                // c as a source
-                for (int m = 0; m < NS; m++) {
-                    int tt = sTgt[m * RN + rc];
-                    double b = sBeta[m * RN + rc];
-                    if (tt < 0 || !(b > 0.0) || tt == c) continue;
-                    double at = alpha_k(g, k, tt);
-                    if (!(ac + at > 0.0)) continue;
-                    for (int q = 0; q < NV; q++)
-                        dl[q] += b * (cons[(size_t)q * g.nc + tt] * ac - cons[(size_t)q * g.nc + c] * at) / (ac + at);
-                }
-                // c as a target of its (distinct) neighbours
-                bool edge = i == 0 || i == g.n[0] - 1 || (D == 2 && (j == 0 || j == g.n[1] - 1));
-                int seen[8];
-                int ns = 0;
-                for (int oy2 = -HY; oy2 <= HY; oy2++)
-                    for (int ox2 = -1; ox2 <= 1; ox2++) {
-                        if (!ox2 && !oy2) continue;
-                        int rs = rc + ox2 + RX * oy2;
-                        int sc = sCell[rs];
-                        if (sc == c) continue;
-                        if (edge) {
-                            bool dup = false;
-                            for (int u = 0; u < ns; u++) dup |= (seen[u] == sc);
-                            if (dup) continue;
-                            seen[ns++] = sc;
-                        }
-                        if (sTgt[rs] < 0) continue;     // not a source
-                        double as = alpha_k(g, k, sc);
-                        if (!(as + ac > 0.0)) continue;
-                        for (int m = 0; m < NS; m++) {
-                            if (sTgt[m * RN + rs] != c) continue;
-                            double b = sBeta[m * RN + rs];
-                            if (!(b > 0.0)) continue;
-                            for (int q = 0; q < NV; q++)
-                                dl[q] -= b * (cons[(size_t)q * g.nc + c] * as - cons[(size_t)q * g.nc + sc] * ac) / (as + ac);
-                        }
-                    }
+                double vc[NV], dl[NV];
+                for (int q = 0; q < NV; q++) { vc[q] = val(q, c); dl[q] = 0.0; }
+                mix_gather<D>(g, k, c, i, j, kk, li, lj, lk, sBeta, sTgt, sCell, val, vc, dl);
                 for (int q = 0; q < NV; q++) g.dmix[(size_t)q * g.nc + c] = dl[q];
             }
         }
@@ -653,10 +626,7 @@ __device__ __forceinline__ void mix_tile(const Dev& g, int t, const MixPart& P, 
                                          int* sTgt, int* sCell)
 {
     constexpr int NV = D + 2;
-    constexpr int NS = (1 << D) - 1;
     constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
-    constexpr int RX = MixRegion<D>::X, RY = MixRegion<D>::Y, RN = RX * RY;
-    constexpr int HY = D == 2 ? 1 : 0;
     const int k = P.k;
     double a1 = P.a1, a2 = P.a2;
     int do_mix = P.do_mix;
@@ -672,65 +642,17 @@ __device__ __forceinline__ void mix_tile(const Dev& g, int t, const MixPart& P, 
         size_t e = (size_t)q * g.nc + c;
         return s2 ? a1 * s1[e] + a2 * s2[e] : s1[e];
     };
-    int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
-    if (do_mix) {
-        for (int r = threadIdx.x; r < RN; r += SHARP_WG) {
-            int rx = r % RX, ry = r / RX;
-            int c = cidx(g, ox - 1 + rx, oy - HY + ry, 0);
-            sCell[r] = c;
-            double beta[7];
-            int tgt[7];
-            bool src = mix_source<D>(g, cur, k, c, beta, tgt);
-            for (int m = 0; m < NS; m++) {
-                sBeta[m * RN + r] = src ? beta[m] : 0.0;
-                sTgt[m * RN + r] = src ? tgt[m] : -1;
-            }
-        }
-    }
+    int ox, oy, oz;
+    tile_origin<D>(g, t, ox, oy, oz);
+    if (do_mix) mix_sources<D>(g, k, ox, oy, oz, cur, sBeta, sTgt, sCell);
     __syncthreads();
-    int li = threadIdx.x % TX, lj = threadIdx.x / TX;
-    int i = ox + li, j = oy + lj;
-    if (i < g.n[0] && j < g.n[1]) {
-        int c = i + g.n[0] * j;
+    int li = threadIdx.x % TX, lj = (threadIdx.x / TX) % TY, lk = threadIdx.x / (TX * TY);
+    int i = ox + li, j = oy + lj, kk = oz + lk;
+    if (i < g.n[0] && j < g.n[1] && kk < g.n[2]) {
+        int c = i + g.n[0] * (j + g.n[1] * kk);
         double vc[NV], dl[NV];
         for (int q = 0; q < NV; q++) { vc[q] = val(q, c); dl[q] = 0.0; }
-        if (do_mix && g.M[c]) {
-            int rc = (li + 1) + RX * (lj + HY);
-            double ac = alpha_k(g, k, c);
-            for (int m = 0; m < NS; m++) {
-                int tt = sTgt[m * RN + rc];
-                double b = sBeta[m * RN + rc];
-                if (tt < 0 || !(b > 0.0) || tt == c) continue;
-                double at = alpha_k(g, k, tt);
-                if (!(ac + at > 0.0)) continue;
-                for (int q = 0; q < NV; q++) dl[q] += b * (val(q, tt) * ac - vc[q] * at) / (ac + at);
-            }
-            bool edge = i == 0 || i == g.n[0] - 1 || (D == 2 && (j == 0 || j == g.n[1] - 1));
-            int seen[8];
-            int ns = 0;
-            for (int oy2 = -HY; oy2 <= HY; oy2++)
-                for (int ox2 = -1; ox2 <= 1; ox2++) {
-                    if (!ox2 && !oy2) continue;
-                    int rs = rc + ox2 + RX * oy2;
-                    int sc = sCell[rs];
-                    if (sc == c) continue;
-                    if (edge) {
-                        bool dup = false;
-                        for (int u = 0; u < ns; u++) dup |= (seen[u] == sc);
-                        if (dup) continue;
-                        seen[ns++] = sc;
-                    }
-                    if (sTgt[rs] < 0) continue;
-                    double as = alpha_k(g, k, sc);
-                    if (!(as + ac > 0.0)) continue;
-                    for (int m = 0; m < NS; m++) {
-                        if (sTgt[m * RN + rs] != c) continue;
-                        double b = sBeta[m * RN + rs];
-                        if (!(b > 0.0)) continue;
-                        for (int q = 0; q < NV; q++) dl[q] -= b * (vc[q] * as - val(q, sc) * ac) / (as + ac);
-                    }
-                }
-        }
+        if (do_mix && g.M[c]) mix_gather<D>(g, k, c, i, j, kk, li, lj, lk, sBeta, sTgt, sCell, val, vc, dl);
         for (int q = 0; q < NV; q++) P.dst[(size_t)q * g.nc + c] = vc[q] + dl[q];
     }
     __syncthreads();
@@ -739,9 +661,8 @@ __device__ __forceinline__ void mix_tile(const Dev& g, int t, const MixPart& P, 
 template <int D>
 __global__ void __launch_bounds__(SHARP_WG) k_mixinterp_lds(Dev g, int list, MixPart P, const double* cur)
 {
-    static_assert(D <= 2, "LDS mixing is for 1-D and 2-D");
     constexpr int NS = (1 << D) - 1;
-    constexpr int RN = MixRegion<D>::X * MixRegion<D>::Y;
+    constexpr int RN = MixRegion<D>::N;
     __shared__ double sBeta[NS * RN];
     __shared__ int sTgt[NS * RN];
     __shared__ int sCell[RN];
@@ -757,10 +678,9 @@ template <int D>
 __global__ void __launch_bounds__(SHARP_WG) k_mix_parts(Dev g, int list, MixPart A, MixPart B, int nparts,
                                                        const double* cur, const double* phi_src, double* phi_dst)
 {
-    static_assert(D <= 2, "LDS mixing is for 1-D and 2-D");
     constexpr int NS = (1 << D) - 1;
     constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
-    constexpr int RN = MixRegion<D>::X * MixRegion<D>::Y;
+    constexpr int RN = MixRegion<D>::N;
     __shared__ double sBeta[NS * RN];
     __shared__ int sTgt[NS * RN];
     __shared__ int sCell[RN];
@@ -770,10 +690,12 @@ __global__ void __launch_bounds__(SHARP_WG) k_mix_parts(Dev g, int list, MixPart
         mix_tile<D>(g, t, A, cur, sBeta, sTgt, sCell);
         if (nparts > 1) mix_tile<D>(g, t, B, cur, sBeta, sTgt, sCell);
         if (phi_dst) {
-            int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
-            int i = ox + (int)threadIdx.x % TX, j = oy + (int)threadIdx.x / TX;
-            if (i < g.n[0] && j < g.n[1]) {
-                int c = i + g.n[0] * j;
+            int ox, oy, oz;
+            tile_origin<D>(g, t, ox, oy, oz);
+            int tid = threadIdx.x;
+            int i = ox + tid % TX, j = oy + (tid / TX) % TY, kk = oz + tid / (TX * TY);
+            if (i < g.n[0] && j < g.n[1] && kk < g.n[2]) {
+                int c = i + g.n[0] * (j + g.n[1] * kk);
                 if (g.M[c]) phi_dst[c] = phi_src[c];
             }
         }
@@ -1391,7 +1313,7 @@ __device__ __forceinline__ void load_state(const Dev& g, int k, const double* in
 template <int D, bool BAND>
 __global__ void __launch_bounds__(SHARP_WG) k_stage(Dev g, int list, int k, const double* in, const double* self2,
                                                    const double* base, double* out, double a, double dt,
-                                                   double wflux, int wb)
+                                                   double wflux, int wb, double* tmp)
 {
     constexpr int NV = D + 2;
     constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
@@ -1490,10 +1412,11 @@ __global__ void __launch_bounds__(SHARP_WG) k_stage(Dev g, int list, int k, cons
                     }
                 }
                 const double* sin_ = (BAND && self2 && g.M[c]) ? self2 : in;
+                double* dst = (BAND && tmp && !(g.tflag[t] & 4)) ? tmp : out;
                 for (int q = 0; q < NV; q++) {
                     size_t e = (size_t)q * g.nc + c;
                     double s = sin_[e] + dt * Lr[q];
-                    out[e] = (a == 0.0) ? s : a * base[e] + (1.0 - a) * s;
+                    dst[e] = (a == 0.0) ? s : a * base[e] + (1.0 - a) * s;
                 }
             }
         }
@@ -2321,22 +2244,18 @@ struct Engine {
     void corr_add(double w, int S) { k_corr_add<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, w, S); }
     void mix(int k, double* cons, const double* cur)
     {
-        if constexpr (D <= 2)
-            k_mixdelta_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, k, cons, cur);
-        else
-            k_mixdelta<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, k, cons, cur);
+        k_mixdelta_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, k, cons, cur);
         k_mixapply<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, cons);
     }
-    // 1-D/2-D: the band stage writes the inner tiles' output to Tm and one
-    // launch mixes it into the stage buffer, optionally together with a
-    // second mixed copy (the other fluid, or the slow fluid's interpolated
-    // state for the next stage) and the level-set commit
-    static constexpr bool fmix = D <= 2;
+    // the band stage writes the inner tiles' output to Tm and one launch
+    // mixes it into the stage buffer, optionally together with a second
+    // mixed copy (the other fluid, or the slow fluid's interpolated state
+    // for the next stage) and the level-set commit
+    static constexpr bool fmix = true;
     void mix_fused(const MixPart& A, const MixPart* B, const double* cur, const double* commit)
     {
-        if constexpr (D <= 2)
-            k_mix_parts<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, A, B ? *B : A, B ? 2 : 1, cur,
-                                                                    commit, commit ? g.phiP : nullptr);
+        k_mix_parts<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, A, B ? *B : A, B ? 2 : 1, cur, commit,
+                                                                commit ? g.phiP : nullptr);
     }
     MixPart tm_part(int k, double* out) const
     {
@@ -2420,7 +2339,7 @@ struct Engine {
                                   self2, base, out, a, dt, wflux, s.wcur, cfl, tmp);
         else
             hipExtLaunchKernelGGL(k_stage<D, BAND>, gr, dim3(wg()), 0, st, e0, e1, 0, g, list, k, in, self2, base,
-                                  out, a, dt, wflux, s.wcur);
+                                  out, a, dt, wflux, s.wcur, tmp);
     }
     void profile_flush()
     {
@@ -2568,23 +2487,13 @@ struct Engine {
     }
     void interp_slow(int S, double theta, const double* cur)
     {
-        if constexpr (D <= 2) {
-            k_mixinterp_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, interp_part(S, theta), cur);
-            return;
-        }
-        axpby(1.0 - theta, g.X[S], theta, g.Y[S], g.T2, NV);
-        if (theta != 0.0) mix(S, g.T2, cur);
+        k_mixinterp_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, interp_part(S, theta), cur);
     }
     // copy of src mixed with the current geometry
     void mixed_copy(int S, const double* src, const double* cur)
     {
-        if constexpr (D <= 2) {
-            MixPart P = {S, 1.0, src, 0.0, nullptr, g.T2, 1, 0};
-            k_mixinterp_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, P, cur);
-            return;
-        }
-        axpby(1.0, src, 0.0, nullptr, g.T2, NV);
-        mix(S, g.T2, cur);
+        MixPart P = {S, 1.0, src, 0.0, nullptr, g.T2, 1, 0};
+        k_mixinterp_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, P, cur);
     }
 
     // ---- the accelerated cycle (Sec. 3.1) ----
