@@ -42,7 +42,8 @@ def parse():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
-    ap.add_argument("--no-l1", action="store_true", help="skip the matched-L1 comparison on the 1-D tube ladder")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-l1", action="store_true", help="skip the matched-L1 comparisons (1-D tube and 3-D droplet ladders)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
@@ -121,9 +122,9 @@ def reduce_counters(fetch_dir, write_dir):
                source_sha256=source_digest(), sources=KERNEL_SOURCES, counters=out,
                traffic_bytes_per_launch=traffic,
                commands=["timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <FETCH_DIR> -o run "
-                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --copy-probe",
+                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --no-adjoint --copy-probe",
                          "timeout -s KILL 150 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <WRITE_DIR> -o run "
-                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --copy-probe",
+                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --no-adjoint --copy-probe",
                          "python bench.py --reduce-counters <FETCH_DIR> <WRITE_DIR>"])
     with open(COUNTERS, "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -245,6 +246,89 @@ def matched_l1(P, WL, ladder=(400, 800, 1600, 3200, 6400)):
                 geomean=float(np.exp(np.mean(np.log(ratios)))) if ratios else None)
 
 
+def matched_l1_3d(P, WL, ladder=(64, 128, 256), t_end=3.0e-4):
+    """The 3-D shock-droplet (slow air fills 97% of the grid) over a
+    resolution ladder in both modes to t_end: GPU time and the relative L1
+    error of the cell-average density against the finest single-dt run
+    (restricted by averaging); the time ratio single/multi at matched error
+    (log-log interpolation along the single-dt ladder) on the coarser
+    levels, and at the finest level the same-grid ratio with the distance
+    between the two modes (far below the coarser levels' error)."""
+    import numpy as np
+    import torch
+    rho = {}
+    rows = {0: [], 1: []}
+    for n in ladder:
+        for mode in (0, 1):
+            case = WL.shock_droplet_3d(n=n, seed=0, t_end=t_end)
+            sim = P.Sim(case)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = sim.advance(t_end, mode=mode)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            _, cons, _ = sim.state(device=False)
+            rho[(n, mode)] = (cons[0, 0] + cons[1, 0]).reshape(n, n, n)
+            rows[mode].append(dict(n=n, seconds=el, cycles=st["cycles"], steps=st["steps"],
+                                   cell_updates=st["cell_updates"]))
+            sim.close()
+    nf = ladder[-1]
+    ref = rho[(nf, 0)]
+    for mode in (0, 1):
+        for r in rows[mode]:
+            n = r["n"]
+            f = nf // n
+            R = ref.reshape(n, f, n, f, n, f).mean(axis=(1, 3, 5))
+            r["l1_rho"] = float(np.abs(rho[(n, mode)] - R).mean() / np.abs(R).mean()) if n < nf else None
+    dist = float(np.abs(rho[(nf, 1)] - ref).mean() / np.abs(ref).mean())
+    ls = np.log([r["l1_rho"] for r in rows[0][:-1]])
+    ts = np.log([r["seconds"] for r in rows[0][:-1]])
+    order = np.argsort(ls)
+    ratios = []
+    for r in rows[1][:-1]:
+        l = np.log(r["l1_rho"])
+        if ls.min() <= l <= ls.max():
+            ratios.append(float(np.exp(np.interp(l, ls[order], ts[order])) / r["seconds"]))
+    return dict(workload="shock_droplet_3d ladder %s, t_end %.1e s, reference: %d^3 single_dt" % (list(ladder), t_end, nf),
+                single_dt=rows[0], multi_dt=rows[1],
+                time_ratio_single_over_multi_at_matched_l1=ratios,
+                finest_same_grid_ratio=rows[0][-1]["seconds"] / rows[1][-1]["seconds"],
+                finest_l1_distance_multi_vs_single=dist)
+
+
+def adjoint_timing(P, WL, n=512, steps=400, ckpt=20, probes=16):
+    """The differentiable configuration on one fluid: an acoustic pulse in
+    air filling 512^2 (zero-gradient), 400 single-dt steps, loss = sum of
+    (p - 1e5)^2 at 16 probe cells; gradient with respect to the initial
+    primitives and (gamma, p_inf) through sim_backward with a checkpoint
+    every 20 steps.  Reports the forward (taped) and backward times."""
+    import numpy as np
+    import torch
+    c = WL.pulse_air(n=n, ndim=2, seed=0)
+    W = c["prim"][0]
+    cs = np.sqrt(1.4 * W[3] / W[0])
+    dt = 0.6 / ((np.abs(W[1]) + cs + np.abs(W[2]) + cs) * n).max()
+    prim = torch.tensor(c["prim"], device="cuda", requires_grad=True)
+    eos = torch.tensor([[1.4, 0.0], [4.4, 6.0e8]], dtype=torch.float64, device="cuda", requires_grad=True)
+    pr = torch.tensor(WL.probe_cells(n, 2, count=probes, seed=0), device="cuda")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    cons = P.AdvanceFn.apply(prim, eos, c, steps * dt, dict(ckpt_every=ckpt, dt_fixed=dt))
+    U = cons[0]
+    p = (eos[0, 0] - 1.0) * (U[3] - 0.5 * (U[1] ** 2 + U[2] ** 2) / U[0]) - eos[0, 0] * eos[0, 1]
+    J = ((p[pr] - 1.0e5) ** 2).sum()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    J.backward()
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    g = prim.grad[0]
+    return dict(workload="pulse_air 2-D %dx%d, %d single-dt steps, %d probes, checkpoint every %d" % (n, n, steps, probes, ckpt),
+                forward_s=t1 - t0, backward_s=t2 - t1, backward_over_forward=(t2 - t1) / (t1 - t0),
+                cell_steps_per_s_backward=n * n * steps / (t2 - t1),
+                grad_norm=float(torch.linalg.vector_norm(g)), d_gamma=float(eos.grad[0, 0]), d_pinf=float(eos.grad[0, 1]))
+
+
 def cpu_baseline(case_fn, seconds):
     """The CPU oracle (single thread) on the same workload at reduced
     resolution, scaled to cell-updates/s."""
@@ -349,6 +433,16 @@ def main():
         ml1 = matched_l1(P, WL)
         print("bench: matched L1 (1-D tube ladder): single/multi time ratios %s"
               % ml1["time_ratio_single_over_multi_at_matched_l1"], flush=True)
+        ml1_3d = matched_l1_3d(P, WL)
+        ml1["droplet_3d"] = ml1_3d
+        print("bench: matched L1 (3-D droplet ladder): single/multi time ratios %s, same grid %d^3 %.2f"
+              % (ml1_3d["time_ratio_single_over_multi_at_matched_l1"], ml1_3d["single_dt"][-1]["n"],
+                 ml1_3d["finest_same_grid_ratio"]), flush=True)
+    adj = None
+    if not a.no_adjoint:
+        adj = adjoint_timing(P, WL)
+        print("bench: adjoint (512^2, 400 steps): forward %.3f s, backward %.3f s"
+              % (adj["forward_s"], adj["backward_s"]), flush=True)
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(WL.shock_bubble_2d, a.cpu_seconds)
@@ -372,6 +466,7 @@ def main():
                       "steps": st["steps"]},
         "single_dt": single,
         "matched_l1": ml1,
+        "adjoint": adj,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

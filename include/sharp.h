@@ -90,6 +90,11 @@ typedef struct {
     int serial;          /* run every kernel on the simulation's stream instead of
                             overlapping the bulk-tile stages with the band work on
                             two library-owned streams; results are identical [0] */
+    int tape;            /* record single-dt steps for sim_backward [0] */
+    int ckpt_every;      /* taped steps between stored states (checkpoints) [20] */
+    double dt_fixed;     /* > 0: single-dt steps of this length (the last one
+                            clamped to t_end) instead of the CFL step, so that
+                            perturbed runs share one schedule [0] */
 } sim_opts;
 
 typedef struct {
@@ -144,6 +149,26 @@ sim_status sim_totals(sim_t* s, double* out10);
  * step (which read no base state).  Enabling resets the counters. */
 sim_status sim_profile(sim_t* s, int enable);
 sim_status sim_profile_read(sim_t* s, double* ms, int64_t* launches, int64_t* cells, int64_t* first_cells);
+
+/* Adjoint of the taped run (opts->tape = 1): the gradient of a scalar J
+ * through every sim_advance call since the last sim_set_state, with the
+ * step lengths frozen at their forward values.  It covers runs in which one
+ * fluid fills the grid (no interface, so no geometry, exchange term,
+ * extension, mixing or interpolation enters) and single-dt steps: the
+ * Shu-Osher stages (Sec. 2.1, Sec. 3) of the WENO5-LLF finite-volume
+ * update and the stiffened-gas EOS.  The forward stores the state every
+ * ckpt_every steps; the backward recomputes each segment's stages from its
+ * checkpoint and runs the reverse sweep through them.
+ *   g_cons[2][NV][cells]  dJ/dcons at the end of the run (input)
+ *   g_prim0[2][NV][cells] dJ/dprim given to sim_set_state (output; zero for
+ *                         the fluid that holds no cell)
+ *   g_eos[4]              dJ/dgamma_0, dJ/dpinf_0, dJ/dgamma_1, dJ/dpinf_1
+ *                         through the dynamics and the initial prim -> cons
+ *                         map (host array, output; nullable)
+ * Returns SIM_EINVAL when the run is not covered (the message says why),
+ * SIM_ESTATE without a tape, SIM_ENOMEM when the recomputation buffers
+ * (3 ckpt_every states) do not fit. */
+sim_status sim_backward(sim_t* s, const double* g_cons, double* g_prim0, double* g_eos, int on_device);
 
 void sim_destroy(sim_t* s);
 const char* sim_strerror(sim_status st);

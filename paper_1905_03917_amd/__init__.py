@@ -34,7 +34,8 @@ class Opts(C.Structure):
                 ("ls_band", C.c_double), ("ext_band", C.c_double), ("mix_band", C.c_double),
                 ("ext_iters", C.c_int), ("reinit_iters", C.c_int), ("weno_eps", C.c_double),
                 ("force_cycle", C.c_int), ("no_correction", C.c_int),
-                ("serial", C.c_int)]
+                ("serial", C.c_int), ("tape", C.c_int), ("ckpt_every", C.c_int),
+                ("dt_fixed", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -49,7 +50,7 @@ class Stats(C.Structure):
 
 
 EXPORTS = ["sim_default_opts", "sim_create", "sim_set_state", "sim_advance", "sim_get_state",
-           "sim_totals", "sim_profile", "sim_profile_read", "sim_destroy", "sim_strerror",
+           "sim_totals", "sim_profile", "sim_profile_read", "sim_backward", "sim_destroy", "sim_strerror",
            "sim_last_error"]
 
 _lib = None
@@ -74,13 +75,14 @@ def lib():
         L.sim_profile.argtypes = [vp, C.c_int]
         L.sim_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int64)]
+        L.sim_backward.argtypes = [vp, vp, vp, vp, C.c_int]
         L.sim_destroy.argtypes = [vp]
         L.sim_destroy.restype = None
         L.sim_strerror.argtypes = [C.c_int]
         L.sim_strerror.restype = C.c_char_p
         L.sim_last_error.restype = C.c_char_p
         for f in ("sim_create", "sim_set_state", "sim_advance", "sim_get_state", "sim_totals",
-                  "sim_profile", "sim_profile_read"):
+                  "sim_profile", "sim_profile_read", "sim_backward"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -197,6 +199,25 @@ class Sim:
         _check(lib().sim_totals(self.h, C.c_void_p(out.ctypes.data)), "sim_totals")
         return out.reshape(2, 5)
 
+    def backward(self, g_cons):
+        """Adjoint of the taped run (opts tape=1): g_cons = dJ/dcons at the
+        end, [2][NV][cells] (float64 CUDA tensor or ndarray).  Returns
+        (dJ/dprim0 [2][NV][cells] of the same kind, dJ/d(gamma, p_inf) as a
+        (2, 2) ndarray through the dynamics and the initial map)."""
+        import torch
+        eos = np.zeros(4)
+        if isinstance(g_cons, torch.Tensor) and g_cons.is_cuda:
+            g = g_cons.contiguous()
+            out = torch.empty_like(g)
+            _check(lib().sim_backward(self.h, C.c_void_p(g.data_ptr()), C.c_void_p(out.data_ptr()),
+                                      C.c_void_p(eos.ctypes.data), 1), "sim_backward")
+        else:
+            g = np.ascontiguousarray(g_cons, dtype=np.float64)
+            out = np.empty_like(g)
+            _check(lib().sim_backward(self.h, C.c_void_p(g.ctypes.data), C.c_void_p(out.ctypes.data),
+                                      C.c_void_p(eos.ctypes.data), 0), "sim_backward")
+        return out, eos.reshape(2, 2)
+
     def profile(self, enable=True):
         _check(lib().sim_profile(self.h, int(enable)), "sim_profile")
 
@@ -209,3 +230,53 @@ class Sim:
         _check(lib().sim_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(cells), C.byref(first)),
                "sim_profile_read")
         return ms.value, n.value, cells.value, first.value
+
+
+def _advance_fn():
+    import torch
+
+    class AdvanceFn(torch.autograd.Function):
+        """cons_final = advance(prim0; gamma, p_inf) with single-dt steps on a
+        case whose grid one fluid fills; backward through sim_backward (step
+        lengths frozen at their forward values).
+
+        prim0: [2][NV][cells] float64 CUDA tensor; eos: (2, 2) float64 tensor
+        of (gamma, p_inf) per fluid; case: workload dict (its level set);
+        t_end: end time; opts: further sim_opts fields (ckpt_every, rk, cfl).
+        Returns cons [2][NV][cells]."""
+
+        @staticmethod
+        def forward(ctx, prim0, eos, case, t_end, opts):
+            e = eos.detach().cpu().numpy()
+            c = {k: v for k, v in case.items() if k not in ("phi", "prim")}
+            c["gamma"] = [float(e[0, 0]), float(e[1, 0])]
+            c["pinf"] = [float(e[0, 1]), float(e[1, 1])]
+            sim = Sim(c, tape=1, **(opts or {}))
+            phi = torch.as_tensor(np.asarray(case["phi"], dtype=np.float64), device=prim0.device)
+            sim.set_state(phi, prim0.detach().contiguous())
+            sim.advance(t_end, mode=SIM_SINGLE_DT)
+            _, cons, _ = sim.state()
+            ctx.sim = sim
+            ctx.eos_device = eos.device
+            return cons
+
+        @staticmethod
+        def backward(ctx, g):
+            gp, geos = ctx.sim.backward(g.contiguous())
+            ctx.sim.close()
+            return gp, torch.as_tensor(geos, device=ctx.eos_device), None, None, None
+
+    return AdvanceFn
+
+
+class _Lazy:
+    def __init__(self):
+        self._cls = None
+
+    def __getattr__(self, name):
+        if self._cls is None:
+            self._cls = _advance_fn()
+        return getattr(self._cls, name)
+
+
+AdvanceFn = _Lazy()

@@ -44,6 +44,7 @@ static sim_status dalloc(Sim& s, T** p, size_t n)
 
 static void release(Sim& s)
 {
+    tape_clear(s);
     for (void* p : s.dev_allocs) (void)hipFree(p);
     s.dev_allocs.clear();
     for (hipEvent_t e : s.ev_pool) (void)hipEventDestroy(e);
@@ -83,6 +84,7 @@ void sim_default_opts(sim_opts* o)
     o->ext_iters = 8;
     o->reinit_iters = 2;
     o->weno_eps = 1e-6;
+    o->ckpt_every = 20;
 }
 
 const char* sim_strerror(sim_status st)
@@ -122,6 +124,8 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     if (opts) o = *opts; else sim_default_opts(&o);
     if (o.rk != 2 && o.rk != 3) { set_error("rk must be 2 or 3"); return SIM_EINVAL; }
     if (!(o.cfl > 0.0) || o.ext_iters < 0 || o.reinit_iters < 0) { set_error("invalid options"); return SIM_EINVAL; }
+    if (o.tape && o.ckpt_every < 1) { set_error("ckpt_every must be >= 1"); return SIM_EINVAL; }
+    if (!(o.dt_fixed >= 0.0) || !std::isfinite(o.dt_fixed)) { set_error("dt_fixed must be >= 0"); return SIM_EINVAL; }
 
     sim_t* h = new sim_t();
     Sim& s = h->s;
@@ -299,6 +303,36 @@ sim_status sim_advance(sim_t* h, double t_end, int mode, int64_t max_cycles, sim
     sim_status rc = engine_advance(s, t_end, mode, (long long)max_cycles, &st);
     if (rc == SIM_OK) rc = engine_bflux(s, st.bflux);
     if (out) *out = st;
+    return rc;
+}
+
+sim_status sim_backward(sim_t* h, const double* g_cons, double* g_prim0, double* g_eos, int on_device)
+{
+    if (!h || !g_cons || !g_prim0) { set_error("null argument"); return SIM_EINVAL; }
+    Sim& s = h->s;
+    if (!s.o.tape || !s.has_state) { set_error("no tape: create with opts.tape = 1, then set_state and advance"); return SIM_ESTATE; }
+    if (s.tape_fluid < 0) { set_error("%s", s.tape_why.c_str()); return SIM_EINVAL; }
+    size_t n = (size_t)2 * (s.g.D + 2) * s.g.nc;
+    double *tg = nullptr, *tp = nullptr;
+    sim_status rc = stage_in(s, g_cons, n, on_device, &tg);
+    if (rc == SIM_OK && !on_device) {
+        if (hipMalloc((void**)&tp, n * sizeof(double)) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("staging allocation failed");
+            rc = SIM_ENOMEM;
+        }
+    }
+    double eos[4] = {0.0, 0.0, 0.0, 0.0};
+    if (rc == SIM_OK) rc = engine_backward(s, tg ? tg : g_cons, tp ? tp : g_prim0, eos);
+    if (rc == SIM_OK && tp && hipMemcpyAsync(g_prim0, tp, n * sizeof(double), hipMemcpyDeviceToHost, s.stream) != hipSuccess) {
+        set_error("device-to-host copy failed");
+        rc = SIM_EDEVICE;
+    }
+    (void)hipStreamSynchronize(s.stream);
+    if (tg) (void)hipFree(tg);
+    if (tp) (void)hipFree(tp);
+    if (rc == SIM_OK && g_eos)
+        for (int i = 0; i < 4; i++) g_eos[i] = eos[i];
     return rc;
 }
 

@@ -58,6 +58,12 @@ struct Sim {
     long long prof_launches = 0, prof_cell_stages = 0, prof_first_stages = 0;
     long long bulk_cells[2] = {0, 0};   // cells in the bulk lists (host copy)
     int lcount[NLISTS] = {1, 1, 1, 1, 1, 1};   // tiles per list (host copy, sizes the grids)
+    // tape of the adjoint (o.tape): single-dt steps of a single-fluid run
+    int tape_fluid = -1;                // the fluid holding every cell; -1: not differentiable
+    std::string tape_why;               // why this run cannot be differentiated
+    std::vector<double> tape_dt;        // length of each taped step
+    std::vector<double*> tape_ckpt;     // state of tape_fluid before steps 0, K, 2K, ... (K = o.ckpt_every)
+    double* tape_prim0 = nullptr;       // primitives of tape_fluid given to sim_set_state
 };
 
 void set_error(const char* fmt, ...);
@@ -66,6 +72,14 @@ void set_error(const char* fmt, ...);
 sim_status engine_set_state(Sim& s, const double* phi_dev, const double* prim_dev);
 sim_status engine_advance(Sim& s, double t_end, int mode, long long max_cycles, sim_stats* st);
 sim_status engine_bflux(Sim& s, double out[2][5]);
+// one bulk-tile stage of fluid k on the simulation stream (the forward
+// recomputation of the adjoint): out = a*base + (1-a)*(in + dt*L(in))
+void engine_bulk_stage(Sim& s, int k, const double* in, const double* base, double* out, double a, double dt);
+// adjoint (sharp_adjoint.hip)
+void tape_clear(Sim& s);
+sim_status tape_begin(Sim& s, const double* prim_dev);
+sim_status tape_step(Sim& s, double dt);
+sim_status engine_backward(Sim& s, const double* g_cons, double* g_prim0, double* g_eos);
 
 #define SHARP_HIP(call)                                                              \
     do {                                                                             \

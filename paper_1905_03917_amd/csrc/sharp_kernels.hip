@@ -1637,6 +1637,222 @@ __global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, in
 }
 
 // ---------------------------------------------------------------------------
+// LDS-staged stage kernel (3-D), one direction at a time: for d = x, y, z
+// the primitives of the tile and its three-cell halo along d (448 or 640
+// cells) are staged in LDS, the tile's faces normal to d (288 or 320) are
+// computed from LDS, and each cell adds its flux difference along d.  The
+// tile's own cells are converted once and kept in registers; LDS holds one
+// direction's region and faces (49 KB).  Same arithmetic as the 2-D kernel.
+// ---------------------------------------------------------------------------
+#ifndef SHARP_WG3
+#define SHARP_WG3 320
+#endif
+#ifndef SHARP_WG3_WAVES
+#define SHARP_WG3_WAVES 3
+#endif
+template <bool BAND>
+__global__ void __launch_bounds__(SHARP_WG3, SHARP_WG3_WAVES) k_stage_lds3(Dev g, int list, int k, const double* in,
+                                                         const double* self2, const double* base, double* out,
+                                                         double a, double dt, double wflux, int wb, int cfl,
+                                                         double* tmp)
+{
+    constexpr int D = 3, NV = 5, NT = SHARP_WG3;
+    constexpr int TX = 8, TY = 8, TZ = 4, TN = TX * TY * TZ;
+    constexpr int RMAX = TX * TY * (TZ + 6);          // largest directional region (z)
+    constexpr int FMAX = TX * TY * (TZ + 1);          // most faces normal to one direction (z)
+    __shared__ double sR[RMAX], sU[RMAX], sV[RMAX], sW[RMAX], sE[RMAX], sP[RMAX], sC[RMAX];
+    __shared__ double sF[FMAX * NV];
+    __shared__ double sMax[(NT + 63) / 64];
+    __shared__ unsigned long long sCnt[(NT + 63) / 64];
+    double cmax = 0.0;
+    unsigned long long ccnt = 0;
+    const int* L = list_ptr(g, list);
+    const double gm = g.gam[k], pi = g.pinf[k];
+    const double farea = g.h * g.h;
+    const double ih = 1.0 / g.h;
+    const double eps4 = 4.0 * g.eps;
+    if (g.use_sched) { dt = g.sched[SCHED_DT]; wflux = g.sched[SCHED_W0]; }
+    const int tid = threadIdx.x;
+    const bool own = tid < TN;
+    const int li = tid % TX, lj = (tid / TX) % TY, lk = tid / (TX * TY);
+    const ListRange lr = xcd_range(list_count(g, list));
+    for (int ti = lr.begin; ti < lr.end; ti += lr.step) {
+        int t = L[ti];
+        int ox, oy, oz;
+        tile_origin<D>(g, t, ox, oy, oz);
+        const int i = ox + li, j = oy + lj, kk = oz + lk;
+        const bool inside = own && i < g.n[0] && j < g.n[1] && kk < g.n[2];
+        // the thread's own cell, converted once
+        double Wc[NV], Uc[NV], cc = 0.0;
+        if (own) {
+            int c = cidx(g, i, j, kk);
+            load_state<D, BAND>(g, k, in, self2, wb, c, Wc, Uc);
+            cc = csound(gm, pi, Wc[0], Wc[NV - 1]);
+        }
+        double Lr[NV];
+#pragma unroll
+        for (int q = 0; q < NV; q++) Lr[q] = 0.0;
+#pragma unroll 1
+        for (int d = 0; d < D; d++) {
+            const int RX = TX + (d == 0 ? 6 : 0), RY = TY + (d == 1 ? 6 : 0), RZ = TZ + (d == 2 ? 6 : 0);
+            const int RN = RX * RY * RZ;
+            const int hx = d == 0 ? 3 : 0, hy = d == 1 ? 3 : 0, hz = d == 2 ? 3 : 0;
+            // halo cells along d (the tile's own cells come from registers)
+            for (int q = tid; q < RN; q += NT) {
+                int rx = q % RX, ry = (q / RX) % RY, rz = q / (RX * RY);
+                int od = d == 0 ? rx : (d == 1 ? ry : rz);
+                int nd = d == 0 ? RX : (d == 1 ? RY : RZ);
+                if (od >= 3 && od < nd - 3) continue;
+                int c = cidx(g, ox - hx + rx, oy - hy + ry, oz - hz + rz);
+                double W[NV], U[NV];
+                load_state<D, BAND>(g, k, in, self2, wb, c, W, U);
+                sR[q] = W[0];
+                sU[q] = W[1];
+                sV[q] = W[2];
+                sW[q] = W[3];
+                sE[q] = U[NV - 1];
+                sP[q] = W[NV - 1];
+                sC[q] = csound(gm, pi, W[0], W[NV - 1]);
+            }
+            if (own) {
+                int r = (li + hx) + RX * ((lj + hy) + RY * (lk + hz));
+                sR[r] = Wc[0];
+                sU[r] = Wc[1];
+                sV[r] = Wc[2];
+                sW[r] = Wc[3];
+                sE[r] = Uc[NV - 1];
+                sP[r] = Wc[NV - 1];
+                sC[r] = cc;
+            }
+            __syncthreads();
+            // faces normal to d
+            const int FX = TX + (d == 0), FY = TY + (d == 1), FZ = TZ + (d == 2);
+            const int FN = FX * FY * FZ;
+            const int st = d == 0 ? 1 : (d == 1 ? RX : RX * RY);
+            for (int f = tid; f < FN; f += NT) {
+                int fx = f % FX, fy = (f / FX) % FY, fz = f / (FX * FY);
+                int fi = ox + fx, fj = oy + fy, fk = oz + fz;
+                int fd = d == 0 ? fi : (d == 1 ? fj : fk);
+                bool ok = (d == 0 ? fi <= g.n[0] : fi < g.n[0]) && (d == 1 ? fj <= g.n[1] : fj < g.n[1]) &&
+                          (d == 2 ? fk <= g.n[2] : fk < g.n[2]);
+                double* Fo = sF + (size_t)f * NV;
+                double A = 1.0;
+                if (ok && BAND) {
+                    A = g.ap[d][fidx(g, fi, fj, fk)];
+                    if (k == 1) A = 1.0 - A;
+                    ok = A > 0.0;
+                }
+                if (!ok) {
+#pragma unroll
+                    for (int q = 0; q < NV; q++) Fo[q] = 0.0;
+                    continue;
+                }
+                // stencil m = 0..5 <-> cells -3 .. +2 along d from the face
+                int r0 = fx + RX * (fy + RY * fz);
+                double rho[6], vel[3][6], un[6], E[6], p[6];
+                double amax = 0.0;
+#pragma unroll
+                for (int m = 0; m < 6; m++) {
+                    int r = r0 + m * st;
+                    rho[m] = sR[r];
+                    vel[0][m] = sU[r];
+                    vel[1][m] = sV[r];
+                    vel[2][m] = sW[r];
+                    un[m] = d == 0 ? vel[0][m] : (d == 1 ? vel[1][m] : vel[2][m]);
+                    E[m] = sE[r];
+                    p[m] = sP[r];
+                    amax = fmax(amax, fabs(un[m]) + sC[r]);
+                }
+#pragma unroll
+                for (int q = 0; q < NV; q++) {
+                    double fp[6], fm[6];
+#pragma unroll
+                    for (int m = 0; m < 6; m++) {
+                        double Uq, Fq;
+                        if (q == 0) { Uq = rho[m]; Fq = rho[m] * un[m]; }
+                        else if (q == NV - 1) { Uq = E[m]; Fq = (E[m] + p[m]) * un[m]; }
+                        else {
+                            // momentum component along axis q-1
+                            const int e = q - 1;
+                            Uq = rho[m] * vel[e][m];
+                            Fq = Uq * un[m] + (e == d ? p[m] : 0.0);
+                        }
+                        fp[m] = fma(amax, Uq, Fq);
+                        fm[m] = fma(-amax, Uq, Fq);
+                    }
+                    double Fh = weno5_q(fp[0], fp[1], fp[2], fp[3], fp[4], eps4)
+                              + weno5_q(fm[5], fm[4], fm[3], fm[2], fm[1], eps4);
+                    Fo[q] = (A * (1.0 / 12.0)) * Fh;
+                }
+                if (g.bc[d] == 0 && wflux != 0.0 && (fd == 0 || fd == g.n[d])) {
+                    int side = fd == 0 ? 0 : 1;
+                    int o1 = d == 0 ? fj : fi, o2 = d == 2 ? fj : fk;
+                    int n1 = d == 0 ? g.n[1] : g.n[0];
+                    int b = g.bface_off[d][side] + o1 + n1 * o2;
+                    double sgn = side == 0 ? 1.0 : -1.0;
+                    for (int q = 0; q < NV; q++) g.bacc[k][(size_t)q * g.nbface + b] += sgn * wflux * farea * Fo[q];
+                }
+            }
+            __syncthreads();
+            if (inside) {
+                int flo = li + FX * (lj + FY * lk);
+                int fhi = flo + (d == 0 ? 1 : (d == 1 ? FX : FX * FY));
+#pragma unroll
+                for (int q = 0; q < NV; q++) Lr[q] += (sF[(size_t)flo * NV + q] - sF[(size_t)fhi * NV + q]) * ih;
+            }
+            __syncthreads();
+        }
+        // ---- cell update ----
+        if (inside) {
+            int c = i + g.n[0] * (j + g.n[1] * kk);
+            if (BAND) {
+                double gv[3];
+                double gn = iface<D>(g, i, j, kk, gv);
+                if (gn > 0.0) {
+                    double sg = k == 0 ? 1.0 : -1.0, pp = g.ps[c];
+                    for (int e = 0; e < D; e++) Lr[1 + e] += -sg * pp * gv[e];
+                    Lr[D + 1] += -sg * pp * g.us[c] * gn;
+                }
+            }
+            const double* sin_ = (BAND && self2 && g.M[c]) ? self2 : in;
+            double* dst = (BAND && tmp && !(g.tflag[t] & 4)) ? tmp : out;
+            double Uo[NV];
+#pragma unroll
+            for (int q = 0; q < NV; q++) {
+                size_t e = (size_t)q * g.nc + c;
+                double sv = sin_[e] + dt * Lr[q];
+                Uo[q] = (a == 0.0) ? sv : a * base[e] + (1.0 - a) * sv;
+                dst[e] = Uo[q];
+            }
+            if (!BAND && cfl) {
+                double W[NV];
+                if (!cons2prim<D>(gm, pi, Uo, W)) flag_error(g, ERR_NONPHYS);
+                double cs = csound(gm, pi, W[0], W[D + 1]), sp = 0.0;
+                for (int e = 0; e < D; e++) sp += (fabs(W[1 + e]) + cs) / g.h;
+                cmax = fmax(cmax, sp);
+                ccnt++;
+            }
+        }
+    }
+    if (!BAND && cfl) {
+        if (lr.begin >= lr.end) return;   // idle block: nothing to reduce
+        for (int off = 32; off > 0; off >>= 1) {
+            cmax = fmax(cmax, __shfl_down(cmax, off, 64));
+            ccnt += __shfl_down(ccnt, off, 64);
+        }
+        int lane = tid & 63, wid = tid >> 6;
+        if (lane == 0) { sMax[wid] = cmax; sCnt[wid] = ccnt; }
+        __syncthreads();
+        if (tid == 0) {
+            for (int w = 1; w < (NT + 63) / 64; w++) { cmax = fmax(cmax, sMax[w]); ccnt += sCnt[w]; }
+            if (!(cmax >= 0.0) || isinf(cmax)) { flag_error(g, ERR_NONPHYS); cmax = 0.0; }
+            atomicMax(&g.red[k], (unsigned long long)__double_as_longlong(cmax));
+            atomicAdd(&g.red[2 + k], ccnt);
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
 // level set: one Shu-Osher stage of Eq. (LS:linearadvection), WENO5 upwind
 // derivatives, band cells only
 // ---------------------------------------------------------------------------
@@ -2314,7 +2530,7 @@ struct Engine {
             (void)hipEventRecord(s.ev_band[k], s.stream);
             s.band_rec[k] = true;
         }
-        fused_cfl = cfl && D <= 2;
+        fused_cfl = cfl;
     }
     // order the outstanding bulk stages before what follows on the stream
     void join()
@@ -2338,8 +2554,8 @@ struct Engine {
             hipExtLaunchKernelGGL(k_stage_lds<D, BAND>, gr, dim3(StageWG<D>::N), 0, st, e0, e1, 0, g, list, k, in,
                                   self2, base, out, a, dt, wflux, s.wcur, cfl, tmp);
         else
-            hipExtLaunchKernelGGL(k_stage<D, BAND>, gr, dim3(wg()), 0, st, e0, e1, 0, g, list, k, in, self2, base,
-                                  out, a, dt, wflux, s.wcur, tmp);
+            hipExtLaunchKernelGGL(k_stage_lds3<BAND>, gr, dim3(SHARP_WG3), 0, st, e0, e1, 0, g, list, k, in, self2,
+                                  base, out, a, dt, wflux, s.wcur, cfl, tmp);
     }
     void profile_flush()
     {
@@ -2675,13 +2891,21 @@ struct Engine {
             st->last_dt[1] = dt[1];
             if (!(fmin(dt[0], dt[1]) > 0.0)) { set_error("invalid time step"); rc = SIM_ENONPHYS; break; }
             if (mode == SIM_SINGLE_DT) {
-                double d = dt[0] < dt[1] ? dt[0] : dt[1];
+                double d = s.o.dt_fixed > 0.0 ? s.o.dt_fixed : (dt[0] < dt[1] ? dt[0] : dt[1]);
                 if (d > t_end - s.t) d = t_end - s.t;
+                if (s.o.tape) {
+                    rc = tape_step(s, d);
+                    if (rc != SIM_OK) break;
+                }
                 step_single(d);
                 st->cycles++;
                 for (int k = 0; k < 2; k++) { st->steps[k]++; st->cell_updates[k] += cnt[k]; }
                 st->last_n = 1.0;
             } else {
+                if (s.o.tape && s.tape_fluid >= 0) {
+                    s.tape_fluid = -1;
+                    s.tape_why = "the run took accelerated (multi-dt) cycles: the tape records single-dt steps";
+                }
                 rc = cycle(dt, cnt, t_end, st);
                 if (rc != SIM_OK) break;
             }
@@ -2725,6 +2949,7 @@ struct Engine {
         s.wcur = 0;
         s.vcur = 0;
         s.has_state = true;
+        if (s.o.tape) return tape_begin(s, prim);
         return SIM_OK;
     }
 
@@ -2767,6 +2992,16 @@ sim_status engine_advance(Sim& s, double t_end, int mode, long long max_cycles, 
         return SIM_EDEVICE;
     }
     return rc;
+}
+
+void engine_bulk_stage(Sim& s, int k, const double* in, const double* base, double* out, double a, double dt)
+{
+    const int list = k == 0 ? LIST_BULK0 : LIST_BULK1;
+    switch (s.g.D) {
+    case 1: Engine<1>(s).launch_stage<false>(s.stream, list, k, in, nullptr, base, out, a, dt, 0.0, 0, nullptr); break;
+    case 2: Engine<2>(s).launch_stage<false>(s.stream, list, k, in, nullptr, base, out, a, dt, 0.0, 0, nullptr); break;
+    default: Engine<3>(s).launch_stage<false>(s.stream, list, k, in, nullptr, base, out, a, dt, 0.0, 0, nullptr); break;
+    }
 }
 
 sim_status engine_bflux(Sim& s, double out[2][5])

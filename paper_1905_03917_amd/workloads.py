@@ -17,6 +17,7 @@ re-posed with stiffened-gas water gamma=4.4, p_inf=6e8 Pa and air gamma=1.4):
   shock_droplet_3d Mach-1.5 air shock hitting a water droplet
   smooth_2d        Gaussian acoustic pulse in air crossing a flat interface
   droplet_2d       periodic translation of a water droplet (Sec. 4.2 analogue)
+  pulse_air        acoustic pulse in a grid filled by air (differentiable runs)
 """
 from __future__ import annotations
 
@@ -191,6 +192,47 @@ def entropy_wave_1d(n=64, amp=0.2, u=1.0, p=1.0, t_end=0.1):
     st[0] = 1.0 + amp * np.sin(2 * np.pi * x)
     prim = np.stack([st, np.stack([np.ones(n), np.zeros(n), np.ones(n)])])
     return _case(1, n, 1, (1.4, 0.0), (1.4, 0.0), phi, prim, t_end, "entropy_wave_1d")
+
+
+def pulse_air(n=64, ndim=2, seed=0, amp=1.0e3, width=0.05, bc=0, t_end=None, u0=None, bg=0.0):
+    """Single fluid (air, phi < 0 everywhere): a Gaussian pressure pulse
+    p' = amp exp(-|x - x0|^2 / width^2) with rho' = p'/c0^2 (c0^2 = 1.4e5),
+    centred near (0.4, 0.5, 0.5) with a seeded sub-cell offset, in air at
+    rest or moving with the uniform velocity u0 (one entry per direction),
+    optionally over a smooth background wave of amplitude bg (Pa),
+    bg sin(2 pi (x + 0.1)) cos(2 pi (y - 0.2)) ..., with the same isentropic
+    density perturbation.
+    The smooth acoustic case of the differentiable configuration without its
+    water half (the adjoint covers runs in which one fluid fills the grid)."""
+    h, grid = _grid(ndim, n)
+    r = _rng(seed)
+    c0 = [0.4, 0.5, 0.5][:ndim]
+    c = [ci + r.uniform(-0.5, 0.5) * h for ci in c0]
+    r2 = sum((g - ci) ** 2 for g, ci in zip(grid, c))
+    pp = amp * np.exp(-r2 / width ** 2)
+    if bg:
+        wave = np.sin(2 * np.pi * (grid[0] + 0.1))
+        for d in range(1, ndim):
+            wave = wave * np.cos(2 * np.pi * (grid[d] - 0.2 * d))
+        pp = pp + bg * wave
+    pp = pp.reshape(-1)
+    nc = n ** ndim
+    air = _fill(ndim, nc, dict(rho=1.0, p=1.0e5))
+    air[0] += pp / 1.4e5
+    air[ndim + 1] += pp
+    if u0 is not None:
+        for d in range(ndim):
+            air[1 + d] = u0[d]
+    other = _fill(ndim, nc, dict(rho=1000.0, p=1.0e5))
+    phi = -np.ones(nc)
+    return _case(ndim, n, bc, AIR, WATER, phi, np.stack([air, other]),
+                 t_end if t_end is not None else 1e30, "pulse_air_%dd" % ndim, centre=c)
+
+
+def probe_cells(n, ndim=2, count=16, seed=0):
+    """Seeded distinct cell indices (x fastest) for a pressure-probe loss."""
+    r = _rng(seed + 1000)
+    return np.sort(r.choice(n ** ndim, size=count, replace=False))
 
 
 def CONFIGS():

@@ -1,0 +1,153 @@
+"""GPU adjoint (sim_backward / AdvanceFn) of single-fluid single-dt runs:
+against the oracle-side reference gradient on the same inputs and step
+schedule, against central finite differences of the GPU forward, bitwise
+independence of the checkpoint interval, and the refused cases."""
+import numpy as np
+import pytest
+
+import _adjoint_cases as AC
+
+pytestmark = pytest.mark.gpu
+
+GAMMA, PINF = 1.4, 2.0e4
+
+
+def _setup(n, ndim, bc):
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    c = AC.case(n, ndim, bc=bc)
+    c["gamma"] = [GAMMA, c["gamma"][1]]
+    c["pinf"] = [PINF, c["pinf"][1]]
+    return c
+
+
+def _dt0(c):
+    """CFL step of the initial state (the fixed step of these runs)"""
+    W = c["prim"][0]
+    D = c["ndim"]
+    cs = np.sqrt(GAMMA * (W[D + 1] + PINF) / W[0])
+    s = sum((np.abs(W[1 + d]) + cs) / c["h"] for d in range(D))
+    return 0.6 / s.max()
+
+
+def _gpu_grad(c, steps, rk=3, ckpt=20):
+    import torch
+    import paper_1905_03917_amd as P
+    dt = _dt0(c)
+    prim = torch.tensor(c["prim"], device="cuda", requires_grad=True)
+    eos = torch.tensor([[GAMMA, PINF], [c["gamma"][1], c["pinf"][1]]], dtype=torch.float64, device="cuda",
+                       requires_grad=True)
+    cons = P.AdvanceFn.apply(prim, eos, c, steps * dt, dict(rk=rk, ckpt_every=ckpt, dt_fixed=dt))
+    D = c["ndim"]
+    U = cons[0]
+    ke = 0.5 * (U[1:D + 1] ** 2).sum(0) / U[0]
+    p = (eos[0, 0] - 1.0) * (U[D + 1] - ke) - eos[0, 0] * eos[0, 1]
+    pr = torch.tensor(AC.probes(c["n"][0], D), device="cuda")
+    J = ((p[pr] - AC.P0) ** 2).sum() / 1e6
+    J.backward()
+    return float(J), prim.grad[0].cpu().numpy(), eos.grad[0].cpu().numpy(), dt
+
+
+@pytest.mark.parametrize("ndim,n,bc,rk", [(1, 64, 0, 3), (1, 50, 1, 3), (2, 24, 0, 3), (2, 20, 1, 3), (2, 20, 0, 2),
+                                          (3, 10, 0, 3)])
+def test_gpu_gradient_matches_reference(ndim, n, bc, rk):
+    import torch
+    from oracle import adjoint_ref as R
+    c = _setup(n, ndim, bc)
+    steps = 6
+    print("adjoint case ndim=%d n=%d bc=%d rk=%d" % (ndim, n, bc, rk), flush=True)
+    Jg, gp, ge, dt = _gpu_grad(c, steps, rk=rk, ckpt=4)
+    prim0 = torch.tensor(c["prim"][0], requires_grad=True)
+    gam = torch.tensor(GAMMA, dtype=torch.float64, requires_grad=True)
+    pin = torch.tensor(PINF, dtype=torch.float64, requires_grad=True)
+    U, _ = R.run(prim0, gam, pin, c, 1e30, rk=rk, dts=[dt] * steps)
+    p = R.pressure(U, gam, pin)
+    pr = torch.tensor(AC.probes(n, ndim))
+    J = ((p[pr] - AC.P0) ** 2).sum() / 1e6
+    J.backward()
+    assert abs(Jg - float(J)) <= 1e-10 * abs(float(J))
+    ref = prim0.grad.numpy()
+    for q in range(ndim + 2):
+        err = np.abs(gp[q] - ref[q]).max() / np.abs(ref[q]).max()
+        assert err <= 1e-9, (q, err)
+    for got, want in ((ge[0], float(gam.grad)), (ge[1], float(pin.grad))):
+        assert abs(got - want) <= 1e-9 * abs(want), (got, want)
+
+
+def test_gpu_gradient_matches_finite_differences():
+    """directional derivatives of J through 10 steps on 64^2, against central
+    differences of the GPU forward on the same fixed step schedule"""
+    import torch
+    import paper_1905_03917_amd as P
+    n, ndim, steps = 64, 2, 10
+    c = _setup(n, ndim, 0)
+    J0, gp, ge, dt = _gpu_grad(c, steps)
+    pr = AC.probes(n, ndim)
+
+    def J_at(prim0, gm=GAMMA, pi=PINF):
+        cc = dict(c)
+        cc["gamma"] = [gm, c["gamma"][1]]
+        cc["pinf"] = [pi, c["pinf"][1]]
+        prim = c["prim"].copy()
+        prim[0] = prim0
+        cc["prim"] = prim
+        s = P.Sim(cc, dt_fixed=dt)
+        s.advance(steps * dt, mode=P.SIM_SINGLE_DT)
+        _, cons, _ = s.state(device=False)
+        s.close()
+        U = cons[0]
+        p = (gm - 1.0) * (U[3] - 0.5 * (U[1] ** 2 + U[2] ** 2) / U[0]) - gm * pi
+        return ((p[pr] - AC.P0) ** 2).sum() / 1e6
+
+    x0 = c["prim"][0]
+    for q in range(ndim + 2):
+        dirn = np.zeros_like(x0)
+        dirn[q] = AC.direction(n, ndim, seed=21 + q)[q]
+        eps = 1e-6
+        fd = (J_at(x0 + eps * dirn) - J_at(x0 - eps * dirn)) / (2 * eps)
+        ad = float((gp * dirn).sum())
+        print("component %d: adjoint %.12e  finite difference %.12e" % (q, ad, fd))
+        assert abs(ad - fd) <= 1e-6 * abs(fd), (q, ad, fd)
+    for j, (gm, pi, e) in enumerate(((GAMMA, PINF, GAMMA * 1e-6), (GAMMA, PINF, PINF * 1e-6))):
+        if j == 0:
+            fd = (J_at(x0, gm + e, pi) - J_at(x0, gm - e, pi)) / (2 * e)
+        else:
+            fd = (J_at(x0, gm, pi + e) - J_at(x0, gm, pi - e)) / (2 * e)
+        print("eos %d: adjoint %.12e  finite difference %.12e" % (j, ge[j], fd))
+        assert abs(ge[j] - fd) <= 1e-6 * abs(fd), (j, ge[j], fd)
+
+
+def test_checkpoint_interval_does_not_change_the_gradient():
+    c = _setup(32, 2, 1)
+    res = [_gpu_grad(c, 7, ckpt=k) for k in (1, 3, 100)]
+    for r in res[1:]:
+        np.testing.assert_array_equal(r[1], res[0][1])
+        np.testing.assert_array_equal(r[2], res[0][2])
+
+
+def test_backward_refuses_uncovered_runs():
+    import torch
+    import paper_1905_03917_amd as P
+    from paper_1905_03917_amd import workloads as WL
+    g = np.zeros((2, 4, 32 * 32))
+    # no tape
+    c = _setup(32, 2, 0)
+    s = P.Sim(c)
+    s.advance(1e30, mode=P.SIM_SINGLE_DT, max_cycles=1)
+    with pytest.raises(P.SimError) as e:
+        s.backward(g)
+    assert e.value.status == -5
+    # an interface in the grid
+    b = WL.shock_bubble_2d(n=32, seed=0)
+    s = P.Sim(b, tape=1)
+    s.advance(1e30, mode=P.SIM_SINGLE_DT, max_cycles=1)
+    with pytest.raises(P.SimError) as e:
+        s.backward(g)
+    assert e.value.status == -1 and "interface" in str(e.value)
+    # accelerated cycles
+    s = P.Sim(c, tape=1)
+    s.advance(1e30, mode=P.SIM_MULTI_DT, max_cycles=1)
+    with pytest.raises(P.SimError) as e:
+        s.backward(g)
+    assert e.value.status == -1
+    torch.cuda.synchronize()
