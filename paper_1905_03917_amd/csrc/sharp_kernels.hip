@@ -1277,7 +1277,7 @@ __global__ void k_zero_red(Dev g)
 }
 
 // ---------------------------------------------------------------------------
-// one Shu-Osher stage of fluid k:
+// one Shu-Osher stage of fluid k (the stage kernels below):
 //   out = a*base + (1-a)*(self + dt*L),  L = sum_d (A_lo F_lo - A_hi F_hi)/dx + X/dV
 // Face fluxes of a tile are computed once into LDS (the high faces of the
 // tile edge are recomputed by the neighbour tile), then combined per cell.
@@ -1287,8 +1287,9 @@ __global__ void k_zero_red(Dev g)
 template <int D> struct FaceCount;
 template <> struct FaceCount<1> { static constexpr int n0 = 257, n1 = 0, n2 = 0; };
 template <> struct FaceCount<2> { static constexpr int n0 = 17 * 16, n1 = 16 * 17, n2 = 0; };
-template <> struct FaceCount<3> { static constexpr int n0 = 9 * 8 * 4, n1 = 8 * 9 * 4, n2 = 8 * 8 * 5; };
 
+// state of fluid k at cell c for a stage: primitives W and conservative U
+// (ghost states below alpha_mix on band tiles)
 template <int D, bool BAND>
 __device__ __forceinline__ void load_state(const Dev& g, int k, const double* in, const double* self2, int wb,
                                            int c, double* W, double* U)
@@ -1310,125 +1311,10 @@ __device__ __forceinline__ void load_state(const Dev& g, int k, const double* in
     cons2prim<D>(g.gam[k], g.pinf[k], U, W);
 }
 
-template <int D, bool BAND>
-__global__ void __launch_bounds__(SHARP_WG) k_stage(Dev g, int list, int k, const double* in, const double* self2,
-                                                   const double* base, double* out, double a, double dt,
-                                                   double wflux, int wb, double* tmp)
-{
-    constexpr int NV = D + 2;
-    constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
-    constexpr int F0 = FaceCount<D>::n0, F1 = FaceCount<D>::n1, F2 = FaceCount<D>::n2;
-    constexpr int FT = F0 + F1 + F2;
-    __shared__ double sF[FT * NV];
-    const int* L = list_ptr(g, list);
-    const double gm = g.gam[k], pi = g.pinf[k];
-    const double farea = D == 1 ? 1.0 : (D == 2 ? g.h : g.h * g.h);
-    const ListRange lr = xcd_range(list_count(g, list));
-    for (int ti = lr.begin; ti < lr.end; ti += lr.step) {
-        int t = L[ti];
-        int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1], tz = t / (g.nt[0] * g.nt[1]);
-        int ox = tx * TX, oy = ty * TY, oz = tz * TZ;
-        // ---- face fluxes ----
-        for (int f = threadIdx.x; f < FT; f += SHARP_WG) {
-            int d, li, lj, lk;
-            if (f < F0) { d = 0; li = f % (TX + 1); lj = (f / (TX + 1)) % TY; lk = f / ((TX + 1) * TY); }
-            else if (f < F0 + F1) { int r = f - F0; d = 1; li = r % TX; lj = (r / TX) % (TY + 1); lk = r / (TX * (TY + 1)); }
-            else { int r = f - F0 - F1; d = 2; li = r % TX; lj = (r / TX) % TY; lk = r / (TX * TY); }
-            int i = ox + li, j = oy + lj, kk = oz + lk;
-            int fi[3] = {i, j, kk};
-            bool ok = true;
-            for (int e = 0; e < 3; e++) ok &= (e == d) ? fi[e] <= g.n[e] : fi[e] < g.n[e];
-            double* Fo = sF + (size_t)f * NV;
-            if (!ok) { for (int q = 0; q < NV; q++) Fo[q] = 0.0; continue; }
-            double A = 1.0;
-            if (BAND) {
-                A = g.ap[d][fidx(g, i, j, kk)];
-                if (k == 1) A = 1.0 - A;
-                if (!(A > 0.0)) { for (int q = 0; q < NV; q++) Fo[q] = 0.0; continue; }
-            }
-            // six-cell stencil i-3 .. i+2 along d; face between m = 2 and m = 3
-            double Us[6][NV], Fs[6][NV];
-            double amax = 0.0;
-#pragma unroll
-            for (int m = 0; m < 6; m++) {
-                int off = m - 3;
-                int c = cidx(g, i + (d == 0) * off, j + (d == 1) * off, kk + (d == 2) * off);
-                double W[NV];
-                load_state<D, BAND>(g, k, in, self2, wb, c, W, Us[m]);
-                double un = W[1 + d], p = W[D + 1];
-                Fs[m][0] = Us[m][0] * un;
-#pragma unroll
-                for (int e = 0; e < D; e++) Fs[m][1 + e] = Us[m][1 + e] * un;
-                Fs[m][1 + d] += p;
-                Fs[m][D + 1] = (Us[m][D + 1] + p) * un;
-                amax = fmax(amax, fabs(un) + csound(gm, pi, W[0], p));
-            }
-#pragma unroll
-            for (int q = 0; q < NV; q++) {
-                double fp[5], fm[5];
-#pragma unroll
-                for (int m = 0; m < 5; m++) {
-                    fp[m] = 0.5 * (Fs[m][q] + amax * Us[m][q]);
-                    fm[m] = 0.5 * (Fs[m + 1][q] - amax * Us[m + 1][q]);
-                }
-                double Fh = weno5(fp[0], fp[1], fp[2], fp[3], fp[4], g.eps)
-                          + weno5(fm[4], fm[3], fm[2], fm[1], fm[0], g.eps);
-                Fo[q] = A * Fh;
-            }
-            // boundary-face inflow bookkeeping (zero-gradient boundaries)
-            if (g.bc[d] == 0 && wflux != 0.0 && (fi[d] == 0 || fi[d] == g.n[d])) {
-                int side = fi[d] == 0 ? 0 : 1;
-                int o1 = d == 0 ? j : i, o2 = d == 2 ? j : kk;
-                int n1 = d == 0 ? g.n[1] : g.n[0];
-                int b = g.bface_off[d][side] + o1 + n1 * o2;
-                double sgn = side == 0 ? 1.0 : -1.0;
-                for (int q = 0; q < NV; q++) g.bacc[k][(size_t)q * g.nbface + b] += sgn * wflux * farea * Fo[q];
-            }
-        }
-        __syncthreads();
-        // ---- cell update ----
-        {
-            int li = threadIdx.x % TX, lj = (threadIdx.x / TX) % TY, lk = threadIdx.x / (TX * TY);
-            int i = ox + li, j = oy + lj, kk = oz + lk;
-            if (i < g.n[0] && j < g.n[1] && kk < g.n[2]) {
-                int c = i + g.n[0] * (j + g.n[1] * kk);
-                double Lr[NV];
-                for (int q = 0; q < NV; q++) Lr[q] = 0.0;
-#pragma unroll
-                for (int d = 0; d < D; d++) {
-                    int flo, fhi;
-                    if (d == 0) { flo = li + (TX + 1) * (lj + TY * lk); fhi = flo + 1; }
-                    else if (d == 1) { flo = F0 + li + TX * (lj + (TY + 1) * lk); fhi = flo + TX; }
-                    else { flo = F0 + F1 + li + TX * (lj + TY * lk); fhi = flo + TX * TY; }
-                    for (int q = 0; q < NV; q++) Lr[q] += (sF[(size_t)flo * NV + q] - sF[(size_t)fhi * NV + q]) / g.h;
-                }
-                if (BAND) {
-                    double gv[3];
-                    double gn = iface<D>(g, i, j, kk, gv);
-                    if (gn > 0.0) {
-                        double sg = k == 0 ? 1.0 : -1.0, p = g.ps[c];
-                        for (int d = 0; d < D; d++) Lr[1 + d] += -sg * p * gv[d];
-                        Lr[D + 1] += -sg * p * g.us[c] * gn;
-                    }
-                }
-                const double* sin_ = (BAND && self2 && g.M[c]) ? self2 : in;
-                double* dst = (BAND && tmp && !(g.tflag[t] & 4)) ? tmp : out;
-                for (int q = 0; q < NV; q++) {
-                    size_t e = (size_t)q * g.nc + c;
-                    double s = sin_[e] + dt * Lr[q];
-                    dst[e] = (a == 0.0) ? s : a * base[e] + (1.0 - a) * s;
-                }
-            }
-        }
-        __syncthreads();
-    }
-}
-
 // ---------------------------------------------------------------------------
 // LDS-staged stage kernel (1-D and 2-D): the primitives of the tile and its
 // three-cell halo are computed once per cell into LDS (SoA), every face flux
 // of the tile is computed once from LDS, then each cell combines its faces.
-// Same arithmetic as k_stage above.
 // ---------------------------------------------------------------------------
 template <int D> struct Region;
 template <> struct Region<1> { static constexpr int X = 256 + 6, Y = 1; };
@@ -1645,7 +1531,7 @@ __global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, in
 // direction's region and faces (49 KB).  Same arithmetic as the 2-D kernel.
 // ---------------------------------------------------------------------------
 #ifndef SHARP_WG3
-#define SHARP_WG3 320
+#define SHARP_WG3 256
 #endif
 #ifndef SHARP_WG3_WAVES
 #define SHARP_WG3_WAVES 3

@@ -49,7 +49,7 @@ def _gpu_grad(c, steps, rk=3, ckpt=20):
 
 
 @pytest.mark.parametrize("ndim,n,bc,rk", [(1, 64, 0, 3), (1, 50, 1, 3), (2, 24, 0, 3), (2, 20, 1, 3), (2, 20, 0, 2),
-                                          (3, 10, 0, 3)])
+                                          (3, 12, 0, 3)])
 def test_gpu_gradient_matches_reference(ndim, n, bc, rk):
     import torch
     from oracle import adjoint_ref as R
@@ -67,8 +67,9 @@ def test_gpu_gradient_matches_reference(ndim, n, bc, rk):
     J.backward()
     assert abs(Jg - float(J)) <= 1e-10 * abs(float(J))
     ref = prim0.grad.numpy()
-    for q in range(ndim + 2):
-        err = np.abs(gp[q] - ref[q]).max() / np.abs(ref[q]).max()
+    errs = [np.abs(gp[q] - ref[q]).max() / np.abs(ref[q]).max() for q in range(ndim + 2)]
+    print("relative max error per component", errs)
+    for q, err in enumerate(errs):
         assert err <= 1e-9, (q, err)
     for got, want in ((ge[0], float(gam.grad)), (ge[1], float(pin.grad))):
         assert abs(got - want) <= 1e-9 * abs(want), (got, want)
@@ -99,20 +100,26 @@ def test_gpu_gradient_matches_finite_differences():
         p = (gm - 1.0) * (U[3] - 0.5 * (U[1] ** 2 + U[2] ** 2) / U[0]) - gm * pi
         return ((p[pr] - AC.P0) ** 2).sum() / 1e6
 
+    def central(f, e):
+        # central differences at e and e/2, Richardson-extrapolated (the
+        # O(e^2) truncation cancels)
+        d1 = (f(e) - f(-e)) / (2 * e)
+        d2 = (f(e / 2) - f(-e / 2)) / e
+        return (4 * d2 - d1) / 3
+
     x0 = c["prim"][0]
     for q in range(ndim + 2):
         dirn = np.zeros_like(x0)
         dirn[q] = AC.direction(n, ndim, seed=21 + q)[q]
-        eps = 1e-6
-        fd = (J_at(x0 + eps * dirn) - J_at(x0 - eps * dirn)) / (2 * eps)
+        fd = central(lambda e: J_at(x0 + e * dirn), 2e-6)
         ad = float((gp * dirn).sum())
         print("component %d: adjoint %.12e  finite difference %.12e" % (q, ad, fd))
         assert abs(ad - fd) <= 1e-6 * abs(fd), (q, ad, fd)
-    for j, (gm, pi, e) in enumerate(((GAMMA, PINF, GAMMA * 1e-6), (GAMMA, PINF, PINF * 1e-6))):
+    for j in range(2):
         if j == 0:
-            fd = (J_at(x0, gm + e, pi) - J_at(x0, gm - e, pi)) / (2 * e)
+            fd = central(lambda e: J_at(x0, GAMMA + e, PINF), GAMMA * 2e-6)
         else:
-            fd = (J_at(x0, gm, pi + e) - J_at(x0, gm, pi - e)) / (2 * e)
+            fd = central(lambda e: J_at(x0, GAMMA, PINF + e), PINF * 2e-6)
         print("eos %d: adjoint %.12e  finite difference %.12e" % (j, ge[j], fd))
         assert abs(ge[j] - fd) <= 1e-6 * abs(fd), (j, ge[j], fd)
 
