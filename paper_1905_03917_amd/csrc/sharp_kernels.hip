@@ -743,8 +743,10 @@ __global__ void __launch_bounds__(SHARP_WG) k_prims(Dev g, int list, int k, cons
 // extension: one Jacobi sweep of the upwind steady state of
 // dq/dtau + n.grad q = 0 for both fluids' primitives
 // ---------------------------------------------------------------------------
+// copy: also copy the cells that are not extended (only the first sweep of a
+// call needs to: afterwards both Jacobi buffers hold the same values there)
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_extw(Dev g, int list, int in, int out, const double* cur)
+__global__ void __launch_bounds__(SHARP_WG) k_extw(Dev g, int list, int in, int out, const double* cur, int copy)
 {
     constexpr int NV = D + 2;
     const int* L = list_ptr(g, list);
@@ -763,7 +765,8 @@ __global__ void __launch_bounds__(SHARP_WG) k_extw(Dev g, int list, int in, int 
             bool target = alpha_k(g, k, c) < g.amix && !(sk * ph > g.extb * g.h);
             if (target && gm < 0.0) gm = grad_phi<D>(g, cur, c, gr);
             if (!target || !(gm > 0.0)) {
-                for (int q = 0; q < NV; q++) Wo[(size_t)q * g.nc + c] = Wi[(size_t)q * g.nc + c];
+                if (copy)
+                    for (int q = 0; q < NV; q++) Wo[(size_t)q * g.nc + c] = Wi[(size_t)q * g.nc + c];
                 continue;
             }
             int up[3];
@@ -785,7 +788,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_extw(Dev g, int list, int in, int 
 
 // level-set velocity: from the cut cells to the rest of the band
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_extv(Dev g, int list, int in, int out, const double* cur)
+__global__ void __launch_bounds__(SHARP_WG) k_extv(Dev g, int list, int in, int out, const double* cur, int copy)
 {
     const int* L = list_ptr(g, list);
     for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
@@ -798,7 +801,8 @@ __global__ void __launch_bounds__(SHARP_WG) k_extv(Dev g, int list, int in, int 
         double gr[3];
         double gm = cut ? 0.0 : grad_phi<D>(g, cur, c, gr);
         if (cut || !(gm > 0.0)) {
-            for (int e = 0; e < D; e++) g.v[out][e][c] = g.v[in][e][c];
+            if (copy)
+                for (int e = 0; e < D; e++) g.v[out][e][c] = g.v[in][e][c];
             continue;
         }
         double sg = phi_at(g, cur, c) < 0.0 ? -1.0 : 1.0;
@@ -2293,7 +2297,7 @@ struct Engine {
     void extw(const double* cur)
     {
         for (int it = 0; it < s.o.ext_iters; it++) {
-            k_extw<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, s.wcur, 1 - s.wcur, cur);
+            k_extw<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, s.wcur, 1 - s.wcur, cur, it == 0);
             s.wcur ^= 1;
         }
     }
@@ -2301,7 +2305,7 @@ struct Engine {
     void extv(const double* cur)
     {
         for (int it = 0; it < s.o.ext_iters; it++) {
-            k_extv<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, s.vcur, 1 - s.vcur, cur);
+            k_extv<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, s.vcur, 1 - s.vcur, cur, it == 0);
             s.vcur ^= 1;
         }
     }
@@ -2383,15 +2387,25 @@ struct Engine {
         int bl = k == 0 ? LIST_BULK0 : LIST_BULK1;
         const bool ov = s.side[k] != nullptr;
         hipStream_t bs = ov ? s.side[k] : s.stream;
+        // the band stage is enqueued first: on the critical path, it takes the
+        // CUs before the bulk stage fills them
+        hipEvent_t prev_band = nullptr;
         if (ov) {
             if (s.bulk_pending[k]) (void)hipStreamWaitEvent(s.stream, s.ev_bulk[k], 0);
+            prev_band = s.band_rec[k] ? s.ev_band[k] : nullptr;
+        }
+        launch_stage<true>(s.stream, LIST_BAND, k, in, self2, base, out, a, dt, wflux, 0, tmp);
+        if (ov) {
             if (g.use_sched) {
                 // a planned stage: the bulk kernel reads its step from the plan,
-                // so it also waits for everything enqueued so far (the planner)
+                // so it waits for everything enqueued so far (the planner)
                 (void)hipEventRecord(s.ev_band[k], s.stream);
-                s.band_rec[k] = true;
+                (void)hipStreamWaitEvent(bs, s.ev_band[k], 0);
+            } else if (prev_band) {
+                // the bulk stage reads ring-tile cells of `in`, written by the
+                // previous band stage
+                (void)hipStreamWaitEvent(bs, prev_band, 0);
             }
-            if (s.band_rec[k]) (void)hipStreamWaitEvent(bs, s.ev_band[k], 0);
         }
         if (cfl) k_zero_red<<<1, 64, 0, bs>>>(g);
         size_t ev = 0;
@@ -2410,10 +2424,7 @@ struct Engine {
         if (ov) {
             (void)hipEventRecord(s.ev_bulk[k], bs);
             s.bulk_pending[k] = true;
-        }
-        launch_stage<true>(s.stream, LIST_BAND, k, in, self2, base, out, a, dt, wflux, 0, tmp);
-        if (ov) {
-            (void)hipEventRecord(s.ev_band[k], s.stream);
+            if (!g.use_sched) (void)hipEventRecord(s.ev_band[k], s.stream);
             s.band_rec[k] = true;
         }
         fused_cfl = cfl;
