@@ -39,6 +39,9 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--case", default="shock_bubble_2d", choices=["shock_bubble_2d", "shock_droplet_3d"],
+                    help="workload of the timed cycles (the headline line is shock_bubble_2d at 1024^2; "
+                         "shock_droplet_3d at --n 256 is for profiling the 3-D path)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
@@ -376,9 +379,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, flush, dst
-    case = WL.shock_bubble_2d(n=a.n, seed=0)
+    case = getattr(WL, a.case)(n=a.n, seed=0)
     D = case["ndim"]
-    print("bench: shock_bubble_2d %dx%d, warmup %d, steps %d" % (a.n, a.n, a.warmup, a.steps), flush=True)
+    grid_name = "x".join([str(a.n)] * D)
+    print("bench: %s %s, warmup %d, steps %d" % (a.case, grid_name, a.warmup, a.steps), flush=True)
 
     sim = P.Sim(case)
     if a.warmup:
@@ -422,11 +426,13 @@ def main():
     sec_k = ms_k * 1e-3
     ach_tf = flops_k / sec_k / 1e12 if sec_k > 0 else 0.0
     ach_gbs = bytes_k / sec_k / 1e9 if sec_k > 0 else 0.0
-    traffic = measured_traffic()
+    # the counter record belongs to the 1024^2 shock-bubble workload
+    traffic = measured_traffic() if (a.case == "shock_bubble_2d" and a.n == 1024) else None
     roof = dict(bound="alu", achieved=round(ach_tf, 2), peak=round(FP64_VECTOR_TFLOPS, 1), unit="TFLOP/s",
                 frac=round(ach_tf / FP64_VECTOR_TFLOPS, 4),
                 traffic=round(traffic) if traffic else None,
-                kernel="k_stage_lds<2, false>", launches=launches, avg_ms=round(ms_k / max(launches, 1), 4),
+                kernel="k_stage_lds<%d, false>" % D if D <= 2 else "k_stage_lds3<false>", launches=launches,
+                avg_ms=round(ms_k / max(launches, 1), 4),
                 flops_per_launch=round(flops_k / max(launches, 1)),
                 algorithmic_bytes_per_launch=round(bytes_k / max(launches, 1)),
                 hbm=dict(achieved=round(ach_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -462,7 +468,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f64",
         "data": "synthetic",
-        "config": {"workload": "shock_bubble_2d %dx%d multi_dt" % (a.n, a.n), "cells": a.n * a.n,
+        "config": {"workload": "%s %s multi_dt" % (a.case, grid_name), "cells": a.n ** D,
                    "mode": "multi_dt", "rk": 3, "cfl": 0.6},
         "per_fluid": {"air_cell_updates_per_s": st["cell_updates"][0] / el,
                       "water_cell_updates_per_s": st["cell_updates"][1] / el,
