@@ -210,6 +210,7 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
         for (int d = 0; d < 3; d++) A(g.v[b][d], d < D ? (size_t)g.nc : 1);
     A(g.M, (size_t)g.nc); A(g.nearif, (size_t)g.nc);
     A(g.tcore, (size_t)g.ntiles); A(g.tflag, (size_t)g.ntiles); A(g.tsign, (size_t)g.ntiles);
+    A(g.tphimin, (size_t)g.ntiles);
     A(g.lists, (size_t)NLISTS * g.ntiles);
     // reductions (8 words) and list counts (16 ints) share one block, read
     // back with one copy; the counts, read by every grid-stride loop, sit

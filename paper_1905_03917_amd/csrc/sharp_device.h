@@ -55,6 +55,7 @@ struct Dev {
     double* dmix;     // mixing increments [NV][cells]
     double* bacc[2];  // boundary inflow accumulators [NV][nbface]
     // tiles
+    double* tphimin;  // per tile: min |phi| over the tile and its one-cell halo at the last geometry
     int* tcore;       // tile holds band cells
     int* tflag;       // bit0 band tile, bit1 candidate tile, bit2 ring tile
     int* tsign;       // fluid of a tile outside the band

@@ -316,16 +316,26 @@ __global__ void __launch_bounds__(SHARP_WG) k_geom_lds(Dev g, int list, const do
     constexpr int VX = TX + 1, VY = D > 1 ? TY + 1 : 1, VZ = D > 2 ? TZ + 1 : 1, VN = VX * VY * VZ;
     __shared__ double sP[CN];
     __shared__ double sV[VN];
+    __shared__ double sMin[SHARP_WG / 64];
     const int* L = list_ptr(g, list);
     for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
         int t = L[ti];
         int ox = (t % g.nt[0]) * TX, oy = ((t / g.nt[0]) % g.nt[1]) * TY, oz = (t / (g.nt[0] * g.nt[1])) * TZ;
-        // cells (ox-1 .. ox+TX) x ...
+        // cells (ox-1 .. ox+TX) x ...; also min |phi| over them (the mixing
+        // region of the tile)
+        double pmin = INFINITY;
         for (int r = threadIdx.x; r < CN; r += SHARP_WG) {
             int cx = r % CX, cy = (r / CX) % CY, cz = r / (CX * CY);
             sP[r] = phi_at(g, cur, cidx(g, ox - 1 + cx, D > 1 ? oy - 1 + cy : 0, D > 2 ? oz - 1 + cz : 0));
+            pmin = fmin(pmin, fabs(sP[r]));
         }
+        for (int off = 32; off > 0; off >>= 1) pmin = fmin(pmin, __shfl_down(pmin, off, 64));
+        if ((threadIdx.x & 63) == 0) sMin[threadIdx.x >> 6] = pmin;
         __syncthreads();
+        if (threadIdx.x == 0) {
+            for (int w = 1; w < SHARP_WG / 64; w++) pmin = fmin(pmin, sMin[w]);
+            g.tphimin[t] = pmin;
+        }
         // vertex (vx, vy, vz) <-> corner (ox+vx, ...): mean of cells (vx-1 .. vx) in region offset +1
         for (int r = threadIdx.x; r < VN; r += SHARP_WG) {
             int vx = r % VX, vy = (r / VX) % VY, vz = r / (VX * VY);
@@ -468,7 +478,8 @@ __device__ __forceinline__ bool mix_source(const Dev& g, const double* cur, int 
         double prod = 1.0;
         for (int d = 0; d < D; d++)
             if (m & (1 << d)) { cnt++; prod *= fabs(dir[d]); }
-        double b = cnt == 1 ? prod * prod : (cnt == 2 ? prod : pow(prod, 2.0 / 3.0));
+        // the three-axis weight |n_x n_y n_z|^(2/3) as a cube root of the square
+        double b = cnt == 1 ? prod * prod : (cnt == 2 ? prod : cbrt(prod * prod));
         beta[m - 1] = b;
         bsum += b;
     }
@@ -549,6 +560,15 @@ __device__ __forceinline__ void mix_gather(const Dev& g, int k, int c, int i, in
             }
 }
 
+// 3-D: no cell of the tile's mixing region can be a source (|phi| > the
+// source band at the last geometry, with two cells of margin for the level
+// set's change since then: one stage's advection and reinitialisation move
+// it by less than that), so the tile's mixing increments are all zero
+__device__ __forceinline__ bool mix_far(const Dev& g, int t)
+{
+    return g.tphimin[t] > (g.mixb + 2.0) * g.h;
+}
+
 // tabulate the mixing sources of the tile's region (cells outside the grid
 // map to their boundary images)
 template <int D>
@@ -587,7 +607,8 @@ __global__ void __launch_bounds__(SHARP_WG) k_mixdelta_lds(Dev g, int list, int 
     for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
         int ox, oy, oz;
         tile_origin<D>(g, L[ti], ox, oy, oz);
-        mix_sources<D>(g, k, ox, oy, oz, cur, sBeta, sTgt, sCell);
+        const bool far = D == 3 && mix_far(g, L[ti]);
+        if (!far) mix_sources<D>(g, k, ox, oy, oz, cur, sBeta, sTgt, sCell);
         __syncthreads();
         int li = threadIdx.x % TX, lj = (threadIdx.x / TX) % TY, lk = threadIdx.x / (TX * TY);
         int i = ox + li, j = oy + lj, kk = oz + lk;
@@ -596,7 +617,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_mixdelta_lds(Dev g, int list, int 
             if (g.M[c]) {
                 double vc[NV], dl[NV];
                 for (int q = 0; q < NV; q++) { vc[q] = val(q, c); dl[q] = 0.0; }
-                mix_gather<D>(g, k, c, i, j, kk, li, lj, lk, sBeta, sTgt, sCell, val, vc, dl);
+                if (!far) mix_gather<D>(g, k, c, i, j, kk, li, lj, lk, sBeta, sTgt, sCell, val, vc, dl);
                 for (int q = 0; q < NV; q++) g.dmix[(size_t)q * g.nc + c] = dl[q];
             }
         }
@@ -644,6 +665,7 @@ __device__ __forceinline__ void mix_tile(const Dev& g, int t, const MixPart& P, 
     };
     int ox, oy, oz;
     tile_origin<D>(g, t, ox, oy, oz);
+    if (D == 3 && mix_far(g, t)) do_mix = 0;
     if (do_mix) mix_sources<D>(g, k, ox, oy, oz, cur, sBeta, sTgt, sCell);
     __syncthreads();
     int li = threadIdx.x % TX, lj = (threadIdx.x / TX) % TY, lk = threadIdx.x / (TX * TY);
