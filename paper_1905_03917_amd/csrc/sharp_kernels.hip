@@ -773,6 +773,9 @@ __global__ void __launch_bounds__(SHARP_WG) k_extw(Dev g, int list, int in, int 
     constexpr int NV = D + 2;
     const int* L = list_ptr(g, list);
     for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+        // 3-D, after the first sweep: a tile beyond the extension depth (two
+        // cells of margin, as for mixing) holds no target
+        if (D == 3 && !copy && g.tphimin[L[ti]] > (g.extb + 2.0) * g.h) continue;
         int i, j, kk;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
         int c = i + g.n[0] * (j + g.n[1] * kk);
