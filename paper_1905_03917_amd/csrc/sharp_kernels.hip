@@ -560,10 +560,11 @@ __device__ __forceinline__ void mix_gather(const Dev& g, int k, int c, int i, in
             }
 }
 
-// 3-D: no cell of the tile's mixing region can be a source (|phi| > the
-// source band at the last geometry, with two cells of margin for the level
-// set's change since then: one stage's advection and reinitialisation move
-// it by less than that), so the tile's mixing increments are all zero
+// No cell of the tile's mixing region can be a source (|phi| > the source
+// band at the last geometry, with two cells of margin for the level set's
+// change since then: one stage's advection and reinitialisation move it by
+// less than that), so the tile's mixing increments are all zero.  The
+// geometry kernels record the per-tile minimum.
 __device__ __forceinline__ bool mix_far(const Dev& g, int t)
 {
     return g.tphimin[t] > (g.mixb + 2.0) * g.h;
@@ -607,7 +608,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_mixdelta_lds(Dev g, int list, int 
     for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
         int ox, oy, oz;
         tile_origin<D>(g, L[ti], ox, oy, oz);
-        const bool far = D == 3 && mix_far(g, L[ti]);
+        const bool far = mix_far(g, L[ti]);
         if (!far) mix_sources<D>(g, k, ox, oy, oz, cur, sBeta, sTgt, sCell);
         __syncthreads();
         int li = threadIdx.x % TX, lj = (threadIdx.x / TX) % TY, lk = threadIdx.x / (TX * TY);
@@ -665,7 +666,7 @@ __device__ __forceinline__ void mix_tile(const Dev& g, int t, const MixPart& P, 
     };
     int ox, oy, oz;
     tile_origin<D>(g, t, ox, oy, oz);
-    if (D == 3 && mix_far(g, t)) do_mix = 0;
+    if (mix_far(g, t)) do_mix = 0;
     if (do_mix) mix_sources<D>(g, k, ox, oy, oz, cur, sBeta, sTgt, sCell);
     __syncthreads();
     int li = threadIdx.x % TX, lj = (threadIdx.x / TX) % TY, lk = threadIdx.x / (TX * TY);
@@ -1907,6 +1908,7 @@ k_lsgeo_tb(Dev g, int list, int vin, int vout, int iters, const double* phin, do
     __shared__ double sL[LN];
     __shared__ uint8_t sM[LN], sN[LN];
     __shared__ double sV[GX * GY];
+    __shared__ double sMn[WGS / 64];
     const int* L = list_ptr(g, list);
     const bool last = K >= 0;
     if (g.use_sched) dt = g.sched[SCHED_DT];
@@ -2103,7 +2105,21 @@ k_lsgeo_tb(Dev g, int list, int vin, int vout, int iters, const double* phin, do
             }
             sV[r] = sum / (double)(1 << D);
         }
+        // min |phi| over the tile and its one-cell halo (the mixing region)
+        {
+            constexpr int MX = TX + 2, MN = MX * (D == 2 ? TY + 2 : 1);
+            double pmin = INFINITY;
+            for (int r = threadIdx.x; r < MN; r += WGS)
+                pmin = fmin(pmin, fabs(fin[(HL - 1 + r % MX) + LX * (D == 2 ? HL - 1 + r / MX : 0)]));
+            for (int off = 32; off > 0; off >>= 1) pmin = fmin(pmin, __shfl_down(pmin, off, 64));
+            if ((threadIdx.x & 63) == 0) sMn[threadIdx.x >> 6] = pmin;
+        }
         __syncthreads();
+        if (threadIdx.x == 0) {
+            double pmin = sMn[0];
+            for (int w = 1; w < WGS / 64; w++) pmin = fmin(pmin, sMn[w]);
+            g.tphimin[t] = pmin;
+        }
         for (int u = threadIdx.x; u < TX * TY; u += WGS) {
             int li = u % TX, lj = u / TX;
             int i = ox + li, j = oy + lj;
