@@ -470,9 +470,9 @@ def main():
         "data": "synthetic",
         "config": {"workload": "%s %s multi_dt" % (a.case, grid_name), "cells": a.n ** D,
                    "mode": "multi_dt", "rk": 3, "cfl": 0.6},
-        "per_fluid": {"air_cell_updates_per_s": st["cell_updates"][0] / el,
-                      "water_cell_updates_per_s": st["cell_updates"][1] / el,
-                      "steps": st["steps"]},
+        "per_fluid": {("%s_cell_updates_per_s" % ("air" if case["gamma"][k] == 1.4 else "water")):
+                      st["cell_updates"][k] / el for k in range(2)},
+        "steps_per_fluid": st["steps"],
         "single_dt": single,
         "matched_l1": ml1,
         "adjoint": adj,
