@@ -2398,7 +2398,6 @@ struct Engine {
     // mixes it into the stage buffer, optionally together with a second
     // mixed copy (the other fluid, or the slow fluid's interpolated state
     // for the next stage) and the level-set commit
-    static constexpr bool fmix = true;
     void mix_fused(const MixPart& A, const MixPart* B, const double* cur, const double* commit)
     {
         k_mix_parts<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, A, B ? *B : A, B ? 2 : 1, cur, commit,
@@ -2612,18 +2611,13 @@ struct Engine {
             double* out[2];
             for (int k = 0; k < 2; k++) {
                 out[k] = (st == ns - 1) ? g.X[k] : (st == 0 ? g.Y[k] : g.Z[k]);
-                stage(k, in[k], nullptr, g.X[k], out[k], A[st], dt, B[st] * dt, 0, fmix ? g.Tm[k] : nullptr);
+                stage(k, in[k], nullptr, g.X[k], out[k], A[st], dt, B[st] * dt, 0, g.Tm[k]);
             }
             const double* commit = nullptr;
-            const double* cur = ls_chain(st, st == ns - 1, A[st], dt, phin, fmix ? &commit : nullptr);
-            if (fmix) {
-                MixPart m1 = tm_part(1, out[1]);
-                mix_fused(tm_part(0, out[0]), &m1, cur, commit);
-                if (commit) cur = g.phiP;
-            } else {
-                mix(0, out[0], cur);
-                mix(1, out[1], cur);
-            }
+            const double* cur = ls_chain(st, st == ns - 1, A[st], dt, phin, &commit);
+            MixPart m1 = tm_part(1, out[1]);
+            mix_fused(tm_part(0, out[0]), &m1, cur, commit);
+            if (commit) cur = g.phiP;
             in[0] = out[0];
             in[1] = out[1];
             phin = cur;
@@ -2692,8 +2686,8 @@ struct Engine {
         auto fast_stage = [&](int q, const double*& in, const double*& phin, double dl, int fin, bool planned) {
             bool shared = false;
             if (q > 0) {
-                double theta = (fin && C[q] == 1.0) ? 1.0 : (tau + C[q] * dl) / t1;
-                if (!fmix) interp_slow(S, theta, phin);   // else done with the previous stage's mixing
+                // the slow fluid's interpolated state for this stage was
+                // built by the previous stage's mixing launch
                 shared = fin && C[q] == 1.0;
                 double w = !corr ? 0.0 : (shared ? -B[q] * t1 + B[q] * dl : B[q] * dl);
                 interaction(S == 0 ? g.T2 : in, S == 0 ? in : g.T2, phin, w, S);
@@ -2703,33 +2697,28 @@ struct Engine {
                 stage(S, g.Y[S], g.T2, g.X[S], ns == 2 ? g.X[S] : g.Z[S], A[q], t1, B[q] * t1);
             }
             double* out = (q == ns - 1) ? g.X[F] : (q == 0 ? g.Y[F] : g.Z[F]);
-            stage(F, in, nullptr, g.X[F], out, A[q], dl, B[q] * dl, (q == ns - 1 && !fin) ? 1 : 0,
-                  fmix ? g.Tm[F] : nullptr);
+            stage(F, in, nullptr, g.X[F], out, A[q], dl, B[q] * dl, (q == ns - 1 && !fin) ? 1 : 0, g.Tm[F]);
             // Eq. (secondcorrection); booked after the stage launch (the stage does not
             // read the correction) so that the GPU gets work soon after the readback
             if (q == 0 && !first && corr) corr_add(B[0] * dl, S);
             const double* commit = nullptr;
-            const double* cur = ls_chain(q, q == ns - 1, A[q], dl, phin, fmix ? &commit : nullptr);
-            if (fmix) {
-                if (q + 1 < ns) {
-                    // the slow fluid's state for the next stage, Eq. (interpolation)
-                    double theta1 = (fin && C[q + 1] == 1.0) ? 1.0 : (tau + C[q + 1] * dl) / t1;
-                    MixPart ms = interp_part(S, theta1);
-                    ms.sched_theta = planned ? 1 : 0;
-                    mix_fused(tm_part(F, out), &ms, cur, commit);
-                } else {
-                    mix_fused(tm_part(F, out), nullptr, cur, commit);
-                }
-                if (commit) cur = g.phiP;
+            const double* cur = ls_chain(q, q == ns - 1, A[q], dl, phin, &commit);
+            if (q + 1 < ns) {
+                // the slow fluid's state for the next stage, Eq. (interpolation)
+                double theta1 = (fin && C[q + 1] == 1.0) ? 1.0 : (tau + C[q + 1] * dl) / t1;
+                MixPart ms = interp_part(S, theta1);
+                ms.sched_theta = planned ? 1 : 0;
+                mix_fused(tm_part(F, out), &ms, cur, commit);
             } else {
-                mix(F, out, cur);
+                mix_fused(tm_part(F, out), nullptr, cur, commit);
             }
+            if (commit) cur = g.phiP;
             in = out;
             phin = cur;
         };
         // sub-steps after the first are planned on the device when every
         // kernel of a stage can take its step from there
-        const bool plan_dev = fmix && fused_ls();
+        const bool plan_dev = fused_ls();
         for (;;) {
             int hh = 0, fin = 0, q0 = 0;
             double dl = 0.0;
