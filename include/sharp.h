@@ -138,7 +138,10 @@ sim_status sim_advance(sim_t* s, double t_end, int mode, int64_t max_cycles, sim
  * fraction out (any pointer may be NULL). */
 sim_status sim_get_state(sim_t* s, double* phi, double* cons, double* alpha, int on_device);
 
-/* Total content sum_c dV cons[k][q][c] -> out[k*5 + q] (q < NV). */
+/* Conservation ledger (the totals whose drift Sec. 4.2 tracks): the total
+ * content sum_c dV cons[k][q][c] -> out[k*5 + q] (q < NV; 0 for q >= NV),
+ * by a fixed-order tree reduction on the device (the same state always gives
+ * the same bits).  out10 is a host array. */
 sim_status sim_totals(sim_t* s, double* out10);
 
 /* Kernel timing of the fused face-flux/RK stage kernel on bulk tiles: when

@@ -5,7 +5,7 @@ import subprocess
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsharp_hip.so")
-SOURCES = ["sharp_kernels.hip", "sharp_capi.hip", "sharp_adjoint.hip"]
+SOURCES = ["sharp_kernels.hip", "sharp_capi.hip", "sharp_adjoint.hip", "sharp_ledger.hip"]
 FLAGS = [
     "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
     # packed FP32 instructions are kept out of the code object

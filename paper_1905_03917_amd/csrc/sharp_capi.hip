@@ -358,21 +358,7 @@ sim_status sim_totals(sim_t* h, double* out10)
     if (!h || !out10) { set_error("null argument"); return SIM_EINVAL; }
     Sim& s = h->s;
     if (!s.has_state) { set_error("no state"); return SIM_ESTATE; }
-    int NV = s.g.D + 2;
-    size_t nc = s.g.nc;
-    std::vector<double> buf(nc);
-    double dv = std::pow(s.g.h, s.g.D);
-    SHARP_HIP(hipStreamSynchronize(s.stream));
-    for (int k = 0; k < 2; k++)
-        for (int q = 0; q < 5; q++) {
-            double sum = 0.0;
-            if (q < NV) {
-                SHARP_HIP(hipMemcpy(buf.data(), s.g.X[k] + q * nc, nc * sizeof(double), hipMemcpyDeviceToHost));
-                for (size_t c = 0; c < nc; c++) sum += buf[c];
-            }
-            out10[k * 5 + q] = sum * dv;
-        }
-    return SIM_OK;
+    return engine_totals(s, out10);
 }
 
 sim_status sim_profile(sim_t* h, int enable)

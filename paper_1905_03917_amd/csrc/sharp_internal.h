@@ -75,6 +75,8 @@ sim_status engine_bflux(Sim& s, double out[2][5]);
 // one bulk-tile stage of fluid k on the simulation stream (the forward
 // recomputation of the adjoint): out = a*base + (1-a)*(in + dt*L(in))
 void engine_bulk_stage(Sim& s, int k, const double* in, const double* base, double* out, double a, double dt);
+// conservation ledger (sharp_ledger.hip): out10[k*5 + q] = sum_c dV cons[k][q][c], zero for q >= NV
+sim_status engine_totals(Sim& s, double* out10);
 // adjoint (sharp_adjoint.hip)
 void tape_clear(Sim& s);
 sim_status tape_begin(Sim& s, const double* prim_dev);

@@ -160,6 +160,24 @@ def test_gpu_conservation(mode):
     assert np.all(drift[:4] <= 1e-12 * steps * scale[:4]), drift / scale
 
 
+def test_ledger_is_the_deterministic_sum_of_the_state():
+    """sim_totals (device tree reduction) against a compensated host sum of
+    the same state, and bit-identical on repeated calls."""
+    import math
+    c = WL.shock_bubble_2d(n=200, seed=4)
+    g = _gpu(c)
+    g.advance(1.0, mode=1, max_cycles=2)
+    tot = g.totals()
+    _, cons, _ = g.state(device=False)
+    dv = c["h"] ** 2
+    for k in range(2):
+        for q in range(4):
+            ref = math.fsum(cons[k, q]) * dv
+            assert abs(tot[k, q] - ref) <= 1e-13 * max(abs(ref), np.abs(cons[k, q]).sum() * dv), (k, q, tot[k, q], ref)
+        assert tot[k, 4] == 0.0
+    np.testing.assert_array_equal(tot, g.totals())
+
+
 def test_gpu_rk2_cycle_reduces_bitwise():
     """RK2 and n truncated to 1: the accelerated cycle equals the original step."""
     c = WL.tube_1d_single(n=200, seed=3)
