@@ -234,6 +234,27 @@ def test_full_size_shock_bubble_properties():
     np.testing.assert_allclose(c1[1][:, far], c0[1][:, far], rtol=4e-16, atol=0)
 
 
+def test_full_size_shock_droplet_3d_properties():
+    """256^3 shock-droplet, one accelerated cycle at the benchmark's launch
+    configuration: conservation per fluid, and the air ahead of the shock
+    and beyond the droplet untouched."""
+    c = WL.shock_droplet_3d(n=256, seed=0)
+    g = _gpu(c)
+    tot0 = g.totals()
+    _, c0, _ = g.state(device=False)
+    st = g.advance(1.0, mode=1, max_cycles=1)
+    assert st["steps"][0] > st["steps"][1]          # water sub-steps, one air step
+    tot1 = g.totals()
+    bf = st["bflux"]
+    steps = max(st["steps"])
+    assert np.all(np.abs(tot1[:, 0] - tot0[:, 0] - bf[:, 0]) <= 1e-12 * steps * np.abs(tot0[:, 0]))
+    _, c1, _ = g.state(device=False)
+    n = 256
+    X = (np.arange(n) + 0.5) / n
+    far = np.broadcast_to(X > 0.75, (n, n, n)).reshape(-1)
+    np.testing.assert_allclose(c1[1][:, far], c0[1][:, far], rtol=4e-16, atol=0)
+
+
 def test_error_paths():
     import paper_1905_03917_amd as P
     c = WL.tube_1d(n=64)
