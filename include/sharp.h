@@ -95,6 +95,9 @@ typedef struct {
     double dt_fixed;     /* > 0: single-dt steps of this length (the last one
                             clamped to t_end) instead of the CFL step, so that
                             perturbed runs share one schedule [0] */
+    int autotune;        /* time the first cycles with each candidate grid bound
+                            of the bulk-tile stage kernel and keep the fastest;
+                            results do not depend on the choice [0] */
 } sim_opts;
 
 typedef struct {
@@ -172,6 +175,10 @@ sim_status sim_profile_read(sim_t* s, double* ms, int64_t* launches, int64_t* ce
  * SIM_ESTATE without a tape, SIM_ENOMEM when the recomputation buffers
  * (3 ckpt_every states) do not fit. */
 sim_status sim_backward(sim_t* s, const double* g_cons, double* g_prim0, double* g_eos, int on_device);
+
+/* Launch configuration in use: the bulk-tile stage's grid bound (blocks)
+ * and whether the autotuner (opts->autotune) has finished choosing it. */
+sim_status sim_tuned(sim_t* s, int* bulk_blocks, int* done);
 
 void sim_destroy(sim_t* s);
 const char* sim_strerror(sim_status st);

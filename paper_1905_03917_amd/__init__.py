@@ -35,7 +35,7 @@ class Opts(C.Structure):
                 ("ext_iters", C.c_int), ("reinit_iters", C.c_int), ("weno_eps", C.c_double),
                 ("force_cycle", C.c_int), ("no_correction", C.c_int),
                 ("serial", C.c_int), ("tape", C.c_int), ("ckpt_every", C.c_int),
-                ("dt_fixed", C.c_double)]
+                ("dt_fixed", C.c_double), ("autotune", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -50,8 +50,8 @@ class Stats(C.Structure):
 
 
 EXPORTS = ["sim_default_opts", "sim_create", "sim_set_state", "sim_advance", "sim_get_state",
-           "sim_totals", "sim_profile", "sim_profile_read", "sim_backward", "sim_destroy", "sim_strerror",
-           "sim_last_error"]
+           "sim_totals", "sim_profile", "sim_profile_read", "sim_backward", "sim_tuned", "sim_destroy",
+           "sim_strerror", "sim_last_error"]
 
 _lib = None
 
@@ -76,13 +76,14 @@ def lib():
         L.sim_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int64)]
         L.sim_backward.argtypes = [vp, vp, vp, vp, C.c_int]
+        L.sim_tuned.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.sim_destroy.argtypes = [vp]
         L.sim_destroy.restype = None
         L.sim_strerror.argtypes = [C.c_int]
         L.sim_strerror.restype = C.c_char_p
         L.sim_last_error.restype = C.c_char_p
         for f in ("sim_create", "sim_set_state", "sim_advance", "sim_get_state", "sim_totals",
-                  "sim_profile", "sim_profile_read", "sim_backward"):
+                  "sim_profile", "sim_profile_read", "sim_backward", "sim_tuned"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -217,6 +218,13 @@ class Sim:
             _check(lib().sim_backward(self.h, C.c_void_p(g.ctypes.data), C.c_void_p(out.ctypes.data),
                                       C.c_void_p(eos.ctypes.data), 0), "sim_backward")
         return out, eos.reshape(2, 2)
+
+    def tuned(self):
+        """(bulk-stage grid bound in use, whether the autotuner has finished)"""
+        b = C.c_int()
+        d = C.c_int()
+        _check(lib().sim_tuned(self.h, C.byref(b), C.byref(d)), "sim_tuned")
+        return b.value, bool(d.value)
 
     def profile(self, enable=True):
         _check(lib().sim_profile(self.h, int(enable)), "sim_profile")

@@ -42,6 +42,14 @@ struct Sim {
     double* ap_alt[3] = {nullptr, nullptr, nullptr};
     int max_blocks = 2048; // grid-stride bound for tile-list kernels
     int bulk_blocks = SHARP_BULK_BLOCKS;  // the same bound for the bulk-tile stages
+    // autotuner of bulk_blocks (o.autotune): candidate being timed (-1: the
+    // warm-up cycle), wall seconds per cell-update of each candidate
+    static constexpr int NTUNE = 4;
+    int tune_cur = -2;                    // -2: not started, NTUNE: done
+    double tune_cost[NTUNE] = {0, 0, 0, 0};
+    double tune_t0 = 0.0;
+    long long tune_cells0 = 0;
+    bool tune_open = false;
     bool has_state = false;
     double t = 0.0;
     int wcur = 0;          // Jacobi buffer holding the latest primitives

@@ -15,6 +15,7 @@
 // only walk the inner band tiles.  All per-cell state is
 // structure-of-arrays FP64 in HBM, x fastest, so a wavefront reads 64
 // consecutive doubles of one component.
+#include <chrono>
 #include <cmath>
 #include <cstring>
 #include <utility>
@@ -2814,6 +2815,7 @@ struct Engine {
             long long cnt[2];
             rc = prepare(true, dt, cnt);
             if (rc != SIM_OK) break;
+            if (s.o.autotune) tune_step(st);
             st->last_dt[0] = dt[0];
             st->last_dt[1] = dt[1];
             if (!(fmin(dt[0], dt[1]) > 0.0)) { set_error("invalid time step"); rc = SIM_ENONPHYS; break; }
@@ -2840,6 +2842,7 @@ struct Engine {
             done++;
         }
         join();
+        s.tune_open = false;    // time between calls is not a cycle
         if (rc == SIM_OK) {
             // late non-physical flags (stages after the last readback)
             SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s.stream));
@@ -2849,6 +2852,40 @@ struct Engine {
         if (s.prof) profile_flush();
         st->t = s.t;
         return rc;
+    }
+
+    // Autotuner of the bulk-stage grid bound: called at each cycle start,
+    // after the readback that ends the previous cycle's work.  One warm-up
+    // cycle, then one cycle per candidate, timed by the host clock per
+    // cell-update; then the fastest candidate stays.  The bound only changes
+    // how tiles are spread over blocks, never a result.
+    static double now_s()
+    {
+        return std::chrono::duration<double>(std::chrono::steady_clock::now().time_since_epoch()).count();
+    }
+    void tune_step(const sim_stats* st)
+    {
+        static const int cand[Sim::NTUNE] = {1024, 2048, 4096, 8192};
+        if (s.tune_cur >= Sim::NTUNE) return;
+        const long long cells = st->cell_updates[0] + st->cell_updates[1];
+        if (s.tune_open) {
+            if (s.tune_cur >= 0 && cells > s.tune_cells0)
+                s.tune_cost[s.tune_cur] = (now_s() - s.tune_t0) / (double)(cells - s.tune_cells0);
+            s.tune_cur++;
+        } else if (s.tune_cur == -2) {
+            s.tune_cur = -1;
+        }
+        if (s.tune_cur >= Sim::NTUNE) {
+            int best = 0;
+            for (int i = 1; i < Sim::NTUNE; i++)
+                if (s.tune_cost[i] < s.tune_cost[best]) best = i;
+            s.bulk_blocks = cand[best];
+            return;
+        }
+        s.bulk_blocks = cand[s.tune_cur < 0 ? 1 : s.tune_cur];
+        s.tune_t0 = now_s();
+        s.tune_cells0 = cells;
+        s.tune_open = true;
     }
 
     sim_status set_state(const double* phi, const double* prim)

@@ -213,6 +213,26 @@ def test_overlapped_bulk_stages_equal_serial(name, n, mode, cycles):
         np.testing.assert_array_equal(u, v)
 
 
+def test_autotuned_launch_gives_identical_results():
+    """The autotuner changes only the bulk stage's grid bound: states, step
+    counts and boundary ledgers equal those of the default configuration."""
+    import paper_1905_03917_amd as P
+    c = WL.shock_bubble_2d(n=512, seed=2)
+    a = _gpu(c)
+    sa = a.advance(1.0, mode=1, max_cycles=4)
+    sa2 = a.advance(1.0, mode=1, max_cycles=4)
+    b = _gpu(c, autotune=1)
+    sb = b.advance(1.0, mode=1, max_cycles=4)
+    assert not b.tuned()[1]
+    sb2 = b.advance(1.0, mode=1, max_cycles=4)
+    blocks, done = b.tuned()
+    assert done and blocks in (1024, 2048, 4096, 8192), (blocks, done)
+    assert sa2["t"] == sb2["t"] and sa["steps"] == sb["steps"] and sa2["steps"] == sb2["steps"]
+    for u, v in zip(a.state(device=False), b.state(device=False)):
+        np.testing.assert_array_equal(u, v)
+    assert P.Sim(c).tuned() == (2048, True)
+
+
 def test_full_size_shock_bubble_properties():
     """1024^2 shock-bubble, one accelerated cycle at the benchmark's launch
     configuration: conservation, and the far field untouched."""
