@@ -43,6 +43,8 @@ def parse():
                     help="workload of the timed cycles (the headline line is shock_bubble_2d at 1024^2; "
                          "shock_droplet_3d at --n 256 is for profiling the 3-D path)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--autotune", action="store_true",
+                    help="let the library choose the bulk stage's grid bound during the warm-up cycles (needs --warmup >= 5)")
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
@@ -384,7 +386,7 @@ def main():
     grid_name = "x".join([str(a.n)] * D)
     print("bench: %s %s, warmup %d, steps %d" % (a.case, grid_name, a.warmup, a.steps), flush=True)
 
-    sim = P.Sim(case)
+    sim = P.Sim(case, autotune=1 if a.autotune else 0)
     if a.warmup:
         sim.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=a.warmup)
     torch.cuda.synchronize()
@@ -469,7 +471,7 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "%s %s multi_dt" % (a.case, grid_name), "cells": a.n ** D,
-                   "mode": "multi_dt", "rk": 3, "cfl": 0.6},
+                   "mode": "multi_dt", "rk": 3, "cfl": 0.6, "bulk_grid_bound": sim.tuned()[0]},
         "per_fluid": {("%s_cell_updates_per_s" % ("air" if case["gamma"][k] == 1.4 else "water")):
                       st["cell_updates"][k] / el for k in range(2)},
         "steps_per_fluid": st["steps"],

@@ -130,6 +130,9 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     sim_t* h = new sim_t();
     Sim& s = h->s;
     s.o = o;
+    // 3-D bulk lists are long (the slow fluid fills most of the grid): a
+    // larger grid bound measured faster there (the autotuner's choice at 256^3)
+    if (D == 3) s.bulk_blocks = 4 * SHARP_BULK_BLOCKS;
     if (stream) {
         s.stream = (hipStream_t)stream;
     } else {
