@@ -180,6 +180,44 @@ sim_status sim_backward(sim_t* s, const double* g_cons, double* g_prim0, double*
  * and whether the autotuner (opts->autotune) has finished choosing it. */
 sim_status sim_tuned(sim_t* s, int* bulk_blocks, int* done);
 
+/* ---- batches: many simulations advanced together ----
+ * A batch advances independent simulations (any sizes, dimensions and
+ * options; each created, filled and read with the calls above) to their own
+ * end times, running each one's single-dt steps or accelerated cycles
+ * (Sec. 3.1) unchanged, while the kernel launches of all of them are fused:
+ * the launches of every simulation up to its next host decision (CFL steps,
+ * tile lists, sub-step plan: a readback of its reduction block) are merged
+ * into one launch per kernel over all simulations that have it next, and
+ * one copy brings every simulation's readback to the host.  Each
+ * simulation takes the steps sim_advance would take on it alone and reaches
+ * the same state up to round-off (the fused kernels are the same kernel
+ * bodies compiled in another context).
+ *   sims[n]     simulations (1 <= n <= SIM_BATCH_MAX), distinct, without a
+ *               tape; borrowed: they must outlive the batch and must not be
+ *               used from another thread during sim_batch_advance
+ * The batch enqueues its work on sims[0]'s stream; sim_batch_advance first
+ * waits for the work already on each simulation's streams and returns with
+ * all of the batch's work complete.  Returns SIM_EINVAL on bad arguments,
+ * SIM_ENOMEM if the batch's buffers do not fit. */
+#define SIM_BATCH_MAX 4096
+typedef struct sim_batch sim_batch_t;
+sim_status sim_batch_create(sim_t* const* sims, int n, sim_batch_t** out);
+
+/* Advance simulation i to t_end[i] (host array of n) in `mode`, at most
+ * max_cycles cycles or steps each when max_cycles > 0.  stats[i] and
+ * status[i] (nullable host arrays of n) receive what sim_advance would
+ * return for simulation i.  Returns SIM_OK when every simulation succeeded,
+ * else the first failing simulation's status (sim_last_error names it);
+ * a failing simulation stops, the others go on. */
+sim_status sim_batch_advance(sim_batch_t* b, const double* t_end, int mode, int64_t max_cycles, sim_stats* stats,
+                             sim_status* status);
+
+/* Totals since creation: rounds (host decisions), fused launches issued,
+ * and launch records they carried (each a launch that the simulations would
+ * have issued on their own). */
+sim_status sim_batch_info(sim_batch_t* b, int64_t* rounds, int64_t* fused_launches, int64_t* records);
+void sim_batch_destroy(sim_batch_t* b);
+
 void sim_destroy(sim_t* s);
 const char* sim_strerror(sim_status st);
 const char* sim_last_error(void);

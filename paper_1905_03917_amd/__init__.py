@@ -51,7 +51,8 @@ class Stats(C.Structure):
 
 EXPORTS = ["sim_default_opts", "sim_create", "sim_set_state", "sim_advance", "sim_get_state",
            "sim_totals", "sim_profile", "sim_profile_read", "sim_backward", "sim_tuned", "sim_destroy",
-           "sim_strerror", "sim_last_error"]
+           "sim_strerror", "sim_last_error", "sim_batch_create", "sim_batch_advance", "sim_batch_info",
+           "sim_batch_destroy"]
 
 _lib = None
 
@@ -82,8 +83,14 @@ def lib():
         L.sim_strerror.argtypes = [C.c_int]
         L.sim_strerror.restype = C.c_char_p
         L.sim_last_error.restype = C.c_char_p
+        L.sim_batch_create.argtypes = [C.POINTER(vp), C.c_int, C.POINTER(vp)]
+        L.sim_batch_advance.argtypes = [vp, vp, C.c_int, C.c_int64, vp, vp]
+        L.sim_batch_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
+        L.sim_batch_destroy.argtypes = [vp]
+        L.sim_batch_destroy.restype = None
         for f in ("sim_create", "sim_set_state", "sim_advance", "sim_get_state", "sim_totals",
-                  "sim_profile", "sim_profile_read", "sim_backward", "sim_tuned"):
+                  "sim_profile", "sim_profile_read", "sim_backward", "sim_tuned", "sim_batch_create",
+                  "sim_batch_advance", "sim_batch_info"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -238,6 +245,49 @@ class Sim:
         _check(lib().sim_profile_read(self.h, C.byref(ms), C.byref(n), C.byref(cells), C.byref(first)),
                "sim_profile_read")
         return ms.value, n.value, cells.value, first.value
+
+
+class Batch:
+    """Simulations advanced together by sim_batch_advance: each one's steps
+    or cycles unchanged, their kernel launches fused across the batch.  The
+    Sim objects are borrowed and must stay open while the batch lives."""
+
+    def __init__(self, sims):
+        self.sims = list(sims)
+        arr = (C.c_void_p * len(self.sims))(*[s.h for s in self.sims])
+        h = C.c_void_p()
+        _check(lib().sim_batch_create(arr, len(self.sims), C.byref(h)), "sim_batch_create")
+        self.h = h
+
+    def advance(self, t_end, mode=SIM_MULTI_DT, max_cycles=0, check=True):
+        """t_end: one end time for all or one per simulation.  Returns the
+        list of per-simulation stats dicts (and statuses when check=False)."""
+        n = len(self.sims)
+        te = np.broadcast_to(np.asarray(t_end, dtype=np.float64), (n,)).copy()
+        st = (Stats * n)()
+        rc = (C.c_int * n)()
+        r = lib().sim_batch_advance(self.h, C.c_void_p(te.ctypes.data), int(mode), int(max_cycles),
+                                    C.cast(st, C.c_void_p), C.cast(rc, C.c_void_p))
+        if check:
+            _check(r, "sim_batch_advance")
+            return [x.as_dict() for x in st]
+        return [x.as_dict() for x in st], list(rc)
+
+    def info(self):
+        v = [C.c_int64() for _ in range(3)]
+        _check(lib().sim_batch_info(self.h, *[C.byref(x) for x in v]), "sim_batch_info")
+        return dict(rounds=v[0].value, fused_launches=v[1].value, records=v[2].value)
+
+    def close(self):
+        if getattr(self, "h", None):
+            lib().sim_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def _advance_fn():

@@ -1,13 +1,16 @@
 """Build the gfx950 HIP library libsharp_hip.so in-tree with hipcc."""
+import concurrent.futures
 import os
+import shutil
 import subprocess
+import tempfile
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsharp_hip.so")
-SOURCES = ["sharp_kernels.hip", "sharp_capi.hip", "sharp_adjoint.hip", "sharp_ledger.hip"]
+SOURCES = ["sharp_kernels.hip", "sharp_capi.hip", "sharp_adjoint.hip", "sharp_ledger.hip", "sharp_batch.hip"]
 FLAGS = [
-    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
+    "-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC",
     # packed FP32 instructions are kept out of the code object
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function",
@@ -15,15 +18,27 @@ FLAGS = [
 
 
 def build(verbose=False):
+    """Compile every source to an object in parallel, then link the library."""
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc] + FLAGS + ["-o", tmp] + [os.path.join(CSRC, s) for s in SOURCES]
-    r = subprocess.run(cmd, capture_output=True, text=True)
-    if r.returncode != 0:
-        raise RuntimeError("hipcc failed:\n" + r.stderr[-6000:])
-    if verbose and r.stderr:
-        print(r.stderr[-3000:])
-    os.replace(tmp, LIB)
+    tmpdir = tempfile.mkdtemp(prefix="sharp_build_")
+    try:
+        objs = [os.path.join(tmpdir, os.path.splitext(src)[0] + ".o") for src in SOURCES]
+        cmds = [[hipcc] + FLAGS + ["-c", "-o", o, os.path.join(CSRC, src)] for src, o in zip(SOURCES, objs)]
+        with concurrent.futures.ThreadPoolExecutor(max_workers=min(len(cmds), os.cpu_count() or 1)) as ex:
+            results = list(ex.map(lambda c: subprocess.run(c, capture_output=True, text=True), cmds))
+        for c, r in zip(cmds, results):
+            if r.returncode != 0:
+                raise RuntimeError("hipcc failed on %s:\n%s" % (c[-1], r.stderr[-6000:]))
+            if verbose and r.stderr:
+                print(r.stderr[-3000:])
+        tmp = LIB + ".tmp"
+        r = subprocess.run([hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs,
+                           capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError("link failed:\n" + r.stderr[-6000:])
+        os.replace(tmp, LIB)
+    finally:
+        shutil.rmtree(tmpdir, ignore_errors=True)
     return LIB
 
 

@@ -1,0 +1,369 @@
+// sharp_batch.hip -- batches of simulations advanced together (the
+// batched form of the hot path: many independent instances of uneven sizes,
+// each running the unchanged single-dt step or accelerated cycle of
+// Sec. 3.1, with their launches fused across instances).
+//
+// Each simulation of a batch runs its engine in a coroutine of its own with
+// a Recorder attached: the engine's launches become records, and a readback
+// of its reduction block (the host decisions of the method: the CFL steps,
+// the tile lists, the sub-step plan) becomes a recorded copy into a slot
+// followed by a yield.  The driver resumes every unfinished simulation in
+// turn until each has yielded or finished (a round), then merges the
+// recorded launches: it repeatedly takes the kernel that heads the most
+// simulations' queues and issues one fused launch for all of them, so that
+// each simulation's launches keep their order.  One upload carries the
+// rounds' device views and argument records, one copy brings every slot
+// back, and the round ends with one synchronisation.  The work a round
+// enqueues is what the simulations would have enqueued on their own, in the
+// same order per simulation: the same steps, with states equal to those of
+// separate runs up to round-off (a fused kernel is the same body compiled
+// in another context, where the compiler may contract other multiply-adds).
+#include <sys/mman.h>
+#include <ucontext.h>
+
+#include <cmath>
+#include <cstdint>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "sharp_internal.h"
+
+namespace sharp {
+
+struct BatchInst {
+    Sim* s = nullptr;
+    Recorder rec;
+    ucontext_t ctx;
+    bool done = false;
+    sim_status rc = SIM_OK;
+    std::string err;
+    sim_stats st;
+    double t_end = 0.0;
+    struct sim_batch_impl* b = nullptr;
+};
+
+static constexpr size_t CO_STACK = 1u << 20;   // per simulation (mapped lazily)
+
+struct sim_batch_impl {
+    std::vector<BatchInst> in;
+    std::vector<void*> stacks;
+    hipStream_t stream = nullptr;
+    ucontext_t sched;
+    int mode = 0;
+    long long max_cycles = 0;
+    unsigned long long* d_slots = nullptr;   // n * RED_WORDS readback slots
+    unsigned long long* h_slots = nullptr;   // pinned copy of the slots
+    unsigned char* d_buf = nullptr;          // device views, record offsets and argument records of a round
+    unsigned char* h_buf = nullptr;          // pinned staging of d_buf
+    size_t cap = 0;
+    std::vector<unsigned char> stage;
+    long long rounds = 0, fused = 0, recorded = 0;
+};
+
+static void co_entry(unsigned lo, unsigned hi)
+{
+    BatchInst* bi = reinterpret_cast<BatchInst*>(((uintptr_t)hi << 32) | (uintptr_t)lo);
+    std::memset(&bi->st, 0, sizeof bi->st);
+    bi->rc = engine_advance(*bi->s, bi->t_end, bi->b->mode, bi->b->max_cycles, &bi->st);
+    if (bi->rc != SIM_OK) bi->err = sim_last_error();
+    bi->done = true;
+    // returning resumes the driver (uc_link)
+}
+
+static void co_yield(void* p)
+{
+    BatchInst* bi = static_cast<BatchInst*>(p);
+    swapcontext(&bi->ctx, &bi->b->sched);
+}
+
+static size_t align16(size_t x) { return (x + 15) & ~(size_t)15; }
+
+struct FusedLaunch {
+    const void* fn;
+    int block, grid, nrec;
+    size_t pre_off, rec_off;
+};
+
+// merge and issue the recorded launches of a round, then bring the
+// readback slots to the simulations that asked for them
+static sim_status flush(sim_batch_impl& B)
+{
+    const int n = (int)B.in.size();
+    std::vector<unsigned char>& H = B.stage;
+    H.clear();
+    std::vector<size_t> dbase(n);
+    size_t ndev = 0;
+    for (int i = 0; i < n; i++) {
+        dbase[i] = ndev;
+        ndev += B.in[i].rec.devs.size();
+    }
+    H.resize(ndev * sizeof(Dev));
+    for (int i = 0; i < n; i++)
+        if (!B.in[i].rec.devs.empty())
+            std::memcpy(H.data() + dbase[i] * sizeof(Dev), B.in[i].rec.devs.data(),
+                        B.in[i].rec.devs.size() * sizeof(Dev));
+    std::vector<size_t> cur(n, 0);
+    std::vector<FusedLaunch> L;
+    std::vector<std::pair<const void*, int>> heads;
+    std::vector<int> members, pre;
+    for (;;) {
+        heads.clear();
+        for (int i = 0; i < n; i++) {
+            const Recorder& r = B.in[i].rec;
+            if (cur[i] >= r.ops.size()) continue;
+            const void* f = r.ops[cur[i]].fn;
+            size_t h = 0;
+            while (h < heads.size() && heads[h].first != f) h++;
+            if (h == heads.size()) heads.push_back({f, 0});
+            heads[h].second++;
+        }
+        if (heads.empty()) break;
+        size_t best = 0;
+        for (size_t h = 1; h < heads.size(); h++)
+            if (heads[h].second > heads[best].second) best = h;
+        const void* f = heads[best].first;
+        members.clear();
+        pre.clear();
+        int grid = 0, block = 0;
+        size_t rsize = 0;
+        for (int i = 0; i < n; i++) {
+            const Recorder& r = B.in[i].rec;
+            if (cur[i] >= r.ops.size() || r.ops[cur[i]].fn != f) continue;
+            const FusedOp& op = r.ops[cur[i]];
+            if (members.empty()) { block = op.block; rsize = op.size; }
+            if (op.block != block || op.size != rsize) { set_error("batch: inconsistent fused launch"); return SIM_EDEVICE; }
+            int start = grid;
+            if (op.nblk >= 8 && (op.nblk & 7) == 0) start = (grid + 7) & ~7;
+            pre.push_back(start);
+            grid = start + op.nblk;
+            members.push_back(i);
+        }
+        FusedLaunch fl;
+        fl.fn = f;
+        fl.block = block;
+        fl.grid = grid;
+        fl.nrec = (int)members.size();
+        fl.pre_off = align16(H.size());
+        H.resize(fl.pre_off + pre.size() * sizeof(int));
+        std::memcpy(H.data() + fl.pre_off, pre.data(), pre.size() * sizeof(int));
+        fl.rec_off = align16(H.size());
+        H.resize(fl.rec_off + members.size() * rsize);
+        for (size_t m = 0; m < members.size(); m++) {
+            const int i = members[m];
+            const FusedOp& op = B.in[i].rec.ops[cur[i]];
+            unsigned char* dst = H.data() + fl.rec_off + m * rsize;
+            std::memcpy(dst, B.in[i].rec.args.data() + op.off, rsize);
+            int dev;
+            std::memcpy(&dev, dst, sizeof dev);
+            dev += (int)dbase[i];
+            std::memcpy(dst, &dev, sizeof dev);
+            cur[i]++;
+        }
+        L.push_back(fl);
+        B.recorded += fl.nrec;
+    }
+    if (!H.empty()) {
+        if (H.size() > B.cap) {
+            size_t c = H.size() * 2;
+            if (B.d_buf) (void)hipFree(B.d_buf);
+            if (B.h_buf) (void)hipHostFree(B.h_buf);
+            B.d_buf = nullptr;
+            B.h_buf = nullptr;
+            B.cap = 0;
+            SHARP_HIP(hipMalloc((void**)&B.d_buf, c));
+            SHARP_HIP(hipHostMalloc((void**)&B.h_buf, c, hipHostMallocDefault));
+            B.cap = c;
+        }
+        std::memcpy(B.h_buf, H.data(), H.size());
+        SHARP_HIP(hipMemcpyAsync(B.d_buf, B.h_buf, H.size(), hipMemcpyHostToDevice, B.stream));
+    }
+    for (const FusedLaunch& fl : L) {
+        const Dev* devs = reinterpret_cast<const Dev*>(B.d_buf);
+        const void* recs = B.d_buf + fl.rec_off;
+        const int* pre_d = reinterpret_cast<const int*>(B.d_buf + fl.pre_off);
+        int nrec = fl.nrec;
+        void* args[4] = {(void*)&devs, (void*)&recs, (void*)&pre_d, (void*)&nrec};
+        SHARP_HIP(hipLaunchKernel(fl.fn, dim3(fl.grid), dim3(fl.block), args, 0, B.stream));
+        B.fused++;
+    }
+    bool rb = false;
+    for (int i = 0; i < n; i++) rb = rb || B.in[i].rec.rb_pending;
+    if (rb)
+        SHARP_HIP(hipMemcpyAsync(B.h_slots, B.d_slots, (size_t)n * RED_WORDS * sizeof(unsigned long long),
+                                 hipMemcpyDeviceToHost, B.stream));
+    SHARP_HIP(hipStreamSynchronize(B.stream));
+    for (int i = 0; i < n; i++) {
+        Recorder& r = B.in[i].rec;
+        if (r.rb_pending) {
+            std::memcpy(B.in[i].s->h_red, B.h_slots + (size_t)i * RED_WORDS, RED_WORDS * sizeof(unsigned long long));
+            r.rb_pending = false;
+        }
+        r.clear();
+    }
+    B.rounds++;
+    return SIM_OK;
+}
+
+static void batch_free(sim_batch_impl* B)
+{
+    if (!B) return;
+    if (B->stream) (void)hipStreamSynchronize(B->stream);
+    for (void* p : B->stacks) munmap(p, CO_STACK);
+    if (B->d_slots) (void)hipFree(B->d_slots);
+    if (B->h_slots) (void)hipHostFree(B->h_slots);
+    if (B->d_buf) (void)hipFree(B->d_buf);
+    if (B->h_buf) (void)hipHostFree(B->h_buf);
+    delete B;
+}
+
+}  // namespace sharp
+
+using namespace sharp;
+
+struct sim_batch {
+    sim_batch_impl* b;
+};
+
+extern "C" {
+
+sim_status sim_batch_create(sim_t* const* sims, int n, sim_batch_t** out)
+{
+    if (!sims || !out) { set_error("null argument"); return SIM_EINVAL; }
+    *out = nullptr;
+    if (n < 1 || n > SIM_BATCH_MAX) { set_error("batch size must be in [1, %d]", SIM_BATCH_MAX); return SIM_EINVAL; }
+    for (int i = 0; i < n; i++) {
+        if (!sims[i]) { set_error("null simulation %d", i); return SIM_EINVAL; }
+        for (int j = 0; j < i; j++)
+            if (sims[j] == sims[i]) { set_error("simulation %d appears twice", i); return SIM_EINVAL; }
+        if (sims[i]->s.o.tape) { set_error("simulation %d records a tape (not batched)", i); return SIM_EINVAL; }
+    }
+    sim_batch_impl* B = new sim_batch_impl();
+    B->in.resize(n);
+    B->stream = sims[0]->s.stream;
+    sim_status rc = SIM_OK;
+    if (hipMalloc((void**)&B->d_slots, (size_t)n * RED_WORDS * sizeof(unsigned long long)) != hipSuccess ||
+        hipHostMalloc((void**)&B->h_slots, (size_t)n * RED_WORDS * sizeof(unsigned long long), hipHostMallocDefault) !=
+            hipSuccess) {
+        (void)hipGetLastError();
+        set_error("batch: allocation of the readback slots failed");
+        rc = SIM_ENOMEM;
+    }
+    for (int i = 0; i < n && rc == SIM_OK; i++) {
+        BatchInst& bi = B->in[i];
+        bi.s = &sims[i]->s;
+        bi.b = B;
+        bi.rec.slot = B->d_slots + (size_t)i * RED_WORDS;
+        bi.rec.yield = co_yield;
+        bi.rec.yield_arg = &bi;
+        void* st = mmap(nullptr, CO_STACK, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_NORESERVE, -1, 0);
+        if (st == MAP_FAILED) { set_error("batch: stack allocation failed"); rc = SIM_ENOMEM; break; }
+        B->stacks.push_back(st);
+    }
+    if (rc != SIM_OK) {
+        batch_free(B);
+        return rc;
+    }
+    sim_batch* h = new sim_batch;
+    h->b = B;
+    *out = h;
+    return SIM_OK;
+}
+
+sim_status sim_batch_advance(sim_batch_t* h, const double* t_end, int mode, int64_t max_cycles, sim_stats* stats,
+                             sim_status* status)
+{
+    if (!h || !t_end) { set_error("null argument"); return SIM_EINVAL; }
+    sim_batch_impl& B = *h->b;
+    const int n = (int)B.in.size();
+    if (mode != SIM_SINGLE_DT && mode != SIM_MULTI_DT) { set_error("bad mode"); return SIM_EINVAL; }
+    for (int i = 0; i < n; i++) {
+        if (!B.in[i].s->has_state) { set_error("simulation %d: sim_set_state has not been called", i); return SIM_ESTATE; }
+        if (!std::isfinite(t_end[i])) { set_error("simulation %d: t_end must be finite", i); return SIM_EINVAL; }
+    }
+    // work the simulations enqueued on their own streams comes first
+    for (int i = 0; i < n; i++) {
+        Sim& s = *B.in[i].s;
+        SHARP_HIP(hipStreamSynchronize(s.stream));
+        for (int k = 0; k < 2; k++)
+            if (s.side[k]) SHARP_HIP(hipStreamSynchronize(s.side[k]));
+    }
+    B.mode = mode;
+    B.max_cycles = (long long)max_cycles;
+    std::vector<char> prof(n);
+    for (int i = 0; i < n; i++) {
+        BatchInst& bi = B.in[i];
+        prof[i] = bi.s->prof;
+        bi.s->prof = false;
+        bi.s->rec = &bi.rec;
+        bi.rec.clear();
+        bi.rec.rb_pending = false;
+        bi.rec.status = SIM_OK;
+        bi.done = false;
+        bi.rc = SIM_OK;
+        bi.err.clear();
+        bi.t_end = t_end[i];
+        getcontext(&bi.ctx);
+        bi.ctx.uc_stack.ss_sp = B.stacks[i];
+        bi.ctx.uc_stack.ss_size = CO_STACK;
+        bi.ctx.uc_link = &B.sched;
+        const uintptr_t p = reinterpret_cast<uintptr_t>(&bi);
+        makecontext(&bi.ctx, (void (*)())co_entry, 2, (unsigned)(p & 0xffffffffu), (unsigned)(p >> 32));
+    }
+    sim_status frc = SIM_OK;
+    for (;;) {
+        int live = 0;
+        for (int i = 0; i < n; i++) {
+            BatchInst& bi = B.in[i];
+            if (bi.done) continue;
+            swapcontext(&B.sched, &bi.ctx);
+            live++;
+        }
+        if (live == 0) break;
+        if (frc == SIM_OK) frc = flush(B);
+        if (frc != SIM_OK) {
+            // every waiting simulation sees the failure at its readback and returns
+            for (int i = 0; i < n; i++) {
+                B.in[i].rec.status = frc;
+                B.in[i].rec.rb_pending = false;
+                B.in[i].rec.clear();
+            }
+        }
+    }
+    sim_status first = frc;
+    std::string msg = frc != SIM_OK ? std::string(sim_last_error()) : std::string();
+    for (int i = 0; i < n; i++) {
+        BatchInst& bi = B.in[i];
+        bi.s->rec = nullptr;
+        bi.s->prof = prof[i];
+        if (bi.rc == SIM_OK && stats) bi.rc = engine_bflux(*bi.s, bi.st.bflux);
+        if (stats) stats[i] = bi.st;
+        if (status) status[i] = bi.rc;
+        if (bi.rc != SIM_OK && first == SIM_OK) {
+            first = bi.rc;
+            msg = "simulation " + std::to_string(i) + ": " + bi.err;
+        }
+    }
+    if (first != SIM_OK) set_error("%s", msg.c_str());
+    return first;
+}
+
+sim_status sim_batch_info(sim_batch_t* h, int64_t* rounds, int64_t* fused_launches, int64_t* records)
+{
+    if (!h) { set_error("null handle"); return SIM_EINVAL; }
+    if (rounds) *rounds = h->b->rounds;
+    if (fused_launches) *fused_launches = h->b->fused;
+    if (records) *records = h->b->recorded;
+    return SIM_OK;
+}
+
+void sim_batch_destroy(sim_batch_t* h)
+{
+    if (!h) return;
+    for (BatchInst& bi : h->b->in)
+        if (bi.s) bi.s->rec = nullptr;
+    batch_free(h->b);
+    delete h;
+}
+
+}  // extern "C"

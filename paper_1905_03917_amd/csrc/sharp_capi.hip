@@ -7,10 +7,6 @@
 
 #include "sharp_internal.h"
 
-struct sim {
-    sharp::Sim s;
-};
-
 namespace sharp {
 
 static thread_local char g_err[512] = "";

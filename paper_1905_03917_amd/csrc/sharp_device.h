@@ -14,6 +14,17 @@
 namespace sharp {
 
 // ---------------------------------------------------------------------------
+// Block coordinates seen by a kernel body: the block's index among the blocks
+// working on one simulation, and their number.  A launch for one simulation
+// passes its grid; a fused launch over several simulations passes each
+// block's place in its own simulation's share of the grid.
+// ---------------------------------------------------------------------------
+struct VB {
+    int b, n;
+    static __device__ __forceinline__ VB grid() { return {(int)blockIdx.x, (int)gridDim.x}; }
+};
+
+// ---------------------------------------------------------------------------
 // Device view of one simulation: grid, tiling, parameters and buffers.
 // Passed by value to every kernel.
 // ---------------------------------------------------------------------------

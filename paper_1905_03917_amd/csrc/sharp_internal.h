@@ -3,6 +3,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <cstring>
 #include <string>
 #include <vector>
 
@@ -24,8 +25,52 @@ constexpr int RED_SCHED = 16;
 constexpr int RED_COUNTS = 32;
 constexpr int RED_WORDS = RED_COUNTS + 8;
 
+// Recording of one simulation's launches for a batch (sharp_batch.hip).
+// While a Sim has a recorder, the engine enqueues nothing: each launch is
+// appended here (kernel, block size, grid, argument record) and the batch
+// driver issues the launches of all its simulations as fused launches, in
+// each simulation's order.  A readback of the reduction block becomes a
+// recorded copy into the batch's readback slot, and waiting for it hands
+// control back to the driver (yield), which resumes the simulation once the
+// slot has reached s.h_red.
+struct FusedOp {
+    const void* fn;    // fused kernel (one per kernel body and argument list)
+    int block;         // threads per block
+    int nblk;          // blocks of this simulation's share
+    size_t off, size;  // argument record in Recorder::args (its first int is the device-view index)
+};
+struct Recorder {
+    std::vector<FusedOp> ops;
+    std::vector<unsigned char> args;
+    std::vector<Dev> devs;        // device views the records refer to (index local to this simulation)
+    unsigned long long* slot = nullptr;   // device readback slot of this simulation (RED_WORDS words)
+    bool rb_pending = false;
+    sim_status status = SIM_OK;   // of the driver's last round, returned by the wait
+    void (*yield)(void*) = nullptr;
+    void* yield_arg = nullptr;
+    int dev_index(const Dev& d)
+    {
+        if (devs.empty() || std::memcmp(&devs.back(), &d, sizeof(Dev)) != 0) devs.push_back(d);
+        return (int)devs.size() - 1;
+    }
+    void add(const void* fn, int block, int nblk, const void* rec, size_t size)
+    {
+        size_t off = (args.size() + 15) & ~(size_t)15;
+        args.resize(off + size);
+        std::memcpy(args.data() + off, rec, size);
+        ops.push_back({fn, block, nblk, off, size});
+    }
+    void clear()
+    {
+        ops.clear();
+        args.clear();
+        devs.clear();
+    }
+};
+
 struct Sim {
     Dev g;                 // device view (pointers live in device memory)
+    Recorder* rec = nullptr;   // set while a batch advances this simulation
     sim_opts o;
     hipStream_t stream = nullptr;
     bool own_stream = false;
@@ -102,3 +147,8 @@ sim_status engine_backward(Sim& s, const double* g_cons, double* g_prim0, double
     } while (0)
 
 }  // namespace sharp
+
+// the C ABI's handle (include/sharp.h)
+struct sim {
+    sharp::Sim s;
+};

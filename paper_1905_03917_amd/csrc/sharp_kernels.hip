@@ -49,13 +49,14 @@ __device__ __forceinline__ const int* list_ptr(const Dev& g, int list) { return 
 // loop.  Workgroup b runs on XCD b % 8, and each XCD has its own L2; giving
 // every XCD a contiguous range of the (row-major) tile list keeps tiles whose
 // halos overlap in the same L2.  Grids that are not a multiple of 8 use the
-// plain stride.
+// plain stride.  (A fused launch starts each simulation's share of 8k blocks
+// at a multiple of 8, so blk.b % 8 is still the XCD.)
 struct ListRange { int begin, end, step; };
-__device__ __forceinline__ ListRange xcd_range(int count)
+__device__ __forceinline__ ListRange xcd_range(const VB blk, int count)
 {
-    const int G = gridDim.x;
-    if (G < 8 || (G & 7)) return {(int)blockIdx.x, count, G};
-    const int x = blockIdx.x & 7, j = blockIdx.x >> 3, chunk = (count + 7) >> 3;
+    const int G = blk.n;
+    if (G < 8 || (G & 7)) return {blk.b, count, G};
+    const int x = blk.b & 7, j = blk.b >> 3, chunk = (count + 7) >> 3;
     const int b = x * chunk;
     return {b + j, min(count, b + chunk), G >> 3};
 }
@@ -75,12 +76,12 @@ __device__ __forceinline__ void flag_error(const Dev& g, unsigned long long bits
 // band off the ring tiles however close to a tile edge it starts.
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_mask(Dev g, int list, int check_ring)
+__device__ __forceinline__ void b_mask(const VB blk, const Dev& g, int list, int check_ring)
 {
     __shared__ int any;
     const int* L = list_ptr(g, list);
     const double R = g.lsb * g.h, Rc = (g.lsb + 2.0) * g.h;
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int t = L[ti];
         if (threadIdx.x == 0) any = 0;
         __syncthreads();
@@ -103,6 +104,11 @@ __global__ void __launch_bounds__(SHARP_WG) k_mask(Dev g, int list, int check_ri
         __syncthreads();
     }
 }
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_mask(Dev g, int list, int check_ring)
+{
+    b_mask<D>(VB::grid(), g, list, check_ring);
+}
 
 // tile classification: band = within one tile of a core tile, candidate =
 // within two, ring = band tile with a non-band neighbour
@@ -120,9 +126,9 @@ __device__ __forceinline__ int tile_nbr(const Dev& g, int t, int dx, int dy, int
 }
 
 template <int D>
-__global__ void k_tiles1(Dev g)
+__device__ __forceinline__ void b_tiles1(const VB blk, const Dev& g)
 {
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.ntiles; t += gridDim.x * blockDim.x) {
+    for (int t = blk.b * blockDim.x + threadIdx.x; t < g.ntiles; t += blk.n * blockDim.x) {
         int band = 0, cand = 0;
         int r2y = D > 1 ? 2 : 0, r2z = D > 2 ? 2 : 0;
         for (int dz = -r2z; dz <= r2z; dz++)
@@ -139,11 +145,16 @@ __global__ void k_tiles1(Dev g)
         g.tsign[t] = g.phiP[c] < 0.0 ? 0 : 1;
     }
 }
+template <int D>
+__global__ void k_tiles1(Dev g)
+{
+    b_tiles1<D>(VB::grid(), g);
+}
 
 template <int D>
-__global__ void k_tiles2(Dev g)
+__device__ __forceinline__ void b_tiles2(const VB blk, const Dev& g)
 {
-    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < g.ntiles; t += gridDim.x * blockDim.x) {
+    for (int t = blk.b * blockDim.x + threadIdx.x; t < g.ntiles; t += blk.n * blockDim.x) {
         int f = g.tflag[t];
         if (!(f & 1)) continue;
         int ring = 0;
@@ -156,6 +167,11 @@ __global__ void k_tiles2(Dev g)
                 }
         g.tflag[t] = f | (ring << 2);
     }
+}
+template <int D>
+__global__ void k_tiles2(Dev g)
+{
+    b_tiles2<D>(VB::grid(), g);
 }
 
 // cells of tile t inside the domain
@@ -170,7 +186,7 @@ __device__ __forceinline__ int tile_cells(const Dev& g, int t)
 
 // single-block compaction of the tile lists (band, candidate, bulk of each
 // fluid, inner) and their cell counts
-__global__ void __launch_bounds__(1024) k_compact(Dev g)
+__device__ __forceinline__ void b_compact(const VB blk, const Dev& g)
 {
     constexpr int NL = 5;   // list slot 4 holds LIST_INNER
     __shared__ int cnt[NL][1024];
@@ -221,6 +237,10 @@ __global__ void __launch_bounds__(1024) k_compact(Dev g)
         }
         if ((f & 1) && !(f & 4)) g.lists[(size_t)LIST_INNER * nt + base[4]++] = t;
     }
+}
+__global__ void __launch_bounds__(1024) k_compact(Dev g)
+{
+    b_compact(VB::grid(), g);
 }
 
 // ---------------------------------------------------------------------------
@@ -310,7 +330,7 @@ template <> struct GeoRegion<2> { static constexpr int X = 16 + 2, Y = 16 + 2, Z
 template <> struct GeoRegion<3> { static constexpr int X = 8 + 2, Y = 8 + 2, Z = 4 + 2; };
 
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_geom_lds(Dev g, int list, const double* cur)
+__device__ __forceinline__ void b_geom_lds(const VB blk, const Dev& g, int list, const double* cur)
 {
     constexpr int TX = Tile<D>::X, TY = Tile<D>::Y, TZ = Tile<D>::Z;
     constexpr int CX = GeoRegion<D>::X, CY = GeoRegion<D>::Y, CZ = GeoRegion<D>::Z, CN = CX * CY * CZ;
@@ -319,7 +339,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_geom_lds(Dev g, int list, const do
     __shared__ double sV[VN];
     __shared__ double sMin[SHARP_WG / 64];
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int t = L[ti];
         int ox = (t % g.nt[0]) * TX, oy = ((t / g.nt[0]) % g.nt[1]) * TY, oz = (t / (g.nt[0] * g.nt[1])) * TZ;
         // cells (ox-1 .. ox+TX) x ...; also min |phi| over them (the mixing
@@ -402,6 +422,11 @@ __global__ void __launch_bounds__(SHARP_WG) k_geom_lds(Dev g, int list, const do
         __syncthreads();
     }
 }
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_geom_lds(Dev g, int list, const double* cur)
+{
+    b_geom_lds<D>(VB::grid(), g, list, cur);
+}
 
 // interface segment per unit volume of fluid 0 (points into fluid 1)
 template <int D>
@@ -439,11 +464,11 @@ __device__ __forceinline__ double grad_phi(const Dev& g, const double* cur, int 
 // ---------------------------------------------------------------------------
 // dst = a1 * src1 + a2 * src2 on ncomp components
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_axpby(Dev g, int list, double a1, const double* s1, double a2,
-                                                   const double* s2, double* dst, int ncomp)
+__device__ __forceinline__ void b_axpby(const VB blk, const Dev& g, int list, double a1, const double* s1, double a2,
+                                        const double* s2, double* dst, int ncomp)
 {
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int i, j, k;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, k)) continue;
         int c = i + g.n[0] * (j + g.n[1] * k);
@@ -452,6 +477,12 @@ __global__ void __launch_bounds__(SHARP_WG) k_axpby(Dev g, int list, double a1, 
             dst[e] = s2 ? a1 * s1[e] + a2 * s2[e] : s1[e];
         }
     }
+}
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_axpby(Dev g, int list, double a1, const double* s1, double a2,
+                                                    const double* s2, double* dst, int ncomp)
+{
+    b_axpby<D>(VB::grid(), g, list, a1, s1, a2, s2, dst, ncomp);
 }
 
 // ---------------------------------------------------------------------------
@@ -595,7 +626,8 @@ __device__ __forceinline__ void mix_sources(const Dev& g, int k, int ox, int oy,
 }
 
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_mixdelta_lds(Dev g, int list, int k, const double* cons, const double* cur)
+__device__ __forceinline__ void b_mixdelta_lds(const VB blk, const Dev& g, int list, int k, const double* cons,
+                                               const double* cur)
 {
     constexpr int NV = D + 2;
     constexpr int NS = (1 << D) - 1;
@@ -606,7 +638,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_mixdelta_lds(Dev g, int list, int 
     __shared__ int sCell[RN];
     const int* L = list_ptr(g, list);
     auto val = [&](int q, int c) { return cons[(size_t)q * g.nc + c]; };
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int ox, oy, oz;
         tile_origin<D>(g, L[ti], ox, oy, oz);
         const bool far = mix_far(g, L[ti]);
@@ -625,6 +657,12 @@ __global__ void __launch_bounds__(SHARP_WG) k_mixdelta_lds(Dev g, int list, int 
         }
         __syncthreads();
     }
+}
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_mixdelta_lds(Dev g, int list, int k, const double* cons,
+                                                           const double* cur)
+{
+    b_mixdelta_lds<D>(VB::grid(), g, list, k, cons, cur);
 }
 
 // Mixed copy of one tile: dst = v + mixing increment of v, where
@@ -683,7 +721,7 @@ __device__ __forceinline__ void mix_tile(const Dev& g, int t, const MixPart& P, 
 }
 
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_mixinterp_lds(Dev g, int list, MixPart P, const double* cur)
+__device__ __forceinline__ void b_mixinterp_lds(const VB blk, const Dev& g, int list, MixPart P, const double* cur)
 {
     constexpr int NS = (1 << D) - 1;
     constexpr int RN = MixRegion<D>::N;
@@ -691,16 +729,21 @@ __global__ void __launch_bounds__(SHARP_WG) k_mixinterp_lds(Dev g, int list, Mix
     __shared__ int sTgt[NS * RN];
     __shared__ int sCell[RN];
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x)
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n)
         mix_tile<D>(g, L[ti], P, cur, sBeta, sTgt, sCell);
+}
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_mixinterp_lds(Dev g, int list, MixPart P, const double* cur)
+{
+    b_mixinterp_lds<D>(VB::grid(), g, list, P, cur);
 }
 
 // Several mixed copies of the same tiles in one launch (the parts read no
 // buffer another part writes), and optionally phi_dst = phi_src on the
 // band-mask cells (the mixing reads the level set through phi_src).
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_mix_parts(Dev g, int list, MixPart A, MixPart B, int nparts,
-                                                       const double* cur, const double* phi_src, double* phi_dst)
+__device__ __forceinline__ void b_mix_parts(const VB blk, const Dev& g, int list, MixPart A, MixPart B, int nparts,
+                                            const double* cur, const double* phi_src, double* phi_dst)
 {
     constexpr int NS = (1 << D) - 1;
     constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
@@ -709,7 +752,7 @@ __global__ void __launch_bounds__(SHARP_WG) k_mix_parts(Dev g, int list, MixPart
     __shared__ int sTgt[NS * RN];
     __shared__ int sCell[RN];
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int t = L[ti];
         mix_tile<D>(g, t, A, cur, sBeta, sTgt, sCell);
         if (nparts > 1) mix_tile<D>(g, t, B, cur, sBeta, sTgt, sCell);
@@ -725,13 +768,19 @@ __global__ void __launch_bounds__(SHARP_WG) k_mix_parts(Dev g, int list, MixPart
         }
     }
 }
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_mix_parts(Dev g, int list, MixPart A, MixPart B, int nparts,
+                                                        const double* cur, const double* phi_src, double* phi_dst)
+{
+    b_mix_parts<D>(VB::grid(), g, list, A, B, nparts, cur, phi_src, phi_dst);
+}
 
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_mixapply(Dev g, int list, double* cons)
+__device__ __forceinline__ void b_mixapply(const VB blk, const Dev& g, int list, double* cons)
 {
     constexpr int NV = D + 2;
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int i, j, k;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, k)) continue;
         int c = i + g.n[0] * (j + g.n[1] * k);
@@ -739,17 +788,22 @@ __global__ void __launch_bounds__(SHARP_WG) k_mixapply(Dev g, int list, double* 
         for (int q = 0; q < NV; q++) cons[(size_t)q * g.nc + c] += g.dmix[(size_t)q * g.nc + c];
     }
 }
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_mixapply(Dev g, int list, double* cons)
+{
+    b_mixapply<D>(VB::grid(), g, list, cons);
+}
 
 // ---------------------------------------------------------------------------
 // primitive recovery on real band cells (alpha_k >= alpha_mix)
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_prims(Dev g, int list, int k, const double* src, int wb)
+__device__ __forceinline__ void b_prims(const VB blk, const Dev& g, int list, int k, const double* src, int wb)
 {
     constexpr int NV = D + 2;
     const int* L = list_ptr(g, list);
     double* W = g.Wb[k][wb];
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int i, j, kk;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
         int c = i + g.n[0] * (j + g.n[1] * kk);
@@ -762,6 +816,11 @@ __global__ void __launch_bounds__(SHARP_WG) k_prims(Dev g, int list, int k, cons
         for (int q = 0; q < NV; q++) W[(size_t)q * g.nc + c] = w[q];
     }
 }
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_prims(Dev g, int list, int k, const double* src, int wb)
+{
+    b_prims<D>(VB::grid(), g, list, k, src, wb);
+}
 
 // ---------------------------------------------------------------------------
 // extension: one Jacobi sweep of the upwind steady state of
@@ -770,11 +829,12 @@ __global__ void __launch_bounds__(SHARP_WG) k_prims(Dev g, int list, int k, cons
 // copy: also copy the cells that are not extended (only the first sweep of a
 // call needs to: afterwards both Jacobi buffers hold the same values there)
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_extw(Dev g, int list, int in, int out, const double* cur, int copy)
+__device__ __forceinline__ void b_extw(const VB blk, const Dev& g, int list, int in, int out, const double* cur,
+                                       int copy)
 {
     constexpr int NV = D + 2;
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         // 3-D, after the first sweep: a tile beyond the extension depth (two
         // cells of margin, as for mixing) holds no target
         if (D == 3 && !copy && g.tphimin[L[ti]] > (g.extb + 2.0) * g.h) continue;
@@ -812,13 +872,19 @@ __global__ void __launch_bounds__(SHARP_WG) k_extw(Dev g, int list, int in, int 
         }
     }
 }
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_extw(Dev g, int list, int in, int out, const double* cur, int copy)
+{
+    b_extw<D>(VB::grid(), g, list, in, out, cur, copy);
+}
 
 // level-set velocity: from the cut cells to the rest of the band
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_extv(Dev g, int list, int in, int out, const double* cur, int copy)
+__device__ __forceinline__ void b_extv(const VB blk, const Dev& g, int list, int in, int out, const double* cur,
+                                       int copy)
 {
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int i, j, kk;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
         int c = i + g.n[0] * (j + g.n[1] * kk);
@@ -847,6 +913,11 @@ __global__ void __launch_bounds__(SHARP_WG) k_extv(Dev g, int list, int in, int 
             g.v[out][e][c] = acc / wsum;
         }
     }
+}
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_extv(Dev g, int list, int in, int out, const double* cur, int copy)
+{
+    b_extv<D>(VB::grid(), g, list, in, out, cur, copy);
 }
 
 // ---------------------------------------------------------------------------
@@ -882,9 +953,8 @@ __device__ __forceinline__ int src_pos(const Dev& g, int d, int o, int x)
 // Wb[k][in], writes the band cells of Wb[k][out]
 // (at most 64 VGPRs, so that two 1024-thread blocks share a CU)
 template <int D>
-__global__ void __launch_bounds__(ExtWG<D>::W, 2 * ExtWG<D>::W / 256) k_extw_tb(Dev g, int list, const double* src0,
-                                                                              const double* src1, int in, int out,
-                                                                              int iters, const double* cur)
+__device__ __forceinline__ void b_extw_tb(const VB blk, const Dev& g, int list, const double* src0, const double* src1,
+                                          int in, int out, int iters, const double* cur)
 {
     static_assert(D <= 2, "temporally blocked extension is for 1-D and 2-D");
     constexpr int NV = D + 2;
@@ -897,7 +967,7 @@ __global__ void __launch_bounds__(ExtWG<D>::W, 2 * ExtWG<D>::W / 256) k_extw_tb(
     __shared__ double sA[NV * RN], sB[NV * RN];
     __shared__ double sPhi[PN];
     const int* L = list_ptr(g, list);
-    for (int wi = blockIdx.x; wi < 2 * list_count(g, list); wi += gridDim.x) {
+    for (int wi = blk.b; wi < 2 * list_count(g, list); wi += blk.n) {
         int t = L[wi >> 1], k = wi & 1;
         int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
         const double* src = k == 0 ? src0 : src1;
@@ -991,6 +1061,13 @@ __global__ void __launch_bounds__(ExtWG<D>::W, 2 * ExtWG<D>::W / 256) k_extw_tb(
         __syncthreads();
     }
 }
+template <int D>
+__global__ void __launch_bounds__(ExtWG<D>::W, 2 * ExtWG<D>::W / 256) k_extw_tb(Dev g, int list, const double* src0,
+                                                                                const double* src1, int in, int out,
+                                                                                int iters, const double* cur)
+{
+    b_extw_tb<D>(VB::grid(), g, list, src0, src1, in, out, iters, cur);
+}
 
 // Riemann problem of cut cell c with fluid states from Wb[.][wb], started
 // from the cell's previous p*: st = {p*, u*, rho*_0, rho*_1}
@@ -1041,10 +1118,10 @@ __device__ __forceinline__ void interface_store(const Dev& g, int c, const doubl
 // the correction share, and u* n as the source of the velocity extension;
 // the other band-mask cells get zeros
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_riemann(Dev g, int list, int wb, int vb, double wcorr, int S)
+__device__ __forceinline__ void b_riemann(const VB blk, const Dev& g, int list, int wb, int vb, double wcorr, int S)
 {
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int i, j, kk;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
         int c = i + g.n[0] * (j + g.n[1] * kk);
@@ -1061,12 +1138,17 @@ __global__ void __launch_bounds__(SHARP_WG) k_riemann(Dev g, int list, int wb, i
         for (int e = 0; e < D; e++) g.v[vb][e][c] = st[1] * gv[e] / gm;
     }
 }
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_riemann(Dev g, int list, int wb, int vb, double wcorr, int S)
+{
+    b_riemann<D>(VB::grid(), g, list, wb, vb, wcorr, S);
+}
 
 // level-set velocity extension, temporally blocked: u* n of the cut cells
 // (from k_riemann, in v[in]) is extended over the tile's region in LDS
 template <int D>
-__global__ void __launch_bounds__(ExtWG<D>::V, 2 * ExtWG<D>::V / 256) k_vext_tb(Dev g, int list, int in, int out,
-                                                                              int iters, const double* cur)
+__device__ __forceinline__ void b_vext_tb(const VB blk, const Dev& g, int list, int in, int out, int iters,
+                                          const double* cur)
 {
     static_assert(D <= 2, "temporally blocked extension is for 1-D and 2-D");
     constexpr int WGS = ExtWG<D>::V;
@@ -1078,7 +1160,7 @@ __global__ void __launch_bounds__(ExtWG<D>::V, 2 * ExtWG<D>::V / 256) k_vext_tb(
     __shared__ double sA[D * RN], sB[D * RN];
     __shared__ double sPhi[PN];
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int t = L[ti];
         int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
         for (int r = threadIdx.x; r < PN; r += WGS) {
@@ -1166,6 +1248,12 @@ __global__ void __launch_bounds__(ExtWG<D>::V, 2 * ExtWG<D>::V / 256) k_vext_tb(
         __syncthreads();
     }
 }
+template <int D>
+__global__ void __launch_bounds__(ExtWG<D>::V, 2 * ExtWG<D>::V / 256) k_vext_tb(Dev g, int list, int in, int out,
+                                                                                int iters, const double* cur)
+{
+    b_vext_tb<D>(VB::grid(), g, list, in, out, iters, cur);
+}
 
 // ---------------------------------------------------------------------------
 // interface interaction: exact Riemann problem per cut cell; exchange term of
@@ -1173,10 +1261,10 @@ __global__ void __launch_bounds__(ExtWG<D>::V, 2 * ExtWG<D>::V / 256) k_vext_tb(
 // wcorr * X_slow into the interfacial flux correction
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_interact(Dev g, int list, int wb, int vb, double wcorr, int S)
+__device__ __forceinline__ void b_interact(const VB blk, const Dev& g, int list, int wb, int vb, double wcorr, int S)
 {
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int i, j, kk;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
         int c = i + g.n[0] * (j + g.n[1] * kk);
@@ -1214,14 +1302,19 @@ __global__ void __launch_bounds__(SHARP_WG) k_interact(Dev g, int list, int wb, 
         }
     }
 }
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_interact(Dev g, int list, int wb, int vb, double wcorr, int S)
+{
+    b_interact<D>(VB::grid(), g, list, wb, vb, wcorr, S);
+}
 
 // corr += w * X_slow from the stored interface solution (cycle start)
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_corr_add(Dev g, int list, double w, int S)
+__device__ __forceinline__ void b_corr_add(const VB blk, const Dev& g, int list, double w, int S)
 {
     if (g.use_sched) w = g.sched[SCHED_W0];
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int i, j, kk;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
         int c = i + g.n[0] * (j + g.n[1] * kk);
@@ -1233,14 +1326,19 @@ __global__ void __launch_bounds__(SHARP_WG) k_corr_add(Dev g, int list, double w
         g.corr[(size_t)(D + 1) * g.nc + c] += w * (-sg * p * g.us[c] * gm);
     }
 }
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_corr_add(Dev g, int list, double w, int S)
+{
+    b_corr_add<D>(VB::grid(), g, list, w, S);
+}
 
 // slow fluid += correction; the correction is reset for the next cycle
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_corr_apply(Dev g, int list, int S, int apply)
+__device__ __forceinline__ void b_corr_apply(const VB blk, const Dev& g, int list, int S, int apply)
 {
     constexpr int NV = D + 2;
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int i, j, kk;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
         int c = i + g.n[0] * (j + g.n[1] * kk);
@@ -1251,22 +1349,27 @@ __global__ void __launch_bounds__(SHARP_WG) k_corr_apply(Dev g, int list, int S,
         }
     }
 }
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_corr_apply(Dev g, int list, int S, int apply)
+{
+    b_corr_apply<D>(VB::grid(), g, list, S, apply);
+}
 
 // ---------------------------------------------------------------------------
 // CFL: max over cells holding fluid k of sum_d (|u_d| + c)/dx, with the star
 // state of cut cells; also counts the cells holding the fluid
 // ---------------------------------------------------------------------------
 template <int D, bool BAND>
-__global__ void __launch_bounds__(SHARP_WG) k_cfl(Dev g, int list, int k, const double* cons, int wb)
+__device__ __forceinline__ void b_cfl(const VB blk, const Dev& g, int list, int k, const double* cons, int wb)
 {
     constexpr int NV = D + 2;
     __shared__ double smax[SHARP_WG / 64];
     __shared__ unsigned long long scnt[SHARP_WG / 64];
     const int* L = list_ptr(g, list);
-    if (blockIdx.x >= list_count(g, list)) return;   // idle block: nothing to reduce
+    if (blk.b >= list_count(g, list)) return;   // idle block: nothing to reduce
     double mx = 0.0;
     unsigned long long cnt = 0;
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int i, j, kk;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
         int c = i + g.n[0] * (j + g.n[1] * kk);
@@ -1301,10 +1404,19 @@ __global__ void __launch_bounds__(SHARP_WG) k_cfl(Dev g, int list, int k, const 
         atomicAdd(&g.red[2 + k], cnt);
     }
 }
+template <int D, bool BAND>
+__global__ void __launch_bounds__(SHARP_WG) k_cfl(Dev g, int list, int k, const double* cons, int wb)
+{
+    b_cfl<D, BAND>(VB::grid(), g, list, k, cons, wb);
+}
 
-__global__ void k_zero_red(Dev g)
+__device__ __forceinline__ void b_zero_red(const VB blk, const Dev& g)
 {
     if (threadIdx.x < 4) g.red[threadIdx.x] = 0ull;
+}
+__global__ void k_zero_red(Dev g)
+{
+    b_zero_red(VB::grid(), g);
 }
 
 // ---------------------------------------------------------------------------
@@ -1358,10 +1470,9 @@ template <int D> struct StageWG { static constexpr int N = SHARP_WG; };
 // `tmp` (band tiles, may be null): the output of inner band tiles goes there
 // instead of `out`, to be mixed into `out` out of place
 template <int D, bool BAND>
-__global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, int k, const double* in,
-                                                            const double* self2, const double* base, double* out,
-                                                            double a, double dt, double wflux, int wb, int cfl,
-                                                            double* tmp)
+__device__ __forceinline__ void b_stage_lds(const VB blk, const Dev& g, int list, int k, const double* in,
+                                            const double* self2, const double* base, double* out, double a, double dt,
+                                            double wflux, int wb, int cfl, double* tmp)
 {
     constexpr int NT = StageWG<D>::N;
     __shared__ double sMax[NT / 64];
@@ -1381,7 +1492,7 @@ __global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, in
     const double ih = 1.0 / g.h;
     const double eps4 = 4.0 * g.eps;
     if (g.use_sched) { dt = g.sched[SCHED_DT]; wflux = g.sched[SCHED_W0]; }
-    const ListRange lr = xcd_range(list_count(g, list));
+    const ListRange lr = xcd_range(blk, list_count(g, list));
     for (int ti = lr.begin; ti < lr.end; ti += lr.step) {
         int t = L[ti];
         int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1];
@@ -1552,6 +1663,14 @@ __global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, in
         }
     }
 }
+template <int D, bool BAND>
+__global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, int k, const double* in,
+                                                             const double* self2, const double* base, double* out,
+                                                             double a, double dt, double wflux, int wb, int cfl,
+                                                             double* tmp)
+{
+    b_stage_lds<D, BAND>(VB::grid(), g, list, k, in, self2, base, out, a, dt, wflux, wb, cfl, tmp);
+}
 
 // ---------------------------------------------------------------------------
 // LDS-staged stage kernel (3-D), one direction at a time: for d = x, y, z
@@ -1568,10 +1687,9 @@ __global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, in
 #define SHARP_WG3_WAVES 3
 #endif
 template <bool BAND>
-__global__ void __launch_bounds__(SHARP_WG3, SHARP_WG3_WAVES) k_stage_lds3(Dev g, int list, int k, const double* in,
-                                                         const double* self2, const double* base, double* out,
-                                                         double a, double dt, double wflux, int wb, int cfl,
-                                                         double* tmp)
+__device__ __forceinline__ void b_stage_lds3(const VB blk, const Dev& g, int list, int k, const double* in,
+                                             const double* self2, const double* base, double* out, double a, double dt,
+                                             double wflux, int wb, int cfl, double* tmp)
 {
     constexpr int D = 3, NV = 5, NT = SHARP_WG3;
     constexpr int TX = 8, TY = 8, TZ = 4, TN = TX * TY * TZ;
@@ -1592,7 +1710,7 @@ __global__ void __launch_bounds__(SHARP_WG3, SHARP_WG3_WAVES) k_stage_lds3(Dev g
     const int tid = threadIdx.x;
     const bool own = tid < TN;
     const int li = tid % TX, lj = (tid / TX) % TY, lk = tid / (TX * TY);
-    const ListRange lr = xcd_range(list_count(g, list));
+    const ListRange lr = xcd_range(blk, list_count(g, list));
     for (int ti = lr.begin; ti < lr.end; ti += lr.step) {
         int t = L[ti];
         int ox, oy, oz;
@@ -1768,17 +1886,25 @@ __global__ void __launch_bounds__(SHARP_WG3, SHARP_WG3_WAVES) k_stage_lds3(Dev g
         }
     }
 }
+template <bool BAND>
+__global__ void __launch_bounds__(SHARP_WG3, SHARP_WG3_WAVES) k_stage_lds3(Dev g, int list, int k, const double* in,
+                                                                           const double* self2, const double* base,
+                                                                           double* out, double a, double dt,
+                                                                           double wflux, int wb, int cfl, double* tmp)
+{
+    b_stage_lds3<BAND>(VB::grid(), g, list, k, in, self2, base, out, a, dt, wflux, wb, cfl, tmp);
+}
 
 // ---------------------------------------------------------------------------
 // level set: one Shu-Osher stage of Eq. (LS:linearadvection), WENO5 upwind
 // derivatives, band cells only
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_ls(Dev g, int list, double a, double dt, const double* in, double* out,
-                                                int vb)
+__device__ __forceinline__ void b_ls(const VB blk, const Dev& g, int list, double a, double dt, const double* in,
+                                     double* out, int vb)
 {
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int i, j, kk;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
         int c = i + g.n[0] * (j + g.n[1] * kk);
@@ -1799,16 +1925,22 @@ __global__ void __launch_bounds__(SHARP_WG) k_ls(Dev g, int list, double a, doub
         out[c] = (a == 0.0) ? s : a * g.phiP[c] + (1.0 - a) * s;
     }
 }
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_ls(Dev g, int list, double a, double dt, const double* in, double* out,
+                                                 int vb)
+{
+    b_ls<D>(VB::grid(), g, list, a, dt, in, out, vb);
+}
 
 // ---------------------------------------------------------------------------
 // reinitialisation: Godunov sweeps of phi_tau + S(phi0)(|grad phi| - 1) = 0,
 // cells near a sign change of phi0 are kept
 // ---------------------------------------------------------------------------
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_nearif(Dev g, int list, const double* phi0)
+__device__ __forceinline__ void b_nearif(const VB blk, const Dev& g, int list, const double* phi0)
 {
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int i, j, kk;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
         int c = i + g.n[0] * (j + g.n[1] * kk);
@@ -1823,13 +1955,19 @@ __global__ void __launch_bounds__(SHARP_WG) k_nearif(Dev g, int list, const doub
         g.nearif[c] = (uint8_t)(neg && pos);
     }
 }
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_nearif(Dev g, int list, const double* phi0)
+{
+    b_nearif<D>(VB::grid(), g, list, phi0);
+}
 
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_reinit(Dev g, int list, const double* phi0, const double* in, double* out)
+__device__ __forceinline__ void b_reinit(const VB blk, const Dev& g, int list, const double* phi0, const double* in,
+                                         double* out)
 {
     const int* L = list_ptr(g, list);
     const double h = g.h, dtau = 0.5 * g.h;
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int i, j, kk;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
         int c = i + g.n[0] * (j + g.n[1] * kk);
@@ -1854,18 +1992,29 @@ __global__ void __launch_bounds__(SHARP_WG) k_reinit(Dev g, int list, const doub
         out[c] = pc - dtau * S * (sqrt(g2) - 1.0);
     }
 }
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_reinit(Dev g, int list, const double* phi0, const double* in,
+                                                     double* out)
+{
+    b_reinit<D>(VB::grid(), g, list, phi0, in, out);
+}
 
 // copy a scalar field on the band-mask cells (reinitialisation disabled)
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_copy_masked(Dev g, int list, const double* src, double* dst)
+__device__ __forceinline__ void b_copy_masked(const VB blk, const Dev& g, int list, const double* src, double* dst)
 {
     const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int i, j, kk;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
         int c = i + g.n[0] * (j + g.n[1] * kk);
         if (g.M[c]) dst[c] = src[c];
     }
+}
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_copy_masked(Dev g, int list, const double* src, double* dst)
+{
+    b_copy_masked<D>(VB::grid(), g, list, src, dst);
 }
 
 // ---------------------------------------------------------------------------
@@ -1889,9 +2038,9 @@ __global__ void __launch_bounds__(SHARP_WG) k_copy_masked(Dev g, int list, const
 
 // ---------------------------------------------------------------------------
 template <int D, int HL>
-__global__ void __launch_bounds__(ExtWG<D>::V)
-k_lsgeo_tb(Dev g, int list, int vin, int vout, int iters, const double* phin, double a, double dt, double* po,
-           int K, double* alpha_out, double* ap_out0, double* ap_out1)
+__device__ __forceinline__ void b_lsgeo_tb(const VB blk, const Dev& g, int list, int vin, int vout, int iters,
+                                           const double* phin, double a, double dt, double* po, int K,
+                                           double* alpha_out, double* ap_out0, double* ap_out1)
 {
     static_assert(D <= 2, "temporally blocked level-set chain is for 1-D and 2-D");
     constexpr int WGS = ExtWG<D>::V;
@@ -1913,7 +2062,7 @@ k_lsgeo_tb(Dev g, int list, int vin, int vout, int iters, const double* phin, do
     const int* L = list_ptr(g, list);
     const bool last = K >= 0;
     if (g.use_sched) dt = g.sched[SCHED_DT];
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int t = L[ti];
         int ox = (t % g.nt[0]) * TX, oy = D == 2 ? ((t / g.nt[0]) % g.nt[1]) * TY : 0;
         const int vox = ox - VH, voy = D == 2 ? oy - VH : 0;     // velocity region origin
@@ -2157,6 +2306,13 @@ k_lsgeo_tb(Dev g, int list, int vin, int vout, int iters, const double* phin, do
         __syncthreads();
     }
 }
+template <int D, int HL>
+__global__ void __launch_bounds__(ExtWG<D>::V) k_lsgeo_tb(Dev g, int list, int vin, int vout, int iters,
+                                                          const double* phin, double a, double dt, double* po, int K,
+                                                          double* alpha_out, double* ap_out0, double* ap_out1)
+{
+    b_lsgeo_tb<D, HL>(VB::grid(), g, list, vin, vout, iters, phin, a, dt, po, K, alpha_out, ap_out0, ap_out1);
+}
 
 // ---------------------------------------------------------------------------
 // initial state: cell contents alpha_k U_k of the given primitives; the
@@ -2180,6 +2336,98 @@ __global__ void __launch_bounds__(SHARP_WG) k_init(Dev g, const double* prim)
             }
         }
     }
+}
+
+// ===========================================================================
+// Fused launches over the simulations of a batch.  One grid runs a kernel
+// body for every simulation whose next launch it is; record r holds that
+// simulation's block count, its device view (an index into `devs`) and the
+// launch's other arguments, and owns blocks [pre[r], pre[r] + nblk) of the
+// grid.  Shares of 8k blocks start at a multiple of 8 (the XCD mapping of
+// xcd_range); the blocks in between exit at once.
+// ===========================================================================
+template <typename... P> struct Pack;
+template <> struct Pack<> {};
+template <typename H, typename... T> struct Pack<H, T...> {
+    H h;
+    Pack<T...> t;
+};
+template <typename... P> struct PackOf;
+template <> struct PackOf<> {
+    static Pack<> make() { return {}; }
+};
+template <typename H, typename... T> struct PackOf<H, T...> {
+    template <typename A0, typename... A>
+    static Pack<H, T...> make(A0&& a0, A&&... a)
+    {
+        Pack<H, T...> p;
+        p.h = H(a0);
+        p.t = PackOf<T...>::make(std::forward<A>(a)...);
+        return p;
+    }
+};
+template <typename... P> struct FusedRec {
+    int dev;
+    int nblk;
+    Pack<P...> a;
+};
+
+template <auto F, typename... Done>
+__device__ __forceinline__ void unpack(const VB blk, const Dev& g, const Pack<>&, Done... d)
+{
+    F(blk, g, d...);
+}
+template <auto F, typename H, typename... T, typename... Done>
+__device__ __forceinline__ void unpack(const VB blk, const Dev& g, const Pack<H, T...>& p, Done... d)
+{
+    unpack<F>(blk, g, p.t, d..., p.h);
+}
+
+// record of block b: the last r with pre[r] <= b (pre ascending, pre[0] = 0),
+// by two ballots over a wave: first over every chunk-th record, then within
+// the chunk (at most 64 * 64 records)
+__device__ __forceinline__ int fused_rec(const int* __restrict__ pre, int nrec, int b)
+{
+    const int lane = threadIdx.x & 63;
+    const int chunk = (nrec + 63) >> 6;
+    const int i = lane * chunk;
+    unsigned long long m = __ballot(i < nrec && pre[i] <= b);
+    const int base = (63 - __clzll((long long)m)) * chunk;
+    const int j = base + lane;
+    m = __ballot(lane < chunk && j < nrec && pre[j] <= b);
+    return __builtin_amdgcn_readfirstlane(base + 63 - __clzll((long long)m));
+}
+
+template <auto F, typename... P>
+__device__ __forceinline__ void fused_body(const Dev* __restrict__ devs, const FusedRec<P...>* __restrict__ recs,
+                                           const int* __restrict__ pre, int nrec)
+{
+    const int r = fused_rec(pre, nrec, (int)blockIdx.x);
+    const FusedRec<P...>& R = recs[r];
+    const int b = (int)blockIdx.x - pre[r];
+    if (b >= R.nblk) return;
+    unpack<F>(VB{b, R.nblk}, devs[R.dev], R.a);
+}
+// the bounds of the kernel the body comes from: maximum block size only, or
+// block size and minimum waves per SIMD
+template <auto F, int WG, typename... P>
+__global__ void __launch_bounds__(WG) k_fused(const Dev* __restrict__ devs, const FusedRec<P...>* __restrict__ recs,
+                                              const int* __restrict__ pre, int nrec)
+{
+    fused_body<F, P...>(devs, recs, pre, nrec);
+}
+template <auto F, int WG, int WAVES, typename... P>
+__global__ void __launch_bounds__(WG, WAVES) k_fused_w(const Dev* __restrict__ devs,
+                                                       const FusedRec<P...>* __restrict__ recs,
+                                                       const int* __restrict__ pre, int nrec)
+{
+    fused_body<F, P...>(devs, recs, pre, nrec);
+}
+
+// readback copy of the reduction block into a batch slot
+__device__ __forceinline__ void b_red_copy(const VB blk, const Dev& g, unsigned long long* dst)
+{
+    for (int w = threadIdx.x; w < RED_WORDS; w += blockDim.x) dst[w] = g.red[w];
 }
 
 // ===========================================================================
@@ -2229,7 +2477,8 @@ __host__ __device__ static double next_substep(double tau, double t1, double dt_
 // t1/2 and t1), and the values the sub-step's first stage needs (dl, b_1 dl,
 // and the slow fluid's interpolation weight for the second stage).  The host
 // enqueues that first stage before it has read the plan back.
-__global__ void k_plan(Dev g, int F, double tau, double t1, int rk, int half_done, double cfl, double b0, double c1)
+__device__ __forceinline__ void b_plan(const VB blk, const Dev& g, int F, double tau, double t1, int rk, int half_done,
+                                       double cfl, double b0, double c1)
 {
 #pragma clang fp contract(off)
     if (threadIdx.x != 0) return;
@@ -2251,6 +2500,10 @@ __global__ void k_plan(Dev g, int F, double tau, double t1, int rk, int half_don
     sc[SCHED_DTF] = dtf;
     sc[SCHED_CNT] = (double)cnt;
 }
+__global__ void k_plan(Dev g, int F, double tau, double t1, int rk, int half_done, double cfl, double b0, double c1)
+{
+    b_plan(VB::grid(), g, F, tau, t1, rk, half_done, cfl, b0, c1);
+}
 
 template <int D>
 struct Engine {
@@ -2271,23 +2524,76 @@ struct Engine {
     }
     dim3 wg() const { return dim3(SHARP_WG); }
 
+    // Launch of kernel body F: the kernel `direct` on stream st or, while a
+    // batch records this simulation, a record of the fused kernel with the
+    // same body and bounds (WAVES: the minimum waves per SIMD of `direct`,
+    // 0 when it states none)
+    template <auto F, int WG, int WAVES = 0, typename... P, typename... A>
+    void go(void (*direct)(Dev, P...), dim3 gr, dim3 bl, hipStream_t st, const Dev& dv, A... a)
+    {
+        if (s.rec) {
+            record<F, WG, WAVES, P...>((int)gr.x, (int)bl.x, dv, a...);
+            return;
+        }
+        hipLaunchKernelGGL(direct, gr, bl, 0, st, dv, P(a)...);
+    }
+    template <auto F, int WG, int WAVES, typename... P, typename... A>
+    void record(int nblk, int block, const Dev& dv, A... a)
+    {
+        FusedRec<P...> r;
+        r.dev = s.rec->dev_index(dv);
+        r.nblk = nblk;
+        r.a = PackOf<P...>::make(a...);
+        const void* fn;
+        if constexpr (WAVES > 0)
+            fn = reinterpret_cast<const void*>(&k_fused_w<F, WG, WAVES, P...>);
+        else
+            fn = reinterpret_cast<const void*>(&k_fused<F, WG, P...>);
+        s.rec->add(fn, block, nblk, &r, sizeof r);
+    }
+    // Readback of the reduction block into s.h_red: rb_begin enqueues the
+    // copy (with an event when the host waits later), rb_wait waits for it.
+    // Under a batch the copy goes to the simulation's slot and the wait
+    // yields to the batch driver, which fills s.h_red.
+    sim_status rb_begin(int words, bool event)
+    {
+        if (s.rec) {
+            record<b_red_copy, 64, 0, unsigned long long*>(1, 64, g, s.rec->slot);
+            s.rec->rb_pending = true;
+            return SIM_OK;
+        }
+        SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, words * sizeof(unsigned long long), hipMemcpyDeviceToHost, s.stream));
+        if (event) SHARP_HIP(hipEventRecord(s.ev_rb, s.stream));
+        return SIM_OK;
+    }
+    sim_status rb_wait(bool event)
+    {
+        if (s.rec) {
+            s.rec->yield(s.rec->yield_arg);
+            return s.rec->status;
+        }
+        if (event) SHARP_HIP(hipEventSynchronize(s.ev_rb));
+        else SHARP_HIP(hipStreamSynchronize(s.stream));
+        return SIM_OK;
+    }
+
     // ---- tiles and masks ----
-    void mask(int list, int ring) { k_mask<D><<<grid(list), wg(), 0, s.stream>>>(g, list, ring); }
+    void mask(int list, int ring) { go<b_mask<D>, SHARP_WG>(k_mask<D>, grid(list), wg(), s.stream, g, list, ring); }
     void tiles()
     {
         int b = (g.ntiles + 255) / 256;
-        k_tiles1<D><<<b, 256, 0, s.stream>>>(g);
-        k_tiles2<D><<<b, 256, 0, s.stream>>>(g);
-        k_compact<<<1, 1024, 0, s.stream>>>(g);
+        go<b_tiles1<D>, 256>(k_tiles1<D>, b, 256, s.stream, g);
+        go<b_tiles2<D>, 256>(k_tiles2<D>, b, 256, s.stream, g);
+        go<b_compact, 1024>(k_compact, 1, 1024, s.stream, g);
     }
     // geometry of the level set `cur` into the second buffer set, which then
     // becomes current (kernels launched before keep reading the old one)
     void geom(const double* cur, int list = LIST_BAND)
     {
-        Dev go = g;
-        go.alpha = s.alpha_alt;
-        for (int d = 0; d < 3; d++) go.ap[d] = s.ap_alt[d];
-        k_geom_lds<D><<<grid(list), wg(), 0, s.stream>>>(go, list, cur);
+        Dev gn = g;
+        gn.alpha = s.alpha_alt;
+        for (int d = 0; d < 3; d++) gn.ap[d] = s.ap_alt[d];
+        go<b_geom_lds<D>, SHARP_WG>(k_geom_lds<D>, grid(list), wg(), s.stream, gn, list, cur);
         std::swap(g.alpha, s.alpha_alt);
         for (int d = 0; d < 3; d++) std::swap(g.ap[d], s.ap_alt[d]);
     }
@@ -2295,8 +2601,8 @@ struct Engine {
     void launch_lsgeo(const double* phin, double a, double dt, double* po, int K)
     {
         if constexpr (D <= 2)
-            k_lsgeo_tb<D, HL><<<grid(LIST_INNER), ExtWG<D>::V, 0, s.stream>>>(
-                g, LIST_INNER, s.vcur, 1 - s.vcur, s.o.ext_iters, phin, a, dt, po, K, s.alpha_alt, s.ap_alt[0],
+            go<b_lsgeo_tb<D, HL>, ExtWG<D>::V>(
+                k_lsgeo_tb<D, HL>, grid(LIST_INNER), ExtWG<D>::V, s.stream, g, LIST_INNER, s.vcur, 1 - s.vcur, s.o.ext_iters, phin, a, dt, po, K, s.alpha_alt, s.ap_alt[0],
                 s.ap_alt[1]);
     }
     // level-set stage q (Shu-Osher coefficient a, step dt) from phin; the
@@ -2322,7 +2628,7 @@ struct Engine {
                 for (int d = 0; d < 3; d++) std::swap(g.ap[d], s.ap_alt[d]);
                 if (!last) return po;
                 if (commit) { *commit = po; return po; }
-                k_copy_masked<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, po, g.phiP);
+                go<b_copy_masked<D>, SHARP_WG>(k_copy_masked<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, po, g.phiP);
                 return g.phiP;
             }
         }
@@ -2335,19 +2641,28 @@ struct Engine {
     }
 
     // ---- band physics ----
-    void prims(int k, const double* src) { k_prims<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, k, src, s.wcur); }
+    void prims(int k, const double* src)
+    {
+        go<b_prims<D>, SHARP_WG>(k_prims<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, k, src, s.wcur);
+    }
     void extw(const double* cur)
     {
         for (int it = 0; it < s.o.ext_iters; it++) {
-            k_extw<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, s.wcur, 1 - s.wcur, cur, it == 0);
+            go<b_extw<D>, SHARP_WG>(k_extw<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, s.wcur, 1 - s.wcur, cur,
+                                     it == 0);
             s.wcur ^= 1;
         }
     }
-    void interact(double wcorr, int S) { k_interact<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, s.wcur, s.vcur, wcorr, S); }
+    void interact(double wcorr, int S)
+    {
+        go<b_interact<D>, SHARP_WG>(k_interact<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, s.wcur, s.vcur,
+                                    wcorr, S);
+    }
     void extv(const double* cur)
     {
         for (int it = 0; it < s.o.ext_iters; it++) {
-            k_extv<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, s.vcur, 1 - s.vcur, cur, it == 0);
+            go<b_extv<D>, SHARP_WG>(k_extv<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, s.vcur, 1 - s.vcur, cur,
+                                     it == 0);
             s.vcur ^= 1;
         }
     }
@@ -2357,8 +2672,9 @@ struct Engine {
     {
         if constexpr (D <= 2) {
             if (s.o.ext_iters <= EXT_H) {
-                k_extw_tb<D><<<grid(LIST_INNER, 2), ExtWG<D>::W, 0, s.stream>>>(g, LIST_INNER, src0, src1, s.wcur, 1 - s.wcur,
-                                                            s.o.ext_iters, cur);
+                go<b_extw_tb<D>, ExtWG<D>::W, 2 * ExtWG<D>::W / 256>(k_extw_tb<D>, grid(LIST_INNER, 2), ExtWG<D>::W,
+                                                                       s.stream, g, LIST_INNER, src0, src1, s.wcur,
+                                                                       1 - s.wcur, s.o.ext_iters, cur);
                 s.wcur ^= 1;
                 return;
             }
@@ -2378,10 +2694,12 @@ struct Engine {
         band_state(src0, src1, cur);
         if constexpr (D <= 2) {
             if (s.o.ext_iters <= EXT_H) {
-                k_riemann<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, s.wcur, s.vcur, wcorr, S);
+                go<b_riemann<D>, SHARP_WG>(k_riemann<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, s.wcur, s.vcur,
+                                           wcorr, S);
                 if (ls_follows && fused_ls()) return;
-                k_vext_tb<D><<<grid(LIST_INNER), ExtWG<D>::V, 0, s.stream>>>(g, LIST_INNER, s.vcur, 1 - s.vcur,
-                                                                            s.o.ext_iters, cur);
+                go<b_vext_tb<D>, ExtWG<D>::V, 2 * ExtWG<D>::V / 256>(k_vext_tb<D>, grid(LIST_INNER), ExtWG<D>::V,
+                                                                       s.stream, g, LIST_INNER, s.vcur, 1 - s.vcur,
+                                                                       s.o.ext_iters, cur);
                 s.vcur ^= 1;
                 return;
             }
@@ -2389,11 +2707,15 @@ struct Engine {
         interact(wcorr, S);
         velocity(cur);
     }
-    void corr_add(double w, int S) { k_corr_add<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, w, S); }
+    void corr_add(double w, int S)
+    {
+        go<b_corr_add<D>, SHARP_WG>(k_corr_add<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, w, S);
+    }
     void mix(int k, double* cons, const double* cur)
     {
-        k_mixdelta_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, k, cons, cur);
-        k_mixapply<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, cons);
+        go<b_mixdelta_lds<D>, SHARP_WG>(k_mixdelta_lds<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, k, cons,
+                                        cur);
+        go<b_mixapply<D>, SHARP_WG>(k_mixapply<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, cons);
     }
     // the band stage writes the inner tiles' output to Tm and one launch
     // mixes it into the stage buffer, optionally together with a second
@@ -2401,7 +2723,8 @@ struct Engine {
     // for the next stage) and the level-set commit
     void mix_fused(const MixPart& A, const MixPart* B, const double* cur, const double* commit)
     {
-        k_mix_parts<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, A, B ? *B : A, B ? 2 : 1, cur, commit,
+        go<b_mix_parts<D>, SHARP_WG>(k_mix_parts<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, A, B ? *B : A,
+                                     B ? 2 : 1, cur, commit,
                                                                 commit ? g.phiP : nullptr);
     }
     MixPart tm_part(int k, double* out) const
@@ -2411,7 +2734,8 @@ struct Engine {
     }
     void axpby(double a1, const double* s1, double a2, const double* s2, double* dst, int ncomp)
     {
-        k_axpby<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, a1, s1, a2, s2, dst, ncomp);
+        go<b_axpby<D>, SHARP_WG>(k_axpby<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, a1, s1, a2, s2, dst,
+                                  ncomp);
     }
 
     // ---- stages ----
@@ -2426,7 +2750,7 @@ struct Engine {
                double wflux, int cfl = 0, double* tmp = nullptr)
     {
         int bl = k == 0 ? LIST_BULK0 : LIST_BULK1;
-        const bool ov = s.side[k] != nullptr;
+        const bool ov = s.side[k] != nullptr && !s.rec;
         hipStream_t bs = ov ? s.side[k] : s.stream;
         // the band stage is enqueued first: on the critical path, it takes the
         // CUs before the bulk stage fills them
@@ -2448,7 +2772,7 @@ struct Engine {
                 (void)hipStreamWaitEvent(bs, prev_band, 0);
             }
         }
-        if (cfl) k_zero_red<<<1, 64, 0, bs>>>(g);
+        if (cfl) go<b_zero_red, 64>(k_zero_red, 1, 64, bs, g);
         size_t ev = 0;
         if (s.prof) {
             if (s.ev_used + 2 > s.ev_pool.size()) profile_flush();
@@ -2488,6 +2812,18 @@ struct Engine {
                       hipEvent_t e0 = nullptr, hipEvent_t e1 = nullptr)
     {
         dim3 gr = grid(list, 1, BAND ? 0 : s.bulk_blocks);
+        if (s.rec) {
+            if constexpr (D <= 2)
+                record<b_stage_lds<D, BAND>, StageWG<D>::N, 0, int, int, const double*, const double*, const double*,
+                       double*, double, double, double, int, int, double*>((int)gr.x, StageWG<D>::N, g, list, k, in,
+                                                                            self2, base, out, a, dt, wflux, s.wcur,
+                                                                            cfl, tmp);
+            else
+                record<b_stage_lds3<BAND>, SHARP_WG3, SHARP_WG3_WAVES, int, int, const double*, const double*,
+                       const double*, double*, double, double, double, int, int, double*>(
+                    (int)gr.x, SHARP_WG3, g, list, k, in, self2, base, out, a, dt, wflux, s.wcur, cfl, tmp);
+            return;
+        }
         if constexpr (D <= 2)
             hipExtLaunchKernelGGL(k_stage_lds<D, BAND>, gr, dim3(StageWG<D>::N), 0, st, e0, e1, 0, g, list, k, in,
                                   self2, base, out, a, dt, wflux, s.wcur, cfl, tmp);
@@ -2520,29 +2856,30 @@ struct Engine {
     {
         int K = s.o.reinit_iters;
         if (K <= 0) {
-            k_copy_masked<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, phi0, g.phiP);
+            go<b_copy_masked<D>, SHARP_WG>(k_copy_masked<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, phi0,
+                                           g.phiP);
             return;
         }
-        k_nearif<D><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, phi0);
+        go<b_nearif<D>, SHARP_WG>(k_nearif<D>, grid(LIST_BAND), wg(), s.stream, g, LIST_BAND, phi0);
         double* other = (phi0 == g.phiB[0]) ? g.phiB[1] : g.phiB[0];
         const double* in = phi0;
         for (int m = 1; m <= K; m++) {
             double* out = (m == K) ? g.phiP : ((m % 2 == 1) ? g.phiB[2] : other);
-            k_reinit<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, phi0, in, out);
+            go<b_reinit<D>, SHARP_WG>(k_reinit<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, phi0, in, out);
             in = out;
         }
     }
     void ls(double a, double dt, const double* in, double* out)
     {
-        k_ls<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, a, dt, in, out, s.vcur);
+        go<b_ls<D>, SHARP_WG>(k_ls<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, a, dt, in, out, s.vcur);
     }
 
     // ---- CFL ----
     void cfl_launch(int k, const double* cons)
     {
         int bl = k == 0 ? LIST_BULK0 : LIST_BULK1;
-        k_cfl<D, false><<<grid(bl), wg(), 0, s.stream>>>(g, bl, k, cons, s.wcur);
-        k_cfl<D, true><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, k, cons, s.wcur);
+        go<b_cfl<D, false>, SHARP_WG>(k_cfl<D, false>, grid(bl), wg(), s.stream, g, bl, k, cons, s.wcur);
+        go<b_cfl<D, true>, SHARP_WG>(k_cfl<D, true>, grid(LIST_BAND), wg(), s.stream, g, LIST_BAND, k, cons, s.wcur);
     }
     // read back the reductions; fills dt and active-cell counts of the fluids in `which`
     // list counts and error flags of a completed readback
@@ -2556,10 +2893,9 @@ struct Engine {
     }
     sim_status readback(int which, double* dt, long long* cnt)
     {
-        SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, RED_WORDS * sizeof(unsigned long long), hipMemcpyDeviceToHost,
-                                 s.stream));
-        SHARP_HIP(hipStreamSynchronize(s.stream));
-        sim_status rc = check_flags();
+        sim_status rc = rb_begin(RED_WORDS, false);
+        if (rc == SIM_OK) rc = rb_wait(false);
+        if (rc == SIM_OK) rc = check_flags();
         if (rc != SIM_OK) return rc;
         for (int k = 0; k < 2; k++) {
             if (!(which & (1 << k))) continue;
@@ -2593,7 +2929,7 @@ struct Engine {
             tiles();
         }
         interaction(g.X[0], g.X[1], g.phiP, 0.0, 0);
-        k_zero_red<<<1, 64, 0, s.stream>>>(g);
+        go<b_zero_red, 64>(k_zero_red, 1, 64, s.stream, g);
         cfl_launch(0, g.X[0]);
         cfl_launch(1, g.X[1]);
         return readback(3, dt, cnt);
@@ -2636,13 +2972,14 @@ struct Engine {
     }
     void interp_slow(int S, double theta, const double* cur)
     {
-        k_mixinterp_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, interp_part(S, theta), cur);
+        go<b_mixinterp_lds<D>, SHARP_WG>(k_mixinterp_lds<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER,
+                                          interp_part(S, theta), cur);
     }
     // copy of src mixed with the current geometry
     void mixed_copy(int S, const double* src, const double* cur)
     {
         MixPart P = {S, 1.0, src, 0.0, nullptr, g.T2, 1, 0};
-        k_mixinterp_lds<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, P, cur);
+        go<b_mixinterp_lds<D>, SHARP_WG>(k_mixinterp_lds<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, P, cur);
     }
 
     // ---- the accelerated cycle (Sec. 3.1) ----
@@ -2732,24 +3069,24 @@ struct Engine {
                 join();
                 if (fused_cfl) {
                     // bulk tiles were reduced by the previous sub-step's last stage
-                    k_cfl<D, true><<<grid(LIST_BAND), wg(), 0, s.stream>>>(g, LIST_BAND, F, g.X[F], s.wcur);
+                    go<b_cfl<D, true>, SHARP_WG>(k_cfl<D, true>, grid(LIST_BAND), wg(), s.stream, g, LIST_BAND, F, g.X[F],
+                                                  s.wcur);
                 } else {
-                    k_zero_red<<<1, 64, 0, s.stream>>>(g);
+                    go<b_zero_red, 64>(k_zero_red, 1, 64, s.stream, g);
                     cfl_launch(F, g.X[F]);
                 }
                 fused_cfl = false;
                 if (plan_dev) {
                     // plan on the device, read the plan back, and enqueue the
                     // first stage before waiting for it
-                    k_plan<<<1, 64, 0, s.stream>>>(g, F, tau, t1, ns, half_done, s.o.cfl, B[0], C[1]);
-                    SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, RED_WORDS * sizeof(unsigned long long),
-                                             hipMemcpyDeviceToHost, s.stream));
-                    SHARP_HIP(hipEventRecord(s.ev_rb, s.stream));
+                    go<b_plan, 64>(k_plan, 1, 64, s.stream, g, F, tau, t1, ns, half_done, s.o.cfl, B[0], C[1]);
+                    sim_status rc = rb_begin(RED_WORDS, true);
+                    if (rc != SIM_OK) return rc;
                     g.use_sched = 1;
                     fast_stage(0, in, phin, 0.0, 0, true);
                     g.use_sched = 0;
-                    SHARP_HIP(hipEventSynchronize(s.ev_rb));
-                    sim_status rc = check_flags();
+                    rc = rb_wait(true);
+                    if (rc == SIM_OK) rc = check_flags();
                     if (rc != SIM_OK) return rc;
                     const double* sc = reinterpret_cast<const double*>(s.h_red + RED_SCHED);
                     dtF = sc[SCHED_DTF];
@@ -2796,7 +3133,8 @@ struct Engine {
             geom(g.phiP);
         }
         // interfacial flux correction of the slow fluid, then mixing
-        k_corr_apply<D><<<grid(LIST_INNER), wg(), 0, s.stream>>>(g, LIST_INNER, S, corr ? 1 : 0);
+        go<b_corr_apply<D>, SHARP_WG>(k_corr_apply<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, S,
+                                      corr ? 1 : 0);
         mix(S, g.X[S], g.phiP);
         join();
         s.t += t1;
@@ -2815,7 +3153,7 @@ struct Engine {
             long long cnt[2];
             rc = prepare(true, dt, cnt);
             if (rc != SIM_OK) break;
-            if (s.o.autotune) tune_step(st);
+            if (s.o.autotune && !s.rec) tune_step(st);
             st->last_dt[0] = dt[0];
             st->last_dt[1] = dt[1];
             if (!(fmin(dt[0], dt[1]) > 0.0)) { set_error("invalid time step"); rc = SIM_ENONPHYS; break; }
@@ -2845,9 +3183,9 @@ struct Engine {
         s.tune_open = false;    // time between calls is not a cycle
         if (rc == SIM_OK) {
             // late non-physical flags (stages after the last readback)
-            SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, 5 * sizeof(unsigned long long), hipMemcpyDeviceToHost, s.stream));
-            SHARP_HIP(hipStreamSynchronize(s.stream));
-            if (s.h_red[4] & ERR_NONPHYS) { set_error("non-physical state"); rc = SIM_ENONPHYS; }
+            rc = rb_begin(5, false);
+            if (rc == SIM_OK) rc = rb_wait(false);
+            if (rc == SIM_OK && (s.h_red[4] & ERR_NONPHYS)) { set_error("non-physical state"); rc = SIM_ENONPHYS; }
         }
         if (s.prof) profile_flush();
         st->t = s.t;

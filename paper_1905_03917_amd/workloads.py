@@ -18,6 +18,7 @@ re-posed with stiffened-gas water gamma=4.4, p_inf=6e8 Pa and air gamma=1.4):
   smooth_2d        Gaussian acoustic pulse in air crossing a flat interface
   droplet_2d       periodic translation of a water droplet (Sec. 4.2 analogue)
   pulse_air        acoustic pulse in a grid filled by air (differentiable runs)
+  batch_cases      many tubes and bubbles of uneven sizes (batched runs)
 """
 from __future__ import annotations
 
@@ -227,6 +228,44 @@ def pulse_air(n=64, ndim=2, seed=0, amp=1.0e3, width=0.05, bc=0, t_end=None, u0=
     phi = -np.ones(nc)
     return _case(ndim, n, bc, AIR, WATER, phi, np.stack([air, other]),
                  t_end if t_end is not None else 1e30, "pulse_air_%dd" % ndim, centre=c)
+
+
+def batch_cases(seed=0, n_tubes=384, n_bubbles=128, tube_n=(200, 4000), bubble_n=(64, 512)):
+    """Independent instances of uneven sizes for a batch.
+
+    Tubes: 1-D water (fluid 0, left) | air (fluid 1, right), N ~ U{tube_n},
+    interface at 0.5 + U(-1, 1) h; water at rho = 1000, p = 1e5 * Rp, air at
+    rho = 1000 / Rr, p = 1e5, at rest.  Bubbles: 2-D air bubble (fluid 0) of
+    radius U(0.1, 0.3) near the centre of water (fluid 1) on an n^2 grid,
+    n ~ U{bubble_n}; water at rho = 1000, p = 1e5 * Rp, air at rho =
+    1000 / Rr, p = 1e5 (a collapsing bubble).  The density and pressure
+    ratios are drawn log-uniform: Rr in [1, 1e3], Rp in [1, 1e4].
+    Expected cells at the default sizes: 384 * 2100 = 0.8M in 1-D and
+    128 * 99.7k = 12.8M in 2-D.
+    """
+    r = _rng(seed + 7000)
+    cases = []
+    for i in range(n_tubes):
+        n = int(r.integers(tube_n[0], tube_n[1] + 1))
+        rr, rp = 10.0 ** r.uniform(0.0, 3.0), 10.0 ** r.uniform(0.0, 4.0)
+        h, (x,) = _grid(1, n)
+        xi = 0.5 + r.uniform(-1.0, 1.0) * h
+        prim = np.stack([_fill(1, n, dict(rho=1000.0, u=0.0, p=1.0e5 * rp)),
+                         _fill(1, n, dict(rho=1000.0 / rr, u=0.0, p=1.0e5))])
+        cases.append(_case(1, n, 0, WATER, AIR, x - xi, prim, 1.0, "batch_tube_%d" % i, ratios=(rr, rp)))
+    for i in range(n_bubbles):
+        n = int(r.integers(bubble_n[0], bubble_n[1] + 1))
+        rr, rp = 10.0 ** r.uniform(0.0, 3.0), 10.0 ** r.uniform(0.0, 4.0)
+        rad = r.uniform(0.1, 0.3)
+        h, (X, Y) = _grid(2, n)
+        cx, cy = 0.5 + r.uniform(-0.5, 0.5) * h, 0.5 + r.uniform(-0.5, 0.5) * h
+        phi = np.sqrt((X - cx) ** 2 + (Y - cy) ** 2) - rad
+        nc = n * n
+        prim = np.stack([_fill(2, nc, dict(rho=1000.0 / rr, p=1.0e5)),
+                         _fill(2, nc, dict(rho=1000.0, p=1.0e5 * rp))])
+        cases.append(_case(2, n, 0, AIR, WATER, phi, prim, 1.0, "batch_bubble_%d" % i, radius=rad,
+                           ratios=(rr, rp)))
+    return cases
 
 
 def probe_cells(n, ndim=2, count=16, seed=0):

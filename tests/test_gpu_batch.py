@@ -1,0 +1,138 @@
+"""Batches (sim_batch_*): many simulations of uneven sizes and dimensions
+advanced together with their launches fused across the batch.  Each
+simulation must take the same steps as when advanced alone and reach the
+same state at the parity bar, and a batched instance must match the oracle
+at the single-run bar."""
+import numpy as np
+import pytest
+
+from paper_1905_03917_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def _mods():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1905_03917_amd as P
+    return torch, P
+
+
+def _cases():
+    cs = WL.batch_cases(seed=3, n_tubes=3, n_bubbles=3, tube_n=(200, 700), bubble_n=(40, 96))
+    cs.append(WL.shock_droplet_3d(n=20, seed=1))
+    cs.append(WL.tube_1d(n=400, seed=2))
+    return cs
+
+
+# Batched and lone runs execute the same kernel bodies, compiled in another
+# context where the compiler may contract other multiply-adds.  Round-off
+# differences then reach the interface Riemann solver, whose Newton iteration
+# (warm-started from the previous solution) stops at |dp| <= 1e-13 (|p| +
+# p_inf): with water's p_inf = 6e8 that leaves p* on the air side free at
+# about 1e-10 relative, and the star speeds, CFL steps and states follow.
+# The bars are therefore the parity bar of the method for runs of several
+# cycles (1e-8 relative, here in L-infinity rather than L1, on the contents
+# and the level set; 1e-9 on steps and times), with identical step counts.
+def _same(a, b, what, tol=1e-8):
+    pa, ca, aa = a.state(device=False)
+    pb, cb, ab = b.state(device=False)
+    D = a.D
+    err = np.abs(pa - pb).max() / max(np.abs(pb).max(), 1e-300)
+    assert err <= tol, (what, "phi", err)
+    err = np.abs(aa - ab).max()
+    assert err <= 10 * tol, (what, "alpha", err)
+    worst = 0.0
+    for k in range(2):
+        for q in range(D + 2):
+            sc = max(np.abs(cb[k, q]).max(), np.sqrt(np.abs(cb[k, 0]).max() * np.abs(cb[k, D + 1]).max()), 1e-300)
+            worst = max(worst, np.abs(ca[k, q] - cb[k, q]).max() / sc)
+    assert worst <= tol, (what, "cons", worst)
+    return worst
+
+
+def _stats_equal(sa, sb, what, totals):
+    """same steps; times to 1e-9; boundary-flux ledger against the fluid's
+    content (a flux that is itself round-off carries no digits)"""
+    for key in ("cycles", "steps", "cell_updates"):
+        assert sa[key] == sb[key], (what, key, sa[key], sb[key])
+    for key in ("t", "last_n", "last_dt"):
+        assert np.allclose(sa[key], sb[key], rtol=1e-9, atol=0.0), (what, key, sa[key], sb[key])
+    for k in range(2):
+        scale = max(np.abs(np.asarray(totals).reshape(2, 5)[k]).max(), 1e-300)
+        assert np.abs(sa["bflux"][k] - sb["bflux"][k]).max() <= 1e-10 * scale, (what, k, sa["bflux"], sb["bflux"])
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_batch_matches_separate_runs(mode):
+    torch, P = _mods()
+    cases = _cases()
+    print("batch of %d: mode %d" % (len(cases), mode), flush=True)
+    probe = [P.Sim(c) for c in cases]
+    t6 = [s.advance(1.0, mode=mode, max_cycles=6)["t"] for s in probe]
+    for s in probe:
+        s.close()
+    # half of the simulations stop at their own (earlier) end time
+    t_end = np.array([1.0 if i % 2 == 0 else 0.5 * t6[i] for i in range(len(cases))])
+    alone = [P.Sim(c) for c in cases]
+    st_alone = [s.advance(t_end[i], mode=mode, max_cycles=6) for i, s in enumerate(alone)]
+    sims = [P.Sim(c) for c in cases]
+    b = P.Batch(sims)
+    st_b = b.advance(t_end, mode=mode, max_cycles=6)
+    for i in range(len(cases)):
+        _stats_equal(st_b[i], st_alone[i], cases[i]["name"], alone[i].totals())
+        print("%s: batched vs alone, worst relative difference %.2e" % (cases[i]["name"],
+                                                                       _same(sims[i], alone[i], cases[i]["name"])))
+    # a second call continues every simulation
+    st_alone = [s.advance(1.0, mode=mode, max_cycles=3) for s in alone]
+    st_b = b.advance(1.0, mode=mode, max_cycles=3)
+    for i in range(len(cases)):
+        _stats_equal(st_b[i], st_alone[i], cases[i]["name"] + " (second call)", alone[i].totals())
+        _same(sims[i], alone[i], cases[i]["name"] + " (second call)")
+    info = b.info()
+    print("batch info", info)
+    assert info["records"] > info["fused_launches"] > 0
+    b.close()
+
+
+def test_batched_instance_matches_oracle():
+    torch, P = _mods()
+    from oracle import oracle as O
+    cases = [WL.tube_1d(n=400, seed=4), WL.shock_bubble_2d(n=64, seed=4), WL.droplet_2d(n=48, seed=1)]
+    sims = [P.Sim(c) for c in cases]
+    b = P.Batch(sims)
+    st = b.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=2)
+    for c, s, sg in zip(cases, sims, st):
+        print("oracle check of batched %s" % c["name"], flush=True)
+        o = O.OracleSim(c)
+        so = o.advance(1.0, mode=1, max_cycles=2)
+        assert sg["steps"] == so["steps"]
+        _, cg, _ = s.state(device=False)
+        _, co, _ = o.state()
+        D = c["ndim"]
+        for k in range(2):
+            for q in range(D + 2):
+                sc = max(np.abs(co[k, q]).max(), np.sqrt(np.abs(co[k, 0]).max() * np.abs(co[k, D + 1]).max()), 1e-300)
+                err = np.abs(cg[k, q] - co[k, q]).max() / sc
+                assert err <= 1e-10, (c["name"], k, q, err)
+    b.close()
+
+
+def test_batch_rejects_bad_arguments():
+    torch, P = _mods()
+    a = P.Sim(WL.tube_1d(n=200, seed=0))
+    with pytest.raises(P.SimError) as e:
+        P.Batch([a, a])
+    assert e.value.status == -1
+    t = P.Sim(WL.pulse_air(n=32, ndim=1, seed=0), tape=1)
+    with pytest.raises(P.SimError) as e:
+        P.Batch([a, t])
+    assert e.value.status == -1 and "tape" in str(e.value)
+    with pytest.raises(P.SimError) as e:
+        P.Batch([])
+    assert e.value.status == -1
+    b = P.Batch([a])
+    with pytest.raises(P.SimError) as e:
+        b.advance(float("nan"))
+    assert e.value.status == -1
+    b.close()
