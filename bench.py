@@ -48,6 +48,10 @@ def parse():
     ap.add_argument("--no-single", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances timing")
+    ap.add_argument("--batch-only", action="store_true", help="only the batched-instances timing")
+    ap.add_argument("--batch-no-sequential", action="store_true",
+                    help="with --batch-only: skip advancing the instances one at a time")
     ap.add_argument("--no-l1", action="store_true", help="skip the matched-L1 comparisons (1-D tube and 3-D droplet ladders)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM byte counters)")
@@ -127,9 +131,9 @@ def reduce_counters(fetch_dir, write_dir):
                source_sha256=source_digest(), sources=KERNEL_SOURCES, counters=out,
                traffic_bytes_per_launch=traffic,
                commands=["timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <FETCH_DIR> -o run "
-                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --no-adjoint --copy-probe",
+                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --no-adjoint --no-batch --copy-probe",
                          "timeout -s KILL 150 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <WRITE_DIR> -o run "
-                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --no-adjoint --copy-probe",
+                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --no-adjoint --no-batch --copy-probe",
                          "python bench.py --reduce-counters <FETCH_DIR> <WRITE_DIR>"])
     with open(COUNTERS, "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -337,6 +341,57 @@ def adjoint_timing(P, WL, n=512, steps=400, ckpt=20, probes=16):
                 grad_norm=float(torch.linalg.vector_norm(g)), d_gamma=float(eos.grad[0, 0]), d_pinf=float(eos.grad[0, 1]))
 
 
+def batch_timing(P, WL, cycles_multi=3, steps_single=10, one_at_a_time=True):
+    """The batched configuration: 512 independent instances (384 1-D
+    water-air tubes with N ~ U[200, 4000] and 128 2-D collapsing air bubbles
+    in water on n^2 grids, n ~ U[64, 512], seeded density ratios 1-1e3 and
+    pressure ratios 1-1e4), advanced by sim_batch_advance with launches
+    fused across the instances; beside it the same instances advanced one
+    at a time by sim_advance (fresh copies, the same cycles).  One warm-up
+    cycle precedes each timed leg."""
+    import numpy as np
+    import torch
+    cases = WL.batch_cases(seed=0)
+    cells = sum(int(np.prod(c["n"][:c["ndim"]])) for c in cases)
+    res = dict(workload="batch of %d: %d 1-D tubes N in [200, 4000], %d 2-D bubbles n^2, n in [64, 512]"
+                        % (len(cases), sum(c["ndim"] == 1 for c in cases), sum(c["ndim"] == 2 for c in cases)),
+               instances=len(cases), cells=cells)
+    for mode, K, key in ((P.SIM_MULTI_DT, cycles_multi, "multi_dt"), (P.SIM_SINGLE_DT, steps_single, "single_dt")):
+        sims = [P.Sim(c, serial=1) for c in cases]
+        b = P.Batch(sims)
+        b.advance(1.0, mode=mode, max_cycles=1)
+        torch.cuda.synchronize()
+        i0 = b.info()
+        t0 = time.perf_counter()
+        st = b.advance(1.0, mode=mode, max_cycles=K)
+        torch.cuda.synchronize()
+        tb = time.perf_counter() - t0
+        i1 = b.info()
+        ub = sum(sum(x["cell_updates"]) for x in st)
+        b.close()
+        for x in sims:
+            x.close()
+        res[key] = dict(cycles=K, batched_s=tb, cell_updates=ub, value=ub / tb,
+                        rounds=i1["rounds"] - i0["rounds"], fused_launches=i1["fused_launches"] - i0["fused_launches"],
+                        launch_records=i1["records"] - i0["records"])
+        if not one_at_a_time:
+            continue
+        sims = [P.Sim(c, serial=1) for c in cases]
+        for x in sims:
+            x.advance(1.0, mode=mode, max_cycles=1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        us = 0
+        for x in sims:
+            us += sum(x.advance(1.0, mode=mode, max_cycles=K)["cell_updates"])
+        torch.cuda.synchronize()
+        ts = time.perf_counter() - t0
+        for x in sims:
+            x.close()
+        res[key].update(one_at_a_time_s=ts, one_at_a_time_value=us / ts, speedup=(ub / tb) / (us / ts))
+    return res
+
+
 def cpu_baseline(case_fn, seconds):
     """The CPU oracle (single thread) on the same workload at reduced
     resolution, scaled to cell-updates/s."""
@@ -371,6 +426,9 @@ def main():
     from paper_1905_03917_amd import workloads as WL
 
     torch.cuda.set_device(0)
+    if a.batch_only:
+        print(json.dumps({"batch": batch_timing(P, WL, one_at_a_time=not a.batch_no_sequential)}), flush=True)
+        return
     if a.copy_probe:
         # a device-to-device copy of exactly 1 GiB read + 1 GiB written; a
         # 1 GiB fill in between evicts the source from the 256 MB last-level
@@ -454,6 +512,12 @@ def main():
         adj = adjoint_timing(P, WL)
         print("bench: adjoint (512^2, 400 steps): forward %.3f s, backward %.3f s"
               % (adj["forward_s"], adj["backward_s"]), flush=True)
+    bat = None
+    if not a.no_batch:
+        bat = batch_timing(P, WL)
+        print("bench: batch of %d: multi_dt %.3e cell-updates/s (%.1fx one at a time), single_dt %.3e (%.1fx)"
+              % (bat["instances"], bat["multi_dt"]["value"], bat["multi_dt"]["speedup"], bat["single_dt"]["value"],
+                 bat["single_dt"]["speedup"]), flush=True)
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(WL.shock_bubble_2d, a.cpu_seconds)
@@ -478,6 +542,7 @@ def main():
         "single_dt": single,
         "matched_l1": ml1,
         "adjoint": adj,
+        "batch": bat,
         "roofline": roof,
         "cpu_baseline": cpu,
     }
