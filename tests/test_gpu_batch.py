@@ -136,3 +136,27 @@ def test_batch_rejects_bad_arguments():
         b.advance(float("nan"))
     assert e.value.status == -1
     b.close()
+
+
+def test_failing_instance_stops_alone():
+    """a simulation that reaches a non-physical state returns SIM_ENONPHYS
+    from the batch while the others finish as they would alone"""
+    torch, P = _mods()
+    good = [WL.tube_1d(n=300, seed=6), WL.shock_bubble_2d(n=48, seed=6)]
+    bad = WL.tube_1d(n=200, seed=7)
+    prim = bad["prim"].copy()
+    prim[0, 0, 10] = -1.0                     # negative density in a water cell
+    bad = dict(bad, prim=prim)
+    cases = [good[0], bad, good[1]]
+    sims = [P.Sim(c) for c in cases]
+    b = P.Batch(sims)
+    st, status = b.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=3, check=False)
+    assert list(status) == [0, -4, 0], status
+    with pytest.raises(P.SimError) as e:
+        b.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=1)
+    assert e.value.status == -4 and "simulation 1" in str(e.value)
+    b.close()
+    for c, s in zip(good, (sims[0], sims[2])):
+        alone = P.Sim(c)
+        alone.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=4)
+        _same(s, alone, c["name"])
