@@ -55,6 +55,8 @@ def parse():
     ap.add_argument("--no-l1", action="store_true", help="skip the matched-L1 comparisons (1-D tube and 3-D droplet ladders)")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM byte counters)")
+    ap.add_argument("--reduce-valu", metavar="VALU_DIR",
+                    help="reduce a pass of SQ instruction counters into the executed-work record")
     ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="reduce two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
                          "'bench.py --copy-probe' into the committed traffic record, then exit")
@@ -138,6 +140,61 @@ def reduce_counters(fetch_dir, write_dir):
     with open(COUNTERS, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
+
+
+VALU_COUNTERS = ["SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64",
+                 "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES"]
+VALU_RECORD = os.path.join(ROOT, "profiles", "stage_bulk_shock_bubble_2d_1024_valu.json")
+
+
+def reduce_valu(valu_dir):
+    """Executed FP64 work of the bulk stage kernel from one rocprofv3 pass of
+    SQ instruction counters (wave-level counts per dispatch): executed FP64
+    flops (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes), and the VALU issue bound,
+    every wave64 VALU instruction holding a 16-lane SIMD for 4 cycles on
+    1024 SIMDs at 2.4 GHz, against the dispatch's duration."""
+    import csv
+    import glob
+    per = {}
+    for f in glob.glob(os.path.join(valu_dir, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            for r in csv.DictReader(fh):
+                if "k_stage_lds<2, false>" not in r["Kernel_Name"]:
+                    continue
+                d = per.setdefault(r["Dispatch_Id"], {})
+                d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+                d["ns"] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+    if not per:
+        raise SystemExit("no bulk stage dispatch found in %s" % valu_dir)
+    avg = {k: sum(v.get(k, 0.0) for v in per.values()) / len(per) for k in VALU_COUNTERS + ["ns"]}
+    flops = avg["SQ_INSTS_VALU_FLOPS_FP64"] * 64
+    issue_s = avg["SQ_INSTS_VALU"] * 4 / (1024 * 2.4e9)
+    fp64 = sum(avg[k] for k in VALU_COUNTERS[:4])
+    rec = dict(kernel="k_stage_lds<2, false>", workload="shock_bubble_2d 1024x1024 multi_dt",
+               source_sha256=source_digest(), sources=KERNEL_SOURCES, dispatches=len(per),
+               counters_per_dispatch={k: avg[k] for k in VALU_COUNTERS},
+               duration_us_under_counters=avg["ns"] / 1e3,
+               executed_fp64_flops_per_launch=flops,
+               fp64_share_of_valu_instructions=fp64 / avg["SQ_INSTS_VALU"],
+               valu_issue_bound_us=issue_s * 1e6,
+               valu_issue_frac=issue_s * 1e9 / avg["ns"],
+               command="timeout -s KILL 150 rocprofv3 --pmc " + " ".join(VALU_COUNTERS) + " --output-format csv "
+                       "-d <VALU_DIR> -o run -- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 "
+                       "--no-adjoint --no-batch; python bench.py --reduce-valu <VALU_DIR>")
+    with open(VALU_RECORD, "w") as fh:
+        json.dump(rec, fh, indent=1)
+    print(json.dumps(rec))
+
+
+def measured_valu():
+    """the committed executed-work record, or None when the kernel sources
+    changed since the counters were taken"""
+    try:
+        with open(VALU_RECORD) as fh:
+            rec = json.load(fh)
+    except (OSError, ValueError):
+        return None
+    return rec if rec.get("source_sha256") == source_digest() else None
 
 
 def measured_traffic():
@@ -418,6 +475,9 @@ def main():
     if a.reduce_counters:
         reduce_counters(*a.reduce_counters)
         return
+    if a.reduce_valu:
+        reduce_valu(a.reduce_valu)
+        return
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % a.gpus, file=sys.stderr)
         sys.exit(2)
@@ -497,6 +557,14 @@ def main():
                 algorithmic_bytes_per_launch=round(bytes_k / max(launches, 1)),
                 hbm=dict(achieved=round(ach_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                          frac=round(ach_gbs / HBM_PEAK_GBS, 4)))
+    valu = measured_valu() if (a.case == "shock_bubble_2d" and a.n == 1024) else None
+    if valu and sec_k > 0:
+        # executed FP64 work over this run's launch durations
+        ex_tf = valu["executed_fp64_flops_per_launch"] * launches / sec_k / 1e12
+        roof["executed"] = dict(fp64_flops_per_launch=round(valu["executed_fp64_flops_per_launch"]),
+                                achieved=round(ex_tf, 2), frac=round(ex_tf / FP64_VECTOR_TFLOPS, 4),
+                                valu_issue_bound_us=round(valu["valu_issue_bound_us"], 1),
+                                valu_issue_frac=round(valu["valu_issue_bound_us"] / (ms_k * 1e3 / max(launches, 1)), 4))
     ml1 = None
     if not a.no_l1:
         ml1 = matched_l1(P, WL)
