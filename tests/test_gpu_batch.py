@@ -160,3 +160,40 @@ def test_failing_instance_stops_alone():
         alone = P.Sim(c)
         alone.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=4)
         _same(s, alone, c["name"])
+
+
+def test_full_size_batch_samples():
+    """the batched configuration at its full size (512 instances, 14.3M
+    cells) for one accelerated cycle, as the benchmark runs it: the largest
+    and smallest tube and bubble against lone runs, the smallest tube
+    against the oracle"""
+    torch, P = _mods()
+    from oracle import oracle as O
+    cases = WL.batch_cases(seed=0)
+    print("full-size batch of %d" % len(cases), flush=True)
+    sims = [P.Sim(c, serial=1) for c in cases]
+    b = P.Batch(sims)
+    st = b.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=1)
+    tubes = [i for i, c in enumerate(cases) if c["ndim"] == 1]
+    bubbles = [i for i, c in enumerate(cases) if c["ndim"] == 2]
+    size = lambda i: cases[i]["n"][0]
+    picks = [min(tubes, key=size), max(tubes, key=size), min(bubbles, key=size), max(bubbles, key=size)]
+    for i in picks:
+        alone = P.Sim(cases[i], serial=1)
+        sa = alone.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=1)
+        _stats_equal(st[i], sa, cases[i]["name"], alone.totals())
+        _same(sims[i], alone, cases[i]["name"])
+        alone.close()
+    i = picks[0]
+    o = O.OracleSim(cases[i])
+    so = o.advance(1.0, mode=1, max_cycles=1)
+    assert st[i]["steps"] == so["steps"]
+    _, cg, _ = sims[i].state(device=False)
+    _, co, _ = o.state()
+    for k in range(2):
+        for q in range(3):
+            sc = max(np.abs(co[k, q]).max(), np.sqrt(np.abs(co[k, 0]).max() * np.abs(co[k, 2]).max()), 1e-300)
+            assert np.abs(cg[k, q] - co[k, q]).max() / sc <= 1e-10, (k, q)
+    b.close()
+    for s in sims:
+        s.close()
