@@ -211,6 +211,13 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     A(g.tcore, (size_t)g.ntiles); A(g.tflag, (size_t)g.ntiles); A(g.tsign, (size_t)g.ntiles);
     A(g.tphimin, (size_t)g.ntiles);
     A(g.lists, (size_t)NLISTS * g.ntiles);
+    // extension stencil lists (3-D): a cell is a target of the primitive
+    // extension at most once per fluid and of the velocity extension once
+    g.wl_cap = D == 3 ? 4 * g.ntiles * 128 : 0;   // 64 cells x 2 fluids per wave
+    g.vl_cap = D == 3 ? 4 * g.ntiles * 64 : 0;
+    A(g.wl_n, D == 3 ? (size_t)4 * g.ntiles : 1); A(g.vl_n, D == 3 ? (size_t)4 * g.ntiles : 1);
+    A(g.wl_c, (size_t)g.wl_cap); A(g.wl_up, (size_t)3 * g.wl_cap); A(g.wl_w, (size_t)4 * g.wl_cap);
+    A(g.vl_c, (size_t)g.vl_cap); A(g.vl_up, (size_t)3 * g.vl_cap); A(g.vl_w, (size_t)4 * g.vl_cap);
     // reductions (8 words) and list counts (16 ints) share one block, read
     // back with one copy; the counts, read by every grid-stride loop, sit
     // 256 bytes away from the words the reductions update atomically

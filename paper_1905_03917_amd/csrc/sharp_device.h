@@ -67,6 +67,19 @@ struct Dev {
     double* bacc[2];  // boundary inflow accumulators [NV][nbface]
     // tiles
     double* tphimin;  // per tile: min |phi| over the tile and its one-cell halo at the last geometry
+    // 3-D extension: the first Jacobi sweep of each extension records its
+    // targets and their upwind stencils; the later sweeps walk these lists.
+    // Wave w of the tile at inner-list position ti owns the slots from
+    // (4 ti + w) * WL_WAVE (primitives) or * VL_WAVE (velocity).
+    int* wl_n;        // [4 ntiles] entries per wave, primitive list
+    int* wl_c;        // primitive list: cell | fluid << 31
+    int* wl_up;       // [3][wl_cap] upwind neighbours
+    double* wl_w;     // [4][wl_cap] weights along x, y, z and their sum
+    int* vl_n;        // [4 ntiles] entries per wave, velocity list
+    int* vl_c;        // velocity list: cell
+    int* vl_up;       // [3][vl_cap]
+    double* vl_w;     // [4][vl_cap]
+    int wl_cap, vl_cap;
     int* tcore;       // tile holds band cells
     int* tflag;       // bit0 band tile, bit1 candidate tile, bit2 ring tile
     int* tsign;       // fluid of a tile outside the band

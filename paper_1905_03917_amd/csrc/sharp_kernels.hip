@@ -823,6 +823,107 @@ __global__ void __launch_bounds__(SHARP_WG) k_prims(Dev g, int list, int k, cons
 }
 
 // ---------------------------------------------------------------------------
+// 3-D extension stencil lists.  The first sweep of an extension records each
+// target (cell, for the primitives also the fluid) with its upwind
+// neighbours and weights; the sweeps after it only redo the weighted average
+// over the list, with the same arithmetic as the full sweep.  The targets and
+// stencils depend on the geometry and the level set only, which do not
+// change between the sweeps of one extension.  Each wave of a tile writes
+// its targets to slots of its own, ranked by a ballot, and its count; no
+// atomics, and the layout does not depend on timing.
+// ---------------------------------------------------------------------------
+constexpr int WL_WAVE = 128;   // primitive targets per wave: 64 cells x 2 fluids
+constexpr int VL_WAVE = 64;
+
+__device__ __forceinline__ void xl_put(int cap, int* lc, int* lup, double* lw, size_t e, int code, const int* up,
+                                       const double* w, double wsum)
+{
+    lc[e] = code;
+    for (int d = 0; d < 3; d++) {
+        lup[(size_t)d * cap + e] = up[d];
+        lw[(size_t)d * cap + e] = w[d];
+    }
+    lw[(size_t)3 * cap + e] = wsum;
+}
+
+// zero the per-wave counts of the inner tiles (waves whose cells all lie
+// outside the grid or the band record nothing)
+__device__ __forceinline__ void b_xl_reset(const VB blk, const Dev& g, int which)
+{
+    int* cnt = which == 0 ? g.wl_n : g.vl_n;
+    const int n = 4 * list_count(g, LIST_INNER);
+    for (int e = blk.b * blockDim.x + threadIdx.x; e < n; e += blk.n * blockDim.x) cnt[e] = 0;
+}
+__global__ void __launch_bounds__(SHARP_WG) k_xl_reset(Dev g, int which)
+{
+    b_xl_reset(VB::grid(), g, which);
+}
+
+// later sweeps of the primitive extension (3-D): both fluids from the list
+__device__ __forceinline__ void b_extw_list(const VB blk, const Dev& g, int in, int out)
+{
+    constexpr int NV = 5;
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int ti = blk.b; ti < list_count(g, LIST_INNER); ti += blk.n) {
+        const int n = g.wl_n[4 * ti + wv];
+        const size_t base = (size_t)(4 * ti + wv) * WL_WAVE;
+        for (int r = lane; r < n; r += 64) {
+            const size_t e = base + r;
+            const int code = g.wl_c[e];
+            const int c = code & 0x7fffffff, k = (int)((unsigned)code >> 31);
+            const double* Wi = g.Wb[k][in];
+            double* Wo = g.Wb[k][out];
+            int up[3];
+            double w[3];
+            for (int d = 0; d < 3; d++) {
+                up[d] = g.wl_up[(size_t)d * g.wl_cap + e];
+                w[d] = g.wl_w[(size_t)d * g.wl_cap + e];
+            }
+            const double wsum = g.wl_w[(size_t)3 * g.wl_cap + e];
+            for (int q = 0; q < NV; q++) {
+                double acc = 0.0;
+                for (int d = 0; d < 3; d++) acc += w[d] * Wi[(size_t)q * g.nc + up[d]];
+                Wo[(size_t)q * g.nc + c] = acc / wsum;
+            }
+        }
+    }
+}
+__global__ void __launch_bounds__(SHARP_WG) k_extw_list(Dev g, int in, int out)
+{
+    b_extw_list(VB::grid(), g, in, out);
+}
+
+// later sweeps of the velocity extension (3-D)
+__device__ __forceinline__ void b_extv_list(const VB blk, const Dev& g, int in, int out)
+{
+    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int ti = blk.b; ti < list_count(g, LIST_INNER); ti += blk.n) {
+        const int n = g.vl_n[4 * ti + wv];
+        const size_t base = (size_t)(4 * ti + wv) * VL_WAVE;
+        for (int r = lane; r < n; r += 64) {
+            const size_t e = base + r;
+            const int c = g.vl_c[e];
+            int up[3];
+            double w[3];
+            for (int d = 0; d < 3; d++) {
+                up[d] = g.vl_up[(size_t)d * g.vl_cap + e];
+                w[d] = g.vl_w[(size_t)d * g.vl_cap + e];
+            }
+            const double wsum = g.vl_w[(size_t)3 * g.vl_cap + e];
+            for (int q = 0; q < 3; q++) {
+                double acc = 0.0;
+                for (int d = 0; d < 3; d++) acc += w[d] * g.v[in][q][up[d]];
+                g.v[out][q][c] = acc / wsum;
+            }
+        }
+    }
+}
+__global__ void __launch_bounds__(SHARP_WG) k_extv_list(Dev g, int in, int out)
+{
+    b_extv_list(VB::grid(), g, in, out);
+}
+
+// ---------------------------------------------------------------------------
 // extension: one Jacobi sweep of the upwind steady state of
 // dq/dtau + n.grad q = 0 for both fluids' primitives
 // ---------------------------------------------------------------------------
@@ -845,12 +946,23 @@ __device__ __forceinline__ void b_extw(const VB blk, const Dev& g, int list, int
         double ph = phi_at(g, cur, c);
         double gr[3];
         double gm = -1.0;
+        // recording (3-D first sweep): this wave's slots and running count
+        const bool record = D == 3 && copy && list == LIST_INNER;
+        const int lane = threadIdx.x & 63;
+        const size_t wbase = (size_t)(4 * ti + (threadIdx.x >> 6)) * WL_WAVE;
+        int off = 0;
         for (int k = 0; k < 2; k++) {
             const double* Wi = g.Wb[k][in];
             double* Wo = g.Wb[k][out];
             double sk = k == 0 ? 1.0 : -1.0;
             bool target = alpha_k(g, k, c) < g.amix && !(sk * ph > g.extb * g.h);
             if (target && gm < 0.0) gm = grad_phi<D>(g, cur, c, gr);
+            int slot = 0;
+            if (record) {
+                const unsigned long long mk = __ballot(target && gm > 0.0);
+                slot = off + __popcll(mk & ((1ull << lane) - 1ull));
+                off += __popcll(mk);
+            }
             if (!target || !(gm > 0.0)) {
                 if (copy)
                     for (int q = 0; q < NV; q++) Wo[(size_t)q * g.nc + c] = Wi[(size_t)q * g.nc + c];
@@ -869,6 +981,13 @@ __device__ __forceinline__ void b_extw(const VB blk, const Dev& g, int list, int
                 for (int d = 0; d < D; d++) acc += w[d] * Wi[(size_t)q * g.nc + up[d]];
                 Wo[(size_t)q * g.nc + c] = acc / wsum;
             }
+            if (record)
+                xl_put(g.wl_cap, g.wl_c, g.wl_up, g.wl_w, wbase + slot, (int)((unsigned)c | ((unsigned)k << 31)), up,
+                       w, wsum);
+        }
+        if (record) {
+            const unsigned long long act = __ballot(1);
+            if (lane == __ffsll((long long)act) - 1) g.wl_n[4 * ti + (threadIdx.x >> 6)] = off;
         }
     }
 }
@@ -893,6 +1012,16 @@ __device__ __forceinline__ void b_extv(const VB blk, const Dev& g, int list, int
         bool cut = iface<D>(g, i, j, kk, gv) > 0.0;
         double gr[3];
         double gm = cut ? 0.0 : grad_phi<D>(g, cur, c, gr);
+        // recording (3-D first sweep): this wave's slot and count
+        const bool record = D == 3 && copy && list == LIST_INNER;
+        int slot = 0;
+        if (record) {
+            const int lane = threadIdx.x & 63;
+            const unsigned long long mk = __ballot(!cut && gm > 0.0);
+            const unsigned long long act = __ballot(1);
+            slot = __popcll(mk & ((1ull << lane) - 1ull));
+            if (lane == __ffsll((long long)act) - 1) g.vl_n[4 * ti + (threadIdx.x >> 6)] = __popcll(mk);
+        }
         if (cut || !(gm > 0.0)) {
             if (copy)
                 for (int e = 0; e < D; e++) g.v[out][e][c] = g.v[in][e][c];
@@ -912,6 +1041,8 @@ __device__ __forceinline__ void b_extv(const VB blk, const Dev& g, int list, int
             for (int d = 0; d < D; d++) acc += w[d] * g.v[in][e][up[d]];
             g.v[out][e][c] = acc / wsum;
         }
+        if (record) xl_put(g.vl_cap, g.vl_c, g.vl_up, g.vl_w, (size_t)(4 * ti + (threadIdx.x >> 6)) * VL_WAVE + slot, c,
+                           up, w, wsum);
     }
 }
 template <int D>
@@ -2647,6 +2778,18 @@ struct Engine {
     }
     void extw(const double* cur)
     {
+        if constexpr (D == 3) {
+            // the first sweep records the targets, the others walk the list
+            if (s.o.ext_iters < 1) return;
+            go<b_xl_reset, SHARP_WG>(k_xl_reset, grid(LIST_INNER), wg(), s.stream, g, 0);
+            go<b_extw<D>, SHARP_WG>(k_extw<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, s.wcur, 1 - s.wcur, cur, 1);
+            s.wcur ^= 1;
+            for (int it = 1; it < s.o.ext_iters; it++) {
+                go<b_extw_list, SHARP_WG>(k_extw_list, grid(LIST_INNER), wg(), s.stream, g, s.wcur, 1 - s.wcur);
+                s.wcur ^= 1;
+            }
+            return;
+        }
         for (int it = 0; it < s.o.ext_iters; it++) {
             go<b_extw<D>, SHARP_WG>(k_extw<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, s.wcur, 1 - s.wcur, cur,
                                      it == 0);
@@ -2660,6 +2803,17 @@ struct Engine {
     }
     void extv(const double* cur)
     {
+        if constexpr (D == 3) {
+            if (s.o.ext_iters < 1) return;
+            go<b_xl_reset, SHARP_WG>(k_xl_reset, grid(LIST_INNER), wg(), s.stream, g, 1);
+            go<b_extv<D>, SHARP_WG>(k_extv<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, s.vcur, 1 - s.vcur, cur, 1);
+            s.vcur ^= 1;
+            for (int it = 1; it < s.o.ext_iters; it++) {
+                go<b_extv_list, SHARP_WG>(k_extv_list, grid(LIST_INNER), wg(), s.stream, g, s.vcur, 1 - s.vcur);
+                s.vcur ^= 1;
+            }
+            return;
+        }
         for (int it = 0; it < s.o.ext_iters; it++) {
             go<b_extv<D>, SHARP_WG>(k_extv<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, s.vcur, 1 - s.vcur, cur,
                                      it == 0);
