@@ -1564,12 +1564,13 @@ template <> struct FaceCount<2> { static constexpr int n0 = 17 * 16, n1 = 16 * 1
 
 // state of fluid k at cell c for a stage: primitives W and conservative U
 // (ghost states below alpha_mix on band tiles)
+// mine: the cell is known to lie in fluid k (alpha_k = 1, not read)
 template <int D, bool BAND>
 __device__ __forceinline__ void load_state(const Dev& g, int k, const double* in, const double* self2, int wb,
-                                           int c, double* W, double* U)
+                                           int c, double* W, double* U, bool mine = false)
 {
     constexpr int NV = D + 2;
-    double a = BAND ? alpha_k(g, k, c) : 1.0;
+    double a = BAND ? (mine ? 1.0 : alpha_k(g, k, c)) : 1.0;
     if (BAND && a < g.amix) {
         const double* Wg = g.Wb[k][wb];
         for (int q = 0; q < NV; q++) W[q] = Wg[(size_t)q * g.nc + c];
@@ -1583,6 +1584,23 @@ __device__ __forceinline__ void load_state(const Dev& g, int k, const double* in
         for (int q = 0; q < NV; q++) U[q] = src[(size_t)q * g.nc + c];
     }
     cons2prim<D>(g.gam[k], g.pinf[k], U, W);
+}
+
+// Band tiles far from the interface.  When the level set stays farther than
+// 8 cells from every cell of the tile and its one-cell halo (the geometry
+// kernels record that minimum), the stage's region (three cells beyond the
+// tile), its faces and their vertices lie on one side of the interface:
+// volume fractions and apertures are exactly 1 or 0 and no cell is cut.
+// Returns 1 when that side is fluid k (the band update is the plain update:
+// the fractions and apertures are not read, the interface term is zero), 2
+// when it is the other fluid (every aperture is 0: no flux, the update keeps
+// the stage input), 0 otherwise.
+constexpr double STAGE_FAR = 8.0;
+template <int D>
+__device__ __forceinline__ int band_far(const Dev& g, int k, int t, int ox, int oy, int oz)
+{
+    if (!(g.tphimin[t] > STAGE_FAR * g.h)) return 0;
+    return alpha_k(g, k, ox + g.n[0] * (oy + g.n[1] * oz)) == 1.0 ? 1 : 2;
 }
 
 // ---------------------------------------------------------------------------
@@ -1628,10 +1646,11 @@ __device__ __forceinline__ void b_stage_lds(const VB blk, const Dev& g, int list
         int t = L[ti];
         int tx = t % g.nt[0], ty = (t / g.nt[0]) % g.nt[1];
         int ox = tx * TX, oy = ty * TY;
+        const int far = BAND ? band_far<D>(g, k, t, ox, oy, 0) : 0;
         // ---- primitives of the tile and its halo (the corners are never used:
         // in 2-D the 448 other region cells are enumerated densely) ----
         constexpr int NL = D == 2 ? RN - 4 * 9 : RN;
-        for (int q = threadIdx.x; q < NL; q += NT) {
+        for (int q = threadIdx.x; q < (far == 2 ? 0 : NL); q += NT) {
             int rx, ry;
             if (D == 1) {
                 rx = q;
@@ -1651,7 +1670,7 @@ __device__ __forceinline__ void b_stage_lds(const VB blk, const Dev& g, int list
             int r = rx + RX * ry;
             int c = cidx(g, ox - 3 + rx, D == 2 ? oy - 3 + ry : 0, 0);
             double W[NV], U[NV];
-            load_state<D, BAND>(g, k, in, self2, wb, c, W, U);
+            load_state<D, BAND>(g, k, in, self2, wb, c, W, U, far == 1);
             sR[r] = W[0];
             sU[r] = W[1];
             if (D == 2) sV[r] = W[2];
@@ -1666,10 +1685,10 @@ __device__ __forceinline__ void b_stage_lds(const VB blk, const Dev& g, int list
             if (f < F0) { d = 0; li = f % (TX + 1); lj = f / (TX + 1); }
             else { int r = f - F0; d = 1; li = r % TX; lj = r / TX; }
             int i = ox + li, j = oy + lj;
-            bool ok = d == 0 ? (i <= g.n[0] && j < g.n[1]) : (i < g.n[0] && j <= g.n[1]);
+            bool ok = far != 2 && (d == 0 ? (i <= g.n[0] && j < g.n[1]) : (i < g.n[0] && j <= g.n[1]));
             double* Fo = sF + (size_t)f * NV;
             double A = 1.0;
-            if (ok && BAND) {
+            if (ok && BAND && !far) {
                 A = g.ap[d][fidx(g, i, j, 0)];
                 if (k == 1) A = 1.0 - A;
                 ok = A > 0.0;
@@ -1745,7 +1764,7 @@ __device__ __forceinline__ void b_stage_lds(const VB blk, const Dev& g, int list
 #pragma unroll
                     for (int q = 0; q < NV; q++) Lr[q] += (sF[(size_t)fyl * NV + q] - sF[(size_t)(fyl + TX) * NV + q]) * ih;
                 }
-                if (BAND) {
+                if (BAND && !far) {
                     double gv[3];
                     double gn = iface<D>(g, i, j, 0, gv);
                     if (gn > 0.0) {
@@ -1848,18 +1867,19 @@ __device__ __forceinline__ void b_stage_lds3(const VB blk, const Dev& g, int lis
         tile_origin<D>(g, t, ox, oy, oz);
         const int i = ox + li, j = oy + lj, kk = oz + lk;
         const bool inside = own && i < g.n[0] && j < g.n[1] && kk < g.n[2];
+        const int far = BAND ? band_far<D>(g, k, t, ox, oy, oz) : 0;
         // the thread's own cell, converted once
         double Wc[NV], Uc[NV], cc = 0.0;
-        if (own) {
+        if (own && far != 2) {
             int c = cidx(g, i, j, kk);
-            load_state<D, BAND>(g, k, in, self2, wb, c, Wc, Uc);
+            load_state<D, BAND>(g, k, in, self2, wb, c, Wc, Uc, far == 1);
             cc = csound(gm, pi, Wc[0], Wc[NV - 1]);
         }
         double Lr[NV];
 #pragma unroll
         for (int q = 0; q < NV; q++) Lr[q] = 0.0;
 #pragma unroll 1
-        for (int d = 0; d < D; d++) {
+        for (int d = 0; d < (far == 2 ? 0 : D); d++) {
             const int RX = TX + (d == 0 ? 6 : 0), RY = TY + (d == 1 ? 6 : 0), RZ = TZ + (d == 2 ? 6 : 0);
             const int RN = RX * RY * RZ;
             const int hx = d == 0 ? 3 : 0, hy = d == 1 ? 3 : 0, hz = d == 2 ? 3 : 0;
@@ -1871,7 +1891,7 @@ __device__ __forceinline__ void b_stage_lds3(const VB blk, const Dev& g, int lis
                 if (od >= 3 && od < nd - 3) continue;
                 int c = cidx(g, ox - hx + rx, oy - hy + ry, oz - hz + rz);
                 double W[NV], U[NV];
-                load_state<D, BAND>(g, k, in, self2, wb, c, W, U);
+                load_state<D, BAND>(g, k, in, self2, wb, c, W, U, far == 1);
                 sR[q] = W[0];
                 sU[q] = W[1];
                 sV[q] = W[2];
@@ -1903,7 +1923,7 @@ __device__ __forceinline__ void b_stage_lds3(const VB blk, const Dev& g, int lis
                           (d == 2 ? fk <= g.n[2] : fk < g.n[2]);
                 double* Fo = sF + (size_t)f * NV;
                 double A = 1.0;
-                if (ok && BAND) {
+                if (ok && BAND && !far) {
                     A = g.ap[d][fidx(g, fi, fj, fk)];
                     if (k == 1) A = 1.0 - A;
                     ok = A > 0.0;
@@ -1971,7 +1991,7 @@ __device__ __forceinline__ void b_stage_lds3(const VB blk, const Dev& g, int lis
         // ---- cell update ----
         if (inside) {
             int c = i + g.n[0] * (j + g.n[1] * kk);
-            if (BAND) {
+            if (BAND && !far) {
                 double gv[3];
                 double gn = iface<D>(g, i, j, kk, gv);
                 if (gn > 0.0) {
