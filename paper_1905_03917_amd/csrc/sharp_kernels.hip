@@ -338,25 +338,40 @@ __device__ __forceinline__ void b_geom_lds(const VB blk, const Dev& g, int list,
     __shared__ double sP[CN];
     __shared__ double sV[VN];
     __shared__ double sMin[SHARP_WG / 64];
+    __shared__ unsigned sSgn[SHARP_WG / 64];
     const int* L = list_ptr(g, list);
     for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int t = L[ti];
         int ox = (t % g.nt[0]) * TX, oy = ((t / g.nt[0]) % g.nt[1]) * TY, oz = (t / (g.nt[0] * g.nt[1])) * TZ;
         // cells (ox-1 .. ox+TX) x ...; also min |phi| over them (the mixing
-        // region of the tile)
+        // region of the tile) and which signs occur (bit 0: phi < 0, bit 1:
+        // phi >= 0)
         double pmin = INFINITY;
+        unsigned sgn = 0;
         for (int r = threadIdx.x; r < CN; r += SHARP_WG) {
             int cx = r % CX, cy = (r / CX) % CY, cz = r / (CX * CY);
             sP[r] = phi_at(g, cur, cidx(g, ox - 1 + cx, D > 1 ? oy - 1 + cy : 0, D > 2 ? oz - 1 + cz : 0));
             pmin = fmin(pmin, fabs(sP[r]));
+            sgn |= sP[r] < 0.0 ? 1u : (sP[r] > 0.0 ? 2u : 3u);
         }
         for (int off = 32; off > 0; off >>= 1) pmin = fmin(pmin, __shfl_down(pmin, off, 64));
-        if ((threadIdx.x & 63) == 0) sMin[threadIdx.x >> 6] = pmin;
+        const unsigned wsgn = (__ballot(sgn & 1u) ? 1u : 0u) | (__ballot(sgn & 2u) ? 2u : 0u);
+        if ((threadIdx.x & 63) == 0) {
+            sMin[threadIdx.x >> 6] = pmin;
+            sSgn[threadIdx.x >> 6] = wsgn;
+        }
         __syncthreads();
         if (threadIdx.x == 0) {
             for (int w = 1; w < SHARP_WG / 64; w++) pmin = fmin(pmin, sMin[w]);
             g.tphimin[t] = pmin;
         }
+        // every cell of the region on one side, none on the level set: all
+        // vertices share that sign, so every aperture (and the volume
+        // fraction) is exactly 1 (phi < 0) or 0 (phi > 0)
+        unsigned tsg = 0;
+        for (int w = 0; w < SHARP_WG / 64; w++) tsg |= sSgn[w];
+        const bool one_side = tsg == 1u || tsg == 2u;
+        const double side_A = tsg == 1u ? 1.0 : 0.0;
         // vertex (vx, vy, vz) <-> corner (ox+vx, ...): mean of cells (vx-1 .. vx) in region offset +1
         for (int r = threadIdx.x; r < VN; r += SHARP_WG) {
             int vx = r % VX, vy = (r / VX) % VY, vz = r / (VX * VY);
@@ -384,7 +399,9 @@ __device__ __forceinline__ void b_geom_lds(const VB blk, const Dev& g, int list,
                 for (int side = 0; side < 2; side++) {
                     int sx = d == 0 ? side : 0, sy = d == 1 ? side : 0, sz = d == 2 ? side : 0;
                     double A;
-                    if (D == 1) {
+                    if (one_side) {
+                        A = side_A;
+                    } else if (D == 1) {
                         A = V(sx, 0, 0) < 0.0 ? 1.0 : 0.0;
                     } else if (D == 2) {
                         A = d == 0 ? edge_frac(V(sx, 0, 0), V(sx, 1, 0)) : edge_frac(V(0, sy, 0), V(1, sy, 0));
@@ -401,7 +418,9 @@ __device__ __forceinline__ void b_geom_lds(const VB blk, const Dev& g, int list,
                 if (ii[d] == g.n[d] - 1) g.ap[d][fidx(g, i + (d == 0), j + (d == 1), k + (d == 2))] = ahi[d];
             }
             double a;
-            if (D == 1) {
+            if (one_side && D <= 2) {
+                a = side_A;
+            } else if (D == 1) {
                 a = edge_frac(V(0, 0, 0), V(1, 0, 0));
             } else if (D == 2) {
                 double v[4] = {V(0, 0, 0), V(1, 0, 0), V(1, 1, 0), V(0, 1, 0)};
