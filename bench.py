@@ -429,7 +429,7 @@ def batch_timing(P, WL, cycles_multi=3, steps_single=10, one_at_a_time=True):
         for x in sims:
             x.close()
         res[key] = dict(cycles=K, batched_s=tb, cell_updates=ub, value=ub / tb,
-                        rounds=i1["rounds"] - i0["rounds"], fused_launches=i1["fused_launches"] - i0["fused_launches"],
+                        passes=i1["passes"] - i0["passes"], fused_launches=i1["fused_launches"] - i0["fused_launches"],
                         launch_records=i1["records"] - i0["records"])
         if not one_at_a_time:
             continue

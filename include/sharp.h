@@ -212,10 +212,11 @@ sim_status sim_batch_create(sim_t* const* sims, int n, sim_batch_t** out);
 sim_status sim_batch_advance(sim_batch_t* b, const double* t_end, int mode, int64_t max_cycles, sim_stats* stats,
                              sim_status* status);
 
-/* Totals since creation: rounds (host decisions), fused launches issued,
+/* Totals since creation: passes (one per host decision point: each ends
+ * with one synchronisation), fused launches issued,
  * and launch records they carried (each a launch that the simulations would
  * have issued on their own). */
-sim_status sim_batch_info(sim_batch_t* b, int64_t* rounds, int64_t* fused_launches, int64_t* records);
+sim_status sim_batch_info(sim_batch_t* b, int64_t* passes, int64_t* fused_launches, int64_t* records);
 void sim_batch_destroy(sim_batch_t* b);
 
 void sim_destroy(sim_t* s);

@@ -276,7 +276,7 @@ class Batch:
     def info(self):
         v = [C.c_int64() for _ in range(3)]
         _check(lib().sim_batch_info(self.h, *[C.byref(x) for x in v]), "sim_batch_info")
-        return dict(rounds=v[0].value, fused_launches=v[1].value, records=v[2].value)
+        return dict(passes=v[0].value, fused_launches=v[1].value, records=v[2].value)
 
     def close(self):
         if getattr(self, "h", None):

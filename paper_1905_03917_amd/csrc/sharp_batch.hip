@@ -8,12 +8,12 @@
 // of its reduction block (the host decisions of the method: the CFL steps,
 // the tile lists, the sub-step plan) becomes a recorded copy into a slot
 // followed by a yield.  The driver resumes every unfinished simulation in
-// turn until each has yielded or finished (a round), then merges the
+// turn until each has yielded or finished (a pass), then merges the
 // recorded launches: it repeatedly takes the kernel that heads the most
 // simulations' queues and issues one fused launch for all of them, so that
 // each simulation's launches keep their order.  One upload carries the
-// rounds' device views and argument records, one copy brings every slot
-// back, and the round ends with one synchronisation.  The work a round
+// pass's device views and argument records, one copy brings every slot
+// back, and the pass ends with one synchronisation.  The work a pass
 // enqueues is what the simulations would have enqueued on their own, in the
 // same order per simulation: the same steps, with states equal to those of
 // separate runs up to round-off (a fused kernel is the same body compiled
@@ -54,11 +54,11 @@ struct sim_batch_impl {
     long long max_cycles = 0;
     unsigned long long* d_slots = nullptr;   // n * RED_WORDS readback slots
     unsigned long long* h_slots = nullptr;   // pinned copy of the slots
-    unsigned char* d_buf = nullptr;          // device views, record offsets and argument records of a round
+    unsigned char* d_buf = nullptr;          // device views, record offsets and argument records of a pass
     unsigned char* h_buf = nullptr;          // pinned staging of d_buf
     size_t cap = 0;
     std::vector<unsigned char> stage;
-    long long rounds = 0, fused = 0, recorded = 0;
+    long long passes = 0, fused = 0, recorded = 0;
 };
 
 static void co_entry(unsigned lo, unsigned hi)
@@ -85,7 +85,7 @@ struct FusedLaunch {
     size_t pre_off, rec_off;
 };
 
-// merge and issue the recorded launches of a round, then bring the
+// merge and issue the recorded launches of a pass, then bring the
 // readback slots to the simulations that asked for them
 static sim_status flush(sim_batch_impl& B)
 {
@@ -201,7 +201,7 @@ static sim_status flush(sim_batch_impl& B)
         }
         r.clear();
     }
-    B.rounds++;
+    B.passes++;
     return SIM_OK;
 }
 
@@ -348,10 +348,10 @@ sim_status sim_batch_advance(sim_batch_t* h, const double* t_end, int mode, int6
     return first;
 }
 
-sim_status sim_batch_info(sim_batch_t* h, int64_t* rounds, int64_t* fused_launches, int64_t* records)
+sim_status sim_batch_info(sim_batch_t* h, int64_t* passes, int64_t* fused_launches, int64_t* records)
 {
     if (!h) { set_error("null handle"); return SIM_EINVAL; }
-    if (rounds) *rounds = h->b->rounds;
+    if (passes) *passes = h->b->passes;
     if (fused_launches) *fused_launches = h->b->fused;
     if (records) *records = h->b->recorded;
     return SIM_OK;

@@ -45,7 +45,7 @@ struct Recorder {
     std::vector<Dev> devs;        // device views the records refer to (index local to this simulation)
     unsigned long long* slot = nullptr;   // device readback slot of this simulation (RED_WORDS words)
     bool rb_pending = false;
-    sim_status status = SIM_OK;   // of the driver's last round, returned by the wait
+    sim_status status = SIM_OK;   // of the driver's last pass, returned by the wait
     void (*yield)(void*) = nullptr;
     void* yield_arg = nullptr;
     int dev_index(const Dev& d)
