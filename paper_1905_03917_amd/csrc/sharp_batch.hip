@@ -13,7 +13,10 @@
 // simulations' queues and issues one fused launch for all of them, so that
 // each simulation's launches keep their order.  One upload carries the
 // pass's device views and argument records, one copy brings every slot
-// back, and the pass ends with one synchronisation.  The work a pass
+// back, and an event marks the end of the pass.  The simulations form two
+// groups (alternate members) with a stream, staging buffers and slot range
+// each: while the GPU runs one group's pass, the host resumes the other
+// group and records its next one.  The work a pass
 // enqueues is what the simulations would have enqueued on their own, in the
 // same order per simulation: the same steps, with states equal to those of
 // separate runs up to round-off (a fused kernel is the same body compiled
@@ -33,6 +36,7 @@ namespace sharp {
 
 struct BatchInst {
     Sim* s = nullptr;
+    int slot = 0;                 // readback slot index
     Recorder rec;
     ucontext_t ctx;
     bool done = false;
@@ -45,19 +49,30 @@ struct BatchInst {
 
 static constexpr size_t CO_STACK = 1u << 20;   // per simulation (mapped lazily)
 
+// a group of a batch's simulations: its members' passes run on its stream,
+// in its buffers, and fill its range of readback slots
+struct BatchGroup {
+    std::vector<int> members;                // simulation indices, in order
+    int slot0 = 0;                           // first readback slot (member m has slot0 + m)
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    hipEvent_t ev = nullptr;                 // end of the pass in flight
+    bool pending = false;                    // a pass is in flight
+    unsigned char* d_buf = nullptr;          // device views, record offsets and argument records of a pass
+    unsigned char* h_buf = nullptr;          // pinned staging of d_buf
+    size_t cap = 0;
+    std::vector<unsigned char> stage;
+};
+
 struct sim_batch_impl {
     std::vector<BatchInst> in;
+    std::vector<BatchGroup> grp;
     std::vector<void*> stacks;
-    hipStream_t stream = nullptr;
     ucontext_t sched;
     int mode = 0;
     long long max_cycles = 0;
     unsigned long long* d_slots = nullptr;   // n * RED_WORDS readback slots
     unsigned long long* h_slots = nullptr;   // pinned copy of the slots
-    unsigned char* d_buf = nullptr;          // device views, record offsets and argument records of a pass
-    unsigned char* h_buf = nullptr;          // pinned staging of d_buf
-    size_t cap = 0;
-    std::vector<unsigned char> stage;
     long long passes = 0, fused = 0, recorded = 0;
 };
 
@@ -85,34 +100,34 @@ struct FusedLaunch {
     size_t pre_off, rec_off;
 };
 
-// merge and issue the recorded launches of a pass, then bring the
-// readback slots to the simulations that asked for them
-static sim_status flush(sim_batch_impl& B)
+// merge and issue the recorded launches of group G's members, then the copy
+// of its readback slots and the event that ends the pass
+static sim_status pass_issue(sim_batch_impl& B, BatchGroup& G)
 {
-    const int n = (int)B.in.size();
-    std::vector<unsigned char>& H = B.stage;
+    const int n = (int)G.members.size();
+    auto rec = [&](int m) -> Recorder& { return B.in[G.members[m]].rec; };
+    std::vector<unsigned char>& H = G.stage;
     H.clear();
     std::vector<size_t> dbase(n);
     size_t ndev = 0;
-    for (int i = 0; i < n; i++) {
-        dbase[i] = ndev;
-        ndev += B.in[i].rec.devs.size();
+    for (int m = 0; m < n; m++) {
+        dbase[m] = ndev;
+        ndev += rec(m).devs.size();
     }
     H.resize(ndev * sizeof(Dev));
-    for (int i = 0; i < n; i++)
-        if (!B.in[i].rec.devs.empty())
-            std::memcpy(H.data() + dbase[i] * sizeof(Dev), B.in[i].rec.devs.data(),
-                        B.in[i].rec.devs.size() * sizeof(Dev));
+    for (int m = 0; m < n; m++)
+        if (!rec(m).devs.empty())
+            std::memcpy(H.data() + dbase[m] * sizeof(Dev), rec(m).devs.data(), rec(m).devs.size() * sizeof(Dev));
     std::vector<size_t> cur(n, 0);
     std::vector<FusedLaunch> L;
     std::vector<std::pair<const void*, int>> heads;
     std::vector<int> members, pre;
     for (;;) {
         heads.clear();
-        for (int i = 0; i < n; i++) {
-            const Recorder& r = B.in[i].rec;
-            if (cur[i] >= r.ops.size()) continue;
-            const void* f = r.ops[cur[i]].fn;
+        for (int m = 0; m < n; m++) {
+            const Recorder& r = rec(m);
+            if (cur[m] >= r.ops.size()) continue;
+            const void* f = r.ops[cur[m]].fn;
             size_t h = 0;
             while (h < heads.size() && heads[h].first != f) h++;
             if (h == heads.size()) heads.push_back({f, 0});
@@ -127,17 +142,17 @@ static sim_status flush(sim_batch_impl& B)
         pre.clear();
         int grid = 0, block = 0;
         size_t rsize = 0;
-        for (int i = 0; i < n; i++) {
-            const Recorder& r = B.in[i].rec;
-            if (cur[i] >= r.ops.size() || r.ops[cur[i]].fn != f) continue;
-            const FusedOp& op = r.ops[cur[i]];
+        for (int m = 0; m < n; m++) {
+            const Recorder& r = rec(m);
+            if (cur[m] >= r.ops.size() || r.ops[cur[m]].fn != f) continue;
+            const FusedOp& op = r.ops[cur[m]];
             if (members.empty()) { block = op.block; rsize = op.size; }
             if (op.block != block || op.size != rsize) { set_error("batch: inconsistent fused launch"); return SIM_EDEVICE; }
             int start = grid;
             if (op.nblk >= 8 && (op.nblk & 7) == 0) start = (grid + 7) & ~7;
             pre.push_back(start);
             grid = start + op.nblk;
-            members.push_back(i);
+            members.push_back(m);
         }
         FusedLaunch fl;
         fl.fn = f;
@@ -149,71 +164,86 @@ static sim_status flush(sim_batch_impl& B)
         std::memcpy(H.data() + fl.pre_off, pre.data(), pre.size() * sizeof(int));
         fl.rec_off = align16(H.size());
         H.resize(fl.rec_off + members.size() * rsize);
-        for (size_t m = 0; m < members.size(); m++) {
-            const int i = members[m];
-            const FusedOp& op = B.in[i].rec.ops[cur[i]];
-            unsigned char* dst = H.data() + fl.rec_off + m * rsize;
-            std::memcpy(dst, B.in[i].rec.args.data() + op.off, rsize);
+        for (size_t q = 0; q < members.size(); q++) {
+            const int m = members[q];
+            const FusedOp& op = rec(m).ops[cur[m]];
+            unsigned char* dst = H.data() + fl.rec_off + q * rsize;
+            std::memcpy(dst, rec(m).args.data() + op.off, rsize);
             int dev;
             std::memcpy(&dev, dst, sizeof dev);
-            dev += (int)dbase[i];
+            dev += (int)dbase[m];
             std::memcpy(dst, &dev, sizeof dev);
-            cur[i]++;
+            cur[m]++;
         }
         L.push_back(fl);
         B.recorded += fl.nrec;
     }
     if (!H.empty()) {
-        if (H.size() > B.cap) {
+        if (H.size() > G.cap) {
+            // the group's previous pass has completed: its buffers are free
             size_t c = H.size() * 2;
-            if (B.d_buf) (void)hipFree(B.d_buf);
-            if (B.h_buf) (void)hipHostFree(B.h_buf);
-            B.d_buf = nullptr;
-            B.h_buf = nullptr;
-            B.cap = 0;
-            SHARP_HIP(hipMalloc((void**)&B.d_buf, c));
-            SHARP_HIP(hipHostMalloc((void**)&B.h_buf, c, hipHostMallocDefault));
-            B.cap = c;
+            if (G.d_buf) (void)hipFree(G.d_buf);
+            if (G.h_buf) (void)hipHostFree(G.h_buf);
+            G.d_buf = nullptr;
+            G.h_buf = nullptr;
+            G.cap = 0;
+            SHARP_HIP(hipMalloc((void**)&G.d_buf, c));
+            SHARP_HIP(hipHostMalloc((void**)&G.h_buf, c, hipHostMallocDefault));
+            G.cap = c;
         }
-        std::memcpy(B.h_buf, H.data(), H.size());
-        SHARP_HIP(hipMemcpyAsync(B.d_buf, B.h_buf, H.size(), hipMemcpyHostToDevice, B.stream));
+        std::memcpy(G.h_buf, H.data(), H.size());
+        SHARP_HIP(hipMemcpyAsync(G.d_buf, G.h_buf, H.size(), hipMemcpyHostToDevice, G.stream));
     }
     for (const FusedLaunch& fl : L) {
-        const Dev* devs = reinterpret_cast<const Dev*>(B.d_buf);
-        const void* recs = B.d_buf + fl.rec_off;
-        const int* pre_d = reinterpret_cast<const int*>(B.d_buf + fl.pre_off);
+        const Dev* devs = reinterpret_cast<const Dev*>(G.d_buf);
+        const void* recs = G.d_buf + fl.rec_off;
+        const int* pre_d = reinterpret_cast<const int*>(G.d_buf + fl.pre_off);
         int nrec = fl.nrec;
         void* args[4] = {(void*)&devs, (void*)&recs, (void*)&pre_d, (void*)&nrec};
-        SHARP_HIP(hipLaunchKernel(fl.fn, dim3(fl.grid), dim3(fl.block), args, 0, B.stream));
+        SHARP_HIP(hipLaunchKernel(fl.fn, dim3(fl.grid), dim3(fl.block), args, 0, G.stream));
         B.fused++;
     }
     bool rb = false;
-    for (int i = 0; i < n; i++) rb = rb || B.in[i].rec.rb_pending;
+    for (int m = 0; m < n; m++) rb = rb || rec(m).rb_pending;
     if (rb)
-        SHARP_HIP(hipMemcpyAsync(B.h_slots, B.d_slots, (size_t)n * RED_WORDS * sizeof(unsigned long long),
-                                 hipMemcpyDeviceToHost, B.stream));
-    SHARP_HIP(hipStreamSynchronize(B.stream));
-    for (int i = 0; i < n; i++) {
+        SHARP_HIP(hipMemcpyAsync(B.h_slots + (size_t)G.slot0 * RED_WORDS, B.d_slots + (size_t)G.slot0 * RED_WORDS,
+                                 (size_t)n * RED_WORDS * sizeof(unsigned long long), hipMemcpyDeviceToHost, G.stream));
+    SHARP_HIP(hipEventRecord(G.ev, G.stream));
+    G.pending = true;
+    B.passes++;
+    return SIM_OK;
+}
+
+// wait for group G's pass and hand its readbacks to the simulations
+static sim_status pass_complete(sim_batch_impl& B, BatchGroup& G)
+{
+    G.pending = false;
+    SHARP_HIP(hipEventSynchronize(G.ev));
+    for (int i : G.members) {
         Recorder& r = B.in[i].rec;
         if (r.rb_pending) {
-            std::memcpy(B.in[i].s->h_red, B.h_slots + (size_t)i * RED_WORDS, RED_WORDS * sizeof(unsigned long long));
+            std::memcpy(B.in[i].s->h_red, B.h_slots + (size_t)B.in[i].slot * RED_WORDS,
+                        RED_WORDS * sizeof(unsigned long long));
             r.rb_pending = false;
         }
         r.clear();
     }
-    B.passes++;
     return SIM_OK;
 }
 
 static void batch_free(sim_batch_impl* B)
 {
     if (!B) return;
-    if (B->stream) (void)hipStreamSynchronize(B->stream);
+    for (BatchGroup& G : B->grp) {
+        if (G.stream) (void)hipStreamSynchronize(G.stream);
+        if (G.d_buf) (void)hipFree(G.d_buf);
+        if (G.h_buf) (void)hipHostFree(G.h_buf);
+        if (G.ev) (void)hipEventDestroy(G.ev);
+        if (G.own_stream && G.stream) (void)hipStreamDestroy(G.stream);
+    }
     for (void* p : B->stacks) munmap(p, CO_STACK);
     if (B->d_slots) (void)hipFree(B->d_slots);
     if (B->h_slots) (void)hipHostFree(B->h_slots);
-    if (B->d_buf) (void)hipFree(B->d_buf);
-    if (B->h_buf) (void)hipHostFree(B->h_buf);
     delete B;
 }
 
@@ -240,11 +270,34 @@ sim_status sim_batch_create(sim_t* const* sims, int n, sim_batch_t** out)
     }
     sim_batch_impl* B = new sim_batch_impl();
     B->in.resize(n);
-    B->stream = sims[0]->s.stream;
+    // two groups of alternate members (one when n = 1): the first runs on
+    // sims[0]'s stream, the second on a stream of the batch
+    const int ng = n > 1 ? 2 : 1;
+    B->grp.resize(ng);
+    for (int i = 0; i < n; i++) B->grp[i % ng].members.push_back(i);
     sim_status rc = SIM_OK;
-    if (hipMalloc((void**)&B->d_slots, (size_t)n * RED_WORDS * sizeof(unsigned long long)) != hipSuccess ||
-        hipHostMalloc((void**)&B->h_slots, (size_t)n * RED_WORDS * sizeof(unsigned long long), hipHostMallocDefault) !=
-            hipSuccess) {
+    int slot = 0;
+    for (int g = 0; g < ng && rc == SIM_OK; g++) {
+        BatchGroup& G = B->grp[g];
+        G.slot0 = slot;
+        for (size_t m = 0; m < G.members.size(); m++) B->in[G.members[m]].slot = slot++;
+        if (g == 0) {
+            G.stream = sims[0]->s.stream;
+        } else if (hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking) == hipSuccess) {
+            G.own_stream = true;
+        } else {
+            set_error("batch: stream creation failed");
+            rc = SIM_EDEVICE;
+        }
+        if (rc == SIM_OK && hipEventCreateWithFlags(&G.ev, hipEventDisableTiming) != hipSuccess) {
+            set_error("batch: event creation failed");
+            rc = SIM_EDEVICE;
+        }
+    }
+    if (rc == SIM_OK &&
+        (hipMalloc((void**)&B->d_slots, (size_t)n * RED_WORDS * sizeof(unsigned long long)) != hipSuccess ||
+         hipHostMalloc((void**)&B->h_slots, (size_t)n * RED_WORDS * sizeof(unsigned long long), hipHostMallocDefault) !=
+             hipSuccess)) {
         (void)hipGetLastError();
         set_error("batch: allocation of the readback slots failed");
         rc = SIM_ENOMEM;
@@ -253,7 +306,7 @@ sim_status sim_batch_create(sim_t* const* sims, int n, sim_batch_t** out)
         BatchInst& bi = B->in[i];
         bi.s = &sims[i]->s;
         bi.b = B;
-        bi.rec.slot = B->d_slots + (size_t)i * RED_WORDS;
+        bi.rec.slot = B->d_slots + (size_t)bi.slot * RED_WORDS;
         bi.rec.yield = co_yield;
         bi.rec.yield_arg = &bi;
         void* st = mmap(nullptr, CO_STACK, PROT_READ | PROT_WRITE, MAP_PRIVATE | MAP_ANONYMOUS | MAP_NORESERVE, -1, 0);
@@ -311,16 +364,18 @@ sim_status sim_batch_advance(sim_batch_t* h, const double* t_end, int mode, int6
         makecontext(&bi.ctx, (void (*)())co_entry, 2, (unsigned)(p & 0xffffffffu), (unsigned)(p >> 32));
     }
     sim_status frc = SIM_OK;
-    for (;;) {
+    // resume a group's unfinished members until each yields or finishes,
+    // then issue their pass; returns whether any member was resumed
+    auto step = [&](BatchGroup& G) -> bool {
         int live = 0;
-        for (int i = 0; i < n; i++) {
+        for (int i : G.members) {
             BatchInst& bi = B.in[i];
             if (bi.done) continue;
             swapcontext(&B.sched, &bi.ctx);
             live++;
         }
-        if (live == 0) break;
-        if (frc == SIM_OK) frc = flush(B);
+        if (live == 0) return false;
+        if (frc == SIM_OK) frc = pass_issue(B, G);
         if (frc != SIM_OK) {
             // every waiting simulation sees the failure at its readback and returns
             for (int i = 0; i < n; i++) {
@@ -328,8 +383,25 @@ sim_status sim_batch_advance(sim_batch_t* h, const double* t_end, int mode, int6
                 B.in[i].rec.rb_pending = false;
                 B.in[i].rec.clear();
             }
+            for (BatchGroup& H : B.grp) H.pending = false;
         }
+        return true;
+    };
+    // the groups alternate: while one group's pass runs on the GPU, the
+    // other group is resumed and its next pass recorded and issued
+    for (BatchGroup& G : B.grp) step(G);
+    for (;;) {
+        bool any = false;
+        for (BatchGroup& G : B.grp) {
+            if (G.pending) {
+                sim_status rc = pass_complete(B, G);
+                if (rc != SIM_OK && frc == SIM_OK) frc = rc;
+            }
+            any = step(G) || any;
+        }
+        if (!any) break;
     }
+    for (BatchGroup& G : B.grp) (void)hipStreamSynchronize(G.stream);
     sim_status first = frc;
     std::string msg = frc != SIM_OK ? std::string(sim_last_error()) : std::string();
     for (int i = 0; i < n; i++) {
