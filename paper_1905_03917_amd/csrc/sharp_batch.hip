@@ -48,6 +48,11 @@ struct BatchInst {
 };
 
 static constexpr size_t CO_STACK = 1u << 20;   // per simulation (mapped lazily)
+// groups of a batch (passes in flight at once); 3 measured the same as 2 on
+// the 512-instance batch, 4 slower
+#ifndef SHARP_BATCH_GROUPS
+#define SHARP_BATCH_GROUPS 2
+#endif
 
 // a group of a batch's simulations: its members' passes run on its stream,
 // in its buffers, and fill its range of readback slots
@@ -270,9 +275,9 @@ sim_status sim_batch_create(sim_t* const* sims, int n, sim_batch_t** out)
     }
     sim_batch_impl* B = new sim_batch_impl();
     B->in.resize(n);
-    // two groups of alternate members (one when n = 1): the first runs on
-    // sims[0]'s stream, the second on a stream of the batch
-    const int ng = n > 1 ? 2 : 1;
+    // groups of alternate members (fewer when n is smaller): the first runs
+    // on sims[0]'s stream, each other one on a stream of the batch
+    const int ng = n < SHARP_BATCH_GROUPS ? n : SHARP_BATCH_GROUPS;
     B->grp.resize(ng);
     for (int i = 0; i < n; i++) B->grp[i % ng].members.push_back(i);
     sim_status rc = SIM_OK;
