@@ -13,11 +13,11 @@
 // simulations' queues and issues one fused launch for all of them, so that
 // each simulation's launches keep their order.  One upload carries the
 // pass's device views and argument records, one copy brings every slot
-// back, and an event marks the end of the pass.  The simulations form two
-// groups (alternate members) with a stream, staging buffers and slot range
-// each: while the GPU runs one group's pass, the host resumes the other
-// group and records its next one.  The work a pass
-// enqueues is what the simulations would have enqueued on their own, in the
+// back, and an event marks the end of the pass.  The simulations form
+// groups (two by default; alternate members) with a stream, staging buffers
+// and slot range each: while the GPU runs one group's pass, the host resumes
+// another group and records its next one.  The work a pass enqueues is what
+// the simulations would have enqueued on their own, in the
 // same order per simulation: the same steps, with states equal to those of
 // separate runs up to round-off (a fused kernel is the same body compiled
 // in another context, where the compiler may contract other multiply-adds).
