@@ -39,7 +39,7 @@ const double ADJ_RK2_A[2] = {0.0, 0.5};
 // indicators b_k, e_k = eps + b_k, alpha_k = d_k / e_k^2 and omega_k =
 // alpha_k / sum(alpha):
 //   dw/dv = sum_k omega_k dq_k/dv - 2 sum_k omega_k (q_k - w) / e_k db_k/dv.
-__host__ __device__ inline void weno5_vjp(const double* v, double eps, double gb, double* vb)
+__host__ __device__ __forceinline__ void weno5_vjp(const double* v, double eps, double gb, double* vb)
 {
     const double c13_12 = 13.0 / 12.0, c13_6 = 13.0 / 6.0;
     double q0 = (2.0 * v[0] - 7.0 * v[1] + 11.0 * v[2]) * (1.0 / 6.0);
@@ -87,11 +87,14 @@ __host__ __device__ inline void weno5_vjp(const double* v, double eps, double gb
 // the six stencil states U[m] (cells -3..+2 from the face), for the upstream
 // flux weights Fb.  Adds dF/dU^T Fb to Ub and the partials with respect to
 // gamma and p_inf (U fixed) to *gb, *pb.
-template <int D>
-__host__ __device__ void face_vjp(const double (*U)[D + 2], double gm, double pi, double eps, int d, const double* Fb,
-                         double (*Ub)[D + 2], double* gb, double* pb)
+// (the direction is a template parameter: with every index static the
+// stencil arrays stay in registers)
+template <int D, int DIR>
+__host__ __device__ __forceinline__ void face_vjp(const double (*U)[D + 2], double gm, double pi, double eps,
+                                                  const double* Fb, double (*Ub)[D + 2], double* gb, double* pb)
 {
     constexpr int NV = D + 2;
+    constexpr int d = DIR;
     double rho[6], vel[6][D], E[6], p[6], c[6], un[6], ke[6];
     double amax = -1.0;
     int ms = 0;
@@ -221,11 +224,13 @@ __device__ __forceinline__ long long face_index(const Dev& g, int d, const int* 
     return fc[0] + n0 * (fc[1] + n1 * (long long)fc[2]);
 }
 
-template <int D>
-__global__ void __launch_bounds__(ADJ_WG) k_adj_face(Dev g, int k, int d, const double* U, const double* lam,
+// two waves per SIMD (a few spills) measured 3% faster than one without
+template <int D, int DIR>
+__global__ void __launch_bounds__(ADJ_WG, 2) k_adj_face(Dev g, int k, const double* U, const double* lam,
                                                      double scale, double* fb, double* pacc)
 {
     constexpr int NV = D + 2;
+    constexpr int d = DIR;
     const long long nf = (long long)(g.n[0] + (d == 0)) * (g.n[1] + (d == 1)) * (g.n[2] + (d == 2));
     const double gm = g.gam[k], pi = g.pinf[k];
     double gsum = 0.0, psum = 0.0;
@@ -252,7 +257,7 @@ __global__ void __launch_bounds__(ADJ_WG) k_adj_face(Dev g, int k, int d, const 
                 Ub[m][q] = 0.0;
             }
         }
-        face_vjp<D>(Us, gm, pi, g.eps, d, Fb, Ub, &gsum, &psum);
+        face_vjp<D, DIR>(Us, gm, pi, g.eps, Fb, Ub, &gsum, &psum);
         double* o = fb + (size_t)f * 6 * NV;
 #pragma unroll
         for (int m = 0; m < 6; m++)
@@ -364,7 +369,12 @@ struct Adjoint {
     void jlt(int k, const double* U, const double* lam, double scale, double* v, double* fb, double* pacc)
     {
         for (int d = 0; d < D; d++) {
-            k_adj_face<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, d, U, lam, scale / g.h, fb, pacc);
+            if (d == 0)
+                k_adj_face<D, 0><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, U, lam, scale / g.h, fb, pacc);
+            if constexpr (D > 1)
+                if (d == 1) k_adj_face<D, 1><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, U, lam, scale / g.h, fb, pacc);
+            if constexpr (D > 2)
+                if (d == 2) k_adj_face<D, 2><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, U, lam, scale / g.h, fb, pacc);
             k_adj_gather<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, d, fb, v, d > 0);
         }
     }
