@@ -247,83 +247,7 @@ __global__ void __launch_bounds__(1024) k_compact(Dev g)
 // geometry: volume fraction and low-face apertures of every cell of the
 // listed tiles (plus the padded high faces on the domain boundary)
 // ---------------------------------------------------------------------------
-template <int D>
-__device__ __forceinline__ double vertex(const Dev& g, const double* cur, int i, int j, int k)
-{
-    double s = 0.0;
-#pragma unroll
-    for (int b = 0; b < (1 << D); b++) {
-        int ii = i - 1 + (b & 1);
-        int jj = D > 1 ? j - 1 + ((b >> 1) & 1) : 0;
-        int kk = D > 2 ? k - 1 + ((b >> 2) & 1) : 0;
-        s += phi_at(g, cur, cidx(g, ii, jj, kk));
-    }
-    return s / (double)(1 << D);
-}
-
-template <int D>
-__device__ __forceinline__ double aperture(const Dev& g, const double* cur, int d, int i, int j, int k)
-{
-    if (D == 1) return vertex<D>(g, cur, i, j, k) < 0.0 ? 1.0 : 0.0;
-    if (D == 2) {
-        if (d == 0) return edge_frac(vertex<D>(g, cur, i, j, k), vertex<D>(g, cur, i, j + 1, k));
-        return edge_frac(vertex<D>(g, cur, i, j, k), vertex<D>(g, cur, i + 1, j, k));
-    }
-    double v[4];
-    if (d == 0) {
-        v[0] = vertex<D>(g, cur, i, j, k);         v[1] = vertex<D>(g, cur, i, j + 1, k);
-        v[2] = vertex<D>(g, cur, i, j + 1, k + 1); v[3] = vertex<D>(g, cur, i, j, k + 1);
-    } else if (d == 1) {
-        v[0] = vertex<D>(g, cur, i, j, k);         v[1] = vertex<D>(g, cur, i + 1, j, k);
-        v[2] = vertex<D>(g, cur, i + 1, j, k + 1); v[3] = vertex<D>(g, cur, i, j, k + 1);
-    } else {
-        v[0] = vertex<D>(g, cur, i, j, k);         v[1] = vertex<D>(g, cur, i + 1, j, k);
-        v[2] = vertex<D>(g, cur, i + 1, j + 1, k); v[3] = vertex<D>(g, cur, i, j + 1, k);
-    }
-    return clip_area(v);
-}
-
-template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_geom(Dev g, int list, const double* cur)
-{
-    const int* L = list_ptr(g, list);
-    for (int ti = blockIdx.x; ti < list_count(g, list); ti += gridDim.x) {
-        int i, j, k;
-        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, k)) continue;
-        int c = i + g.n[0] * (j + g.n[1] * k);
-        int ii[3] = {i, j, k};
-        double alo[3], ahi[3];
-#pragma unroll
-        for (int d = 0; d < D; d++) {
-            alo[d] = aperture<D>(g, cur, d, i, j, k);
-            ahi[d] = aperture<D>(g, cur, d, i + (d == 0), j + (d == 1), k + (d == 2));
-            g.ap[d][fidx(g, i, j, k)] = alo[d];
-            if (ii[d] == g.n[d] - 1) g.ap[d][fidx(g, i + (d == 0), j + (d == 1), k + (d == 2))] = ahi[d];
-        }
-        double a;
-        if (D == 1) {
-            a = edge_frac(vertex<D>(g, cur, i, 0, 0), vertex<D>(g, cur, i + 1, 0, 0));
-        } else if (D == 2) {
-            double v[4] = {vertex<D>(g, cur, i, j, 0), vertex<D>(g, cur, i + 1, j, 0),
-                           vertex<D>(g, cur, i + 1, j + 1, 0), vertex<D>(g, cur, i, j + 1, 0)};
-            a = clip_area(v);
-        } else {
-            // divergence theorem on the wetted part of the unit cube, planar cut
-            double sumA = 0.0, g2 = 0.0;
-#pragma unroll
-            for (int d = 0; d < 3; d++) {
-                sumA += alo[d] + ahi[d];
-                double gd = alo[d] - ahi[d];
-                g2 += gd * gd;
-            }
-            a = (0.5 * sumA + sqrt(g2) * (-phi_at(g, cur, c) / g.h)) / 3.0;
-            a = a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a);
-        }
-        g.alpha[c] = a;
-    }
-}
-
-// LDS variant: the vertex values of the tile are computed once
+// the tile's and its halo's level set and vertex values are staged in LDS
 template <int D> struct GeoRegion;
 template <> struct GeoRegion<1> { static constexpr int X = 256 + 2, Y = 1, Z = 1; };
 template <> struct GeoRegion<2> { static constexpr int X = 16 + 2, Y = 16 + 2, Z = 1; };
