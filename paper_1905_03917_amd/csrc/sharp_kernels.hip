@@ -1342,6 +1342,7 @@ __device__ __forceinline__ void b_interact(const VB blk, const Dev& g, int list,
         int i, j, kk;
         if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
         int c = i + g.n[0] * (j + g.n[1] * kk);
+        if (!g.M[c]) continue;   // a cut cell is a band-mask cell; nothing reads these fields off the mask
         double gv[3];
         double gm = iface<D>(g, i, j, kk, gv);
         if (!(gm > 0.0)) {
