@@ -196,8 +196,8 @@ sim_status sim_tuned(sim_t* s, int* bulk_blocks, int* done);
  *               tape; borrowed: they must outlive the batch and must not be
  *               used from another thread during sim_batch_advance
  * The batch splits the simulations into two groups (alternate members)
- * whose passes overlap: one group's work goes to sims[0]'s stream, the
- * other's to a stream the batch creates.  sim_batch_advance first waits for
+ * whose passes overlap, each on a stream the batch creates.
+ * sim_batch_advance first waits for
  * the work already on each simulation's streams and returns with all of the
  * batch's work complete.  Returns SIM_EINVAL on bad arguments, SIM_ENOMEM
  * if the batch's buffers do not fit, SIM_EDEVICE if its stream or events

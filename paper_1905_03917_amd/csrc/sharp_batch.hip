@@ -275,8 +275,10 @@ sim_status sim_batch_create(sim_t* const* sims, int n, sim_batch_t** out)
     }
     sim_batch_impl* B = new sim_batch_impl();
     B->in.resize(n);
-    // groups of alternate members (fewer when n is smaller): the first runs
-    // on sims[0]'s stream, each other one on a stream of the batch
+    // groups of alternate members (fewer when n is smaller), each on a
+    // stream of the batch's own, created one after the other (the runtime
+    // spreads consecutive streams over its hardware queues, so the groups'
+    // passes overlap; a caller's stream may share a queue with them)
     const int ng = n < SHARP_BATCH_GROUPS ? n : SHARP_BATCH_GROUPS;
     B->grp.resize(ng);
     for (int i = 0; i < n; i++) B->grp[i % ng].members.push_back(i);
@@ -286,9 +288,7 @@ sim_status sim_batch_create(sim_t* const* sims, int n, sim_batch_t** out)
         BatchGroup& G = B->grp[g];
         G.slot0 = slot;
         for (size_t m = 0; m < G.members.size(); m++) B->in[G.members[m]].slot = slot++;
-        if (g == 0) {
-            G.stream = sims[0]->s.stream;
-        } else if (hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking) == hipSuccess) {
+        if (hipStreamCreateWithFlags(&G.stream, hipStreamNonBlocking) == hipSuccess) {
             G.own_stream = true;
         } else {
             set_error("batch: stream creation failed");
