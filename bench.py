@@ -568,7 +568,7 @@ def main():
     # the benchmark simulation's streams are released before the batch (with
     # four hardware queues per process, the batch's two streams would share
     # one with them and stop overlapping)
-    bulk_bound = sim.tuned()[0]
+    bulk_bound, _, serial_sched = sim.tuned()
     sim.close()
     bat = None
     if not a.no_batch:
@@ -608,7 +608,8 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "%s %s multi_dt" % (a.case, grid_name), "cells": a.n ** D,
-                   "mode": "multi_dt", "rk": 3, "cfl": 0.6, "bulk_grid_bound": bulk_bound},
+                   "mode": "multi_dt", "rk": 3, "cfl": 0.6, "bulk_grid_bound": bulk_bound,
+                   "schedule": "serial" if serial_sched else "overlapped"},
         "per_fluid": {("%s_cell_updates_per_s" % ("air" if case["gamma"][k] == 1.4 else "water")):
                       st["cell_updates"][k] / el for k in range(2)},
         "steps_per_fluid": st["steps"],

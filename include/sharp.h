@@ -95,9 +95,11 @@ typedef struct {
     double dt_fixed;     /* > 0: single-dt steps of this length (the last one
                             clamped to t_end) instead of the CFL step, so that
                             perturbed runs share one schedule [0] */
-    int autotune;        /* time the first cycles with each candidate grid bound
-                            of the bulk-tile stage kernel and keep the fastest;
-                            results do not depend on the choice [0] */
+    int autotune;        /* time the first cycles with each candidate launch
+                            (bulk-tile stage grid bound 1024-8192 with the
+                            bulk stages overlapped, and the serial schedule)
+                            and keep the fastest; results do not depend on
+                            the choice [0] */
 } sim_opts;
 
 typedef struct {
@@ -176,9 +178,12 @@ sim_status sim_profile_read(sim_t* s, double* ms, int64_t* launches, int64_t* ce
  * (3 ckpt_every states) do not fit. */
 sim_status sim_backward(sim_t* s, const double* g_cons, double* g_prim0, double* g_eos, int on_device);
 
-/* Launch configuration in use: the bulk-tile stage's grid bound (blocks)
- * and whether the autotuner (opts->autotune) has finished choosing it. */
-sim_status sim_tuned(sim_t* s, int* bulk_blocks, int* done);
+/* Launch configuration in use: the bulk-tile stage's grid bound (blocks),
+ * the schedule (serial = 1: every kernel on the simulation's stream; 0: the
+ * bulk-tile stages overlapped on the side streams), and whether the
+ * autotuner (opts->autotune) has finished choosing them.  Any pointer may be
+ * NULL. */
+sim_status sim_tuned(sim_t* s, int* bulk_blocks, int* serial, int* done);
 
 /* ---- batches: many simulations advanced together ----
  * A batch advances independent simulations (any sizes, dimensions and

@@ -77,7 +77,7 @@ def lib():
         L.sim_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int64)]
         L.sim_backward.argtypes = [vp, vp, vp, vp, C.c_int]
-        L.sim_tuned.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.sim_tuned.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.sim_destroy.argtypes = [vp]
         L.sim_destroy.restype = None
         L.sim_strerror.argtypes = [C.c_int]
@@ -227,11 +227,13 @@ class Sim:
         return out, eos.reshape(2, 2)
 
     def tuned(self):
-        """(bulk-stage grid bound in use, whether the autotuner has finished)"""
+        """(bulk-stage grid bound in use, whether the autotuner has finished,
+        whether the serial schedule is in use)"""
         b = C.c_int()
+        sr = C.c_int()
         d = C.c_int()
-        _check(lib().sim_tuned(self.h, C.byref(b), C.byref(d)), "sim_tuned")
-        return b.value, bool(d.value)
+        _check(lib().sim_tuned(self.h, C.byref(b), C.byref(sr), C.byref(d)), "sim_tuned")
+        return b.value, bool(d.value), bool(sr.value)
 
     def profile(self, enable=True):
         _check(lib().sim_profile(self.h, int(enable)), "sim_profile")

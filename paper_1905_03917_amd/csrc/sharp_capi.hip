@@ -367,11 +367,12 @@ sim_status sim_totals(sim_t* h, double* out10)
     return engine_totals(s, out10);
 }
 
-sim_status sim_tuned(sim_t* h, int* bulk_blocks, int* done)
+sim_status sim_tuned(sim_t* h, int* bulk_blocks, int* serial, int* done)
 {
     if (!h) { set_error("null handle"); return SIM_EINVAL; }
     Sim& s = h->s;
     if (bulk_blocks) *bulk_blocks = s.bulk_blocks;
+    if (serial) *serial = (s.o.serial || s.run_serial) ? 1 : 0;
     if (done) *done = s.o.autotune ? (s.tune_cur >= Sim::NTUNE) : 1;
     return SIM_OK;
 }

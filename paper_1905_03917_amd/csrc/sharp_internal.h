@@ -87,11 +87,15 @@ struct Sim {
     double* ap_alt[3] = {nullptr, nullptr, nullptr};
     int max_blocks = 2048; // grid-stride bound for tile-list kernels
     int bulk_blocks = SHARP_BULK_BLOCKS;  // the same bound for the bulk-tile stages
-    // autotuner of bulk_blocks (o.autotune): candidate being timed (-1: the
-    // warm-up cycle), wall seconds per cell-update of each candidate
-    static constexpr int NTUNE = 4;
+    // autotuner of the bulk stage's launch and of the schedule (o.autotune):
+    // candidate being timed (-1: the warm-up cycle), wall seconds per
+    // cell-update of each candidate; candidates 0-3 overlap the bulk stages
+    // on the side streams with grid bounds 1024-8192, candidate 4 issues
+    // every kernel on the simulation's stream (bound 2048)
+    static constexpr int NTUNE = 5;
     int tune_cur = -2;                    // -2: not started, NTUNE: done
-    double tune_cost[NTUNE] = {0, 0, 0, 0};
+    double tune_cost[NTUNE] = {0, 0, 0, 0, 0};
+    bool run_serial = false;              // the schedule in use: no side streams
     double tune_t0 = 0.0;
     long long tune_cells0 = 0;
     bool tune_open = false;

@@ -2868,7 +2868,7 @@ struct Engine {
                double wflux, int cfl = 0, double* tmp = nullptr)
     {
         int bl = k == 0 ? LIST_BULK0 : LIST_BULK1;
-        const bool ov = s.side[k] != nullptr && !s.rec;
+        const bool ov = s.side[k] != nullptr && !s.rec && !s.run_serial;
         hipStream_t bs = ov ? s.side[k] : s.stream;
         // the band stage is enqueued first: on the critical path, it takes the
         // CUs before the bulk stage fills them
@@ -3321,7 +3321,8 @@ struct Engine {
     }
     void tune_step(const sim_stats* st)
     {
-        static const int cand[Sim::NTUNE] = {1024, 2048, 4096, 8192};
+        static const int cand[Sim::NTUNE] = {1024, 2048, 4096, 8192, 2048};
+        static const bool cser[Sim::NTUNE] = {false, false, false, false, true};
         if (s.tune_cur >= Sim::NTUNE) return;
         const long long cells = st->cell_updates[0] + st->cell_updates[1];
         if (s.tune_open) {
@@ -3336,9 +3337,11 @@ struct Engine {
             for (int i = 1; i < Sim::NTUNE; i++)
                 if (s.tune_cost[i] < s.tune_cost[best]) best = i;
             s.bulk_blocks = cand[best];
+            s.run_serial = cser[best];
             return;
         }
         s.bulk_blocks = cand[s.tune_cur < 0 ? 1 : s.tune_cur];
+        s.run_serial = s.tune_cur < 0 ? false : cser[s.tune_cur];
         s.tune_t0 = now_s();
         s.tune_cells0 = cells;
         s.tune_open = true;

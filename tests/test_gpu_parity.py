@@ -214,8 +214,9 @@ def test_overlapped_bulk_stages_equal_serial(name, n, mode, cycles):
 
 
 def test_autotuned_launch_gives_identical_results():
-    """The autotuner changes only the bulk stage's grid bound: states, step
-    counts and boundary ledgers equal those of the default configuration."""
+    """The autotuner changes only the bulk stage's grid bound and the
+    schedule (overlapped or serial): states, step counts and boundary ledgers
+    equal those of the default configuration."""
     import paper_1905_03917_amd as P
     c = WL.shock_bubble_2d(n=512, seed=2)
     a = _gpu(c)
@@ -225,12 +226,30 @@ def test_autotuned_launch_gives_identical_results():
     sb = b.advance(1.0, mode=1, max_cycles=4)
     assert not b.tuned()[1]
     sb2 = b.advance(1.0, mode=1, max_cycles=4)
-    blocks, done = b.tuned()
+    blocks, done, serial = b.tuned()
+    print("autotuned: bound %d, serial %s" % (blocks, serial))
     assert done and blocks in (1024, 2048, 4096, 8192), (blocks, done)
     assert sa2["t"] == sb2["t"] and sa["steps"] == sb["steps"] and sa2["steps"] == sb2["steps"]
     for u, v in zip(a.state(device=False), b.state(device=False)):
         np.testing.assert_array_equal(u, v)
-    assert P.Sim(c).tuned() == (2048, True)
+    assert P.Sim(c).tuned() == (2048, True, False)
+
+
+def test_autotuned_schedule_1d_gives_identical_results():
+    """On a launch-bound 1-D tube the tuner may pick the serial schedule; the
+    results are those of the default configuration either way."""
+    c = WL.tube_1d(n=400, seed=3)
+    a = _gpu(c)
+    b = _gpu(c, autotune=1)
+    for s in (a, b):
+        s.advance(1.0, mode=1, max_cycles=8)
+    sa = a.advance(1.0, mode=1, max_cycles=40)
+    sb = b.advance(1.0, mode=1, max_cycles=40)
+    blocks, done, serial = b.tuned()
+    print("autotuned 1-D: bound %d, serial %s" % (blocks, serial))
+    assert done and sa["steps"] == sb["steps"] and sa["t"] == sb["t"]
+    for u, v in zip(a.state(device=False), b.state(device=False)):
+        np.testing.assert_array_equal(u, v)
 
 
 def test_full_size_shock_bubble_properties():
