@@ -49,6 +49,7 @@ def parse():
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances timing")
+    ap.add_argument("--no-graph", action="store_true", help="skip the captured-steps timing")
     ap.add_argument("--batch-only", action="store_true", help="only the batched-instances timing")
     ap.add_argument("--batch-no-sequential", action="store_true",
                     help="with --batch-only: skip advancing the instances one at a time")
@@ -133,9 +134,9 @@ def reduce_counters(fetch_dir, write_dir):
                source_sha256=source_digest(), sources=KERNEL_SOURCES, counters=out,
                traffic_bytes_per_launch=traffic,
                commands=["timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <FETCH_DIR> -o run "
-                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --no-adjoint --no-batch --copy-probe",
+                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --no-adjoint --no-batch --no-graph --copy-probe",
                          "timeout -s KILL 150 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <WRITE_DIR> -o run "
-                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --no-adjoint --no-batch --copy-probe",
+                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --no-adjoint --no-batch --no-graph --copy-probe",
                          "python bench.py --reduce-counters <FETCH_DIR> <WRITE_DIR>"])
     with open(COUNTERS, "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -180,7 +181,7 @@ def reduce_valu(valu_dir):
                valu_issue_frac=issue_s * 1e9 / avg["ns"],
                command="timeout -s KILL 150 rocprofv3 --pmc " + " ".join(VALU_COUNTERS) + " --output-format csv "
                        "-d <VALU_DIR> -o run -- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 "
-                       "--no-adjoint --no-batch; python bench.py --reduce-valu <VALU_DIR>")
+                       "--no-adjoint --no-batch --no-graph; python bench.py --reduce-valu <VALU_DIR>")
     with open(VALU_RECORD, "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
@@ -449,6 +450,40 @@ def batch_timing(P, WL, cycles_multi=3, steps_single=10, one_at_a_time=True):
     return res
 
 
+def graph_timing(P, WL, steps=200):
+    """Captured single-dt steps (opts graph=1) against the same steps issued
+    launch by launch, at a fixed step (half the first CFL step): a 1-D
+    water-air tube of 400 cells and the 2-D shock-bubble case at 128^2 and
+    256^2.  Reports ms per step of each and checks that both reach the same
+    state bit for bit."""
+    import torch
+    res = []
+    for name, case in (("tube_1d 400", WL.tube_1d(n=400, seed=0)),
+                       ("shock_bubble_2d 128x128", WL.shock_bubble_2d(n=128, seed=0)),
+                       ("shock_bubble_2d 256x256", WL.shock_bubble_2d(n=256, seed=0))):
+        s0 = P.Sim(case)
+        dt = 0.5 * min(s0.advance(1.0, P.SIM_SINGLE_DT, max_cycles=1)["last_dt"])
+        s0.close()
+        row = dict(workload=name, dt=dt, steps=steps)
+        states = []
+        for key, g in (("launches", 0), ("graph", 1)):
+            sim = P.Sim(case, dt_fixed=dt, graph=g)
+            sim.advance(1.0, P.SIM_SINGLE_DT, max_cycles=4)     # warm-up (and the captures)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = sim.advance(1.0, P.SIM_SINGLE_DT, max_cycles=steps)
+            torch.cuda.synchronize()
+            row[key + "_ms_per_step"] = (time.perf_counter() - t0) / st["cycles"] * 1e3
+            if g:
+                row["captures"], row["replays"], _ = sim.graph_info()
+            states.append(sim.state())
+            sim.close()
+        row["speedup"] = row["launches_ms_per_step"] / row["graph_ms_per_step"]
+        row["identical"] = all(torch.equal(x, y) for x, y in zip(states[0], states[1]))
+        res.append(row)
+    return res
+
+
 def cpu_baseline(case_fn, seconds):
     """The CPU oracle (single thread) on the same workload at reduced
     resolution, scaled to cell-updates/s."""
@@ -576,6 +611,12 @@ def main():
         print("bench: batch of %d: multi_dt %.3e cell-updates/s (%.1fx one at a time), single_dt %.3e (%.1fx)"
               % (bat["instances"], bat["multi_dt"]["value"], bat["multi_dt"]["speedup"], bat["single_dt"]["value"],
                  bat["single_dt"]["speedup"]), flush=True)
+    gph = None
+    if not a.no_graph:
+        gph = graph_timing(P, WL)
+        print("bench: captured steps: %s" % ", ".join("%s %.3f -> %.3f ms (%.2fx, identical %s)"
+              % (r["workload"], r["launches_ms_per_step"], r["graph_ms_per_step"], r["speedup"], r["identical"])
+              for r in gph), flush=True)
     ml1 = None
     if not a.no_l1:
         ml1 = matched_l1(P, WL)
@@ -617,6 +658,7 @@ def main():
         "matched_l1": ml1,
         "adjoint": adj,
         "batch": bat,
+        "graph": gph,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

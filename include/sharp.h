@@ -100,6 +100,14 @@ typedef struct {
                             bulk stages overlapped, and the serial schedule)
                             and keep the fastest; results do not depend on
                             the choice [0] */
+    int graph;           /* with dt_fixed > 0: capture a single-dt step of that
+                            length (all stages of both fluids, level set,
+                            mixing) into a HIP graph once per launch
+                            configuration and replay it for the following
+                            steps; results are identical to the launches
+                            issued one by one.  Steps under a tape, a batch or
+                            kernel profiling, and a step shortened to reach
+                            t_end, are issued one by one [0] */
 } sim_opts;
 
 typedef struct {
@@ -184,6 +192,13 @@ sim_status sim_backward(sim_t* s, const double* g_cons, double* g_prim0, double*
  * autotuner (opts->autotune) has finished choosing them.  Any pointer may be
  * NULL. */
 sim_status sim_tuned(sim_t* s, int* bulk_blocks, int* serial, int* done);
+
+/* Captured steps (opts->graph): the number of single-dt steps captured into
+ * HIP graphs and the number replayed from one (the capturing step included),
+ * and the graphs held (at most 4, one per launch configuration: the grid
+ * sizes follow the tile counts rounded up to powers of two).  Any pointer
+ * may be NULL.  The graphs are released by sim_destroy. */
+sim_status sim_graph_info(sim_t* s, long long* captures, long long* replays, int* held);
 
 /* ---- batches: many simulations advanced together ----
  * A batch advances independent simulations (any sizes, dimensions and

@@ -35,7 +35,8 @@ class Opts(C.Structure):
                 ("ext_iters", C.c_int), ("reinit_iters", C.c_int), ("weno_eps", C.c_double),
                 ("force_cycle", C.c_int), ("no_correction", C.c_int),
                 ("serial", C.c_int), ("tape", C.c_int), ("ckpt_every", C.c_int),
-                ("dt_fixed", C.c_double), ("autotune", C.c_int)]
+                ("dt_fixed", C.c_double), ("autotune", C.c_int),
+                ("graph", C.c_int)]
 
 
 class Stats(C.Structure):
@@ -52,7 +53,7 @@ class Stats(C.Structure):
 EXPORTS = ["sim_default_opts", "sim_create", "sim_set_state", "sim_advance", "sim_get_state",
            "sim_totals", "sim_profile", "sim_profile_read", "sim_backward", "sim_tuned", "sim_destroy",
            "sim_strerror", "sim_last_error", "sim_batch_create", "sim_batch_advance", "sim_batch_info",
-           "sim_batch_destroy"]
+           "sim_batch_destroy", "sim_graph_info"]
 
 _lib = None
 
@@ -78,6 +79,7 @@ def lib():
                                        C.POINTER(C.c_int64)]
         L.sim_backward.argtypes = [vp, vp, vp, vp, C.c_int]
         L.sim_tuned.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
+        L.sim_graph_info.argtypes = [vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong), C.POINTER(C.c_int)]
         L.sim_destroy.argtypes = [vp]
         L.sim_destroy.restype = None
         L.sim_strerror.argtypes = [C.c_int]
@@ -90,7 +92,7 @@ def lib():
         L.sim_batch_destroy.restype = None
         for f in ("sim_create", "sim_set_state", "sim_advance", "sim_get_state", "sim_totals",
                   "sim_profile", "sim_profile_read", "sim_backward", "sim_tuned", "sim_batch_create",
-                  "sim_batch_advance", "sim_batch_info"):
+                  "sim_batch_advance", "sim_batch_info", "sim_graph_info"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -234,6 +236,15 @@ class Sim:
         d = C.c_int()
         _check(lib().sim_tuned(self.h, C.byref(b), C.byref(sr), C.byref(d)), "sim_tuned")
         return b.value, bool(d.value), bool(sr.value)
+
+    def graph_info(self):
+        """(single-dt steps captured into HIP graphs, steps replayed from one,
+        graphs held) under opts graph=1"""
+        c = C.c_longlong()
+        r = C.c_longlong()
+        n = C.c_int()
+        _check(lib().sim_graph_info(self.h, C.byref(c), C.byref(r), C.byref(n)), "sim_graph_info")
+        return c.value, r.value, n.value
 
     def profile(self, enable=True):
         _check(lib().sim_profile(self.h, int(enable)), "sim_profile")

@@ -41,6 +41,17 @@ static sim_status dalloc(Sim& s, T** p, size_t n)
 static void release(Sim& s)
 {
     tape_clear(s);
+    for (auto& sg : s.graphs)
+        if (sg.exec) (void)hipGraphExecDestroy(sg.exec);
+    s.graphs.clear();
+    if (s.cap_stream) (void)hipStreamDestroy(s.cap_stream);
+    s.cap_stream = nullptr;
+    if (s.ev_fork) (void)hipEventDestroy(s.ev_fork);
+    s.ev_fork = nullptr;
+    for (int k = 0; k < 2; k++) {
+        if (s.ev_sjoin[k]) (void)hipEventDestroy(s.ev_sjoin[k]);
+        s.ev_sjoin[k] = nullptr;
+    }
     for (void* p : s.dev_allocs) (void)hipFree(p);
     s.dev_allocs.clear();
     for (hipEvent_t e : s.ev_pool) (void)hipEventDestroy(e);
@@ -122,6 +133,7 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     if (!(o.cfl > 0.0) || o.ext_iters < 0 || o.reinit_iters < 0) { set_error("invalid options"); return SIM_EINVAL; }
     if (o.tape && o.ckpt_every < 1) { set_error("ckpt_every must be >= 1"); return SIM_EINVAL; }
     if (!(o.dt_fixed >= 0.0) || !std::isfinite(o.dt_fixed)) { set_error("dt_fixed must be >= 0"); return SIM_EINVAL; }
+    if (o.graph && !(o.dt_fixed > 0.0)) { set_error("graph needs dt_fixed > 0"); return SIM_EINVAL; }
 
     sim_t* h = new sim_t();
     Sim& s = h->s;
@@ -374,6 +386,16 @@ sim_status sim_tuned(sim_t* h, int* bulk_blocks, int* serial, int* done)
     if (bulk_blocks) *bulk_blocks = s.bulk_blocks;
     if (serial) *serial = (s.o.serial || s.run_serial) ? 1 : 0;
     if (done) *done = s.o.autotune ? (s.tune_cur >= Sim::NTUNE) : 1;
+    return SIM_OK;
+}
+
+sim_status sim_graph_info(sim_t* h, long long* captures, long long* replays, int* held)
+{
+    if (!h) { set_error("null handle"); return SIM_EINVAL; }
+    Sim& s = h->s;
+    if (captures) *captures = s.graph_captures;
+    if (replays) *replays = s.graph_replays;
+    if (held) *held = (int)s.graphs.size();
     return SIM_OK;
 }
 

@@ -121,6 +121,21 @@ struct Sim {
     std::vector<double> tape_dt;        // length of each taped step
     std::vector<double*> tape_ckpt;     // state of tape_fluid before steps 0, K, 2K, ... (K = o.ckpt_every)
     double* tape_prim0 = nullptr;       // primitives of tape_fluid given to sim_set_state
+    // single-dt steps of the fixed length o.dt_fixed captured in HIP graphs
+    // (o.graph): one graph per launch configuration, i.e. per value of the
+    // host state the step's launches are made from (`key`); `after` holds
+    // the host state the step leaves, restored after each replay
+    struct StepGraph {
+        std::vector<unsigned char> key, after;
+        hipGraphExec_t exec = nullptr;
+    };
+    static constexpr size_t MAX_GRAPHS = 4;
+    std::vector<StepGraph> graphs;      // oldest first
+    hipStream_t cap_stream = nullptr;   // library-owned stream the captures run on
+    hipEvent_t ev_fork = nullptr;       // side streams join a capture through it
+    hipEvent_t ev_sjoin[2] = {nullptr, nullptr};
+    bool capturing = false;             // grids are sized for a capture (see Engine::grid)
+    long long graph_captures = 0, graph_replays = 0;
 };
 
 void set_error(const char* fmt, ...);

@@ -2609,13 +2609,21 @@ struct Engine {
 
     // grid of a tile-list kernel: one block per listed tile (capped); the
     // kernels loop over the device-side count, so any grid size is correct
+    // (a captured step is replayed while the lists change: its grids are
+    // sized for the next power of two of the count, the graph's key)
     dim3 grid(int list, int per_tile = 1, int cap = 0) const
     {
-        long long c = (long long)s.lcount[list] * per_tile;
+        long long c = (long long)(s.capturing ? pow2_at_least(s.lcount[list]) : s.lcount[list]) * per_tile;
         if (cap <= 0) cap = s.max_blocks;
         if (c < 1) c = 1;
         if (c > cap) c = cap;
         return dim3((unsigned)c);
+    }
+    static int pow2_at_least(int n)
+    {
+        int p = 1;
+        while (p < n && p < (1 << 30)) p <<= 1;
+        return p;
     }
     dim3 wg() const { return dim3(SHARP_WG); }
 
@@ -2942,6 +2950,15 @@ struct Engine {
                     (int)gr.x, SHARP_WG3, g, list, k, in, self2, base, out, a, dt, wflux, s.wcur, cfl, tmp);
             return;
         }
+        if (!e0 && !e1) {
+            if constexpr (D <= 2)
+                k_stage_lds<D, BAND><<<gr, dim3(StageWG<D>::N), 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux,
+                                                                        s.wcur, cfl, tmp);
+            else
+                k_stage_lds3<BAND><<<gr, dim3(SHARP_WG3), 0, st>>>(g, list, k, in, self2, base, out, a, dt, wflux, s.wcur,
+                                                                  cfl, tmp);
+            return;
+        }
         if constexpr (D <= 2)
             hipExtLaunchKernelGGL(k_stage_lds<D, BAND>, gr, dim3(StageWG<D>::N), 0, st, e0, e1, 0, g, list, k, in,
                                   self2, base, out, a, dt, wflux, s.wcur, cfl, tmp);
@@ -3079,6 +3096,143 @@ struct Engine {
         }
         join();
         s.t += dt;
+    }
+
+    // ---- captured single-dt steps (o.graph) ----
+    // A step of the fixed length dt_fixed issues the same launches whenever
+    // the host state they are made from is the same: the device view (its
+    // geometry buffers alternate), the Jacobi buffer parities, the grid sizes
+    // and the schedule.  Such a step is captured once into a HIP graph (the
+    // simulation stream's kernels and the side streams' bulk stages with the
+    // events that order them) and replayed; the kernels read every count from
+    // the device, so a replay gives the results of the launches it recorded.
+    bool graph_step_ok(double d) const
+    {
+        return s.o.graph && s.o.dt_fixed > 0.0 && d == s.o.dt_fixed && !s.rec && !s.prof && !s.o.tape &&
+               (!s.o.autotune || s.tune_cur >= Sim::NTUNE);
+    }
+    static void put(std::vector<unsigned char>& v, const void* p, size_t n)
+    {
+        const unsigned char* b = static_cast<const unsigned char*>(p);
+        v.insert(v.end(), b, b + n);
+    }
+    // the host state a step changes
+    std::vector<unsigned char> step_state() const
+    {
+        std::vector<unsigned char> v;
+        put(v, &g, sizeof g);
+        put(v, &s.wcur, sizeof s.wcur);
+        put(v, &s.vcur, sizeof s.vcur);
+        put(v, &s.alpha_alt, sizeof s.alpha_alt);
+        put(v, s.ap_alt, sizeof s.ap_alt);
+        return v;
+    }
+    void set_step_state(const std::vector<unsigned char>& v)
+    {
+        size_t o = 0;
+        auto get = [&](void* p, size_t n) {
+            std::memcpy(p, v.data() + o, n);
+            o += n;
+        };
+        get(&g, sizeof g);
+        get(&s.wcur, sizeof s.wcur);
+        get(&s.vcur, sizeof s.vcur);
+        get(&s.alpha_alt, sizeof s.alpha_alt);
+        get(s.ap_alt, sizeof s.ap_alt);
+    }
+    // ... and, with what else sizes or orders the launches, the graph's key
+    std::vector<unsigned char> launch_key(double d) const
+    {
+        std::vector<unsigned char> v = step_state();
+        put(v, &s.bulk_blocks, sizeof s.bulk_blocks);
+        put(v, &s.max_blocks, sizeof s.max_blocks);
+        put(v, &s.run_serial, sizeof s.run_serial);
+        for (int l = 0; l < NLISTS; l++) {
+            int c = pow2_at_least(s.lcount[l]);
+            put(v, &c, sizeof c);
+        }
+        put(v, &d, sizeof d);
+        return v;
+    }
+    sim_status capture_step(double d, std::vector<unsigned char>&& key)
+    {
+        if (!s.cap_stream) {
+            SHARP_HIP(hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking));
+            SHARP_HIP(hipEventCreateWithFlags(&s.ev_fork, hipEventDisableTiming));
+            for (int k = 0; k < 2; k++) SHARP_HIP(hipEventCreateWithFlags(&s.ev_sjoin[k], hipEventDisableTiming));
+        }
+        if (s.graphs.size() >= Sim::MAX_GRAPHS) {
+            (void)hipGraphExecDestroy(s.graphs.front().exec);
+            s.graphs.erase(s.graphs.begin());
+        }
+        // earlier side-stream work is complete (the step's readback waited
+        // for the stream after joining it), so the capture waits for none
+        join();
+        for (int k = 0; k < 2; k++) s.band_rec[k] = false;
+        const std::vector<unsigned char> before = step_state();
+        const bool fork = !s.run_serial;
+        hipStream_t user = s.stream;
+        const double t0 = s.t;
+        SHARP_HIP(hipStreamBeginCapture(s.cap_stream, hipStreamCaptureModeThreadLocal));
+        s.stream = s.cap_stream;
+        s.capturing = true;
+        hipError_t e = hipEventRecord(s.ev_fork, s.cap_stream);
+        for (int k = 0; k < 2 && e == hipSuccess; k++)
+            if (fork && s.side[k]) e = hipStreamWaitEvent(s.side[k], s.ev_fork, 0);
+        if (e == hipSuccess) {
+            step_single(d);
+            // every side stream rejoins the capture stream
+            for (int k = 0; k < 2 && e == hipSuccess; k++)
+                if (fork && s.side[k]) {
+                    e = hipEventRecord(s.ev_sjoin[k], s.side[k]);
+                    if (e == hipSuccess) e = hipStreamWaitEvent(s.cap_stream, s.ev_sjoin[k], 0);
+                }
+        }
+        hipGraph_t graph = nullptr;
+        hipError_t e2 = hipStreamEndCapture(s.cap_stream, &graph);
+        s.stream = user;
+        s.capturing = false;
+        s.t = t0;
+        for (int k = 0; k < 2; k++) {
+            s.band_rec[k] = false;
+            s.bulk_pending[k] = false;
+        }
+        hipGraphExec_t exec = nullptr;
+        if (e == hipSuccess && e2 == hipSuccess) e = hipGetLastError();
+        if (e == hipSuccess && e2 == hipSuccess) e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        if (graph) (void)hipGraphDestroy(graph);
+        if (e != hipSuccess || e2 != hipSuccess) {
+            set_step_state(before);
+            set_error("capture of a single-dt step failed: %s",
+                      hipGetErrorString(e != hipSuccess ? e : e2));
+            return SIM_EDEVICE;
+        }
+        Sim::StepGraph sg;
+        sg.key = std::move(key);
+        sg.after = step_state();
+        sg.exec = exec;
+        set_step_state(before);
+        s.graphs.push_back(std::move(sg));
+        s.graph_captures++;
+        return SIM_OK;
+    }
+    sim_status step_graph(double d)
+    {
+        std::vector<unsigned char> key = launch_key(d);
+        int found = -1;
+        for (size_t i = 0; i < s.graphs.size(); i++)
+            if (s.graphs[i].key == key) found = (int)i;
+        if (found < 0) {
+            sim_status rc = capture_step(d, std::move(key));
+            if (rc != SIM_OK) return rc;
+            found = (int)s.graphs.size() - 1;
+        }
+        join();
+        SHARP_HIP(hipGraphLaunch(s.graphs[found].exec, s.stream));
+        set_step_state(s.graphs[found].after);
+        s.t += d;
+        s.graph_replays++;
+        return SIM_OK;
     }
 
     // slow fluid's intermediate state, Eq. (interpolation), mixed with the
@@ -3282,7 +3436,12 @@ struct Engine {
                     rc = tape_step(s, d);
                     if (rc != SIM_OK) break;
                 }
-                step_single(d);
+                if (graph_step_ok(d)) {
+                    rc = step_graph(d);
+                    if (rc != SIM_OK) break;
+                } else {
+                    step_single(d);
+                }
                 st->cycles++;
                 for (int k = 0; k < 2; k++) { st->steps[k]++; st->cell_updates[k] += cnt[k]; }
                 st->last_n = 1.0;

@@ -1,0 +1,94 @@
+"""Captured steps (opts graph=1): single-dt steps of a fixed length replayed
+from HIP graphs must give the states of the same steps issued launch by
+launch, bit for bit, after every call, with the program's own device work
+and synchronisations between the replays."""
+import numpy as np
+import pytest
+
+from paper_1905_03917_amd import workloads as WL
+
+pytestmark = pytest.mark.gpu
+
+
+def _mods():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    import paper_1905_03917_amd as P
+    return torch, P
+
+
+def _first_dt(P, case):
+    s = P.Sim(case)
+    st = s.advance(1.0, P.SIM_SINGLE_DT, max_cycles=1)
+    s.close()
+    return min(st["last_dt"])
+
+
+CASES = [("tube_1d", lambda: WL.tube_1d(n=600, seed=4)),
+         ("shock_bubble_2d", lambda: WL.shock_bubble_2d(n=80, seed=5)),
+         ("shock_droplet_3d", lambda: WL.shock_droplet_3d(n=24, seed=6))]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+def test_graph_steps_match_launches_one_by_one(name, make):
+    torch, P = _mods()
+    case = make()
+    dt = 0.5 * _first_dt(P, case)
+    plain = P.Sim(case, dt_fixed=dt)
+    graph = P.Sim(case, dt_fixed=dt, graph=1)
+    junk = torch.zeros(1 << 20, dtype=torch.float64, device="cuda")
+    t = 0.0
+    steps = 0
+    print("case", name, "dt", dt, flush=True)
+    for call, m in enumerate([1, 1, 3, 6, 1, 9, 2]):
+        t += m * dt
+        sa = plain.advance(t, P.SIM_SINGLE_DT)
+        sb = graph.advance(t, P.SIM_SINGLE_DT)
+        steps += sa["cycles"]
+        for key in ("cycles", "steps", "cell_updates", "t"):
+            assert np.array_equal(np.asarray(sa[key]), np.asarray(sb[key])), (name, call, key, sa[key], sb[key])
+        pa, ca, aa = plain.state()
+        pb, cb, ab = graph.state()
+        assert torch.equal(pa, pb) and torch.equal(ca, cb) and torch.equal(aa, ab), (name, call)
+        # the program's own device work between replays
+        junk.add_(ca.sum())
+        torch.cuda.synchronize()
+    captures, replays, held = graph.graph_info()
+    print("captures", captures, "replays", replays, "held", held, "steps", steps, flush=True)
+    assert 1 <= captures <= replays and 1 <= held <= 4
+    # the last step of a call may be shortened to reach t_end (rounding of
+    # the summed steps): it runs launch by launch
+    assert replays >= steps - 7, (replays, steps)
+    assert plain.graph_info() == (0, 0, 0)
+    plain.close()
+    graph.close()
+
+
+def test_graph_steps_between_accelerated_cycles():
+    """accelerated cycles (never captured) and captured single-dt steps in
+    turn on one simulation: the host state a replay leaves must be the one
+    the launches would have left"""
+    torch, P = _mods()
+    case = WL.shock_bubble_2d(n=64, seed=7)
+    dt = 0.4 * _first_dt(P, case)
+    plain = P.Sim(case, dt_fixed=dt)
+    graph = P.Sim(case, dt_fixed=dt, graph=1)
+    for r in range(3):
+        ta = plain.advance(1e9, P.SIM_MULTI_DT, max_cycles=1)["t"]
+        tb = graph.advance(1e9, P.SIM_MULTI_DT, max_cycles=1)["t"]
+        assert ta == tb, (r, ta, tb)
+        t = ta + 5 * dt
+        plain.advance(t, P.SIM_SINGLE_DT)
+        graph.advance(t, P.SIM_SINGLE_DT)
+        pa, ca, aa = plain.state()
+        pb, cb, ab = graph.state()
+        assert torch.equal(pa, pb) and torch.equal(ca, cb) and torch.equal(aa, ab), r
+    assert graph.graph_info()[1] >= 10
+    plain.close()
+    graph.close()
+
+
+def test_graph_needs_a_fixed_step():
+    torch, P = _mods()
+    with pytest.raises(RuntimeError, match="dt_fixed"):
+        P.Sim(WL.tube_1d(n=300, seed=1), graph=1)
