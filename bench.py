@@ -452,15 +452,16 @@ def batch_timing(P, WL, cycles_multi=3, steps_single=10, one_at_a_time=True):
 
 def graph_timing(P, WL, steps=200):
     """Captured single-dt steps (opts graph=1) against the same steps issued
-    launch by launch, at a fixed step (half the first CFL step): a 1-D
-    water-air tube of 400 cells and the 2-D shock-bubble case at 128^2 and
-    256^2.  Reports ms per step of each and checks that both reach the same
+    launch by launch (default schedule), at a fixed step (half the first
+    CFL step): 1-D water-air tubes of 400 and 4000 cells and the 2-D
+    shock-bubble case at 128^2 and 512^2.  Reports ms per step of each and checks that both reach the same
     state bit for bit."""
     import torch
     res = []
     for name, case in (("tube_1d 400", WL.tube_1d(n=400, seed=0)),
+                       ("tube_1d 4000", WL.tube_1d(n=4000, seed=0)),
                        ("shock_bubble_2d 128x128", WL.shock_bubble_2d(n=128, seed=0)),
-                       ("shock_bubble_2d 256x256", WL.shock_bubble_2d(n=256, seed=0))):
+                       ("shock_bubble_2d 512x512", WL.shock_bubble_2d(n=512, seed=0))):
         s0 = P.Sim(case)
         dt = 0.5 * min(s0.advance(1.0, P.SIM_SINGLE_DT, max_cycles=1)["last_dt"])
         s0.close()

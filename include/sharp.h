@@ -100,14 +100,21 @@ typedef struct {
                             bulk stages overlapped, and the serial schedule)
                             and keep the fastest; results do not depend on
                             the choice [0] */
-    int graph;           /* with dt_fixed > 0: capture a single-dt step of that
-                            length (all stages of both fluids, level set,
-                            mixing) into a HIP graph once per launch
-                            configuration and replay it for the following
-                            steps; results are identical to the launches
-                            issued one by one.  Steps under a tape, a batch or
-                            kernel profiling, and a step shortened to reach
-                            t_end, are issued one by one [0] */
+    int graph;           /* with dt_fixed > 0: capture a whole single-dt step
+                            of that length (band tiles, interaction and CFL
+                            reductions, then all stages of both fluids, level
+                            set, mixing; every kernel in one chain, with no
+                            side streams) into a HIP graph once per launch
+                            configuration, and enqueue the whole steps of a
+                            sim_advance call as replays without waiting for
+                            any: the active-cell counts are summed on the
+                            device and read back, with the error flags, once
+                            after them (an error is reported at the end of
+                            that run of steps).  Results are identical to the
+                            launches issued one by one.  Steps under a tape, a
+                            batch, kernel profiling or an unfinished autotuner,
+                            and a step shortened to reach t_end, are issued
+                            one by one [0] */
 } sim_opts;
 
 typedef struct {

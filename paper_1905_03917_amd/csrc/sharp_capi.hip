@@ -46,12 +46,6 @@ static void release(Sim& s)
     s.graphs.clear();
     if (s.cap_stream) (void)hipStreamDestroy(s.cap_stream);
     s.cap_stream = nullptr;
-    if (s.ev_fork) (void)hipEventDestroy(s.ev_fork);
-    s.ev_fork = nullptr;
-    for (int k = 0; k < 2; k++) {
-        if (s.ev_sjoin[k]) (void)hipEventDestroy(s.ev_sjoin[k]);
-        s.ev_sjoin[k] = nullptr;
-    }
     for (void* p : s.dev_allocs) (void)hipFree(p);
     s.dev_allocs.clear();
     for (hipEvent_t e : s.ev_pool) (void)hipEventDestroy(e);

@@ -132,8 +132,6 @@ struct Sim {
     static constexpr size_t MAX_GRAPHS = 4;
     std::vector<StepGraph> graphs;      // oldest first
     hipStream_t cap_stream = nullptr;   // library-owned stream the captures run on
-    hipEvent_t ev_fork = nullptr;       // side streams join a capture through it
-    hipEvent_t ev_sjoin[2] = {nullptr, nullptr};
     bool capturing = false;             // grids are sized for a capture (see Engine::grid)
     long long graph_captures = 0, graph_replays = 0;
 };

@@ -1493,6 +1493,20 @@ __global__ void k_zero_red(Dev g)
 {
     b_zero_red(VB::grid(), g);
 }
+// accumulators of a run of captured steps (reduction words 5-7): each
+// fluid's active-cell count summed over the steps, and the step count
+__device__ __forceinline__ void b_acc(const VB blk, const Dev& g, int add)
+{
+    if (threadIdx.x == 0) {
+        g.red[5] = add ? g.red[5] + g.red[2] : 0ull;
+        g.red[6] = add ? g.red[6] + g.red[3] : 0ull;
+        g.red[7] = add ? g.red[7] + 1ull : 0ull;
+    }
+}
+__global__ void k_acc(Dev g, int add)
+{
+    b_acc(VB::grid(), g, add);
+}
 
 // ---------------------------------------------------------------------------
 // one Shu-Osher stage of fluid k (the stage kernels below):
@@ -3099,16 +3113,21 @@ struct Engine {
     }
 
     // ---- captured single-dt steps (o.graph) ----
-    // A step of the fixed length dt_fixed issues the same launches whenever
-    // the host state they are made from is the same: the device view (its
-    // geometry buffers alternate), the Jacobi buffer parities, the grid sizes
-    // and the schedule.  Such a step is captured once into a HIP graph (the
-    // simulation stream's kernels and the side streams' bulk stages with the
-    // events that order them) and replayed; the kernels read every count from
-    // the device, so a replay gives the results of the launches it recorded.
-    bool graph_step_ok(double d) const
+    // A step of the fixed length dt_fixed (its start: band tiles,
+    // interaction, CFL reductions; then the stages) issues the same launches
+    // whenever the host state they are made from is the same: the device
+    // view (its geometry buffers alternate), the Jacobi buffer parities and
+    // the grid sizes.  Such a step is captured once into a HIP graph and
+    // replayed; the kernels read every count from the device, so a replay
+    // gives the results of the launches it recorded.  The capture issues
+    // every kernel on the one stream (a graph with the bulk stages on side
+    // streams and the events between them ran slower than the launches it
+    // replaces).  A run of whole steps is enqueued without waiting for any of
+    // them: the active-cell counts are summed on the device and read back,
+    // with the error flags, once at the end of the run.
+    bool graph_run_ok() const
     {
-        return s.o.graph && s.o.dt_fixed > 0.0 && d == s.o.dt_fixed && !s.rec && !s.prof && !s.o.tape &&
+        return s.o.graph && s.o.dt_fixed > 0.0 && !s.rec && !s.prof && !s.o.tape &&
                (!s.o.autotune || s.tune_cur >= Sim::NTUNE);
     }
     static void put(std::vector<unsigned char>& v, const void* p, size_t n)
@@ -3146,7 +3165,6 @@ struct Engine {
         std::vector<unsigned char> v = step_state();
         put(v, &s.bulk_blocks, sizeof s.bulk_blocks);
         put(v, &s.max_blocks, sizeof s.max_blocks);
-        put(v, &s.run_serial, sizeof s.run_serial);
         for (int l = 0; l < NLISTS; l++) {
             int c = pow2_at_least(s.lcount[l]);
             put(v, &c, sizeof c);
@@ -3154,44 +3172,44 @@ struct Engine {
         put(v, &d, sizeof d);
         return v;
     }
+    // the launches of one whole step, as the uncaptured path issues them
+    void graph_step_body(double d)
+    {
+        mask(LIST_CAND, 0);
+        tiles();
+        interaction(g.X[0], g.X[1], g.phiP, 0.0, 0);
+        go<b_zero_red, 64>(k_zero_red, 1, 64, s.stream, g);
+        cfl_launch(0, g.X[0]);
+        cfl_launch(1, g.X[1]);
+        go<b_acc, 64>(k_acc, 1, 64, s.stream, g, 1);
+        step_single(d);
+    }
     sim_status capture_step(double d, std::vector<unsigned char>&& key)
     {
-        if (!s.cap_stream) {
-            SHARP_HIP(hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking));
-            SHARP_HIP(hipEventCreateWithFlags(&s.ev_fork, hipEventDisableTiming));
-            for (int k = 0; k < 2; k++) SHARP_HIP(hipEventCreateWithFlags(&s.ev_sjoin[k], hipEventDisableTiming));
-        }
+        if (!s.cap_stream) SHARP_HIP(hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking));
         if (s.graphs.size() >= Sim::MAX_GRAPHS) {
             (void)hipGraphExecDestroy(s.graphs.front().exec);
             s.graphs.erase(s.graphs.begin());
         }
-        // earlier side-stream work is complete (the step's readback waited
-        // for the stream after joining it), so the capture waits for none
+        // what the uncaptured path put on the side streams was joined into
+        // the stream before the graphs that follow it
         join();
         for (int k = 0; k < 2; k++) s.band_rec[k] = false;
         const std::vector<unsigned char> before = step_state();
-        const bool fork = !s.run_serial;
         hipStream_t user = s.stream;
         const double t0 = s.t;
+        const bool serial = s.run_serial;
         SHARP_HIP(hipStreamBeginCapture(s.cap_stream, hipStreamCaptureModeThreadLocal));
         s.stream = s.cap_stream;
         s.capturing = true;
-        hipError_t e = hipEventRecord(s.ev_fork, s.cap_stream);
-        for (int k = 0; k < 2 && e == hipSuccess; k++)
-            if (fork && s.side[k]) e = hipStreamWaitEvent(s.side[k], s.ev_fork, 0);
-        if (e == hipSuccess) {
-            step_single(d);
-            // every side stream rejoins the capture stream
-            for (int k = 0; k < 2 && e == hipSuccess; k++)
-                if (fork && s.side[k]) {
-                    e = hipEventRecord(s.ev_sjoin[k], s.side[k]);
-                    if (e == hipSuccess) e = hipStreamWaitEvent(s.cap_stream, s.ev_sjoin[k], 0);
-                }
-        }
+        s.run_serial = true;
+        graph_step_body(d);
         hipGraph_t graph = nullptr;
+        hipError_t e = hipSuccess;
         hipError_t e2 = hipStreamEndCapture(s.cap_stream, &graph);
         s.stream = user;
         s.capturing = false;
+        s.run_serial = serial;
         s.t = t0;
         for (int k = 0; k < 2; k++) {
             s.band_rec[k] = false;
@@ -3203,8 +3221,7 @@ struct Engine {
         if (graph) (void)hipGraphDestroy(graph);
         if (e != hipSuccess || e2 != hipSuccess) {
             set_step_state(before);
-            set_error("capture of a single-dt step failed: %s",
-                      hipGetErrorString(e != hipSuccess ? e : e2));
+            set_error("capture of a single-dt step failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
             return SIM_EDEVICE;
         }
         Sim::StepGraph sg;
@@ -3216,22 +3233,49 @@ struct Engine {
         s.graph_captures++;
         return SIM_OK;
     }
-    sim_status step_graph(double d)
+    // K whole steps of length dt_fixed from graphs, then one readback
+    sim_status graph_steps(long long K, double t_end, sim_stats* st)
     {
-        std::vector<unsigned char> key = launch_key(d);
-        int found = -1;
-        for (size_t i = 0; i < s.graphs.size(); i++)
-            if (s.graphs[i].key == key) found = (int)i;
-        if (found < 0) {
-            sim_status rc = capture_step(d, std::move(key));
-            if (rc != SIM_OK) return rc;
-            found = (int)s.graphs.size() - 1;
-        }
+        const double d = s.o.dt_fixed;
         join();
-        SHARP_HIP(hipGraphLaunch(s.graphs[found].exec, s.stream));
-        set_step_state(s.graphs[found].after);
-        s.t += d;
-        s.graph_replays++;
+        go<b_acc, 64>(k_acc, 1, 64, s.stream, g, 0);
+        for (long long i = 0; i < K; i++) {
+            std::vector<unsigned char> key = launch_key(d);
+            int found = -1;
+            for (size_t j = 0; j < s.graphs.size(); j++)
+                if (s.graphs[j].key == key) found = (int)j;
+            if (found < 0) {
+                sim_status rc = capture_step(d, std::move(key));
+                if (rc != SIM_OK) return rc;
+                found = (int)s.graphs.size() - 1;
+            }
+            SHARP_HIP(hipGraphLaunch(s.graphs[found].exec, s.stream));
+            set_step_state(s.graphs[found].after);
+            s.t += d;
+            if (t_end - s.t <= 1e-14 * t_end) s.t = t_end;
+            s.graph_replays++;
+        }
+        sim_status rc = rb_begin(RED_WORDS, false);
+        if (rc == SIM_OK) rc = rb_wait(false);
+        if (rc == SIM_OK) rc = check_flags();
+        if (rc != SIM_OK) return rc;
+        if ((long long)s.h_red[7] != K) {
+            set_error("captured steps: %lld of %lld ran", (long long)s.h_red[7], K);
+            return SIM_EDEVICE;
+        }
+        for (int k = 0; k < 2; k++) {
+            double m = __longlong_as_double_host(s.h_red[k]);
+            long long cnt = (long long)s.h_red[2 + k];
+            st->last_dt[k] = (cnt > 0 && m > 0.0) ? s.o.cfl / m : INFINITY;
+            st->steps[k] += K;
+            st->cell_updates[k] += (long long)s.h_red[5 + k];
+        }
+        st->cycles += K;
+        st->last_n = 1.0;
+        if (!(fmin(st->last_dt[0], st->last_dt[1]) > 0.0)) {
+            set_error("invalid time step");
+            return SIM_ENONPHYS;
+        }
         return SIM_OK;
     }
 
@@ -3421,6 +3465,22 @@ struct Engine {
         long long done = 0;
         sim_status rc = SIM_OK;
         while (s.t < t_end && (max_cycles <= 0 || done < max_cycles)) {
+            if (mode == SIM_SINGLE_DT && graph_run_ok()) {
+                // the whole steps of length dt_fixed before t_end, from graphs
+                long long K = 0;
+                double t = s.t;
+                while ((max_cycles <= 0 || done + K < max_cycles) && t < t_end && !(s.o.dt_fixed > t_end - t)) {
+                    t += s.o.dt_fixed;
+                    if (t_end - t <= 1e-14 * t_end) t = t_end;
+                    K++;
+                }
+                if (K > 0) {
+                    rc = graph_steps(K, t_end, st);
+                    if (rc != SIM_OK) break;
+                    done += K;
+                    continue;
+                }
+            }
             double dt[2];
             long long cnt[2];
             rc = prepare(true, dt, cnt);
@@ -3436,12 +3496,7 @@ struct Engine {
                     rc = tape_step(s, d);
                     if (rc != SIM_OK) break;
                 }
-                if (graph_step_ok(d)) {
-                    rc = step_graph(d);
-                    if (rc != SIM_OK) break;
-                } else {
-                    step_single(d);
-                }
+                step_single(d);
                 st->cycles++;
                 for (int k = 0; k < 2; k++) { st->steps[k]++; st->cell_updates[k] += cnt[k]; }
                 st->last_n = 1.0;

@@ -45,7 +45,7 @@ def test_graph_steps_match_launches_one_by_one(name, make):
         sa = plain.advance(t, P.SIM_SINGLE_DT)
         sb = graph.advance(t, P.SIM_SINGLE_DT)
         steps += sa["cycles"]
-        for key in ("cycles", "steps", "cell_updates", "t"):
+        for key in ("cycles", "steps", "cell_updates", "t", "last_dt"):
             assert np.array_equal(np.asarray(sa[key]), np.asarray(sb[key])), (name, call, key, sa[key], sb[key])
         pa, ca, aa = plain.state()
         pb, cb, ab = graph.state()
