@@ -681,10 +681,9 @@ __global__ void __launch_bounds__(SHARP_WG) k_mixinterp_lds(Dev g, int list, Mix
     b_mixinterp_lds<D>(VB::grid(), g, list, P, cur);
 }
 
-// Several mixed copies of the same tiles in one launch, one (tile, part)
-// pair per block (the parts read no buffer another part writes), and
-// optionally phi_dst = phi_src on the band-mask cells, by the part-0 blocks
-// (the mixing reads the level set through phi_src).
+// Several mixed copies of the same tiles in one launch (the parts read no
+// buffer another part writes), and optionally phi_dst = phi_src on the
+// band-mask cells (the mixing reads the level set through phi_src).
 template <int D>
 __device__ __forceinline__ void b_mix_parts(const VB blk, const Dev& g, int list, MixPart A, MixPart B, int nparts,
                                             const double* cur, const double* phi_src, double* phi_dst)
@@ -696,12 +695,11 @@ __device__ __forceinline__ void b_mix_parts(const VB blk, const Dev& g, int list
     __shared__ int sTgt[NS * RN];
     __shared__ int sCell[RN];
     const int* L = list_ptr(g, list);
-    const int np = nparts > 1 ? 2 : 1;
-    for (int wi = blk.b; wi < np * list_count(g, list); wi += blk.n) {
-        const int t = L[wi / np];
-        const int part = wi % np;
-        mix_tile<D>(g, t, part ? B : A, cur, sBeta, sTgt, sCell);
-        if (phi_dst && part == 0) {
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
+        int t = L[ti];
+        mix_tile<D>(g, t, A, cur, sBeta, sTgt, sCell);
+        if (nparts > 1) mix_tile<D>(g, t, B, cur, sBeta, sTgt, sCell);
+        if (phi_dst) {
             int ox, oy, oz;
             tile_origin<D>(g, t, ox, oy, oz);
             int tid = threadIdx.x;
@@ -2865,7 +2863,7 @@ struct Engine {
     // for the next stage) and the level-set commit
     void mix_fused(const MixPart& A, const MixPart* B, const double* cur, const double* commit)
     {
-        go<b_mix_parts<D>, SHARP_WG>(k_mix_parts<D>, grid(LIST_INNER, B ? 2 : 1), wg(), s.stream, g, LIST_INNER, A, B ? *B : A,
+        go<b_mix_parts<D>, SHARP_WG>(k_mix_parts<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, A, B ? *B : A,
                                      B ? 2 : 1, cur, commit,
                                                                 commit ? g.phiP : nullptr);
     }
