@@ -92,3 +92,21 @@ def test_graph_needs_a_fixed_step():
     torch, P = _mods()
     with pytest.raises(RuntimeError, match="dt_fixed"):
         P.Sim(WL.tube_1d(n=300, seed=1), graph=1)
+
+
+def test_graph_run_reports_a_nonphysical_state():
+    """a run of captured steps reads the error flags once, after its last
+    step: a non-physical state is reported by that call, as by the launches
+    issued one by one"""
+    torch, P = _mods()
+    case = WL.tube_1d(n=200, seed=7)
+    dt = 0.5 * _first_dt(P, case)
+    prim = case["prim"].copy()
+    prim[0, 0, 10] = -1.0                     # negative density in a water cell
+    bad = dict(case, prim=prim)
+    for g in (0, 1):
+        s = P.Sim(bad, dt_fixed=dt, graph=g)
+        with pytest.raises(P.SimError) as e:
+            s.advance(4 * dt, P.SIM_SINGLE_DT)
+        assert e.value.status == -4, (g, str(e.value))
+        s.close()
