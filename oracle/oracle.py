@@ -55,51 +55,69 @@ _lib = None
 _dp = np.ctypeslib.ndpointer(dtype=np.float64, flags="C_CONTIGUOUS")
 
 
+def build_at(src, out, defines=()):
+    """Compile an oracle source file to a shared library at `out` (the tests
+    also build deliberately broken copies of the oracle this way, to show
+    that a pin catches the mistake)."""
+    subprocess.check_call(["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off"]
+                          + ["-D" + d for d in defines] + ["-o", out, src, "-lm"])
+    return out
+
+
+def load(path):
+    """ctypes handle of an oracle library with every entry point typed."""
+    L = C.CDLL(path)
+    L.or_default_params.argtypes = [C.POINTER(Params)]
+    L.or_create.argtypes = [C.POINTER(Params)]
+    L.or_create.restype = C.c_void_p
+    L.or_destroy.argtypes = [C.c_void_p]
+    L.or_set_state.argtypes = [C.c_void_p, _dp, _dp]
+    L.or_advance.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_long, C.POINTER(Stats)]
+    L.or_get_state.argtypes = [C.c_void_p, _dp, _dp, _dp]
+    L.or_totals.argtypes = [C.c_void_p, _dp]
+    L.or_last_error.restype = C.c_char_p
+    L.or_prim2cons.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp]
+    L.or_cons2prim.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp]
+    L.or_weno5.argtypes = [C.c_double] * 6
+    L.or_weno5.restype = C.c_double
+    L.or_riemann.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double, _dp]
+    L.or_riemann_sample.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
+                                    C.c_double, _dp]
+    L.or_clip_area.argtypes = [_dp]
+    L.or_clip_area.restype = C.c_double
+    L.or_face_flux_1d.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp]
+    L.or_geometry.argtypes = [C.c_void_p, _dp, _dp]
+    L.or_face_count.argtypes = [C.c_void_p]
+    L.or_face_count.restype = C.c_long
+    L.or_plan_cycle.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double,
+                                C.POINTER(C.c_double), C.POINTER(C.c_int)]
+    L.or_substep.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
+                             C.POINTER(C.c_int), C.POINTER(C.c_int)]
+    L.or_substep.restype = C.c_double
+    L.or_ls_transport.argtypes = [C.POINTER(Params), _dp, _dp, C.c_double, C.c_int]
+    L.or_reinit_run.argtypes = [C.POINTER(Params), _dp]
+    L.or_extend_v_run.argtypes = [C.POINTER(Params), _dp, _dp]
+    L.or_extend_w_run.argtypes = [C.POINTER(Params), _dp, _dp]
+    return L
+
+
 def lib():
     global _lib
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             build()
-        L = C.CDLL(LIB_PATH)
-        L.or_default_params.argtypes = [C.POINTER(Params)]
-        L.or_create.argtypes = [C.POINTER(Params)]
-        L.or_create.restype = C.c_void_p
-        L.or_destroy.argtypes = [C.c_void_p]
-        L.or_set_state.argtypes = [C.c_void_p, _dp, _dp]
-        L.or_advance.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_long, C.POINTER(Stats)]
-        L.or_get_state.argtypes = [C.c_void_p, _dp, _dp, _dp]
-        L.or_totals.argtypes = [C.c_void_p, _dp]
-        L.or_last_error.restype = C.c_char_p
-        L.or_prim2cons.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp]
-        L.or_cons2prim.argtypes = [C.c_int, C.c_double, C.c_double, _dp, _dp]
-        L.or_weno5.argtypes = [C.c_double] * 6
-        L.or_weno5.restype = C.c_double
-        L.or_riemann.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double, _dp]
-        L.or_riemann_sample.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
-                                        C.c_double, _dp]
-        L.or_clip_area.argtypes = [_dp]
-        L.or_clip_area.restype = C.c_double
-        L.or_face_flux_1d.argtypes = [_dp, C.c_double, C.c_double, C.c_double, _dp]
-        L.or_geometry.argtypes = [C.c_void_p, _dp, _dp]
-        L.or_face_count.argtypes = [C.c_void_p]
-        L.or_face_count.restype = C.c_long
-        L.or_plan_cycle.argtypes = [C.c_double, C.c_double, C.c_double, C.c_double,
-                                    C.POINTER(C.c_double), C.POINTER(C.c_int)]
-        L.or_substep.argtypes = [C.c_double, C.c_double, C.c_double, C.c_int, C.c_int,
-                                 C.POINTER(C.c_int), C.POINTER(C.c_int)]
-        L.or_substep.restype = C.c_double
-        _lib = L
+        _lib = load(LIB_PATH)
     return _lib
 
 
-def default_params():
+def default_params(L=None):
     p = Params()
-    lib().or_default_params(C.byref(p))
+    (L or lib()).or_default_params(C.byref(p))
     return p
 
 
-def params_from_case(case, **over):
-    p = default_params()
+def params_from_case(case, L=None, **over):
+    p = default_params(L)
     p.ndim = case["ndim"]
     for d in range(3):
         p.n[d] = case["n"][d]
@@ -116,52 +134,53 @@ def params_from_case(case, **over):
 class OracleSim:
     """Plain CPU reference of the whole method (test infrastructure)."""
 
-    def __init__(self, case, **over):
+    def __init__(self, case, L=None, **over):
         self.case = case
-        self.p = params_from_case(case, **over)
+        self.L = L or lib()
+        self.p = params_from_case(case, self.L, **over)
         self.D = case["ndim"]
         self.NV = self.D + 2
         self.nc = int(np.prod(case["n"]))
-        self.h = lib().or_create(C.byref(self.p))
+        self.h = self.L.or_create(C.byref(self.p))
         if not self.h:
-            raise RuntimeError(lib().or_last_error().decode())
+            raise RuntimeError(self.L.or_last_error().decode())
         self.set_state(case["phi"], case["prim"])
 
     def __del__(self):
         if getattr(self, "h", None):
-            lib().or_destroy(self.h)
+            self.L.or_destroy(self.h)
             self.h = None
 
     def set_state(self, phi, prim):
-        rc = lib().or_set_state(self.h, np.ascontiguousarray(phi, dtype=np.float64).reshape(-1),
+        rc = self.L.or_set_state(self.h, np.ascontiguousarray(phi, dtype=np.float64).reshape(-1),
                                 np.ascontiguousarray(prim, dtype=np.float64).reshape(-1))
         if rc:
-            raise RuntimeError(lib().or_last_error().decode())
+            raise RuntimeError(self.L.or_last_error().decode())
 
     def advance(self, t_end, mode=0, max_cycles=0):
         st = Stats()
-        rc = lib().or_advance(self.h, float(t_end), int(mode), int(max_cycles), C.byref(st))
+        rc = self.L.or_advance(self.h, float(t_end), int(mode), int(max_cycles), C.byref(st))
         if rc:
-            raise RuntimeError("oracle advance failed (%d): %s" % (rc, lib().or_last_error().decode()))
+            raise RuntimeError("oracle advance failed (%d): %s" % (rc, self.L.or_last_error().decode()))
         return st.as_dict()
 
     def state(self):
         phi = np.empty(self.nc)
         cons = np.empty(2 * self.NV * self.nc)
         alpha = np.empty(self.nc)
-        lib().or_get_state(self.h, phi, cons, alpha)
+        self.L.or_get_state(self.h, phi, cons, alpha)
         return phi, cons.reshape(2, self.NV, self.nc), alpha
 
     def totals(self):
         out = np.empty(10)
-        lib().or_totals(self.h, out)
+        self.L.or_totals(self.h, out)
         return out.reshape(2, 5)
 
     def geometry(self):
-        nf = lib().or_face_count(self.h)
+        nf = self.L.or_face_count(self.h)
         alpha = np.empty(self.nc)
         ap = np.empty(3 * nf)
-        lib().or_geometry(self.h, alpha, ap)
+        self.L.or_geometry(self.h, alpha, ap)
         return alpha, ap.reshape(3, nf)
 
 
@@ -230,3 +249,55 @@ def exact_tube(case, x, t):
     for i, xx in enumerate(x):
         out[i] = riemann_sample(WL, WR, g[0], pi[0], g[1], pi[1], (xx - xi) / t)
     return out
+
+
+def _grid_params(L, ndim, n, bc, **over):
+    """parameters of a unit run on [0, 1]^ndim with n cells per direction"""
+    p = default_params(L)
+    p.ndim = ndim
+    for d in range(3):
+        p.n[d] = n if d < ndim else 1
+        p.lo[d] = 0.0
+        p.bc[d] = bc if d < ndim else 0
+    p.h = 1.0 / n
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def ls_transport(phi, vel, dt, nsteps, ndim, n, bc=1, L=None, **over):
+    """level-set transport by the fixed velocity field vel[D][cells]"""
+    L = L or lib()
+    p = _grid_params(L, ndim, n, bc, **over)
+    out = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1).copy()
+    v = np.ascontiguousarray(vel, dtype=np.float64).reshape(-1)
+    if L.or_ls_transport(C.byref(p), out, v, float(dt), int(nsteps)):
+        raise RuntimeError("or_ls_transport failed")
+    return out
+
+
+def reinit_run(phi, ndim, n, bc=0, L=None, **over):
+    L = L or lib()
+    p = _grid_params(L, ndim, n, bc, **over)
+    out = np.ascontiguousarray(phi, dtype=np.float64).reshape(-1).copy()
+    if L.or_reinit_run(C.byref(p), out):
+        raise RuntimeError("or_reinit_run failed")
+    return out
+
+
+def extend_v_run(phi, v, ndim, n, bc=0, L=None, **over):
+    L = L or lib()
+    p = _grid_params(L, ndim, n, bc, **over)
+    out = np.ascontiguousarray(v, dtype=np.float64).reshape(-1).copy()
+    if L.or_extend_v_run(C.byref(p), np.ascontiguousarray(phi, dtype=np.float64).reshape(-1), out):
+        raise RuntimeError("or_extend_v_run failed")
+    return out.reshape(ndim, -1)
+
+
+def extend_w_run(phi, W, ndim, n, bc=0, L=None, **over):
+    L = L or lib()
+    p = _grid_params(L, ndim, n, bc, **over)
+    out = np.ascontiguousarray(W, dtype=np.float64).reshape(-1).copy()
+    if L.or_extend_w_run(C.byref(p), np.ascontiguousarray(phi, dtype=np.float64).reshape(-1), out):
+        raise RuntimeError("or_extend_w_run failed")
+    return out.reshape(2, ndim + 2, -1)

@@ -91,6 +91,11 @@ void or_plan_cycle(double dt_slow, double dt_fast, double remaining, double thr,
                    double* dt_slow_out, int* single);
 double or_substep(double tau, double t1, double dt_fast, int rk, int half_done,
                   int* hits_half, int* final_step);
+/* single method steps run alone (Sec. 2.3), arrays [D or NV][cells] */
+int or_ls_transport(const or_params* p, double* phi, const double* vel, double dt, int nsteps);
+int or_reinit_run(const or_params* p, double* phi);
+int or_extend_v_run(const or_params* p, const double* phi, double* v);
+int or_extend_w_run(const or_params* p, const double* phi, double* W);
 
 #ifdef __cplusplus
 }

@@ -243,3 +243,35 @@ def test_droplet_mass_is_constant(oracle):
     for mode in (1,):
         o.advance(1.0, mode=mode, max_cycles=10)
         assert abs(o.totals()[0, 0] / m0 - 1.0) < 1e-13
+
+
+def test_droplet_translation_returns(oracle):
+    """Sec. 4.2 analogue with the full scheme and the accelerated cycle: a
+    water droplet (radius 0.2, 24^2 cells) carried diagonally by a uniform
+    flow u = (200, 100) m/s through a periodic box for one period in both
+    directions (t = 0.01 s: two in x, one in y).  The exact solution is the
+    initial state.  Mass of each fluid is conserved to round-off over the
+    ~1900 water sub-steps; the droplet's centroid comes back within a small
+    fraction of a cell and its volume-fraction field within 15% in L1
+    (measured 0.08 cells and 9%)."""
+    n, R, u = 24, 0.2, (200.0, 100.0)
+    h, (X, Y) = WL._grid(2, n)
+    phi = (np.sqrt((X - 0.5) ** 2 + (Y - 0.5) ** 2) - R).reshape(-1)
+    prim = np.zeros((2, 4, n * n))
+    for k, rho in enumerate((1000.0, 1.2)):
+        prim[k, 0], prim[k, 1], prim[k, 2], prim[k, 3] = rho, u[0], u[1], 1e5
+    c = WL._case(2, n, 1, WL.WATER, WL.AIR, phi, prim, 0.01, "droplet_diagonal")
+    o = oracle.OracleSim(c)
+    tot0 = o.totals()
+    _, _, a0 = o.state()
+    st = o.advance(0.01, mode=1)
+    assert st["t"] == 0.01 and st["steps"][0] > 3 * st["steps"][1]    # water sub-stepped
+    tot1 = o.totals()
+    _, _, a1 = o.state()
+    mass = np.abs(tot1[:, 0] - tot0[:, 0]) / tot0[:, 0]
+    assert np.all(mass < 1e-12), mass
+    x, y = X.reshape(-1), Y.reshape(-1)
+    for w in (x, y):
+        shift = ((a1 * w).sum() / a1.sum() - (a0 * w).sum() / a0.sum()) * n
+        assert abs(shift) < 0.15, shift
+    assert np.abs(a1 - a0).sum() / a0.sum() < 0.15
