@@ -115,6 +115,18 @@ typedef struct {
                             batch, kernel profiling or an unfinished autotuner,
                             and a step shortened to reach t_end, are issued
                             one by one [0] */
+    int no_rollback;     /* do not keep the state of the last cycle start: a
+                            call that fails with SIM_ENONPHYS then leaves the
+                            state of the failing step instead of rolling it
+                            back (saves one copy of the contents and level
+                            set per cycle, 2 NV + 1 fields of memory) [0] */
+    int grid_cap;        /* > 0: at most this many blocks for every kernel that
+                            walks a tile list (each block then loops over
+                            several tiles; a multiple of 8 keeps the XCD-aware
+                            tile order, other values use a plain stride).  The
+                            kernels loop over the device-side list counts, so
+                            results do not depend on it; for tests and
+                            tuning [0] */
 } sim_opts;
 
 typedef struct {
@@ -126,12 +138,17 @@ typedef struct {
     double last_dt[2];       /* last CFL time step of each fluid */
     double bflux[2][5];      /* time-integrated inflow through the domain boundary,
                                 per fluid and component (x dV units) */
+    int64_t active_cells[2]; /* cells holding each fluid (alpha_k > 0) at the start
+                                of the call's last cycle or step */
 } sim_stats;
 
 /* Fill *o with the defaults listed above. */
 void sim_default_opts(sim_opts* o);
 
-/* Create a simulation.  eos[0] is fluid 0 (phi < 0), eos[1] fluid 1.
+/* Create a simulation of the two-fluid problem of Sec. 2.1 (the Euler
+ * equations of each fluid, Eq. (EulerEquation), on one uniform grid, with
+ * the interface the zero level set of Sec. 2.3).  eos[0] is fluid 0
+ * (phi < 0), eos[1] fluid 1.
  * stream: a hipStream_t to order all work on, or NULL for a private stream.
  * Unless opts->serial is set, the library also creates two non-blocking
  * streams for the bulk-tile stages; every call joins them back into `stream`
@@ -148,14 +165,33 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
  * fluid's ghost states.  Resets time and the boundary-flux ledger. */
 sim_status sim_set_state(sim_t* s, const double* phi, const double* prim, int on_device);
 
-/* Advance to t_end with the original method (SIM_SINGLE_DT) or the
- * accelerated cycle (SIM_MULTI_DT), stopping early after max_cycles
- * cycles/steps when max_cycles > 0.  Statistics of this call go to *out
- * (nullable).  On SIM_ENONPHYS the state is that of the failing step. */
+/* Advance to t_end with the original method of Sec. 3.1 (SIM_SINGLE_DT: one
+ * CFL time step for both fluids and the level set) or the accelerated cycle
+ * of Sec. 3.1 (SIM_MULTI_DT: the slow fluid takes one step of its own CFL
+ * length, truncated to a whole number of fast steps when the fractional
+ * part of n is below 0.7; the fast fluid sub-steps with its CFL step,
+ * interacting with the slow fluid's states interpolated by Eq.
+ * (interpolation); the interfacial flux correction of Eqs.
+ * (firstcorrection)/(secondcorrection) keeps the update conservative),
+ * stopping early after max_cycles cycles/steps when max_cycles > 0.  The
+ * last cycle is shortened so that t lands on t_end.  Statistics of this
+ * call go to *out (nullable).
+ * On SIM_ENONPHYS (a state with rho <= 0, p + p_inf <= 0 or NaN, or no valid
+ * time step) the contents, level set, boundary ledger and time are rolled
+ * back to the start of the failing cycle or step, the last completed one
+ * (unless opts->no_rollback); *out then counts the completed cycles only,
+ * and sim_last_error() names the fluid, the cell and the time of the
+ * failing cycle.  The extension's and the Riemann solver's warm-start values
+ * are not rolled back, so a repeated call can differ from the first at the
+ * level of their stopping tolerances.  A run of captured steps (opts->graph)
+ * learns of a failure only after the whole run: it rolls back to the start
+ * of that run.  Batched simulations (sim_batch_advance) are not rolled back:
+ * they keep the state of the failing step. */
 sim_status sim_advance(sim_t* s, double t_end, int mode, int64_t max_cycles, sim_stats* out);
 
-/* Copy the level set, contents cons[2][NV][cells] and fluid-0 volume
- * fraction out (any pointer may be NULL). */
+/* Copy the level set, the cell contents cons[2][NV][cells] = alpha_k U_k
+ * (the per-volume contents that Eq. (Eulerdiscrete) of Sec. 2.1 advances)
+ * and the fluid-0 volume fraction out (any pointer may be NULL). */
 sim_status sim_get_state(sim_t* s, double* phi, double* cons, double* alpha, int on_device);
 
 /* Conservation ledger (the totals whose drift Sec. 4.2 tracks): the total

@@ -36,18 +36,19 @@ class Opts(C.Structure):
                 ("force_cycle", C.c_int), ("no_correction", C.c_int),
                 ("serial", C.c_int), ("tape", C.c_int), ("ckpt_every", C.c_int),
                 ("dt_fixed", C.c_double), ("autotune", C.c_int),
-                ("graph", C.c_int)]
+                ("graph", C.c_int), ("no_rollback", C.c_int),
+                ("grid_cap", C.c_int)]
 
 
 class Stats(C.Structure):
     _fields_ = [("cycles", C.c_int64), ("steps", C.c_int64 * 2), ("cell_updates", C.c_int64 * 2),
                 ("t", C.c_double), ("last_n", C.c_double), ("last_dt", C.c_double * 2),
-                ("bflux", (C.c_double * 5) * 2)]
+                ("bflux", (C.c_double * 5) * 2), ("active_cells", C.c_int64 * 2)]
 
     def as_dict(self):
         return dict(cycles=self.cycles, steps=list(self.steps), cell_updates=list(self.cell_updates),
                     t=self.t, last_n=self.last_n, last_dt=list(self.last_dt),
-                    bflux=np.array([list(r) for r in self.bflux]))
+                    bflux=np.array([list(r) for r in self.bflux]), active_cells=list(self.active_cells))
 
 
 EXPORTS = ["sim_default_opts", "sim_create", "sim_set_state", "sim_advance", "sim_get_state",
@@ -183,9 +184,13 @@ class Sim:
         _check(lib().sim_set_state(self.h, pp, pr, dev), "sim_set_state")
 
     def advance(self, t_end, mode=SIM_MULTI_DT, max_cycles=0):
+        """statistics of the call; on failure they are kept in last_stats
+        (with the state rolled back, they count the completed cycles)"""
         st = Stats()
-        _check(lib().sim_advance(self.h, float(t_end), int(mode), int(max_cycles), C.byref(st)), "sim_advance")
-        return st.as_dict()
+        rc = lib().sim_advance(self.h, float(t_end), int(mode), int(max_cycles), C.byref(st))
+        self.last_stats = st.as_dict()
+        _check(rc, "sim_advance")
+        return self.last_stats
 
     def state(self, device=True):
         """(phi, cons[2][NV][cells], alpha) as float64 CUDA tensors (or numpy)."""

@@ -4,6 +4,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <string>
 
 #include "sharp_internal.h"
 
@@ -46,6 +47,11 @@ static void release(Sim& s)
     s.graphs.clear();
     if (s.cap_stream) (void)hipStreamDestroy(s.cap_stream);
     s.cap_stream = nullptr;
+    if (s.snap_stream) (void)hipStreamDestroy(s.snap_stream);
+    if (s.ev_cs) (void)hipEventDestroy(s.ev_cs);
+    if (s.ev_snap) (void)hipEventDestroy(s.ev_snap);
+    s.snap_stream = nullptr;
+    s.ev_cs = s.ev_snap = nullptr;
     for (void* p : s.dev_allocs) (void)hipFree(p);
     s.dev_allocs.clear();
     for (hipEvent_t e : s.ev_pool) (void)hipEventDestroy(e);
@@ -128,6 +134,7 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     if (o.tape && o.ckpt_every < 1) { set_error("ckpt_every must be >= 1"); return SIM_EINVAL; }
     if (!(o.dt_fixed >= 0.0) || !std::isfinite(o.dt_fixed)) { set_error("dt_fixed must be >= 0"); return SIM_EINVAL; }
     if (o.graph && !(o.dt_fixed > 0.0)) { set_error("graph needs dt_fixed > 0"); return SIM_EINVAL; }
+    if (o.grid_cap < 0) { set_error("grid_cap must be >= 0"); return SIM_EINVAL; }
 
     sim_t* h = new sim_t();
     Sim& s = h->s;
@@ -228,6 +235,19 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     // back with one copy; the counts, read by every grid-stride loop, sit
     // 256 bytes away from the words the reductions update atomically
     A(g.red, RED_WORDS);
+    if (!o.no_rollback) {
+        for (int k = 0; k < 2; k++) {
+            A(s.snapX[k], nv);
+            A(s.snapBacc[k], (size_t)NV * (g.nbface > 0 ? g.nbface : 1));
+        }
+        A(s.snapPhi, (size_t)g.nc);
+        if (rc == SIM_OK && (hipStreamCreateWithFlags(&s.snap_stream, hipStreamNonBlocking) != hipSuccess ||
+                             hipEventCreateWithFlags(&s.ev_cs, hipEventDisableTiming) != hipSuccess ||
+                             hipEventCreateWithFlags(&s.ev_snap, hipEventDisableTiming) != hipSuccess)) {
+            set_error("snapshot stream/event creation failed");
+            rc = SIM_EDEVICE;
+        }
+    }
     if (rc == SIM_OK) {
         g.counts = reinterpret_cast<int*>(g.red + RED_COUNTS);
         g.sched = reinterpret_cast<double*>(g.red + RED_SCHED);
@@ -270,6 +290,7 @@ void sim_destroy(sim_t* h)
     (void)hipStreamSynchronize(h->s.stream);
     for (int k = 0; k < 2; k++)
         if (h->s.side[k]) (void)hipStreamSynchronize(h->s.side[k]);
+    if (h->s.snap_stream) (void)hipStreamSynchronize(h->s.snap_stream);
     release(h->s);
     delete h;
 }
@@ -314,7 +335,14 @@ sim_status sim_advance(sim_t* h, double t_end, int mode, int64_t max_cycles, sim
     sim_stats st;
     memset(&st, 0, sizeof st);
     sim_status rc = engine_advance(s, t_end, mode, (long long)max_cycles, &st);
-    if (rc == SIM_OK) rc = engine_bflux(s, st.bflux);
+    if (rc == SIM_OK) {
+        rc = engine_bflux(s, st.bflux);
+    } else if (rc == SIM_ENONPHYS && s.snap_valid) {
+        // the rolled-back ledger; the failure's message is kept
+        std::string msg = sim_last_error();
+        if (engine_bflux(s, st.bflux) != SIM_OK) memset(st.bflux, 0, sizeof st.bflux);
+        set_error("%s", msg.c_str());
+    }
     if (out) *out = st;
     return rc;
 }

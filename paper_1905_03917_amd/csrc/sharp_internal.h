@@ -134,6 +134,22 @@ struct Sim {
     hipStream_t cap_stream = nullptr;   // library-owned stream the captures run on
     bool capturing = false;             // grids are sized for a capture (see Engine::grid)
     long long graph_captures = 0, graph_replays = 0;
+    // Rollback (unless o.no_rollback): at every cycle start the contents and
+    // the level set are copied on snap_stream (beside the cycle's first
+    // stages, which write only stage buffers) and the boundary ledger on
+    // the stream; every kernel that writes X or phiP waits for ev_snap first.
+    // A non-physical state restores the copies and the time.
+    double* snapX[2] = {nullptr, nullptr};
+    double* snapPhi = nullptr;
+    double* snapBacc[2] = {nullptr, nullptr};
+    hipStream_t snap_stream = nullptr;
+    hipEvent_t ev_cs = nullptr, ev_snap = nullptr;
+    bool snap_valid = false;            // the copies hold the start of the current cycle
+    bool snap_pending = false;          // writers of X / phiP must still wait for ev_snap
+    bool snap_waited[3] = {false, false, false};   // stream, side[0], side[1] have waited
+    double snap_t = 0.0;
+    sim_stats snap_stats;               // the call's statistics at that cycle start
+    long long rollbacks = 0;
 };
 
 void set_error(const char* fmt, ...);
@@ -152,6 +168,10 @@ void tape_clear(Sim& s);
 sim_status tape_begin(Sim& s, const double* prim_dev);
 sim_status tape_step(Sim& s, double dt);
 sim_status engine_backward(Sim& s, const double* g_cons, double* g_prim0, double* g_eos);
+
+// reduction word holding the lowest (cell << 1 | fluid) code of a cell found
+// non-physical (all ones when none)
+constexpr int RED_CELL = 8;
 
 #define SHARP_HIP(call)                                                              \
     do {                                                                             \

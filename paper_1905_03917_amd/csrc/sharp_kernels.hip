@@ -18,6 +18,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <string>
 #include <utility>
 
 #include <hip/hip_ext.h>
@@ -64,6 +65,13 @@ __device__ __forceinline__ ListRange xcd_range(const VB blk, int count)
 __device__ __forceinline__ void flag_error(const Dev& g, unsigned long long bits)
 {
     atomicOr(&g.red[4], bits);
+}
+// a non-physical state of fluid k in cell c: the flag, and the lowest
+// (cell, fluid) code found, which names the cell in the error message
+__device__ __forceinline__ void flag_nonphys(const Dev& g, int c, int k)
+{
+    atomicOr(&g.red[4], (unsigned long long)ERR_NONPHYS);
+    atomicMin(&g.red[RED_CELL], ((unsigned long long)(unsigned)c << 1) | (unsigned long long)(k & 1));
 }
 
 // ---------------------------------------------------------------------------
@@ -755,7 +763,7 @@ __device__ __forceinline__ void b_prims(const VB blk, const Dev& g, int list, in
         if (a < g.amix) continue;
         double U[NV], w[NV];
         for (int q = 0; q < NV; q++) U[q] = src[(size_t)q * g.nc + c] / a;
-        if (!cons2prim<D>(g.gam[k], g.pinf[k], U, w)) flag_error(g, ERR_NONPHYS);
+        if (!cons2prim<D>(g.gam[k], g.pinf[k], U, w)) flag_nonphys(g, c, k);
         for (int q = 0; q < NV; q++) W[(size_t)q * g.nc + c] = w[q];
     }
 }
@@ -1068,7 +1076,7 @@ __device__ __forceinline__ void b_extw_tb(const VB blk, const Dev& g, int list, 
             if (inM && a >= g.amix) {
                 double U[NV], W[NV];
                 for (int q = 0; q < NV; q++) U[q] = src[(size_t)q * g.nc + c] / a;
-                if (!cons2prim<D>(g.gam[k], g.pinf[k], U, W)) flag_error(g, ERR_NONPHYS);
+                if (!cons2prim<D>(g.gam[k], g.pinf[k], U, W)) flag_nonphys(g, c, k);
                 for (int q = 0; q < NV; q++) sA[q * RN + r] = W[q];
             } else {
                 for (int q = 0; q < NV; q++) sA[q * RN + r] = Wi[(size_t)q * g.nc + c];
@@ -1457,7 +1465,7 @@ __device__ __forceinline__ void b_cfl(const VB blk, const Dev& g, int list, int 
         } else {
             double U[NV];
             for (int q = 0; q < NV; q++) U[q] = cons[(size_t)q * g.nc + c] / a;
-            if (!cons2prim<D>(g.gam[k], g.pinf[k], U, W)) flag_error(g, ERR_NONPHYS);
+            if (!cons2prim<D>(g.gam[k], g.pinf[k], U, W)) flag_nonphys(g, c, k);
         }
         double cs = csound(g.gam[k], g.pinf[k], W[0], W[D + 1]), s = 0.0;
         for (int d = 0; d < D; d++) s += (fabs(W[1 + d]) + cs) / g.h;
@@ -1483,6 +1491,33 @@ template <int D, bool BAND>
 __global__ void __launch_bounds__(SHARP_WG) k_cfl(Dev g, int list, int k, const double* cons, int wb)
 {
     b_cfl<D, BAND>(VB::grid(), g, list, k, cons, wb);
+}
+
+// Check of a call's final state: every cell of fluid k on its bulk tiles,
+// and every real cell (alpha_k >= alpha_mix) of the band tiles, must hold a
+// physical state.  The lists are those of the last cycle start, which cover
+// every cell the cycle could move into a fluid.
+template <int D>
+__device__ __forceinline__ void b_verify(const VB blk, const Dev& g, int list, int k)
+{
+    constexpr int NV = D + 2;
+    const int* L = list_ptr(g, list);
+    const double* cons = g.X[k];
+    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
+        int i, j, kk;
+        if (!tile_cell<D>(g, L[ti], threadIdx.x, i, j, kk)) continue;
+        int c = i + g.n[0] * (j + g.n[1] * kk);
+        double a = list == LIST_BAND ? alpha_k(g, k, c) : 1.0;
+        if (a < g.amix) continue;
+        double U[NV], W[NV];
+        for (int q = 0; q < NV; q++) U[q] = cons[(size_t)q * g.nc + c] / a;
+        if (!cons2prim<D>(g.gam[k], g.pinf[k], U, W)) flag_nonphys(g, c, k);
+    }
+}
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG) k_verify(Dev g, int list, int k)
+{
+    b_verify<D>(VB::grid(), g, list, k);
 }
 
 __device__ __forceinline__ void b_zero_red(const VB blk, const Dev& g)
@@ -1743,7 +1778,7 @@ __device__ __forceinline__ void b_stage_lds(const VB blk, const Dev& g, int list
                 }
                 if (!BAND && cfl) {
                     double W[NV];
-                    if (!cons2prim<D>(gm, pi, Uo, W)) flag_error(g, ERR_NONPHYS);
+                    if (!cons2prim<D>(gm, pi, Uo, W)) flag_nonphys(g, c, k);
                     double cs = csound(gm, pi, W[0], W[D + 1]), sp = 0.0;
                     for (int d = 0; d < D; d++) sp += (fabs(W[1 + d]) + cs) / g.h;
                     cmax = fmax(cmax, sp);
@@ -1970,7 +2005,7 @@ __device__ __forceinline__ void b_stage_lds3(const VB blk, const Dev& g, int lis
             }
             if (!BAND && cfl) {
                 double W[NV];
-                if (!cons2prim<D>(gm, pi, Uo, W)) flag_error(g, ERR_NONPHYS);
+                if (!cons2prim<D>(gm, pi, Uo, W)) flag_nonphys(g, c, k);
                 double cs = csound(gm, pi, W[0], W[D + 1]), sp = 0.0;
                 for (int e = 0; e < D; e++) sp += (fabs(W[1 + e]) + cs) / g.h;
                 cmax = fmax(cmax, sp);
@@ -2629,6 +2664,7 @@ struct Engine {
     {
         long long c = (long long)(s.capturing ? pow2_at_least(s.lcount[list]) : s.lcount[list]) * per_tile;
         if (cap <= 0) cap = s.max_blocks;
+        if (s.o.grid_cap > 0 && cap > s.o.grid_cap) cap = s.o.grid_cap;
         if (c < 1) c = 1;
         if (c > cap) c = cap;
         return dim3((unsigned)c);
@@ -2899,6 +2935,7 @@ struct Engine {
             if (s.bulk_pending[k]) (void)hipStreamWaitEvent(s.stream, s.ev_bulk[k], 0);
             prev_band = s.band_rec[k] ? s.ev_band[k] : nullptr;
         }
+        if (out == g.X[k]) snap_guard(s.stream);
         launch_stage<true>(s.stream, LIST_BAND, k, in, self2, base, out, a, dt, wflux, 0, tmp);
         if (ov) {
             if (g.use_sched) {
@@ -2919,6 +2956,7 @@ struct Engine {
             ev = s.ev_used;
             s.ev_used += 2;
         }
+        if (out == g.X[k]) snap_guard(bs);
         launch_stage<false>(bs, bl, k, in, nullptr, base, out, a, dt, wflux, cfl, nullptr,
                             s.prof ? s.ev_pool[ev] : nullptr, s.prof ? s.ev_pool[ev + 1] : nullptr);
         if (s.prof) {
@@ -3023,6 +3061,95 @@ struct Engine {
         go<b_ls<D>, SHARP_WG>(k_ls<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, a, dt, in, out, s.vcur);
     }
 
+    // ---- rollback snapshot ----
+    // Taken at a cycle start once the readback of that start has found the
+    // state physical: the boundary ledger in stream order (every stage adds
+    // to it), the contents and the level set on the snapshot stream, beside
+    // the cycle's first stages (which write stage buffers only).  Every
+    // kernel that writes X or phiP waits for the copies first (snap_guard).
+    // Under the serial schedule the copies run on the stream.
+    sim_status snap_begin(const sim_stats* st)
+    {
+        s.snap_valid = false;
+        s.snap_pending = false;
+        if (!s.snapPhi || s.rec || s.capturing) return SIM_OK;
+        const size_t nv = (size_t)NV * g.nc, nb = (size_t)NV * (g.nbface > 0 ? g.nbface : 1);
+        for (int k = 0; k < 2; k++)
+            SHARP_HIP(hipMemcpyAsync(s.snapBacc[k], g.bacc[k], nb * sizeof(double), hipMemcpyDeviceToDevice, s.stream));
+        const bool own = !s.run_serial && !s.o.serial;
+        hipStream_t cs = s.stream;
+        if (own) {
+            if (!s.snap_stream) SHARP_HIP(hipStreamCreateWithFlags(&s.snap_stream, hipStreamNonBlocking));
+            SHARP_HIP(hipEventRecord(s.ev_cs, s.stream));
+            SHARP_HIP(hipStreamWaitEvent(s.snap_stream, s.ev_cs, 0));
+            cs = s.snap_stream;
+        }
+        for (int k = 0; k < 2; k++)
+            SHARP_HIP(hipMemcpyAsync(s.snapX[k], g.X[k], nv * sizeof(double), hipMemcpyDeviceToDevice, cs));
+        SHARP_HIP(hipMemcpyAsync(s.snapPhi, g.phiP, (size_t)g.nc * sizeof(double), hipMemcpyDeviceToDevice, cs));
+        if (own) {
+            SHARP_HIP(hipEventRecord(s.ev_snap, cs));
+            s.snap_pending = true;
+            for (bool& w : s.snap_waited) w = false;
+        }
+        s.snap_t = s.t;
+        s.snap_stats = *st;
+        s.snap_valid = true;
+        return SIM_OK;
+    }
+    // order the next writer of X or phiP on stream st after the snapshot
+    void snap_guard(hipStream_t st)
+    {
+        if (!s.snap_pending || s.capturing) return;
+        const int i = (s.side[0] && st == s.side[0]) ? 1 : ((s.side[1] && st == s.side[1]) ? 2 : 0);
+        if (s.snap_waited[i]) return;
+        (void)hipStreamWaitEvent(st, s.ev_snap, 0);
+        s.snap_waited[i] = true;
+    }
+    // back to the snapshot: contents, level set, boundary ledger, time and
+    // the call's statistics; the geometry, band and tile lists are rebuilt
+    // from the level set as sim_set_state builds them
+    sim_status rollback(sim_stats* st)
+    {
+        join();
+        for (int k = 0; k < 2; k++)
+            if (s.side[k]) SHARP_HIP(hipStreamSynchronize(s.side[k]));
+        if (s.snap_stream) SHARP_HIP(hipStreamSynchronize(s.snap_stream));
+        SHARP_HIP(hipStreamSynchronize(s.stream));
+        s.snap_pending = false;
+        const size_t nv = (size_t)NV * g.nc, nb = (size_t)NV * (g.nbface > 0 ? g.nbface : 1);
+        for (int k = 0; k < 2; k++) {
+            SHARP_HIP(hipMemcpyAsync(g.X[k], s.snapX[k], nv * sizeof(double), hipMemcpyDeviceToDevice, s.stream));
+            SHARP_HIP(hipMemcpyAsync(g.bacc[k], s.snapBacc[k], nb * sizeof(double), hipMemcpyDeviceToDevice, s.stream));
+        }
+        SHARP_HIP(hipMemcpyAsync(g.phiP, s.snapPhi, (size_t)g.nc * sizeof(double), hipMemcpyDeviceToDevice, s.stream));
+        s.lcount[LIST_ALL] = g.ntiles;
+        geom(g.phiP, LIST_ALL);
+        geom(g.phiP, LIST_ALL);
+        mask(LIST_ALL, 0);
+        tiles();
+        SHARP_HIP(reset_flags());
+        SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, RED_WORDS * sizeof(unsigned long long), hipMemcpyDeviceToHost,
+                                 s.stream));
+        SHARP_HIP(hipStreamSynchronize(s.stream));
+        take_counts();
+        s.t = s.snap_t;
+        *st = s.snap_stats;
+        s.rollbacks++;
+        if (s.o.tape && s.tape_fluid >= 0) {
+            s.tape_fluid = -1;
+            s.tape_why = "a step turned non-physical and the state was rolled back";
+        }
+        return SIM_OK;
+    }
+    // reductions and error flags to zero, no non-physical cell recorded
+    hipError_t reset_flags()
+    {
+        hipError_t e = hipMemsetAsync(g.red, 0, 8 * sizeof(unsigned long long), s.stream);
+        if (e == hipSuccess) e = hipMemsetAsync(g.red + RED_CELL, 0xff, sizeof(unsigned long long), s.stream);
+        return e;
+    }
+
     // ---- CFL ----
     void cfl_launch(int k, const double* cons)
     {
@@ -3037,8 +3164,21 @@ struct Engine {
         take_counts();
         unsigned long long err = s.h_red[4];
         if (err & ERR_BAND_OVERFLOW) { set_error("the interface band left its tile set within a cycle"); return SIM_EDEVICE; }
-        if (err & ERR_NONPHYS) { set_error("non-physical state (rho <= 0, p + p_inf <= 0 or NaN)"); return SIM_ENONPHYS; }
+        if (err & ERR_NONPHYS) { nonphys_error(); return SIM_ENONPHYS; }
         return SIM_OK;
+    }
+    // message of a non-physical state, naming the cell the kernels recorded
+    void nonphys_error()
+    {
+        const unsigned long long code = s.h_red[RED_CELL];
+        if (code == ~0ull) {
+            set_error("non-physical state (rho <= 0, p + p_inf <= 0 or NaN)");
+            return;
+        }
+        const int c = (int)(code >> 1), k = (int)(code & 1);
+        const int i = c % g.n[0], j = (c / g.n[0]) % g.n[1], kk = c / (g.n[0] * g.n[1]);
+        set_error("non-physical state (rho <= 0, p + p_inf <= 0 or NaN) of fluid %d in cell %d (i %d, j %d, k %d)", k,
+                  c, i, j, kk);
     }
     sim_status readback(int which, double* dt, long long* cnt)
     {
@@ -3238,6 +3378,7 @@ struct Engine {
     {
         const double d = s.o.dt_fixed;
         join();
+        snap_guard(s.stream);
         go<b_acc, 64>(k_acc, 1, 64, s.stream, g, 0);
         for (long long i = 0; i < K; i++) {
             std::vector<unsigned char> key = launch_key(d);
@@ -3269,6 +3410,7 @@ struct Engine {
             st->last_dt[k] = (cnt > 0 && m > 0.0) ? s.o.cfl / m : INFINITY;
             st->steps[k] += K;
             st->cell_updates[k] += (long long)s.h_red[5 + k];
+            st->active_cells[k] = cnt;
         }
         st->cycles += K;
         st->last_n = 1.0;
@@ -3464,6 +3606,10 @@ struct Engine {
     {
         long long done = 0;
         sim_status rc = SIM_OK;
+        // a state found non-physical at this call's first cycle start is
+        // left as the call found it
+        s.snap_valid = false;
+        s.snap_pending = false;
         while (s.t < t_end && (max_cycles <= 0 || done < max_cycles)) {
             if (mode == SIM_SINGLE_DT && graph_run_ok()) {
                 // the whole steps of length dt_fixed before t_end, from graphs
@@ -3475,7 +3621,10 @@ struct Engine {
                     K++;
                 }
                 if (K > 0) {
-                    rc = graph_steps(K, t_end, st);
+                    // the run reports its flags once, at its end: the
+                    // snapshot is that of the run's start
+                    rc = snap_begin(st);
+                    if (rc == SIM_OK) rc = graph_steps(K, t_end, st);
                     if (rc != SIM_OK) break;
                     done += K;
                     continue;
@@ -3485,9 +3634,13 @@ struct Engine {
             long long cnt[2];
             rc = prepare(true, dt, cnt);
             if (rc != SIM_OK) break;
+            rc = snap_begin(st);
+            if (rc != SIM_OK) break;
             if (s.o.autotune && !s.rec) tune_step(st);
             st->last_dt[0] = dt[0];
             st->last_dt[1] = dt[1];
+            st->active_cells[0] = cnt[0];
+            st->active_cells[1] = cnt[1];
             if (!(fmin(dt[0], dt[1]) > 0.0)) { set_error("invalid time step"); rc = SIM_ENONPHYS; break; }
             if (mode == SIM_SINGLE_DT) {
                 double d = s.o.dt_fixed > 0.0 ? s.o.dt_fixed : (dt[0] < dt[1] ? dt[0] : dt[1]);
@@ -3513,13 +3666,31 @@ struct Engine {
         }
         join();
         s.tune_open = false;    // time between calls is not a cycle
+        if (rc == SIM_OK && done > 0) {
+            // the call's final state: a cycle whose last stages produced a
+            // non-physical state is found here, not at the next call's start
+            for (int k = 0; k < 2; k++) {
+                const int bl = k == 0 ? LIST_BULK0 : LIST_BULK1;
+                go<b_verify<D>, SHARP_WG>(k_verify<D>, grid(bl), wg(), s.stream, g, bl, k);
+                go<b_verify<D>, SHARP_WG>(k_verify<D>, grid(LIST_BAND), wg(), s.stream, g, LIST_BAND, k);
+            }
+        }
         if (rc == SIM_OK) {
-            // late non-physical flags (stages after the last readback)
-            rc = rb_begin(5, false);
+            // late non-physical flags (stages after the last readback, and
+            // the check of the final state)
+            rc = rb_begin(RED_CELL + 1, false);
             if (rc == SIM_OK) rc = rb_wait(false);
-            if (rc == SIM_OK && (s.h_red[4] & ERR_NONPHYS)) { set_error("non-physical state"); rc = SIM_ENONPHYS; }
+            if (rc == SIM_OK && (s.h_red[4] & ERR_NONPHYS)) { nonphys_error(); rc = SIM_ENONPHYS; }
         }
         if (s.prof) profile_flush();
+        if (rc == SIM_ENONPHYS && s.snap_valid) {
+            std::string why = sim_last_error();
+            sim_status r2 = rollback(st);
+            if (r2 != SIM_OK) return r2;
+            set_error("%s, in the cycle or step starting at t = %.17g (after %lld completed ones in this call); "
+                      "the state is rolled back to that start",
+                      why.c_str(), s.t, (long long)st->cycles);
+        }
         st->t = s.t;
         return rc;
     }
@@ -3576,12 +3747,14 @@ struct Engine {
         tiles();
         for (int k = 0; k < 2; k++)
             SHARP_HIP(hipMemsetAsync(g.bacc[k], 0, sizeof(double) * NV * (size_t)(g.nbface > 0 ? g.nbface : 1), s.stream));
-        SHARP_HIP(hipMemsetAsync(g.red, 0, 8 * sizeof(unsigned long long), s.stream));
+        SHARP_HIP(reset_flags());
         SHARP_HIP(hipMemcpyAsync(s.h_red, g.red, RED_WORDS * sizeof(unsigned long long), hipMemcpyDeviceToHost,
                                  s.stream));
         SHARP_HIP(hipStreamSynchronize(s.stream));
         SHARP_HIP(hipGetLastError());
         take_counts();
+        s.snap_valid = false;
+        s.snap_pending = false;
         s.t = 0.0;
         s.wcur = 0;
         s.vcur = 0;

@@ -169,6 +169,18 @@ def droplet_2d(n=64, seed=0, radius=0.1, u=None, ndim=2):
                  "droplet_%dd" % ndim, centre=c, radius=radius)
 
 
+def vacuum_tube_1d(n=200, U=3000.0):
+    """Air | air pulled apart at -U | +U (Mach 8 at U = 3000 m/s): the
+    interface cell empties and turns non-physical after some 30 cycles, the
+    input of the tests of the non-physical-state handling."""
+    h, (x,) = _grid(1, n)
+    prim = np.zeros((2, 3, n))
+    prim[:, 0] = 1.0
+    prim[:, 1] = np.where(x < 0.5, -U, U)
+    prim[:, 2] = 1.0e5
+    return _case(1, n, 0, AIR, AIR, x - 0.5, prim, 1e30, "vacuum_tube_1d")
+
+
 def wall_bubble_2d(n=64, seed=0, radius=0.2):
     """Air bubble (fluid 0) cut by the zero-gradient wall x = 0, at a higher
     pressure than the surrounding water: the interface band touches the wall,
