@@ -200,6 +200,20 @@ sim_status sim_get_state(sim_t* s, double* phi, double* cons, double* alpha, int
  * the same bits).  out10 is a host array. */
 sim_status sim_totals(sim_t* s, double* out10);
 
+/* sim_totals for callers that cannot allocate device memory (code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc): the
+ * same totals, bit for bit, with the reduction's partial sums kept in a
+ * file-scope device array of 41 KB per device (512 x 10 partial sums and the
+ * 10 totals; its size does not depend on the grid, so no grid is refused for
+ * it) instead of a buffer allocated per call.  No hipMalloc, hipFree or
+ * other allocation.  on_device = 1: out10 is a device pointer, written on
+ * the simulation's stream without waiting (ordered like the other work of
+ * the simulation); 0: out10 is a host array and the call waits for it.
+ * Every call on one device shares that device's array: calls that overlap
+ * on one device (simulations on different streams, or threads) race, and
+ * must be ordered by the caller.  SIM_ESTATE before sim_set_state. */
+sim_status sim_totals_noalloc(sim_t* s, double* out10, int on_device);
+
 /* Kernel timing of the fused face-flux/RK stage kernel on bulk tiles: when
  * enabled, sim_advance brackets every launch of it with HIP events on the
  * stream the kernel runs on.  sim_profile_read returns the summed duration

@@ -54,7 +54,7 @@ class Stats(C.Structure):
 EXPORTS = ["sim_default_opts", "sim_create", "sim_set_state", "sim_advance", "sim_get_state",
            "sim_totals", "sim_profile", "sim_profile_read", "sim_backward", "sim_tuned", "sim_destroy",
            "sim_strerror", "sim_last_error", "sim_batch_create", "sim_batch_advance", "sim_batch_info",
-           "sim_batch_destroy", "sim_graph_info"]
+           "sim_batch_destroy", "sim_graph_info", "sim_totals_noalloc"]
 
 _lib = None
 
@@ -75,6 +75,7 @@ def lib():
         L.sim_advance.argtypes = [vp, C.c_double, C.c_int, C.c_int64, C.POINTER(Stats)]
         L.sim_get_state.argtypes = [vp, vp, vp, vp, C.c_int]
         L.sim_totals.argtypes = [vp, vp]
+        L.sim_totals_noalloc.argtypes = [vp, vp, C.c_int]
         L.sim_profile.argtypes = [vp, C.c_int]
         L.sim_profile_read.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(C.c_int64), C.POINTER(C.c_int64),
                                        C.POINTER(C.c_int64)]
@@ -91,7 +92,7 @@ def lib():
         L.sim_batch_info.argtypes = [vp, C.POINTER(C.c_int64), C.POINTER(C.c_int64), C.POINTER(C.c_int64)]
         L.sim_batch_destroy.argtypes = [vp]
         L.sim_batch_destroy.restype = None
-        for f in ("sim_create", "sim_set_state", "sim_advance", "sim_get_state", "sim_totals",
+        for f in ("sim_create", "sim_set_state", "sim_advance", "sim_get_state", "sim_totals", "sim_totals_noalloc",
                   "sim_profile", "sim_profile_read", "sim_backward", "sim_tuned", "sim_batch_create",
                   "sim_batch_advance", "sim_batch_info", "sim_graph_info"):
             getattr(L, f).restype = C.c_int
@@ -213,6 +214,19 @@ class Sim:
         out = np.empty(10)
         _check(lib().sim_totals(self.h, C.c_void_p(out.ctypes.data)), "sim_totals")
         return out.reshape(2, 5)
+
+    def totals_noalloc(self, out=None):
+        """sim_totals_noalloc: into a float64 CUDA tensor of 10 (written on
+        the simulation's stream, not waited for) or, without `out`, into a
+        host array"""
+        if out is not None:
+            p, dev = _ptr(out)
+            assert dev == 1 and out.numel() == 10
+            _check(lib().sim_totals_noalloc(self.h, p, 1), "sim_totals_noalloc")
+            return out
+        host = np.empty(10)
+        _check(lib().sim_totals_noalloc(self.h, C.c_void_p(host.ctypes.data), 0), "sim_totals_noalloc")
+        return host.reshape(2, 5)
 
     def backward(self, g_cons):
         """Adjoint of the taped run (opts tape=1): g_cons = dJ/dcons at the

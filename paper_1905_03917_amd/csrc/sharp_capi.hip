@@ -136,9 +136,16 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     if (o.graph && !(o.dt_fixed > 0.0)) { set_error("graph needs dt_fixed > 0"); return SIM_EINVAL; }
     if (o.grid_cap < 0) { set_error("grid_cap must be >= 0"); return SIM_EINVAL; }
 
+    int device = -1;
+    if (hipGetDevice(&device) != hipSuccess) { set_error("hipGetDevice failed"); return SIM_EDEVICE; }
+    {
+        sim_status r = ledger_scratch_attach(device);
+        if (r != SIM_OK) return r;
+    }
     sim_t* h = new sim_t();
     Sim& s = h->s;
     s.o = o;
+    s.device = device;
     // 3-D bulk lists are long (the slow fluid fills most of the grid): a
     // larger grid bound measured faster there (the autotuner's choice at 256^3)
     if (D == 3) s.bulk_blocks = 4 * SHARP_BULK_BLOCKS;
@@ -399,6 +406,14 @@ sim_status sim_totals(sim_t* h, double* out10)
     Sim& s = h->s;
     if (!s.has_state) { set_error("no state"); return SIM_ESTATE; }
     return engine_totals(s, out10);
+}
+
+sim_status sim_totals_noalloc(sim_t* h, double* out10, int on_device)
+{
+    if (!h || !out10) { set_error("null argument"); return SIM_EINVAL; }
+    Sim& s = h->s;
+    if (!s.has_state) { set_error("no state"); return SIM_ESTATE; }
+    return engine_totals_noalloc(s, out10, on_device);
 }
 
 sim_status sim_tuned(sim_t* h, int* bulk_blocks, int* serial, int* done)

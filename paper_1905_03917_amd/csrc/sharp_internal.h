@@ -74,6 +74,7 @@ struct Sim {
     sim_opts o;
     hipStream_t stream = nullptr;
     bool own_stream = false;
+    int device = -1;       // device current at sim_create (the simulation's device)
     // bulk-tile stages run on one side stream per fluid, ordered against the
     // band work on `stream` by events (none when o.serial is set)
     hipStream_t side[2] = {nullptr, nullptr};
@@ -163,6 +164,10 @@ sim_status engine_bflux(Sim& s, double out[2][5]);
 void engine_bulk_stage(Sim& s, int k, const double* in, const double* base, double* out, double a, double dt);
 // conservation ledger (sharp_ledger.hip): out10[k*5 + q] = sum_c dV cons[k][q][c], zero for q >= NV
 sim_status engine_totals(Sim& s, double* out10);
+// the same through the device's file-scope scratch array (sharp_ledger.hip):
+// ledger_scratch_attach looks up its address once per device
+sim_status ledger_scratch_attach(int device);
+sim_status engine_totals_noalloc(Sim& s, double* out10, int on_device);
 // adjoint (sharp_adjoint.hip)
 void tape_clear(Sim& s);
 sim_status tape_begin(Sim& s, const double* prim_dev);
