@@ -1,19 +1,22 @@
 """Benchmark: accelerated sharp-interface method on one MI355X.
 
-Workload: 2-D shock-bubble, 1024x1024 cells, FP64 (planar water shock with
-post-shock p = 1e9 Pa hitting an air bubble of radius 0.15; stiffened-gas
-water, ideal-gas air; zero-gradient boundaries; reinitialisation every
-level-set step), advanced with the accelerated cycle (multi_dt).  One "step"
-is one accelerated cycle: the slow fluid's RK step plus the fast fluid's
-sub-steps, with interpolation, interaction, extension, mixing, level-set
-advection/reinitialisation and the interfacial flux correction.
+Headline workload: 3-D shock-droplet, 256^3 cells, FP64 (a Mach-1.5 air
+shock hitting a water droplet of radius 0.2; stiffened-gas water, ideal-gas
+air; zero-gradient boundaries; reinitialisation every level-set step),
+advanced with the accelerated cycle (multi_dt), the water fluid sub-stepped.
+One "step" is one accelerated cycle: the slow fluid's RK step plus the fast
+fluid's sub-steps, with interpolation, interaction, extension, mixing,
+level-set advection/reinitialisation and the interfacial flux correction.
 
 Metric: cell-updates/s summed over both fluids (one cell-update = one cell
-holding fluid k advanced through one complete RK step of fluid k).  The JSON
-line also carries the roofline of the dominant kernel (the fused face-flux +
-RK stage kernel on bulk tiles, timed with HIP events on the simulation's
-stream), the time of the original single-dt method over the same simulated
-interval, and the CPU oracle's rate on a bounded sample.
+holding fluid k advanced through one complete RK step of fluid k), timed
+without kernel profiling.  The JSON line also carries the roofline of the
+dominant kernel (the fused face-flux + RK stage kernel on bulk tiles),
+whose launch durations come from HIP events stamped by the dispatches on
+the stream the kernel runs on, in a re-run of the same cycles; the time of
+the original single-dt method over the same simulated interval; the 2-D
+1024^2 shock-bubble as a second workload; and the CPU oracle's rate on a
+bounded sample, on one thread and on every core of the affinity mask.
 """
 import argparse
 import hashlib
@@ -28,7 +31,6 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 # FP64 vector peak: 256 CUs x 4 SIMDs x 16 lanes x 2 (FMA) x 2.4 GHz
 FP64_VECTOR_TFLOPS = 256 * 4 * 16 * 2 * 2.4e9 / 1e12
-COUNTERS = os.path.join(ROOT, "profiles", "stage_bulk_shock_bubble_2d_1024_counters.json")
 COPY_PROBE_BYTES = 1 << 30
 KERNEL_SOURCES = ["paper_1905_03917_amd/csrc/sharp_kernels.hip", "paper_1905_03917_amd/csrc/sharp_device.h"]
 
@@ -38,15 +40,17 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=1024)
-    ap.add_argument("--case", default="shock_bubble_2d", choices=["shock_bubble_2d", "shock_droplet_3d"],
-                    help="workload of the timed cycles (the headline line is shock_bubble_2d at 1024^2; "
-                         "shock_droplet_3d at --n 256 is for profiling the 3-D path)")
+    ap.add_argument("--n", type=int, default=None, help="cells per direction (default 256 in 3-D, 1024 in 2-D)")
+    ap.add_argument("--case", default="shock_droplet_3d", choices=["shock_bubble_2d", "shock_droplet_3d"],
+                    help="workload of the timed cycles (the headline line is shock_droplet_3d at 256^3)")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-2d", action="store_true", help="skip the 1024^2 shock-bubble leg")
     ap.add_argument("--autotune", action="store_true",
                     help="let the library choose the bulk stage's grid bound during the warm-up cycles (needs --warmup >= 5)")
     ap.add_argument("--no-single", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
+    ap.add_argument("--cpu-worker", nargs=3, metavar=("CASE", "N", "SECONDS"),
+                    help="(internal) run the oracle on CASE at N cells per direction for SECONDS and print its rate")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances timing")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-steps timing")
@@ -57,11 +61,14 @@ def parse():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     ap.add_argument("--reduce-valu", metavar="VALU_DIR",
-                    help="reduce a pass of SQ instruction counters into the executed-work record")
+                    help="reduce a pass of SQ instruction counters into the executed-work record of --case/--n")
     ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="reduce two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
-                         "'bench.py --copy-probe' into the committed traffic record, then exit")
-    return ap.parse_args()
+                         "'bench.py --copy-probe' into the traffic record of --case/--n, then exit")
+    a = ap.parse_args()
+    if a.n is None:
+        a.n = 256 if a.case == "shock_droplet_3d" else 1024
+    return a
 
 
 def stage_bytes(D, first):
@@ -89,6 +96,20 @@ def stage_flops(D, first):
     return D * face + (3 * D + 9) + NV * (2 * D + (2 if first else 5))
 
 
+def stage_kernel(D):
+    """name of the bulk-tile stage kernel as the profiler prints it"""
+    return "k_stage_lds<%d, false>" % D if D <= 2 else "k_stage_lds3<false>"
+
+
+def record_path(case, n, what):
+    """committed per-workload record of the bulk stage's counters"""
+    return os.path.join(ROOT, "profiles", "stage_bulk_%s_%d_%s.json" % (case, n, what))
+
+
+def bench_args(case, n):
+    return "--case %s --n %d --steps 3 --warmup 1 --no-cpu --no-2d --no-single --no-l1 --no-adjoint --no-batch --no-graph" % (case, n)
+
+
 def source_digest():
     h = hashlib.sha256()
     for f in KERNEL_SOURCES:
@@ -97,12 +118,14 @@ def source_digest():
     return h.hexdigest()
 
 
-def reduce_counters(fetch_dir, write_dir):
+def reduce_counters(fetch_dir, write_dir, case, n):
     """HBM traffic of the bulk stage kernel from FETCH_SIZE and WRITE_SIZE
     (KiB per dispatch), each scaled by what the same counter reads for the
     1 GiB device copy of --copy-probe (the largest copy dispatch)."""
     import csv
     import glob
+    D = 3 if case == "shock_droplet_3d" else 2
+    kname = stage_kernel(D)
 
     def read(d, counter):
         rows = []
@@ -123,32 +146,32 @@ def reduce_counters(fetch_dir, write_dir):
         if not copies or max(copies) < 0.25 * copy_kib:
             raise SystemExit("no 1 GiB copy dispatch found in %s" % d)
         scale = copy_kib / max(copies)
-        stage = [v for (i, k), v in per.items() if "k_stage_lds<2, false>" in k]
+        stage = [v for (i, k), v in per.items() if kname in k]
         if not stage:
             raise SystemExit("no bulk stage dispatch found in %s" % d)
         out[name] = dict(counter=counter, copy_kib_read=max(copies), scale=scale, dispatches=len(stage),
                          kib_per_dispatch=sum(stage) / len(stage))
     traffic = (out["fetch"]["kib_per_dispatch"] * out["fetch"]["scale"]
                + out["write"]["kib_per_dispatch"] * out["write"]["scale"]) * 1024.0
-    rec = dict(kernel="k_stage_lds<2, false>", workload="shock_bubble_2d 1024x1024 multi_dt",
+    args = bench_args(case, n)
+    rec = dict(kernel=kname, workload="%s %s multi_dt" % (case, "x".join([str(n)] * D)),
                source_sha256=source_digest(), sources=KERNEL_SOURCES, counters=out,
                traffic_bytes_per_launch=traffic,
                commands=["timeout -s KILL 150 rocprofv3 --pmc FETCH_SIZE --output-format csv -d <FETCH_DIR> -o run "
-                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --no-adjoint --no-batch --no-graph --copy-probe",
+                         "-- python -u bench.py %s --copy-probe" % args,
                          "timeout -s KILL 150 rocprofv3 --pmc WRITE_SIZE --output-format csv -d <WRITE_DIR> -o run "
-                         "-- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 --no-adjoint --no-batch --no-graph --copy-probe",
-                         "python bench.py --reduce-counters <FETCH_DIR> <WRITE_DIR>"])
-    with open(COUNTERS, "w") as fh:
+                         "-- python -u bench.py %s --copy-probe" % args,
+                         "python bench.py --case %s --n %d --reduce-counters <FETCH_DIR> <WRITE_DIR>" % (case, n)])
+    with open(record_path(case, n, "counters"), "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
 
 
 VALU_COUNTERS = ["SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64",
                  "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES"]
-VALU_RECORD = os.path.join(ROOT, "profiles", "stage_bulk_shock_bubble_2d_1024_valu.json")
 
 
-def reduce_valu(valu_dir):
+def reduce_valu(valu_dir, case, n):
     """Executed FP64 work of the bulk stage kernel from one rocprofv3 pass of
     SQ instruction counters (wave-level counts per dispatch): executed FP64
     flops (SQ_INSTS_VALU_FLOPS_FP64 x 64 lanes), and the VALU issue bound,
@@ -156,11 +179,13 @@ def reduce_valu(valu_dir):
     1024 SIMDs at 2.4 GHz, against the dispatch's duration."""
     import csv
     import glob
+    D = 3 if case == "shock_droplet_3d" else 2
+    kname = stage_kernel(D)
     per = {}
     for f in glob.glob(os.path.join(valu_dir, "**", "*counter_collection.csv"), recursive=True):
         with open(f) as fh:
             for r in csv.DictReader(fh):
-                if "k_stage_lds<2, false>" not in r["Kernel_Name"]:
+                if kname not in r["Kernel_Name"]:
                     continue
                 d = per.setdefault(r["Dispatch_Id"], {})
                 d[r["Counter_Name"]] = d.get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
@@ -171,7 +196,7 @@ def reduce_valu(valu_dir):
     flops = avg["SQ_INSTS_VALU_FLOPS_FP64"] * 64
     issue_s = avg["SQ_INSTS_VALU"] * 4 / (1024 * 2.4e9)
     fp64 = sum(avg[k] for k in VALU_COUNTERS[:4])
-    rec = dict(kernel="k_stage_lds<2, false>", workload="shock_bubble_2d 1024x1024 multi_dt",
+    rec = dict(kernel=kname, workload="%s %s multi_dt" % (case, "x".join([str(n)] * D)),
                source_sha256=source_digest(), sources=KERNEL_SOURCES, dispatches=len(per),
                counters_per_dispatch={k: avg[k] for k in VALU_COUNTERS},
                duration_us_under_counters=avg["ns"] / 1e3,
@@ -180,35 +205,22 @@ def reduce_valu(valu_dir):
                valu_issue_bound_us=issue_s * 1e6,
                valu_issue_frac=issue_s * 1e9 / avg["ns"],
                command="timeout -s KILL 150 rocprofv3 --pmc " + " ".join(VALU_COUNTERS) + " --output-format csv "
-                       "-d <VALU_DIR> -o run -- python -u bench.py --steps 3 --warmup 1 --no-cpu --no-single --no-l1 "
-                       "--no-adjoint --no-batch --no-graph; python bench.py --reduce-valu <VALU_DIR>")
-    with open(VALU_RECORD, "w") as fh:
+                       "-d <VALU_DIR> -o run -- python -u bench.py %s; python bench.py --case %s --n %d "
+                       "--reduce-valu <VALU_DIR>" % (bench_args(case, n), case, n))
+    with open(record_path(case, n, "valu"), "w") as fh:
         json.dump(rec, fh, indent=1)
     print(json.dumps(rec))
 
 
-def measured_valu():
-    """the committed executed-work record, or None when the kernel sources
-    changed since the counters were taken"""
+def committed_record(case, n, what):
+    """a committed counter record of this workload, or None when the kernel
+    sources changed since the counters were taken"""
     try:
-        with open(VALU_RECORD) as fh:
+        with open(record_path(case, n, what)) as fh:
             rec = json.load(fh)
     except (OSError, ValueError):
         return None
     return rec if rec.get("source_sha256") == source_digest() else None
-
-
-def measured_traffic():
-    """bytes per launch from the committed counter record, or None when the
-    kernel sources changed since the counters were taken"""
-    try:
-        with open(COUNTERS) as fh:
-            rec = json.load(fh)
-    except (OSError, ValueError):
-        return None
-    if rec.get("source_sha256") != source_digest():
-        return None
-    return rec.get("traffic_bytes_per_launch")
 
 
 def exact_tube_1d(case, x, t):
@@ -454,13 +466,14 @@ def graph_timing(P, WL, steps=200):
     """Captured single-dt steps (opts graph=1) against the same steps issued
     launch by launch (default schedule), at a fixed step (half the first
     CFL step): 1-D water-air tubes of 400 and 4000 cells and the 2-D
-    shock-bubble case at 128^2 and 512^2.  Reports ms per step of each and checks that both reach the same
+    shock-bubble case at 128^2, 256^2 and 512^2.  Reports ms per step of each and checks that both reach the same
     state bit for bit."""
     import torch
     res = []
     for name, case in (("tube_1d 400", WL.tube_1d(n=400, seed=0)),
                        ("tube_1d 4000", WL.tube_1d(n=4000, seed=0)),
                        ("shock_bubble_2d 128x128", WL.shock_bubble_2d(n=128, seed=0)),
+                       ("shock_bubble_2d 256x256", WL.shock_bubble_2d(n=256, seed=0)),
                        ("shock_bubble_2d 512x512", WL.shock_bubble_2d(n=512, seed=0))):
         s0 = P.Sim(case)
         dt = 0.5 * min(s0.advance(1.0, P.SIM_SINGLE_DT, max_cycles=1)["last_dt"])
@@ -485,34 +498,169 @@ def graph_timing(P, WL, steps=200):
     return res
 
 
-def cpu_baseline(case_fn, seconds):
-    """The CPU oracle (single thread) on the same workload at reduced
-    resolution, scaled to cell-updates/s."""
+def cpu_worker(case_name, n, seconds):
+    """(child process) the oracle as it is, on one thread: accelerated cycles
+    of the workload at n cells per direction for about `seconds`"""
     from oracle import oracle as O
-    O.build(force=False)
-    n = 128
-    case = case_fn(n=n, seed=0)
+    from paper_1905_03917_amd import workloads as WL
+    case = getattr(WL, case_name)(n=n, seed=0)
     o = O.OracleSim(case)
     t0 = time.perf_counter()
-    cells = 0
-    cycles = 0
+    cells = cycles = 0
     while time.perf_counter() - t0 < seconds:
         st = o.advance(1.0, mode=1, max_cycles=1)
         cells += sum(st["cell_updates"])
         cycles += 1
+    print(json.dumps(dict(cells=cells, cycles=cycles, seconds=time.perf_counter() - t0)), flush=True)
+
+
+def cpu_baseline(case_name, n, seconds):
+    """The CPU oracle (plain C, one thread per process) on a bounded sample of
+    the headline workload: the same physical setup at n cells per direction,
+    accelerated cycles for about `seconds`, first alone, then in one process
+    per core of the affinity mask (at most 16, the box's CPU share) at once;
+    the aggregate of the second is the all-core rate."""
+    import subprocess
+    from oracle import oracle as O
+    O.build(force=False)
+    cores = min(len(os.sched_getaffinity(0)), 16)
+    env = dict(os.environ, OMP_NUM_THREADS="1")
+    cmd = [sys.executable, os.path.abspath(__file__), "--cpu-worker", case_name, str(n), str(seconds)]
+
+    def run(k):
+        procs = [subprocess.Popen(cmd, stdout=subprocess.PIPE, text=True, env=env) for _ in range(k)]
+        outs = [json.loads(p.communicate()[0].strip().splitlines()[-1]) for p in procs]
+        if any(p.returncode for p in procs):
+            raise RuntimeError("oracle worker failed")
+        return outs
+
+    one = run(1)[0]
+    many = run(cores)
+    agg = sum(r["cells"] / r["seconds"] for r in many)
+    cpu_model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    dims = {"shock_droplet_3d": 3, "shock_bubble_2d": 2}[case_name]
+    grid = "x".join([str(n)] * dims)
+    return dict(value=agg, unit="cell-updates/s", cores=cores, kind="oracle",
+                sample="%s at %s (same physical setup as the timed workload), accelerated cycles for %.0f s: "
+                       "one oracle process per core of the affinity mask (%d), summed; alone on one core: %.4g "
+                       "cell-updates/s (%d cycles)" % (case_name, grid, seconds, cores, one["cells"] / one["seconds"],
+                                                         one["cycles"]),
+                single_thread=one["cells"] / one["seconds"], cpu_model=cpu_model)
+
+
+def time_workload(P, case, steps, warmup, want_single=True):
+    """The accelerated cycle on `case`: `steps` timed cycles after `warmup`
+    (no kernel profiling), the original method over the same simulated
+    interval, and a re-run of the same cycles with the bulk stage's launches
+    bracketed by dispatch-stamped events (its roofline)."""
+    import torch
+    D = case["ndim"]
+    res = {}
+    sim = P.Sim(case)
+    if warmup:
+        sim.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=warmup)
+    torch.cuda.synchronize()
+    t_start = sim.advance(0.0, mode=P.SIM_MULTI_DT)["t"]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    st = sim.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=steps)
+    torch.cuda.synchronize()
     el = time.perf_counter() - t0
-    return dict(value=cells / el, unit="cell-updates/s", cores=1, kind="oracle",
-                sample="shock_bubble_2d at %dx%d (same physical setup), %d accelerated cycles in %.1f s"
-                       % (n, n, cycles, el))
+    bulk_bound, _, serial_sched = sim.tuned()
+    sim.close()
+    res.update(seconds=el, st=st, t_start=t_start, t_end=st["t"], bulk_bound=bulk_bound, serial=serial_sched,
+               value=sum(st["cell_updates"]) / el)
+    # the original method over the same simulated interval
+    if want_single:
+        s2 = P.Sim(case)
+        if t_start > 0:
+            s2.advance(t_start, mode=P.SIM_SINGLE_DT)
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        st2 = s2.advance(st["t"], mode=P.SIM_SINGLE_DT)
+        torch.cuda.synchronize()
+        el2 = time.perf_counter() - t1
+        s2.close()
+        res["single"] = dict(seconds=el2, steps=st2["cycles"], speedup=el2 / el,
+                             cell_updates=st2["cell_updates"])
+    # the same cycles again, with the bulk stage's launches timed
+    sim = P.Sim(case)
+    if warmup:
+        sim.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=warmup)
+    sim.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    stp = sim.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=steps)
+    torch.cuda.synchronize()
+    res["profiled_seconds"] = time.perf_counter() - t0
+    ms_k, launches, cells_k, first_k = sim.profile_read()
+    sim.profile(False)
+    sim.close()
+    assert stp["steps"] == st["steps"], (stp["steps"], st["steps"])
+    flops_k = first_k * stage_flops(D, True) + (cells_k - first_k) * stage_flops(D, False)
+    bytes_k = first_k * stage_bytes(D, True) + (cells_k - first_k) * stage_bytes(D, False)
+    sec_k = ms_k * 1e-3
+    res["kernel"] = dict(ms=ms_k, launches=launches, flops=flops_k, bytes=bytes_k, seconds=sec_k)
+    return res
+
+
+def roofline(case_name, n, D, k):
+    """roofline object of the bulk stage kernel from its timed launches"""
+    sec_k, launches = k["seconds"], max(k["launches"], 1)
+    ach_tf = k["flops"] / sec_k / 1e12 if sec_k > 0 else 0.0
+    ach_gbs = k["bytes"] / sec_k / 1e9 if sec_k > 0 else 0.0
+    cnt = committed_record(case_name, n, "counters")
+    roof = dict(bound="alu", achieved=round(ach_tf, 2), peak=round(FP64_VECTOR_TFLOPS, 1), unit="TFLOP/s",
+                frac=round(ach_tf / FP64_VECTOR_TFLOPS, 4),
+                traffic=round(cnt["traffic_bytes_per_launch"]) if cnt else None,
+                kernel=stage_kernel(D), launches=k["launches"], avg_ms=round(k["ms"] / launches, 4),
+                flops_per_launch=round(k["flops"] / launches),
+                algorithmic_bytes_per_launch=round(k["bytes"] / launches),
+                hbm=dict(achieved=round(ach_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                         frac=round(ach_gbs / HBM_PEAK_GBS, 4)))
+    valu = committed_record(case_name, n, "valu")
+    if valu and sec_k > 0:
+        ex_tf = valu["executed_fp64_flops_per_launch"] * k["launches"] / sec_k / 1e12
+        roof["executed"] = dict(fp64_flops_per_launch=round(valu["executed_fp64_flops_per_launch"]),
+                                achieved=round(ex_tf, 2), frac=round(ex_tf / FP64_VECTOR_TFLOPS, 4),
+                                valu_issue_bound_us=round(valu["valu_issue_bound_us"], 1),
+                                valu_issue_frac=round(valu["valu_issue_bound_us"] / (k["ms"] * 1e3 / launches), 4))
+    return roof
+
+
+def speedup_model(st, single):
+    """Eq. (speedup_ratio) of Sec. 3.1 with the measured step ratio and the
+    slow fluid's share m of the original method's work (cell-updates as the
+    proxy of work), beside the measured ratio"""
+    import math
+    S = 0 if st["steps"][0] < st["steps"][1] else 1
+    F = 1 - S
+    n = st["steps"][F] / max(st["steps"][S], 1)
+    cu = single["cell_updates"]
+    m = cu[S] / max(cu[0] + cu[1], 1)
+    nc = math.ceil(n - 1e-9)
+    pred = n / (nc - (nc - 1) * m) if nc > 0 else None
+    return dict(fast_substeps_per_cycle=n, slow_share_m=m, predicted=pred, measured=single["speedup"])
 
 
 def main():
     a = parse()
+    if a.cpu_worker:
+        cpu_worker(a.cpu_worker[0], int(a.cpu_worker[1]), float(a.cpu_worker[2]))
+        return
     if a.reduce_counters:
-        reduce_counters(*a.reduce_counters)
+        reduce_counters(*a.reduce_counters, a.case, a.n)
         return
     if a.reduce_valu:
-        reduce_valu(a.reduce_valu)
+        reduce_valu(a.reduce_valu, a.case, a.n)
         return
     if a.gpus != 1:
         print("bench.py: this build runs on one GPU only; --gpus %d is not supported" % a.gpus, file=sys.stderr)
@@ -539,73 +687,27 @@ def main():
     D = case["ndim"]
     grid_name = "x".join([str(a.n)] * D)
     print("bench: %s %s, warmup %d, steps %d" % (a.case, grid_name, a.warmup, a.steps), flush=True)
-
-    sim = P.Sim(case, autotune=1 if a.autotune else 0)
-    if a.warmup:
-        sim.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=a.warmup)
-    torch.cuda.synchronize()
-    t_start = sim.advance(0.0, mode=P.SIM_MULTI_DT)["t"]
-    sim.profile(True)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    st = sim.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=a.steps)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-    ms_k, launches, cells_k, first_k = sim.profile_read()
-    sim.profile(False)
-    t_end = st["t"]
-    updates = sum(st["cell_updates"])
-    value = updates / el
-    print("bench: multi_dt %d cycles in %.3f s, t %.3e -> %.3e, steps %s, n_last %.2f"
-          % (st["cycles"], el, t_start, t_end, st["steps"], st["last_n"]), flush=True)
-
-    # the original method over the same simulated interval
-    single = None
-    if not a.no_single:
-        s2 = P.Sim(case)
-        if t_start > 0:
-            s2.advance(t_start, mode=P.SIM_SINGLE_DT)
-        torch.cuda.synchronize()
-        t1 = time.perf_counter()
-        st2 = s2.advance(t_end, mode=P.SIM_SINGLE_DT)
-        torch.cuda.synchronize()
-        el2 = time.perf_counter() - t1
-        single = dict(seconds=el2, steps=st2["cycles"], speedup=el2 / el)
-        print("bench: single_dt %d steps in %.3f s (speedup of multi_dt %.2f)" % (st2["cycles"], el2, el2 / el),
-              flush=True)
-        s2.close()
-
-    # dominant kernel: the bulk-tile stage (FP64 VALU-bound, so its roofline is
-    # the FP64 vector peak; the HBM view of the same launches rides along)
-    flops_k = first_k * stage_flops(D, True) + (cells_k - first_k) * stage_flops(D, False)
-    bytes_k = first_k * stage_bytes(D, True) + (cells_k - first_k) * stage_bytes(D, False)
-    sec_k = ms_k * 1e-3
-    ach_tf = flops_k / sec_k / 1e12 if sec_k > 0 else 0.0
-    ach_gbs = bytes_k / sec_k / 1e9 if sec_k > 0 else 0.0
-    # the counter record belongs to the 1024^2 shock-bubble workload
-    traffic = measured_traffic() if (a.case == "shock_bubble_2d" and a.n == 1024) else None
-    roof = dict(bound="alu", achieved=round(ach_tf, 2), peak=round(FP64_VECTOR_TFLOPS, 1), unit="TFLOP/s",
-                frac=round(ach_tf / FP64_VECTOR_TFLOPS, 4),
-                traffic=round(traffic) if traffic else None,
-                kernel="k_stage_lds<%d, false>" % D if D <= 2 else "k_stage_lds3<false>", launches=launches,
-                avg_ms=round(ms_k / max(launches, 1), 4),
-                flops_per_launch=round(flops_k / max(launches, 1)),
-                algorithmic_bytes_per_launch=round(bytes_k / max(launches, 1)),
-                hbm=dict(achieved=round(ach_gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                         frac=round(ach_gbs / HBM_PEAK_GBS, 4)))
-    valu = measured_valu() if (a.case == "shock_bubble_2d" and a.n == 1024) else None
-    if valu and sec_k > 0:
-        # executed FP64 work over this run's launch durations
-        ex_tf = valu["executed_fp64_flops_per_launch"] * launches / sec_k / 1e12
-        roof["executed"] = dict(fp64_flops_per_launch=round(valu["executed_fp64_flops_per_launch"]),
-                                achieved=round(ex_tf, 2), frac=round(ex_tf / FP64_VECTOR_TFLOPS, 4),
-                                valu_issue_bound_us=round(valu["valu_issue_bound_us"], 1),
-                                valu_issue_frac=round(valu["valu_issue_bound_us"] / (ms_k * 1e3 / max(launches, 1)), 4))
-    # the benchmark simulation's streams are released before the batch (with
-    # four hardware queues per process, the batch's two streams would share
-    # one with them and stop overlapping)
-    bulk_bound, _, serial_sched = sim.tuned()
-    sim.close()
+    h = time_workload(P, case, a.steps, a.warmup, want_single=not a.no_single)
+    st, el = h["st"], h["seconds"]
+    print("bench: multi_dt %d cycles in %.3f s, t %.3e -> %.3e, steps %s, cells %s (profiled re-run %.3f s)"
+          % (st["cycles"], el, h["t_start"], h["t_end"], st["steps"], st["active_cells"], h["profiled_seconds"]),
+          flush=True)
+    single = h.get("single")
+    if single:
+        single = dict(single, speedup_model=speedup_model(st, single))
+        print("bench: single_dt %d steps in %.3f s (speedup of multi_dt %.2f)"
+              % (single["steps"], single["seconds"], single["speedup"]), flush=True)
+    roof = roofline(a.case, a.n, D, h["kernel"])
+    # the 1024^2 shock-bubble: the second workload (its own roofline)
+    w2d = None
+    if not a.no_2d and a.case != "shock_bubble_2d":
+        c2 = WL.shock_bubble_2d(n=1024, seed=0)
+        h2 = time_workload(P, c2, a.steps, a.warmup, want_single=not a.no_single)
+        w2d = dict(workload="shock_bubble_2d 1024x1024 multi_dt", value=h2["value"], unit="cell-updates/s",
+                   ms_per_step=h2["seconds"] / max(h2["st"]["cycles"], 1) * 1e3, steps_per_fluid=h2["st"]["steps"],
+                   single_dt=h2.get("single"), roofline=roofline("shock_bubble_2d", 1024, 2, h2["kernel"]))
+        print("bench: shock_bubble_2d 1024^2: %.3e cell-updates/s, %.3f ms per cycle, single_dt speedup %s"
+              % (w2d["value"], w2d["ms_per_step"], h2.get("single", {}).get("speedup")), flush=True)
     bat = None
     if not a.no_batch:
         bat = batch_timing(P, WL)
@@ -635,10 +737,12 @@ def main():
               % (adj["forward_s"], adj["backward_s"]), flush=True)
     cpu = None
     if not a.no_cpu:
-        cpu = cpu_baseline(WL.shock_bubble_2d, a.cpu_seconds)
+        cpu = cpu_baseline(a.case, 48 if D == 3 else 128, a.cpu_seconds)
+        print("bench: oracle %.3e cell-updates/s on %d cores (%.3e on one)" % (cpu["value"], cpu["cores"],
+              cpu["single_thread"]), flush=True)
     out = {
         "metric": "cell-updates/s per fluid (FP64) & %HBM roofline; multi_dt vs single_dt time @ matched L1",
-        "value": value,
+        "value": h["value"],
         "unit": "cell-updates/s",
         "n_gpus": 1,
         "steps": a.steps,
@@ -650,12 +754,14 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "%s %s multi_dt" % (a.case, grid_name), "cells": a.n ** D,
-                   "mode": "multi_dt", "rk": 3, "cfl": 0.6, "bulk_grid_bound": bulk_bound,
-                   "schedule": "serial" if serial_sched else "overlapped"},
+                   "mode": "multi_dt", "rk": 3, "cfl": 0.6, "bulk_grid_bound": h["bulk_bound"],
+                   "schedule": "serial" if h["serial"] else "overlapped"},
         "per_fluid": {("%s_cell_updates_per_s" % ("air" if case["gamma"][k] == 1.4 else "water")):
                       st["cell_updates"][k] / el for k in range(2)},
+        "cells_per_fluid": st["active_cells"],
         "steps_per_fluid": st["steps"],
         "single_dt": single,
+        "shock_bubble_2d_1024": w2d,
         "matched_l1": ml1,
         "adjoint": adj,
         "batch": bat,
