@@ -1823,23 +1823,154 @@ __global__ void __launch_bounds__(StageWG<D>::N) k_stage_lds(Dev g, int list, in
 // tile's own cells are converted once and kept in registers; LDS holds one
 // direction's region and faces (49 KB).  Same arithmetic as the 2-D kernel.
 // ---------------------------------------------------------------------------
-#ifndef SHARP_WG3
+// 256 threads (one per tile cell), three waves per SIMD.  The block size is
+// fixed: a build with 320 threads per block (one face round per direction)
+// faulted the GPU in a timing experiment, with no cause found in the code.
 #define SHARP_WG3 256
-#endif
-#ifndef SHARP_WG3_WAVES
 #define SHARP_WG3_WAVES 3
-#endif
+// LDS of one block of the 3-D stage: one direction's region (primitives,
+// energy and sound speed of the tile and its three-cell halo along that
+// direction) and the faces normal to it
+struct Stage3Lds {
+    static constexpr int TX = 8, TY = 8, TZ = 4;
+    static constexpr int RMAX = TX * TY * (TZ + 6);   // largest directional region (z)
+    static constexpr int FMAX = TX * TY * (TZ + 1);   // most faces normal to one direction (z)
+    double R[RMAX], U[RMAX], V[RMAX], W[RMAX], E[RMAX], P[RMAX], C[RMAX];
+    double F[FMAX * 5];
+};
+
+// One direction d of the 3-D stage for the tile at (ox, oy, oz): stage the
+// halo along d (the tile's own cells come from registers), compute the faces
+// normal to d, and add each cell's flux difference along d to Lr.  The
+// direction is a template parameter, so the region and face shapes, the
+// stencil stride and the normal velocity are compile-time constants.
+template <int d, bool BAND>
+__device__ __forceinline__ void stage3_dir(const Dev& g, int k, const double* in, const double* self2, int wb,
+                                           int far, int ox, int oy, int oz, int tid, bool own, bool inside,
+                                           int li, int lj, int lk, const double* Wc, const double* Uc, double cc,
+                                           double gm, double pi, double eps4, double ih, double farea, double wflux,
+                                           Stage3Lds& S, double* Lr)
+{
+    constexpr int NV = 5, NT = SHARP_WG3;
+    constexpr int TX = Stage3Lds::TX, TY = Stage3Lds::TY, TZ = Stage3Lds::TZ;
+    constexpr int RX = TX + (d == 0 ? 6 : 0), RY = TY + (d == 1 ? 6 : 0), RZ = TZ + (d == 2 ? 6 : 0);
+    constexpr int hx = d == 0 ? 3 : 0, hy = d == 1 ? 3 : 0, hz = d == 2 ? 3 : 0;
+    // the six halo layers along d: layer l < 3 is below the tile, l >= 3 above
+    constexpr int A0 = d == 0 ? TY : TX;                       // extents across d
+    constexpr int A1 = d == 2 ? TY : TZ;
+    constexpr int NH = 6 * A0 * A1;
+    for (int q = tid; q < NH; q += NT) {
+        const int a0 = q % A0, a1 = (q / A0) % A1, l = q / (A0 * A1);
+        const int od = l < 3 ? l : l + (d == 0 ? TX : (d == 1 ? TY : TZ));   // position along d in the region
+        const int rx = d == 0 ? od : a0, ry = d == 1 ? od : (d == 0 ? a0 : a1), rz = d == 2 ? od : a1;
+        const int r = rx + RX * (ry + RY * rz);
+        int c = cidx(g, ox - hx + rx, oy - hy + ry, oz - hz + rz);
+        double W[NV], U[NV];
+        load_state<3, BAND>(g, k, in, self2, wb, c, W, U, far == 1);
+        S.R[r] = W[0];
+        S.U[r] = W[1];
+        S.V[r] = W[2];
+        S.W[r] = W[3];
+        S.E[r] = U[NV - 1];
+        S.P[r] = W[NV - 1];
+        S.C[r] = csound(gm, pi, W[0], W[NV - 1]);
+    }
+    if (own) {
+        const int r = (li + hx) + RX * ((lj + hy) + RY * (lk + hz));
+        S.R[r] = Wc[0];
+        S.U[r] = Wc[1];
+        S.V[r] = Wc[2];
+        S.W[r] = Wc[3];
+        S.E[r] = Uc[NV - 1];
+        S.P[r] = Wc[NV - 1];
+        S.C[r] = cc;
+    }
+    __syncthreads();
+    // faces normal to d
+    constexpr int FX = TX + (d == 0), FY = TY + (d == 1), FZ = TZ + (d == 2);
+    constexpr int FN = FX * FY * FZ;
+    constexpr int st = d == 0 ? 1 : (d == 1 ? RX : RX * RY);
+    for (int f = tid; f < FN; f += NT) {
+        const int fx = f % FX, fy = (f / FX) % FY, fz = f / (FX * FY);
+        const int fi = ox + fx, fj = oy + fy, fk = oz + fz;
+        const int fd = d == 0 ? fi : (d == 1 ? fj : fk);
+        bool ok = (d == 0 ? fi <= g.n[0] : fi < g.n[0]) && (d == 1 ? fj <= g.n[1] : fj < g.n[1]) &&
+                  (d == 2 ? fk <= g.n[2] : fk < g.n[2]);
+        double* Fo = S.F + (size_t)f * NV;
+        double A = 1.0;
+        if (ok && BAND && !far) {
+            A = g.ap[d][fidx(g, fi, fj, fk)];
+            if (k == 1) A = 1.0 - A;
+            ok = A > 0.0;
+        }
+        if (!ok) {
+#pragma unroll
+            for (int q = 0; q < NV; q++) Fo[q] = 0.0;
+            continue;
+        }
+        // stencil m = 0..5 <-> cells -3 .. +2 along d from the face.  Density
+        // and normal velocity stay in registers; the other values are read
+        // from LDS where each component needs them (no spills at 147 VGPRs).
+        const int r0 = fx + RX * (fy + RY * fz);
+        const double* Sd = d == 0 ? S.U : (d == 1 ? S.V : S.W);
+        double rho[6], un[6];
+        double amax = 0.0;
+#pragma unroll
+        for (int m = 0; m < 6; m++) {
+            const int r = r0 + m * st;
+            rho[m] = S.R[r];
+            un[m] = Sd[r];
+            amax = fmax(amax, fabs(un[m]) + S.C[r]);
+        }
+#pragma unroll
+        for (int q = 0; q < NV; q++) {
+            const double* Sq = q == 1 ? S.U : (q == 2 ? S.V : S.W);
+            double fp[6], fm[6];
+#pragma unroll
+            for (int m = 0; m < 6; m++) {
+                const int r = r0 + m * st;
+                double Uq, Fq;
+                if (q == 0) { Uq = rho[m]; Fq = rho[m] * un[m]; }
+                else if (q == NV - 1) { const double E = S.E[r]; Uq = E; Fq = (E + S.P[r]) * un[m]; }
+                else {
+                    // momentum component along axis q-1
+                    Uq = rho[m] * Sq[r];
+                    Fq = Uq * un[m] + (q - 1 == d ? S.P[r] : 0.0);
+                }
+                fp[m] = fma(amax, Uq, Fq);
+                fm[m] = fma(-amax, Uq, Fq);
+            }
+            double Fh = weno5_q(fp[0], fp[1], fp[2], fp[3], fp[4], eps4)
+                      + weno5_q(fm[5], fm[4], fm[3], fm[2], fm[1], eps4);
+            Fo[q] = (A * (1.0 / 12.0)) * Fh;
+        }
+        if (g.bc[d] == 0 && wflux != 0.0 && (fd == 0 || fd == g.n[d])) {
+            int side = fd == 0 ? 0 : 1;
+            int o1 = d == 0 ? fj : fi, o2 = d == 2 ? fj : fk;
+            int n1 = d == 0 ? g.n[1] : g.n[0];
+            int b = g.bface_off[d][side] + o1 + n1 * o2;
+            double sgn = side == 0 ? 1.0 : -1.0;
+            for (int q = 0; q < NV; q++) g.bacc[k][(size_t)q * g.nbface + b] += sgn * wflux * farea * Fo[q];
+        }
+    }
+    __syncthreads();
+    if (inside) {
+        const int flo = li + FX * (lj + FY * lk);
+        constexpr int fs = d == 0 ? 1 : (d == 1 ? FX : FX * FY);
+#pragma unroll
+        for (int q = 0; q < NV; q++) Lr[q] += (S.F[(size_t)flo * NV + q] - S.F[(size_t)(flo + fs) * NV + q]) * ih;
+    }
+    __syncthreads();
+}
+
 template <bool BAND>
 __device__ __forceinline__ void b_stage_lds3(const VB blk, const Dev& g, int list, int k, const double* in,
                                              const double* self2, const double* base, double* out, double a, double dt,
                                              double wflux, int wb, int cfl, double* tmp)
 {
     constexpr int D = 3, NV = 5, NT = SHARP_WG3;
-    constexpr int TX = 8, TY = 8, TZ = 4, TN = TX * TY * TZ;
-    constexpr int RMAX = TX * TY * (TZ + 6);          // largest directional region (z)
-    constexpr int FMAX = TX * TY * (TZ + 1);          // most faces normal to one direction (z)
-    __shared__ double sR[RMAX], sU[RMAX], sV[RMAX], sW[RMAX], sE[RMAX], sP[RMAX], sC[RMAX];
-    __shared__ double sF[FMAX * NV];
+    constexpr int TX = Stage3Lds::TX, TY = Stage3Lds::TY, TZ = Stage3Lds::TZ, TN = TX * TY * TZ;
+    __shared__ Stage3Lds S;
     __shared__ double sMax[(NT + 63) / 64];
     __shared__ unsigned long long sCnt[(NT + 63) / 64];
     double cmax = 0.0;
@@ -1871,115 +2002,13 @@ __device__ __forceinline__ void b_stage_lds3(const VB blk, const Dev& g, int lis
         double Lr[NV];
 #pragma unroll
         for (int q = 0; q < NV; q++) Lr[q] = 0.0;
-#pragma unroll 1
-        for (int d = 0; d < (far == 2 ? 0 : D); d++) {
-            const int RX = TX + (d == 0 ? 6 : 0), RY = TY + (d == 1 ? 6 : 0), RZ = TZ + (d == 2 ? 6 : 0);
-            const int RN = RX * RY * RZ;
-            const int hx = d == 0 ? 3 : 0, hy = d == 1 ? 3 : 0, hz = d == 2 ? 3 : 0;
-            // halo cells along d (the tile's own cells come from registers)
-            for (int q = tid; q < RN; q += NT) {
-                int rx = q % RX, ry = (q / RX) % RY, rz = q / (RX * RY);
-                int od = d == 0 ? rx : (d == 1 ? ry : rz);
-                int nd = d == 0 ? RX : (d == 1 ? RY : RZ);
-                if (od >= 3 && od < nd - 3) continue;
-                int c = cidx(g, ox - hx + rx, oy - hy + ry, oz - hz + rz);
-                double W[NV], U[NV];
-                load_state<D, BAND>(g, k, in, self2, wb, c, W, U, far == 1);
-                sR[q] = W[0];
-                sU[q] = W[1];
-                sV[q] = W[2];
-                sW[q] = W[3];
-                sE[q] = U[NV - 1];
-                sP[q] = W[NV - 1];
-                sC[q] = csound(gm, pi, W[0], W[NV - 1]);
-            }
-            if (own) {
-                int r = (li + hx) + RX * ((lj + hy) + RY * (lk + hz));
-                sR[r] = Wc[0];
-                sU[r] = Wc[1];
-                sV[r] = Wc[2];
-                sW[r] = Wc[3];
-                sE[r] = Uc[NV - 1];
-                sP[r] = Wc[NV - 1];
-                sC[r] = cc;
-            }
-            __syncthreads();
-            // faces normal to d
-            const int FX = TX + (d == 0), FY = TY + (d == 1), FZ = TZ + (d == 2);
-            const int FN = FX * FY * FZ;
-            const int st = d == 0 ? 1 : (d == 1 ? RX : RX * RY);
-            for (int f = tid; f < FN; f += NT) {
-                int fx = f % FX, fy = (f / FX) % FY, fz = f / (FX * FY);
-                int fi = ox + fx, fj = oy + fy, fk = oz + fz;
-                int fd = d == 0 ? fi : (d == 1 ? fj : fk);
-                bool ok = (d == 0 ? fi <= g.n[0] : fi < g.n[0]) && (d == 1 ? fj <= g.n[1] : fj < g.n[1]) &&
-                          (d == 2 ? fk <= g.n[2] : fk < g.n[2]);
-                double* Fo = sF + (size_t)f * NV;
-                double A = 1.0;
-                if (ok && BAND && !far) {
-                    A = g.ap[d][fidx(g, fi, fj, fk)];
-                    if (k == 1) A = 1.0 - A;
-                    ok = A > 0.0;
-                }
-                if (!ok) {
-#pragma unroll
-                    for (int q = 0; q < NV; q++) Fo[q] = 0.0;
-                    continue;
-                }
-                // stencil m = 0..5 <-> cells -3 .. +2 along d from the face
-                int r0 = fx + RX * (fy + RY * fz);
-                double rho[6], vel[3][6], un[6], E[6], p[6];
-                double amax = 0.0;
-#pragma unroll
-                for (int m = 0; m < 6; m++) {
-                    int r = r0 + m * st;
-                    rho[m] = sR[r];
-                    vel[0][m] = sU[r];
-                    vel[1][m] = sV[r];
-                    vel[2][m] = sW[r];
-                    un[m] = d == 0 ? vel[0][m] : (d == 1 ? vel[1][m] : vel[2][m]);
-                    E[m] = sE[r];
-                    p[m] = sP[r];
-                    amax = fmax(amax, fabs(un[m]) + sC[r]);
-                }
-#pragma unroll
-                for (int q = 0; q < NV; q++) {
-                    double fp[6], fm[6];
-#pragma unroll
-                    for (int m = 0; m < 6; m++) {
-                        double Uq, Fq;
-                        if (q == 0) { Uq = rho[m]; Fq = rho[m] * un[m]; }
-                        else if (q == NV - 1) { Uq = E[m]; Fq = (E[m] + p[m]) * un[m]; }
-                        else {
-                            // momentum component along axis q-1
-                            const int e = q - 1;
-                            Uq = rho[m] * vel[e][m];
-                            Fq = Uq * un[m] + (e == d ? p[m] : 0.0);
-                        }
-                        fp[m] = fma(amax, Uq, Fq);
-                        fm[m] = fma(-amax, Uq, Fq);
-                    }
-                    double Fh = weno5_q(fp[0], fp[1], fp[2], fp[3], fp[4], eps4)
-                              + weno5_q(fm[5], fm[4], fm[3], fm[2], fm[1], eps4);
-                    Fo[q] = (A * (1.0 / 12.0)) * Fh;
-                }
-                if (g.bc[d] == 0 && wflux != 0.0 && (fd == 0 || fd == g.n[d])) {
-                    int side = fd == 0 ? 0 : 1;
-                    int o1 = d == 0 ? fj : fi, o2 = d == 2 ? fj : fk;
-                    int n1 = d == 0 ? g.n[1] : g.n[0];
-                    int b = g.bface_off[d][side] + o1 + n1 * o2;
-                    double sgn = side == 0 ? 1.0 : -1.0;
-                    for (int q = 0; q < NV; q++) g.bacc[k][(size_t)q * g.nbface + b] += sgn * wflux * farea * Fo[q];
-                }
-            }
-            __syncthreads();
-            if (inside) {
-                int flo = li + FX * (lj + FY * lk);
-                int fhi = flo + (d == 0 ? 1 : (d == 1 ? FX : FX * FY));
-#pragma unroll
-                for (int q = 0; q < NV; q++) Lr[q] += (sF[(size_t)flo * NV + q] - sF[(size_t)fhi * NV + q]) * ih;
-            }
-            __syncthreads();
+        if (far != 2) {
+            stage3_dir<0, BAND>(g, k, in, self2, wb, far, ox, oy, oz, tid, own, inside, li, lj, lk, Wc, Uc, cc, gm, pi,
+                                eps4, ih, farea, wflux, S, Lr);
+            stage3_dir<1, BAND>(g, k, in, self2, wb, far, ox, oy, oz, tid, own, inside, li, lj, lk, Wc, Uc, cc, gm, pi,
+                                eps4, ih, farea, wflux, S, Lr);
+            stage3_dir<2, BAND>(g, k, in, self2, wb, far, ox, oy, oz, tid, own, inside, li, lj, lk, Wc, Uc, cc, gm, pi,
+                                eps4, ih, farea, wflux, S, Lr);
         }
         // ---- cell update ----
         if (inside) {
