@@ -1839,6 +1839,35 @@ struct Stage3Lds {
     double F[FMAX * 5];
 };
 
+// Component q of the WENO5-LLF flux through the face whose stencil starts at
+// region index r0 (cells -3 .. +2 along d, stride st), times A/12.  Density
+// and normal velocity come in registers; the other values are read from LDS
+// where the component needs them.
+template <int d, int q>
+__device__ __forceinline__ double face3_comp(const Stage3Lds& S, int r0, int st, const double* rho, const double* un,
+                                             double amax, double eps4, double A)
+{
+    constexpr int NV = 5;
+    const double* Sq = q == 1 ? S.U : (q == 2 ? S.V : S.W);
+    double fp[6], fm[6];
+#pragma unroll
+    for (int m = 0; m < 6; m++) {
+        const int r = r0 + m * st;
+        double Uq, Fq;
+        if (q == 0) { Uq = rho[m]; Fq = rho[m] * un[m]; }
+        else if (q == NV - 1) { const double E = S.E[r]; Uq = E; Fq = (E + S.P[r]) * un[m]; }
+        else {
+            // momentum component along axis q-1
+            Uq = rho[m] * Sq[r];
+            Fq = Uq * un[m] + (q - 1 == d ? S.P[r] : 0.0);
+        }
+        fp[m] = fma(amax, Uq, Fq);
+        fm[m] = fma(-amax, Uq, Fq);
+    }
+    double Fh = weno5_q(fp[0], fp[1], fp[2], fp[3], fp[4], eps4) + weno5_q(fm[5], fm[4], fm[3], fm[2], fm[1], eps4);
+    return (A * (1.0 / 12.0)) * Fh;
+}
+
 // One direction d of the 3-D stage for the tile at (ox, oy, oz): stage the
 // halo along d (the tile's own cells come from registers), compute the faces
 // normal to d, and add each cell's flux difference along d to Lr.  The
@@ -1890,30 +1919,37 @@ __device__ __forceinline__ void stage3_dir(const Dev& g, int k, const double* in
     constexpr int FX = TX + (d == 0), FY = TY + (d == 1), FZ = TZ + (d == 2);
     constexpr int FN = FX * FY * FZ;
     constexpr int st = d == 0 ? 1 : (d == 1 ? RX : RX * RY);
-    for (int f = tid; f < FN; f += NT) {
+    // The face's aperture (0 when it carries no flux of fluid k) and its
+    // boundary side; the LLF speed of its six-cell stencil.
+    auto face_at = [&](int f, int& fi, int& fj, int& fk, double& A) {
         const int fx = f % FX, fy = (f / FX) % FY, fz = f / (FX * FY);
-        const int fi = ox + fx, fj = oy + fy, fk = oz + fz;
-        const int fd = d == 0 ? fi : (d == 1 ? fj : fk);
+        fi = ox + fx;
+        fj = oy + fy;
+        fk = oz + fz;
         bool ok = (d == 0 ? fi <= g.n[0] : fi < g.n[0]) && (d == 1 ? fj <= g.n[1] : fj < g.n[1]) &&
                   (d == 2 ? fk <= g.n[2] : fk < g.n[2]);
-        double* Fo = S.F + (size_t)f * NV;
-        double A = 1.0;
+        A = ok ? 1.0 : 0.0;
         if (ok && BAND && !far) {
             A = g.ap[d][fidx(g, fi, fj, fk)];
             if (k == 1) A = 1.0 - A;
-            ok = A > 0.0;
         }
-        if (!ok) {
-#pragma unroll
-            for (int q = 0; q < NV; q++) Fo[q] = 0.0;
-            continue;
+        return fx + RX * (fy + RY * fz);      // region index of stencil cell m = 0
+    };
+    auto bflux = [&](int fi, int fj, int fk, int q, double Fq) {
+        const int fd = d == 0 ? fi : (d == 1 ? fj : fk);
+        if (g.bc[d] == 0 && wflux != 0.0 && (fd == 0 || fd == g.n[d])) {
+            int side = fd == 0 ? 0 : 1;
+            int o1 = d == 0 ? fj : fi, o2 = d == 2 ? fj : fk;
+            int n1 = d == 0 ? g.n[1] : g.n[0];
+            int b = g.bface_off[d][side] + o1 + n1 * o2;
+            double sgn = side == 0 ? 1.0 : -1.0;
+            g.bacc[k][(size_t)q * g.nbface + b] += sgn * wflux * farea * Fq;
         }
-        // stencil m = 0..5 <-> cells -3 .. +2 along d from the face.  Density
-        // and normal velocity stay in registers; the other values are read
-        // from LDS where each component needs them (no spills at 147 VGPRs).
-        const int r0 = fx + RX * (fy + RY * fz);
-        const double* Sd = d == 0 ? S.U : (d == 1 ? S.V : S.W);
-        double rho[6], un[6];
+    };
+    // stencil m = 0..5 <-> cells -3 .. +2 along d from the face: density,
+    // normal velocity and the LLF speed max(|u_d| + c)
+    const double* Sd = d == 0 ? S.U : (d == 1 ? S.V : S.W);
+    auto stencil = [&](int r0, double* rho, double* un) {
         double amax = 0.0;
 #pragma unroll
         for (int m = 0; m < 6; m++) {
@@ -1922,36 +1958,60 @@ __device__ __forceinline__ void stage3_dir(const Dev& g, int k, const double* in
             un[m] = Sd[r];
             amax = fmax(amax, fabs(un[m]) + S.C[r]);
         }
+        return amax;
+    };
+    // One thread per face, all components, for the first NT faces
+    constexpr int FULL = FN < NT ? FN : NT;
+    if (tid < FULL) {
+        const int f = tid;
+        int fi, fj, fk;
+        double A;
+        const int r0 = face_at(f, fi, fj, fk, A);
+        double* Fo = S.F + (size_t)f * NV;
+        if (!(A > 0.0)) {
 #pragma unroll
-        for (int q = 0; q < NV; q++) {
-            const double* Sq = q == 1 ? S.U : (q == 2 ? S.V : S.W);
-            double fp[6], fm[6];
+            for (int q = 0; q < NV; q++) Fo[q] = 0.0;
+        } else {
+            double rho[6], un[6];
+            const double amax = stencil(r0, rho, un);
+            Fo[0] = face3_comp<d, 0>(S, r0, st, rho, un, amax, eps4, A);
+            Fo[1] = face3_comp<d, 1>(S, r0, st, rho, un, amax, eps4, A);
+            Fo[2] = face3_comp<d, 2>(S, r0, st, rho, un, amax, eps4, A);
+            Fo[3] = face3_comp<d, 3>(S, r0, st, rho, un, amax, eps4, A);
+            Fo[4] = face3_comp<d, 4>(S, r0, st, rho, un, amax, eps4, A);
 #pragma unroll
-            for (int m = 0; m < 6; m++) {
-                const int r = r0 + m * st;
-                double Uq, Fq;
-                if (q == 0) { Uq = rho[m]; Fq = rho[m] * un[m]; }
-                else if (q == NV - 1) { const double E = S.E[r]; Uq = E; Fq = (E + S.P[r]) * un[m]; }
-                else {
-                    // momentum component along axis q-1
-                    Uq = rho[m] * Sq[r];
-                    Fq = Uq * un[m] + (q - 1 == d ? S.P[r] : 0.0);
-                }
-                fp[m] = fma(amax, Uq, Fq);
-                fm[m] = fma(-amax, Uq, Fq);
+            for (int q = 0; q < NV; q++) bflux(fi, fj, fk, q, Fo[q]);
+        }
+    }
+    // The remaining FN - NT faces (32 or 64) would leave all but one wave
+    // idle for a whole face each: they are spread over the block as one
+    // thread per (face, component), 64 slots per component so that each
+    // wave works on one component (a uniform branch to the same code as
+    // above).
+    constexpr int REST = FN - FULL;
+    static_assert(REST <= 64, "at most 64 remaining faces");
+    for (int it = tid; REST > 0 && it < NV * 64; it += NT) {
+        const int q = __builtin_amdgcn_readfirstlane(it >> 6), j = it & 63;
+        if (j >= REST) continue;
+        const int f = FULL + j;
+        int fi, fj, fk;
+        double A;
+        const int r0 = face_at(f, fi, fj, fk, A);
+        double* Fo = S.F + (size_t)f * NV;
+        double Fq = 0.0;
+        if (A > 0.0) {
+            double rho[6], un[6];
+            const double amax = stencil(r0, rho, un);
+            switch (q) {
+            case 0: Fq = face3_comp<d, 0>(S, r0, st, rho, un, amax, eps4, A); break;
+            case 1: Fq = face3_comp<d, 1>(S, r0, st, rho, un, amax, eps4, A); break;
+            case 2: Fq = face3_comp<d, 2>(S, r0, st, rho, un, amax, eps4, A); break;
+            case 3: Fq = face3_comp<d, 3>(S, r0, st, rho, un, amax, eps4, A); break;
+            default: Fq = face3_comp<d, 4>(S, r0, st, rho, un, amax, eps4, A); break;
             }
-            double Fh = weno5_q(fp[0], fp[1], fp[2], fp[3], fp[4], eps4)
-                      + weno5_q(fm[5], fm[4], fm[3], fm[2], fm[1], eps4);
-            Fo[q] = (A * (1.0 / 12.0)) * Fh;
+            bflux(fi, fj, fk, q, Fq);
         }
-        if (g.bc[d] == 0 && wflux != 0.0 && (fd == 0 || fd == g.n[d])) {
-            int side = fd == 0 ? 0 : 1;
-            int o1 = d == 0 ? fj : fi, o2 = d == 2 ? fj : fk;
-            int n1 = d == 0 ? g.n[1] : g.n[0];
-            int b = g.bface_off[d][side] + o1 + n1 * o2;
-            double sgn = side == 0 ? 1.0 : -1.0;
-            for (int q = 0; q < NV; q++) g.bacc[k][(size_t)q * g.nbface + b] += sgn * wflux * farea * Fo[q];
-        }
+        Fo[q] = Fq;
     }
     __syncthreads();
     if (inside) {
