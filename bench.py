@@ -58,6 +58,9 @@ def parse():
     ap.add_argument("--batch-no-sequential", action="store_true",
                     help="with --batch-only: skip advancing the instances one at a time")
     ap.add_argument("--no-l1", action="store_true", help="skip the matched-L1 comparisons (1-D tube and 3-D droplet ladders)")
+    ap.add_argument("--paper-cases", action="store_true",
+                    help="only the paper's own cases in its RK2 scheme: the Sec. 4.1 tubes and the Sec. 4.2 droplet "
+                         "ladder (Table 1), a few minutes")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     ap.add_argument("--reduce-valu", metavar="VALU_DIR",
@@ -498,6 +501,65 @@ def graph_timing(P, WL, steps=200):
     return res
 
 
+def paper_cases(P, WL, ladder=(32, 64, 128, 256), n3=128, frac3=0.1):
+    """The paper's compressible cases in its TVD-RK2 scheme (Tait water as the
+    stiffened gas of its isentrope): the two 1-D tubes of Sec. 4.1 at 200
+    cells in both modes (relative L1 of the density against the exact
+    solution), and the Sec. 4.2 droplet over one period on 32^2 .. 256^2
+    and a tenth of a period on 128^3, timed in both modes (r_s = original
+    time / accelerated time, beside Table 1 as context), with the droplet's
+    area error E(area) = |S - 0.01 pi| / (0.01 pi) after the period and its
+    relative mass."""
+    import math
+    import numpy as np
+    import torch
+    out = dict(tubes=[], droplet=[])
+    for name in ("e1_gas_water_tube", "e2_shock_air_water"):
+        c = getattr(WL, name)(n=200)
+        x = (np.arange(200) + 0.5) / 200
+        ex = exact_tube_1d(c, x, c["t_end"])[:, 0]
+        row = dict(case=name)
+        for mode in (0, 1):
+            s = P.Sim(c, rk=2)
+            st = s.advance(c["t_end"], mode=mode)
+            _, cons, alpha = s.state(device=False)
+            s.close()
+            rho = np.where(alpha >= 0.5, cons[0, 0] / np.maximum(alpha, 1e-300),
+                           cons[1, 0] / np.maximum(1 - alpha, 1e-300))
+            row["l1_rho_%s" % ("multi" if mode else "single")] = float(np.abs(rho - ex).mean() / np.abs(ex).mean())
+            row["steps_%s" % ("multi" if mode else "single")] = st["steps"]
+        out["tubes"].append(row)
+    table1 = {32: 1.539, 64: 1.923, 128: 2.322, 256: 2.873, "128^3": 2.862}
+    for ndim, n in [(2, m) for m in ladder] + [(3, n3)]:
+        c = WL.e3_droplet(n=n, ndim=ndim)
+        t_end = c["t_end"] * (1.0 if ndim == 2 else frac3)
+        row = dict(grid="x".join([str(n)] * ndim), t_end=t_end)
+        for mode in (0, 1):
+            s = P.Sim(c, rk=2)
+            m0 = s.totals()[0, 0]
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = s.advance(t_end, mode=mode)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            key = "multi" if mode else "single"
+            row["seconds_" + key] = el
+            row["cycles_" + key] = st["cycles"]
+            row["steps_" + key] = st["steps"]
+            row["relative_mass_" + key] = float(s.totals()[0, 0] / m0)
+            if ndim == 2:
+                _, _, alpha = s.state(device=False)
+                area = float(alpha.sum()) / n ** 2
+                row["area_error_" + key] = abs(area - 0.01 * math.pi) / (0.01 * math.pi)
+            s.close()
+        row["r_s"] = row["seconds_single"] / row["seconds_multi"]
+        row["paper_r_s"] = table1[n if ndim == 2 else "128^3"]
+        out["droplet"].append(row)
+        print("bench: paper droplet %s: single %.2f s, multi %.2f s, r_s %.2f (paper, CPU: %.3f)"
+              % (row["grid"], row["seconds_single"], row["seconds_multi"], row["r_s"], row["paper_r_s"]), flush=True)
+    return out
+
+
 def cpu_worker(case_name, n, seconds):
     """(child process) the oracle as it is, on one thread: accelerated cycles
     of the workload at n cells per direction for about `seconds`"""
@@ -672,6 +734,9 @@ def main():
     torch.cuda.set_device(0)
     if a.batch_only:
         print(json.dumps({"batch": batch_timing(P, WL, one_at_a_time=not a.batch_no_sequential)}), flush=True)
+        return
+    if a.paper_cases:
+        print(json.dumps({"paper_cases": paper_cases(P, WL)}), flush=True)
         return
     if a.copy_probe:
         # a device-to-device copy of exactly 1 GiB read + 1 GiB written; a

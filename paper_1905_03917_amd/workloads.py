@@ -181,6 +181,49 @@ def vacuum_tube_1d(n=200, U=3000.0):
     return _case(1, n, 0, AIR, AIR, x - 0.5, prim, 1e30, "vacuum_tube_1d")
 
 
+# Tait water of the paper's Sec. 4.1-4.2 (B = 3310, p0 = 1, gamma 7.15,
+# non-dimensional): along an isentrope p + (B - p0) = B (rho/rho0)^gamma, the
+# stiffened gas with p_inf = B - p0
+TAIT_WATER = (7.15, 3310.0 - 1.0)
+
+
+def e1_gas_water_tube(n=200):
+    """Sec. 4.1.1 gas-water shock tube (non-dimensional): gas
+    (rho, u, p) = (0.01, 0, 1000), gamma 2, for x < 0.5 and Tait water
+    (1, 0, 1) for x > 0.5; t_end = 0.0008."""
+    h, (x,) = _grid(1, n)
+    gas = _fill(1, n, dict(rho=0.01, p=1000.0))
+    water = _fill(1, n, dict(rho=1.0, p=1.0))
+    return _case(1, n, 0, (2.0, 0.0), TAIT_WATER, x - 0.5, np.stack([gas, water]), 8.0e-4, "e1_gas_water_tube",
+                 x_interface=0.5)
+
+
+def e2_shock_air_water(n=200):
+    """Sec. 4.1.2 underwater shock hitting an air-water interface
+    (non-dimensional): shocked Tait water (1.0376, 6.0151, 1000) for
+    x < 0.7 and air (0.001, 0, 1), gamma 1.4, for x > 0.7; t_end = 0.003."""
+    h, (x,) = _grid(1, n)
+    water = _fill(1, n, dict(rho=1.0376, u=6.0151, p=1000.0))
+    air = _fill(1, n, dict(rho=0.001, p=1.0))
+    return _case(1, n, 0, TAIT_WATER, (1.4, 0.0), x - 0.7, np.stack([water, air]), 3.0e-3, "e2_shock_air_water",
+                 x_interface=0.7)
+
+
+def e3_droplet(n=64, ndim=2):
+    """Sec. 4.2 periodic translation of a water droplet (non-dimensional):
+    Tait water (rho 1000, p 1) inside radius 0.1 at the centre of the unit
+    box, air (1.2, 1), gamma 1.4, outside, both moving with u = sqrt(10)/100
+    along x; periodic; one period t_end = 10 sqrt(10)."""
+    h, grid = _grid(ndim, n)
+    r = np.sqrt(sum((g - 0.5) ** 2 for g in grid))
+    nc = n ** ndim
+    u = np.sqrt(10.0) / 100.0
+    water = _fill(ndim, nc, dict(rho=1000.0, u=u, p=1.0))
+    air = _fill(ndim, nc, dict(rho=1.2, u=u, p=1.0))
+    return _case(ndim, n, 1, TAIT_WATER, (1.4, 0.0), r - 0.1, np.stack([water, air]), 10.0 * np.sqrt(10.0),
+                 "e3_droplet_%dd" % ndim, radius=0.1)
+
+
 def wall_bubble_2d(n=64, seed=0, radius=0.2):
     """Air bubble (fluid 0) cut by the zero-gradient wall x = 0, at a higher
     pressure than the surrounding water: the interface band touches the wall,

@@ -381,3 +381,20 @@ def test_shock_bubble_2d_to_t_end(mode):
 def test_shock_droplet_3d_to_t_end(mode):
     c = WL.shock_droplet_3d(n=24, seed=9)
     _compare(c, mode, 0, t_end=3.0e-4, tol=1e-8, l1=True)
+
+
+# ---- the paper's own cases in its TVD-RK2 scheme, Tait water as the
+# stiffened gas of its isentrope: the two 1-D tubes of Sec. 4.1 to their
+# t_end (L1 1e-8) and one cycle (L-infinity 1e-10), the Sec. 4.2 droplet
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("name", ["e1_gas_water_tube", "e2_shock_air_water"])
+def test_paper_tubes_rk2(name, mode):
+    c = getattr(WL, name)(n=200)
+    _compare(c, mode, 1, rk=2)
+    _compare(c, mode, 0, t_end=c["t_end"], tol=1e-8, l1=True, rk=2)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+@pytest.mark.parametrize("ndim,n", [(2, 32), (3, 24)])
+def test_paper_droplet_rk2(ndim, n, mode):
+    _compare(WL.e3_droplet(n=n, ndim=ndim), mode, 3, rk=2)
