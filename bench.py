@@ -466,24 +466,26 @@ def batch_timing(P, WL, cycles_multi=3, steps_single=10, one_at_a_time=True):
 
 
 def graph_timing(P, WL, steps=200):
-    """Captured single-dt steps (opts graph=1) against the same steps issued
-    launch by launch (default schedule), at a fixed step (half the first
-    CFL step): 1-D water-air tubes of 400 and 4000 cells and the 2-D
-    shock-bubble case at 128^2, 256^2 and 512^2.  Reports ms per step of each and checks that both reach the same
-    state bit for bit."""
+    """Captured single-dt steps (opts graph=2: captured at any size) against
+    the same steps issued launch by launch (default schedule), at a fixed
+    step (half the first CFL step): 1-D water-air tubes of 400 and 4000 cells
+    and the 2-D shock-bubble case at 128^2 to 1024^2, which brackets the
+    largest grid graph=1 captures.  Reports ms per step of each and checks
+    that both reach the same state bit for bit."""
     import torch
     res = []
     for name, case in (("tube_1d 400", WL.tube_1d(n=400, seed=0)),
                        ("tube_1d 4000", WL.tube_1d(n=4000, seed=0)),
                        ("shock_bubble_2d 128x128", WL.shock_bubble_2d(n=128, seed=0)),
                        ("shock_bubble_2d 256x256", WL.shock_bubble_2d(n=256, seed=0)),
-                       ("shock_bubble_2d 512x512", WL.shock_bubble_2d(n=512, seed=0))):
+                       ("shock_bubble_2d 512x512", WL.shock_bubble_2d(n=512, seed=0)),
+                       ("shock_bubble_2d 1024x1024", WL.shock_bubble_2d(n=1024, seed=0))):
         s0 = P.Sim(case)
         dt = 0.5 * min(s0.advance(1.0, P.SIM_SINGLE_DT, max_cycles=1)["last_dt"])
         s0.close()
         row = dict(workload=name, dt=dt, steps=steps)
         states = []
-        for key, g in (("launches", 0), ("graph", 1)):
+        for key, g in (("launches", 0), ("graph", 2)):
             sim = P.Sim(case, dt_fixed=dt, graph=g)
             sim.advance(1.0, P.SIM_SINGLE_DT, max_cycles=4)     # warm-up (and the captures)
             torch.cuda.synchronize()

@@ -43,6 +43,11 @@
 extern "C" {
 #endif
 
+/* Largest grid (cells) on which opts->graph = 1 captures single-dt steps:
+ * 512^2, where a captured step of the 2-D shock-bubble case still measured
+ * 1.01x the launches it replaces (1.5x on a 400-cell tube). */
+#define SIM_GRAPH_MAX_CELLS 262144
+
 typedef struct sim sim_t;
 
 typedef enum {
@@ -114,7 +119,11 @@ typedef struct {
                             launches issued one by one.  Steps under a tape, a
                             batch, kernel profiling or an unfinished autotuner,
                             and a step shortened to reach t_end, are issued
-                            one by one [0] */
+                            one by one.  1: capture on grids of at most
+                            SIM_GRAPH_MAX_CELLS cells (measured faster up to
+                            there; on larger grids the bulk stages overlapped
+                            on side streams win and the steps are issued one
+                            by one); 2: capture at any size [0] */
     int no_rollback;     /* do not keep the state of the last cycle start: a
                             call that fails with SIM_ENONPHYS then leaves the
                             state of the failing step instead of rolling it

@@ -17,6 +17,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libsharp_hip.so")
 
 SIM_SINGLE_DT = 0
+SIM_GRAPH_MAX_CELLS = 262144     # largest grid opts graph=1 captures (graph=2: any size)
 SIM_MULTI_DT = 1
 
 
@@ -258,7 +259,7 @@ class Sim:
 
     def graph_info(self):
         """(single-dt steps captured into HIP graphs, steps replayed from one,
-        graphs held) under opts graph=1"""
+        graphs held) under opts graph=1 or 2"""
         c = C.c_longlong()
         r = C.c_longlong()
         n = C.c_int()

@@ -133,6 +133,7 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     if (!(o.cfl > 0.0) || o.ext_iters < 0 || o.reinit_iters < 0) { set_error("invalid options"); return SIM_EINVAL; }
     if (o.tape && o.ckpt_every < 1) { set_error("ckpt_every must be >= 1"); return SIM_EINVAL; }
     if (!(o.dt_fixed >= 0.0) || !std::isfinite(o.dt_fixed)) { set_error("dt_fixed must be >= 0"); return SIM_EINVAL; }
+    if (o.graph < 0 || o.graph > 2) { set_error("graph must be 0, 1 or 2 (got %d)", o.graph); return SIM_EINVAL; }
     if (o.graph && !(o.dt_fixed > 0.0)) { set_error("graph needs dt_fixed > 0"); return SIM_EINVAL; }
     if (o.grid_cap < 0) { set_error("grid_cap must be >= 0"); return SIM_EINVAL; }
 

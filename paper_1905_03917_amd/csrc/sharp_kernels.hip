@@ -3353,10 +3353,14 @@ struct Engine {
     // streams and the events between them ran slower than the launches it
     // replaces).  A run of whole steps is enqueued without waiting for any of
     // them: the active-cell counts are summed on the device and read back,
-    // with the error flags, once at the end of the run.
+    // with the error flags, once at the end of the run.  Under graph = 1
+    // only grids of at most SIM_GRAPH_MAX_CELLS cells are captured: above
+    // that the side-stream overlap of the bulk stages, which the graph gives
+    // up, is worth more than the launch latency it saves.
     bool graph_run_ok() const
     {
-        return s.o.graph && s.o.dt_fixed > 0.0 && !s.rec && !s.prof && !s.o.tape &&
+        const bool size_ok = s.o.graph == 2 || (s.o.graph == 1 && (long long)g.nc <= SIM_GRAPH_MAX_CELLS);
+        return size_ok && s.o.dt_fixed > 0.0 && !s.rec && !s.prof && !s.o.tape &&
                (!s.o.autotune || s.tune_cur >= Sim::NTUNE);
     }
     static void put(std::vector<unsigned char>& v, const void* p, size_t n)

@@ -38,3 +38,14 @@ def test_binding_refuses_to_run_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(P, "_lib", None)
     with pytest.raises(RuntimeError):
         P.lib()
+
+
+def test_binding_constants_match_the_header():
+    """the integer #defines of the header and the binding's copies agree"""
+    import paper_1905_03917_amd as P
+    txt = open(os.path.join(ROOT, "include", "sharp.h")).read()
+    defs = dict(re.findall(r"#define\s+(SIM_[A-Z_]+)\s+(-?\d+)\b", txt))
+    assert "SIM_GRAPH_MAX_CELLS" in defs
+    for name, val in defs.items():
+        if hasattr(P, name):
+            assert getattr(P, name) == int(val), name

@@ -90,6 +90,25 @@ def test_graph_steps_between_accelerated_cycles():
     graph.close()
 
 
+def test_graph_size_gate():
+    """graph=1 captures only grids of at most SIM_GRAPH_MAX_CELLS cells,
+    graph=2 at any size; both give the launches' state"""
+    torch, P = _mods()
+    case = WL.tube_1d(n=P.SIM_GRAPH_MAX_CELLS + 1, seed=2)
+    dt = 0.5 * _first_dt(P, case)
+    sims = [P.Sim(case, dt_fixed=dt, graph=g) for g in (0, 1, 2)]
+    for s in sims:
+        s.advance(6 * dt, P.SIM_SINGLE_DT)
+    assert sims[1].graph_info()[0] == 0 and sims[2].graph_info()[0] >= 1
+    ref = sims[0].state()
+    for s in sims[1:]:
+        assert all(torch.equal(x, y) for x, y in zip(ref, s.state()))
+    for s in sims:
+        s.close()
+    with pytest.raises(RuntimeError, match="graph must be"):
+        P.Sim(WL.tube_1d(n=300, seed=1), dt_fixed=dt, graph=3)
+
+
 def test_graph_needs_a_fixed_step():
     torch, P = _mods()
     with pytest.raises(RuntimeError, match="dt_fixed"):
