@@ -439,44 +439,21 @@ __global__ void __launch_bounds__(SHARP_WG) k_axpby(Dev g, int list, double a1, 
 // ---------------------------------------------------------------------------
 // small-cell mixing (Sec. 2.2): increments in gather form
 // ---------------------------------------------------------------------------
-template <int D>
-__device__ __forceinline__ bool mix_source(const Dev& g, const double* cur, int k, int c, double* beta, int* tgt)
-{
-    double as = alpha_k(g, k, c);
-    if (!(as < g.amix) || !(fabs(phi_at(g, cur, c)) <= g.mixb * g.h)) return false;
-    double gr[3];
-    double gm = grad_phi<D>(g, cur, c, gr);
-    if (!(gm > 0.0)) return false;
-    double dir[3] = {0.0, 0.0, 0.0};
-    int sx[3] = {1, 1, 1};
-#pragma unroll
-    for (int d = 0; d < D; d++) {
-        dir[d] = (k == 0 ? -1.0 : 1.0) * gr[d] / gm;
-        sx[d] = dir[d] < 0.0 ? -1 : 1;
-    }
-    const int nsub = (1 << D) - 1;
-    double bsum = 0.0;
-    for (int m = 1; m <= nsub; m++) {
-        int cnt = 0;
-        double prod = 1.0;
-        for (int d = 0; d < D; d++)
-            if (m & (1 << d)) { cnt++; prod *= fabs(dir[d]); }
-        // the three-axis weight |n_x n_y n_z|^(2/3) as a cube root of the square
-        double b = cnt == 1 ? prod * prod : (cnt == 2 ? prod : cbrt(prod * prod));
-        beta[m - 1] = b;
-        bsum += b;
-    }
-    int i, j, kk;
-    coords(g, c, i, j, kk);
-    for (int m = 1; m <= nsub; m++) {
-        beta[m - 1] /= bsum;
-        tgt[m - 1] = cidx(g, i + ((m & 1) ? sx[0] : 0), j + ((m & 2) ? sx[1] : 0), kk + ((m & 4) ? sx[2] : 0));
-    }
-    return true;
-}
+// A cell is a mixing source of fluid k when its volume fraction alpha_k is
+// below alpha_mix, it lies within the source band (|phi| <= mix_band h) and
+// the level-set gradient there is non-zero.  Its targets are the cells one
+// step away along the normal into fluid k: on each axis the step has the
+// sign of that normal component, and each non-empty subset of the axes gives
+// one target, weighted |n_d|^2 (one axis), |n_a n_b| (two) or
+// |n_x n_y n_z|^(2/3) (three), the weights normalised to sum to one.  The
+// two fluids' normals are opposite, so the weights are the same for both;
+// only the step signs and the source condition differ.
 
-// LDS variant: the source data (weights and targets) of every cell of the
-// tile and its one-cell halo is computed once, then gathered.
+// Waves per SIMD the mixing kernels are compiled for (at most 128 VGPRs; the
+// 3-D source table takes 36 KB of LDS, four blocks per CU).
+#define SHARP_MIX_WAVES 4
+
+// The region of a tile that mixing reads: the tile and its one-cell halo.
 template <int D> struct MixRegion;
 template <> struct MixRegion<1> { static constexpr int X = 256 + 2, Y = 1, Z = 1, N = X; };
 template <> struct MixRegion<2> { static constexpr int X = 16 + 2, Y = 16 + 2, Z = 1, N = X * Y; };
@@ -491,56 +468,67 @@ __device__ __forceinline__ void tile_origin(const Dev& g, int t, int& ox, int& o
     oz = D == 3 ? (t / (g.nt[0] * g.nt[1])) * Tile<D>::Z : 0;
 }
 
-// Mixing increment of cell c (local coordinates li, lj, lk in the tile) from
-// the sources tabulated for the tile's region: c as a source, then c as a
-// target of each distinct neighbour (z, y, x order).  val(q, cell) gives the
-// pre-mixing values.
-template <int D, typename Val>
-__device__ __forceinline__ void mix_gather(const Dev& g, int k, int c, int i, int j, int kk, int li, int lj, int lk,
-                                           const double* sBeta, const int* sTgt, const int* sCell, Val val,
-                                           const double* vc, double* dl)
+// The tile and two cells around it lie inside the grid: every cell the
+// mixing of the tile reads (region cells, their level-set neighbours, the
+// targets of region cells) is then found by index arithmetic, with no
+// boundary images and no cell reached twice.
+template <int D>
+__device__ __forceinline__ bool mix_interior(const Dev& g, int ox, int oy, int oz)
 {
-    constexpr int NV = D + 2;
+    bool in = ox >= 2 && ox + Tile<D>::X + 2 <= g.n[0];
+    if (D >= 2) in = in && oy >= 2 && oy + Tile<D>::Y + 2 <= g.n[1];
+    if (D == 3) in = in && oz >= 2 && oz + Tile<D>::Z + 2 <= g.n[2];
+    return in;
+}
+
+// Source-table code of a region cell: bit k set = source of fluid k; bit
+// 2 + 3k + d set = fluid k's step on axis d is -1.
+__device__ __forceinline__ int mix_step(int code, int k, int d)
+{
+    return (code >> (2 + 3 * k + d)) & 1 ? -1 : 1;
+}
+
+// Table entry of cell c for both fluids (0: a source of neither); the
+// weights of its targets (subset m of the axes at m - 1) go to beta.
+// phinb(d, o) is the level set at the neighbour o = +-1 along axis d.
+template <int D, typename PhiNb>
+__device__ __forceinline__ int mix_entry(const Dev& g, const double* cur, int c, PhiNb phinb, double* beta)
+{
     constexpr int NS = (1 << D) - 1;
-    constexpr int RX = MixRegion<D>::X, RY = MixRegion<D>::Y, RN = MixRegion<D>::N;
-    constexpr int HY = D >= 2 ? 1 : 0, HZ = D == 3 ? 1 : 0;
-    const int rc = (li + 1) + RX * ((lj + HY) + RY * (lk + HZ));
-    double ac = alpha_k(g, k, c);
-    for (int m = 0; m < NS; m++) {
-        int tt = sTgt[m * RN + rc];
-        double b = sBeta[m * RN + rc];
-        if (tt < 0 || !(b > 0.0) || tt == c) continue;
-        double at = alpha_k(g, k, tt);
-        if (!(ac + at > 0.0)) continue;
-        for (int q = 0; q < NV; q++) dl[q] += b * (val(q, tt) * ac - vc[q] * at) / (ac + at);
+    const double a = g.alpha[c];
+    const bool src0 = a < g.amix, src1 = 1.0 - a < g.amix;
+    if (!(src0 || src1) || !(fabs(phi_at(g, cur, c)) <= g.mixb * g.h)) return 0;
+    double gr[3];
+    double g2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        gr[d] = (phinb(d, 1) - phinb(d, -1)) / (2.0 * g.h);
+        g2 += gr[d] * gr[d];
     }
-    bool edge = i == 0 || i == g.n[0] - 1 || (D >= 2 && (j == 0 || j == g.n[1] - 1)) ||
-                (D == 3 && (kk == 0 || kk == g.n[2] - 1));
-    int seen[26];
-    int ns = 0;
-    for (int oz2 = -HZ; oz2 <= HZ; oz2++)
-        for (int oy2 = -HY; oy2 <= HY; oy2++)
-            for (int ox2 = -1; ox2 <= 1; ox2++) {
-                if (!ox2 && !oy2 && !oz2) continue;
-                int rs = rc + ox2 + RX * (oy2 + RY * oz2);
-                int sc = sCell[rs];
-                if (sc == c) continue;
-                if (edge) {
-                    bool dup = false;
-                    for (int u = 0; u < ns; u++) dup |= (seen[u] == sc);
-                    if (dup) continue;
-                    seen[ns++] = sc;
-                }
-                if (sTgt[rs] < 0) continue;     // not a source
-                double as = alpha_k(g, k, sc);
-                if (!(as + ac > 0.0)) continue;
-                for (int m = 0; m < NS; m++) {
-                    if (sTgt[m * RN + rs] != c) continue;
-                    double b = sBeta[m * RN + rs];
-                    if (!(b > 0.0)) continue;
-                    for (int q = 0; q < NV; q++) dl[q] -= b * (vc[q] * as - val(q, sc) * ac) / (as + ac);
-                }
-            }
+    const double gm = sqrt(g2);
+    if (!(gm > 0.0)) return 0;
+    int code = (src0 ? 1 : 0) | (src1 ? 2 : 0);
+    double nrm[3];
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        const double n0 = -1.0 * gr[d] / gm, n1 = 1.0 * gr[d] / gm;   // fluid 0 / fluid 1 normal
+        nrm[d] = fabs(n0);
+        if (n0 < 0.0) code |= 1 << (2 + d);
+        if (n1 < 0.0) code |= 1 << (5 + d);
+    }
+    double bsum = 0.0;
+    for (int m = 1; m <= NS; m++) {
+        int cnt = 0;
+        double prod = 1.0;
+        for (int d = 0; d < D; d++)
+            if (m & (1 << d)) { cnt++; prod *= nrm[d]; }
+        // the three-axis weight |n_x n_y n_z|^(2/3) as a cube root of the square
+        double b = cnt == 1 ? prod * prod : (cnt == 2 ? prod : cbrt(prod * prod));
+        beta[m - 1] = b;
+        bsum += b;
+    }
+    for (int m = 0; m < NS; m++) beta[m] /= bsum;
+    return code;
 }
 
 // No cell of the tile's mixing region can be a source (|phi| > the source
@@ -553,25 +541,157 @@ __device__ __forceinline__ bool mix_far(const Dev& g, int t)
     return g.tphimin[t] > (g.mixb + 2.0) * g.h;
 }
 
-// tabulate the mixing sources of the tile's region (cells outside the grid
-// map to their boundary images)
+// Source table of the tile's region for both fluids (cells outside the grid
+// hold the entry of their boundary image): sCode per region cell, and the
+// target weights of the sources at sBeta[(m - 1) * N + r].
 template <int D>
-__device__ __forceinline__ void mix_sources(const Dev& g, int k, int ox, int oy, int oz, const double* cur,
-                                            double* sBeta, int* sTgt, int* sCell)
+__device__ __forceinline__ void mix_table(const Dev& g, int ox, int oy, int oz, bool interior, const double* cur,
+                                          double* sBeta, int* sCode)
 {
     constexpr int NS = (1 << D) - 1;
     constexpr int RX = MixRegion<D>::X, RY = MixRegion<D>::Y, RN = MixRegion<D>::N;
     constexpr int HY = D >= 2 ? 1 : 0, HZ = D == 3 ? 1 : 0;
+    const int st[3] = {1, g.n[0], g.n[0] * g.n[1]};
     for (int r = threadIdx.x; r < RN; r += SHARP_WG) {
-        int rx = r % RX, ry = (r / RX) % RY, rz = r / (RX * RY);
-        int c = cidx(g, ox - 1 + rx, oy - HY + ry, oz - HZ + rz);
-        sCell[r] = c;
+        const int rx = r % RX, ry = (r / RX) % RY, rz = r / (RX * RY);
         double beta[7];
-        int tgt[7];
-        bool src = mix_source<D>(g, cur, k, c, beta, tgt);
-        for (int m = 0; m < NS; m++) {
-            sBeta[m * RN + r] = src ? beta[m] : 0.0;
-            sTgt[m * RN + r] = src ? tgt[m] : -1;
+        int code;
+        if (interior) {
+            const int c = (ox - 1 + rx) + st[1] * (oy - HY + ry) + st[2] * (oz - HZ + rz);
+            code = mix_entry<D>(g, cur, c, [&](int d, int o) { return phi_at(g, cur, c + o * st[d]); }, beta);
+        } else {
+            const int c = cidx(g, ox - 1 + rx, oy - HY + ry, oz - HZ + rz);
+            code = mix_entry<D>(g, cur, c, [&](int d, int o) { return phi_at(g, cur, nbr(g, c, d, o)); }, beta);
+        }
+        sCode[r] = code;
+        if (code)
+            for (int m = 0; m < NS; m++) sBeta[m * RN + r] = beta[m];
+    }
+}
+
+// Mixing increment of fluid k at cell c (grid coordinates i, j, kk; local
+// li, lj, lk in the tile) from the tile's source table: c as a source (its
+// targets in subset order), then c as a target of each distinct neighbour
+// (z, y, x order).  val(q, cell) gives the pre-mixing values.
+template <int D, typename Val>
+__device__ __forceinline__ void mix_gather(const Dev& g, int k, int c, int i, int j, int kk, int li, int lj, int lk,
+                                           bool interior, const double* sBeta, const int* sCode, Val val,
+                                           const double* vc, double* dl)
+{
+    constexpr int NV = D + 2;
+    constexpr int NS = (1 << D) - 1;
+    constexpr int RX = MixRegion<D>::X, RY = MixRegion<D>::Y, RN = MixRegion<D>::N;
+    constexpr int HY = D >= 2 ? 1 : 0, HZ = D == 3 ? 1 : 0;
+    const int rc = (li + 1) + RX * ((lj + HY) + RY * (lk + HZ));
+    const int kbit = 1 << k;
+    const int st[3] = {1, g.n[0], g.n[0] * g.n[1]};
+    const double ac = alpha_k(g, k, c);
+    const int cc = sCode[rc];
+    if (cc & kbit) {
+        int sx[3] = {1, 1, 1};
+        for (int d = 0; d < D; d++) sx[d] = mix_step(cc, k, d);
+        for (int m = 1; m <= NS; m++) {
+            const double b = sBeta[(m - 1) * RN + rc];
+            int tt;
+            if (interior) {
+                tt = c;
+                for (int d = 0; d < D; d++)
+                    if (m & (1 << d)) tt += sx[d] * st[d];
+            } else {
+                tt = cidx(g, i + ((m & 1) ? sx[0] : 0), j + ((m & 2) ? sx[1] : 0), kk + ((m & 4) ? sx[2] : 0));
+            }
+            if (!(b > 0.0) || tt == c) continue;
+            const double at = alpha_k(g, k, tt);
+            if (!(ac + at > 0.0)) continue;
+            for (int q = 0; q < NV; q++) dl[q] += b * (val(q, tt) * ac - vc[q] * at) / (ac + at);
+        }
+    }
+    // c as a target: first the mask of neighbours that may reach it (bit
+    // (oz + 1) * 9 + (oy + 1) * 3 + (ox + 1) for offset o, so that ascending
+    // bits follow z, y, x order), then their contributions in that order.
+    const int pos[3] = {i, j, kk};
+    int mm[3][3];     // boundary image of c's coordinate + o on each axis
+    unsigned mask = 0;
+    if (interior) {
+        // a neighbour at offset o reaches c through one subset only (the
+        // axes where o is non-zero), and only if it steps by -o on each
+#pragma unroll
+        for (int oz2 = -HZ; oz2 <= HZ; oz2++)
+#pragma unroll
+            for (int oy2 = -HY; oy2 <= HY; oy2++)
+#pragma unroll
+                for (int ox2 = -1; ox2 <= 1; ox2++) {
+                    if (!ox2 && !oy2 && !oz2) continue;
+                    const int code = sCode[rc + ox2 + RX * (oy2 + RY * oz2)];
+                    bool hit = (code & kbit) != 0;
+                    if (ox2) hit = hit && (mix_step(code, k, 0) == -ox2);
+                    if (oy2) hit = hit && (mix_step(code, k, 1) == -oy2);
+                    if (oz2) hit = hit && (mix_step(code, k, 2) == -oz2);
+                    if (hit) mask |= 1u << ((oz2 + 1) * 9 + (oy2 + 1) * 3 + (ox2 + 1));
+                }
+    } else {
+        // near the grid boundary neighbours are boundary images: a cell
+        // reached at several offsets counts once (at the first in z, y, x
+        // order) and c itself not at all.  The boundary maps act per axis,
+        // so offset o repeats an earlier one exactly when on some axis a
+        // smaller offset has the same image, and is c when every axis is.
+#pragma unroll
+        for (int d = 0; d < 3; d++)
+#pragma unroll
+            for (int o = -1; o <= 1; o++)
+                mm[d][o + 1] = d < D ? bcmap(pos[d] + o, g.n[d], g.bc[d]) : pos[d];
+#pragma unroll 1
+        for (int oz2 = -HZ; oz2 <= HZ; oz2++)
+#pragma unroll 1
+            for (int oy2 = -HY; oy2 <= HY; oy2++)
+#pragma unroll 1
+                for (int ox2 = -1; ox2 <= 1; ox2++) {
+                    if (!ox2 && !oy2 && !oz2) continue;
+                    const int off[3] = {ox2, oy2, oz2};
+                    bool self = true, repeat = false;
+#pragma unroll
+                    for (int d = 0; d < D; d++) {
+                        self = self && mm[d][off[d] + 1] == mm[d][1];
+                        for (int o = -1; o < off[d]; o++) repeat = repeat || mm[d][o + 1] == mm[d][off[d] + 1];
+                    }
+                    if (self || repeat) continue;
+                    if (sCode[rc + ox2 + RX * (oy2 + RY * oz2)] & kbit)
+                        mask |= 1u << ((oz2 + 1) * 9 + (oy2 + 1) * 3 + (ox2 + 1));
+                }
+    }
+    while (mask) {
+        const int e = __builtin_ctz(mask);
+        mask &= mask - 1;
+        const int ox2 = e % 3 - 1, oy2 = (e / 3) % 3 - 1, oz2 = e / 9 - 1;
+        const int rs = rc + ox2 + RX * (oy2 + RY * oz2);
+        int sc;
+        unsigned msub;   // bit m - 1: subset m of the neighbour's targets reaches c
+        if (interior) {
+            sc = c + ox2 * st[0] + oy2 * st[1] + oz2 * st[2];
+            msub = 1u << (((ox2 ? 1 : 0) | (oy2 ? 2 : 0) | (oz2 ? 4 : 0)) - 1);
+        } else {
+            const int code = sCode[rs];
+            const int off[3] = {ox2, oy2, oz2};
+            int sp[3] = {0, 0, 0};
+            int onto = 0, held = 0;   // axes that step onto / already hold c's coordinate
+            for (int d = 0; d < D; d++) {
+                sp[d] = mm[d][off[d] + 1];
+                if (bcmap(sp[d] + mix_step(code, k, d), g.n[d], g.bc[d]) == pos[d]) onto |= 1 << d;
+                if (sp[d] == pos[d]) held |= 1 << d;
+            }
+            sc = sp[0] + g.n[0] * (sp[1] + g.n[1] * sp[2]);
+            msub = 0;
+            for (int m = 1; m <= NS; m++)
+                if (((onto & m) | (held & ~m & NS)) == NS) msub |= 1u << (m - 1);
+        }
+        const double as = alpha_k(g, k, sc);
+        if (!(as + ac > 0.0)) continue;
+        while (msub) {
+            const int m = __builtin_ctz(msub) + 1;
+            msub &= msub - 1;
+            const double b = sBeta[(m - 1) * RN + rs];
+            if (!(b > 0.0)) continue;
+            for (int q = 0; q < NV; q++) dl[q] -= b * (vc[q] * as - val(q, sc) * ac) / (as + ac);
         }
     }
 }
@@ -585,15 +705,15 @@ __device__ __forceinline__ void b_mixdelta_lds(const VB blk, const Dev& g, int l
     constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
     constexpr int RN = MixRegion<D>::N;
     __shared__ double sBeta[NS * RN];
-    __shared__ int sTgt[NS * RN];
-    __shared__ int sCell[RN];
+    __shared__ int sCode[RN];
     const int* L = list_ptr(g, list);
     auto val = [&](int q, int c) { return cons[(size_t)q * g.nc + c]; };
     for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
         int ox, oy, oz;
         tile_origin<D>(g, L[ti], ox, oy, oz);
         const bool far = mix_far(g, L[ti]);
-        if (!far) mix_sources<D>(g, k, ox, oy, oz, cur, sBeta, sTgt, sCell);
+        const bool interior = mix_interior<D>(g, ox, oy, oz);
+        if (!far) mix_table<D>(g, ox, oy, oz, interior, cur, sBeta, sCode);
         __syncthreads();
         int li = threadIdx.x % TX, lj = (threadIdx.x / TX) % TY, lk = threadIdx.x / (TX * TY);
         int i = ox + li, j = oy + lj, kk = oz + lk;
@@ -602,7 +722,7 @@ __device__ __forceinline__ void b_mixdelta_lds(const VB blk, const Dev& g, int l
             if (g.M[c]) {
                 double vc[NV], dl[NV];
                 for (int q = 0; q < NV; q++) { vc[q] = val(q, c); dl[q] = 0.0; }
-                if (!far) mix_gather<D>(g, k, c, i, j, kk, li, lj, lk, sBeta, sTgt, sCell, val, vc, dl);
+                if (!far) mix_gather<D>(g, k, c, i, j, kk, li, lj, lk, interior, sBeta, sCode, val, vc, dl);
                 for (int q = 0; q < NV; q++) g.dmix[(size_t)q * g.nc + c] = dl[q];
             }
         }
@@ -610,7 +730,7 @@ __device__ __forceinline__ void b_mixdelta_lds(const VB blk, const Dev& g, int l
     }
 }
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_mixdelta_lds(Dev g, int list, int k, const double* cons,
+__global__ void __launch_bounds__(SHARP_WG, SHARP_MIX_WAVES) k_mixdelta_lds(Dev g, int list, int k, const double* cons,
                                                            const double* cur)
 {
     b_mixdelta_lds<D>(VB::grid(), g, list, k, cons, cur);
@@ -633,14 +753,12 @@ struct MixPart {
     int sched_theta;      // interpolation weight from the device plan: a1 = 1 - th, a2 = th
 };
 
-template <int D>
-__device__ __forceinline__ void mix_tile(const Dev& g, int t, const MixPart& P, const double* cur, double* sBeta,
-                                         int* sTgt, int* sCell)
+// the part's weights and whether it mixes (a plan-given weight of zero
+// leaves the state unmixed)
+__device__ __forceinline__ int mix_weights(const Dev& g, const MixPart& P, double& a1, double& a2)
 {
-    constexpr int NV = D + 2;
-    constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
-    const int k = P.k;
-    double a1 = P.a1, a2 = P.a2;
+    a1 = P.a1;
+    a2 = P.a2;
     int do_mix = P.do_mix;
     if (P.sched_theta) {
         double th = g.sched[SCHED_TH1];
@@ -648,68 +766,64 @@ __device__ __forceinline__ void mix_tile(const Dev& g, int t, const MixPart& P, 
         a2 = th;
         do_mix = th != 0.0;
     }
+    return do_mix;
+}
+
+// the part's cells of the tile, from a table built for the tile (when it mixes)
+template <int D>
+__device__ __forceinline__ void mix_write(const Dev& g, const MixPart& P, double a1, double a2, bool do_mix, int ox,
+                                          int oy, int oz, bool interior, const double* sBeta, const int* sCode)
+{
+    constexpr int NV = D + 2;
+    constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
     const double* s1 = P.s1;
     const double* s2 = P.s2;
     auto val = [&](int q, int c) {
         size_t e = (size_t)q * g.nc + c;
         return s2 ? a1 * s1[e] + a2 * s2[e] : s1[e];
     };
-    int ox, oy, oz;
-    tile_origin<D>(g, t, ox, oy, oz);
-    if (mix_far(g, t)) do_mix = 0;
-    if (do_mix) mix_sources<D>(g, k, ox, oy, oz, cur, sBeta, sTgt, sCell);
-    __syncthreads();
     int li = threadIdx.x % TX, lj = (threadIdx.x / TX) % TY, lk = threadIdx.x / (TX * TY);
     int i = ox + li, j = oy + lj, kk = oz + lk;
     if (i < g.n[0] && j < g.n[1] && kk < g.n[2]) {
         int c = i + g.n[0] * (j + g.n[1] * kk);
         double vc[NV], dl[NV];
         for (int q = 0; q < NV; q++) { vc[q] = val(q, c); dl[q] = 0.0; }
-        if (do_mix && g.M[c]) mix_gather<D>(g, k, c, i, j, kk, li, lj, lk, sBeta, sTgt, sCell, val, vc, dl);
+        if (do_mix && g.M[c])
+            mix_gather<D>(g, P.k, c, i, j, kk, li, lj, lk, interior, sBeta, sCode, val, vc, dl);
         for (int q = 0; q < NV; q++) P.dst[(size_t)q * g.nc + c] = vc[q] + dl[q];
     }
-    __syncthreads();
-}
-
-template <int D>
-__device__ __forceinline__ void b_mixinterp_lds(const VB blk, const Dev& g, int list, MixPart P, const double* cur)
-{
-    constexpr int NS = (1 << D) - 1;
-    constexpr int RN = MixRegion<D>::N;
-    __shared__ double sBeta[NS * RN];
-    __shared__ int sTgt[NS * RN];
-    __shared__ int sCell[RN];
-    const int* L = list_ptr(g, list);
-    for (int ti = blk.b; ti < list_count(g, list); ti += blk.n)
-        mix_tile<D>(g, L[ti], P, cur, sBeta, sTgt, sCell);
-}
-template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_mixinterp_lds(Dev g, int list, MixPart P, const double* cur)
-{
-    b_mixinterp_lds<D>(VB::grid(), g, list, P, cur);
 }
 
 // Several mixed copies of the same tiles in one launch (the parts read no
-// buffer another part writes), and optionally phi_dst = phi_src on the
-// band-mask cells (the mixing reads the level set through phi_src).
+// buffer another part writes; one source table per tile serves every part),
+// and optionally phi_dst = phi_src on the band-mask cells (the mixing reads
+// the level set through phi_src).
 template <int D>
-__device__ __forceinline__ void b_mix_parts(const VB blk, const Dev& g, int list, MixPart A, MixPart B, int nparts,
-                                            const double* cur, const double* phi_src, double* phi_dst)
+__device__ __forceinline__ void mix_parts_tiles(const VB blk, const Dev& g, int list, const MixPart& A,
+                                                const MixPart& B, int nparts, const double* cur,
+                                                const double* phi_src, double* phi_dst)
 {
     constexpr int NS = (1 << D) - 1;
     constexpr int TX = Tile<D>::X, TY = Tile<D>::Y;
     constexpr int RN = MixRegion<D>::N;
     __shared__ double sBeta[NS * RN];
-    __shared__ int sTgt[NS * RN];
-    __shared__ int sCell[RN];
+    __shared__ int sCode[RN];
+    double aA1, aA2, aB1 = 0.0, aB2 = 0.0;
+    const int mixA = mix_weights(g, A, aA1, aA2);
+    const int mixB = nparts > 1 ? mix_weights(g, B, aB1, aB2) : 0;
     const int* L = list_ptr(g, list);
     for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
-        int t = L[ti];
-        mix_tile<D>(g, t, A, cur, sBeta, sTgt, sCell);
-        if (nparts > 1) mix_tile<D>(g, t, B, cur, sBeta, sTgt, sCell);
+        const int t = L[ti];
+        int ox, oy, oz;
+        tile_origin<D>(g, t, ox, oy, oz);
+        const bool far = mix_far(g, t);
+        const bool doA = mixA && !far, doB = mixB && !far;
+        const bool interior = mix_interior<D>(g, ox, oy, oz);
+        if (doA || doB) mix_table<D>(g, ox, oy, oz, interior, cur, sBeta, sCode);
+        __syncthreads();
+        mix_write<D>(g, A, aA1, aA2, doA, ox, oy, oz, interior, sBeta, sCode);
+        if (nparts > 1) mix_write<D>(g, B, aB1, aB2, doB, ox, oy, oz, interior, sBeta, sCode);
         if (phi_dst) {
-            int ox, oy, oz;
-            tile_origin<D>(g, t, ox, oy, oz);
             int tid = threadIdx.x;
             int i = ox + tid % TX, j = oy + (tid / TX) % TY, kk = oz + tid / (TX * TY);
             if (i < g.n[0] && j < g.n[1] && kk < g.n[2]) {
@@ -717,10 +831,29 @@ __device__ __forceinline__ void b_mix_parts(const VB blk, const Dev& g, int list
                 if (g.M[c]) phi_dst[c] = phi_src[c];
             }
         }
+        __syncthreads();
     }
 }
+
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_mix_parts(Dev g, int list, MixPart A, MixPart B, int nparts,
+__device__ __forceinline__ void b_mixinterp_lds(const VB blk, const Dev& g, int list, MixPart P, const double* cur)
+{
+    mix_parts_tiles<D>(blk, g, list, P, P, 1, cur, nullptr, nullptr);
+}
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG, SHARP_MIX_WAVES) k_mixinterp_lds(Dev g, int list, MixPart P, const double* cur)
+{
+    b_mixinterp_lds<D>(VB::grid(), g, list, P, cur);
+}
+
+template <int D>
+__device__ __forceinline__ void b_mix_parts(const VB blk, const Dev& g, int list, MixPart A, MixPart B, int nparts,
+                                            const double* cur, const double* phi_src, double* phi_dst)
+{
+    mix_parts_tiles<D>(blk, g, list, A, B, nparts, cur, phi_src, phi_dst);
+}
+template <int D>
+__global__ void __launch_bounds__(SHARP_WG, SHARP_MIX_WAVES) k_mix_parts(Dev g, int list, MixPart A, MixPart B, int nparts,
                                                         const double* cur, const double* phi_src, double* phi_dst)
 {
     b_mix_parts<D>(VB::grid(), g, list, A, B, nparts, cur, phi_src, phi_dst);
