@@ -60,6 +60,11 @@ static void release(Sim& s)
     s.h_red = nullptr;
     if (s.ev_rb) (void)hipEventDestroy(s.ev_rb);
     s.ev_rb = nullptr;
+    if (s.ls_stream) (void)hipStreamDestroy(s.ls_stream);
+    if (s.ev_ls_go) (void)hipEventDestroy(s.ev_ls_go);
+    if (s.ev_ls_done) (void)hipEventDestroy(s.ev_ls_done);
+    s.ls_stream = nullptr;
+    s.ev_ls_go = s.ev_ls_done = nullptr;
     for (int k = 0; k < 2; k++) {
         if (s.side[k]) (void)hipStreamDestroy(s.side[k]);
         if (s.ev_band[k]) (void)hipEventDestroy(s.ev_band[k]);
@@ -230,7 +235,7 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
         for (int d = 0; d < 3; d++) A(g.v[b][d], d < D ? (size_t)g.nc : 1);
     A(g.M, (size_t)g.nc); A(g.nearif, (size_t)g.nc);
     A(g.tcore, (size_t)g.ntiles); A(g.tflag, (size_t)g.ntiles); A(g.tsign, (size_t)g.ntiles);
-    A(g.tphimin, (size_t)g.ntiles);
+    A(g.tphimin, (size_t)g.ntiles); A(s.tphimin_alt, (size_t)g.ntiles);
     A(g.lists, (size_t)NLISTS * g.ntiles);
     // extension stencil lists (3-D): a cell is a target of the primitive
     // extension at most once per fluid and of the velocity extension once
@@ -299,6 +304,7 @@ void sim_destroy(sim_t* h)
     for (int k = 0; k < 2; k++)
         if (h->s.side[k]) (void)hipStreamSynchronize(h->s.side[k]);
     if (h->s.snap_stream) (void)hipStreamSynchronize(h->s.snap_stream);
+    if (h->s.ls_stream) (void)hipStreamSynchronize(h->s.ls_stream);
     release(h->s);
     delete h;
 }

@@ -86,6 +86,17 @@ struct Sim {
     // kernels (and other blocks of the writing kernel) read the current one
     double* alpha_alt = nullptr;
     double* ap_alt[3] = {nullptr, nullptr, nullptr};
+    double* tphimin_alt = nullptr;     // per-tile |phi| minima of the geometry being built
+    // level-set stream: a stage's level-set chain (velocity extension,
+    // advection, reinitialisation, geometry) beside its band stage
+    hipStream_t ls_stream = nullptr;
+    hipEvent_t ev_ls_go = nullptr;     // on stream: the interaction the chain starts from
+    hipEvent_t ev_ls_done = nullptr;   // on ls_stream: end of the chain
+    bool ls_pending = false;           // stream has not yet waited for ev_ls_done
+    // the velocity extension of the last interaction, left to the level-set
+    // chain that follows it (run there, beside the band stage)
+    bool vel_deferred = false;
+    const double* vel_cur = nullptr;   // the level set that interaction saw
     int max_blocks = 2048; // grid-stride bound for tile-list kernels
     int bulk_blocks = SHARP_BULK_BLOCKS;  // the same bound for the bulk-tile stages
     // autotuner of the bulk stage's launch and of the schedule (o.autotune):
