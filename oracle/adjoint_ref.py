@@ -89,10 +89,14 @@ def rhs(U, gamma, pinf, h, bc, eps):
             return torch.narrow(x, ax, start, nf)
 
         # face f (0..n) lies between cells f-1 and f; padded index of cell j is j + 3
+        # LLF speed: the largest |u_n| + c of the six stencil cells.  The
+        # map is not differentiable where two of them tie; the derivative
+        # taken there is that of the first maximal cell in stencil order
+        # (upwind to downwind), a one-sided derivative of the max
         s = (torch.abs(un) + c)
-        amax = sl(s, 0, axis - 1)
-        for m in range(1, 6):
-            amax = torch.maximum(amax, sl(s, m, axis - 1))
+        S6 = torch.stack([sl(s, m, axis - 1) for m in range(6)], 0)
+        first = torch.argmax(S6, dim=0, keepdim=True)       # first maximal index
+        amax = torch.gather(S6, 0, first).squeeze(0)
         Fh = []
         for q in range(NV):
             fp = [0.5 * (sl(F[q], m, axis - 1) + amax * sl(Up[q], m, axis - 1)) for m in range(6)]

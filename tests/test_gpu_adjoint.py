@@ -75,6 +75,39 @@ def test_gpu_gradient_matches_reference(ndim, n, bc, rk):
         assert abs(got - want) <= 1e-9 * abs(want), (got, want)
 
 
+def test_gpu_gradient_at_exact_ties_of_the_llf_speed():
+    """Pairs of neighbouring cells with equal |u| + c (equal density and
+    pressure, velocities +-v in pairs): the LLF speed of most faces is a tie,
+    where the map is not differentiable.  Both the GPU adjoint and the
+    reference take the derivative through the first maximal stencil cell
+    (upwind to downwind), so they agree there as elsewhere."""
+    import torch
+    from oracle import adjoint_ref as R
+    n, ndim, steps = 64, 1, 3
+    c = _setup(n, ndim, 0)
+    i = np.arange(n)
+    prim = c["prim"].copy()
+    prim[0, 0] = 1.2
+    prim[0, 1] = 10.0 * ((i // 2) % 5) * np.where((i // 10) % 2 == 0, 1.0, -1.0)
+    prim[0, 2] = 1.0e5 + 5.0e3 * ((i // 4) % 3)
+    c["prim"] = prim
+    print("adjoint tie case n=%d steps=%d" % (n, steps), flush=True)
+    Jg, gp, ge, dt = _gpu_grad(c, steps, rk=3, ckpt=2)
+    prim0 = torch.tensor(c["prim"][0], requires_grad=True)
+    gam = torch.tensor(GAMMA, dtype=torch.float64, requires_grad=True)
+    pin = torch.tensor(PINF, dtype=torch.float64, requires_grad=True)
+    U, _ = R.run(prim0, gam, pin, c, 1e30, rk=3, dts=[dt] * steps)
+    p = R.pressure(U, gam, pin)
+    pr = torch.tensor(AC.probes(n, ndim))
+    J = ((p[pr] - AC.P0) ** 2).sum() / 1e6
+    J.backward()
+    ref = prim0.grad.numpy()
+    errs = [np.abs(gp[q] - ref[q]).max() / np.abs(ref[q]).max() for q in range(ndim + 2)]
+    print("relative max error per component", errs)
+    for q, err in enumerate(errs):
+        assert err <= 1e-9, (q, err)
+
+
 def test_gpu_gradient_matches_finite_differences():
     """directional derivatives of J through 10 steps on 64^2, against central
     differences of the GPU forward on the same fixed step schedule"""

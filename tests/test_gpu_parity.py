@@ -97,6 +97,16 @@ def test_tube_1d_one_cycle(n, mode):
     _compare(WL.tube_1d(n=n, seed=n), mode, 1)
 
 
+@pytest.mark.parametrize("cycles", [3, 20])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_cavitation_floor(mode, cycles):
+    """Air pulled apart at Mach 8: the interface Riemann problem lies past
+    the vacuum limit, so p* is the floor from the first cycle on (the GPU
+    solver reaches it lazily, through its Newton iterates; the oracle tests it
+    first).  Cycles before the state turns non-physical, against the oracle."""
+    _compare(WL.vacuum_tube_1d(), mode, cycles)
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_tube_1d_full_run_l1(mode):
     c = WL.tube_1d(n=400, seed=0)

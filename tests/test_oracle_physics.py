@@ -175,3 +175,40 @@ def test_riemann_stiffened_side_in_tension(oracle):
     a = oracle.riemann_sample(WL, WR, 4.4, 6e8, 1.4, 0.0, st[1] - 1e-9)
     b = oracle.riemann_sample(WL, WR, 4.4, 6e8, 1.4, 0.0, st[1] + 1e-9)
     assert a[2] == pytest.approx(b[2], rel=1e-12, abs=1e-6) and a[1] == pytest.approx(b[1], rel=1e-12)
+
+
+def test_riemann_cavitation_floor_at_the_vacuum_limit(oracle):
+    """Two rarefactions leave a vacuum when the sides separate faster than
+    2 cL/(gL - 1) + 2 cR/(gR - 1) (ideal gases; for stiffened gases the same
+    in p + p_inf): beyond that limit p* is the floor -min(p_inf) and the star
+    densities vanish; just below it p* stays above the floor and follows the
+    two-rarefaction closed form."""
+    g = 1.4
+    W = [1.0, 0.0, 1.0e5]
+    c = math.sqrt(g * W[2] / W[0])
+    lim = 2.0 * c / (g - 1.0) * 2.0          # both sides
+    for f in (1.01, 1.5, 16.0):
+        u = 0.5 * f * lim
+        st = oracle.riemann([1.0, -u, 1.0e5], [1.0, u, 1.0e5], g, 0.0, g, 0.0)
+        assert st[0] == 0.0 and st[2] == 0.0 and st[3] == 0.0, (f, st)
+    u = 0.5 * 0.99 * lim
+    WL, WR = [1.0, -u, 1.0e5], [1.0, u, 1.0e5]
+    st = oracle.riemann(WL, WR, g, 0.0, g, 0.0)
+    assert st[0] > 0.0 and st[0] == pytest.approx(_two_rarefaction_pstar(WL, WR, g), rel=1e-10)
+    # two stiffened gases with different p_inf: the floor is -min(p_inf); the
+    # side with the smaller p_inf expands to p + p_inf = 0, the other to the
+    # floor along its isentrope, and the floor is reached exactly when the
+    # separation speed reaches the sum of both rarefactions' velocity changes
+    gL, piL, gR, piR = 4.4, 6.0e8, 7.15, 3.309e8
+    rho, p = 1000.0, 1.0e5
+    cL, cR = math.sqrt(gL * (p + piL) / rho), math.sqrt(gR * (p + piR) / rho)
+    floor = -min(piL, piR)
+    duL = 2.0 * cL / (gL - 1.0) * (1.0 - ((floor + piL) / (p + piL)) ** ((gL - 1.0) / (2.0 * gL)))
+    duR = 2.0 * cR / (gR - 1.0)
+    for f, at_floor in ((1.02, True), (0.98, False)):
+        u = 0.5 * f * (duL + duR)
+        st = oracle.riemann([rho, -u, p], [rho, u, p], gL, piL, gR, piR)
+        if at_floor:
+            assert st[0] == floor and st[3] == 0.0 and st[2] > 0.0, st
+        else:
+            assert st[0] > floor and st[3] > 0.0, st
