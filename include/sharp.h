@@ -136,6 +136,17 @@ typedef struct {
                             kernels loop over the device-side list counts, so
                             results do not depend on it; for tests and
                             tuning [0] */
+    const double* dt_replay;   /* with n_dt_replay > 0: the CFL steps to take
+                            instead of the computed ones, in the order
+                            sim_schedule reports them (both fluids' at each
+                            cycle or single-dt step start, fluid 0 first; the
+                            fast fluid's at each later fast sub-step start).
+                            Copied at sim_create.  A parity run replays the
+                            other library's schedule, so that a rounding
+                            difference in a CFL step cannot change a sub-step
+                            count (a reading of Sec. 3.1's truncation test);
+                            running past the end fails with SIM_EINVAL [NULL] */
+    int64_t n_dt_replay; /* entries of dt_replay [0] */
 } sim_opts;
 
 typedef struct {
@@ -258,6 +269,13 @@ sim_status sim_backward(sim_t* s, const double* g_cons, double* g_prim0, double*
  * autotuner (opts->autotune) has finished choosing them.  Any pointer may be
  * NULL. */
 sim_status sim_tuned(sim_t* s, int* bulk_blocks, int* serial, int* done);
+
+/* The CFL steps the simulation has taken since sim_create (or replayed from
+ * opts->dt_replay), in the order described there: up to cap values are
+ * copied to the host array out, and *n (if not NULL) receives the total
+ * count.  out may be NULL to query the count.  Single-dt steps of the fixed
+ * length opts->dt_fixed take no CFL step and add nothing. */
+sim_status sim_schedule(sim_t* s, double* out, int64_t cap, int64_t* n);
 
 /* Captured steps (opts->graph): the number of single-dt steps captured into
  * HIP graphs and the number replayed from one (the capturing step included),

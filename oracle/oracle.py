@@ -35,6 +35,7 @@ class Params(C.Structure):
         ("ls_band", C.c_double), ("ext_band", C.c_double), ("mix_band", C.c_double),
         ("ext_iters", C.c_int), ("reinit_iters", C.c_int), ("weno_eps", C.c_double),
         ("force_cycle", C.c_int), ("no_correction", C.c_int),
+        ("dt_replay", C.c_void_p), ("n_dt_replay", C.c_long),
     ]
 
 
@@ -73,6 +74,8 @@ def load(path):
     L.or_destroy.argtypes = [C.c_void_p]
     L.or_set_state.argtypes = [C.c_void_p, _dp, _dp]
     L.or_advance.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_long, C.POINTER(Stats)]
+    L.or_schedule.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_long]
+    L.or_schedule.restype = C.c_long
     L.or_get_state.argtypes = [C.c_void_p, _dp, _dp, _dp]
     L.or_totals.argtypes = [C.c_void_p, _dp]
     L.or_last_error.restype = C.c_char_p
@@ -127,6 +130,13 @@ def params_from_case(case, L=None, **over):
     p.gamma[0], p.gamma[1] = case["gamma"]
     p.pinf[0], p.pinf[1] = case["pinf"]
     for k, v in over.items():
+        if k == "dt_replay":
+            # kept on the returned object until or_create has copied it
+            a = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1))
+            p._dt_replay_keep = a
+            p.dt_replay = a.ctypes.data if a.size else None
+            p.n_dt_replay = int(a.size)
+            continue
         setattr(p, k, v)
     return p
 
@@ -156,6 +166,14 @@ class OracleSim:
                                 np.ascontiguousarray(prim, dtype=np.float64).reshape(-1))
         if rc:
             raise RuntimeError(self.L.or_last_error().decode())
+
+    def schedule(self):
+        """the CFL steps taken since creation (or_schedule's order)"""
+        n = self.L.or_schedule(self.h, None, 0)
+        out = np.zeros(n)
+        if n:
+            self.L.or_schedule(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n)
+        return out
 
     def advance(self, t_end, mode=0, max_cycles=0):
         st = Stats()
@@ -261,6 +279,13 @@ def _grid_params(L, ndim, n, bc, **over):
         p.bc[d] = bc if d < ndim else 0
     p.h = 1.0 / n
     for k, v in over.items():
+        if k == "dt_replay":
+            # kept on the returned object until or_create has copied it
+            a = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1))
+            p._dt_replay_keep = a
+            p.dt_replay = a.ctypes.data if a.size else None
+            p.n_dt_replay = int(a.size)
+            continue
         setattr(p, k, v)
     return p
 

@@ -311,6 +311,10 @@ struct or_sim {
     double* dlt;          /* mixing increments */
     double bflux[2][NVMAX];
     long err_cell;
+    double* replay;       /* prescribed CFL steps (copy of P.dt_replay) */
+    long n_replay, replay_pos;
+    double* log;          /* CFL steps taken */
+    long n_log, cap_log;
 };
 
 void or_default_params(or_params* p)
@@ -340,8 +344,18 @@ or_sim* or_create(const or_params* p)
         snprintf(g_err, sizeof g_err, "invalid parameters");
         return NULL;
     }
+    if (p->n_dt_replay < 0 || (p->n_dt_replay > 0 && !p->dt_replay)) {
+        snprintf(g_err, sizeof g_err, "invalid dt_replay");
+        return NULL;
+    }
     or_sim* s = (or_sim*)calloc(1, sizeof(or_sim));
     s->P = *p;
+    s->P.dt_replay = NULL;
+    if (p->n_dt_replay > 0) {
+        s->replay = (double*)malloc(sizeof(double) * (size_t)p->n_dt_replay);
+        memcpy(s->replay, p->dt_replay, sizeof(double) * (size_t)p->n_dt_replay);
+        s->n_replay = p->n_dt_replay;
+    }
     s->D = p->ndim;
     s->NV = p->ndim + 2;
     s->nc = 1; s->nfc = 1;
@@ -389,7 +403,34 @@ void or_destroy(or_sim* s)
     free(s->alpha);
     for (int d = 0; d < 3; d++) { free(s->ap[d]); free(s->v[d]); free(s->vn[d]); }
     free(s->ps); free(s->us); free(s->M);
+    free(s->replay); free(s->log);
     free(s);
+}
+
+long or_schedule(const or_sim* s, double* out, long cap)
+{
+    for (long i = 0; out && i < s->n_log && i < cap; i++) out[i] = s->log[i];
+    return s->n_log;
+}
+
+/* The CFL step of fluid k at a (sub)step start: the prescribed one when the
+ * simulation replays a schedule; every step taken is logged.  -1 when the
+ * schedule has run out. */
+static int take_cfl(or_sim* s, double* dt)
+{
+    if (s->n_replay > 0) {
+        if (s->replay_pos >= s->n_replay) {
+            snprintf(g_err, sizeof g_err, "dt_replay exhausted after %ld steps", s->replay_pos);
+            return -1;
+        }
+        *dt = s->replay[s->replay_pos++];
+    }
+    if (s->n_log == s->cap_log) {
+        s->cap_log = s->cap_log ? 2 * s->cap_log : 64;
+        s->log = (double*)realloc(s->log, sizeof(double) * (size_t)s->cap_log);
+    }
+    s->log[s->n_log++] = *dt;
+    return 0;
 }
 
 /* ---- indexing with domain boundary conditions (no ghost storage) ---- */
@@ -1071,6 +1112,7 @@ static int prepare(or_sim* s, double* dt, long* cnt)
     interaction(s);
     extend_v(s);
     cfl_dt(s, dt, cnt);
+    if (take_cfl(s, &dt[0]) || take_cfl(s, &dt[1])) return -2;
     return 0;
 }
 
@@ -1207,6 +1249,7 @@ static int cycle(or_sim* s, const double* dt, const long* cnt, double t_end, or_
             interaction(s);
             extend_v(s);
             cfl_dt(s, d2, c2);
+            if (take_cfl(s, &d2[F])) return -2;
             dtF = d2[F];
             cntF = c2[F];
             if (!isfinite(dtF) || !(dtF > 0.0)) {

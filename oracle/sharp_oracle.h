@@ -45,6 +45,9 @@ typedef struct {
     double weno_eps;     /* WENO epsilon (1e-6) */
     int force_cycle;     /* test hook: run the accelerated cycle even when n < 2 */
     int no_correction;   /* test hook: skip the interfacial flux correction */
+    const double* dt_replay;  /* n_dt_replay > 0: CFL steps taken instead of the
+                                 computed ones, in or_schedule's order (copied) */
+    long n_dt_replay;
 } or_params;
 
 typedef struct {
@@ -65,6 +68,12 @@ int or_set_state(or_sim* s, const double* phi, const double* prim);
 /* mode 0 single_dt (the original method), 1 multi_dt (the accelerated one).
  * Stops at t_end or after max_cycles cycles/steps (if > 0). */
 int or_advance(or_sim* s, double t_end, int mode, long max_cycles, or_stats* st);
+
+/* CFL steps taken since or_create, in the order they were taken: both
+ * fluids' (fluid 0 first) at each cycle or single-dt step start, the fast
+ * fluid's at each later fast sub-step start (the order dt_replay follows).
+ * Copies up to cap values to out (may be NULL); returns the total count. */
+long or_schedule(const or_sim* s, double* out, long cap);
 void or_get_state(const or_sim* s, double* phi, double* cons, double* alpha);
 /* total content sum_c dV * cons[k][q][c]  -> out[k*5+q] */
 void or_totals(const or_sim* s, double* out);

@@ -141,6 +141,15 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     if (o.graph < 0 || o.graph > 2) { set_error("graph must be 0, 1 or 2 (got %d)", o.graph); return SIM_EINVAL; }
     if (o.graph && !(o.dt_fixed > 0.0)) { set_error("graph needs dt_fixed > 0"); return SIM_EINVAL; }
     if (o.grid_cap < 0) { set_error("grid_cap must be >= 0"); return SIM_EINVAL; }
+    if (o.n_dt_replay < 0 || (o.n_dt_replay > 0 && !o.dt_replay)) {
+        set_error("dt_replay needs n_dt_replay >= 0 values");
+        return SIM_EINVAL;
+    }
+    for (int64_t i = 0; i < o.n_dt_replay; i++)
+        if (!(o.dt_replay[i] > 0.0)) {   // +inf: a fluid that holds no cell
+            set_error("dt_replay[%lld] = %g is not a positive step", (long long)i, o.dt_replay[i]);
+            return SIM_EINVAL;
+        }
 
     int device = -1;
     if (hipGetDevice(&device) != hipSuccess) { set_error("hipGetDevice failed"); return SIM_EDEVICE; }
@@ -152,6 +161,8 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     Sim& s = h->s;
     s.o = o;
     s.device = device;
+    if (o.n_dt_replay > 0) s.dt_replay.assign(o.dt_replay, o.dt_replay + o.n_dt_replay);
+    s.o.dt_replay = nullptr;   // the copy is used; the caller's buffer need not outlive the call
     // 3-D bulk lists are long (the slow fluid fills most of the grid): a
     // larger grid bound measured faster there (the autotuner's choice at 256^3)
     if (D == 3) s.bulk_blocks = 4 * SHARP_BULK_BLOCKS;
@@ -430,6 +441,16 @@ sim_status sim_tuned(sim_t* h, int* bulk_blocks, int* serial, int* done)
     if (bulk_blocks) *bulk_blocks = s.bulk_blocks;
     if (serial) *serial = (s.o.serial || s.run_serial) ? 1 : 0;
     if (done) *done = s.o.autotune ? (s.tune_cur >= Sim::NTUNE) : 1;
+    return SIM_OK;
+}
+
+sim_status sim_schedule(sim_t* h, double* out, int64_t cap, int64_t* n)
+{
+    if (!h || cap < 0 || (cap > 0 && !out)) { set_error("bad arguments"); return SIM_EINVAL; }
+    const std::vector<double>& v = h->s.dt_log;
+    const int64_t m = (int64_t)v.size();
+    for (int64_t i = 0; i < m && i < cap; i++) out[i] = v[(size_t)i];
+    if (n) *n = m;
     return SIM_OK;
 }
 

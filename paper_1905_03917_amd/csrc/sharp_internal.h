@@ -95,6 +95,9 @@ struct Sim {
     bool ls_pending = false;           // stream has not yet waited for ev_ls_done
     // the velocity extension of the last interaction, left to the level-set
     // chain that follows it (run there, beside the band stage)
+    std::vector<double> dt_log;        // CFL steps taken (sim_schedule)
+    std::vector<double> dt_replay;     // prescribed CFL steps (opts.dt_replay)
+    size_t replay_pos = 0;
     bool vel_deferred = false;
     const double* vel_cur = nullptr;   // the level set that interaction saw
     int max_blocks = 2048; // grid-stride bound for tile-list kernels

@@ -3516,6 +3516,24 @@ struct Engine {
         }
         return SIM_OK;
     }
+    // The CFL steps of a (sub)step start (fluid 0 before fluid 1): the
+    // prescribed ones when the simulation replays a schedule; every step
+    // taken goes to the schedule log
+    sim_status take_cfl(int which, double* dt)
+    {
+        for (int k = 0; k < 2; k++) {
+            if (!(which & (1 << k))) continue;
+            if (!s.dt_replay.empty()) {
+                if (s.replay_pos >= s.dt_replay.size()) {
+                    set_error("dt_replay exhausted after %zu steps", s.replay_pos);
+                    return SIM_EINVAL;
+                }
+                dt[k] = s.dt_replay[s.replay_pos++];
+            }
+            s.dt_log.push_back(dt[k]);
+        }
+        return SIM_OK;
+    }
     void take_counts()
     {
         const int* cc = reinterpret_cast<const int*>(s.h_red + RED_COUNTS);
@@ -3848,7 +3866,7 @@ struct Engine {
         };
         // sub-steps after the first are planned on the device when every
         // kernel of a stage can take its step from there
-        const bool plan_dev = fused_ls();
+        const bool plan_dev = fused_ls() && s.dt_replay.empty();
         for (;;) {
             int hh = 0, fin = 0, q0 = 0;
             double dl = 0.0;
@@ -3882,6 +3900,7 @@ struct Engine {
                     if (rc != SIM_OK) return rc;
                     const double* sc = reinterpret_cast<const double*>(s.h_red + RED_SCHED);
                     dtF = sc[SCHED_DTF];
+                    s.dt_log.push_back(dtF);
                     cntF = (long long)sc[SCHED_CNT];
                     dl = sc[SCHED_DT];
                     hh = sc[SCHED_HH] != 0.0;
@@ -3891,6 +3910,7 @@ struct Engine {
                     double d2[2];
                     long long c2[2];
                     sim_status rc = readback(1 << F, d2, c2);
+                    if (rc == SIM_OK) rc = take_cfl(1 << F, d2);
                     if (rc != SIM_OK) return rc;
                     dtF = d2[F];
                     cntF = c2[F];
@@ -3967,6 +3987,9 @@ struct Engine {
             double dt[2];
             long long cnt[2];
             rc = prepare(true, dt, cnt);
+            if (rc != SIM_OK) break;
+            // CFL steps (not for single-dt steps of the fixed length)
+            if (!(mode == SIM_SINGLE_DT && s.o.dt_fixed > 0.0)) rc = take_cfl(3, dt);
             if (rc != SIM_OK) break;
             rc = snap_begin(st);
             if (rc != SIM_OK) break;

@@ -107,6 +107,56 @@ def test_cavitation_floor(mode, cycles):
     _compare(WL.vacuum_tube_1d(), mode, cycles)
 
 
+@pytest.mark.parametrize("name,n,mode,cycles", [("shock_bubble_2d", 48, 1, 3), ("shock_bubble_2d", 48, 0, 4),
+                                                ("shock_droplet_3d", 20, 1, 2), ("tube_1d", 300, 1, 4)])
+def test_schedule_replay(name, n, mode, cycles):
+    """dt_replay in both directions: the oracle replays the GPU's schedule,
+    the GPU replays the oracle's, each reaching the other's state at the
+    parity bar; and the GPU replaying its own schedule (host-planned sub-steps
+    instead of device-planned ones in 1-D/2-D) gives the same bits."""
+    from oracle import oracle as O
+    case = getattr(WL, name)(n=n, seed=3)
+    print("schedule replay case=%s n=%d mode=%d" % (name, n, mode), flush=True)
+    g = _gpu(case)
+    sg = g.advance(1.0, mode=mode, max_cycles=cycles)
+    sch_g = g.schedule()
+    o = O.OracleSim(case)
+    so = o.advance(1.0, mode=mode, max_cycles=cycles)
+    sch_o = o.schedule()
+    assert len(sch_g) == len(sch_o) and sg["steps"] == so["steps"]
+    # the CFL steps of the two libraries differ where the star-state speeds
+    # of cut cells set them: the Riemann solver's root is fixed to ~1e-10
+    # relative (its stopping tolerance), which is why the schedule is replayed
+    np.testing.assert_allclose(sch_g, sch_o, rtol=1e-9)
+    D = case["ndim"]
+    # the oracle on the GPU's schedule
+    o2 = O.OracleSim(case, dt_replay=sch_g)
+    s2 = o2.advance(1.0, mode=mode, max_cycles=cycles)
+    assert s2["steps"] == sg["steps"] and s2["t"] == sg["t"]
+    e, _ = _worst(g.state(device=False)[1], o2.state()[1], D)
+    assert e <= 1e-10, e
+    # the GPU on the oracle's schedule
+    g2 = _gpu(case, dt_replay=sch_o)
+    s3 = g2.advance(1.0, mode=mode, max_cycles=cycles)
+    assert s3["steps"] == so["steps"] and s3["t"] == so["t"]
+    e, _ = _worst(g2.state(device=False)[1], o.state()[1], D)
+    assert e <= 1e-10, e
+    # the GPU on its own schedule
+    g3 = _gpu(case, dt_replay=sch_g)
+    s4 = g3.advance(1.0, mode=mode, max_cycles=cycles)
+    assert s4["steps"] == sg["steps"] and s4["t"] == sg["t"]
+    for x, y in zip(g.state(device=False), g3.state(device=False)):
+        assert np.array_equal(x, y)
+    assert np.array_equal(g3.schedule(), sch_g)
+    # past the end of the schedule
+    with pytest.raises(RuntimeError, match="dt_replay exhausted"):
+        g3.advance(1.0, mode=mode, max_cycles=1)
+    with pytest.raises(RuntimeError, match="not a positive step"):
+        _gpu(case, dt_replay=np.array([1e-6, -1.0]))
+    for s in (g, g2, g3):
+        s.close()
+
+
 @pytest.mark.parametrize("mode", [0, 1])
 def test_tube_1d_full_run_l1(mode):
     c = WL.tube_1d(n=400, seed=0)

@@ -119,3 +119,37 @@ def test_multi_dt_takes_fewer_slow_steps(oracle):
     o2 = oracle.OracleSim(c)
     s2 = o2.advance(c["t_end"], mode=0)
     assert st["steps"][1] < s2["steps"][1] / 2.5
+
+
+def test_replayed_schedule():
+    """dt_replay: the run takes the prescribed CFL steps in schedule order
+    (both fluids at a cycle or step start, the fast fluid at each later
+    sub-step start).  Replaying a run's own schedule gives the same bits; a
+    prescribed single-dt schedule is followed step by step; running past its
+    end is an error."""
+    import numpy as np
+    from oracle import oracle as O
+    from paper_1905_03917_amd import workloads as WL
+    c = WL.shock_bubble_2d(n=40, seed=2)
+    for mode, cycles in ((1, 3), (0, 5)):
+        a = O.OracleSim(c)
+        sa = a.advance(1.0, mode=mode, max_cycles=cycles)
+        sch = a.schedule()
+        expect = cycles * 2 + (sum(sa["steps"]) - 2 * cycles if mode == 1 else 0)
+        assert len(sch) == expect, (mode, len(sch), sa["steps"])
+        b = O.OracleSim(c, dt_replay=sch)
+        sb = b.advance(1.0, mode=mode, max_cycles=cycles)
+        assert sb["steps"] == sa["steps"] and sb["t"] == sa["t"]
+        for x, y in zip(a.state(), b.state()):
+            assert np.array_equal(x, y)
+        assert np.array_equal(b.schedule(), sch)
+    # single-dt: each step takes the smaller of the pair it is given
+    d = np.array([3e-7, 2e-7, 1e-7, 4e-7, 2.5e-7, 2.5e-7])
+    s = O.OracleSim(c, dt_replay=d)
+    t = 0.0
+    for k in range(3):
+        st = s.advance(1.0, mode=0, max_cycles=1)
+        t += min(d[2 * k], d[2 * k + 1])
+        assert st["t"] == t
+    with pytest.raises(RuntimeError, match="dt_replay exhausted"):
+        s.advance(1.0, mode=0, max_cycles=1)
