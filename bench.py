@@ -68,6 +68,9 @@ def parse():
     ap.add_argument("--reduce-counters", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
                     help="reduce two rocprofv3 --pmc runs (FETCH_SIZE, WRITE_SIZE) of "
                          "'bench.py --copy-probe' into the traffic record of --case/--n, then exit")
+    ap.add_argument("--kernel-traffic", nargs=2, metavar=("FETCH_DIR", "WRITE_DIR"),
+                    help="print the measured HBM traffic and achieved bandwidth of every kernel of the same two "
+                         "rocprofv3 --pmc runs (markdown table), then exit")
     a = ap.parse_args()
     if a.n is None:
         a.n = 256 if a.case == "shock_droplet_3d" else 1024
@@ -172,6 +175,52 @@ def reduce_counters(fetch_dir, write_dir, case, n):
 
 VALU_COUNTERS = ["SQ_INSTS_VALU_FMA_F64", "SQ_INSTS_VALU_ADD_F64", "SQ_INSTS_VALU_MUL_F64", "SQ_INSTS_VALU_TRANS_F64",
                  "SQ_INSTS_VALU_FLOPS_FP64", "SQ_INSTS_VALU", "SQ_ACTIVE_INST_VALU", "SQ_WAVE_CYCLES"]
+
+
+def kernel_traffic(fetch_dir, write_dir, top=24):
+    """Measured HBM traffic of every kernel in the FETCH_SIZE and WRITE_SIZE
+    passes (each scaled by what it reads for the 1 GiB copy of --copy-probe)
+    and the bandwidth it achieves over its duration under the counters (the
+    profiler runs the dispatches one at a time), as a markdown table."""
+    import csv
+    import glob
+
+    def read(d, counter):
+        per, dur = {}, {}
+        for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+            with open(f) as fh:
+                for r in csv.DictReader(fh):
+                    if r["Counter_Name"] != counter:
+                        continue
+                    name = r["Kernel_Name"].split("(")[0].replace("void ", "").replace("sharp::", "")
+                    key = (r["Dispatch_Id"], name)
+                    per[key] = per.get(key, 0.0) + float(r["Counter_Value"])
+                    dur[key] = int(r["End_Timestamp"]) - int(r["Start_Timestamp"])
+        return per, dur
+
+    copy_kib = COPY_PROBE_BYTES / 1024.0
+    fe, fd = read(fetch_dir, "FETCH_SIZE")
+    wr, _ = read(write_dir, "WRITE_SIZE")
+    sf = copy_kib / max(v for (i, k), v in fe.items() if "copybuffer" in k.lower())
+    sw = copy_kib / max(v for (i, k), v in wr.items() if "copybuffer" in k.lower())
+    agg = {}
+    for (i, k), v in fe.items():
+        if k.startswith("__amd") or k.startswith("at::"):
+            continue
+        a = agg.setdefault(k, [0, 0.0, 0.0, 0])
+        a[0] += 1
+        a[1] += v * sf * 1024.0
+        a[3] += fd[(i, k)]
+    for (i, k), v in wr.items():
+        if k in agg:
+            agg[k][2] += v * sw * 1024.0
+    rows = sorted(agg.items(), key=lambda kv: -kv[1][3])
+    print("| kernel | dispatches | avg us | read MB | written MB | GB/s | of 8 TB/s |")
+    print("|---|---:|---:|---:|---:|---:|---:|")
+    for k, (n, fb, wb, ns) in rows[:top]:
+        gbs = (fb + wb) / ns if ns else 0.0
+        print("| `%s` | %d | %.1f | %.2f | %.2f | %.0f | %.1f%% |" % (k, n, ns / n / 1e3, fb / n / 1e6, wb / n / 1e6,
+                                                                     gbs, gbs / HBM_PEAK_GBS * 100.0))
 
 
 def reduce_valu(valu_dir, case, n):
@@ -720,6 +769,9 @@ def main():
     a = parse()
     if a.cpu_worker:
         cpu_worker(a.cpu_worker[0], int(a.cpu_worker[1]), float(a.cpu_worker[2]))
+        return
+    if a.kernel_traffic:
+        kernel_traffic(*a.kernel_traffic)
         return
     if a.reduce_counters:
         reduce_counters(*a.reduce_counters, a.case, a.n)
