@@ -632,7 +632,7 @@ def cpu_baseline(case_name, n, seconds):
     """The CPU oracle (plain C, one thread per process) on a bounded sample of
     the headline workload: the same physical setup at n cells per direction,
     accelerated cycles for about `seconds`, first alone, then in one process
-    per core of the affinity mask (at most 16, the box's CPU share) at once;
+    per core of the affinity mask (at most 16, one GPU's share of the host) at once;
     the aggregate of the second is the all-core rate."""
     import subprocess
     from oracle import oracle as O

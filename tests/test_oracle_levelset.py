@@ -303,8 +303,9 @@ def check_cfl_tube(O, L):
 # ------------------------------------------------------------ the pins ----
 
 def test_star_state_values():
-    """the independent star state against the survey's bisection values for
-    the gas-water tube: p* ~ 1.419e7 Pa, u* ~ 482.6 m/s"""
+    """the independent star state against the gas-water tube's star state
+    found by bisection of the pressure function: p* ~ 1.419e7 Pa,
+    u* ~ 482.6 m/s"""
     ps, us, _, _ = _star_state()
     assert ps == pytest.approx(1.419e7, rel=2e-3) and us == pytest.approx(482.6, rel=2e-3)
 
