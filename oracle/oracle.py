@@ -36,6 +36,7 @@ class Params(C.Structure):
         ("ext_iters", C.c_int), ("reinit_iters", C.c_int), ("weno_eps", C.c_double),
         ("force_cycle", C.c_int), ("no_correction", C.c_int),
         ("dt_replay", C.c_void_p), ("n_dt_replay", C.c_long),
+        ("log_levelset", C.c_int), ("ls_replay", C.c_void_p), ("n_ls_replay", C.c_long),
     ]
 
 
@@ -76,6 +77,8 @@ def load(path):
     L.or_advance.argtypes = [C.c_void_p, C.c_double, C.c_int, C.c_long, C.POINTER(Stats)]
     L.or_schedule.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_long]
     L.or_schedule.restype = C.c_long
+    L.or_levelset_log.argtypes = [C.c_void_p, C.POINTER(C.c_double), C.c_long]
+    L.or_levelset_log.restype = C.c_long
     L.or_get_state.argtypes = [C.c_void_p, _dp, _dp, _dp]
     L.or_totals.argtypes = [C.c_void_p, _dp]
     L.or_last_error.restype = C.c_char_p
@@ -129,16 +132,21 @@ def params_from_case(case, L=None, **over):
     p.h = case["h"]
     p.gamma[0], p.gamma[1] = case["gamma"]
     p.pinf[0], p.pinf[1] = case["pinf"]
+    _apply(p, over)
+    return p
+
+
+def _apply(p, over):
+    """set parameter fields; the replayed arrays are kept on the returned
+    object until or_create has copied them"""
     for k, v in over.items():
-        if k == "dt_replay":
-            # kept on the returned object until or_create has copied it
+        if k in ("dt_replay", "ls_replay"):
             a = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1))
-            p._dt_replay_keep = a
-            p.dt_replay = a.ctypes.data if a.size else None
-            p.n_dt_replay = int(a.size)
+            setattr(p, "_%s_keep" % k, a)
+            setattr(p, k, a.ctypes.data if a.size else None)
+            setattr(p, "n_" + k, int(a.size))
             continue
         setattr(p, k, v)
-    return p
 
 
 class OracleSim:
@@ -174,6 +182,14 @@ class OracleSim:
         if n:
             self.L.or_schedule(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n)
         return out
+
+    def levelset_log(self):
+        """the level sets of every single-dt stage (log_levelset), [stages, cells]"""
+        n = self.L.or_levelset_log(self.h, None, 0)
+        out = np.zeros(n)
+        if n:
+            self.L.or_levelset_log(self.h, out.ctypes.data_as(C.POINTER(C.c_double)), n)
+        return out.reshape(-1, self.nc)
 
     def advance(self, t_end, mode=0, max_cycles=0):
         st = Stats()
@@ -278,15 +294,7 @@ def _grid_params(L, ndim, n, bc, **over):
         p.lo[d] = 0.0
         p.bc[d] = bc if d < ndim else 0
     p.h = 1.0 / n
-    for k, v in over.items():
-        if k == "dt_replay":
-            # kept on the returned object until or_create has copied it
-            a = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1))
-            p._dt_replay_keep = a
-            p.dt_replay = a.ctypes.data if a.size else None
-            p.n_dt_replay = int(a.size)
-            continue
-        setattr(p, k, v)
+    _apply(p, over)
     return p
 
 

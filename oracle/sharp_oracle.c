@@ -315,6 +315,10 @@ struct or_sim {
     long n_replay, replay_pos;
     double* log;          /* CFL steps taken */
     long n_log, cap_log;
+    double* ls_rep;       /* prescribed stage level sets (copy of P.ls_replay) */
+    long n_ls_rep, ls_pos;
+    double* lslog;        /* stage level sets taken (P.log_levelset) */
+    long n_lslog, cap_lslog;
 };
 
 void or_default_params(or_params* p)
@@ -348,13 +352,23 @@ or_sim* or_create(const or_params* p)
         snprintf(g_err, sizeof g_err, "invalid dt_replay");
         return NULL;
     }
+    if (p->n_ls_replay < 0 || (p->n_ls_replay > 0 && !p->ls_replay)) {
+        snprintf(g_err, sizeof g_err, "invalid ls_replay");
+        return NULL;
+    }
     or_sim* s = (or_sim*)calloc(1, sizeof(or_sim));
     s->P = *p;
     s->P.dt_replay = NULL;
+    s->P.ls_replay = NULL;
     if (p->n_dt_replay > 0) {
         s->replay = (double*)malloc(sizeof(double) * (size_t)p->n_dt_replay);
         memcpy(s->replay, p->dt_replay, sizeof(double) * (size_t)p->n_dt_replay);
         s->n_replay = p->n_dt_replay;
+    }
+    if (p->n_ls_replay > 0) {
+        s->ls_rep = (double*)malloc(sizeof(double) * (size_t)p->n_ls_replay);
+        memcpy(s->ls_rep, p->ls_replay, sizeof(double) * (size_t)p->n_ls_replay);
+        s->n_ls_rep = p->n_ls_replay;
     }
     s->D = p->ndim;
     s->NV = p->ndim + 2;
@@ -404,6 +418,7 @@ void or_destroy(or_sim* s)
     for (int d = 0; d < 3; d++) { free(s->ap[d]); free(s->v[d]); free(s->vn[d]); }
     free(s->ps); free(s->us); free(s->M);
     free(s->replay); free(s->log);
+    free(s->ls_rep); free(s->lslog);
     free(s);
 }
 
@@ -411,6 +426,12 @@ long or_schedule(const or_sim* s, double* out, long cap)
 {
     for (long i = 0; out && i < s->n_log && i < cap; i++) out[i] = s->log[i];
     return s->n_log;
+}
+
+long or_levelset_log(const or_sim* s, double* out, long cap)
+{
+    for (long i = 0; out && i < s->n_lslog && i < cap; i++) out[i] = s->lslog[i];
+    return s->n_lslog;
 }
 
 /* The CFL step of fluid k at a (sub)step start: the prescribed one when the
@@ -1142,8 +1163,27 @@ static int step_single(or_sim* s, double dt)
             out[k] = (st == ns - 1) ? s->X[k] : (st == 0 ? s->Y[k] : s->Z[k]);
             stage(s, k, in[k], s->X[k], out[k], A[st], dt, B[st] * dt);
         }
-        ls_stage(s, A[st], dt);
-        if (st == ns - 1) reinit(s);
+        if (s->n_ls_rep > 0) {
+            /* frozen geometry: the level set this stage had in the recorded run */
+            if (s->ls_pos + s->nc > s->n_ls_rep) {
+                snprintf(g_err, sizeof g_err, "ls_replay exhausted after %ld stages", s->ls_pos / s->nc);
+                return -2;
+            }
+            memcpy(s->phi, s->ls_rep + s->ls_pos, sizeof(double) * (size_t)s->nc);
+            s->ls_pos += s->nc;
+        } else {
+            ls_stage(s, A[st], dt);
+            if (st == ns - 1) reinit(s);
+        }
+        if (s->P.log_levelset) {
+            if (s->n_lslog + s->nc > s->cap_lslog) {
+                s->cap_lslog = s->cap_lslog ? 2 * s->cap_lslog : 4 * s->nc;
+                if (s->cap_lslog < s->n_lslog + s->nc) s->cap_lslog = s->n_lslog + s->nc;
+                s->lslog = (double*)realloc(s->lslog, sizeof(double) * (size_t)s->cap_lslog);
+            }
+            memcpy(s->lslog + s->n_lslog, s->phi, sizeof(double) * (size_t)s->nc);
+            s->n_lslog += s->nc;
+        }
         geometry(s);
         mix(s, 0, out[0]);
         mix(s, 1, out[1]);
@@ -1339,6 +1379,10 @@ int or_advance(or_sim* s, double t_end, int mode, long max_cycles, or_stats* st)
     memset(st, 0, sizeof(*st));
     long done = 0;
     int rc = 0;
+    if (mode != 0 && (s->n_ls_rep > 0 || s->P.log_levelset)) {
+        snprintf(g_err, sizeof g_err, "level-set log and replay cover single-dt steps only");
+        return -1;
+    }
     while (s->t < t_end && (max_cycles <= 0 || done < max_cycles)) {
         double dt[2];
         long cnt[2];
