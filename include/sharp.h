@@ -147,6 +147,22 @@ typedef struct {
                             count (a reading of Sec. 3.1's truncation test);
                             running past the end fails with SIM_EINVAL [NULL] */
     int64_t n_dt_replay; /* entries of dt_replay [0] */
+    const double* ls_replay;   /* with n_ls_replay > 0: the level set of every
+                            stage of the single-dt steps to take, in stage
+                            order, as sim_levelset_tape reports them
+                            (n_ls_replay = stages x cells), used instead of
+                            the stage's advection and reinitialisation.  Each
+                            stage then has the recorded cut-cell geometry
+                            (Sec. 2.3), so that the contents at the end of a
+                            run are a function of the initial state and the
+                            EOS alone: the map sim_backward differentiates
+                            when an interface is present, and what finite
+                            differences of it perturb.  Host array, copied at
+                            sim_create; every sim_set_state starts again from
+                            its first level set.  Single-dt steps only
+                            (SIM_EINVAL for accelerated cycles, when it runs
+                            out, and together with opts.tape) [NULL] */
+    int64_t n_ls_replay; /* entries of ls_replay [0] */
 } sim_opts;
 
 typedef struct {
@@ -244,24 +260,47 @@ sim_status sim_profile(sim_t* s, int enable);
 sim_status sim_profile_read(sim_t* s, double* ms, int64_t* launches, int64_t* cells, int64_t* first_cells);
 
 /* Adjoint of the taped run (opts->tape = 1): the gradient of a scalar J
- * through every sim_advance call since the last sim_set_state, with the
- * step lengths frozen at their forward values.  It covers runs in which one
- * fluid fills the grid (no interface, so no geometry, exchange term,
- * extension, mixing or interpolation enters) and single-dt steps: the
- * Shu-Osher stages (Sec. 2.1, Sec. 3) of the WENO5-LLF finite-volume
- * update and the stiffened-gas EOS.  The forward stores the state every
- * ckpt_every steps; the backward recomputes each segment's stages from its
- * checkpoint and runs the reverse sweep through them.
+ * through every sim_advance call since the last sim_set_state, for
+ * single-dt steps, with the step lengths frozen at their forward values.
+ * The map is the composition of the Shu-Osher stages (Sec. 2.1, Sec. 3) of
+ * the cut-cell finite-volume update (Eq. Eulerdiscrete: WENO5-LLF face
+ * fluxes times the fluid's apertures, and the exchange term of the
+ * interface Riemann problem) with the primitive recovery, the ghost-fluid
+ * extension and the small-cell mixing of each stage, and of the initial
+ * prim -> cons map (alpha_k U(W_k)).  With an interface, the geometry is
+ * frozen: every stage's level set is the recorded one (see
+ * opts.ls_replay), so the derivative is that of the replayed run; the
+ * exchange term's p*, u* are differentiated by the implicit function
+ * theorem on the Riemann root; extension and mixing are linear maps with
+ * their recorded coefficients.  Ghost states that the extension does not
+ * reach (the values sim_set_state gives outside a fluid's region, and
+ * older extension results) are taken as constants.  A run in which one
+ * fluid fills the grid has no interface and none of these steps.  The
+ * forward stores the state every ckpt_every steps (with an interface: both
+ * fluids' contents and the level set, and every stage's level set); the
+ * backward replays each segment from its checkpoint, every kernel on the
+ * simulation's stream, and runs the reverse sweep through its stages.
+ * Afterwards the simulation holds the state the forward ended with.
  *   g_cons[2][NV][cells]  dJ/dcons at the end of the run (input)
  *   g_prim0[2][NV][cells] dJ/dprim given to sim_set_state (output; zero for
- *                         the fluid that holds no cell)
+ *                         a fluid that holds no cell)
  *   g_eos[4]              dJ/dgamma_0, dJ/dpinf_0, dJ/dgamma_1, dJ/dpinf_1
  *                         through the dynamics and the initial prim -> cons
  *                         map (host array, output; nullable)
- * Returns SIM_EINVAL when the run is not covered (the message says why),
- * SIM_ESTATE without a tape, SIM_ENOMEM when the recomputation buffers
- * (3 ckpt_every states) do not fit. */
+ * Returns SIM_EINVAL when the run is not covered (accelerated cycles, a
+ * rolled-back step; the message says why), SIM_ESTATE without a tape,
+ * SIM_ENOMEM when the recomputation buffers (one fluid: 3 ckpt_every
+ * states; with an interface: rk ckpt_every stage records of about
+ * 4 NV + 2 D + 6 fields each) do not fit. */
 sim_status sim_backward(sim_t* s, const double* g_cons, double* g_prim0, double* g_eos, int on_device);
+
+/* The level sets a taped run with an interface recorded: after each stage
+ * of each single-dt step (after the reinitialisation at a step's last
+ * stage), cells values each, in stage order; the form opts.ls_replay takes.
+ * Up to cap values are copied to the host array out, and *n (if not NULL)
+ * receives the total count.  SIM_ESTATE when the simulation holds no such
+ * tape. */
+sim_status sim_levelset_tape(sim_t* s, double* out, int64_t cap, int64_t* n);
 
 /* Launch configuration in use: the bulk-tile stage's grid bound (blocks),
  * the schedule (serial = 1: every kernel on the simulation's stream; 0: the

@@ -38,7 +38,8 @@ class Opts(C.Structure):
                 ("serial", C.c_int), ("tape", C.c_int), ("ckpt_every", C.c_int),
                 ("dt_fixed", C.c_double), ("autotune", C.c_int),
                 ("graph", C.c_int), ("no_rollback", C.c_int),
-                ("grid_cap", C.c_int), ("dt_replay", C.c_void_p), ("n_dt_replay", C.c_int64)]
+                ("grid_cap", C.c_int), ("dt_replay", C.c_void_p), ("n_dt_replay", C.c_int64),
+                ("ls_replay", C.c_void_p), ("n_ls_replay", C.c_int64)]
 
 
 class Stats(C.Structure):
@@ -55,7 +56,7 @@ class Stats(C.Structure):
 EXPORTS = ["sim_default_opts", "sim_create", "sim_set_state", "sim_advance", "sim_get_state",
            "sim_totals", "sim_profile", "sim_profile_read", "sim_backward", "sim_tuned", "sim_destroy",
            "sim_strerror", "sim_last_error", "sim_batch_create", "sim_batch_advance", "sim_batch_info",
-           "sim_batch_destroy", "sim_graph_info", "sim_totals_noalloc", "sim_schedule"]
+           "sim_batch_destroy", "sim_graph_info", "sim_totals_noalloc", "sim_schedule", "sim_levelset_tape"]
 
 _lib = None
 
@@ -84,6 +85,7 @@ def lib():
         L.sim_tuned.argtypes = [vp, C.POINTER(C.c_int), C.POINTER(C.c_int), C.POINTER(C.c_int)]
         L.sim_graph_info.argtypes = [vp, C.POINTER(C.c_longlong), C.POINTER(C.c_longlong), C.POINTER(C.c_int)]
         L.sim_schedule.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
+        L.sim_levelset_tape.argtypes = [vp, vp, C.c_int64, C.POINTER(C.c_int64)]
         L.sim_destroy.argtypes = [vp]
         L.sim_destroy.restype = None
         L.sim_strerror.argtypes = [C.c_int]
@@ -96,7 +98,7 @@ def lib():
         L.sim_batch_destroy.restype = None
         for f in ("sim_create", "sim_set_state", "sim_advance", "sim_get_state", "sim_totals", "sim_totals_noalloc",
                   "sim_profile", "sim_profile_read", "sim_backward", "sim_tuned", "sim_batch_create",
-                  "sim_batch_advance", "sim_batch_info", "sim_graph_info", "sim_schedule"):
+                  "sim_batch_advance", "sim_batch_info", "sim_graph_info", "sim_schedule", "sim_levelset_tape"):
             getattr(L, f).restype = C.c_int
         _lib = L
     return _lib
@@ -116,16 +118,16 @@ def _check(rc, where):
 
 def default_opts(**over):
     """sim_opts with the library's defaults and the given fields; dt_replay
-    may be a sequence of CFL steps (the array is kept on the returned object
-    until sim_create has copied it)."""
+    (CFL steps) and ls_replay (stage level sets) may be arrays (kept on the
+    returned object until sim_create has copied them)."""
     o = Opts()
     lib().sim_default_opts(C.byref(o))
     for k, v in over.items():
-        if k == "dt_replay":
+        if k in ("dt_replay", "ls_replay"):
             a = np.ascontiguousarray(np.asarray(v, dtype=np.float64).reshape(-1))
-            o._dt_replay_keep = a
-            o.dt_replay = a.ctypes.data if a.size else None
-            o.n_dt_replay = int(a.size)
+            setattr(o, "_%s_keep" % k, a)
+            setattr(o, k, a.ctypes.data if a.size else None)
+            setattr(o, "n_" + k, int(a.size))
             continue
         setattr(o, k, v)
     return o
@@ -275,6 +277,17 @@ class Sim:
         if n.value:
             _check(lib().sim_schedule(self.h, C.c_void_p(out.ctypes.data), n.value, C.byref(n)), "sim_schedule")
         return out
+
+    def levelset_tape(self):
+        """the level sets a taped run with an interface recorded after each
+        single-dt stage, [stages, cells] (numpy; sim_levelset_tape)"""
+        n = C.c_int64()
+        _check(lib().sim_levelset_tape(self.h, None, 0, C.byref(n)), "sim_levelset_tape")
+        out = np.zeros(n.value)
+        if n.value:
+            _check(lib().sim_levelset_tape(self.h, C.c_void_p(out.ctypes.data), n.value, C.byref(n)),
+                   "sim_levelset_tape")
+        return out.reshape(-1, self.nc)
 
     def graph_info(self):
         """(single-dt steps captured into HIP graphs, steps replayed from one,

@@ -1,8 +1,10 @@
-// sharp_adjoint.hip -- reverse-mode derivative (adjoint) of single-dt runs
-// in which one fluid fills the grid: the Shu-Osher stages (Sec. 2.1, Sec. 3)
-// of the finite-volume update with the WENO5 flux under local Lax-Friedrichs
-// splitting, and the stiffened-gas EOS.  The step lengths are frozen at
-// their forward values.
+// sharp_adjoint.hip -- reverse-mode derivative (adjoint) of single-dt runs:
+// the Shu-Osher stages (Sec. 2.1, Sec. 3) of the cut-cell finite-volume
+// update (Eq. Eulerdiscrete) with the WENO5 flux under local Lax-Friedrichs
+// splitting, the exchange term of the interface Riemann problem, the
+// ghost-fluid extension and small-cell mixing (Sec. 2.3, Sec. 2.2), and the
+// stiffened-gas EOS.  The step lengths are frozen at their forward values,
+// and so is the geometry: every stage's level set is the recorded one.
 //
 // Forward tape: the state of the fluid every `ckpt_every` steps and each
 // step's length.  Backward: per segment (last first), the stage states are
@@ -16,6 +18,22 @@
 // the flux of face f receives (mu_right - mu_left)/h, and the face's
 // vector-Jacobian product is written per stencil slot, then gathered per
 // cell in a fixed order (deterministic, no atomics).
+//
+// With an interface (tape_fluid = 2) the forward also records the level set
+// after every stage, and the backward replays each segment from its
+// checkpoint through the forward engine with those level sets, copying
+// every stage's inputs, extended primitives, interface solution and
+// geometry to a stage record.  Per stage and fluid k the map is
+//     out_k = Mix_k(a U_0,k + (1 - a)(U_k + dt L_k)),
+//     L_k = sum_d (A_k,lo F_lo - A_k,hi F_hi)/h + X_k(p*, u*),
+// where a face flux reads, at each stencil cell, U/alpha_k on the fluid's
+// real cells (alpha_k >= alpha_mix) and U(W) of the extended primitives W
+// elsewhere; W = Ext_k(W(U/alpha_k) on real cells); (p*, u*) solve the
+// Riemann problem between the two fluids' W at each cut cell.  Its reverse:
+// Mix_k^T, then the face products (weighted by A_k), the exchange term's
+// product with dp*, du* from the implicit function theorem on
+// f_L(p) + f_R(p) + u_R - u_L = 0, Ext_k^T (the transposed Jacobi sweeps)
+// and the primitive recovery's transpose.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -192,21 +210,36 @@ __host__ __device__ __forceinline__ void face_vjp(const double (*U)[D + 2], doub
     }
 }
 
-__device__ __forceinline__ void block_add_pair(double x, double y, double* acc)
+// parameter partials (gamma_0, p_inf_0, gamma_1, p_inf_1) of a block, added
+// to its slot acc[4 block + i]: launches add in stream order
+__device__ __forceinline__ void block_add4(const double (&x)[4], double* acc)
 {
-    __shared__ double sx[ADJ_WG / 64], sy[ADJ_WG / 64];
-    for (int off = 32; off > 0; off >>= 1) {
-        x += __shfl_down(x, off, 64);
-        y += __shfl_down(y, off, 64);
+    __shared__ double sx[4][ADJ_WG / 64];
+    double v[4];
+#pragma unroll
+    for (int i = 0; i < 4; i++) {
+        v[i] = x[i];
+        for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_down(v[i], off, 64);
     }
     int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
-    if (lane == 0) { sx[wid] = x; sy[wid] = y; }
+    if (lane == 0)
+#pragma unroll
+        for (int i = 0; i < 4; i++) sx[i][wid] = v[i];
     __syncthreads();
-    if (threadIdx.x == 0) {
-        for (int w = 1; w < ADJ_WG / 64; w++) { x += sx[w]; y += sy[w]; }
-        acc[2 * blockIdx.x] += x;       // this block's slot: launches add in stream order
-        acc[2 * blockIdx.x + 1] += y;
-    }
+    if (threadIdx.x == 0)
+#pragma unroll
+        for (int i = 0; i < 4; i++) {
+            double t = v[i];
+            for (int w = 1; w < ADJ_WG / 64; w++) t += sx[i][w];
+            acc[4 * blockIdx.x + i] += t;
+        }
+}
+__device__ __forceinline__ void block_add_pair(int k, double x, double y, double* acc)
+{
+    double v[4] = {0.0, 0.0, 0.0, 0.0};
+    v[2 * k] = x;
+    v[2 * k + 1] = y;
+    block_add4(v, acc);
 }
 
 // face lattice normal to d: n[e] + (e == d) faces per direction e
@@ -224,10 +257,13 @@ __device__ __forceinline__ long long face_index(const Dev& g, int d, const int* 
     return fc[0] + n0 * (fc[1] + n1 * (long long)fc[2]);
 }
 
-// two waves per SIMD (a few spills) measured 3% faster than one without
+// two waves per SIMD (a few spills) measured 3% faster than one without.
+// ap: fluid 0's aperture of the faces normal to d (padded face index), the
+// flux weight of fluid k (1 - ap for fluid 1); null: every face open.  A
+// face with no weight writes zero slots and reads no stencil state.
 template <int D, int DIR>
 __global__ void __launch_bounds__(ADJ_WG, 2) k_adj_face(Dev g, int k, const double* U, const double* lam,
-                                                     double scale, double* fb, double* pacc)
+                                                     double scale, const double* ap, double* fb, double* pacc)
 {
     constexpr int NV = D + 2;
     constexpr int d = DIR;
@@ -243,9 +279,23 @@ __global__ void __launch_bounds__(ADJ_WG, 2) k_adj_face(Dev g, int k, const doub
         const int cr = x < n ? cc[0] + g.n[0] * (cc[1] + g.n[1] * cc[2]) : -1;
         cc[d] = x - 1;
         const int cl = x > 0 ? cc[0] + g.n[0] * (cc[1] + g.n[1] * cc[2]) : -1;
+        double wk = 1.0;
+        if (ap) {
+            const double a0 = ap[fidx(g, fc[0], fc[1], fc[2])];
+            wk = k == 0 ? a0 : 1.0 - a0;
+        }
+        bool any = false;
 #pragma unroll
-        for (int q = 0; q < NV; q++)
-            Fb[q] = scale * ((cr >= 0 ? lam[(size_t)q * g.nc + cr] : 0.0) - (cl >= 0 ? lam[(size_t)q * g.nc + cl] : 0.0));
+        for (int q = 0; q < NV; q++) {
+            Fb[q] = wk * scale *
+                    ((cr >= 0 ? lam[(size_t)q * g.nc + cr] : 0.0) - (cl >= 0 ? lam[(size_t)q * g.nc + cl] : 0.0));
+            any = any || Fb[q] != 0.0;
+        }
+        double* o = fb + (size_t)f * 6 * NV;
+        if (!any) {
+            for (int m = 0; m < 6 * NV; m++) o[m] = 0.0;
+            continue;
+        }
         double Us[6][NV], Ub[6][NV];
 #pragma unroll
         for (int m = 0; m < 6; m++) {
@@ -258,13 +308,12 @@ __global__ void __launch_bounds__(ADJ_WG, 2) k_adj_face(Dev g, int k, const doub
             }
         }
         face_vjp<D, DIR>(Us, gm, pi, g.eps, Fb, Ub, &gsum, &psum);
-        double* o = fb + (size_t)f * 6 * NV;
 #pragma unroll
         for (int m = 0; m < 6; m++)
 #pragma unroll
             for (int q = 0; q < NV; q++) o[m * NV + q] = Ub[m][q];
     }
-    block_add_pair(gsum, psum, pacc);
+    block_add_pair(k, gsum, psum, pacc);
 }
 
 // v (+)= sum over the faces normal to d of the slots that map to each cell:
@@ -325,31 +374,434 @@ __global__ void __launch_bounds__(ADJ_WG) k_adj_comb(long long n, double* lam, d
     }
 }
 
-// reverse of the initial map prim -> cons (rho u, E = (p + gamma p_inf)/(gamma - 1) + rho |u|^2 / 2)
+// reverse of the initial map prim -> cons, alpha_k U(W) with
+// U = (rho, rho u, (p + gamma p_inf)/(gamma - 1) + rho |u|^2 / 2);
+// al: fluid 0's volume fraction of the initial geometry (null: 1)
 template <int D>
 __global__ void __launch_bounds__(ADJ_WG) k_adj_prim0(Dev g, int k, const double* W, const double* lam, double* gp,
-                                                      double* pacc)
+                                                      const double* al, double* pacc)
 {
     constexpr int NV = D + 2;
     const double gm = g.gam[k], pi = g.pinf[k];
     double gsum = 0.0, psum = 0.0;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x) {
+        const double a = al ? (k == 0 ? al[c] : 1.0 - al[c]) : 1.0;
         double rho = W[c], p = W[(size_t)(NV - 1) * g.nc + c];
-        double lE = lam[(size_t)(NV - 1) * g.nc + c];
-        double r = lam[c], k2 = 0.0;
+        double lE = a * lam[(size_t)(NV - 1) * g.nc + c];
+        double r = a * lam[c], k2 = 0.0;
 #pragma unroll
         for (int e = 0; e < D; e++) {
-            double u = W[(size_t)(1 + e) * g.nc + c], lm = lam[(size_t)(1 + e) * g.nc + c];
+            double u = W[(size_t)(1 + e) * g.nc + c], lm = a * lam[(size_t)(1 + e) * g.nc + c];
             r += lm * u;
             k2 += u * u;
             gp[(size_t)(1 + e) * g.nc + c] = lm * rho + lE * rho * u;
         }
         gp[c] = r + lE * 0.5 * k2;
         gp[(size_t)(NV - 1) * g.nc + c] = lE / (gm - 1.0);
+        if (lE != 0.0) {
+            gsum += -lE * (p + pi) / ((gm - 1.0) * (gm - 1.0));
+            psum += lE * gm / (gm - 1.0);
+        }
+    }
+    block_add_pair(k, gsum, psum, pacc);
+}
+
+// ---------------------------------------------------------------------------
+// Two fluids with frozen geometry: the reverse of one stage's band physics.
+// Every kernel reads the stage record's arrays (see StageRec).
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double frac_k(const double* al, int k, int c) { return k == 0 ? al[c] : 1.0 - al[c]; }
+
+// level-set gradient by central differences over the domain's neighbours
+template <int D>
+__device__ __forceinline__ double grad_at(const Dev& g, const double* phi, int c, double* gr)
+{
+    double g2 = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        gr[d] = (phi[nbr(g, c, d, 1)] - phi[nbr(g, c, d, -1)]) / (2.0 * g.h);
+        g2 += gr[d] * gr[d];
+    }
+    return sqrt(g2);
+}
+
+// stencil state of fluid k at every cell: the content over the volume
+// fraction on real cells, U(W) of the extended primitives elsewhere
+template <int D>
+__global__ void __launch_bounds__(ADJ_WG) k_adj2_sten(Dev g, int k, const double* in, const double* al, const double* W,
+                                                      double* S)
+{
+    constexpr int NV = D + 2;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x) {
+        const double a = frac_k(al, k, c);
+        double U[NV];
+        if (a >= g.amix) {
+#pragma unroll
+            for (int q = 0; q < NV; q++) U[q] = in[(size_t)q * g.nc + c] / a;
+        } else {
+            double Wc[NV];
+#pragma unroll
+            for (int q = 0; q < NV; q++) Wc[q] = W[(size_t)q * g.nc + c];
+            prim2cons<D>(g.gam[k], g.pinf[k], Wc, U);
+        }
+#pragma unroll
+        for (int q = 0; q < NV; q++) S[(size_t)q * g.nc + c] = U[q];
+    }
+}
+
+// the stencil states' adjoint v: real cells -> d(content) = v / alpha_k (in
+// place); ghost cells -> the primitives' adjoint Wb = (dU/dW)^T v (v := 0),
+// with the EOS partials of U(W)
+template <int D>
+__global__ void __launch_bounds__(ADJ_WG) k_adj2_split(Dev g, int k, const double* al, const double* W, double* v,
+                                                       double* Wb, double* pacc)
+{
+    constexpr int NV = D + 2;
+    const double gm = g.gam[k], pi = g.pinf[k];
+    double gsum = 0.0, psum = 0.0;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x) {
+        const double a = frac_k(al, k, c);
+        double ub[NV];
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < NV; q++) {
+            ub[q] = v[(size_t)q * g.nc + c];
+            any = any || ub[q] != 0.0;
+        }
+        if (a >= g.amix) {
+#pragma unroll
+            for (int q = 0; q < NV; q++) {
+                v[(size_t)q * g.nc + c] = ub[q] / a;
+                Wb[(size_t)q * g.nc + c] = 0.0;
+            }
+            continue;
+        }
+#pragma unroll
+        for (int q = 0; q < NV; q++) {
+            v[(size_t)q * g.nc + c] = 0.0;
+            Wb[(size_t)q * g.nc + c] = 0.0;
+        }
+        if (!any) continue;
+        const double rho = W[c], p = W[(size_t)(NV - 1) * g.nc + c], lE = ub[NV - 1];
+        double r = ub[0], k2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < D; e++) {
+            const double u = W[(size_t)(1 + e) * g.nc + c];
+            r += ub[1 + e] * u;
+            k2 += u * u;
+            Wb[(size_t)(1 + e) * g.nc + c] = ub[1 + e] * rho + lE * rho * u;
+        }
+        Wb[c] = r + lE * 0.5 * k2;
+        Wb[(size_t)(NV - 1) * g.nc + c] = lE / (gm - 1.0);
         gsum += -lE * (p + pi) / ((gm - 1.0) * (gm - 1.0));
         psum += lE * gm / (gm - 1.0);
     }
-    block_add_pair(gsum, psum, pacc);
+    block_add_pair(k, gsum, psum, pacc);
+}
+
+// one side's wave function f(p) of the interface Riemann problem and its
+// partials: df = df/dp, a = df/d(rho, p_side, gamma, p_inf) at fixed p
+// (shock: Hugoniot branch; rarefaction: isentropic branch)
+__device__ inline double wave_partials(double rho, double ps, double gm, double pi, double p, double* df, double* a)
+{
+    const double pk = ps + pi, pb = p + pi;
+    if (p > ps) {
+        const double A = 2.0 / ((gm + 1.0) * rho), m = (gm - 1.0) / (gm + 1.0), B = m * pk;
+        const double t = 1.0 / (pb + B), q = sqrt(A * t), f = (p - ps) * q, hq = -0.5 * (p - ps) * q * t;
+        *df = q * (1.0 - 0.5 * (p - ps) * t);
+        a[0] = -0.5 * f / rho;
+        a[1] = -q + hq * m;
+        a[2] = 0.5 * f * (-1.0 / (gm + 1.0)) + hq * 2.0 * pk / ((gm + 1.0) * (gm + 1.0));
+        a[3] = hq * (1.0 + m);
+        return f;
+    }
+    const double c = sqrt(gm * pk / rho), z = (gm - 1.0) / (2.0 * gm), r = pb / pk;
+    const double rz = r > 0.0 ? pow(r, z) : 0.0, lr = r > 0.0 ? log(r) : 0.0;
+    const double f = 2.0 * c / (gm - 1.0) * (rz - 1.0);
+    *df = r > 0.0 ? rz / (r * rho * c) : 0.0;
+    a[0] = -0.5 * f / rho;
+    a[1] = 0.5 * f / pk - c * rz / (gm * pk);
+    a[2] = 0.5 * f / gm + (2.0 * c / (gm - 1.0)) * rz * lr / (2.0 * gm * gm) - f / (gm - 1.0);
+    a[3] = a[1] + (pb > 0.0 ? c * rz / (gm * pb) : 0.0);
+    return f;
+}
+
+// Reverse of the exchange term at every cut cell: X_0 = (0, -p* g, -p* u*
+// |g|) per unit volume, X_1 = -X_0, with g = (A_lo - A_hi)/h of fluid 0's
+// apertures (Sec. 2.1, Eq. Eulerdiscrete).  mu_k = scale lam_k; the
+// primitives' adjoints Wb_k (+=) and the four EOS partials follow from
+// dp*/dtheta = -(df/dtheta)/(df/dp) at the root of f_L + f_R + u_R - u_L
+// and u* = (u_L + u_R)/2 + (f_R(p*) - f_L(p*))/2.  At the cavitation floor
+// p* = -min(p_inf) is held fixed.
+template <int D>
+__global__ void __launch_bounds__(ADJ_WG) k_adj2_riemann(Dev g, const double* ap, const double* W0, const double* W1,
+                                                         const double* ps, const double* us, const double* lam0,
+                                                         const double* lam1, double scale, double* Wb0, double* Wb1,
+                                                         double* pacc)
+{
+    constexpr int NV = D + 2;
+    double par[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x) {
+        int i, j, kk;
+        coords(g, c, i, j, kk);
+        double gv[3], g2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            const double* a = ap + (size_t)d * g.nfc;
+            gv[d] = (a[fidx(g, i, j, kk)] - a[fidx(g, i + (d == 0), j + (d == 1), kk + (d == 2))]) / g.h;
+            g2 += gv[d] * gv[d];
+        }
+        const double gn = sqrt(g2);
+        if (!(gn > 0.0)) continue;
+        const double pst = ps[c], ust = us[c];
+        double pb = 0.0, ub = 0.0;
+        for (int k = 0; k < 2; k++) {
+            const double* lam = k == 0 ? lam0 : lam1;
+            const double sg = k == 0 ? 1.0 : -1.0;
+            double dot = 0.0;
+#pragma unroll
+            for (int d = 0; d < D; d++) dot += gv[d] * lam[(size_t)(1 + d) * g.nc + c];
+            const double lE = lam[(size_t)(NV - 1) * g.nc + c];
+            pb += sg * scale * (-dot - ust * gn * lE);
+            ub += sg * scale * (-pst * gn * lE);
+        }
+        if (pb == 0.0 && ub == 0.0) continue;
+        // (the wave functions depend on the normal velocities only through
+        // u_R - u_L, whose partials are the sides' velocity adjoints below)
+        const double r0 = W0[c], p0 = W0[(size_t)(NV - 1) * g.nc + c];
+        const double r1 = W1[c], p1 = W1[(size_t)(NV - 1) * g.nc + c];
+        double dfl, dfr, al4[4], ar4[4];
+        wave_partials(r0, p0, g.gam[0], g.pinf[0], pst, &dfl, al4);
+        wave_partials(r1, p1, g.gam[1], g.pinf[1], pst, &dfr, ar4);
+        const double pfl = -(g.pinf[0] < g.pinf[1] ? g.pinf[0] : g.pinf[1]);
+        const double G = 0.5 * (dfr - dfl);
+        const bool cav = !(pst > pfl);
+        const double sig = cav ? 0.0 : (pb + ub * G) / (dfl + dfr);
+        const double uL = sig + 0.5 * ub, uR = -sig + 0.5 * ub;
+        // the sides' (rho, p, gamma, p_inf)
+        const double cl = -(sig + 0.5 * ub), cr = -(sig - 0.5 * ub);
+        Wb0[c] += cl * al4[0];
+        Wb0[(size_t)(NV - 1) * g.nc + c] += cl * al4[1];
+        Wb1[c] += cr * ar4[0];
+        Wb1[(size_t)(NV - 1) * g.nc + c] += cr * ar4[1];
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            Wb0[(size_t)(1 + d) * g.nc + c] += uL * gv[d] / gn;
+            Wb1[(size_t)(1 + d) * g.nc + c] += uR * gv[d] / gn;
+        }
+        par[0] += cl * al4[2];
+        par[1] += cl * al4[3];
+        par[2] += cr * ar4[2];
+        par[3] += cr * ar4[3];
+    }
+    block_add4(par, pacc);
+}
+
+// Extension of fluid k (Sec. 2.3): target cells are band cells with
+// alpha_k < alpha_mix within ext_band cells on the far side of the
+// interface with a nonzero level-set gradient; each Jacobi sweep sets a
+// target to sum_d w_d W[up_d] with n = s_k grad phi / |grad phi|, w_d =
+// |n_d| / sum |n|, up_d the neighbour against n_d (s_0 = 1, s_1 = -1).
+template <int D>
+__device__ __forceinline__ bool ext_target(const Dev& g, int k, const double* phi, const double* al,
+                                           const uint8_t* M, int c, double* w, int* up)
+{
+    const double sk = k == 0 ? 1.0 : -1.0;
+    if (!M[c] || !(frac_k(al, k, c) < g.amix) || sk * phi[c] > g.extb * g.h) return false;
+    double gr[3];
+    const double gm = grad_at<D>(g, phi, c, gr);
+    if (!(gm > 0.0)) return false;
+    double ws = 0.0;
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        const double nd = sk * gr[d] / gm;
+        up[d] = nbr(g, c, d, nd > 0.0 ? -1 : 1);
+        w[d] = fabs(nd);
+        ws += w[d];
+    }
+#pragma unroll
+    for (int d = 0; d < D; d++) w[d] /= ws;
+    return true;
+}
+
+// one transposed Jacobi sweep: Wo = T^T Wi, gathered per cell from the
+// targets among the cell and its axis neighbours whose upwind stencil holds
+// it; a target's own entry is replaced by the sweep, other cells pass
+template <int D>
+__global__ void __launch_bounds__(ADJ_WG) k_adj2_extT(Dev g, int k, const double* phi, const double* al,
+                                                      const uint8_t* M, const double* Wi, double* Wo)
+{
+    constexpr int NV = D + 2;
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < g.nc; x += gridDim.x * blockDim.x) {
+        double w[3];
+        int up[3];
+        double acc[NV];
+        const bool tx = ext_target<D>(g, k, phi, al, M, x, w, up);
+#pragma unroll
+        for (int q = 0; q < NV; q++) acc[q] = tx ? 0.0 : Wi[(size_t)q * g.nc + x];
+        int cand[1 + 2 * D], nc = 0;
+        cand[nc++] = x;
+#pragma unroll
+        for (int d = 0; d < D; d++)
+            for (int o = -1; o <= 1; o += 2) {
+                const int c = nbr(g, x, d, o);
+                bool seen = false;
+                for (int m = 0; m < nc; m++) seen = seen || cand[m] == c;
+                if (!seen) cand[nc++] = c;
+            }
+        for (int m = 0; m < nc; m++) {
+            const int c = cand[m];
+            if (!ext_target<D>(g, k, phi, al, M, c, w, up)) continue;
+            for (int d = 0; d < D; d++) {
+                if (up[d] != x || w[d] == 0.0) continue;
+#pragma unroll
+                for (int q = 0; q < NV; q++) acc[q] += w[d] * Wi[(size_t)q * g.nc + c];
+            }
+        }
+#pragma unroll
+        for (int q = 0; q < NV; q++) Wo[(size_t)q * g.nc + x] = acc[q];
+    }
+}
+
+// reverse of the primitive recovery W = W(U), U = content / alpha_k, on the
+// real cells of fluid k: v += (dW/dU)^T Wb / alpha_k, with its EOS partials
+template <int D>
+__global__ void __launch_bounds__(ADJ_WG) k_adj2_c2pT(Dev g, int k, const double* in, const double* al,
+                                                      const double* Wb, double* v, double* pacc)
+{
+    constexpr int NV = D + 2;
+    const double gm = g.gam[k], pi = g.pinf[k];
+    double gsum = 0.0, psum = 0.0;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x) {
+        const double a = frac_k(al, k, c);
+        if (!(a >= g.amix)) continue;
+        double wb[NV];
+        bool any = false;
+#pragma unroll
+        for (int q = 0; q < NV; q++) {
+            wb[q] = Wb[(size_t)q * g.nc + c];
+            any = any || wb[q] != 0.0;
+        }
+        if (!any) continue;
+        const double rho = in[c] / a, E = in[(size_t)(NV - 1) * g.nc + c] / a;
+        double u[3], k2 = 0.0;
+#pragma unroll
+        for (int e = 0; e < D; e++) {
+            u[e] = in[(size_t)(1 + e) * g.nc + c] / a / rho;
+            k2 += u[e] * u[e];
+        }
+        const double pbw = wb[NV - 1];
+        double r = wb[0] + pbw * (gm - 1.0) * 0.5 * k2;
+#pragma unroll
+        for (int e = 0; e < D; e++) {
+            r -= wb[1 + e] * u[e] / rho;
+            v[(size_t)(1 + e) * g.nc + c] += (wb[1 + e] / rho - pbw * (gm - 1.0) * u[e]) / a;
+        }
+        v[c] += r / a;
+        v[(size_t)(NV - 1) * g.nc + c] += pbw * (gm - 1.0) / a;
+        gsum += pbw * (E - 0.5 * rho * k2 - pi);
+        psum += -pbw * gm;
+    }
+    block_add_pair(k, gsum, psum, pacc);
+}
+
+// Small-cell mixing of fluid k (Sec. 2.2): a source s (alpha_k < alpha_mix,
+// |phi| <= mix_band cells, nonzero gradient) exchanges
+// M = beta [(aU)_t a_s - (aU)_s a_t] / (a_s + a_t) with each target t
+// toward the bulk of fluid k along a non-empty subset of the axes (weights
+// |n_d|^2, |n_a n_b|, |n_x n_y n_z|^(2/3), normalised); s gains M, t loses
+// it.  mix_target returns the target of subset m and its weight (t = -1:
+// none).
+template <int D>
+__device__ __forceinline__ bool mix_source(const Dev& g, int k, const double* phi, const double* al, int c,
+                                           double* beta, int* sx)
+{
+    if (!(frac_k(al, k, c) < g.amix) || !(fabs(phi[c]) <= g.mixb * g.h)) return false;
+    double gr[3];
+    const double gm = grad_at<D>(g, phi, c, gr);
+    if (!(gm > 0.0)) return false;
+    double dir[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int d = 0; d < D; d++) {
+        dir[d] = (k == 0 ? -1.0 : 1.0) * gr[d] / gm;
+        sx[d] = dir[d] < 0.0 ? -1 : 1;
+    }
+    double bs = 0.0;
+    for (int m = 1; m < (1 << D); m++) {
+        int cnt = 0;
+        double prod = 1.0;
+        for (int d = 0; d < D; d++)
+            if (m & (1 << d)) { cnt++; prod *= fabs(dir[d]); }
+        const double b = cnt == 1 ? prod * prod : (cnt == 2 ? prod : pow(prod, 2.0 / 3.0));
+        beta[m - 1] = b;
+        bs += b;
+    }
+    for (int m = 1; m < (1 << D); m++) beta[m - 1] /= bs;
+    return true;
+}
+
+template <int D>
+__device__ __forceinline__ int mix_target(const Dev& g, int c, int m, const int* sx)
+{
+    int i, j, kk;
+    coords(g, c, i, j, kk);
+    return cidx(g, i + ((m & 1) ? sx[0] : 0), j + (D > 1 && (m & 2) ? sx[1] : 0), kk + (D > 2 && (m & 4) ? sx[2] : 0));
+}
+
+// lo = Mix_k^T li, gathered per cell: its own exchanges as a source and
+// those of the sources in its 3^D neighbourhood that target it
+template <int D>
+__global__ void __launch_bounds__(ADJ_WG) k_adj2_mixT(Dev g, int k, const double* al, const double* phi,
+                                                      const double* li, double* lo)
+{
+    constexpr int NV = D + 2;
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < g.nc; x += gridDim.x * blockDim.x) {
+        double lx[NV], acc[NV];
+#pragma unroll
+        for (int q = 0; q < NV; q++) acc[q] = lx[q] = li[(size_t)q * g.nc + x];
+        const double ax = frac_k(al, k, x);
+        double beta[7];
+        int sx[3] = {1, 1, 1};
+        if (mix_source<D>(g, k, phi, al, x, beta, sx)) {
+            for (int m = 1; m < (1 << D); m++) {
+                const double b = beta[m - 1];
+                if (!(b > 0.0)) continue;
+                const int t = mix_target<D>(g, x, m, sx);
+                if (t == x) continue;
+                const double at = frac_k(al, k, t);
+                if (!(ax + at > 0.0)) continue;
+                const double f = b * at / (ax + at);
+#pragma unroll
+                for (int q = 0; q < NV; q++) acc[q] -= f * (lx[q] - li[(size_t)q * g.nc + t]);
+            }
+        }
+        int i, j, kk;
+        coords(g, x, i, j, kk);
+        int seen[27], ns = 0;
+        for (int oz = (D > 2 ? -1 : 0); oz <= (D > 2 ? 1 : 0); oz++)
+            for (int oy = (D > 1 ? -1 : 0); oy <= (D > 1 ? 1 : 0); oy++)
+                for (int ox = -1; ox <= 1; ox++) {
+                    const int c = cidx(g, i + ox, j + oy, kk + oz);
+                    if (c == x) continue;
+                    bool dup = false;
+                    for (int m = 0; m < ns; m++) dup = dup || seen[m] == c;
+                    if (dup) continue;
+                    seen[ns++] = c;
+                    int sc[3] = {1, 1, 1};
+                    if (!mix_source<D>(g, k, phi, al, c, beta, sc)) continue;
+                    const double ac = frac_k(al, k, c);
+                    if (!(ac + ax > 0.0)) continue;
+                    for (int m = 1; m < (1 << D); m++) {
+                        const double b = beta[m - 1];
+                        if (!(b > 0.0) || mix_target<D>(g, c, m, sc) != x) continue;
+                        const double f = b * ac / (ac + ax);
+#pragma unroll
+                        for (int q = 0; q < NV; q++) acc[q] += f * (li[(size_t)q * g.nc + c] - lx[q]);
+                    }
+                }
+#pragma unroll
+        for (int q = 0; q < NV; q++) lo[(size_t)q * g.nc + x] = acc[q];
+    }
 }
 
 template <int D>
@@ -365,16 +817,20 @@ struct Adjoint {
         return (int)(b < 1 ? 1 : (b > 65535 ? 65535 : b));
     }
 
-    // v = J_L(U)^T (scale * lam), per direction through the face buffer
-    void jlt(int k, const double* U, const double* lam, double scale, double* v, double* fb, double* pacc)
+    // v = J^T (scale * lam) of the face fluxes of fluid k, per direction
+    // through the face buffer (ap: fluid 0's apertures, D padded face
+    // arrays; null: every face open)
+    void jlt(int k, const double* U, const double* lam, double scale, double* v, double* fb, double* pacc,
+             const double* ap = nullptr)
     {
         for (int d = 0; d < D; d++) {
+            const double* a = ap ? ap + (size_t)d * g.nfc : nullptr;
             if (d == 0)
-                k_adj_face<D, 0><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, U, lam, scale / g.h, fb, pacc);
+                k_adj_face<D, 0><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, U, lam, scale / g.h, a, fb, pacc);
             if constexpr (D > 1)
-                if (d == 1) k_adj_face<D, 1><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, U, lam, scale / g.h, fb, pacc);
+                if (d == 1) k_adj_face<D, 1><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, U, lam, scale / g.h, a, fb, pacc);
             if constexpr (D > 2)
-                if (d == 2) k_adj_face<D, 2><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, U, lam, scale / g.h, fb, pacc);
+                if (d == 2) k_adj_face<D, 2><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, U, lam, scale / g.h, a, fb, pacc);
             k_adj_gather<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, d, fb, v, d > 0);
         }
     }
@@ -382,10 +838,41 @@ struct Adjoint {
     sim_status run(const double* g_cons, double* g_prim0, double* g_eos)
     {
         std::vector<void*> own;
-        sim_status rc = sweep(g_cons, g_prim0, g_eos, own);
+        sim_status rc = s.tape_fluid == 2 ? sweep2(g_cons, g_prim0, g_eos, own) : sweep(g_cons, g_prim0, g_eos, own);
         (void)hipStreamSynchronize(s.stream);
         for (void* p : own) (void)hipFree(p);
         return rc;
+    }
+
+    double* alloc(std::vector<void*>& own, size_t bytes)
+    {
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
+        own.push_back(p);
+        return (double*)p;
+    }
+
+    long long max_faces() const
+    {
+        long long nfmax = 0;
+        for (int d = 0; d < D; d++)
+            nfmax = std::max(nfmax, (long long)(g.n[0] + (d == 0)) * (g.n[1] + (d == 1)) * (g.n[2] + (d == 2)));
+        return nfmax;
+    }
+
+    // the four parameter partials, summed over the blocks in a fixed order
+    sim_status read_params(const double* pacc, double* g_eos)
+    {
+        std::vector<double> h(4 * ADJ_BLOCKS);
+        SHARP_HIP(hipMemcpyAsync(h.data(), pacc, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s.stream));
+        SHARP_HIP(hipStreamSynchronize(s.stream));
+        SHARP_HIP(hipGetLastError());
+        for (int i = 0; i < 4; i++) {
+            double t = 0.0;
+            for (int b = 0; b < ADJ_BLOCKS; b++) t += h[4 * b + i];
+            g_eos[i] = t;
+        }
+        return SIM_OK;
     }
 
     sim_status sweep(const double* g_cons, double* g_prim0, double* g_eos, std::vector<void*>& own)
@@ -397,30 +884,21 @@ struct Adjoint {
         const long long N = (long long)s.tape_dt.size();
         const int K = s.o.ckpt_every;
         g.use_sched = 0;   // stage lengths come from the tape
-        long long nfmax = 0;
-        for (int d = 0; d < D; d++)
-            nfmax = std::max(nfmax, (long long)(g.n[0] + (d == 0)) * (g.n[1] + (d == 1)) * (g.n[2] + (d == 2)));
         // buffers: the stage inputs of one segment (ns per step), lam, lam0,
         // v, the face buffer (6 NV per face), the per-block parameter partials
         const size_t nstore = (size_t)std::min<long long>(N > 0 ? N : 1, K) * ns;
-        auto alloc = [&](size_t bytes) -> double* {
-            void* p = nullptr;
-            if (hipMalloc(&p, bytes) != hipSuccess) { (void)hipGetLastError(); return nullptr; }
-            own.push_back(p);
-            return (double*)p;
-        };
-        double* store = alloc(sizeof(double) * nv * nstore);
-        double* lam = alloc(sizeof(double) * nv);
-        double* lam0 = alloc(sizeof(double) * nv);
-        double* v = alloc(sizeof(double) * nv);
-        double* fb = alloc(sizeof(double) * (size_t)nfmax * 6 * NV);
-        double* pacc = alloc(sizeof(double) * 2 * ADJ_BLOCKS);
+        double* store = alloc(own, sizeof(double) * nv * nstore);
+        double* lam = alloc(own, sizeof(double) * nv);
+        double* lam0 = alloc(own, sizeof(double) * nv);
+        double* v = alloc(own, sizeof(double) * nv);
+        double* fb = alloc(own, sizeof(double) * (size_t)max_faces() * 6 * NV);
+        double* pacc = alloc(own, sizeof(double) * 4 * ADJ_BLOCKS);
         if (!store || !lam || !lam0 || !v || !fb || !pacc) {
             set_error("adjoint buffers do not fit in device memory (%zu MB for the recomputed stages)",
                       sizeof(double) * nv * nstore >> 20);
             return SIM_ENOMEM;
         }
-        SHARP_HIP(hipMemsetAsync(pacc, 0, sizeof(double) * 2 * ADJ_BLOCKS, s.stream));
+        SHARP_HIP(hipMemsetAsync(pacc, 0, sizeof(double) * 4 * ADJ_BLOCKS, s.stream));
         SHARP_HIP(hipMemcpyAsync(lam, g_cons + (size_t)k * nv, sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
         const long long nseg = (N + K - 1) / K;
         for (long long seg = nseg - 1; seg >= 0; seg--) {
@@ -451,17 +929,129 @@ struct Adjoint {
         }
         // initial map; the other fluid holds no cell
         SHARP_HIP(hipMemsetAsync(g_prim0, 0, sizeof(double) * 2 * nv, s.stream));
-        k_adj_prim0<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, s.tape_prim0, lam, g_prim0 + (size_t)k * nv, pacc);
-        std::vector<double> h(2 * ADJ_BLOCKS);
-        SHARP_HIP(hipMemcpyAsync(h.data(), pacc, sizeof(double) * h.size(), hipMemcpyDeviceToHost, s.stream));
-        SHARP_HIP(hipStreamSynchronize(s.stream));
-        SHARP_HIP(hipGetLastError());
-        double gsum = 0.0, psum = 0.0;
-        for (int b = 0; b < ADJ_BLOCKS; b++) { gsum += h[2 * b]; psum += h[2 * b + 1]; }
-        for (int i = 0; i < 4; i++) g_eos[i] = 0.0;
-        g_eos[2 * k] = gsum;
-        g_eos[2 * k + 1] = psum;
-        return SIM_OK;
+        k_adj_prim0<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, s.tape_prim0, lam, g_prim0 + (size_t)k * nv, nullptr,
+                                                            pacc);
+        return read_params(pacc, g_eos);
+    }
+
+    // Two fluids and an interface, geometry frozen at the recorded stage
+    // level sets.  Per segment (last first): the state is set to the
+    // segment's checkpoint and its steps are replayed by the forward engine
+    // (every kernel on the simulation's stream) into one stage record per
+    // stage; then the reverse sweep runs through the records.  The state
+    // the forward ended with is restored at the end.
+    sim_status sweep2(const double* g_cons, double* g_prim0, double* g_eos, std::vector<void*>& own)
+    {
+        const int ns = s.o.rk;
+        const double* A = ns == 3 ? ADJ_RK3_A : ADJ_RK2_A;
+        const size_t nv = (size_t)NV * g.nc;
+        const long long N = (long long)s.tape_dt.size();
+        const int K = s.o.ckpt_every;
+        StageRec rec;
+        rec.layout(D, (size_t)g.nc, (size_t)g.nfc);
+        const size_t nrec = (size_t)std::min<long long>(N > 0 ? N : 1, K) * ns;
+        double* store = alloc(own, sizeof(double) * rec.stride * nrec);
+        double *lam[2], *lam0[2], *v[2], *Wb[2][2];
+        for (int k = 0; k < 2; k++) {
+            lam[k] = alloc(own, sizeof(double) * nv);
+            lam0[k] = alloc(own, sizeof(double) * nv);
+            v[k] = alloc(own, sizeof(double) * nv);
+            Wb[k][0] = alloc(own, sizeof(double) * nv);
+            Wb[k][1] = alloc(own, sizeof(double) * nv);
+        }
+        double* S = alloc(own, sizeof(double) * nv);
+        double* tmp = alloc(own, sizeof(double) * nv);
+        double* fb = alloc(own, sizeof(double) * (size_t)max_faces() * 6 * NV);
+        double* pacc = alloc(own, sizeof(double) * 4 * ADJ_BLOCKS);
+        double* fin = alloc(own, sizeof(double) * (2 * nv + g.nc));
+        bool ok = store && S && tmp && fb && pacc && fin;
+        for (int k = 0; k < 2; k++) ok = ok && lam[k] && lam0[k] && v[k] && Wb[k][0] && Wb[k][1];
+        if (!ok) {
+            set_error("adjoint buffers do not fit in device memory (%zu MB for %zu stage records)",
+                      sizeof(double) * rec.stride * nrec >> 20, nrec);
+            return SIM_ENOMEM;
+        }
+        // the state the forward ended with, restored afterwards
+        SHARP_HIP(hipMemcpyAsync(fin, g.X[0], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
+        SHARP_HIP(hipMemcpyAsync(fin + nv, g.X[1], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
+        SHARP_HIP(hipMemcpyAsync(fin + 2 * nv, g.phiP, sizeof(double) * g.nc, hipMemcpyDeviceToDevice, s.stream));
+        SHARP_HIP(hipMemsetAsync(pacc, 0, sizeof(double) * 4 * ADJ_BLOCKS, s.stream));
+        for (int k = 0; k < 2; k++)
+            SHARP_HIP(hipMemcpyAsync(lam[k], g_cons + (size_t)k * nv, sizeof(double) * nv, hipMemcpyDeviceToDevice,
+                                     s.stream));
+        const double t_end = s.t;
+        const bool serial = s.run_serial;
+        s.run_serial = true;
+        g.use_sched = 0;
+        s.ls_src.clear();
+        for (double* p : s.tape_ls)
+            for (int q = 0; q < ns; q++) s.ls_src.push_back(p + (size_t)q * g.nc);
+        sim_status rc = SIM_OK;
+        const long long nseg = (N + K - 1) / K;
+        for (long long seg = nseg - 1; seg >= 0 && rc == SIM_OK; seg--) {
+            const long long s0 = seg * K, s1 = std::min(N, s0 + K);
+            const double* ck = s.tape_ckpt[(size_t)seg];
+            rc = engine_restore(s, ck, ck + nv, ck + 2 * nv);
+            s.ls_pos = (size_t)s0 * ns;
+            rec.base = store;
+            rec.next = 0;
+            for (long long st = s0; st < s1 && rc == SIM_OK; st++) rc = engine_replay_step(s, s.tape_dt[(size_t)st], &rec);
+            if (rc != SIM_OK) break;
+            for (long long st = s1 - 1; st >= s0; st--) {
+                const double dt = s.tape_dt[(size_t)st];
+                for (int q = ns; q >= 1; q--) {
+                    const double* R = store + ((size_t)(st - s0) * ns + (q - 1)) * rec.stride;
+                    const double w = 1.0 - A[q - 1];
+                    // mixing after the stage, with the stage's new geometry
+                    for (int k = 0; k < 2; k++) {
+                        k_adj2_mixT<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, k, R + rec.aln, R + rec.phin, lam[k],
+                                                                             tmp);
+                        std::swap(lam[k], tmp);
+                    }
+                    // face fluxes: content adjoints on real cells, primitive
+                    // adjoints on ghost cells
+                    for (int k = 0; k < 2; k++) {
+                        k_adj2_sten<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, k, R + rec.in[k], R + rec.al,
+                                                                             R + rec.W[k], S);
+                        jlt(k, S, lam[k], w * dt, v[k], fb, pacc, R + rec.ap);
+                        k_adj2_split<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, R + rec.al, R + rec.W[k], v[k],
+                                                                            Wb[k][0], pacc);
+                    }
+                    // exchange term
+                    k_adj2_riemann<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, R + rec.ap, R + rec.W[0], R + rec.W[1],
+                                                                          R + rec.ps, R + rec.us, lam[0], lam[1],
+                                                                          w * dt, Wb[0][0], Wb[1][0], pacc);
+                    const uint8_t* Mk = reinterpret_cast<const uint8_t*>(R + rec.M);
+                    for (int k = 0; k < 2; k++) {
+                        int cur = 0;
+                        for (int it = 0; it < s.o.ext_iters; it++) {
+                            k_adj2_extT<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, k, R + rec.phi, R + rec.al, Mk,
+                                                                                 Wb[k][cur], Wb[k][1 - cur]);
+                            cur ^= 1;
+                        }
+                        k_adj2_c2pT<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, R + rec.in[k], R + rec.al, Wb[k][cur],
+                                                                           v[k], pacc);
+                        k_adj_comb<<<blocks((long long)nv), ADJ_WG, 0, s.stream>>>((long long)nv, lam[k], lam0[k], v[k],
+                                                                                   A[q - 1], w, q == ns, q == 1);
+                    }
+                }
+            }
+            if (seg == 0) {
+                // initial map alpha_k U(W_k) with the initial geometry (the
+                // first record's)
+                for (int k = 0; k < 2; k++)
+                    k_adj_prim0<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, s.tape_prim0 + (size_t)k * nv, lam[k],
+                                                                        g_prim0 + (size_t)k * nv, store + rec.al, pacc);
+            }
+        }
+        s.ls_src.clear();
+        s.ls_pos = 0;
+        s.run_serial = serial;
+        sim_status r2 = engine_restore(s, fin, fin + nv, fin + 2 * nv);
+        s.t = t_end;
+        if (rc != SIM_OK) return rc;
+        if (r2 != SIM_OK) return r2;
+        return read_params(pacc, g_eos);
     }
 };
 
@@ -471,6 +1061,8 @@ void tape_clear(Sim& s)
 {
     for (double* p : s.tape_ckpt) (void)hipFree(p);
     s.tape_ckpt.clear();
+    for (double* p : s.tape_ls) (void)hipFree(p);
+    s.tape_ls.clear();
     s.tape_dt.clear();
     if (s.tape_prim0) (void)hipFree(s.tape_prim0);
     s.tape_prim0 = nullptr;
@@ -481,21 +1073,18 @@ sim_status tape_begin(Sim& s, const double* prim_dev)
 {
     tape_clear(s);
     const bool none0 = s.bulk_cells[0] == 0, none1 = s.bulk_cells[1] == 0;
-    if (s.lcount[LIST_BAND] != 0 || none0 == none1) {
-        s.tape_why = "the level set places an interface (or its band) in the grid: the adjoint covers runs in "
-                     "which one fluid fills the grid";
-        return SIM_OK;
-    }
-    const int k = none0 ? 1 : 0;
-    const size_t nv = (size_t)(s.g.D + 2) * s.g.nc;
-    if (hipMalloc((void**)&s.tape_prim0, sizeof(double) * nv) != hipSuccess) {
+    // one fluid fills the grid (k), or an interface (2): both fluids
+    const bool two = s.lcount[LIST_BAND] != 0 || none0 == none1;
+    const int k = two ? 2 : (none0 ? 1 : 0);
+    const size_t nv = (size_t)(s.g.D + 2) * s.g.nc, n0 = two ? 2 * nv : nv;
+    if (hipMalloc((void**)&s.tape_prim0, sizeof(double) * n0) != hipSuccess) {
         (void)hipGetLastError();
         s.tape_prim0 = nullptr;
         set_error("tape allocation failed");
         return SIM_ENOMEM;
     }
-    SHARP_HIP(hipMemcpyAsync(s.tape_prim0, prim_dev + (size_t)k * nv, sizeof(double) * nv, hipMemcpyDeviceToDevice,
-                             s.stream));
+    SHARP_HIP(hipMemcpyAsync(s.tape_prim0, prim_dev + (two ? 0 : (size_t)k * nv), sizeof(double) * n0,
+                             hipMemcpyDeviceToDevice, s.stream));
     s.tape_fluid = k;
     s.tape_why.clear();
     return SIM_OK;
@@ -504,16 +1093,34 @@ sim_status tape_begin(Sim& s, const double* prim_dev)
 sim_status tape_step(Sim& s, double dt)
 {
     if (s.tape_fluid < 0) return SIM_OK;
+    const size_t nv = (size_t)(s.g.D + 2) * s.g.nc, nc = (size_t)s.g.nc;
+    const bool two = s.tape_fluid == 2;
     if (s.tape_dt.size() % (size_t)s.o.ckpt_every == 0) {
-        const size_t nv = (size_t)(s.g.D + 2) * s.g.nc;
         double* p = nullptr;
-        if (hipMalloc((void**)&p, sizeof(double) * nv) != hipSuccess) {
+        const size_t n = two ? 2 * nv + nc : nv;
+        if (hipMalloc((void**)&p, sizeof(double) * n) != hipSuccess) {
             (void)hipGetLastError();
             set_error("tape checkpoint allocation failed");
             return SIM_ENOMEM;
         }
         s.tape_ckpt.push_back(p);
-        SHARP_HIP(hipMemcpyAsync(p, s.g.X[s.tape_fluid], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
+        if (two) {
+            SHARP_HIP(hipMemcpyAsync(p, s.g.X[0], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
+            SHARP_HIP(hipMemcpyAsync(p + nv, s.g.X[1], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
+            SHARP_HIP(hipMemcpyAsync(p + 2 * nv, s.g.phiP, sizeof(double) * nc, hipMemcpyDeviceToDevice, s.stream));
+        } else {
+            SHARP_HIP(hipMemcpyAsync(p, s.g.X[s.tape_fluid], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
+        }
+    }
+    if (two) {
+        // the step's stage level sets, written by the step itself
+        double* p = nullptr;
+        if (hipMalloc((void**)&p, sizeof(double) * (size_t)s.o.rk * nc) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("level-set tape allocation failed");
+            return SIM_ENOMEM;
+        }
+        s.tape_ls.push_back(p);
     }
     s.tape_dt.push_back(dt);
     return SIM_OK;
@@ -524,6 +1131,9 @@ sim_status engine_backward(Sim& s, const double* g_cons, double* g_prim0, double
     (void)hipStreamSynchronize(s.stream);
     for (int k = 0; k < 2; k++)
         if (s.side[k]) (void)hipStreamSynchronize(s.side[k]);
+    if (s.ls_stream) (void)hipStreamSynchronize(s.ls_stream);
+    if (s.snap_stream) (void)hipStreamSynchronize(s.snap_stream);
+    s.snap_pending = false;   // the cycle-start copies are complete
     switch (s.g.D) {
     case 1: return Adjoint<1>(s).run(g_cons, g_prim0, g_eos);
     case 2: return Adjoint<2>(s).run(g_cons, g_prim0, g_eos);

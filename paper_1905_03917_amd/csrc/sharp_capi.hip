@@ -1,5 +1,6 @@
 // sharp_capi.hip -- C ABI of the gfx950 sharp-interface library (include/sharp.h):
 // argument checking, device allocation, host/device staging.
+#include <algorithm>
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
@@ -150,6 +151,14 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
             set_error("dt_replay[%lld] = %g is not a positive step", (long long)i, o.dt_replay[i]);
             return SIM_EINVAL;
         }
+    if (o.n_ls_replay < 0 || (o.n_ls_replay > 0 && !o.ls_replay) || o.n_ls_replay % nc != 0) {
+        set_error("ls_replay needs a whole number of level sets (%lld values each)", nc);
+        return SIM_EINVAL;
+    }
+    if (o.n_ls_replay > 0 && o.tape) {
+        set_error("a run that replays level sets cannot record a tape");
+        return SIM_EINVAL;
+    }
 
     int device = -1;
     if (hipGetDevice(&device) != hipSuccess) { set_error("hipGetDevice failed"); return SIM_EDEVICE; }
@@ -163,6 +172,7 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     s.device = device;
     if (o.n_dt_replay > 0) s.dt_replay.assign(o.dt_replay, o.dt_replay + o.n_dt_replay);
     s.o.dt_replay = nullptr;   // the copy is used; the caller's buffer need not outlive the call
+    s.o.ls_replay = nullptr;   // copied to the device below
     // 3-D bulk lists are long (the slow fluid fills most of the grid): a
     // larger grid bound measured faster there (the autotuner's choice at 256^3)
     if (D == 3) s.bulk_blocks = 4 * SHARP_BULK_BLOCKS;
@@ -259,6 +269,10 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     // back with one copy; the counts, read by every grid-stride loop, sit
     // 256 bytes away from the words the reductions update atomically
     A(g.red, RED_WORDS);
+    if (o.n_ls_replay > 0) {
+        A(s.ls_rep, (size_t)o.n_ls_replay);
+        s.n_ls_rep = (size_t)(o.n_ls_replay / nc);
+    }
     if (!o.no_rollback) {
         for (int k = 0; k < 2; k++) {
             A(s.snapX[k], nv);
@@ -290,6 +304,8 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
         if (hipMemcpyAsync(g.lists + (size_t)LIST_ALL * g.ntiles, all.data(), sizeof(int) * g.ntiles,
                            hipMemcpyHostToDevice, s.stream) != hipSuccess ||
             hipMemcpyAsync(g.counts, cnt, sizeof cnt, hipMemcpyHostToDevice, s.stream) != hipSuccess ||
+            (s.ls_rep && hipMemcpyAsync(s.ls_rep, o.ls_replay, sizeof(double) * (size_t)o.n_ls_replay,
+                                        hipMemcpyHostToDevice, s.stream) != hipSuccess) ||
             hipStreamSynchronize(s.stream) != hipSuccess) {
             set_error("initial upload failed");
             rc = SIM_EDEVICE;
@@ -451,6 +467,30 @@ sim_status sim_schedule(sim_t* h, double* out, int64_t cap, int64_t* n)
     const int64_t m = (int64_t)v.size();
     for (int64_t i = 0; i < m && i < cap; i++) out[i] = v[(size_t)i];
     if (n) *n = m;
+    return SIM_OK;
+}
+
+sim_status sim_levelset_tape(sim_t* h, double* out, int64_t cap, int64_t* n)
+{
+    if (!h || cap < 0 || (cap > 0 && !out)) { set_error("bad arguments"); return SIM_EINVAL; }
+    Sim& s = h->s;
+    if (!s.o.tape || s.tape_fluid != 2) {
+        set_error("no level-set tape: it is recorded by a taped run (opts.tape = 1) with an interface");
+        return SIM_ESTATE;
+    }
+    const size_t per = (size_t)s.o.rk * s.g.nc;
+    const int64_t m = (int64_t)(per * s.tape_ls.size());
+    if (n) *n = m;
+    for (size_t i = 0; i < s.tape_ls.size(); i++) {
+        const int64_t o0 = (int64_t)(i * per);
+        if (o0 >= cap) break;
+        const size_t cnt = (size_t)std::min<int64_t>((int64_t)per, cap - o0);
+        if (hipMemcpyAsync(out + o0, s.tape_ls[i], cnt * sizeof(double), hipMemcpyDeviceToHost, s.stream) != hipSuccess) {
+            set_error("device-to-host copy failed");
+            return SIM_EDEVICE;
+        }
+    }
+    if (hipStreamSynchronize(s.stream) != hipSuccess) { set_error("stream synchronisation failed"); return SIM_EDEVICE; }
     return SIM_OK;
 }
 

@@ -68,6 +68,37 @@ struct Recorder {
     }
 };
 
+// Where a replayed single-dt step copies what its stages saw (the adjoint's
+// recomputation of a segment): one record per stage, each holding, at the
+// offsets below (doubles), the stage inputs of both fluids, their
+// primitives after the extension, the interface solution, the geometry and
+// the level set the stage's interaction used, the volume fraction and level
+// set after the stage's level-set update (those of its mixing), and the
+// band mask of the step (bytes).
+struct StageRec {
+    double* base = nullptr;   // first record
+    size_t stride = 0;        // doubles per record
+    int next = 0;             // record the next stage fills
+    size_t in[2], W[2], ps, us, al, ap, phi, aln, phin, M;
+    void layout(int D, size_t nc, size_t nfc)
+    {
+        const size_t nv = (size_t)(D + 2) * nc;
+        in[0] = 0;
+        in[1] = nv;
+        W[0] = 2 * nv;
+        W[1] = 3 * nv;
+        ps = 4 * nv;
+        us = ps + nc;
+        al = us + nc;
+        ap = al + nc;   // D padded face arrays
+        phi = ap + (size_t)D * nfc;
+        aln = phi + nc;
+        phin = aln + nc;
+        M = phin + nc;
+        stride = M + (nc + 7) / 8;
+    }
+};
+
 struct Sim {
     Dev g;                 // device view (pointers live in device memory)
     Recorder* rec = nullptr;   // set while a batch advances this simulation
@@ -130,12 +161,23 @@ struct Sim {
     long long prof_launches = 0, prof_cell_stages = 0, prof_first_stages = 0;
     long long bulk_cells[2] = {0, 0};   // cells in the bulk lists (host copy)
     int lcount[NLISTS] = {1, 1, 1, 1, 1, 1};   // tiles per list (host copy, sizes the grids)
-    // tape of the adjoint (o.tape): single-dt steps of a single-fluid run
-    int tape_fluid = -1;                // the fluid holding every cell; -1: not differentiable
+    // tape of the adjoint (o.tape): single-dt steps
+    int tape_fluid = -1;                // the fluid holding every cell, 2 with an interface; -1: not differentiable
     std::string tape_why;               // why this run cannot be differentiated
     std::vector<double> tape_dt;        // length of each taped step
-    std::vector<double*> tape_ckpt;     // state of tape_fluid before steps 0, K, 2K, ... (K = o.ckpt_every)
-    double* tape_prim0 = nullptr;       // primitives of tape_fluid given to sim_set_state
+    // state before steps 0, K, 2K, ... (K = o.ckpt_every): the contents of
+    // tape_fluid, or (tape_fluid = 2) of both fluids and the level set
+    std::vector<double*> tape_ckpt;
+    double* tape_prim0 = nullptr;       // primitives given to sim_set_state (tape_fluid, or both)
+    std::vector<double*> tape_ls;       // tape_fluid = 2: per step, the level set after each stage
+    // level-set replay: the stages of single-dt steps take these level sets
+    // (device arrays of cells values, in stage order) instead of their own
+    // advection and reinitialisation, which fixes every stage's geometry
+    std::vector<const double*> ls_src;
+    size_t ls_pos = 0;
+    double* ls_rep = nullptr;           // device copy of opts.ls_replay
+    size_t n_ls_rep = 0;                // its level sets
+    StageRec* stage_rec = nullptr;      // set while the adjoint replays a step
     // single-dt steps of the fixed length o.dt_fixed captured in HIP graphs
     // (o.graph): one graph per launch configuration, i.e. per value of the
     // host state the step's launches are made from (`key`); `after` holds
@@ -176,6 +218,13 @@ sim_status engine_bflux(Sim& s, double out[2][5]);
 // one bulk-tile stage of fluid k on the simulation stream (the forward
 // recomputation of the adjoint): out = a*base + (1-a)*(in + dt*L(in))
 void engine_bulk_stage(Sim& s, int k, const double* in, const double* base, double* out, double a, double dt);
+// the adjoint's recomputation with an interface: the state set to the
+// contents X0, X1 and level set phi (device), geometry and tile lists
+// rebuilt from phi; then single-dt steps of length dt, every kernel on the
+// simulation's stream, their stage level sets taken from s.ls_src and
+// their stages copied to *rec
+sim_status engine_restore(Sim& s, const double* X0, const double* X1, const double* phi);
+sim_status engine_replay_step(Sim& s, double dt, StageRec* rec);
 // conservation ledger (sharp_ledger.hip): out10[k*5 + q] = sum_c dV cons[k][q][c], zero for q >= NV
 sim_status engine_totals(Sim& s, double* out10);
 // the same through the device's file-scope scratch array (sharp_ledger.hip):

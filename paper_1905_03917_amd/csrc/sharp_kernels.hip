@@ -2392,6 +2392,14 @@ __global__ void __launch_bounds__(SHARP_WG) k_copy_masked(Dev g, int list, const
     b_copy_masked<D>(VB::grid(), g, list, src, dst);
 }
 
+// the level set a stage sees, over every cell (a tape entry or a stage
+// record): the working buffer on the band-mask cells, the base elsewhere
+__global__ void __launch_bounds__(256) k_phi_merge(Dev g, const double* cur, double* out)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x)
+        out[c] = g.M[c] ? cur[c] : g.phiP[c];
+}
+
 // ---------------------------------------------------------------------------
 // The level-set chain of one stage for one tile in one kernel (1-D and 2-D),
 // temporally blocked: extension of the interface velocity from the cut cells'
@@ -3025,9 +3033,18 @@ struct Engine {
             }
         }
         double* po = phi_stage_out(q);
-        ls(a, dt, phin, po);
         const double* cur = po;
-        if (last) { reinit(po); cur = g.phiP; }
+        if (replaying()) {
+            // the recorded level set of this stage (every cell: the band
+            // values the stage had and the base values elsewhere)
+            double* dst = last ? g.phiP : po;
+            if (last && s.stream != s.ls_stream) snap_guard(s.stream);
+            (void)hipMemcpyAsync(dst, s.ls_src[s.ls_pos++], sizeof(double) * g.nc, hipMemcpyDeviceToDevice, s.stream);
+            cur = dst;
+        } else {
+            ls(a, dt, phin, po);
+            if (last) { reinit(po); cur = g.phiP; }
+        }
         geom(cur);
         return cur;
     }
@@ -3097,7 +3114,9 @@ struct Engine {
     }
     void velocity(const double* cur) { extv(cur); }
     // the velocity extension runs inside the fused level-set kernel
-    bool fused_ls() const { return D <= 2 && s.o.ext_iters <= EXT_H && s.o.reinit_iters <= 2; }
+    bool fused_ls() const { return D <= 2 && s.o.ext_iters <= EXT_H && s.o.reinit_iters <= 2 && !replaying(); }
+    // the stages take recorded level sets (frozen geometry)
+    bool replaying() const { return !s.ls_src.empty(); }
     // interface interaction: ghost states, Riemann problems, and (unless a
     // fused level-set stage follows and extends it) the level-set velocity
     void interaction(const double* src0, const double* src1, const double* cur, double wcorr, int S,
@@ -3184,6 +3203,9 @@ struct Engine {
         }
         ls_forked = false;
         (void)hipStreamWaitEvent(s.ls_stream, s.ev_ls_go, 0);
+        // the last stage writes the base level set: after the cycle-start
+        // copy of it (the main stream's own wait may come after the fork)
+        if (last && s.snap_pending && !s.capturing) (void)hipStreamWaitEvent(s.ls_stream, s.ev_snap, 0);
         hipStream_t main = s.stream;
         s.stream = s.ls_stream;
         if (s.vel_deferred) {
@@ -3439,12 +3461,28 @@ struct Engine {
         if (s.snap_stream) SHARP_HIP(hipStreamSynchronize(s.snap_stream));
         SHARP_HIP(hipStreamSynchronize(s.stream));
         s.snap_pending = false;
-        const size_t nv = (size_t)NV * g.nc, nb = (size_t)NV * (g.nbface > 0 ? g.nbface : 1);
-        for (int k = 0; k < 2; k++) {
-            SHARP_HIP(hipMemcpyAsync(g.X[k], s.snapX[k], nv * sizeof(double), hipMemcpyDeviceToDevice, s.stream));
+        const size_t nb = (size_t)NV * (g.nbface > 0 ? g.nbface : 1);
+        for (int k = 0; k < 2; k++)
             SHARP_HIP(hipMemcpyAsync(g.bacc[k], s.snapBacc[k], nb * sizeof(double), hipMemcpyDeviceToDevice, s.stream));
+        sim_status rc = restore_state(s.snapX[0], s.snapX[1], s.snapPhi);
+        if (rc != SIM_OK) return rc;
+        s.t = s.snap_t;
+        *st = s.snap_stats;
+        s.rollbacks++;
+        if (s.o.tape && s.tape_fluid >= 0) {
+            s.tape_fluid = -1;
+            s.tape_why = "a step turned non-physical and the state was rolled back";
         }
-        SHARP_HIP(hipMemcpyAsync(g.phiP, s.snapPhi, (size_t)g.nc * sizeof(double), hipMemcpyDeviceToDevice, s.stream));
+        return SIM_OK;
+    }
+    // contents and level set from device copies; the geometry, band and
+    // tile lists rebuilt from the level set as sim_set_state builds them
+    sim_status restore_state(const double* X0, const double* X1, const double* phi)
+    {
+        const size_t nv = (size_t)NV * g.nc;
+        SHARP_HIP(hipMemcpyAsync(g.X[0], X0, nv * sizeof(double), hipMemcpyDeviceToDevice, s.stream));
+        SHARP_HIP(hipMemcpyAsync(g.X[1], X1, nv * sizeof(double), hipMemcpyDeviceToDevice, s.stream));
+        SHARP_HIP(hipMemcpyAsync(g.phiP, phi, (size_t)g.nc * sizeof(double), hipMemcpyDeviceToDevice, s.stream));
         s.lcount[LIST_ALL] = g.ntiles;
         geom(g.phiP, LIST_ALL);
         geom(g.phiP, LIST_ALL);
@@ -3455,14 +3493,22 @@ struct Engine {
                                  s.stream));
         SHARP_HIP(hipStreamSynchronize(s.stream));
         take_counts();
-        s.t = s.snap_t;
-        *st = s.snap_stats;
-        s.rollbacks++;
-        if (s.o.tape && s.tape_fluid >= 0) {
-            s.tape_fluid = -1;
-            s.tape_why = "a step turned non-physical and the state was rolled back";
-        }
         return SIM_OK;
+    }
+    // one single-dt step of length dt from the current state (the stage
+    // level sets from s.ls_src), its stages recorded to *rec
+    sim_status replay_step(double dt, StageRec* rec)
+    {
+        double d[2];
+        long long cnt[2];
+        s.stage_rec = rec;
+        sim_status rc = prepare(true, d, cnt);
+        if (rc == SIM_OK) {
+            step_single(dt);
+            join();
+        }
+        s.stage_rec = nullptr;
+        return rc;
     }
     // reductions and error flags to zero, no non-physical cell recorded
     hipError_t reset_flags()
@@ -3565,6 +3611,39 @@ struct Engine {
     }
 
     // ---- the original method: one dt for both fluids and the level set ----
+    int fill_blocks() const
+    {
+        int b = (g.nc + 255) / 256;
+        return b > 65535 ? 65535 : b;
+    }
+    // the stage record of a replayed step: what the stage's interaction saw
+    void rec_in(const double* const* in, const double* phin)
+    {
+        StageRec& r = *s.stage_rec;
+        double* b = r.base + (size_t)r.next * r.stride;
+        const size_t nv = (size_t)NV * g.nc, nc = (size_t)g.nc;
+        for (int k = 0; k < 2; k++) {
+            (void)hipMemcpyAsync(b + r.in[k], in[k], nv * sizeof(double), hipMemcpyDeviceToDevice, s.stream);
+            (void)hipMemcpyAsync(b + r.W[k], g.Wb[k][s.wcur], nv * sizeof(double), hipMemcpyDeviceToDevice, s.stream);
+        }
+        (void)hipMemcpyAsync(b + r.ps, g.ps, nc * sizeof(double), hipMemcpyDeviceToDevice, s.stream);
+        (void)hipMemcpyAsync(b + r.us, g.us, nc * sizeof(double), hipMemcpyDeviceToDevice, s.stream);
+        (void)hipMemcpyAsync(b + r.al, g.alpha, nc * sizeof(double), hipMemcpyDeviceToDevice, s.stream);
+        for (int d = 0; d < D; d++)
+            (void)hipMemcpyAsync(b + r.ap + (size_t)d * g.nfc, g.ap[d], (size_t)g.nfc * sizeof(double),
+                                 hipMemcpyDeviceToDevice, s.stream);
+        k_phi_merge<<<fill_blocks(), 256, 0, s.stream>>>(g, phin, b + r.phi);
+        (void)hipMemcpyAsync(b + r.M, g.M, nc, hipMemcpyDeviceToDevice, s.stream);
+    }
+    // ... and the geometry its mixing used
+    void rec_out(const double* cur)
+    {
+        StageRec& r = *s.stage_rec;
+        double* b = r.base + (size_t)r.next * r.stride;
+        (void)hipMemcpyAsync(b + r.aln, g.alpha, (size_t)g.nc * sizeof(double), hipMemcpyDeviceToDevice, s.stream);
+        k_phi_merge<<<fill_blocks(), 256, 0, s.stream>>>(g, cur, b + r.phin);
+        r.next++;
+    }
     void step_single(double dt)
     {
         int ns = s.o.rk;
@@ -3574,6 +3653,7 @@ struct Engine {
         const double* phin = g.phiP;
         for (int st = 0; st < ns; st++) {
             if (st > 0) interaction(in[0], in[1], phin, 0.0, 0);
+            if (s.stage_rec) rec_in(in, phin);
             ls_fork();
             double* out[2];
             for (int k = 0; k < 2; k++) {
@@ -3583,6 +3663,9 @@ struct Engine {
             const double* commit = nullptr;
             const double* cur = ls_stage(st, st == ns - 1, A[st], dt, phin, &commit);
             ls_join();
+            if (s.stage_rec) rec_out(cur);
+            else if (s.tape_fluid == 2 && !s.tape_ls.empty())
+                k_phi_merge<<<fill_blocks(), 256, 0, s.stream>>>(g, cur, s.tape_ls.back() + (size_t)st * g.nc);
             MixPart m1 = tm_part(1, out[1]);
             mix_fused(tm_part(0, out[0]), &m1, cur, commit);
             if (commit) cur = g.phiP;
@@ -3613,7 +3696,7 @@ struct Engine {
     bool graph_run_ok() const
     {
         const bool size_ok = s.o.graph == 2 || (s.o.graph == 1 && (long long)g.nc <= SIM_GRAPH_MAX_CELLS);
-        return size_ok && s.o.dt_fixed > 0.0 && !s.rec && !s.prof && !s.o.tape &&
+        return size_ok && s.o.dt_fixed > 0.0 && !s.rec && !s.prof && !s.o.tape && !replaying() &&
                (!s.o.autotune || s.tune_cur >= Sim::NTUNE);
     }
     static void put(std::vector<unsigned char>& v, const void* p, size_t n)
@@ -3960,6 +4043,10 @@ struct Engine {
     {
         long long done = 0;
         sim_status rc = SIM_OK;
+        if (mode != SIM_SINGLE_DT && replaying()) {
+            set_error("ls_replay covers single-dt steps only");
+            return SIM_EINVAL;
+        }
         // a state found non-physical at this call's first cycle start is
         // left as the call found it
         s.snap_valid = false;
@@ -4002,6 +4089,11 @@ struct Engine {
             if (mode == SIM_SINGLE_DT) {
                 double d = s.o.dt_fixed > 0.0 ? s.o.dt_fixed : (dt[0] < dt[1] ? dt[0] : dt[1]);
                 if (d > t_end - s.t) d = t_end - s.t;
+                if (replaying() && s.ls_pos + (size_t)s.o.rk > s.ls_src.size()) {
+                    set_error("ls_replay exhausted after %zu stages", s.ls_pos);
+                    rc = SIM_EINVAL;
+                    break;
+                }
                 if (s.o.tape) {
                     rc = tape_step(s, d);
                     if (rc != SIM_OK) break;
@@ -4116,6 +4208,9 @@ struct Engine {
         s.wcur = 0;
         s.vcur = 0;
         s.has_state = true;
+        s.ls_src.clear();
+        s.ls_pos = 0;
+        for (size_t i = 0; i < s.n_ls_rep; i++) s.ls_src.push_back(s.ls_rep + i * (size_t)g.nc);
         if (s.o.tape) return tape_begin(s, prim);
         return SIM_OK;
     }
@@ -4168,6 +4263,24 @@ void engine_bulk_stage(Sim& s, int k, const double* in, const double* base, doub
     case 1: Engine<1>(s).launch_stage<false>(s.stream, list, k, in, nullptr, base, out, a, dt, 0.0, 0, nullptr); break;
     case 2: Engine<2>(s).launch_stage<false>(s.stream, list, k, in, nullptr, base, out, a, dt, 0.0, 0, nullptr); break;
     default: Engine<3>(s).launch_stage<false>(s.stream, list, k, in, nullptr, base, out, a, dt, 0.0, 0, nullptr); break;
+    }
+}
+
+sim_status engine_restore(Sim& s, const double* X0, const double* X1, const double* phi)
+{
+    switch (s.g.D) {
+    case 1: return Engine<1>(s).restore_state(X0, X1, phi);
+    case 2: return Engine<2>(s).restore_state(X0, X1, phi);
+    default: return Engine<3>(s).restore_state(X0, X1, phi);
+    }
+}
+
+sim_status engine_replay_step(Sim& s, double dt, StageRec* rec)
+{
+    switch (s.g.D) {
+    case 1: return Engine<1>(s).replay_step(dt, rec);
+    case 2: return Engine<2>(s).replay_step(dt, rec);
+    default: return Engine<3>(s).replay_step(dt, rec);
     }
 }
 

@@ -1,0 +1,215 @@
+"""GPU adjoint of single-dt runs with an interface, the geometry frozen at
+the recorded stage level sets (Sec. 2.1 Eq. Eulerdiscrete with the exchange
+term, Sec. 2.2-2.3 mixing and extension): the level-set tape and its replay,
+against central finite differences of the oracle's own replayed run (the
+oracle records and replays its own level sets; nothing of the GPU's enters
+it), against central differences of the GPU's replayed run, and the
+checkpoint interval."""
+import numpy as np
+import pytest
+
+import _adjoint_cases as AC
+
+pytestmark = pytest.mark.gpu
+
+
+def _dt(c):
+    """a CFL-limited step of the initial state of both fluids"""
+    D = c["ndim"]
+    m = 0.0
+    for k in (0, 1):
+        W = c["prim"][k]
+        cs = np.sqrt(c["gamma"][k] * (W[D + 1] + c["pinf"][k]) / W[0])
+        m = max(m, float(np.max(sum((np.abs(W[1 + d]) + cs) / c["h"] for d in range(D)))))
+    return 0.6 / m
+
+
+def _gpu_taped(c, steps, dt, ckpt, rk=3):
+    import paper_1905_03917_amd as P
+    sim = P.Sim(c, tape=1, dt_fixed=dt, ckpt_every=ckpt, rk=rk)
+    sim.advance(1e30, mode=P.SIM_SINGLE_DT, max_cycles=steps)
+    _, cons, alpha = sim.state(device=False)
+    return sim, cons, alpha
+
+
+def _gpu_J(c, prim, gamma, pinf, tape, dt, steps, probes, rk=3):
+    import paper_1905_03917_amd as P
+    cc = dict(c, gamma=list(gamma), pinf=list(pinf))
+    cc.pop("phi")
+    cc.pop("prim")
+    sim = P.Sim(cc, ls_replay=tape, dt_fixed=dt, rk=rk)
+    sim.set_state(c["phi"], prim)
+    sim.advance(1e30, mode=P.SIM_SINGLE_DT, max_cycles=steps)
+    _, cons, alpha = sim.state(device=False)
+    sim.close()
+    return AC.interface_loss(cons, alpha, gamma, pinf, probes, c["ndim"])[0]
+
+
+def _oracle_J(c, prim, gamma, pinf, log, dt, steps, probes, rk=3):
+    from oracle import oracle as O
+    cc = dict(c, gamma=list(gamma), pinf=list(pinf))
+    s = O.OracleSim(cc, ls_replay=log, dt_replay=[dt] * (2 * steps), rk=rk)
+    s.set_state(c["phi"], prim)
+    s.advance(1e30, mode=0, max_cycles=steps)
+    _, cons, alpha = s.state()
+    return AC.interface_loss(cons, alpha, gamma, pinf, probes, c["ndim"])[0]
+
+
+def _oracle_log(c, dt, steps, rk=3):
+    from oracle import oracle as O
+    s = O.OracleSim(c, log_levelset=1, dt_replay=[dt] * (2 * steps), rk=rk)
+    s.advance(1e30, mode=0, max_cycles=steps)
+    return s.levelset_log()
+
+
+def _richardson(J, e):
+    """central difference quotient at e and e/2, extrapolated"""
+    q1 = (J(e) - J(-e)) / (2 * e)
+    q2 = (J(e / 2) - J(-e / 2)) / e
+    return q2 + (q2 - q1) / 3.0
+
+
+def _gradient(c, steps, ckpt, rk=3, fluid=None):
+    """taped GPU run and its adjoint for the pressure-probe loss (probes in
+    both fluids, or in `fluid` only)"""
+    dt = _dt(c)
+    sim, cons, alpha = _gpu_taped(c, steps, dt, ckpt, rk)
+    if fluid is None:
+        probes = AC.interface_probes(alpha, count=8)
+    else:
+        probes = AC.interface_probes(np.where(alpha == (1.0 if fluid == 0 else 0.0), alpha, 0.5), count=24)
+    J, gc, ge_loss = AC.interface_loss(cons, alpha, c["gamma"], c["pinf"], probes, c["ndim"])
+    gp, ge = sim.backward(gc)
+    tape = sim.levelset_tape()
+    sim.close()
+    return dict(dt=dt, J=J, probes=probes, gp=gp, ge=ge + ge_loss, tape=tape)
+
+
+CASES = [(1, 64, 3), (2, 24, 3), (2, 20, 2), (3, 12, 3)]
+
+
+@pytest.mark.parametrize("ndim,n,rk", CASES)
+def test_levelset_tape_replays_the_run(ndim, n, rk):
+    """the replayed run (stage level sets from the tape) reproduces the taped
+    one, and matches the oracle's replay of its own level sets"""
+    import paper_1905_03917_amd as P
+    from oracle import oracle as O
+    print("replay case ndim=%d n=%d rk=%d" % (ndim, n, rk), flush=True)
+    c = AC.interface_case(n, ndim)
+    steps, dt = 4, _dt(c)
+    sim, cons, alpha = _gpu_taped(c, steps, dt, 2, rk)
+    tape = sim.levelset_tape()
+    sim.close()
+    assert tape.shape == (steps * rk, c["phi"].size)
+    rep = P.Sim(c, ls_replay=tape, dt_fixed=dt, rk=rk)
+    rep.advance(1e30, mode=P.SIM_SINGLE_DT, max_cycles=steps)
+    _, cons2, alpha2 = rep.state(device=False)
+    # (the replay runs the unfused level-set path: the geometry kernels of
+    # the two paths may round differently; momentum is measured against
+    # sqrt(max rho max E), as in the parity tests)
+    scale = AC.state_scales(cons, ndim)
+    assert np.max(np.abs(cons2 - cons) / scale) <= 1e-12
+    assert np.max(np.abs(alpha2 - alpha)) <= 1e-13
+    # past the tape's end the replay refuses to go on
+    with pytest.raises(P.SimError):
+        rep.advance(1e30, mode=P.SIM_SINGLE_DT, max_cycles=1)
+    rep.close()
+    o = O.OracleSim(c, log_levelset=1, dt_replay=[dt] * (2 * steps), rk=rk)
+    o.advance(1e30, mode=0, max_cycles=steps)
+    log = o.levelset_log()
+    assert np.max(np.abs(log - tape)) <= 1e-10 * max(1.0, np.abs(log).max())
+    _, ocons, _ = o.state()
+    # four steps (the one-step bar is 1e-10): the two libraries' interface
+    # roots agree to the root's stopping tolerance only
+    assert np.max(np.abs(ocons - cons) / scale) <= 1e-9
+
+
+@pytest.mark.parametrize("ndim,n,rk", CASES)
+def test_gradient_matches_oracle_finite_differences(ndim, n, rk):
+    """directional derivatives along smooth perturbations of both fluids'
+    primitives, and each fluid's EOS parameters (for the loss on that
+    fluid's probes, where it is not buried under the other's), against
+    Richardson-extrapolated central differences of the oracle's replayed run
+    (1e-6 relative).  The steps are small because the map is piecewise
+    smooth: the LLF speed is a maximum, and in the water's energy flux it
+    multiplies a content of ~8e8 J/m^3, so a step that moves an argmax
+    changes the quotient; the steps are far above the interface root's
+    tolerance (~6e-5 Pa)."""
+    print("adjoint interface case ndim=%d n=%d rk=%d" % (ndim, n, rk), flush=True)
+    c = AC.interface_case(n, ndim)
+    steps = 6
+    e_dir = 1e-3 if ndim == 3 else 1e-2
+    r = _gradient(c, steps, ckpt=4, rk=rk)
+    log = _oracle_log(c, r["dt"], steps, rk)
+    g0, p0 = list(c["gamma"]), list(c["pinf"])
+
+    def Jp(e, dirn):
+        return _oracle_J(c, c["prim"] + e * dirn, g0, p0, log, r["dt"], steps, r["probes"], rk)
+
+    for seed in (7, 11):
+        dirn = AC.interface_direction(c, seed=seed)
+        want = _richardson(lambda e: Jp(e, dirn), e_dir)
+        got = float(np.sum(r["gp"] * dirn))
+        print("direction", seed, got, want, abs(got - want) / abs(want), flush=True)
+        assert abs(got - want) <= 1e-6 * abs(want), (seed, got, want)
+    steps_eos = {(0, 0): 1e-3 * g0[0], (0, 1): 100.0, (1, 0): 1e-6 * g0[1], (1, 1): 1e-6 * p0[1]}
+    for k in (0, 1):
+        rk_ = _gradient(c, steps, ckpt=4, rk=rk, fluid=k)
+        for j in (0, 1):
+            def Je(e, j=j):
+                g, p = list(g0), list(p0)
+                (g if j == 0 else p)[k] += e
+                return _oracle_J(c, c["prim"], g, p, log, r["dt"], steps, rk_["probes"], rk)
+            want = _richardson(Je, steps_eos[(k, j)])
+            got = float(rk_["ge"][k, j])
+            print("eos", k, j, got, want, abs(got - want) / abs(want), flush=True)
+            assert abs(got - want) <= 1e-6 * abs(want), (k, j, got, want)
+
+
+def test_gradient_matches_gpu_finite_differences_and_ignores_the_checkpoint_interval():
+    """2-D: the same directional derivative from central differences of the
+    GPU's own replayed run; checkpoints every 1, 3 and 10 steps give the same
+    gradient to rounding"""
+    c = AC.interface_case(24, 2)
+    steps = 6
+    ref = _gradient(c, steps, ckpt=3)
+    # (a segment's replay starts each cut cell's Riemann iteration from
+    # another previous root than the forward did, so the recomputed stages
+    # agree with the forward's to the root's tolerance, ~6e-10 relative, not
+    # bitwise)
+    for ck in (1, 10):
+        other = _gradient(c, steps, ckpt=ck)
+        scale = np.abs(ref["gp"]).max(axis=(0, 2), keepdims=True) + 1e-300
+        assert np.max(np.abs(other["gp"] - ref["gp"]) / scale) <= 1e-8, ck
+        assert np.allclose(other["ge"], ref["ge"], rtol=1e-8, atol=0.0), ck
+    dirn = AC.interface_direction(c, seed=7)
+    want = _richardson(lambda e: _gpu_J(c, c["prim"] + e * dirn, c["gamma"], c["pinf"], ref["tape"], ref["dt"],
+                                        steps, ref["probes"]), 1e-2)
+    got = float(np.sum(ref["gp"] * dirn))
+    assert abs(got - want) <= 1e-6 * abs(want), (got, want)
+
+
+def test_backward_restores_the_forward_state_and_refuses_accelerated_cycles():
+    import paper_1905_03917_amd as P
+    c = AC.interface_case(20, 2)
+    dt = _dt(c)
+    sim, cons, alpha = _gpu_taped(c, 3, dt, 2)
+    J, gc, _ = AC.interface_loss(cons, alpha, c["gamma"], c["pinf"], AC.interface_probes(alpha), 2)
+    sim.backward(gc)
+    _, cons2, alpha2 = sim.state(device=False)
+    assert np.array_equal(cons2, cons) and np.array_equal(alpha2, alpha)
+    # and the simulation goes on from there as the run without a backward
+    # (to the interface root's tolerance: its iteration starts from the
+    # replay's last roots)
+    sim.advance(1e30, mode=P.SIM_SINGLE_DT, max_cycles=1)
+    _, c3, _ = sim.state(device=False)
+    sim.close()
+    ref, _, _ = _gpu_taped(c, 4, dt, 2)
+    _, c4, _ = ref.state(device=False)
+    ref.close()
+    assert np.max(np.abs(c3 - c4) / AC.state_scales(c4, 2)) <= 1e-10
+    m = P.Sim(c, tape=1)
+    m.advance(1e30, mode=P.SIM_MULTI_DT, max_cycles=1)
+    with pytest.raises(P.SimError):
+        m.backward(np.zeros((2, 4, c["phi"].size)))
+    m.close()
