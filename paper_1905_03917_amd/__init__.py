@@ -359,9 +359,10 @@ def _advance_fn():
     import torch
 
     class AdvanceFn(torch.autograd.Function):
-        """cons_final = advance(prim0; gamma, p_inf) with single-dt steps on a
-        case whose grid one fluid fills; backward through sim_backward (step
-        lengths frozen at their forward values).
+        """cons_final = advance(prim0; gamma, p_inf) with single-dt steps;
+        backward through sim_backward (step lengths frozen at their forward
+        values; with an interface, the geometry frozen at the level sets the
+        forward recorded at each stage).
 
         prim0: [2][NV][cells] float64 CUDA tensor; eos: (2, 2) float64 tensor
         of (gamma, p_inf) per fluid; case: workload dict (its level set);
