@@ -624,22 +624,20 @@ __device__ __forceinline__ bool ext_target(const Dev& g, int k, const double* ph
     return true;
 }
 
-// one transposed Jacobi sweep: Wo = T^T Wi, gathered per cell from the
-// targets among the cell and its axis neighbours whose upwind stencil holds
-// it; a target's own entry is replaced by the sweep, other cells pass
+// The transposed sweep's gather for every cell, computed once per stage and
+// fluid (every sweep of a stage has the same targets and weights): the
+// cell's own entry passes (tx = 0) or is replaced (tx = 1), and up to 2D + 1
+// (source cell, weight) pairs are added; slots past `cnt` are unused.
+// Layout: cnt[c] = number of pairs | tx << 7; idx[m * nc + c], wt[m * nc + c].
 template <int D>
-__global__ void __launch_bounds__(ADJ_WG) k_adj2_extT(Dev g, int k, const double* phi, const double* al,
-                                                      const uint8_t* M, const double* Wi, double* Wo)
+__global__ void __launch_bounds__(ADJ_WG) k_adj2_extprep(Dev g, int k, const double* phi, const double* al,
+                                                         const uint8_t* M, uint8_t* cnt, int* idx, double* wt)
 {
-    constexpr int NV = D + 2;
     for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < g.nc; x += gridDim.x * blockDim.x) {
         double w[3];
         int up[3];
-        double acc[NV];
         const bool tx = ext_target<D>(g, k, phi, al, M, x, w, up);
-#pragma unroll
-        for (int q = 0; q < NV; q++) acc[q] = tx ? 0.0 : Wi[(size_t)q * g.nc + x];
-        int cand[1 + 2 * D], nc = 0;
+        int cand[1 + 2 * D], nc = 0, np = 0;
         cand[nc++] = x;
 #pragma unroll
         for (int d = 0; d < D; d++)
@@ -654,9 +652,31 @@ __global__ void __launch_bounds__(ADJ_WG) k_adj2_extT(Dev g, int k, const double
             if (!ext_target<D>(g, k, phi, al, M, c, w, up)) continue;
             for (int d = 0; d < D; d++) {
                 if (up[d] != x || w[d] == 0.0) continue;
-#pragma unroll
-                for (int q = 0; q < NV; q++) acc[q] += w[d] * Wi[(size_t)q * g.nc + c];
+                idx[(size_t)np * g.nc + x] = c;
+                wt[(size_t)np * g.nc + x] = w[d];
+                np++;
             }
+        }
+        cnt[x] = (uint8_t)(np | (tx ? 0x80 : 0));
+    }
+}
+
+// one transposed Jacobi sweep from the precomputed gathers (k_adj2_extprep)
+template <int D>
+__global__ void __launch_bounds__(ADJ_WG) k_adj2_extT2(Dev g, const uint8_t* cnt, const int* idx, const double* wt,
+                                                       const double* Wi, double* Wo)
+{
+    constexpr int NV = D + 2;
+    for (int x = blockIdx.x * blockDim.x + threadIdx.x; x < g.nc; x += gridDim.x * blockDim.x) {
+        const int cx = cnt[x], np = cx & 0x7f;
+        double acc[NV];
+#pragma unroll
+        for (int q = 0; q < NV; q++) acc[q] = (cx & 0x80) ? 0.0 : Wi[(size_t)q * g.nc + x];
+        for (int m = 0; m < np; m++) {
+            const int c = idx[(size_t)m * g.nc + x];
+            const double w = wt[(size_t)m * g.nc + x];
+#pragma unroll
+            for (int q = 0; q < NV; q++) acc[q] += w * Wi[(size_t)q * g.nc + c];
         }
 #pragma unroll
         for (int q = 0; q < NV; q++) Wo[(size_t)q * g.nc + x] = acc[q];
@@ -961,10 +981,14 @@ struct Adjoint {
         }
         double* S = alloc(own, sizeof(double) * nv);
         double* tmp = alloc(own, sizeof(double) * nv);
+        // the transposed extension's gathers of one stage and fluid
+        uint8_t* xcnt = reinterpret_cast<uint8_t*>(alloc(own, (size_t)g.nc + 8));
+        int* xidx = reinterpret_cast<int*>(alloc(own, sizeof(int) * (size_t)(2 * D + 1) * g.nc));
+        double* xwt = alloc(own, sizeof(double) * (size_t)(2 * D + 1) * g.nc);
         double* fb = alloc(own, sizeof(double) * (size_t)max_faces() * 6 * NV);
         double* pacc = alloc(own, sizeof(double) * 4 * ADJ_BLOCKS);
         double* fin = alloc(own, sizeof(double) * (2 * nv + g.nc));
-        bool ok = store && S && tmp && fb && pacc && fin;
+        bool ok = store && S && tmp && fb && pacc && fin && xcnt && xidx && xwt;
         for (int k = 0; k < 2; k++) ok = ok && lam[k] && lam0[k] && v[k] && Wb[k][0] && Wb[k][1];
         if (!ok) {
             set_error("adjoint buffers do not fit in device memory (%zu MB for %zu stage records)",
@@ -1024,9 +1048,12 @@ struct Adjoint {
                     const uint8_t* Mk = reinterpret_cast<const uint8_t*>(R + rec.M);
                     for (int k = 0; k < 2; k++) {
                         int cur = 0;
+                        if (s.o.ext_iters > 0)
+                            k_adj2_extprep<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, k, R + rec.phi, R + rec.al, Mk,
+                                                                                    xcnt, xidx, xwt);
                         for (int it = 0; it < s.o.ext_iters; it++) {
-                            k_adj2_extT<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, k, R + rec.phi, R + rec.al, Mk,
-                                                                                 Wb[k][cur], Wb[k][1 - cur]);
+                            k_adj2_extT2<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, xcnt, xidx, xwt, Wb[k][cur],
+                                                                                  Wb[k][1 - cur]);
                             cur ^= 1;
                         }
                         k_adj2_c2pT<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, R + rec.in[k], R + rec.al, Wb[k][cur],
