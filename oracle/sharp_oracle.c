@@ -1137,6 +1137,34 @@ static int prepare(or_sim* s, double* dt, long* cnt)
     return 0;
 }
 
+/* One stage of the level set (advection, and reinitialisation after a step's
+ * last stage), or, with ls_replay, the level set this stage had in the
+ * recorded run (frozen geometry); logged with log_levelset. */
+static int ls_step(or_sim* s, double a, double dt, int last)
+{
+    if (s->n_ls_rep > 0) {
+        if (s->ls_pos + s->nc > s->n_ls_rep) {
+            snprintf(g_err, sizeof g_err, "ls_replay exhausted after %ld stages", s->ls_pos / s->nc);
+            return -2;
+        }
+        memcpy(s->phi, s->ls_rep + s->ls_pos, sizeof(double) * (size_t)s->nc);
+        s->ls_pos += s->nc;
+    } else {
+        ls_stage(s, a, dt);
+        if (last) reinit(s);
+    }
+    if (s->P.log_levelset) {
+        if (s->n_lslog + s->nc > s->cap_lslog) {
+            s->cap_lslog = s->cap_lslog ? 2 * s->cap_lslog : 4 * s->nc;
+            if (s->cap_lslog < s->n_lslog + s->nc) s->cap_lslog = s->n_lslog + s->nc;
+            s->lslog = (double*)realloc(s->lslog, sizeof(double) * (size_t)s->cap_lslog);
+        }
+        memcpy(s->lslog + s->n_lslog, s->phi, sizeof(double) * (size_t)s->nc);
+        s->n_lslog += s->nc;
+    }
+    return 0;
+}
+
 /* ------------------------------------------------------------------------ */
 /* The original method: both fluids and the level set advance with one dt.    */
 /* Expects prepare() to have run on the current state.                        */
@@ -1163,27 +1191,8 @@ static int step_single(or_sim* s, double dt)
             out[k] = (st == ns - 1) ? s->X[k] : (st == 0 ? s->Y[k] : s->Z[k]);
             stage(s, k, in[k], s->X[k], out[k], A[st], dt, B[st] * dt);
         }
-        if (s->n_ls_rep > 0) {
-            /* frozen geometry: the level set this stage had in the recorded run */
-            if (s->ls_pos + s->nc > s->n_ls_rep) {
-                snprintf(g_err, sizeof g_err, "ls_replay exhausted after %ld stages", s->ls_pos / s->nc);
-                return -2;
-            }
-            memcpy(s->phi, s->ls_rep + s->ls_pos, sizeof(double) * (size_t)s->nc);
-            s->ls_pos += s->nc;
-        } else {
-            ls_stage(s, A[st], dt);
-            if (st == ns - 1) reinit(s);
-        }
-        if (s->P.log_levelset) {
-            if (s->n_lslog + s->nc > s->cap_lslog) {
-                s->cap_lslog = s->cap_lslog ? 2 * s->cap_lslog : 4 * s->nc;
-                if (s->cap_lslog < s->n_lslog + s->nc) s->cap_lslog = s->n_lslog + s->nc;
-                s->lslog = (double*)realloc(s->lslog, sizeof(double) * (size_t)s->cap_lslog);
-            }
-            memcpy(s->lslog + s->n_lslog, s->phi, sizeof(double) * (size_t)s->nc);
-            s->n_lslog += s->nc;
-        }
+        int rc = ls_step(s, A[st], dt, st == ns - 1);
+        if (rc) return rc;
         geometry(s);
         mix(s, 0, out[0]);
         mix(s, 1, out[1]);
@@ -1324,8 +1333,8 @@ static int cycle(or_sim* s, const double* dt, const long* cnt, double t_end, or_
             }
             double* out = (q == ns - 1) ? s->X[F] : (q == 0 ? s->Y[F] : s->Z[F]);
             stage(s, F, in, s->X[F], out, A[q], dl, B[q] * dl);
-            ls_stage(s, A[q], dl);
-            if (q == ns - 1) reinit(s);
+            rc = ls_step(s, A[q], dl, q == ns - 1);
+            if (rc) return rc;
             geometry(s);
             mix(s, F, out);
             in = out;
@@ -1379,10 +1388,6 @@ int or_advance(or_sim* s, double t_end, int mode, long max_cycles, or_stats* st)
     memset(st, 0, sizeof(*st));
     long done = 0;
     int rc = 0;
-    if (mode != 0 && (s->n_ls_rep > 0 || s->P.log_levelset)) {
-        snprintf(g_err, sizeof g_err, "level-set log and replay cover single-dt steps only");
-        return -1;
-    }
     while (s->t < t_end && (max_cycles <= 0 || done < max_cycles)) {
         double dt[2];
         long cnt[2];

@@ -48,10 +48,12 @@ typedef struct {
     const double* dt_replay;  /* n_dt_replay > 0: CFL steps taken instead of the
                                  computed ones, in or_schedule's order (copied) */
     long n_dt_replay;
-    int log_levelset;    /* record the level set after every single-dt stage */
-    const double* ls_replay;  /* n_ls_replay > 0: single-dt stages take these level
-                                 sets (cells each, in or_levelset_log's order)
-                                 instead of advecting and reinitialising (copied) */
+    int log_levelset;    /* record the level set after every stage that advances it */
+    const double* ls_replay;  /* n_ls_replay > 0: the stages that advance the level set
+                                 (every single-dt stage; every fast sub-step stage of an
+                                 accelerated cycle) take these level sets (cells each,
+                                 in or_levelset_log's order) instead of advecting and
+                                 reinitialising (copied) */
     long n_ls_replay;
 } or_params;
 
@@ -79,8 +81,10 @@ int or_advance(or_sim* s, double t_end, int mode, long max_cycles, or_stats* st)
  * fluid's at each later fast sub-step start (the order dt_replay follows).
  * Copies up to cap values to out (may be NULL); returns the total count. */
 long or_schedule(const or_sim* s, double* out, long cap);
-/* Level sets recorded with log_levelset: after each stage of each single-dt
- * step (the reinitialised one after the last stage), cells values each.
+/* Level sets recorded with log_levelset: after each stage that advances the
+ * level set (each single-dt stage, each fast sub-step stage of an
+ * accelerated cycle; the reinitialised one after a step's last stage),
+ * cells values each.
  * Copies up to cap values to out (may be NULL); returns the total count.
  * Replaying them (ls_replay) fixes the geometry of every stage, so that the
  * state at the end of the run is a function of the initial state and the

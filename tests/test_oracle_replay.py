@@ -47,11 +47,23 @@ def test_replaying_the_own_level_sets_reproduces_the_run():
     assert np.max(np.abs(log[-1] - case["phi"])) > 1e-9
 
 
-def test_replay_refuses_accelerated_cycles():
-    case = _case(16)
-    s = O.OracleSim(case, log_levelset=1)
+def test_replaying_accelerated_cycles_reproduces_them():
+    """accelerated cycles (Sec. 3.1): the fast sub-steps' stage level sets
+    and the CFL schedule replayed reproduce the run"""
+    case = _case(24)
+    a = O.OracleSim(case, log_levelset=1)
+    st = a.advance(1e30, mode=1, max_cycles=2)
+    assert st["steps"][0] != st["steps"][1]          # sub-stepping took place
+    log = a.levelset_log()
+    assert log.shape[0] == 3 * max(st["steps"])
+    b = O.OracleSim(case, ls_replay=log, dt_replay=a.schedule())
+    b.advance(1e30, mode=1, max_cycles=2)
+    pa, ca, _ = a.state()
+    pb, cb, _ = b.state()
+    assert np.array_equal(pa, pb) and np.array_equal(ca, cb)
+    # past the log's end the replay stops with an error
     with pytest.raises(RuntimeError):
-        s.advance(1e30, mode=1, max_cycles=1)
+        b.advance(1e30, mode=1, max_cycles=1)
 
 
 def test_the_replayed_map_is_smooth():
