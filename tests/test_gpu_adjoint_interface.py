@@ -88,6 +88,14 @@ def _gradient(c, steps, ckpt, rk=3, fluid=None):
 CASES = [(1, 64, 3), (2, 24, 3), (2, 20, 2), (3, 12, 3)]
 
 
+def _periodic_y(c):
+    """the same flat interface with the y direction periodic (the background
+    waves are periodic in y)"""
+    c = dict(c)
+    c["bc"] = [0, 1, 0]
+    return c
+
+
 @pytest.mark.parametrize("ndim,n,rk", CASES)
 def test_levelset_tape_replays_the_run(ndim, n, rk):
     """the replayed run (stage level sets from the tape) reproduces the taped
@@ -164,6 +172,22 @@ def test_gradient_matches_oracle_finite_differences(ndim, n, rk):
             got = float(rk_["ge"][k, j])
             print("eos", k, j, got, want, abs(got - want) / abs(want), flush=True)
             assert abs(got - want) <= 1e-6 * abs(want), (k, j, got, want)
+
+
+def test_gradient_with_a_periodic_direction_matches_oracle_finite_differences():
+    """2-D, y periodic: the transposed extension and mixing gather across the
+    periodic boundary"""
+    c = _periodic_y(AC.interface_case(20, 2))
+    steps = 6
+    r = _gradient(c, steps, ckpt=4)
+    log = _oracle_log(c, r["dt"], steps)
+    for seed in (7, 11):
+        dirn = AC.interface_direction(c, seed=seed)
+        want = _richardson(lambda e: _oracle_J(c, c["prim"] + e * dirn, c["gamma"], c["pinf"], log, r["dt"], steps,
+                                               r["probes"]), 1e-2)
+        got = float(np.sum(r["gp"] * dirn))
+        print("periodic direction", seed, got, want, abs(got - want) / abs(want), flush=True)
+        assert abs(got - want) <= 1e-6 * abs(want), (seed, got, want)
 
 
 def test_gradient_matches_gpu_finite_differences_and_ignores_the_checkpoint_interval():
