@@ -272,14 +272,16 @@ sim_status sim_profile_read(sim_t* s, double* ms, int64_t* launches, int64_t* ce
  * opts.ls_replay), so the derivative is that of the replayed run; the
  * exchange term's p*, u* are differentiated by the implicit function
  * theorem on the Riemann root; extension and mixing are linear maps with
- * their recorded coefficients.  Ghost states that the extension does not
- * reach (the values sim_set_state gives outside a fluid's region, and
- * older extension results) are taken as constants.  A run in which one
- * fluid fills the grid has no interface and none of these steps.  The
- * forward stores the state every ckpt_every steps (with an interface: both
- * fluids' contents and the level set, and every stage's level set); the
- * backward replays each segment from its checkpoint, every kernel on the
- * simulation's stream, and runs the reverse sweep through its stages.
+ * their recorded coefficients, and the ghost values an extension starts
+ * from (the previous extension's results; sim_set_state's primitives at
+ * the first) are differentiated through.  A run in which one fluid fills
+ * the grid has no interface and none of these steps.  The forward stores
+ * the state every ckpt_every steps (with an interface: both fluids'
+ * contents, the level set and the step-start interaction's results, and
+ * every stage's level set); the backward replays each segment from its
+ * checkpoint, every kernel on the simulation's stream, and runs the
+ * reverse sweep through its stages; the gradient does not depend on
+ * ckpt_every.
  * Afterwards the simulation holds the state the forward ended with.
  *   g_cons[2][NV][cells]  dJ/dcons at the end of the run (input)
  *   g_prim0[2][NV][cells] dJ/dprim given to sim_set_state (output; zero for

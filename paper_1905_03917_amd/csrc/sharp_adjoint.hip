@@ -374,6 +374,13 @@ __global__ void __launch_bounds__(ADJ_WG) k_adj_comb(long long n, double* lam, d
     }
 }
 
+// x += y (element-wise over n)
+__global__ void __launch_bounds__(ADJ_WG) k_adj_add(long long n, double* x, const double* y)
+{
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        x[e] += y[e];
+}
+
 // reverse of the initial map prim -> cons, alpha_k U(W) with
 // U = (rho, rho u, (p + gamma p_inf)/(gamma - 1) + rho |u|^2 / 2);
 // al: fluid 0's volume fraction of the initial geometry (null: 1)
@@ -683,6 +690,20 @@ __global__ void __launch_bounds__(ADJ_WG) k_adj2_extT2(Dev g, const uint8_t* cnt
     }
 }
 
+// the primitives' adjoint left on the cells that are not real cells of
+// fluid k (alpha_k < alpha_mix): there the extension's first sweep read the
+// values the previous extension left (or those sim_set_state gave)
+template <int D>
+__global__ void __launch_bounds__(ADJ_WG) k_adj2_ghost(Dev g, int k, const double* al, const double* Wb, double* carry)
+{
+    constexpr int NV = D + 2;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x) {
+        const bool real = frac_k(al, k, c) >= g.amix;
+#pragma unroll
+        for (int q = 0; q < NV; q++) carry[(size_t)q * g.nc + c] = real ? 0.0 : Wb[(size_t)q * g.nc + c];
+    }
+}
+
 // reverse of the primitive recovery W = W(U), U = content / alpha_k, on the
 // real cells of fluid k: v += (dW/dU)^T Wb / alpha_k, with its EOS partials
 template <int D>
@@ -981,6 +1002,9 @@ struct Adjoint {
         }
         double* S = alloc(own, sizeof(double) * nv);
         double* tmp = alloc(own, sizeof(double) * nv);
+        // adjoint of the ghost values an extension starts from (the previous
+        // interaction's extension results), carried to the stage before
+        double* carry[2] = {alloc(own, sizeof(double) * nv), alloc(own, sizeof(double) * nv)};
         // the transposed extension's gathers of one stage and fluid
         uint8_t* xcnt = reinterpret_cast<uint8_t*>(alloc(own, (size_t)g.nc + 8));
         int* xidx = reinterpret_cast<int*>(alloc(own, sizeof(int) * (size_t)(2 * D + 1) * g.nc));
@@ -988,7 +1012,7 @@ struct Adjoint {
         double* fb = alloc(own, sizeof(double) * (size_t)max_faces() * 6 * NV);
         double* pacc = alloc(own, sizeof(double) * 4 * ADJ_BLOCKS);
         double* fin = alloc(own, sizeof(double) * (2 * nv + g.nc));
-        bool ok = store && S && tmp && fb && pacc && fin && xcnt && xidx && xwt;
+        bool ok = store && S && tmp && fb && pacc && fin && xcnt && xidx && xwt && carry[0] && carry[1];
         for (int k = 0; k < 2; k++) ok = ok && lam[k] && lam0[k] && v[k] && Wb[k][0] && Wb[k][1];
         if (!ok) {
             set_error("adjoint buffers do not fit in device memory (%zu MB for %zu stage records)",
@@ -1000,9 +1024,11 @@ struct Adjoint {
         SHARP_HIP(hipMemcpyAsync(fin + nv, g.X[1], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
         SHARP_HIP(hipMemcpyAsync(fin + 2 * nv, g.phiP, sizeof(double) * g.nc, hipMemcpyDeviceToDevice, s.stream));
         SHARP_HIP(hipMemsetAsync(pacc, 0, sizeof(double) * 4 * ADJ_BLOCKS, s.stream));
-        for (int k = 0; k < 2; k++)
+        for (int k = 0; k < 2; k++) {
             SHARP_HIP(hipMemcpyAsync(lam[k], g_cons + (size_t)k * nv, sizeof(double) * nv, hipMemcpyDeviceToDevice,
                                      s.stream));
+            SHARP_HIP(hipMemsetAsync(carry[k], 0, sizeof(double) * nv, s.stream));
+        }
         const double t_end = s.t;
         const bool serial = s.run_serial;
         s.run_serial = true;
@@ -1016,10 +1042,21 @@ struct Adjoint {
             const long long s0 = seg * K, s1 = std::min(N, s0 + K);
             const double* ck = s.tape_ckpt[(size_t)seg];
             rc = engine_restore(s, ck, ck + nv, ck + 2 * nv);
+            if (rc != SIM_OK) break;
+            // the step-start interaction's results as the forward had them:
+            // the first step of the segment starts with its stages
+            for (int k = 0; k < 2; k++)
+                SHARP_HIP(hipMemcpyAsync(g.Wb[k][s.wcur], ck + 2 * nv + g.nc + (size_t)k * nv, sizeof(double) * nv,
+                                         hipMemcpyDeviceToDevice, s.stream));
+            SHARP_HIP(hipMemcpyAsync(g.ps, ck + 4 * nv + g.nc, sizeof(double) * g.nc, hipMemcpyDeviceToDevice,
+                                     s.stream));
+            SHARP_HIP(hipMemcpyAsync(g.us, ck + 4 * nv + 2 * g.nc, sizeof(double) * g.nc, hipMemcpyDeviceToDevice,
+                                     s.stream));
             s.ls_pos = (size_t)s0 * ns;
             rec.base = store;
             rec.next = 0;
-            for (long long st = s0; st < s1 && rc == SIM_OK; st++) rc = engine_replay_step(s, s.tape_dt[(size_t)st], &rec);
+            for (long long st = s0; st < s1 && rc == SIM_OK; st++)
+                rc = engine_replay_step(s, s.tape_dt[(size_t)st], &rec, st == s0);
             if (rc != SIM_OK) break;
             for (long long st = s1 - 1; st >= s0; st--) {
                 const double dt = s.tape_dt[(size_t)st];
@@ -1048,6 +1085,9 @@ struct Adjoint {
                     const uint8_t* Mk = reinterpret_cast<const uint8_t*>(R + rec.M);
                     for (int k = 0; k < 2; k++) {
                         int cur = 0;
+                        // the later stage's extension started from this
+                        // one's results
+                        k_adj_add<<<blocks((long long)nv), ADJ_WG, 0, s.stream>>>((long long)nv, Wb[k][0], carry[k]);
                         if (s.o.ext_iters > 0)
                             k_adj2_extprep<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, k, R + rec.phi, R + rec.al, Mk,
                                                                                     xcnt, xidx, xwt);
@@ -1058,6 +1098,7 @@ struct Adjoint {
                         }
                         k_adj2_c2pT<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, R + rec.in[k], R + rec.al, Wb[k][cur],
                                                                            v[k], pacc);
+                        k_adj2_ghost<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, k, R + rec.al, Wb[k][cur], carry[k]);
                         k_adj_comb<<<blocks((long long)nv), ADJ_WG, 0, s.stream>>>((long long)nv, lam[k], lam0[k], v[k],
                                                                                    A[q - 1], w, q == ns, q == 1);
                     }
@@ -1065,10 +1106,14 @@ struct Adjoint {
             }
             if (seg == 0) {
                 // initial map alpha_k U(W_k) with the initial geometry (the
-                // first record's)
-                for (int k = 0; k < 2; k++)
+                // first record's); the first extension started from the
+                // given primitives outside each fluid's real cells
+                for (int k = 0; k < 2; k++) {
                     k_adj_prim0<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, s.tape_prim0 + (size_t)k * nv, lam[k],
                                                                         g_prim0 + (size_t)k * nv, store + rec.al, pacc);
+                    k_adj_add<<<blocks((long long)nv), ADJ_WG, 0, s.stream>>>((long long)nv, g_prim0 + (size_t)k * nv,
+                                                                              carry[k]);
+                }
             }
         }
         s.ls_src.clear();
@@ -1124,7 +1169,7 @@ sim_status tape_step(Sim& s, double dt)
     const bool two = s.tape_fluid == 2;
     if (s.tape_dt.size() % (size_t)s.o.ckpt_every == 0) {
         double* p = nullptr;
-        const size_t n = two ? 2 * nv + nc : nv;
+        const size_t n = two ? 4 * nv + 3 * nc : nv;
         if (hipMalloc((void**)&p, sizeof(double) * n) != hipSuccess) {
             (void)hipGetLastError();
             set_error("tape checkpoint allocation failed");
@@ -1132,9 +1177,17 @@ sim_status tape_step(Sim& s, double dt)
         }
         s.tape_ckpt.push_back(p);
         if (two) {
+            // contents, level set, and what the step-start interaction left
+            // (taken after it: the replay starts with the step's stages)
             SHARP_HIP(hipMemcpyAsync(p, s.g.X[0], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
             SHARP_HIP(hipMemcpyAsync(p + nv, s.g.X[1], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
             SHARP_HIP(hipMemcpyAsync(p + 2 * nv, s.g.phiP, sizeof(double) * nc, hipMemcpyDeviceToDevice, s.stream));
+            for (int k = 0; k < 2; k++)
+                SHARP_HIP(hipMemcpyAsync(p + 2 * nv + nc + (size_t)k * nv, s.g.Wb[k][s.wcur], sizeof(double) * nv,
+                                         hipMemcpyDeviceToDevice, s.stream));
+            SHARP_HIP(hipMemcpyAsync(p + 4 * nv + nc, s.g.ps, sizeof(double) * nc, hipMemcpyDeviceToDevice, s.stream));
+            SHARP_HIP(hipMemcpyAsync(p + 4 * nv + 2 * nc, s.g.us, sizeof(double) * nc, hipMemcpyDeviceToDevice,
+                                     s.stream));
         } else {
             SHARP_HIP(hipMemcpyAsync(p, s.g.X[s.tape_fluid], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
         }

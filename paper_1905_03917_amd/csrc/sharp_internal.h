@@ -166,7 +166,10 @@ struct Sim {
     std::string tape_why;               // why this run cannot be differentiated
     std::vector<double> tape_dt;        // length of each taped step
     // state before steps 0, K, 2K, ... (K = o.ckpt_every): the contents of
-    // tape_fluid, or (tape_fluid = 2) of both fluids and the level set
+    // tape_fluid, or (tape_fluid = 2) of both fluids, the level set, and the
+    // results of the step-start interaction: both fluids' primitives after
+    // the extension (whose ghost values the next extension starts from) and
+    // the interface solution p*, u* (p* starts the next Riemann iterations)
     std::vector<double*> tape_ckpt;
     double* tape_prim0 = nullptr;       // primitives given to sim_set_state (tape_fluid, or both)
     std::vector<double*> tape_ls;       // tape_fluid = 2: per step, the level set after each stage
@@ -222,9 +225,10 @@ void engine_bulk_stage(Sim& s, int k, const double* in, const double* base, doub
 // contents X0, X1 and level set phi (device), geometry and tile lists
 // rebuilt from phi; then single-dt steps of length dt, every kernel on the
 // simulation's stream, their stage level sets taken from s.ls_src and
-// their stages copied to *rec
+// their stages copied to *rec (`prepared`: the step-start interaction's
+// results are in place already, so the step starts with its stages)
 sim_status engine_restore(Sim& s, const double* X0, const double* X1, const double* phi);
-sim_status engine_replay_step(Sim& s, double dt, StageRec* rec);
+sim_status engine_replay_step(Sim& s, double dt, StageRec* rec, bool prepared);
 // conservation ledger (sharp_ledger.hip): out10[k*5 + q] = sum_c dV cons[k][q][c], zero for q >= NV
 sim_status engine_totals(Sim& s, double* out10);
 // the same through the device's file-scope scratch array (sharp_ledger.hip):

@@ -3496,13 +3496,15 @@ struct Engine {
         return SIM_OK;
     }
     // one single-dt step of length dt from the current state (the stage
-    // level sets from s.ls_src), its stages recorded to *rec
-    sim_status replay_step(double dt, StageRec* rec)
+    // level sets from s.ls_src), its stages recorded to *rec; `prepared`:
+    // the step-start interaction's results (primitives, interface solution)
+    // are already in place, restored with the state
+    sim_status replay_step(double dt, StageRec* rec, bool prepared)
     {
         double d[2];
         long long cnt[2];
         s.stage_rec = rec;
-        sim_status rc = prepare(true, d, cnt);
+        sim_status rc = prepared ? SIM_OK : prepare(true, d, cnt);
         if (rc == SIM_OK) {
             step_single(dt);
             join();
@@ -4275,12 +4277,12 @@ sim_status engine_restore(Sim& s, const double* X0, const double* X1, const doub
     }
 }
 
-sim_status engine_replay_step(Sim& s, double dt, StageRec* rec)
+sim_status engine_replay_step(Sim& s, double dt, StageRec* rec, bool prepared)
 {
     switch (s.g.D) {
-    case 1: return Engine<1>(s).replay_step(dt, rec);
-    case 2: return Engine<2>(s).replay_step(dt, rec);
-    default: return Engine<3>(s).replay_step(dt, rec);
+    case 1: return Engine<1>(s).replay_step(dt, rec, prepared);
+    case 2: return Engine<2>(s).replay_step(dt, rec, prepared);
+    default: return Engine<3>(s).replay_step(dt, rec, prepared);
     }
 }
 

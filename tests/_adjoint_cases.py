@@ -74,6 +74,52 @@ def interface_case(n, ndim=2, seed=3):
     return c
 
 
+def curved_case(n, ndim=2, seed=3, radius=0.3):
+    """A water column (2-D) or droplet (3-D) of the given radius at the
+    centre, in air (phi = |x - c| - R, fluid 0 = water inside), with the same
+    background waves as interface_case: the extension then runs along both
+    or all axes with weights from the normal, and the mixing has diagonal
+    targets."""
+    h = 1.0 / n
+    c0 = 0.5 + np.random.default_rng(seed).uniform(-0.3, 0.3, size=ndim) * h
+    x = (np.arange(n) + 0.5) * h
+    grids = np.meshgrid(*([x] * ndim), indexing="ij")
+    r2 = 0.0
+    for d in range(ndim):
+        r2 = r2 + (grids[ndim - 1 - d].reshape(-1) - c0[d]) ** 2
+    phi = np.sqrt(r2) - radius
+    nc = n ** ndim
+    prim = np.zeros((2, ndim + 2, nc))
+    prim[0, 0] = 1000.0
+    prim[0, ndim + 1] = 1.0e5
+    prim[1, 0] = 1.0
+    prim[1, ndim + 1] = 1.0e5
+    c = dict(ndim=ndim, n=[n if d < ndim else 1 for d in range(3)], lo=[0.0, 0.0, 0.0], h=h,
+             bc=[0, 0, 0], gamma=[4.4, 1.4], pinf=[6.0e8, 0.0], phi=phi, prim=prim,
+             t_end=1e30, name="column_%dd" % ndim)
+    _background(c, ndim, n)
+    return c
+
+
+def _background(c, ndim, n):
+    """smooth waves in every primitive of both fluids (see interface_case)"""
+    x = (np.arange(n) + 0.5) * c["h"]
+    grids = np.meshgrid(*([x] * ndim), indexing="ij")
+
+    def wave(ph):
+        w = np.sin(2 * np.pi * (grids[ndim - 1].reshape(-1) + ph))
+        for d in range(1, ndim):
+            w = w * np.cos(2 * np.pi * (grids[ndim - 1 - d].reshape(-1) - 0.2 * d + ph))
+        return w
+
+    for k in (0, 1):
+        c["prim"][k, 0] *= 1.0 + 0.03 * wave(0.3 + 0.1 * k)
+        c["prim"][k, 1] += 20.0 + 10.0 * wave(0.05 + 0.2 * k)
+        for d in range(1, ndim):
+            c["prim"][k, 1 + d] += 5.0 * wave(0.15 * d + 0.1 * k)
+        c["prim"][k, ndim + 1] += 5.0e3 * wave(0.1)
+
+
 def _flat_case(n, ndim, seed):
     """air (x < xi) / water (x > xi) with a Gaussian pulse in the air, 1-D or 3-D"""
     h = 1.0 / n
