@@ -253,3 +253,31 @@ def test_backward_restores_the_forward_state_and_refuses_accelerated_cycles():
     with pytest.raises(P.SimError):
         m.backward(np.zeros((2, 4, c["phi"].size)))
     m.close()
+
+
+def test_levelset_replay_argument_errors():
+    """the replay's arguments are checked at sim_create and the tape's
+    read-out needs a tape with an interface"""
+    import paper_1905_03917_amd as P
+    c = AC.interface_case(16, 2)
+    nc = c["phi"].size
+    with pytest.raises(P.SimError) as e:
+        P.Sim(c, ls_replay=np.zeros(nc + 1))            # not a whole number of level sets
+    assert e.value.status == -1
+    with pytest.raises(P.SimError) as e:
+        P.Sim(c, ls_replay=np.zeros(nc), tape=1)       # a replay records no tape
+    assert e.value.status == -1
+    s = P.Sim(c)
+    s.advance(1e30, mode=P.SIM_SINGLE_DT, max_cycles=1)
+    with pytest.raises(P.SimError) as e:
+        s.levelset_tape()
+    assert e.value.status == -5
+    s.close()
+    r = P.Sim(c, ls_replay=np.tile(c["phi"], 3), dt_fixed=_dt(c))
+    with pytest.raises(P.SimError) as e:
+        r.advance(1e30, mode=P.SIM_MULTI_DT, max_cycles=1)   # single-dt steps only
+    assert e.value.status == -1
+    r.advance(1e30, mode=P.SIM_SINGLE_DT, max_cycles=1)       # three stage level sets: one step
+    with pytest.raises(P.SimError):
+        r.advance(1e30, mode=P.SIM_SINGLE_DT, max_cycles=1)
+    r.close()
