@@ -51,6 +51,12 @@ constexpr int ADJ_BLOCKS = 1024;   // fixed grid of the kernels with per-block p
 
 const double ADJ_RK3_A[3] = {0.0, 0.75, 1.0 / 3.0};
 const double ADJ_RK2_A[2] = {0.0, 0.5};
+// stage times (c) and quadrature weights (b) of the Shu-Osher tables: the
+// accelerated cycle's interpolation and correction weights (Sec. 3.1)
+const double ADJ_RK3_B[3] = {1.0 / 6.0, 1.0 / 6.0, 2.0 / 3.0};
+const double ADJ_RK3_C[3] = {0.0, 1.0, 0.5};
+const double ADJ_RK2_B[2] = {0.5, 0.5};
+const double ADJ_RK2_C[2] = {0.0, 1.0};
 
 // reverse of the WENO5-JS value w(v0..v4) (left-biased, at the right edge
 // of v2): vb += gb * dw/dv.  With candidate values q_k, smoothness
@@ -604,6 +610,111 @@ __global__ void __launch_bounds__(ADJ_WG) k_adj2_riemann(Dev g, const double* ap
     block_add4(par, pacc);
 }
 
+// the exchange term's partials of one of its uses, accumulated per cut
+// cell: X_k = s_k (0, -p* g, -p* u* |g|) enters with weight `scale` against
+// the adjoint lam (a stage's (1 - a) dt, or a correction weight), s_0 = 1,
+// s_1 = -1; pb += dJ/dp*, ub += dJ/du*
+template <int D>
+__global__ void __launch_bounds__(ADJ_WG) k_adj2_xacc(Dev g, const double* ap, const double* ps, const double* us,
+                                                      const double* lam, double scale, double* pb, double* ub)
+{
+    constexpr int NV = D + 2;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x) {
+        int i, j, kk;
+        coords(g, c, i, j, kk);
+        double gv[3], g2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            const double* a = ap + (size_t)d * g.nfc;
+            gv[d] = (a[fidx(g, i, j, kk)] - a[fidx(g, i + (d == 0), j + (d == 1), kk + (d == 2))]) / g.h;
+            g2 += gv[d] * gv[d];
+        }
+        const double gn = sqrt(g2);
+        if (!(gn > 0.0)) continue;
+        double dot = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; d++) dot += gv[d] * lam[(size_t)(1 + d) * g.nc + c];
+        const double lE = lam[(size_t)(NV - 1) * g.nc + c];
+        pb[c] += scale * (-dot - us[c] * gn * lE);
+        ub[c] += scale * (-ps[c] * gn * lE);
+    }
+}
+
+// the Riemann problem's reverse from accumulated dJ/dp*, dJ/du* (see
+// k_adj2_riemann, which forms them from the two fluids' stage adjoints)
+template <int D>
+__global__ void __launch_bounds__(ADJ_WG) k_adj2_riemann2(Dev g, const double* ap, const double* W0, const double* W1,
+                                                          const double* ps, const double* pbv, const double* ubv,
+                                                          double* Wb0, double* Wb1, double* pacc)
+{
+    constexpr int NV = D + 2;
+    double par[4] = {0.0, 0.0, 0.0, 0.0};
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x) {
+        const double pb = pbv[c], ub = ubv[c];
+        if (pb == 0.0 && ub == 0.0) continue;
+        int i, j, kk;
+        coords(g, c, i, j, kk);
+        double gv[3], g2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            const double* a = ap + (size_t)d * g.nfc;
+            gv[d] = (a[fidx(g, i, j, kk)] - a[fidx(g, i + (d == 0), j + (d == 1), kk + (d == 2))]) / g.h;
+            g2 += gv[d] * gv[d];
+        }
+        const double gn = sqrt(g2);
+        if (!(gn > 0.0)) continue;
+        const double pst = ps[c];
+        double dfl, dfr, al4[4], ar4[4];
+        wave_partials(W0[c], W0[(size_t)(NV - 1) * g.nc + c], g.gam[0], g.pinf[0], pst, &dfl, al4);
+        wave_partials(W1[c], W1[(size_t)(NV - 1) * g.nc + c], g.gam[1], g.pinf[1], pst, &dfr, ar4);
+        const double pfl = -(g.pinf[0] < g.pinf[1] ? g.pinf[0] : g.pinf[1]);
+        const double G = 0.5 * (dfr - dfl);
+        const double sig = !(pst > pfl) ? 0.0 : (pb + ub * G) / (dfl + dfr);
+        const double uL = sig + 0.5 * ub, uR = -sig + 0.5 * ub;
+        const double cl = -(sig + 0.5 * ub), cr = -(sig - 0.5 * ub);
+        Wb0[c] += cl * al4[0];
+        Wb0[(size_t)(NV - 1) * g.nc + c] += cl * al4[1];
+        Wb1[c] += cr * ar4[0];
+        Wb1[(size_t)(NV - 1) * g.nc + c] += cr * ar4[1];
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            Wb0[(size_t)(1 + d) * g.nc + c] += uL * gv[d] / gn;
+            Wb1[(size_t)(1 + d) * g.nc + c] += uR * gv[d] / gn;
+        }
+        par[0] += cl * al4[2];
+        par[1] += cl * al4[3];
+        par[2] += cr * ar4[2];
+        par[3] += cr * ar4[3];
+    }
+    block_add4(par, pacc);
+}
+
+// reverse of X_S += corr on the momentum and energy components: the
+// correction's adjoint gains the slow fluid's
+template <int D>
+__global__ void __launch_bounds__(ADJ_WG) k_adj2_corrT(Dev g, const double* lx, double* lc)
+{
+    constexpr int NV = D + 2;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x)
+#pragma unroll
+        for (int q = 1; q < NV; q++) lc[(size_t)q * g.nc + c] += lx[(size_t)q * g.nc + c];
+}
+
+// x = a x + b y (element-wise over n)
+__global__ void __launch_bounds__(ADJ_WG) k_adj_axpby(long long n, double* x, double a, const double* y, double b)
+{
+    for (long long e = blockIdx.x * (long long)blockDim.x + threadIdx.x; e < n; e += (long long)gridDim.x * blockDim.x)
+        x[e] = a * x[e] + b * y[e];
+}
+
+// the level set a stage saw over every cell (its band-mask cells from the
+// working buffer, the others from the base one)
+__global__ void __launch_bounds__(ADJ_WG) k_adj_phi(Dev g, const double* cur, double* out)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x)
+        out[c] = g.M[c] ? cur[c] : g.phiP[c];
+}
+
 // Extension of fluid k (Sec. 2.3): target cells are band cells with
 // alpha_k < alpha_mix within ext_band cells on the far side of the
 // interface with a nonzero level-set gradient; each Jacobi sweep sets a
@@ -879,10 +990,40 @@ struct Adjoint {
     sim_status run(const double* g_cons, double* g_prim0, double* g_eos)
     {
         std::vector<void*> own;
-        sim_status rc = s.tape_fluid == 2 ? sweep2(g_cons, g_prim0, g_eos, own) : sweep(g_cons, g_prim0, g_eos, own);
+        bool cycles = false;
+        for (const Sim::TapeUnit& u : s.tape_units) cycles = cycles || u.cycle;
+        sim_status rc = s.tape_fluid != 2 ? sweep(g_cons, g_prim0, g_eos, own)
+                                          : (cycles ? sweep3(g_cons, g_prim0, g_eos, own)
+                                                    : sweep2(g_cons, g_prim0, g_eos, own));
         (void)hipStreamSynchronize(s.stream);
         for (void* p : own) (void)hipFree(p);
         return rc;
+    }
+
+    // what the last interaction left (both fluids' extended primitives, p*,
+    // u* and the extended level-set velocity) to or from p (2 NV + 2 + D
+    // cells values): the state a step starts from besides the contents and
+    // the level set
+    hipError_t save_interaction(double* p, bool back)
+    {
+        const size_t nv = (size_t)NV * g.nc, nc = (size_t)g.nc;
+        double* dst[4 + D];
+        double* src[4 + D];
+        size_t n[4 + D];
+        dst[0] = p; src[0] = g.Wb[0][s.wcur]; n[0] = nv;
+        dst[1] = p + nv; src[1] = g.Wb[1][s.wcur]; n[1] = nv;
+        dst[2] = p + 2 * nv; src[2] = g.ps; n[2] = nc;
+        dst[3] = p + 2 * nv + nc; src[3] = g.us; n[3] = nc;
+        for (int d = 0; d < D; d++) {
+            dst[4 + d] = p + 2 * nv + (2 + d) * nc;
+            src[4 + d] = g.v[s.vcur][d];
+            n[4 + d] = nc;
+        }
+        hipError_t e = hipSuccess;
+        for (int i = 0; i < 4 + D && e == hipSuccess; i++)
+            e = hipMemcpyAsync(back ? src[i] : dst[i], back ? dst[i] : src[i], n[i] * sizeof(double),
+                               hipMemcpyDeviceToDevice, s.stream);
+        return e;
     }
 
     double* alloc(std::vector<void*>& own, size_t bytes)
@@ -1011,7 +1152,7 @@ struct Adjoint {
         double* xwt = alloc(own, sizeof(double) * (size_t)(2 * D + 1) * g.nc);
         double* fb = alloc(own, sizeof(double) * (size_t)max_faces() * 6 * NV);
         double* pacc = alloc(own, sizeof(double) * 4 * ADJ_BLOCKS);
-        double* fin = alloc(own, sizeof(double) * (2 * nv + g.nc));
+        double* fin = alloc(own, sizeof(double) * (4 * nv + (3 + D) * g.nc));
         bool ok = store && S && tmp && fb && pacc && fin && xcnt && xidx && xwt && carry[0] && carry[1];
         for (int k = 0; k < 2; k++) ok = ok && lam[k] && lam0[k] && v[k] && Wb[k][0] && Wb[k][1];
         if (!ok) {
@@ -1023,6 +1164,7 @@ struct Adjoint {
         SHARP_HIP(hipMemcpyAsync(fin, g.X[0], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
         SHARP_HIP(hipMemcpyAsync(fin + nv, g.X[1], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
         SHARP_HIP(hipMemcpyAsync(fin + 2 * nv, g.phiP, sizeof(double) * g.nc, hipMemcpyDeviceToDevice, s.stream));
+        SHARP_HIP(save_interaction(fin + 2 * nv + g.nc, false));
         SHARP_HIP(hipMemsetAsync(pacc, 0, sizeof(double) * 4 * ADJ_BLOCKS, s.stream));
         for (int k = 0; k < 2; k++) {
             SHARP_HIP(hipMemcpyAsync(lam[k], g_cons + (size_t)k * nv, sizeof(double) * nv, hipMemcpyDeviceToDevice,
@@ -1120,6 +1262,376 @@ struct Adjoint {
         s.ls_pos = 0;
         s.run_serial = serial;
         sim_status r2 = engine_restore(s, fin, fin + nv, fin + 2 * nv);
+        if (r2 == SIM_OK && save_interaction(fin + 2 * nv + g.nc, true) != hipSuccess) r2 = SIM_EDEVICE;
+        s.t = t_end;
+        if (rc != SIM_OK) return rc;
+        if (r2 != SIM_OK) return r2;
+        return read_params(pacc, g_eos);
+    }
+    // ---- accelerated cycles (Sec. 3.1) with an interface ----
+    // The segment's units (single-dt steps and accelerated cycles) are
+    // recomputed by a forward composed of single engine operations in the
+    // order of the method's steps, which records every interaction (its two
+    // inputs, the extended primitives, p*, u*, the geometry and level set)
+    // and the geometry of every mixing, and lists the operations; the
+    // reverse walks that list backwards with one adjoint per state buffer
+    // and, per interaction, the accumulated dJ/dp*, dJ/du* and primitive
+    // adjoints, which it turns into its inputs' adjoints once every use of
+    // the interaction is reversed.
+    enum { BX0, BX1, BY0, BY1, BZ0, BZ1, BT2, BFH, BCORR, NBUF };
+    enum OpKind { OP_IX, OP_STAGE, OP_MIX, OP_INTERP, OP_COPY, OP_CORR, OP_CORR_ZERO, OP_CORR_APPLY };
+    struct Op {
+        OpKind kind;
+        int k, r, in, base, out;   // fluid, record (interaction or geometry), buffers
+        double a, dt;              // stage coefficient and length; interpolation weight; correction weight
+    };
+    double* bufptr(int id) const
+    {
+        switch (id) {
+        case BX0: return g.X[0];
+        case BX1: return g.X[1];
+        case BY0: return g.Y[0];
+        case BY1: return g.Y[1];
+        case BZ0: return g.Z[0];
+        case BZ1: return g.Z[1];
+        case BT2: return g.T2;
+        case BFH: return g.Fh;
+        default: return g.corr;
+        }
+    }
+
+    sim_status sweep3(const double* g_cons, double* g_prim0, double* g_eos, std::vector<void*>& own)
+    {
+        const int ns = s.o.rk;
+        const double* A = ns == 3 ? ADJ_RK3_A : ADJ_RK2_A;
+        const double* B = ns == 3 ? ADJ_RK3_B : ADJ_RK2_B;
+        const double* C = ns == 3 ? ADJ_RK3_C : ADJ_RK2_C;
+        const size_t nv = (size_t)NV * g.nc, nc = (size_t)g.nc;
+        const long long N = (long long)s.tape_units.size();
+        const int K = s.o.ckpt_every;
+        const long long nseg = (N + K - 1) / K;
+        // records per unit: interactions and mixings
+        auto counts = [&](const Sim::TapeUnit& u, size_t& nix, size_t& ngeo) {
+            if (!u.cycle) { nix += ns; ngeo += 2 * ns; return; }
+            const size_t m = u.sub.size();
+            nix += 1 + (m - 1) + m * (ns - 1) + (ns == 3 ? 1 : 0);
+            ngeo += (m - 1) + m * (ns - 1) + m * ns + (ns == 3 ? 1 : 0) + 1;
+        };
+        size_t maxix = 1, maxgeo = 1;
+        for (long long seg = 0; seg < nseg; seg++) {
+            size_t a = 0, b = 0;
+            for (long long u = seg * K; u < std::min(N, (seg + 1) * K); u++) counts(s.tape_units[(size_t)u], a, b);
+            maxix = std::max(maxix, a);
+            maxgeo = std::max(maxgeo, b);
+        }
+        StageRec rec;
+        rec.layout(D, nc, (size_t)g.nfc);
+        const size_t gstride = 2 * nc;                       // geometry record: alpha, level set
+        const size_t astride = 2 * nv + 2 * nc;              // per interaction: W-bar 0, 1, p*-bar, u*-bar
+        double* store = alloc(own, sizeof(double) * rec.stride * maxix);
+        double* geo = alloc(own, sizeof(double) * gstride * maxgeo);
+        double* acc = alloc(own, sizeof(double) * astride * maxix);
+        double* lam[NBUF];
+        bool ok = store && geo && acc;
+        for (int b = 0; b < NBUF; b++) ok = ok && (lam[b] = alloc(own, sizeof(double) * nv)) != nullptr;
+        double* L = alloc(own, sizeof(double) * nv);
+        double* v = alloc(own, sizeof(double) * nv);
+        double* Wt = alloc(own, sizeof(double) * nv);
+        double* Wx[2] = {alloc(own, sizeof(double) * nv), alloc(own, sizeof(double) * nv)};
+        double* S = alloc(own, sizeof(double) * nv);
+        double* tmp = alloc(own, sizeof(double) * nv);
+        double* carry[2] = {alloc(own, sizeof(double) * nv), alloc(own, sizeof(double) * nv)};
+        uint8_t* xcnt = reinterpret_cast<uint8_t*>(alloc(own, nc + 8));
+        int* xidx = reinterpret_cast<int*>(alloc(own, sizeof(int) * (size_t)(2 * D + 1) * nc));
+        double* xwt = alloc(own, sizeof(double) * (size_t)(2 * D + 1) * nc);
+        double* fb = alloc(own, sizeof(double) * (size_t)max_faces() * 6 * NV);
+        double* pacc = alloc(own, sizeof(double) * 4 * ADJ_BLOCKS);
+        double* fin = alloc(own, sizeof(double) * (4 * nv + (3 + D) * nc));
+        ok = ok && L && v && Wt && Wx[0] && Wx[1] && S && tmp && carry[0] && carry[1] && xcnt && xidx && xwt && fb &&
+             pacc && fin;
+        if (!ok) {
+            set_error("adjoint buffers do not fit in device memory (%zu interaction records of %zu MB)", maxix,
+                      sizeof(double) * rec.stride >> 20);
+            return SIM_ENOMEM;
+        }
+        SHARP_HIP(hipMemcpyAsync(fin, g.X[0], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
+        SHARP_HIP(hipMemcpyAsync(fin + nv, g.X[1], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
+        SHARP_HIP(hipMemcpyAsync(fin + 2 * nv, g.phiP, sizeof(double) * nc, hipMemcpyDeviceToDevice, s.stream));
+        SHARP_HIP(save_interaction(fin + 2 * nv + nc, false));
+        SHARP_HIP(hipMemsetAsync(pacc, 0, sizeof(double) * 4 * ADJ_BLOCKS, s.stream));
+        for (int b = 0; b < NBUF; b++) SHARP_HIP(hipMemsetAsync(lam[b], 0, sizeof(double) * nv, s.stream));
+        for (int k = 0; k < 2; k++) {
+            SHARP_HIP(hipMemcpyAsync(lam[BX0 + k], g_cons + (size_t)k * nv, sizeof(double) * nv,
+                                     hipMemcpyDeviceToDevice, s.stream));
+            SHARP_HIP(hipMemsetAsync(carry[k], 0, sizeof(double) * nv, s.stream));
+        }
+        const double t_end = s.t;
+        const bool serial = s.run_serial;
+        s.run_serial = true;
+        g.use_sched = 0;
+        s.ls_src.clear();
+        for (double* p : s.tape_ls)
+            for (int q = 0; q < ns; q++) s.ls_src.push_back(p + (size_t)q * nc);
+        const int nb = blocks((long long)nv);
+        std::vector<Op> ops;
+        size_t nix = 0, ngeo = 0;
+        // ---- recording helpers of the composed forward ----
+        auto ix = [&](int id0, int id1, const double* cur) {
+            double* b = store + nix * rec.stride;
+            const double* in[2] = {bufptr(id0), bufptr(id1)};
+            for (int k = 0; k < 2; k++) {
+                (void)hipMemcpyAsync(b + rec.in[k], in[k], nv * sizeof(double), hipMemcpyDeviceToDevice, s.stream);
+                (void)hipMemcpyAsync(b + rec.W[k], g.Wb[k][s.wcur], nv * sizeof(double), hipMemcpyDeviceToDevice,
+                                     s.stream);
+            }
+            (void)hipMemcpyAsync(b + rec.ps, g.ps, nc * sizeof(double), hipMemcpyDeviceToDevice, s.stream);
+            (void)hipMemcpyAsync(b + rec.us, g.us, nc * sizeof(double), hipMemcpyDeviceToDevice, s.stream);
+            (void)hipMemcpyAsync(b + rec.al, g.alpha, nc * sizeof(double), hipMemcpyDeviceToDevice, s.stream);
+            for (int d = 0; d < D; d++)
+                (void)hipMemcpyAsync(b + rec.ap + (size_t)d * g.nfc, g.ap[d], (size_t)g.nfc * sizeof(double),
+                                     hipMemcpyDeviceToDevice, s.stream);
+            k_adj_phi<<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, cur, b + rec.phi);
+            (void)hipMemcpyAsync(b + rec.M, g.M, nc, hipMemcpyDeviceToDevice, s.stream);
+            ops.push_back({OP_IX, 0, (int)nix, id0, id1, 0, 0.0, 0.0});
+            return (int)nix++;
+        };
+        auto mixop = [&](int k, int id, const double* cur) {
+            engine_op_mix(s, k, bufptr(id), cur);
+            double* b = geo + ngeo * gstride;
+            (void)hipMemcpyAsync(b, g.alpha, nc * sizeof(double), hipMemcpyDeviceToDevice, s.stream);
+            k_adj_phi<<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, cur, b + nc);
+            ops.push_back({OP_MIX, k, (int)ngeo++, id, id, id, 0.0, 0.0});
+        };
+        auto stageop = [&](int k, int r, int in, int base, int out, double a, double dt) {
+            engine_op_stage(s, k, bufptr(in), bufptr(base), bufptr(out), a, dt);
+            ops.push_back({OP_STAGE, k, r, in, base, out, a, dt});
+        };
+        auto interp = [&](int S_, double th) {
+            engine_op_axpby(s, 1.0 - th, bufptr(BX0 + S_), th, bufptr(BY0 + S_), g.T2);
+            ops.push_back({OP_INTERP, S_, 0, BX0 + S_, BY0 + S_, BT2, th, 0.0});
+        };
+        const bool use_corr = !s.o.no_correction;
+        auto corr = [&](int r, double w, int S_) {
+            if (!use_corr) return;
+            engine_op_corr_add(s, w, S_);
+            ops.push_back({OP_CORR, S_, r, 0, 0, 0, w, 0.0});
+        };
+        sim_status rc = SIM_OK;
+        for (long long seg = nseg - 1; seg >= 0 && rc == SIM_OK; seg--) {
+            const long long u0 = seg * K, u1 = std::min(N, u0 + K);
+            const double* ck = s.tape_ckpt[(size_t)seg];
+            rc = engine_restore(s, ck, ck + nv, ck + 2 * nv);
+            if (rc != SIM_OK) break;
+            for (int k = 0; k < 2; k++)
+                SHARP_HIP(hipMemcpyAsync(g.Wb[k][s.wcur], ck + 2 * nv + nc + (size_t)k * nv, sizeof(double) * nv,
+                                         hipMemcpyDeviceToDevice, s.stream));
+            SHARP_HIP(hipMemcpyAsync(g.ps, ck + 4 * nv + nc, sizeof(double) * nc, hipMemcpyDeviceToDevice, s.stream));
+            SHARP_HIP(hipMemcpyAsync(g.us, ck + 4 * nv + 2 * nc, sizeof(double) * nc, hipMemcpyDeviceToDevice,
+                                     s.stream));
+            SHARP_HIP(hipMemsetAsync(g.corr, 0, sizeof(double) * nv, s.stream));
+            s.ls_pos = s.tape_units[(size_t)u0].ls_block * ns;
+            ops.clear();
+            nix = ngeo = 0;
+            // ---- the composed forward of the segment ----
+            for (long long ui = u0; ui < u1 && rc == SIM_OK; ui++) {
+                const Sim::TapeUnit& u = s.tape_units[(size_t)ui];
+                if (ui > u0) rc = engine_op_prepare(s);
+                if (rc != SIM_OK) break;
+                if (!u.cycle) {
+                    int in[2] = {BX0, BX1};
+                    const double* phin = g.phiP;
+                    for (int q = 0; q < ns; q++) {
+                        if (q > 0) engine_op_interaction(s, bufptr(in[0]), bufptr(in[1]), phin);
+                        const int r = ix(in[0], in[1], phin);
+                        int out[2];
+                        for (int k = 0; k < 2; k++) {
+                            out[k] = q == ns - 1 ? BX0 + k : (q == 0 ? BY0 + k : BZ0 + k);
+                            stageop(k, r, in[k], BX0 + k, out[k], A[q], u.t1);
+                        }
+                        const double* cur = engine_op_ls(s, q, q == ns - 1, A[q], u.t1, phin);
+                        for (int k = 0; k < 2; k++) mixop(k, out[k], cur);
+                        in[0] = out[0];
+                        in[1] = out[1];
+                        phin = cur;
+                    }
+                    continue;
+                }
+                const int Sf = u.S, F = 1 - Sf;
+                const double t1 = u.t1;
+                const int XS = BX0 + Sf, XF = BX0 + F;
+                auto order = [&](int sid, int fid, int& id0, int& id1) {
+                    id0 = Sf == 0 ? sid : fid;
+                    id1 = Sf == 0 ? fid : sid;
+                };
+                const int r0 = ix(BX0, BX1, g.phiP);
+                ops.push_back({OP_CORR_ZERO, 0, 0, 0, 0, 0, 0.0, 0.0});
+                stageop(Sf, r0, XS, XS, BY0 + Sf, A[0], t1);
+                double tau = 0.0;
+                int last = r0;
+                for (size_t j = 0; j < u.sub.size(); j++) {
+                    const double dl = u.sub[j].dl;
+                    const int hh = u.sub[j].hh, fin_ = u.sub[j].fin;
+                    int in = XF;
+                    const double* phin = g.phiP;
+                    if (j > 0) {
+                        engine_op_mask(s);
+                        interp(Sf, tau / t1);
+                        mixop(Sf, BT2, g.phiP);
+                        int i0, i1;
+                        order(BT2, XF, i0, i1);
+                        engine_op_interaction(s, bufptr(i0), bufptr(i1), g.phiP);
+                        last = ix(i0, i1, g.phiP);
+                    } else {
+                        corr(r0, -B[0] * t1 + B[0] * dl, Sf);
+                    }
+                    for (int q = 0; q < ns; q++) {
+                        if (q > 0) {
+                            const bool shared = fin_ && C[q] == 1.0;
+                            const double th = shared ? 1.0 : (tau + C[q] * dl) / t1;
+                            interp(Sf, th);
+                            mixop(Sf, BT2, phin);
+                            int i0, i1;
+                            order(BT2, in, i0, i1);
+                            engine_op_interaction(s, bufptr(i0), bufptr(i1), phin);
+                            last = ix(i0, i1, phin);
+                            corr(last, shared ? -B[q] * t1 + B[q] * dl : B[q] * dl, Sf);
+                            if (shared) stageop(Sf, last, BT2, XS, ns == 2 ? XS : BZ0 + Sf, A[q], t1);
+                        } else if (j > 0) {
+                            corr(last, B[0] * dl, Sf);
+                        }
+                        const int out = q == ns - 1 ? XF : (q == 0 ? BY0 + F : BZ0 + F);
+                        stageop(F, last, in, XF, out, A[q], dl);
+                        const double* cur = engine_op_ls(s, q, q == ns - 1, A[q], dl, phin);
+                        mixop(F, out, cur);
+                        in = out;
+                        phin = cur;
+                    }
+                    tau = hh ? 0.5 * t1 : (fin_ ? t1 : tau + dl);
+                    if (hh) {
+                        SHARP_HIP(hipMemcpyAsync(g.Fh, g.X[F], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
+                        SHARP_HIP(hipMemcpyAsync(g.phiH, g.phiP, sizeof(double) * nc, hipMemcpyDeviceToDevice,
+                                                 s.stream));
+                        ops.push_back({OP_COPY, 0, 0, XF, 0, BFH, 0.0, 0.0});
+                    }
+                }
+                if (ns == 3) {
+                    engine_op_geom(s, g.phiH);
+                    SHARP_HIP(hipMemcpyAsync(g.T2, g.Z[Sf], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
+                    ops.push_back({OP_COPY, 0, 0, BZ0 + Sf, 0, BT2, 0.0, 0.0});
+                    mixop(Sf, BT2, g.phiH);
+                    int i0, i1;
+                    order(BT2, BFH, i0, i1);
+                    engine_op_interaction(s, bufptr(i0), bufptr(i1), g.phiH);
+                    const int rh = ix(i0, i1, g.phiH);
+                    corr(rh, -B[2] * t1, Sf);
+                    stageop(Sf, rh, BT2, XS, XS, A[2], t1);
+                    engine_op_geom(s, g.phiP);
+                }
+                if (use_corr) {
+                    engine_op_corr_apply(s, Sf);
+                    ops.push_back({OP_CORR_APPLY, Sf, 0, 0, 0, 0, 0.0, 0.0});
+                }
+                mixop(Sf, XS, g.phiP);
+            }
+            if (rc != SIM_OK) break;
+            // ---- the reverse of the segment ----
+            SHARP_HIP(hipMemsetAsync(acc, 0, sizeof(double) * astride * nix, s.stream));
+            for (size_t oi = ops.size(); oi-- > 0;) {
+                const Op& o = ops[oi];
+                switch (o.kind) {
+                case OP_CORR_APPLY:
+                    k_adj2_corrT<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, lam[BX0 + o.k], lam[BCORR]);
+                    break;
+                case OP_MIX: {
+                    const double* gr = geo + (size_t)o.r * gstride;
+                    k_adj2_mixT<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, o.k, gr, gr + nc, lam[o.out], tmp);
+                    std::swap(lam[o.out], tmp);
+                    break;
+                }
+                case OP_INTERP:
+                    k_adj_axpby<<<nb, ADJ_WG, 0, s.stream>>>((long long)nv, lam[o.in], 1.0, lam[o.out], 1.0 - o.a);
+                    k_adj_axpby<<<nb, ADJ_WG, 0, s.stream>>>((long long)nv, lam[o.base], 1.0, lam[o.out], o.a);
+                    SHARP_HIP(hipMemsetAsync(lam[o.out], 0, sizeof(double) * nv, s.stream));
+                    break;
+                case OP_COPY:
+                    k_adj_add<<<nb, ADJ_WG, 0, s.stream>>>((long long)nv, lam[o.in], lam[o.out]);
+                    SHARP_HIP(hipMemsetAsync(lam[o.out], 0, sizeof(double) * nv, s.stream));
+                    break;
+                case OP_CORR_ZERO:
+                    SHARP_HIP(hipMemsetAsync(lam[BCORR], 0, sizeof(double) * nv, s.stream));
+                    break;
+                case OP_CORR: {
+                    const double* R = store + (size_t)o.r * rec.stride;
+                    double* a = acc + (size_t)o.r * astride;
+                    const double sg = o.k == 0 ? 1.0 : -1.0;
+                    k_adj2_xacc<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, R + rec.ap, R + rec.ps, R + rec.us,
+                                                                         lam[BCORR], sg * o.a, a + 2 * nv,
+                                                                         a + 2 * nv + nc);
+                    break;
+                }
+                case OP_STAGE: {
+                    const double* R = store + (size_t)o.r * rec.stride;
+                    double* a = acc + (size_t)o.r * astride;
+                    const int k = o.k;
+                    const double w = 1.0 - o.a, sg = k == 0 ? 1.0 : -1.0;
+                    SHARP_HIP(hipMemcpyAsync(L, lam[o.out], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
+                    SHARP_HIP(hipMemsetAsync(lam[o.out], 0, sizeof(double) * nv, s.stream));
+                    if (o.a != 0.0) k_adj_axpby<<<nb, ADJ_WG, 0, s.stream>>>((long long)nv, lam[o.base], 1.0, L, o.a);
+                    k_adj2_sten<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, k, R + rec.in[k], R + rec.al, R + rec.W[k],
+                                                                         S);
+                    jlt(k, S, L, w * o.dt, v, fb, pacc, R + rec.ap);
+                    k_adj2_split<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, R + rec.al, R + rec.W[k], v, Wt, pacc);
+                    k_adj_add<<<nb, ADJ_WG, 0, s.stream>>>((long long)nv, a + (size_t)k * nv, Wt);
+                    k_adj_axpby<<<nb, ADJ_WG, 0, s.stream>>>((long long)nv, lam[o.in], 1.0, L, w);
+                    k_adj_add<<<nb, ADJ_WG, 0, s.stream>>>((long long)nv, lam[o.in], v);
+                    k_adj2_xacc<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, R + rec.ap, R + rec.ps, R + rec.us, L,
+                                                                         sg * w * o.dt, a + 2 * nv, a + 2 * nv + nc);
+                    break;
+                }
+                case OP_IX: {
+                    const double* R = store + (size_t)o.r * rec.stride;
+                    double* a = acc + (size_t)o.r * astride;
+                    k_adj2_riemann2<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, R + rec.ap, R + rec.W[0], R + rec.W[1],
+                                                                           R + rec.ps, a + 2 * nv, a + 2 * nv + nc,
+                                                                           a, a + nv, pacc);
+                    const uint8_t* Mk = reinterpret_cast<const uint8_t*>(R + rec.M);
+                    const int ids[2] = {o.in, o.base};
+                    for (int k = 0; k < 2; k++) {
+                        SHARP_HIP(hipMemcpyAsync(Wx[0], a + (size_t)k * nv, sizeof(double) * nv,
+                                                 hipMemcpyDeviceToDevice, s.stream));
+                        k_adj_add<<<nb, ADJ_WG, 0, s.stream>>>((long long)nv, Wx[0], carry[k]);
+                        int cur = 0;
+                        if (s.o.ext_iters > 0)
+                            k_adj2_extprep<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, k, R + rec.phi, R + rec.al, Mk,
+                                                                                    xcnt, xidx, xwt);
+                        for (int it = 0; it < s.o.ext_iters; it++) {
+                            k_adj2_extT2<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, xcnt, xidx, xwt, Wx[cur],
+                                                                                  Wx[1 - cur]);
+                            cur ^= 1;
+                        }
+                        k_adj2_c2pT<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, R + rec.in[k], R + rec.al, Wx[cur],
+                                                                           lam[ids[k]], pacc);
+                        k_adj2_ghost<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, k, R + rec.al, Wx[cur], carry[k]);
+                    }
+                    break;
+                }
+                }
+            }
+            if (seg == 0) {
+                for (int k = 0; k < 2; k++) {
+                    k_adj_prim0<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, k, s.tape_prim0 + (size_t)k * nv,
+                                                                        lam[BX0 + k], g_prim0 + (size_t)k * nv,
+                                                                        store + rec.al, pacc);
+                    k_adj_add<<<nb, ADJ_WG, 0, s.stream>>>((long long)nv, g_prim0 + (size_t)k * nv, carry[k]);
+                }
+            }
+        }
+        s.ls_src.clear();
+        s.ls_pos = 0;
+        s.run_serial = serial;
+        sim_status r2 = engine_restore(s, fin, fin + nv, fin + 2 * nv);
+        if (r2 == SIM_OK && save_interaction(fin + 2 * nv + g.nc, true) != hipSuccess) r2 = SIM_EDEVICE;
+        SHARP_HIP(hipMemsetAsync(g.corr, 0, sizeof(double) * nv, s.stream));
         s.t = t_end;
         if (rc != SIM_OK) return rc;
         if (r2 != SIM_OK) return r2;
@@ -1135,6 +1647,7 @@ void tape_clear(Sim& s)
     s.tape_ckpt.clear();
     for (double* p : s.tape_ls) (void)hipFree(p);
     s.tape_ls.clear();
+    s.tape_units.clear();
     s.tape_dt.clear();
     if (s.tape_prim0) (void)hipFree(s.tape_prim0);
     s.tape_prim0 = nullptr;
@@ -1162,45 +1675,93 @@ sim_status tape_begin(Sim& s, const double* prim_dev)
     return SIM_OK;
 }
 
+// a checkpoint of a two-fluid tape: contents, level set, and what the
+// unit's start interaction left
+static sim_status tape_checkpoint2(Sim& s)
+{
+    const size_t nv = (size_t)(s.g.D + 2) * s.g.nc, nc = (size_t)s.g.nc;
+    double* p = nullptr;
+    if (hipMalloc((void**)&p, sizeof(double) * (4 * nv + 3 * nc)) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("tape checkpoint allocation failed");
+        return SIM_ENOMEM;
+    }
+    s.tape_ckpt.push_back(p);
+    SHARP_HIP(hipMemcpyAsync(p, s.g.X[0], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
+    SHARP_HIP(hipMemcpyAsync(p + nv, s.g.X[1], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
+    SHARP_HIP(hipMemcpyAsync(p + 2 * nv, s.g.phiP, sizeof(double) * nc, hipMemcpyDeviceToDevice, s.stream));
+    for (int k = 0; k < 2; k++)
+        SHARP_HIP(hipMemcpyAsync(p + 2 * nv + nc + (size_t)k * nv, s.g.Wb[k][s.wcur], sizeof(double) * nv,
+                                 hipMemcpyDeviceToDevice, s.stream));
+    SHARP_HIP(hipMemcpyAsync(p + 4 * nv + nc, s.g.ps, sizeof(double) * nc, hipMemcpyDeviceToDevice, s.stream));
+    SHARP_HIP(hipMemcpyAsync(p + 4 * nv + 2 * nc, s.g.us, sizeof(double) * nc, hipMemcpyDeviceToDevice, s.stream));
+    return SIM_OK;
+}
+
+// one block of stage level sets (a single-dt step or a fast sub-step)
+static sim_status tape_ls_block(Sim& s)
+{
+    double* p = nullptr;
+    if (hipMalloc((void**)&p, sizeof(double) * (size_t)s.o.rk * s.g.nc) != hipSuccess) {
+        (void)hipGetLastError();
+        set_error("level-set tape allocation failed");
+        return SIM_ENOMEM;
+    }
+    s.tape_ls.push_back(p);
+    return SIM_OK;
+}
+
+sim_status tape_cycle(Sim& s, int S, double t1)
+{
+    if (s.tape_fluid != 2) return SIM_OK;
+    if (s.tape_units.size() % (size_t)s.o.ckpt_every == 0) {
+        sim_status rc = tape_checkpoint2(s);
+        if (rc != SIM_OK) return rc;
+    }
+    Sim::TapeUnit u;
+    u.cycle = 1;
+    u.S = S;
+    u.t1 = t1;
+    u.ls_block = s.tape_ls.size();
+    s.tape_units.push_back(u);
+    return SIM_OK;
+}
+
+sim_status tape_sub(Sim& s)
+{
+    if (s.tape_fluid != 2 || s.tape_units.empty()) return SIM_OK;
+    s.tape_units.back().sub.push_back({0.0, 0, 0});
+    return tape_ls_block(s);
+}
+
 sim_status tape_step(Sim& s, double dt)
 {
     if (s.tape_fluid < 0) return SIM_OK;
-    const size_t nv = (size_t)(s.g.D + 2) * s.g.nc, nc = (size_t)s.g.nc;
+    const size_t nv = (size_t)(s.g.D + 2) * s.g.nc;
     const bool two = s.tape_fluid == 2;
+    if (two) {
+        if (s.tape_units.size() % (size_t)s.o.ckpt_every == 0) {
+            sim_status rc = tape_checkpoint2(s);
+            if (rc != SIM_OK) return rc;
+        }
+        Sim::TapeUnit u;
+        u.t1 = dt;
+        u.ls_block = s.tape_ls.size();
+        s.tape_units.push_back(u);
+        sim_status rc = tape_ls_block(s);
+        if (rc != SIM_OK) return rc;
+        s.tape_dt.push_back(dt);
+        return SIM_OK;
+    }
     if (s.tape_dt.size() % (size_t)s.o.ckpt_every == 0) {
         double* p = nullptr;
-        const size_t n = two ? 4 * nv + 3 * nc : nv;
-        if (hipMalloc((void**)&p, sizeof(double) * n) != hipSuccess) {
+        if (hipMalloc((void**)&p, sizeof(double) * nv) != hipSuccess) {
             (void)hipGetLastError();
             set_error("tape checkpoint allocation failed");
             return SIM_ENOMEM;
         }
         s.tape_ckpt.push_back(p);
-        if (two) {
-            // contents, level set, and what the step-start interaction left
-            // (taken after it: the replay starts with the step's stages)
-            SHARP_HIP(hipMemcpyAsync(p, s.g.X[0], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
-            SHARP_HIP(hipMemcpyAsync(p + nv, s.g.X[1], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
-            SHARP_HIP(hipMemcpyAsync(p + 2 * nv, s.g.phiP, sizeof(double) * nc, hipMemcpyDeviceToDevice, s.stream));
-            for (int k = 0; k < 2; k++)
-                SHARP_HIP(hipMemcpyAsync(p + 2 * nv + nc + (size_t)k * nv, s.g.Wb[k][s.wcur], sizeof(double) * nv,
-                                         hipMemcpyDeviceToDevice, s.stream));
-            SHARP_HIP(hipMemcpyAsync(p + 4 * nv + nc, s.g.ps, sizeof(double) * nc, hipMemcpyDeviceToDevice, s.stream));
-            SHARP_HIP(hipMemcpyAsync(p + 4 * nv + 2 * nc, s.g.us, sizeof(double) * nc, hipMemcpyDeviceToDevice,
-                                     s.stream));
-        } else {
-            SHARP_HIP(hipMemcpyAsync(p, s.g.X[s.tape_fluid], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
-        }
-    }
-    if (two) {
-        // the step's stage level sets, written by the step itself
-        double* p = nullptr;
-        if (hipMalloc((void**)&p, sizeof(double) * (size_t)s.o.rk * nc) != hipSuccess) {
-            (void)hipGetLastError();
-            set_error("level-set tape allocation failed");
-            return SIM_ENOMEM;
-        }
-        s.tape_ls.push_back(p);
+        SHARP_HIP(hipMemcpyAsync(p, s.g.X[s.tape_fluid], sizeof(double) * nv, hipMemcpyDeviceToDevice, s.stream));
     }
     s.tape_dt.push_back(dt);
     return SIM_OK;

@@ -172,7 +172,19 @@ struct Sim {
     // the interface solution p*, u* (p* starts the next Riemann iterations)
     std::vector<double*> tape_ckpt;
     double* tape_prim0 = nullptr;       // primitives given to sim_set_state (tape_fluid, or both)
-    std::vector<double*> tape_ls;       // tape_fluid = 2: per step, the level set after each stage
+    std::vector<double*> tape_ls;       // tape_fluid = 2: per step or fast sub-step, the level set after each stage
+    // tape_fluid = 2: every single-dt step and accelerated cycle, in order
+    // (checkpoints every ckpt_every of them); a cycle lists its slow fluid,
+    // length and fast sub-steps
+    struct TapeSub { double dl; int hh, fin; };
+    struct TapeUnit {
+        int cycle = 0;          // 0: a single-dt step of length t1
+        int S = 0;
+        double t1 = 0.0;
+        size_t ls_block = 0;    // index of its first tape_ls block
+        std::vector<TapeSub> sub;
+    };
+    std::vector<TapeUnit> tape_units;
     // level-set replay: the stages of single-dt steps take these level sets
     // (device arrays of cells values, in stage order) instead of their own
     // advection and reinitialisation, which fixes every stage's geometry
@@ -239,6 +251,22 @@ sim_status engine_totals_noalloc(Sim& s, double* out10, int on_device);
 void tape_clear(Sim& s);
 sim_status tape_begin(Sim& s, const double* prim_dev);
 sim_status tape_step(Sim& s, double dt);
+// an accelerated cycle (slow fluid S, length t1) starts / one of its fast
+// sub-steps starts (its length and flags are set once known)
+sim_status tape_cycle(Sim& s, int S, double t1);
+sim_status tape_sub(Sim& s);
+// the composed forward of the adjoint's recomputation: one engine
+// operation each, every kernel on the simulation's stream
+sim_status engine_op_prepare(Sim& s);
+void engine_op_interaction(Sim& s, const double* in0, const double* in1, const double* cur);
+void engine_op_stage(Sim& s, int k, const double* in, const double* base, double* out, double a, double dt);
+const double* engine_op_ls(Sim& s, int q, bool last, double a, double dt, const double* phin);
+void engine_op_mix(Sim& s, int k, double* buf, const double* cur);
+void engine_op_mask(Sim& s);
+void engine_op_geom(Sim& s, const double* phi);
+void engine_op_corr_add(Sim& s, double w, int S);
+void engine_op_corr_apply(Sim& s, int S);
+void engine_op_axpby(Sim& s, double a1, const double* x, double a2, const double* y, double* dst);
 sim_status engine_backward(Sim& s, const double* g_cons, double* g_prim0, double* g_eos);
 
 // reduction word holding the lowest (cell << 1 | fluid) code of a cell found

@@ -3512,6 +3512,21 @@ struct Engine {
         s.stage_rec = nullptr;
         return rc;
     }
+    // ---- single operations of the adjoint's composed forward ----
+    sim_status op_prepare()
+    {
+        double d[2];
+        long long cnt[2];
+        return prepare(true, d, cnt);
+    }
+    void op_corr_apply(int S)
+    {
+        go<b_corr_apply<D>, SHARP_WG>(k_corr_apply<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, S, 1);
+    }
+    void op_axpby_all(double a1, const double* x, double a2, const double* y, double* dst)
+    {
+        go<b_axpby<D>, SHARP_WG>(k_axpby<D>, grid(LIST_ALL), wg(), s.stream, g, LIST_ALL, a1, x, a2, y, dst, NV);
+    }
     // reductions and error flags to zero, no non-physical cell recorded
     hipError_t reset_flags()
     {
@@ -3895,7 +3910,12 @@ struct Engine {
             plan_cycle(dt[S], dt[F], rem, s.o.n_thr, &dtS, &single);
             if (single && s.o.force_cycle && dtS >= dt[F] * (1.0 - 1e-12)) single = 0;
         }
+        const bool taped = s.o.tape && s.tape_fluid == 2 && !s.stage_rec;
         if (single) {
+            if (taped) {
+                sim_status rc = tape_step(s, dtS);
+                if (rc != SIM_OK) return rc;
+            }
             step_single(dtS);
             st->cycles++;
             for (int k = 0; k < 2; k++) { st->steps[k]++; st->cell_updates[k] += cnt[k]; }
@@ -3905,6 +3925,10 @@ struct Engine {
         const bool corr = !s.o.no_correction;
         double t1 = dtS;
         st->last_n = t1 / dt[F];
+        if (taped) {
+            sim_status rc = tape_cycle(s, S, t1);
+            if (rc != SIM_OK) return rc;
+        }
         // (1) slow fluid's first stage with dt_S on the cycle-start interaction
         stage(S, g.X[S], nullptr, g.X[S], g.Y[S], A[0], t1, B[0] * t1);
         double tau = 0.0, dtF = dt[F];
@@ -3936,6 +3960,8 @@ struct Engine {
             const double* commit = nullptr;
             const double* cur = ls_stage(q, q == ns - 1, A[q], dl, phin, &commit);
             ls_join();
+            if (taped)
+                k_phi_merge<<<fill_blocks(), 256, 0, s.stream>>>(g, cur, s.tape_ls.back() + (size_t)q * g.nc);
             if (q + 1 < ns) {
                 // the slow fluid's state for the next stage, Eq. (interpolation)
                 double theta1 = (fin && C[q + 1] == 1.0) ? 1.0 : (tau + C[q + 1] * dl) / t1;
@@ -3957,6 +3983,10 @@ struct Engine {
             double dl = 0.0;
             const double* in = g.X[F];
             const double* phin = g.phiP;
+            if (taped) {
+                sim_status rc = tape_sub(s);
+                if (rc != SIM_OK) return rc;
+            }
             if (!first) {
                 mask(LIST_BAND, 1);
                 interp_slow(S, tau / t1, g.phiP);
@@ -4009,6 +4039,7 @@ struct Engine {
                 dl = next_substep(tau, t1, dtF, ns, half_done, &hh, &fin);
                 if (first && corr) corr_add(-B[0] * t1 + B[0] * dl, S);
             }
+            if (taped) s.tape_units.back().sub.back() = {dl, hh, fin};
             for (int q = q0; q < ns; q++) fast_stage(q, in, phin, dl, fin, false);
             st->steps[F]++;
             st->cell_updates[F] += cntF;
@@ -4105,9 +4136,9 @@ struct Engine {
                 for (int k = 0; k < 2; k++) { st->steps[k]++; st->cell_updates[k] += cnt[k]; }
                 st->last_n = 1.0;
             } else {
-                if (s.o.tape && s.tape_fluid >= 0) {
+                if (s.o.tape && s.tape_fluid >= 0 && s.tape_fluid != 2) {
                     s.tape_fluid = -1;
-                    s.tape_why = "the run took accelerated (multi-dt) cycles: the tape records single-dt steps";
+                    s.tape_why = "a run in which one fluid fills the grid took accelerated (multi-dt) cycles";
                 }
                 rc = cycle(dt, cnt, t_end, st);
                 if (rc != SIM_OK) break;
@@ -4285,6 +4316,58 @@ sim_status engine_replay_step(Sim& s, double dt, StageRec* rec, bool prepared)
     default: return Engine<3>(s).replay_step(dt, rec, prepared);
     }
 }
+
+#define SHARP_ENGINE(call)                 \
+    switch (s.g.D) {                       \
+    case 1: { Engine<1> e(s); call; } break; \
+    case 2: { Engine<2> e(s); call; } break; \
+    default: { Engine<3> e(s); call; } break; \
+    }
+sim_status engine_op_prepare(Sim& s)
+{
+    sim_status rc = SIM_OK;
+    SHARP_ENGINE(rc = e.op_prepare());
+    return rc;
+}
+void engine_op_interaction(Sim& s, const double* in0, const double* in1, const double* cur)
+{
+    SHARP_ENGINE(e.interaction(in0, in1, cur, 0.0, 0, false));
+}
+void engine_op_stage(Sim& s, int k, const double* in, const double* base, double* out, double a, double dt)
+{
+    SHARP_ENGINE(e.stage(k, in, nullptr, base, out, a, dt, 0.0, 0, nullptr); e.join());
+}
+const double* engine_op_ls(Sim& s, int q, bool last, double a, double dt, const double* phin)
+{
+    const double* cur = nullptr;
+    SHARP_ENGINE(cur = e.ls_chain(q, last, a, dt, phin, nullptr));
+    return cur;
+}
+void engine_op_mix(Sim& s, int k, double* buf, const double* cur)
+{
+    SHARP_ENGINE(e.mix(k, buf, cur));
+}
+void engine_op_mask(Sim& s)
+{
+    SHARP_ENGINE(e.mask(LIST_BAND, 1));
+}
+void engine_op_geom(Sim& s, const double* phi)
+{
+    SHARP_ENGINE(e.geom(phi));
+}
+void engine_op_corr_add(Sim& s, double w, int S)
+{
+    SHARP_ENGINE(e.corr_add(w, S));
+}
+void engine_op_corr_apply(Sim& s, int S)
+{
+    SHARP_ENGINE(e.op_corr_apply(S));
+}
+void engine_op_axpby(Sim& s, double a1, const double* x, double a2, const double* y, double* dst)
+{
+    SHARP_ENGINE(e.op_axpby_all(a1, x, a2, y, dst));
+}
+#undef SHARP_ENGINE
 
 sim_status engine_bflux(Sim& s, double out[2][5])
 {

@@ -229,7 +229,7 @@ def test_gradient_matches_gpu_finite_differences_and_ignores_the_checkpoint_inte
     assert abs(got - want) <= 1e-6 * abs(want), (got, want)
 
 
-def test_backward_restores_the_forward_state_and_refuses_accelerated_cycles():
+def test_backward_restores_the_forward_state():
     import paper_1905_03917_amd as P
     c = AC.interface_case(20, 2)
     dt = _dt(c)
@@ -248,11 +248,6 @@ def test_backward_restores_the_forward_state_and_refuses_accelerated_cycles():
     _, c4, _ = ref.state(device=False)
     ref.close()
     assert np.max(np.abs(c3 - c4) / AC.state_scales(c4, 2)) <= 1e-10
-    m = P.Sim(c, tape=1)
-    m.advance(1e30, mode=P.SIM_MULTI_DT, max_cycles=1)
-    with pytest.raises(P.SimError):
-        m.backward(np.zeros((2, 4, c["phi"].size)))
-    m.close()
 
 
 def test_levelset_replay_argument_errors():
@@ -281,3 +276,46 @@ def test_levelset_replay_argument_errors():
     with pytest.raises(P.SimError):
         r.advance(1e30, mode=P.SIM_SINGLE_DT, max_cycles=1)
     r.close()
+
+
+def _oracle_J_multi(c, prim, gamma, pinf, log, sched, cycles, probes, rk=3):
+    from oracle import oracle as O
+    cc = dict(c, gamma=list(gamma), pinf=list(pinf))
+    s = O.OracleSim(cc, ls_replay=log, dt_replay=sched, rk=rk)
+    s.set_state(c["phi"], prim)
+    s.advance(1e30, mode=1, max_cycles=cycles)
+    _, cons, alpha = s.state()
+    return AC.interface_loss(cons, alpha, gamma, pinf, probes, c["ndim"])[0]
+
+
+@pytest.mark.parametrize("ndim,n,rk,ckpt,curved", [(1, 64, 3, 1, False), (2, 24, 3, 2, False), (2, 20, 2, 1, False),
+                                                    (2, 24, 3, 1, True), (3, 12, 3, 2, True)])
+def test_accelerated_cycles_gradient_matches_oracle_finite_differences(ndim, n, rk, ckpt, curved):
+    """accelerated cycles (Sec. 3.1): the slow fluid's interpolation, the
+    correction and the sub-stepped fast fluid reversed, against central
+    differences of the oracle's accelerated cycles replayed with its own
+    level sets and CFL steps"""
+    import paper_1905_03917_amd as P
+    from oracle import oracle as O
+    print("adjoint multi_dt case ndim=%d n=%d rk=%d ckpt=%d curved=%d" % (ndim, n, rk, ckpt, curved), flush=True)
+    c = AC.curved_case(n, ndim) if curved else AC.interface_case(n, ndim)
+    cycles = 2
+    sim = P.Sim(c, tape=1, ckpt_every=ckpt, rk=rk)
+    st = sim.advance(1e30, mode=P.SIM_MULTI_DT, max_cycles=cycles)
+    assert st["steps"][0] != st["steps"][1]          # sub-stepping took place
+    _, cons, alpha = sim.state(device=False)
+    probes = AC.interface_probes(alpha)
+    J, gc, ge_loss = AC.interface_loss(cons, alpha, c["gamma"], c["pinf"], probes, ndim)
+    gp, ge = sim.backward(gc)
+    sim.close()
+    o = O.OracleSim(c, log_levelset=1, rk=rk)
+    ost = o.advance(1e30, mode=1, max_cycles=cycles)
+    assert ost["steps"] == st["steps"]
+    log, sched = o.levelset_log(), o.schedule()
+    for seed in (7, 11):
+        dirn = AC.interface_direction(c, seed=seed)
+        want = _richardson(lambda e: _oracle_J_multi(c, c["prim"] + e * dirn, c["gamma"], c["pinf"], log, sched,
+                                                     cycles, probes, rk), 1e-3)
+        got = float(np.sum(gp * dirn))
+        print("multi direction", seed, got, want, abs(got - want) / abs(want), flush=True)
+        assert abs(got - want) <= 1e-6 * abs(want), (seed, got, want)
