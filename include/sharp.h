@@ -260,8 +260,9 @@ sim_status sim_profile(sim_t* s, int enable);
 sim_status sim_profile_read(sim_t* s, double* ms, int64_t* launches, int64_t* cells, int64_t* first_cells);
 
 /* Adjoint of the taped run (opts->tape = 1): the gradient of a scalar J
- * through every sim_advance call since the last sim_set_state, for
- * single-dt steps, with the step lengths frozen at their forward values.
+ * through every sim_advance call since the last sim_set_state (single-dt
+ * steps and, with an interface, accelerated cycles), with the step lengths
+ * frozen at their forward values.
  * The map is the composition of the Shu-Osher stages (Sec. 2.1, Sec. 3) of
  * the cut-cell finite-volume update (Eq. Eulerdiscrete: WENO5-LLF face
  * fluxes times the fluid's apertures, and the exchange term of the
@@ -275,13 +276,16 @@ sim_status sim_profile_read(sim_t* s, double* ms, int64_t* launches, int64_t* ce
  * their recorded coefficients, and the ghost values an extension starts
  * from (the previous extension's results; sim_set_state's primitives at
  * the first) are differentiated through.  A run in which one fluid fills
- * the grid has no interface and none of these steps.  The forward stores
- * the state every ckpt_every steps (with an interface: both fluids'
- * contents, the level set and the step-start interaction's results, and
- * every stage's level set); the backward replays each segment from its
- * checkpoint, every kernel on the simulation's stream, and runs the
- * reverse sweep through its stages; the gradient does not depend on
- * ckpt_every.
+ * the grid has no interface and none of these steps.  Accelerated cycles
+ * (Sec. 3.1) add the slow fluid's interpolation, Eq. (interpolation), and
+ * the interfacial flux correction, Eqs. (firstcorrection) and
+ * (secondcorrection), both linear maps of the recorded states.  The forward
+ * stores the state every ckpt_every steps or cycles (with an interface:
+ * both fluids' contents, the level set and the start interaction's
+ * results, and the level set of every stage that advances it); the
+ * backward replays each segment from its checkpoint, every kernel on the
+ * simulation's stream, and runs the reverse sweep through it; the gradient
+ * does not depend on ckpt_every.
  * Afterwards the simulation holds the state the forward ended with.
  *   g_cons[2][NV][cells]  dJ/dcons at the end of the run (input)
  *   g_prim0[2][NV][cells] dJ/dprim given to sim_set_state (output; zero for
@@ -289,16 +293,18 @@ sim_status sim_profile_read(sim_t* s, double* ms, int64_t* launches, int64_t* ce
  *   g_eos[4]              dJ/dgamma_0, dJ/dpinf_0, dJ/dgamma_1, dJ/dpinf_1
  *                         through the dynamics and the initial prim -> cons
  *                         map (host array, output; nullable)
- * Returns SIM_EINVAL when the run is not covered (accelerated cycles, a
- * rolled-back step; the message says why), SIM_ESTATE without a tape,
- * SIM_ENOMEM when the recomputation buffers (one fluid: 3 ckpt_every
- * states; with an interface: rk ckpt_every stage records of about
- * 4 NV + 2 D + 6 fields each) do not fit. */
+ * Returns SIM_EINVAL when the run is not covered (accelerated cycles of a
+ * run in which one fluid fills the grid, a rolled-back step; the message
+ * says why), SIM_ESTATE without a tape, SIM_ENOMEM when the recomputation
+ * buffers (one fluid: 3 ckpt_every states; with an interface: a record of
+ * about 4 NV + 2 D + 6 fields per interaction of ckpt_every steps or
+ * cycles) do not fit. */
 sim_status sim_backward(sim_t* s, const double* g_cons, double* g_prim0, double* g_eos, int on_device);
 
 /* The level sets a taped run with an interface recorded: after each stage
- * of each single-dt step (after the reinitialisation at a step's last
- * stage), cells values each, in stage order; the form opts.ls_replay takes.
+ * of each single-dt step and of each fast sub-step of an accelerated cycle
+ * (after the reinitialisation at a step's last stage), cells values each,
+ * in stage order; opts.ls_replay takes the single-dt ones.
  * Up to cap values are copied to the host array out, and *n (if not NULL)
  * receives the total count.  SIM_ESTATE when the simulation holds no such
  * tape. */
