@@ -427,7 +427,7 @@ def matched_l1_3d(P, WL, ladder=(64, 128, 256), t_end=3.0e-4):
                 finest_l1_distance_multi_vs_single=dist)
 
 
-def adjoint_timing(P, WL, n=512, steps=400, ckpt=20, probes=16):
+def adjoint_timing(P, WL, n=512, steps=400, ckpt=20, probes=16, multi=False):
     """The differentiable configuration: a Gaussian acoustic pulse in air
     crossing a flat air/water interface on 512^2 (zero-gradient), 400
     single-dt steps of the CFL step of the initial state, loss = sum of
@@ -435,7 +435,9 @@ def adjoint_timing(P, WL, n=512, steps=400, ckpt=20, probes=16):
     gradient with respect to the initial primitives of both fluids and the
     (gamma, p_inf) of each through sim_backward (geometry frozen at the
     recorded stage level sets, a checkpoint every 20 steps).  Reports the
-    forward (taped) and backward times."""
+    forward (taped) and backward times.  With `multi`, the same interval
+    (400 steps of that length) in accelerated cycles on the fluids' own CFL
+    steps, a checkpoint every 20 cycles."""
     import numpy as np
     import torch
     c = WL.smooth_2d(n=n, seed=0)
@@ -458,7 +460,8 @@ def adjoint_timing(P, WL, n=512, steps=400, ckpt=20, probes=16):
         eos.grad = None
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        cons = P.AdvanceFn.apply(prim, eos, c, nst * dt, dict(ckpt_every=ckpt, dt_fixed=dt))
+        o = dict(ckpt_every=ckpt, mode=P.SIM_MULTI_DT) if multi else dict(ckpt_every=ckpt, dt_fixed=dt)
+        cons = P.AdvanceFn.apply(prim, eos, c, nst * dt, o)
         J = 0.0
         for cell, k in zip(cells, side):
             U = cons[k, :, cell]
@@ -470,8 +473,10 @@ def adjoint_timing(P, WL, n=512, steps=400, ckpt=20, probes=16):
         torch.cuda.synchronize()
         t2 = time.perf_counter()
     g = prim.grad
-    return dict(workload="smooth_2d %dx%d (air pulse at a flat air/water interface), %d single-dt steps, %d probes, "
-                         "checkpoint every %d, geometry frozen at the recorded level sets" % (n, n, steps, probes, ckpt),
+    what = ("accelerated cycles over the interval of %d single-dt steps" % steps) if multi else \
+        ("%d single-dt steps" % steps)
+    return dict(workload="smooth_2d %dx%d (air pulse at a flat air/water interface), %s, %d probes, "
+                         "checkpoint every %d, geometry frozen at the recorded level sets" % (n, n, what, probes, ckpt),
                 forward_s=t1 - t0, backward_s=t2 - t1, backward_over_forward=(t2 - t1) / (t1 - t0),
                 cell_steps_per_s_backward=n * n * steps / (t2 - t1),
                 grad_norm=[float(torch.linalg.vector_norm(g[k])) for k in (0, 1)],
@@ -870,6 +875,9 @@ def main():
         adj = adjoint_timing(P, WL)
         print("bench: adjoint (512^2 air/water, 400 steps): forward %.3f s, backward %.3f s"
               % (adj["forward_s"], adj["backward_s"]), flush=True)
+        adj["multi_dt"] = adjoint_timing(P, WL, multi=True)
+        print("bench: adjoint (512^2 air/water, accelerated cycles over the same interval): forward %.3f s, "
+              "backward %.3f s" % (adj["multi_dt"]["forward_s"], adj["multi_dt"]["backward_s"]), flush=True)
     cpu = None
     if not a.no_cpu:
         cpu = cpu_baseline(a.case, 48 if D == 3 else 128, a.cpu_seconds)

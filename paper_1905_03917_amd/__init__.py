@@ -366,7 +366,8 @@ def _advance_fn():
 
         prim0: [2][NV][cells] float64 CUDA tensor; eos: (2, 2) float64 tensor
         of (gamma, p_inf) per fluid; case: workload dict (its level set);
-        t_end: end time; opts: further sim_opts fields (ckpt_every, rk, cfl).
+        t_end: end time; opts: further sim_opts fields (ckpt_every, rk, cfl),
+        and "mode" (SIM_SINGLE_DT, the default, or SIM_MULTI_DT).
         Returns cons [2][NV][cells]."""
 
         @staticmethod
@@ -375,10 +376,12 @@ def _advance_fn():
             c = {k: v for k, v in case.items() if k not in ("phi", "prim")}
             c["gamma"] = [float(e[0, 0]), float(e[1, 0])]
             c["pinf"] = [float(e[0, 1]), float(e[1, 1])]
-            sim = Sim(c, tape=1, **(opts or {}))
+            o = dict(opts or {})
+            mode = o.pop("mode", SIM_SINGLE_DT)
+            sim = Sim(c, tape=1, **o)
             phi = torch.as_tensor(np.asarray(case["phi"], dtype=np.float64), device=prim0.device)
             sim.set_state(phi, prim0.detach().contiguous())
-            sim.advance(t_end, mode=SIM_SINGLE_DT)
+            sim.advance(t_end, mode=mode)
             _, cons, _ = sim.state()
             ctx.sim = sim
             ctx.eos_device = eos.device
