@@ -37,6 +37,7 @@ class Params(C.Structure):
         ("force_cycle", C.c_int), ("no_correction", C.c_int),
         ("dt_replay", C.c_void_p), ("n_dt_replay", C.c_long),
         ("log_levelset", C.c_int), ("ls_replay", C.c_void_p), ("n_ls_replay", C.c_long),
+        ("sigma", C.c_double),
     ]
 
 
@@ -87,6 +88,7 @@ def load(path):
     L.or_weno5.argtypes = [C.c_double] * 6
     L.or_weno5.restype = C.c_double
     L.or_riemann.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double, _dp]
+    L.or_riemann_jump.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double, C.c_double, _dp]
     L.or_riemann_sample.argtypes = [_dp, _dp, C.c_double, C.c_double, C.c_double, C.c_double,
                                     C.c_double, _dp]
     L.or_clip_area.argtypes = [_dp]
@@ -104,6 +106,7 @@ def load(path):
     L.or_reinit_run.argtypes = [C.POINTER(Params), _dp]
     L.or_extend_v_run.argtypes = [C.POINTER(Params), _dp, _dp]
     L.or_extend_w_run.argtypes = [C.POINTER(Params), _dp, _dp]
+    L.or_curvature_run.argtypes = [C.POINTER(Params), _dp, _dp]
     return L
 
 
@@ -132,6 +135,7 @@ def params_from_case(case, L=None, **over):
     p.h = case["h"]
     p.gamma[0], p.gamma[1] = case["gamma"]
     p.pinf[0], p.pinf[1] = case["pinf"]
+    p.sigma = float(case.get("sigma", 0.0))
     _apply(p, over)
     return p
 
@@ -226,6 +230,15 @@ def riemann(WL, WR, gL, piL, gR, piR):
     out = np.empty(5)
     lib().or_riemann(np.asarray(WL, dtype=np.float64), np.asarray(WR, dtype=np.float64),
                      gL, piL, gR, piR, out)
+    return out
+
+
+def riemann_jump(WL, WR, gL, piL, gR, piR, jump):
+    """Riemann problem with the contact pressure jump p_L - p_R = jump:
+    {p*_L, u*, rho*_L, rho*_R, iterations}"""
+    out = np.empty(5)
+    lib().or_riemann_jump(np.asarray(WL, dtype=np.float64), np.asarray(WR, dtype=np.float64),
+                          gL, piL, gR, piR, float(jump), out)
     return out
 
 
@@ -334,3 +347,14 @@ def extend_w_run(phi, W, ndim, n, bc=0, L=None, **over):
     if L.or_extend_w_run(C.byref(p), np.ascontiguousarray(phi, dtype=np.float64).reshape(-1), out):
         raise RuntimeError("or_extend_w_run failed")
     return out.reshape(2, ndim + 2, -1)
+
+
+def curvature_run(phi, ndim, n, bc=0, L=None, **over):
+    """curvature of the level set at the interface point nearest each cell
+    centre (the one the Laplace jump takes)"""
+    L = L or lib()
+    p = _grid_params(L, ndim, n, bc, **over)
+    out = np.empty(int(n) ** ndim)
+    if L.or_curvature_run(C.byref(p), np.ascontiguousarray(phi, dtype=np.float64).reshape(-1), out):
+        raise RuntimeError("or_curvature_run failed")
+    return out

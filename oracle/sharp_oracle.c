@@ -18,6 +18,9 @@
  *     interface segment dGamma*n of each cut cell (Sec. 2.1, Sec. 2.3);
  *   - the interface exchange X from the exact two-material stiffened-gas
  *     Riemann problem, and the level-set velocity it implies (Sec. 2.3);
+ *     with surface tension, the Laplace pressure jump sigma kappa of Eq.
+ *     (surfacetension) across the contact, each fluid taking its own
+ *     interface pressure (Sec. 3.1: X_1 / X_2 = p_I1 / p_I2);
  *   - ghost-fluid extension of each fluid's state normal to the interface,
  *     level-set advection, Eq. (LS:linearadvection), and reinitialisation
  *     (Sec. 2.3);
@@ -125,36 +128,43 @@ static double star_density(const side_t* s, double ps)
     return s->rho * pow(pb / pk, 1.0 / s->g);
 }
 
-int or_riemann(const double* WL, const double* WR, double gL, double piL,
-               double gR, double piR, double* out)
+/* The contact carries the pressure jump p_L - p_R = jump (0 without surface
+ * tension): the root is p = p*_L of f_L(p) + f_R(p - jump) + (u_R - u_L) = 0,
+ * increasing in p, each side's wave function taken at its own contact
+ * pressure.  Cavitation floor: the larger of the two sides' lower bounds
+ * on p, -p_inf_L and jump - p_inf_R. */
+static int riemann_core(const double* WL, const double* WR, double gL, double piL,
+                        double gR, double piR, double jump, double* out)
 {
     side_t L = {WL[0], WL[1], WL[2], gL, piL};
     side_t R = {WR[0], WR[1], WR[2], gR, piR};
     double du = R.u - L.u, dfl, dfr;
-    double pfloor = -(piL < piR ? piL : piR);
+    double fl_lo = -piL, fr_lo = jump - piR;
+    double pfloor = fl_lo > fr_lo ? fl_lo : fr_lo;
+    double pR = R.p + jump;   /* the right side's pressure on the left side's scale */
     int it = 0;
     double p;
     /* cavitation: no positive root above the floor */
-    double fl0 = wave_f(&L, pfloor, &dfl), fr0 = wave_f(&R, pfloor, &dfr);
+    double fl0 = wave_f(&L, pfloor, &dfl), fr0 = wave_f(&R, pfloor - jump, &dfr);
     if (fl0 + fr0 + du >= 0.0) {
         p = pfloor;
     } else {
         /* start from the geometric mean of the side pressures measured from
          * the floor; a side below the floor (possible for the larger p_inf)
          * falls back to the linearised (PVRS) estimate */
-        if (L.p > pfloor && R.p > pfloor) {
-            p = pfloor + sqrt((L.p - pfloor) * (R.p - pfloor));
+        if (L.p > pfloor && pR > pfloor) {
+            p = pfloor + sqrt((L.p - pfloor) * (pR - pfloor));
         } else {
             double cL = sound(gL, piL, L.rho, L.p), cR = sound(gR, piR, R.rho, R.p);
-            p = 0.5 * (L.p + R.p) - 0.125 * du * (L.rho + R.rho) * (cL + cR);
+            p = 0.5 * (L.p + pR) - 0.125 * du * (L.rho + R.rho) * (cL + cR);
             /* the side with the smaller p_inf has p > pfloor; the other side may not */
-            double pmax = (L.p > R.p ? L.p : R.p);
+            double pmax = (L.p > pR ? L.p : pR);
             if (!(p > pfloor)) p = pfloor + 0.5 * (pmax - pfloor);
         }
         double lo = pfloor, hi = INFINITY;
-        double scale = fabs(piL) + fabs(piR) + 1e-300;
+        double scale = fabs(piL) + fabs(piR) + fabs(jump) + 1e-300;
         for (it = 1; it <= 200; it++) {
-            double f = wave_f(&L, p, &dfl) + wave_f(&R, p, &dfr) + du;
+            double f = wave_f(&L, p, &dfl) + wave_f(&R, p - jump, &dfr) + du;
             if (f > 0.0) { if (p < hi) hi = p; }
             else { if (p > lo) lo = p; }
             double pn = p - f / (dfl + dfr);
@@ -165,13 +175,25 @@ int or_riemann(const double* WL, const double* WR, double gL, double piL,
             if (fabs(dp) <= 1e-13 * (fabs(p) + scale)) break;
         }
     }
-    double fl = wave_f(&L, p, &dfl), fr = wave_f(&R, p, &dfr);
+    double fl = wave_f(&L, p, &dfl), fr = wave_f(&R, p - jump, &dfr);
     out[0] = p;
     out[1] = 0.5 * (L.u + R.u) + 0.5 * (fr - fl);
     out[2] = star_density(&L, p);
-    out[3] = star_density(&R, p);
+    out[3] = star_density(&R, p - jump);
     out[4] = (double)it;
     return 0;
+}
+
+int or_riemann(const double* WL, const double* WR, double gL, double piL,
+               double gR, double piR, double* out)
+{
+    return riemann_core(WL, WR, gL, piL, gR, piR, 0.0, out);
+}
+
+int or_riemann_jump(const double* WL, const double* WR, double gL, double piL,
+                    double gR, double piR, double jump, double* out)
+{
+    return riemann_core(WL, WR, gL, piL, gR, piR, jump, out);
 }
 
 void or_riemann_sample(const double* WL, const double* WR, double gL, double piL,
@@ -302,6 +324,7 @@ struct or_sim {
     double* alpha;        /* fluid-0 volume fraction */
     double* ap[3];        /* fluid-0 aperture of the low face (padded index) */
     double* ps;           /* interface pressure p*   (cut cells) */
+    double* pj;           /* Laplace jump sigma kappa: fluid 1's interface pressure is ps - pj */
     double* us;           /* interface normal velocity u* (cut cells) */
     double* ss[2];        /* star-state CFL speed of each fluid (cut cells) */
     double* v[3];         /* level-set velocity */
@@ -395,7 +418,7 @@ or_sim* or_create(const or_params* p)
         s->v[d] = dalloc(s->nc);
         s->vn[d] = dalloc(s->nc);
     }
-    s->ps = dalloc(s->nc); s->us = dalloc(s->nc);
+    s->ps = dalloc(s->nc); s->us = dalloc(s->nc); s->pj = dalloc(s->nc);
     s->M = (unsigned char*)calloc((size_t)s->nc, 1);
     /* finite placeholder for ghost states never reached by the extension */
     for (int k = 0; k < 2; k++)
@@ -416,7 +439,7 @@ void or_destroy(or_sim* s)
     free(s->phi); free(s->phib); free(s->phi0); free(s->phit); free(s->phih);
     free(s->alpha);
     for (int d = 0; d < 3; d++) { free(s->ap[d]); free(s->v[d]); free(s->vn[d]); }
-    free(s->ps); free(s->us); free(s->M);
+    free(s->ps); free(s->us); free(s->pj); free(s->M);
     free(s->replay); free(s->log);
     free(s->ls_rep); free(s->lslog);
     free(s);
@@ -644,6 +667,46 @@ static double grad_phi(const or_sim* s, const double* phi, long c, double* gr)
     return sqrt(g2);
 }
 
+/* Curvature of the level set for the Laplace jump of Eq. (surfacetension):
+ * kappa = div(grad phi / |grad phi|), expanded as
+ *   (|g|^2 trace(H) - g.H.g) / |g|^3
+ * with the gradient g and the Hessian H of phi by second-order central
+ * differences at the cell centre; positive where fluid 0 (phi < 0) is
+ * convex.  The cell centre lies phi from the interface: each principal
+ * curvature k of a signed distance function is k / (1 + phi k) there, so
+ * the value at the nearest interface point is taken, with the principal
+ * curvatures assumed equal (exact for circles and spheres):
+ *   kappa_I = kappa / (1 - phi kappa / (D - 1)),
+ * the denominator held at >= 1/2 where the level set is not resolved.
+ * 0 in 1-D (a point interface has no curvature) and where |g| vanishes. */
+static double curvature(const or_sim* s, const double* phi, long c)
+{
+    int D = s->D;
+    if (D < 2) return 0.0;
+    double h = s->h, g[3], H[3][3];
+    for (int d = 0; d < D; d++) {
+        double pp = phi[nbr(s, c, d, 1)], pm = phi[nbr(s, c, d, -1)];
+        g[d] = (pp - pm) / (2.0 * h);
+        H[d][d] = (pp - 2.0 * phi[c] + pm) / (h * h);
+        for (int e = d + 1; e < D; e++) {
+            double a = phi[nbr(s, nbr(s, c, d, 1), e, 1)], b = phi[nbr(s, nbr(s, c, d, 1), e, -1)];
+            double cc = phi[nbr(s, nbr(s, c, d, -1), e, 1)], dd = phi[nbr(s, nbr(s, c, d, -1), e, -1)];
+            H[d][e] = H[e][d] = (a - b - cc + dd) / (4.0 * h * h);
+        }
+    }
+    double g2 = 0.0, tr = 0.0, gHg = 0.0;
+    for (int d = 0; d < D; d++) {
+        g2 += g[d] * g[d];
+        tr += H[d][d];
+        for (int e = 0; e < D; e++) gHg += g[d] * H[d][e] * g[e];
+    }
+    if (!(g2 > 1e-24)) return 0.0;
+    double kap = (g2 * tr - gHg) / (g2 * sqrt(g2));
+    double den = 1.0 - phi[c] * kap / (double)(D - 1);
+    if (den < 0.5) den = 0.5;
+    return kap / den;
+}
+
 /* ------------------------------------------------------------------------ */
 /* Band mask of the (sub)step: a cell is in the level-set band when it or one */
 /* of its axis neighbours is closer than ls_band cells to the interface.      */
@@ -770,7 +833,7 @@ static void interaction(or_sim* s)
     for (long c = 0; c < s->nc; c++) {
         double g[3];
         double gm = interface_vec(s, c, g);
-        s->ps[c] = 0.0; s->us[c] = 0.0; s->ss[0][c] = 0.0; s->ss[1][c] = 0.0;
+        s->ps[c] = 0.0; s->us[c] = 0.0; s->ss[0][c] = 0.0; s->ss[1][c] = 0.0; s->pj[c] = 0.0;
         if (!(gm > 0.0)) continue;
         double WL[3], WR[3], un0 = 0.0, un1 = 0.0;
         for (int d = 0; d < D; d++) {
@@ -780,12 +843,17 @@ static void interaction(or_sim* s)
         WL[0] = s->W[0][c]; WL[1] = un0; WL[2] = s->W[0][(D + 1) * s->nc + c];
         WR[0] = s->W[1][c]; WR[1] = un1; WR[2] = s->W[1][(D + 1) * s->nc + c];
         double st[5];
-        or_riemann(WL, WR, s->P.gamma[0], s->P.pinf[0], s->P.gamma[1], s->P.pinf[1], st);
+        /* Laplace jump of Eq. (surfacetension): fluid 0's interface
+         * pressure exceeds fluid 1's by sigma kappa */
+        double jump = s->P.sigma != 0.0 ? s->P.sigma * curvature(s, s->phi, c) : 0.0;
+        riemann_core(WL, WR, s->P.gamma[0], s->P.pinf[0], s->P.gamma[1], s->P.pinf[1], jump, st);
         s->ps[c] = st[0];
         s->us[c] = st[1];
+        s->pj[c] = jump;
         for (int k = 0; k < 2; k++) {
             double rs = st[2 + k];
-            double cs = rs > 0.0 ? sound(s->P.gamma[k], s->P.pinf[k], rs, st[0]) : 0.0;
+            double pk = k == 0 ? st[0] : st[0] - jump;
+            double cs = rs > 0.0 ? sound(s->P.gamma[k], s->P.pinf[k], rs, pk) : 0.0;
             double sum = 0.0;
             for (int d = 0; d < D; d++) sum += (fabs(st[1] * g[d] / gm) + cs) / s->h;
             s->ss[k][c] = sum;
@@ -794,7 +862,8 @@ static void interaction(or_sim* s)
     }
 }
 
-/* exchange term of fluid k in cell c, per unit volume */
+/* exchange term of fluid k in cell c, per unit volume, at fluid k's own
+ * interface pressure (fluid 1's is lower by the Laplace jump) */
 static void exchange(const or_sim* s, int k, long c, double* Xh)
 {
     int D = s->D;
@@ -803,8 +872,9 @@ static void exchange(const or_sim* s, int k, long c, double* Xh)
     for (int q = 0; q < s->NV; q++) Xh[q] = 0.0;
     if (!(gm > 0.0)) return;
     double sg = (k == 0) ? 1.0 : -1.0;
-    for (int d = 0; d < D; d++) Xh[1 + d] = -sg * s->ps[c] * g[d];
-    Xh[D + 1] = -sg * s->ps[c] * s->us[c] * gm;
+    double p = k == 0 ? s->ps[c] : s->ps[c] - s->pj[c];
+    for (int d = 0; d < D; d++) Xh[1 + d] = -sg * p * g[d];
+    Xh[D + 1] = -sg * p * s->us[c] * gm;
 }
 
 /* Eqs. (firstcorrection)/(secondcorrection): corr += w * X_slow */
@@ -1491,6 +1561,15 @@ int or_extend_w_run(const or_params* p, const double* phi, double* W)
     for (int k = 0; k < 2; k++) memcpy(s->W[k], W + (size_t)k * s->NV * s->nc, nb);
     extend_w(s);
     for (int k = 0; k < 2; k++) memcpy(W + (size_t)k * s->NV * s->nc, s->W[k], nb);
+    or_destroy(s);
+    return 0;
+}
+
+int or_curvature_run(const or_params* p, const double* phi, double* kappa)
+{
+    or_sim* s = or_create(p);
+    if (!s) return -1;
+    for (long c = 0; c < s->nc; c++) kappa[c] = curvature(s, phi, c);
     or_destroy(s);
     return 0;
 }

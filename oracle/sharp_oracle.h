@@ -55,6 +55,9 @@ typedef struct {
                                  in or_levelset_log's order) instead of advecting and
                                  reinitialising (copied) */
     long n_ls_replay;
+    double sigma;        /* surface tension coefficient of the interface (0: none);
+                            the interaction then takes the Laplace pressure jump
+                            p_0 - p_1 = sigma kappa of Eq. (surfacetension) */
 } or_params;
 
 typedef struct {
@@ -102,6 +105,11 @@ double or_weno5(double v0, double v1, double v2, double v3, double v4, double ep
 /* exact two-material stiffened-gas Riemann problem: out = {p*, u*, rho*L, rho*R, iters} */
 int or_riemann(const double* WL, const double* WR, double gL, double piL,
                double gR, double piR, double* out);
+/* the same problem with the pressure jump p_L - p_R = jump across the
+ * contact (Eq. surfacetension): out = {p*_L, u*, rho*L, rho*R, iters}, and
+ * the right side's contact pressure is p*_L - jump */
+int or_riemann_jump(const double* WL, const double* WR, double gL, double piL,
+                    double gR, double piR, double jump, double* out);
 /* sample the exact solution at xi = x/t: out = {rho, u, p, side} */
 void or_riemann_sample(const double* WL, const double* WR, double gL, double piL,
                        double gR, double piR, double xi, double* out);
@@ -121,6 +129,9 @@ int or_ls_transport(const or_params* p, double* phi, const double* vel, double d
 int or_reinit_run(const or_params* p, double* phi);
 int or_extend_v_run(const or_params* p, const double* phi, double* v);
 int or_extend_w_run(const or_params* p, const double* phi, double* W);
+/* curvature of the level set at the interface point nearest each cell
+ * centre, kappa[cells] (0 in 1-D) */
+int or_curvature_run(const or_params* p, const double* phi, double* kappa);
 
 #ifdef __cplusplus
 }

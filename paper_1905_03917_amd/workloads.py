@@ -18,6 +18,7 @@ re-posed with stiffened-gas water gamma=4.4, p_inf=6e8 Pa and air gamma=1.4):
   smooth_2d        Gaussian acoustic pulse in air crossing a flat interface
   droplet_2d       periodic translation of a water droplet (Sec. 4.2 analogue)
   pulse_air        acoustic pulse in a grid filled by air (differentiable runs)
+  static_drop      Tait liquid drop in Tait air with surface tension (Sec. 4.3)
   batch_cases      many tubes and bubbles of uneven sizes (batched runs)
 """
 from __future__ import annotations
@@ -222,6 +223,32 @@ def e3_droplet(n=64, ndim=2):
     air = _fill(ndim, nc, dict(rho=1.2, u=u, p=1.0))
     return _case(ndim, n, 1, TAIT_WATER, (1.4, 0.0), r - 0.1, np.stack([water, air]), 10.0 * np.sqrt(10.0),
                  "e3_droplet_%dd" % ndim, radius=0.1)
+
+
+# Sec. 4.3 fluids (non-dimensional), Tait's equation with p0 = 1000 as the
+# stiffened gas p_inf = B - p0: liquid B = 5e5, gamma 7.15; air B = 100,
+# gamma 1.4 (p_inf = -900: the air holds p > 900)
+DROP_LIQUID = (7.15, 5.0e5 - 1.0e3)
+DROP_AIR = (1.4, 100.0 - 1.0e3)
+
+
+def static_drop(n=64, ndim=2, seed=0, radius=0.1, sigma=36.0, equilibrium=True, t_end=0.02):
+    """Sec. 4.3 static drop: liquid (fluid 0, rho 1000) of radius 0.1 at the
+    centre of the unit box (offset by a seeded fraction of a cell), air
+    (rho 1) outside, both at rest, surface tension sigma = 36; zero-gradient
+    boundaries.  The paper starts both fluids at p0 = 1000 and lets the drop
+    relax to the Laplace jump sigma (D - 1) / R; with `equilibrium` the drop
+    starts at that pressure, the state the relaxation ends in."""
+    h, grid = _grid(ndim, n)
+    r = _rng(seed)
+    c = [0.5 + r.uniform(-0.5, 0.5) * h for _ in range(ndim)]
+    phi = np.sqrt(sum((g - ci) ** 2 for g, ci in zip(grid, c))) - radius
+    nc = n ** ndim
+    jump = sigma * (ndim - 1) / radius if equilibrium else 0.0
+    liquid = _fill(ndim, nc, dict(rho=1000.0, p=1.0e3 + jump))
+    air = _fill(ndim, nc, dict(rho=1.0, p=1.0e3))
+    return _case(ndim, n, 0, DROP_LIQUID, DROP_AIR, phi, np.stack([liquid, air]), t_end,
+                 "static_drop_%dd" % ndim, centre=c, radius=radius, sigma=sigma)
 
 
 def wall_bubble_2d(n=64, seed=0, radius=0.2):
