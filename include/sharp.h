@@ -71,8 +71,10 @@ typedef struct {
     int bc[3];
 } sim_grid;
 
-/* Stiffened gas p = (gamma - 1) rho e - gamma p_inf (p_inf >= 0).  The
- * paper's Tait water (Sec. 2.2) is the isentrope with p_inf = B - p0. */
+/* Stiffened gas p = (gamma - 1) rho e - gamma p_inf (p_inf finite; the
+ * states must keep p + p_inf > 0).  The paper's Tait fluids (Sec. 2.2, Eq.
+ * Tait's equation) are the isentropes with p_inf = B - p0, negative where
+ * B < p0 (the gas-like fluid of Sec. 4.3). */
 typedef struct {
     double gamma;
     double pinf;
@@ -163,6 +165,21 @@ typedef struct {
                             (SIM_EINVAL for accelerated cycles, when it runs
                             out, and together with opts.tape) [NULL] */
     int64_t n_ls_replay; /* entries of ls_replay [0] */
+    double sigma;        /* surface tension coefficient of the interface
+                            (Sec. 3.1, Eq. surfacetension).  Nonzero: each cut
+                            cell's interaction takes the Laplace pressure jump
+                            p*_0 - p*_1 = sigma kappa across the contact, kappa
+                            = div(grad phi / |grad phi|) from central
+                            differences of the level set, moved to the
+                            interface point nearest the cell centre as for a
+                            circle or sphere (positive where fluid 0, phi < 0,
+                            is convex); each fluid's exchange term takes its
+                            own interface pressure, and the interfacial flux
+                            correction books the slow fluid's (Eqs.
+                            firstcorrection_surfacetension and
+                            secondcorrection_surface_tension).  No effect in
+                            1-D.  Not together with opts.tape (SIM_EINVAL)
+                            [0] */
 } sim_opts;
 
 typedef struct {
@@ -190,7 +207,7 @@ void sim_default_opts(sim_opts* o);
  * streams for the bulk-tile stages; every call joins them back into `stream`
  * before it returns, so callers see all work ordered on `stream`.
  * Requires equal spacing in every direction (h), 1 <= ndim <= 3,
- * n[d] >= 1, gamma > 1, p_inf >= 0, rk in {2, 3}.  Returns SIM_EINVAL on bad
+ * n[d] >= 1, gamma > 1, p_inf finite, rk in {2, 3}.  Returns SIM_EINVAL on bad
  * arguments, SIM_ENOMEM if device memory runs out. */
 sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts* opts,
                       void* stream, sim_t** out);

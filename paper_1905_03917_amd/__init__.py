@@ -39,7 +39,7 @@ class Opts(C.Structure):
                 ("dt_fixed", C.c_double), ("autotune", C.c_int),
                 ("graph", C.c_int), ("no_rollback", C.c_int),
                 ("grid_cap", C.c_int), ("dt_replay", C.c_void_p), ("n_dt_replay", C.c_int64),
-                ("ls_replay", C.c_void_p), ("n_ls_replay", C.c_int64)]
+                ("ls_replay", C.c_void_p), ("n_ls_replay", C.c_int64), ("sigma", C.c_double)]
 
 
 class Stats(C.Structure):
@@ -146,8 +146,9 @@ def _ptr(a):
 class Sim:
     """One two-fluid simulation on the current CUDA (HIP) device.
 
-    case: dict with ndim, n, lo, h, bc, gamma, pinf (see workloads.py), or
-    explicit keyword arguments.  Options are sim_opts fields.
+    case: dict with ndim, n, lo, h, bc, gamma, pinf and optionally sigma
+    (see workloads.py).  Options are sim_opts fields; a sigma given there
+    overrides the case's.
     """
 
     def __init__(self, case, stream=None, **opts):
@@ -164,6 +165,8 @@ class Sim:
             g.bc[d] = int(case["bc"][d]) if d < self.D else 0
         g.h = float(case["h"])
         eos = (Eos * 2)(Eos(case["gamma"][0], case["pinf"][0]), Eos(case["gamma"][1], case["pinf"][1]))
+        if "sigma" in case and "sigma" not in opts:
+            opts = dict(opts, sigma=float(case["sigma"]))
         self.opts = default_opts(**opts)
         if stream is None:
             stream = torch.cuda.current_stream()

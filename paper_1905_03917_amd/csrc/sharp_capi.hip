@@ -132,12 +132,14 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     }
     if (nc * 5 >= (1ll << 31)) { set_error("grid too large for 32-bit cell indexing"); return SIM_EINVAL; }
     for (int k = 0; k < 2; k++)
-        if (!(eos[k].gamma > 1.0) || !(eos[k].pinf >= 0.0)) { set_error("eos %d: need gamma > 1, p_inf >= 0", k); return SIM_EINVAL; }
+        if (!(eos[k].gamma > 1.0) || !std::isfinite(eos[k].pinf)) { set_error("eos %d: need gamma > 1 and a finite p_inf", k); return SIM_EINVAL; }
     sim_opts o;
     if (opts) o = *opts; else sim_default_opts(&o);
     if (o.rk != 2 && o.rk != 3) { set_error("rk must be 2 or 3"); return SIM_EINVAL; }
     if (!(o.cfl > 0.0) || o.ext_iters < 0 || o.reinit_iters < 0) { set_error("invalid options"); return SIM_EINVAL; }
     if (o.tape && o.ckpt_every < 1) { set_error("ckpt_every must be >= 1"); return SIM_EINVAL; }
+    if (!std::isfinite(o.sigma)) { set_error("sigma must be finite"); return SIM_EINVAL; }
+    if (o.tape && o.sigma != 0.0) { set_error("the adjoint does not cover surface tension (sigma != 0)"); return SIM_EINVAL; }
     if (!(o.dt_fixed >= 0.0) || !std::isfinite(o.dt_fixed)) { set_error("dt_fixed must be >= 0"); return SIM_EINVAL; }
     if (o.graph < 0 || o.graph > 2) { set_error("graph must be 0, 1 or 2 (got %d)", o.graph); return SIM_EINVAL; }
     if (o.graph && !(o.dt_fixed > 0.0)) { set_error("graph needs dt_fixed > 0"); return SIM_EINVAL; }
@@ -219,6 +221,7 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     g.extb = o.ext_band;
     g.mixb = o.mix_band;
     g.eps = o.weno_eps;
+    g.sigma = o.sigma;
     // boundary faces: two sides per direction, product of the other extents
     int off = 0;
     for (int d = 0; d < 3; d++) {
@@ -252,6 +255,8 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     A(s.alpha_alt, (size_t)g.nc);
     for (int d = 0; d < 3; d++) A(s.ap_alt[d], d < D ? (size_t)g.nfc : 1);
     A(g.ps, (size_t)g.nc); A(g.us, (size_t)g.nc);
+    // a point interface (1-D) has no curvature: no jump to keep
+    if (o.sigma != 0.0 && D > 1) A(g.pj, (size_t)g.nc);
     for (int b = 0; b < 2; b++)
         for (int d = 0; d < 3; d++) A(g.v[b][d], d < D ? (size_t)g.nc : 1);
     A(g.M, (size_t)g.nc); A(g.nearif, (size_t)g.nc);

@@ -59,6 +59,9 @@ struct Dev {
     double* ps;       // interface pressure (cut cells)
     double* us;       // interface normal velocity (cut cells)
     double* ss[2];    // star-state CFL speed per fluid (cut cells)
+    double sigma;     // surface tension coefficient (0: none)
+    double* pj;       // with sigma: Laplace jump sigma kappa per cut cell; fluid 1's
+                      // interface pressure is ps - pj (nullptr without sigma)
     double* v[2][3];  // level-set velocity, two Jacobi buffers
     uint8_t* M;       // band mask of the (sub)step
     uint8_t* nearif;  // sign change within the 3^D neighbourhood (reinit)

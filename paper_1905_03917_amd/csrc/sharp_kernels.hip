@@ -1293,10 +1293,62 @@ __global__ void __launch_bounds__(ExtWG<D>::W, 2 * ExtWG<D>::W / 256) k_extw_tb(
     b_extw_tb<D>(VB::grid(), g, list, src0, src1, in, out, iters, cur);
 }
 
-// Riemann problem of cut cell c with fluid states from Wb[.][wb], started
-// from the cell's previous p*: st = {p*, u*, rho*_0, rho*_1}
+// Laplace pressure jump sigma kappa of Eq. (surfacetension) at cut cell
+// (i, j, k): kappa = div(grad phi / |grad phi|) = (|G|^2 tr H - G.H.G) / |G|^3
+// with G and H from central differences of phi, positive where fluid 0 is
+// convex, moved from the cell centre to the nearest interface point as for
+// a circle or sphere (each principal curvature k at distance phi is
+// k / (1 + phi k)): kappa / (1 - phi kappa / (D - 1)), the denominator held
+// at >= 1/2; 0 in 1-D
 template <int D>
-__device__ __forceinline__ void interface_solve(const Dev& g, int c, const double* gv, double gm, int wb, double* st)
+__device__ __forceinline__ double laplace_jump(const Dev& g, const double* phi, int i, int j, int k)
+{
+    if constexpr (D < 2) {
+        return 0.0;
+    } else {
+        const double pc = phi[i + g.n[0] * (j + g.n[1] * k)];
+        const double h = g.h;
+        double G[D], H[D][D];
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            const int u = d == 0, v = d == 1, w = d == 2;
+            const double pp = phi[cidx(g, i + u, j + v, k + w)], pm = phi[cidx(g, i - u, j - v, k - w)];
+            G[d] = (pp - pm) / (2.0 * h);
+            H[d][d] = (pp - 2.0 * pc + pm) / (h * h);
+#pragma unroll
+            for (int e = d + 1; e < D; e++) {
+                const int a = e == 0, b = e == 1, f = e == 2;
+                const double q1 = phi[cidx(g, i + u + a, j + v + b, k + w + f)];
+                const double q2 = phi[cidx(g, i + u - a, j + v - b, k + w - f)];
+                const double q3 = phi[cidx(g, i - u + a, j - v + b, k - w + f)];
+                const double q4 = phi[cidx(g, i - u - a, j - v - b, k - w - f)];
+                H[d][e] = H[e][d] = (q1 - q2 - q3 + q4) / (4.0 * h * h);
+            }
+        }
+        double g2 = 0.0, tr = 0.0, ghg = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            g2 += G[d] * G[d];
+            tr += H[d][d];
+#pragma unroll
+            for (int e = 0; e < D; e++) ghg += G[d] * H[d][e] * G[e];
+        }
+        if (!(g2 > 1e-24)) return 0.0;
+        const double kap = (g2 * tr - ghg) / (g2 * sqrt(g2));
+        const double den = fmax(1.0 - pc * kap / (double)(D - 1), 0.5);
+        return g.sigma * (kap / den);
+    }
+}
+
+// Riemann problem of cut cell c with fluid states from Wb[.][wb], started
+// from the cell's previous p*: st = {p*, u*, rho*_0, rho*_1}.  With the
+// Laplace jump p*_0 - p*_1 = jump, fluid 1's wave curve at p - jump is that
+// of the same state with (p, p_inf) shifted by (+jump, -jump) (a stiffened
+// gas's wave curves see p only through p + p_inf and p - p_k), so the plain
+// solver takes the shifted side and p* is fluid 0's contact pressure.
+template <int D>
+__device__ __forceinline__ void interface_solve(const Dev& g, int c, const double* gv, double gm, int wb, double* st,
+                                                double jump = 0.0)
 {
     const double p0 = g.ps[c];
     const double* W0 = g.Wb[0][wb];
@@ -1307,16 +1359,18 @@ __device__ __forceinline__ void interface_solve(const Dev& g, int c, const doubl
         un1 += W1[(size_t)(1 + d) * g.nc + c] * gv[d] / gm;
     }
     Side Ls = {W0[c], un0, W0[(size_t)(D + 1) * g.nc + c], g.gam[0], g.pinf[0]};
-    Side Rs = {W1[c], un1, W1[(size_t)(D + 1) * g.nc + c], g.gam[1], g.pinf[1]};
+    Side Rs = {W1[c], un1, W1[(size_t)(D + 1) * g.nc + c] + jump, g.gam[1], g.pinf[1] - jump};
     riemann(Ls, Rs, p0, st);
 }
 
 // store the interface solution of the tile's own cut cell c (and book the
-// correction); non-cut cells get zeros
+// correction at the slow fluid's own interface pressure); non-cut cells get
+// zeros
 template <int D>
 __device__ __forceinline__ void interface_store(const Dev& g, int c, const double* gv, double gm, const double* st,
-                                                double wcorr, int S)
+                                                double wcorr, int S, double jump = 0.0)
 {
+    if (g.pj) g.pj[c] = gm > 0.0 ? jump : 0.0;
     if (!(gm > 0.0)) {
         g.ps[c] = 0.0; g.us[c] = 0.0; g.ss[0][c] = 0.0; g.ss[1][c] = 0.0;
         return;
@@ -1325,15 +1379,15 @@ __device__ __forceinline__ void interface_store(const Dev& g, int c, const doubl
     g.us[c] = st[1];
     for (int k = 0; k < 2; k++) {
         double rs = st[2 + k];
-        double cs = rs > 0.0 ? csound(g.gam[k], g.pinf[k], rs, st[0]) : 0.0;
+        double cs = rs > 0.0 ? csound(g.gam[k], g.pinf[k], rs, k == 0 ? st[0] : st[0] - jump) : 0.0;
         double sum = 0.0;
         for (int d = 0; d < D; d++) sum += (fabs(st[1] * gv[d] / gm) + cs) / g.h;
         g.ss[k][c] = sum;
     }
     if (wcorr != 0.0) {
-        double sg = S == 0 ? 1.0 : -1.0;
-        for (int d = 0; d < D; d++) g.corr[(size_t)(1 + d) * g.nc + c] += wcorr * (-sg * st[0] * gv[d]);
-        g.corr[(size_t)(D + 1) * g.nc + c] += wcorr * (-sg * st[0] * st[1] * gm);
+        double sg = S == 0 ? 1.0 : -1.0, pS = S == 0 ? st[0] : st[0] - jump;
+        for (int d = 0; d < D; d++) g.corr[(size_t)(1 + d) * g.nc + c] += wcorr * (-sg * pS * gv[d]);
+        g.corr[(size_t)(D + 1) * g.nc + c] += wcorr * (-sg * pS * st[1] * gm);
     }
 }
 
@@ -1342,7 +1396,8 @@ __device__ __forceinline__ void interface_store(const Dev& g, int c, const doubl
 // the correction share, and u* n as the source of the velocity extension;
 // the other band-mask cells get zeros
 template <int D>
-__device__ __forceinline__ void b_riemann(const VB blk, const Dev& g, int list, int wb, int vb, double wcorr, int S)
+__device__ __forceinline__ void b_riemann(const VB blk, const Dev& g, int list, int wb, int vb, double wcorr, int S,
+                                          const double* cur)
 {
     const int* L = list_ptr(g, list);
     for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
@@ -1357,15 +1412,17 @@ __device__ __forceinline__ void b_riemann(const VB blk, const Dev& g, int list, 
             continue;
         }
         double st[4];
-        interface_solve<D>(g, c, gv, gm, wb, st);
-        interface_store<D>(g, c, gv, gm, st, wcorr, S);
+        const double jump = g.pj ? laplace_jump<D>(g, cur, i, j, kk) : 0.0;
+        interface_solve<D>(g, c, gv, gm, wb, st, jump);
+        interface_store<D>(g, c, gv, gm, st, wcorr, S, jump);
         for (int e = 0; e < D; e++) g.v[vb][e][c] = st[1] * gv[e] / gm;
     }
 }
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_riemann(Dev g, int list, int wb, int vb, double wcorr, int S)
+__global__ void __launch_bounds__(SHARP_WG) k_riemann(Dev g, int list, int wb, int vb, double wcorr, int S,
+                                                      const double* cur)
 {
-    b_riemann<D>(VB::grid(), g, list, wb, vb, wcorr, S);
+    b_riemann<D>(VB::grid(), g, list, wb, vb, wcorr, S, cur);
 }
 
 // level-set velocity extension, temporally blocked: u* n of the cut cells
@@ -1485,7 +1542,8 @@ __global__ void __launch_bounds__(ExtWG<D>::V, 2 * ExtWG<D>::V / 256) k_vext_tb(
 // wcorr * X_slow into the interfacial flux correction
 // ---------------------------------------------------------------------------
 template <int D>
-__device__ __forceinline__ void b_interact(const VB blk, const Dev& g, int list, int wb, int vb, double wcorr, int S)
+__device__ __forceinline__ void b_interact(const VB blk, const Dev& g, int list, int wb, int vb, double wcorr, int S,
+                                           const double* cur)
 {
     const int* L = list_ptr(g, list);
     for (int ti = blk.b; ti < list_count(g, list); ti += blk.n) {
@@ -1496,41 +1554,21 @@ __device__ __forceinline__ void b_interact(const VB blk, const Dev& g, int list,
         double gv[3];
         double gm = iface<D>(g, i, j, kk, gv);
         if (!(gm > 0.0)) {
-            g.ps[c] = 0.0; g.us[c] = 0.0; g.ss[0][c] = 0.0; g.ss[1][c] = 0.0;
+            interface_store<D>(g, c, gv, gm, nullptr, 0.0, S);
             continue;
         }
-        const double* W0 = g.Wb[0][wb];
-        const double* W1 = g.Wb[1][wb];
-        double un0 = 0.0, un1 = 0.0;
-        for (int d = 0; d < D; d++) {
-            un0 += W0[(size_t)(1 + d) * g.nc + c] * gv[d] / gm;
-            un1 += W1[(size_t)(1 + d) * g.nc + c] * gv[d] / gm;
-        }
-        Side Ls = {W0[c], un0, W0[(size_t)(D + 1) * g.nc + c], g.gam[0], g.pinf[0]};
-        Side Rs = {W1[c], un1, W1[(size_t)(D + 1) * g.nc + c], g.gam[1], g.pinf[1]};
         double st[4];
-        riemann(Ls, Rs, g.ps[c], st);
-        g.ps[c] = st[0];
-        g.us[c] = st[1];
-        for (int k = 0; k < 2; k++) {
-            double rs = st[2 + k];
-            double cs = rs > 0.0 ? csound(g.gam[k], g.pinf[k], rs, st[0]) : 0.0;
-            double sum = 0.0;
-            for (int d = 0; d < D; d++) sum += (fabs(st[1] * gv[d] / gm) + cs) / g.h;
-            g.ss[k][c] = sum;
-        }
+        const double jump = g.pj ? laplace_jump<D>(g, cur, i, j, kk) : 0.0;
+        interface_solve<D>(g, c, gv, gm, wb, st, jump);
+        interface_store<D>(g, c, gv, gm, st, wcorr, S, jump);
         for (int d = 0; d < D; d++) g.v[vb][d][c] = st[1] * gv[d] / gm;
-        if (wcorr != 0.0) {
-            double sg = S == 0 ? 1.0 : -1.0;
-            for (int d = 0; d < D; d++) g.corr[(size_t)(1 + d) * g.nc + c] += wcorr * (-sg * st[0] * gv[d]);
-            g.corr[(size_t)(D + 1) * g.nc + c] += wcorr * (-sg * st[0] * st[1] * gm);
-        }
     }
 }
 template <int D>
-__global__ void __launch_bounds__(SHARP_WG) k_interact(Dev g, int list, int wb, int vb, double wcorr, int S)
+__global__ void __launch_bounds__(SHARP_WG) k_interact(Dev g, int list, int wb, int vb, double wcorr, int S,
+                                                       const double* cur)
 {
-    b_interact<D>(VB::grid(), g, list, wb, vb, wcorr, S);
+    b_interact<D>(VB::grid(), g, list, wb, vb, wcorr, S, cur);
 }
 
 // corr += w * X_slow from the stored interface solution (cycle start)
@@ -1546,7 +1584,7 @@ __device__ __forceinline__ void b_corr_add(const VB blk, const Dev& g, int list,
         double gv[3];
         double gm = iface<D>(g, i, j, kk, gv);
         if (!(gm > 0.0)) continue;
-        double sg = S == 0 ? 1.0 : -1.0, p = g.ps[c];
+        double sg = S == 0 ? 1.0 : -1.0, p = (S == 1 && g.pj) ? g.ps[c] - g.pj[c] : g.ps[c];
         for (int d = 0; d < D; d++) g.corr[(size_t)(1 + d) * g.nc + c] += w * (-sg * p * gv[d]);
         g.corr[(size_t)(D + 1) * g.nc + c] += w * (-sg * p * g.us[c] * gm);
     }
@@ -1903,7 +1941,7 @@ __device__ __forceinline__ void b_stage_lds(const VB blk, const Dev& g, int list
                     double gv[3];
                     double gn = iface<D>(g, i, j, 0, gv);
                     if (gn > 0.0) {
-                        double sg = k == 0 ? 1.0 : -1.0, p = g.ps[c];
+                        double sg = k == 0 ? 1.0 : -1.0, p = (k == 1 && g.pj) ? g.ps[c] - g.pj[c] : g.ps[c];
                         for (int d = 0; d < D; d++) Lr[1 + d] += -sg * p * gv[d];
                         Lr[D + 1] += -sg * p * g.us[c] * gn;
                     }
@@ -2219,7 +2257,7 @@ __device__ __forceinline__ void b_stage_lds3(const VB blk, const Dev& g, int lis
                 double gv[3];
                 double gn = iface<D>(g, i, j, kk, gv);
                 if (gn > 0.0) {
-                    double sg = k == 0 ? 1.0 : -1.0, pp = g.ps[c];
+                    double sg = k == 0 ? 1.0 : -1.0, pp = (k == 1 && g.pj) ? g.ps[c] - g.pj[c] : g.ps[c];
                     for (int e = 0; e < D; e++) Lr[1 + e] += -sg * pp * gv[e];
                     Lr[D + 1] += -sg * pp * g.us[c] * gn;
                 }
@@ -3073,10 +3111,10 @@ struct Engine {
             s.wcur ^= 1;
         }
     }
-    void interact(double wcorr, int S)
+    void interact(double wcorr, int S, const double* cur)
     {
         go<b_interact<D>, SHARP_WG>(k_interact<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, s.wcur, s.vcur,
-                                    wcorr, S);
+                                    wcorr, S, cur);
     }
     void extv(const double* cur)
     {
@@ -3132,7 +3170,7 @@ struct Engine {
         if constexpr (D <= 2) {
             if (s.o.ext_iters <= EXT_H) {
                 go<b_riemann<D>, SHARP_WG>(k_riemann<D>, grid(LIST_INNER), wg(), s.stream, g, LIST_INNER, s.wcur, s.vcur,
-                                           wcorr, S);
+                                           wcorr, S, cur);
                 if (ls_follows && fused_ls()) return;
                 go<b_vext_tb<D>, ExtWG<D>::V, 2 * ExtWG<D>::V / 256>(k_vext_tb<D>, grid(LIST_INNER), ExtWG<D>::V,
                                                                        s.stream, g, LIST_INNER, s.vcur, 1 - s.vcur,
@@ -3141,7 +3179,7 @@ struct Engine {
                 return;
             }
         }
-        interact(wcorr, S);
+        interact(wcorr, S, cur);
         if (ls_follows && ls_overlap()) {
             // the level-set chain that follows extends the velocity, beside
             // the band stage

@@ -1,0 +1,42 @@
+"""GPU path with surface tension (the Laplace jump sigma kappa of Eq.
+(surfacetension) in the interface interaction) against the CPU oracle, on the
+Sec. 4.3 static drop: relative L-infinity 1e-10 over a few steps or cycles in
+2-D and 3-D, both methods, with the tile-list grids capped so that every
+block walks several tiles; relative L1 1e-8 over longer runs, where the drop
+still holds the Laplace jump; and the refused combination with the adjoint's
+tape."""
+import numpy as np
+import pytest
+
+from paper_1905_03917_amd import workloads as WL
+from test_gpu_parity import _compare
+from test_oracle_surface_tension import drop_jump
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("ndim,n,mode,cycles,cap", [(2, 48, 0, 4, 0), (2, 64, 1, 3, 0), (2, 64, 1, 2, 8),
+                                                    (3, 24, 0, 3, 0), (3, 24, 1, 2, 0), (3, 24, 1, 2, 16)])
+def test_static_drop_matches_oracle(ndim, n, mode, cycles, cap):
+    case = WL.static_drop(n, ndim, seed=n, radius=0.1 if ndim == 2 else 0.2)
+    _compare(case, mode, cycles, gpu_opts=dict(grid_cap=cap) if cap else None)
+
+
+@pytest.mark.parametrize("mode,cycles", [(0, 40), (1, 8)])
+def test_static_drop_longer_run(mode, cycles):
+    case = WL.static_drop(64, 2, seed=1)
+    g, o, sg, so = _compare(case, mode, cycles, tol=1e-8, l1=True)
+    phi, cons, alpha = g.state(device=False)
+    jump, vmax = drop_jump(case, phi, cons, alpha)
+    print("GPU static drop: jump %.4f (Laplace 360), max speed %.3e" % (jump, vmax))
+    assert abs(jump - 360.0) <= 2e-3 * 360.0 and vmax < 2e-3, (jump, vmax)
+
+
+def test_surface_tension_refuses_the_tape():
+    import torch
+    import paper_1905_03917_amd as P
+    assert torch.cuda.is_available(), "GPU tests need a GPU"
+    case = WL.static_drop(32, 2)
+    with pytest.raises(P.SimError) as e:
+        P.Sim(case, tape=1)
+    assert e.value.status == -1
