@@ -54,6 +54,7 @@ def parse():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint timing")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-instances timing")
     ap.add_argument("--no-graph", action="store_true", help="skip the captured-steps timing")
+    ap.add_argument("--no-st", action="store_true", help="skip the surface-tension (oscillating drop) timing")
     ap.add_argument("--batch-only", action="store_true", help="only the batched-instances timing")
     ap.add_argument("--batch-no-sequential", action="store_true",
                     help="with --batch-only: skip advancing the instances one at a time")
@@ -113,7 +114,7 @@ def record_path(case, n, what):
 
 
 def bench_args(case, n):
-    return "--case %s --n %d --steps 3 --warmup 1 --no-cpu --no-2d --no-single --no-l1 --no-adjoint --no-batch --no-graph" % (case, n)
+    return "--case %s --n %d --steps 3 --warmup 1 --no-cpu --no-2d --no-single --no-l1 --no-adjoint --no-batch --no-graph --no-st" % (case, n)
 
 
 def source_digest():
@@ -572,6 +573,39 @@ def graph_timing(P, WL, steps=200):
     return res
 
 
+def surface_tension_timing(P, WL, steps=20, warmup=1):
+    """The Sec. 4.5 oscillating drop (surface tension: the Laplace jump in
+    every interaction).  At the paper's 128^2, one period (t = 0.0878) in
+    each mode from t = 0, after a warm-up run: r_s = original time /
+    accelerated time (the paper's 2.196 on its CPU is context only).  At
+    1024^2, `steps` accelerated cycles after `warmup` against the original
+    method over the same interval: cell-updates/s summed over both fluids."""
+    import torch
+    c = WL.oscillating_drop(128)
+    res = {"workload": "oscillating_drop 128x128, one period", "t_end": c["period"]}
+    w = P.Sim(c)
+    w.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=2)
+    w.advance(1.0, mode=P.SIM_SINGLE_DT, max_cycles=2)
+    w.close()
+    for mode, key in ((P.SIM_SINGLE_DT, "single_dt"), (P.SIM_MULTI_DT, "multi_dt")):
+        sim = P.Sim(c)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        st = sim.advance(c["period"], mode=mode)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        sim.close()
+        res[key] = dict(seconds=el, cycles=st["cycles"], steps=st["steps"], value=sum(st["cell_updates"]) / el)
+    res["r_s"] = res["single_dt"]["seconds"] / res["multi_dt"]["seconds"]
+    c2 = WL.oscillating_drop(1024)
+    h = time_workload(P, c2, steps, warmup)
+    res["oscillating_drop_1024"] = dict(workload="oscillating_drop 1024x1024 multi_dt", value=h["value"],
+                                        unit="cell-updates/s",
+                                        ms_per_cycle=h["seconds"] / max(h["st"]["cycles"], 1) * 1e3,
+                                        steps_per_fluid=h["st"]["steps"], single_dt=h.get("single"))
+    return res
+
+
 def paper_cases(P, WL, ladder=(32, 64, 128, 256), n3=128, frac3=0.1, skip3=False):
     """The paper's compressible cases in its TVD-RK2 scheme (Tait water as the
     stiffened gas of its isentrope): the two 1-D tubes of Sec. 4.1 at 200
@@ -860,6 +894,14 @@ def main():
         print("bench: captured steps: %s" % ", ".join("%s %.3f -> %.3f ms (%.2fx, identical %s)"
               % (r["workload"], r["launches_ms_per_step"], r["graph_ms_per_step"], r["speedup"], r["identical"])
               for r in gph), flush=True)
+    stt = None
+    if not a.no_st:
+        stt = surface_tension_timing(P, WL)
+        print("bench: oscillating drop (surface tension) 128^2 one period: single %.3f s, multi %.3f s (r_s %.2f); "
+              "1024^2: %.3e cell-updates/s, %.2f ms per cycle, single_dt speedup %.2f"
+              % (stt["single_dt"]["seconds"], stt["multi_dt"]["seconds"], stt["r_s"],
+                 stt["oscillating_drop_1024"]["value"], stt["oscillating_drop_1024"]["ms_per_cycle"],
+                 stt["oscillating_drop_1024"]["single_dt"]["speedup"]), flush=True)
     ml1 = None
     if not a.no_l1:
         ml1 = matched_l1(P, WL)
@@ -909,6 +951,7 @@ def main():
         "adjoint": adj,
         "batch": bat,
         "graph": gph,
+        "surface_tension": stt,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

@@ -19,6 +19,7 @@ re-posed with stiffened-gas water gamma=4.4, p_inf=6e8 Pa and air gamma=1.4):
   droplet_2d       periodic translation of a water droplet (Sec. 4.2 analogue)
   pulse_air        acoustic pulse in a grid filled by air (differentiable runs)
   static_drop      Tait liquid drop in Tait air with surface tension (Sec. 4.3)
+  oscillating_drop elliptic drop oscillating under surface tension (Sec. 4.5)
   batch_cases      many tubes and bubbles of uneven sizes (batched runs)
 """
 from __future__ import annotations
@@ -249,6 +250,50 @@ def static_drop(n=64, ndim=2, seed=0, radius=0.1, sigma=36.0, equilibrium=True, 
     air = _fill(ndim, nc, dict(rho=1.0, p=1.0e3))
     return _case(ndim, n, 0, DROP_LIQUID, DROP_AIR, phi, np.stack([liquid, air]), t_end,
                  "static_drop_%dd" % ndim, centre=c, radius=radius, sigma=sigma)
+
+
+def _ellipse_distance(X, Y, a, b, iters=16):
+    """signed distance to the ellipse x^2/a^2 + y^2/b^2 = 1 (negative
+    inside), from the foot point x = a cos t, y = b sin t found by Newton's
+    method on the orthogonality condition, in the first quadrant, started
+    from several angles (inside the evolute a point has several foot
+    points): the nearest one found"""
+    x, y = np.abs(X), np.abs(Y)
+    best = np.minimum(np.hypot(a - x, y), np.hypot(x, b - y))
+    starts = [np.arctan2(a * y, b * x)] + [np.full_like(x, v) for v in np.linspace(0.05, 0.5 * np.pi - 0.05, 5)]
+    for t in starts:
+        for _ in range(iters):
+            ct, st = np.cos(t), np.sin(t)
+            f = (a * a - b * b) * st * ct - a * x * st + b * y * ct
+            df = (a * a - b * b) * (ct * ct - st * st) - a * x * ct - b * y * st
+            t = np.clip(t - f / np.where(np.abs(df) > 1e-300, df, 1e-300), 0.0, 0.5 * np.pi)
+        best = np.minimum(best, np.hypot(a * np.cos(t) - x, b * np.sin(t) - y))
+    inside = (x / a) ** 2 + (y / b) ** 2 < 1.0
+    return np.where(inside, -best, best)
+
+
+# Sec. 4.5 fluids: gas B = 500, gamma 1.4; liquid B = 2e5, gamma 7.15; p0 = 1e4
+OSC_LIQUID = (7.15, 2.0e5 - 1.0e4)
+OSC_GAS = (1.4, 500.0 - 1.0e4)
+
+
+def oscillating_drop(n=128, seed=0, sigma=341.642, t_end=0.1):
+    """Sec. 4.5 drop oscillation: an elliptic liquid drop (fluid 0, rho 100,
+    semi-axes 0.2 along x and 0.12 along y) at the centre of the unit box,
+    gas (rho 1) outside, at rest at p0 = 1e4, surface tension sigma =
+    341.642; the level set is the signed distance to the ellipse (the paper
+    reinitialises its implicit function before the run).  Mode 2 of
+    Rayleigh's formula extended to two fluids, Eq. (oscillation), with the
+    paper's R = 0.15825, gives the period 0.0878."""
+    h, (X, Y) = _grid(2, n)
+    r = _rng(seed)
+    c = [0.5 + r.uniform(-0.5, 0.5) * h for _ in range(2)]
+    phi = _ellipse_distance(X - c[0], Y - c[1], 0.2, 0.12)
+    nc = n * n
+    liquid = _fill(2, nc, dict(rho=100.0, p=1.0e4))
+    gas = _fill(2, nc, dict(rho=1.0, p=1.0e4))
+    return _case(2, n, 0, OSC_LIQUID, OSC_GAS, phi, np.stack([liquid, gas]), t_end, "oscillating_drop",
+                 centre=c, sigma=sigma, period=0.0878)
 
 
 def wall_bubble_2d(n=64, seed=0, radius=0.2):

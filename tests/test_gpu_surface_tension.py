@@ -10,7 +10,7 @@ import pytest
 
 from paper_1905_03917_amd import workloads as WL
 from test_gpu_parity import _compare
-from test_oracle_surface_tension import drop_jump
+from test_oracle_surface_tension import drop_jump, drop_period
 
 pytestmark = pytest.mark.gpu
 
@@ -30,6 +30,25 @@ def test_static_drop_longer_run(mode, cycles):
     jump, vmax = drop_jump(case, phi, cons, alpha)
     print("GPU static drop: jump %.4f (Laplace 360), max speed %.3e" % (jump, vmax))
     assert abs(jump - 360.0) <= 2e-3 * 360.0 and vmax < 2e-3, (jump, vmax)
+
+
+@pytest.mark.parametrize("mode,cycles", [(0, 6), (1, 3)])
+def test_oscillating_drop_matches_oracle(mode, cycles):
+    _compare(WL.oscillating_drop(64, seed=2), mode, cycles)
+
+
+@pytest.mark.parametrize("n", [128, 256])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_oscillating_drop_period(n, mode):
+    """the Sec. 4.5 drop's period against mode 2 of Rayleigh's formula for
+    two fluids, Eq. (oscillation), which the paper evaluates to 0.0878"""
+    import paper_1905_03917_amd as P
+    case = WL.oscillating_drop(n)
+    g = P.Sim(case)
+    print("oscillating drop n=%d mode=%d" % (n, mode), flush=True)
+    T = drop_period(g, case, mode, lambda: g.state(device=False)[0])
+    print("period %.5f (Rayleigh %.4f), relative %.2e" % (T, case["period"], T / case["period"] - 1.0))
+    assert abs(T - case["period"]) <= 5e-3 * case["period"], T
 
 
 def test_surface_tension_refuses_the_tape():
