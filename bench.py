@@ -573,6 +573,43 @@ def graph_timing(P, WL, steps=200):
     return res
 
 
+def graph_cycle_timing(P, WL, cycles=40):
+    """Captured accelerated cycles (opts dt_fixed_fluid: both fluids' steps
+    prescribed, half their first CFL steps; graph=2) against the same cycles
+    issued launch by launch: the 1-D water-air tube at 400 and 4000 cells and
+    the 2-D shock-bubble at 128^2 and 512^2.  Reports ms per cycle of each,
+    the fast sub-steps per cycle, and whether both reach the same state bit
+    for bit."""
+    import torch
+    res = []
+    for name, case in (("tube_1d 400", WL.tube_1d(n=400, seed=0)),
+                       ("tube_1d 4000", WL.tube_1d(n=4000, seed=0)),
+                       ("shock_bubble_2d 128x128", WL.shock_bubble_2d(n=128, seed=0)),
+                       ("shock_bubble_2d 512x512", WL.shock_bubble_2d(n=512, seed=0))):
+        s0 = P.Sim(case)
+        dts = [0.5 * x for x in s0.advance(1.0, P.SIM_MULTI_DT, max_cycles=1)["last_dt"]]
+        s0.close()
+        row = dict(workload=name + " accelerated cycles", dt_fixed_fluid=dts, cycles=cycles)
+        states = []
+        for key, g in (("launches", 0), ("graph", 2)):
+            sim = P.Sim(case, dt_fixed_fluid=dts, graph=g)
+            sim.advance(1.0, P.SIM_MULTI_DT, max_cycles=4)     # warm-up (and the captures)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = sim.advance(1.0, P.SIM_MULTI_DT, max_cycles=cycles)
+            torch.cuda.synchronize()
+            row[key + "_ms_per_cycle"] = (time.perf_counter() - t0) / st["cycles"] * 1e3
+            row["steps_per_fluid"] = st["steps"]
+            if g:
+                row["captures"], row["replays"], _ = sim.graph_info()
+            states.append(sim.state())
+            sim.close()
+        row["speedup"] = row["launches_ms_per_cycle"] / row["graph_ms_per_cycle"]
+        row["identical"] = all(torch.equal(x, y) for x, y in zip(states[0], states[1]))
+        res.append(row)
+    return res
+
+
 def surface_tension_timing(P, WL, steps=20, warmup=1):
     """The Sec. 4.5 oscillating drop (surface tension: the Laplace jump in
     every interaction).  At the paper's 128^2, one period (t = 0.0878) in
@@ -894,6 +931,11 @@ def main():
         print("bench: captured steps: %s" % ", ".join("%s %.3f -> %.3f ms (%.2fx, identical %s)"
               % (r["workload"], r["launches_ms_per_step"], r["graph_ms_per_step"], r["speedup"], r["identical"])
               for r in gph), flush=True)
+        gph_c = graph_cycle_timing(P, WL)
+        print("bench: captured cycles: %s" % ", ".join("%s %.3f -> %.3f ms (%.2fx, identical %s)"
+              % (r["workload"], r["launches_ms_per_cycle"], r["graph_ms_per_cycle"], r["speedup"], r["identical"])
+              for r in gph_c), flush=True)
+        gph = dict(steps=gph, cycles=gph_c)
     stt = None
     if not a.no_st:
         stt = surface_tension_timing(P, WL)

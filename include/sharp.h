@@ -108,7 +108,9 @@ typedef struct {
                             and keep the fastest; results do not depend on
                             the choice [0] */
     int graph;           /* with dt_fixed > 0: capture a whole single-dt step
-                            of that length (band tiles, interaction and CFL
+                            of that length (with dt_fixed_fluid: a whole
+                            accelerated cycle, all its fast sub-steps; the same
+                            rules hold) (band tiles, interaction and CFL
                             reductions, then all stages of both fluids, level
                             set, mixing; every kernel in one chain, with no
                             side streams) into a HIP graph once per launch
@@ -180,6 +182,18 @@ typedef struct {
                             secondcorrection_surface_tension).  No effect in
                             1-D.  Not together with opts.tape (SIM_EINVAL)
                             [0] */
+    double dt_fixed_fluid[2]; /* both > 0: accelerated cycles (SIM_MULTI_DT)
+                            take these steps of fluid 0 and fluid 1 instead of
+                            their CFL steps; the cycle's plan (Sec. 3.1: the
+                            slow fluid's step, n with the 0.7 truncation, the
+                            fast sub-steps stopping at t1/2 for RK3 and at t1)
+                            follows from them as from CFL steps.  With
+                            opts.graph, every whole cycle before t_end is
+                            captured into a HIP graph once per launch
+                            configuration and replayed, without host
+                            readbacks between cycles.  Both 0 or both > 0;
+                            not together with dt_replay or tape (SIM_EINVAL)
+                            [0, 0] */
 } sim_opts;
 
 typedef struct {

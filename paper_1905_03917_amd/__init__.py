@@ -39,7 +39,8 @@ class Opts(C.Structure):
                 ("dt_fixed", C.c_double), ("autotune", C.c_int),
                 ("graph", C.c_int), ("no_rollback", C.c_int),
                 ("grid_cap", C.c_int), ("dt_replay", C.c_void_p), ("n_dt_replay", C.c_int64),
-                ("ls_replay", C.c_void_p), ("n_ls_replay", C.c_int64), ("sigma", C.c_double)]
+                ("ls_replay", C.c_void_p), ("n_ls_replay", C.c_int64), ("sigma", C.c_double),
+                ("dt_fixed_fluid", C.c_double * 2)]
 
 
 class Stats(C.Structure):
@@ -128,6 +129,9 @@ def default_opts(**over):
             setattr(o, "_%s_keep" % k, a)
             setattr(o, k, a.ctypes.data if a.size else None)
             setattr(o, "n_" + k, int(a.size))
+            continue
+        if k == "dt_fixed_fluid":
+            o.dt_fixed_fluid[0], o.dt_fixed_fluid[1] = (float(x) for x in v)
             continue
         setattr(o, k, v)
     return o

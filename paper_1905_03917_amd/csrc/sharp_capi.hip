@@ -140,9 +140,19 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     if (o.tape && o.ckpt_every < 1) { set_error("ckpt_every must be >= 1"); return SIM_EINVAL; }
     if (!std::isfinite(o.sigma)) { set_error("sigma must be finite"); return SIM_EINVAL; }
     if (o.tape && o.sigma != 0.0) { set_error("the adjoint does not cover surface tension (sigma != 0)"); return SIM_EINVAL; }
+    {
+        const double* f = o.dt_fixed_fluid;
+        const bool none = f[0] == 0.0 && f[1] == 0.0;
+        const bool both = f[0] > 0.0 && f[1] > 0.0 && std::isfinite(f[0]) && std::isfinite(f[1]);
+        if (!none && !both) { set_error("dt_fixed_fluid: both 0 or both positive and finite"); return SIM_EINVAL; }
+        if (both && (o.tape || o.n_dt_replay > 0)) { set_error("dt_fixed_fluid together with tape or dt_replay"); return SIM_EINVAL; }
+    }
     if (!(o.dt_fixed >= 0.0) || !std::isfinite(o.dt_fixed)) { set_error("dt_fixed must be >= 0"); return SIM_EINVAL; }
     if (o.graph < 0 || o.graph > 2) { set_error("graph must be 0, 1 or 2 (got %d)", o.graph); return SIM_EINVAL; }
-    if (o.graph && !(o.dt_fixed > 0.0)) { set_error("graph needs dt_fixed > 0"); return SIM_EINVAL; }
+    if (o.graph && !(o.dt_fixed > 0.0) && !(o.dt_fixed_fluid[0] > 0.0)) {
+        set_error("graph needs dt_fixed > 0 or dt_fixed_fluid");
+        return SIM_EINVAL;
+    }
     if (o.grid_cap < 0) { set_error("grid_cap must be >= 0"); return SIM_EINVAL; }
     if (o.n_dt_replay < 0 || (o.n_dt_replay > 0 && !o.dt_replay)) {
         set_error("dt_replay needs n_dt_replay >= 0 values");

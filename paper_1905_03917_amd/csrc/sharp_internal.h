@@ -200,6 +200,9 @@ struct Sim {
     struct StepGraph {
         std::vector<unsigned char> key, after;
         hipGraphExec_t exec = nullptr;
+        double adv = 0.0;              // time one replay advances
+        long long steps[2] = {0, 0};   // steps of each fluid in one replay (a cycle's)
+        double last_n = 1.0;           // the cycle's time-step ratio
     };
     static constexpr size_t MAX_GRAPHS = 4;
     std::vector<StepGraph> graphs;      // oldest first

@@ -1708,14 +1708,28 @@ __global__ void k_zero_red(Dev g)
 {
     b_zero_red(VB::grid(), g);
 }
-// accumulators of a run of captured steps (reduction words 5-7): each
-// fluid's active-cell count summed over the steps, and the step count
+// accumulators of a run of captured steps or cycles (reduction words 5-7):
+// each fluid's active-cell count summed over its steps, and the step or
+// cycle count.  `add` 0 resets them; otherwise bit k adds fluid k's count
+// of the last CFL reduction (word 2 + k) to word 5 + k, bit 2 counts a step
+// or cycle, and bit 3 keeps both counts (words 9, 10) as those at the start
+// of the last one
 __device__ __forceinline__ void b_acc(const VB blk, const Dev& g, int add)
 {
     if (threadIdx.x == 0) {
-        g.red[5] = add ? g.red[5] + g.red[2] : 0ull;
-        g.red[6] = add ? g.red[6] + g.red[3] : 0ull;
-        g.red[7] = add ? g.red[7] + 1ull : 0ull;
+        if (add == 0) {
+            g.red[5] = 0ull;
+            g.red[6] = 0ull;
+            g.red[7] = 0ull;
+            return;
+        }
+        if (add & 1) g.red[5] += g.red[2];
+        if (add & 2) g.red[6] += g.red[3];
+        if (add & 4) g.red[7] += 1ull;
+        if (add & 8) {
+            g.red[9] = g.red[2];
+            g.red[10] = g.red[3];
+        }
     }
 }
 __global__ void k_acc(Dev g, int add)
@@ -3748,12 +3762,14 @@ struct Engine {
     // only grids of at most SIM_GRAPH_MAX_CELLS cells are captured: above
     // that the side-stream overlap of the bulk stages, which the graph gives
     // up, is worth more than the launch latency it saves.
-    bool graph_run_ok() const
+    bool graph_run_ok(bool cycles = false) const
     {
         const bool size_ok = s.o.graph == 2 || (s.o.graph == 1 && (long long)g.nc <= SIM_GRAPH_MAX_CELLS);
-        return size_ok && s.o.dt_fixed > 0.0 && !s.rec && !s.prof && !s.o.tape && !replaying() &&
-               (!s.o.autotune || s.tune_cur >= Sim::NTUNE);
+        return size_ok && (cycles ? fixed_multi() : s.o.dt_fixed > 0.0) && !s.rec && !s.prof && !s.o.tape &&
+               !replaying() && (!s.o.autotune || s.tune_cur >= Sim::NTUNE);
     }
+    // accelerated cycles with prescribed steps of both fluids
+    bool fixed_multi() const { return s.o.dt_fixed_fluid[0] > 0.0 && s.o.dt_fixed_fluid[1] > 0.0; }
     static void put(std::vector<unsigned char>& v, const void* p, size_t n)
     {
         const unsigned char* b = static_cast<const unsigned char*>(p);
@@ -3805,10 +3821,30 @@ struct Engine {
         go<b_zero_red, 64>(k_zero_red, 1, 64, s.stream, g);
         cfl_launch(0, g.X[0]);
         cfl_launch(1, g.X[1]);
-        go<b_acc, 64>(k_acc, 1, 64, s.stream, g, 1);
+        go<b_acc, 64>(k_acc, 1, 64, s.stream, g, 15);
         step_single(d);
     }
-    sim_status capture_step(double d, std::vector<unsigned char>&& key)
+    // ... and of one whole accelerated cycle with the prescribed steps: the
+    // same start, then the cycle, whose fast sub-steps add the fast fluid's
+    // counts on the device instead of reading them back; cs gets the
+    // cycle's step counts
+    void graph_cycle_body(sim_stats* cs)
+    {
+        mask(LIST_CAND, 0);
+        tiles();
+        interaction(g.X[0], g.X[1], g.phiP, 0.0, 0);
+        go<b_zero_red, 64>(k_zero_red, 1, 64, s.stream, g);
+        cfl_launch(0, g.X[0]);
+        cfl_launch(1, g.X[1]);
+        go<b_acc, 64>(k_acc, 1, 64, s.stream, g, 15);
+        const long long cnt[2] = {0, 0};
+        (void)cycle(s.o.dt_fixed_fluid, cnt, INFINITY, cs);
+    }
+    // capture of the launches `body` issues (one whole step or cycle) into
+    // a graph under `key`; the graph keeps the host state after it, the
+    // time it advances and the steps each fluid takes in it
+    template <typename Body>
+    sim_status capture(std::vector<unsigned char>&& key, Body body, const char* what)
     {
         if (!s.cap_stream) SHARP_HIP(hipStreamCreateWithFlags(&s.cap_stream, hipStreamNonBlocking));
         if (s.graphs.size() >= Sim::MAX_GRAPHS) {
@@ -3831,7 +3867,10 @@ struct Engine {
         s.stream = s.cap_stream;
         s.capturing = true;
         s.run_serial = true;
-        graph_step_body(d);
+        sim_stats cs;
+        std::memset(&cs, 0, sizeof cs);
+        cycle_adv = 0.0;
+        body(&cs);
         hipGraph_t graph = nullptr;
         hipError_t e = hipSuccess;
         hipError_t e2 = hipStreamEndCapture(s.cap_stream, &graph);
@@ -3849,13 +3888,17 @@ struct Engine {
         if (graph) (void)hipGraphDestroy(graph);
         if (e != hipSuccess || e2 != hipSuccess) {
             set_step_state(before);
-            set_error("capture of a single-dt step failed: %s", hipGetErrorString(e != hipSuccess ? e : e2));
+            set_error("capture of %s failed: %s", what, hipGetErrorString(e != hipSuccess ? e : e2));
             return SIM_EDEVICE;
         }
         Sim::StepGraph sg;
         sg.key = std::move(key);
         sg.after = step_state();
         sg.exec = exec;
+        sg.adv = cycle_adv;
+        sg.steps[0] = cs.steps[0];
+        sg.steps[1] = cs.steps[1];
+        sg.last_n = cs.last_n;
         set_step_state(before);
         s.graphs.push_back(std::move(sg));
         s.graph_captures++;
@@ -3874,7 +3917,7 @@ struct Engine {
             for (size_t j = 0; j < s.graphs.size(); j++)
                 if (s.graphs[j].key == key) found = (int)j;
             if (found < 0) {
-                sim_status rc = capture_step(d, std::move(key));
+                sim_status rc = capture(std::move(key), [&](sim_stats*) { graph_step_body(d); }, "a single-dt step");
                 if (rc != SIM_OK) return rc;
                 found = (int)s.graphs.size() - 1;
             }
@@ -3909,6 +3952,57 @@ struct Engine {
         return SIM_OK;
     }
 
+    // K whole accelerated cycles with the prescribed steps, from graphs, then
+    // one readback (the cycle of Sec. 3.1 with its sub-step plan fixed by
+    // the prescribed steps: the launches of every cycle are the same)
+    sim_status graph_cycles(long long K, sim_stats* st)
+    {
+        const double* dt = s.o.dt_fixed_fluid;
+        const char tag = 'C';
+        join();
+        snap_guard(s.stream);
+        go<b_acc, 64>(k_acc, 1, 64, s.stream, g, 0);
+        int last = -1;
+        for (long long i = 0; i < K; i++) {
+            std::vector<unsigned char> key = launch_key(dt[0]);
+            put(key, &dt[1], sizeof dt[1]);
+            put(key, &tag, 1);
+            int found = -1;
+            for (size_t j = 0; j < s.graphs.size(); j++)
+                if (s.graphs[j].key == key) found = (int)j;
+            if (found < 0) {
+                sim_status rc = capture(std::move(key), [&](sim_stats* cs) { graph_cycle_body(cs); },
+                                        "an accelerated cycle");
+                if (rc != SIM_OK) return rc;
+                found = (int)s.graphs.size() - 1;
+            }
+            const Sim::StepGraph& G = s.graphs[found];
+            SHARP_HIP(hipGraphLaunch(G.exec, s.stream));
+            set_step_state(G.after);
+            s.t += G.adv;
+            for (int k = 0; k < 2; k++) st->steps[k] += G.steps[k];
+            st->last_n = G.last_n;
+            last = found;
+            s.graph_replays++;
+        }
+        sim_status rc = rb_begin(RED_WORDS, false);
+        if (rc == SIM_OK) rc = rb_wait(false);
+        if (rc == SIM_OK) rc = check_flags();
+        if (rc != SIM_OK) return rc;
+        if ((long long)s.h_red[7] != K) {
+            set_error("captured cycles: %lld of %lld ran", (long long)s.h_red[7], K);
+            return SIM_EDEVICE;
+        }
+        (void)last;
+        for (int k = 0; k < 2; k++) {
+            st->last_dt[k] = dt[k];
+            st->cell_updates[k] += (long long)s.h_red[5 + k];
+            st->active_cells[k] = (long long)s.h_red[9 + k];
+        }
+        st->cycles += K;
+        return SIM_OK;
+    }
+
     // slow fluid's intermediate state, Eq. (interpolation), mixed with the
     // current geometry unless it is the (already mixed) previous state
     MixPart interp_part(int S, double theta) const
@@ -3929,6 +4023,7 @@ struct Engine {
     }
 
     // ---- the accelerated cycle (Sec. 3.1) ----
+    double cycle_adv = 0.0;    // the time the last cycle advanced
     sim_status cycle(const double* dt, const long long* cnt, double t_end, sim_stats* st)
     {
         int ns = s.o.rk;
@@ -3954,6 +4049,7 @@ struct Engine {
                 sim_status rc = tape_step(s, dtS);
                 if (rc != SIM_OK) return rc;
             }
+            cycle_adv = dtS;
             step_single(dtS);
             st->cycles++;
             for (int k = 0; k < 2; k++) { st->steps[k]++; st->cell_updates[k] += cnt[k]; }
@@ -4015,7 +4111,8 @@ struct Engine {
         };
         // sub-steps after the first are planned on the device when every
         // kernel of a stage can take its step from there
-        const bool plan_dev = fused_ls() && s.dt_replay.empty();
+        const bool fixed = fixed_multi();
+        const bool plan_dev = fused_ls() && s.dt_replay.empty() && !fixed;
         for (;;) {
             int hh = 0, fin = 0, q0 = 0;
             double dl = 0.0;
@@ -4039,7 +4136,20 @@ struct Engine {
                     cfl_launch(F, g.X[F]);
                 }
                 fused_cfl = false;
-                if (plan_dev) {
+                if (fixed) {
+                    // prescribed steps: the reduction counts the fast fluid's
+                    // cells (summed on the device while captured)
+                    if (s.capturing) {
+                        go<b_acc, 64>(k_acc, 1, 64, s.stream, g, 1 << F);
+                    } else {
+                        double d2[2];
+                        long long c2[2];
+                        sim_status rc = readback(1 << F, d2, c2);
+                        if (rc != SIM_OK) return rc;
+                        cntF = c2[F];
+                    }
+                    dtF = dt[F];
+                } else if (plan_dev) {
                     // plan on the device, read the plan back, and enqueue the
                     // first stage before waiting for it
                     go<b_plan, 64>(k_plan, 1, 64, s.stream, g, F, tau, t1, ns, half_done, s.o.cfl, B[0], C[1]);
@@ -4104,6 +4214,7 @@ struct Engine {
         mix(S, g.X[S], g.phiP);
         join();
         s.t += t1;
+        cycle_adv = t1;
         st->cycles++;
         st->steps[S]++;
         st->cell_updates[S] += cnt[S];
@@ -4142,12 +4253,41 @@ struct Engine {
                     continue;
                 }
             }
+            if (mode == SIM_MULTI_DT && graph_run_ok(true)) {
+                // the whole cycles before t_end, from graphs
+                const double* f = s.o.dt_fixed_fluid;
+                const int S = f[0] >= f[1] ? 0 : 1;
+                double t1;
+                int single;
+                plan_cycle(f[S], f[1 - S], INFINITY, s.o.n_thr, &t1, &single);
+                long long K = 0;
+                double t = s.t;
+                while ((max_cycles <= 0 || done + K < max_cycles) && t < t_end && !(t1 > t_end - t)) {
+                    t += t1;
+                    if (t_end - t <= 1e-14 * t_end) t = t_end;
+                    K++;
+                }
+                if (K > 0) {
+                    rc = snap_begin(st);
+                    if (rc == SIM_OK) rc = graph_cycles(K, st);
+                    if (rc != SIM_OK) break;
+                    if (t_end - s.t <= 1e-14 * t_end) s.t = t_end;
+                    done += K;
+                    continue;
+                }
+            }
             double dt[2];
             long long cnt[2];
             rc = prepare(true, dt, cnt);
             if (rc != SIM_OK) break;
-            // CFL steps (not for single-dt steps of the fixed length)
-            if (!(mode == SIM_SINGLE_DT && s.o.dt_fixed > 0.0)) rc = take_cfl(3, dt);
+            // CFL steps (not for single-dt steps of the fixed length); the
+            // prescribed steps of accelerated cycles
+            if (mode == SIM_MULTI_DT && fixed_multi()) {
+                dt[0] = s.o.dt_fixed_fluid[0];
+                dt[1] = s.o.dt_fixed_fluid[1];
+            } else if (!(mode == SIM_SINGLE_DT && s.o.dt_fixed > 0.0)) {
+                rc = take_cfl(3, dt);
+            }
             if (rc != SIM_OK) break;
             rc = snap_begin(st);
             if (rc != SIM_OK) break;

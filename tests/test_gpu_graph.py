@@ -141,3 +141,103 @@ def test_graph_run_reports_a_nonphysical_state():
         else:
             assert 10 < 10 + st["cycles"] < 200 and st["t"] == pytest.approx((10 + st["cycles"]) * dt, rel=1e-12)
         s.close()
+
+
+def _first_dts(P, case, rk):
+    s = P.Sim(case, rk=rk)
+    st = s.advance(1.0, P.SIM_MULTI_DT, max_cycles=1)
+    s.close()
+    return [float(x) for x in st["last_dt"]]
+
+
+CYCLE_CASES = [("tube_1d", lambda: WL.tube_1d(n=600, seed=4), 3),
+               ("shock_bubble_2d", lambda: WL.shock_bubble_2d(n=80, seed=5), 3),
+               ("shock_bubble_2d_rk2", lambda: WL.shock_bubble_2d(n=64, seed=8), 2),
+               ("shock_droplet_3d", lambda: WL.shock_droplet_3d(n=24, seed=6), 3),
+               ("static_drop_2d", lambda: WL.static_drop(48, 2, seed=2), 3)]
+
+
+@pytest.mark.parametrize("name,make,rk", CYCLE_CASES, ids=[c[0] for c in CYCLE_CASES])
+def test_graph_cycles_match_launches_one_by_one(name, make, rk):
+    """accelerated cycles with prescribed steps (dt_fixed_fluid): captured
+    whole (graph=2) and replayed against the same cycles issued launch by
+    launch, bit for bit after every call, statistics included"""
+    torch, P = _mods()
+    case = make()
+    dts = [0.8 * x for x in _first_dts(P, case, rk)]
+    plain = P.Sim(case, rk=rk, dt_fixed_fluid=dts)
+    graph = P.Sim(case, rk=rk, dt_fixed_fluid=dts, graph=2)
+    junk = torch.zeros(1 << 20, dtype=torch.float64, device="cuda")
+    print("case", name, "rk", rk, "dt", dts, flush=True)
+    cycles = 0
+    for call, m in enumerate([1, 2, 1, 4, 3]):
+        sa = plain.advance(1e9, P.SIM_MULTI_DT, max_cycles=m)
+        sb = graph.advance(1e9, P.SIM_MULTI_DT, max_cycles=m)
+        cycles += sa["cycles"]
+        for key in ("cycles", "steps", "cell_updates", "t", "last_dt", "last_n", "bflux", "active_cells"):
+            assert np.array_equal(np.asarray(sa[key]), np.asarray(sb[key])), (name, call, key, sa[key], sb[key])
+        pa, ca, aa = plain.state()
+        pb, cb, ab = graph.state()
+        assert torch.equal(pa, pb) and torch.equal(ca, cb) and torch.equal(aa, ab), (name, call)
+        assert np.array_equal(plain.totals(), graph.totals()), (name, call)
+        junk.add_(ca.sum())
+        torch.cuda.synchronize()
+    captures, replays, held = graph.graph_info()
+    print("captures", captures, "replays", replays, "held", held, "cycles", cycles, "steps", sb["steps"], flush=True)
+    assert 1 <= captures <= replays == cycles and 1 <= held <= 4
+    plain.close()
+    graph.close()
+
+
+@pytest.mark.parametrize("mode_rk", [3, 2])
+def test_prescribed_cycles_match_oracle(mode_rk):
+    """the prescribed steps give the cycle the paper's plan computed from
+    them (Sec. 3.1): the oracle replays that schedule (both fluids' steps at
+    each cycle start, the fast fluid's at each later sub-step, from its own
+    planning functions) and reaches the captured cycles' state at the parity
+    bar"""
+    torch, P = _mods()
+    from oracle import oracle as O
+    from test_gpu_parity import _worst
+    case = WL.shock_bubble_2d(n=64, seed=9)
+    dts = [0.8 * x for x in _first_dts(P, case, mode_rk)]
+    ncyc = 3
+    g = P.Sim(case, rk=mode_rk, dt_fixed_fluid=dts, graph=2)
+    sg = g.advance(1e9, P.SIM_MULTI_DT, max_cycles=ncyc)
+    S = 0 if dts[0] >= dts[1] else 1
+    F = 1 - S
+    t1, single = O.plan_cycle(dts[S], dts[F], 1e30)
+    assert not single
+    sched = []
+    for _ in range(ncyc):
+        sched += dts
+        tau, half, first = 0.0, 0, True
+        while True:
+            if not first:
+                sched.append(dts[F])
+            d, hh, fin = O.substep(tau, t1, dts[F], mode_rk, half)
+            tau = 0.5 * t1 if hh else (t1 if fin else tau + d)
+            half = half or hh
+            first = False
+            if fin:
+                break
+    o = O.OracleSim(case, rk=mode_rk, dt_replay=sched)
+    so = o.advance(1e9, mode=1, max_cycles=ncyc)
+    assert sg["steps"] == so["steps"] and sg["cycles"] == so["cycles"], (sg, so)
+    assert sg["t"] == pytest.approx(so["t"], rel=1e-13)
+    _, cg, _ = g.state(device=False)
+    _, co, _ = o.state()
+    e, where = _worst(cg, co, 2)
+    print("captured prescribed cycles vs oracle: steps %s, worst relative %.3e at %s" % (sg["steps"], e, where))
+    assert e <= 1e-10, (e, where)
+    g.close()
+
+
+def test_prescribed_steps_refused_combinations():
+    torch, P = _mods()
+    case = WL.shock_bubble_2d(n=32, seed=1)
+    for bad in (dict(dt_fixed_fluid=[1e-6, 0.0]), dict(dt_fixed_fluid=[1e-6, 1e-6], tape=1),
+                dict(dt_fixed_fluid=[1e-6, 1e-6], dt_replay=[1e-6, 1e-6])):
+        with pytest.raises(P.SimError) as e:
+            P.Sim(case, **bad)
+        assert e.value.status == -1, bad
