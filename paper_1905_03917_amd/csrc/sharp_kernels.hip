@@ -3746,7 +3746,7 @@ struct Engine {
         s.t += dt;
     }
 
-    // ---- captured single-dt steps (o.graph) ----
+    // ---- captured single-dt steps and prescribed accelerated cycles (o.graph) ----
     // A step of the fixed length dt_fixed (its start: band tiles,
     // interaction, CFL reductions; then the stages) issues the same launches
     // whenever the host state they are made from is the same: the device
