@@ -180,8 +180,9 @@ typedef struct {
                             correction books the slow fluid's (Eqs.
                             firstcorrection_surfacetension and
                             secondcorrection_surface_tension).  No effect in
-                            1-D.  Not together with opts.tape (SIM_EINVAL)
-                            [0] */
+                            1-D.  sim_backward differentiates it with the
+                            geometry frozen (the jump of each cut cell a
+                            constant of the recorded level set) [0] */
     double dt_fixed_fluid[2]; /* both > 0: accelerated cycles (SIM_MULTI_DT)
                             take these steps of fluid 0 and fluid 1 instead of
                             their CFL steps; the cycle's plan (Sec. 3.1: the

@@ -540,17 +540,27 @@ __device__ inline double wave_partials(double rho, double ps, double gm, double 
 }
 
 // Reverse of the exchange term at every cut cell: X_0 = (0, -p* g, -p* u*
-// |g|) per unit volume, X_1 = -X_0, with g = (A_lo - A_hi)/h of fluid 0's
-// apertures (Sec. 2.1, Eq. Eulerdiscrete).  mu_k = scale lam_k; the
+// |g|) per unit volume, X_1 = -(0, -p_1 g, -p_1 u* |g|) with fluid 1's
+// interface pressure p_1 = p* - j (j the Laplace jump of Eq.
+// (surfacetension), 0 without surface tension), g = (A_lo - A_hi)/h of fluid
+// 0's apertures (Sec. 2.1, Eq. Eulerdiscrete).  mu_k = scale lam_k; the
 // primitives' adjoints Wb_k (+=) and the four EOS partials follow from
-// dp*/dtheta = -(df/dtheta)/(df/dp) at the root of f_L + f_R + u_R - u_L
-// and u* = (u_L + u_R)/2 + (f_R(p*) - f_L(p*))/2.  At the cavitation floor
-// p* = -min(p_inf) is held fixed.
+// dp*/dtheta = -(df/dtheta)/(df/dp) at the root of f_L(p) + f_R(p - j) +
+// u_R - u_L and u* = (u_L + u_R)/2 + (f_R(p* - j) - f_L(p*))/2.  With the
+// geometry frozen, j is a constant of the cut cell (from the level set phi
+// the interaction saw), and f_R(p - j) is the wave curve of fluid 1's state
+// with (p, p_inf) shifted by (+j, -j), whose partials in p and p_inf are
+// those in fluid 1's own.  At the cavitation floor p* is held fixed.
+template <int D>
+__device__ __forceinline__ double adj_jump(const Dev& g, const double* phi, int i, int j, int k)
+{
+    return (g.pj && phi) ? laplace_jump<D>(g, phi, i, j, k) : 0.0;
+}
 template <int D>
 __global__ void __launch_bounds__(ADJ_WG) k_adj2_riemann(Dev g, const double* ap, const double* W0, const double* W1,
                                                          const double* ps, const double* us, const double* lam0,
                                                          const double* lam1, double scale, double* Wb0, double* Wb1,
-                                                         double* pacc)
+                                                         double* pacc, const double* phi)
 {
     constexpr int NV = D + 2;
     double par[4] = {0.0, 0.0, 0.0, 0.0};
@@ -567,26 +577,29 @@ __global__ void __launch_bounds__(ADJ_WG) k_adj2_riemann(Dev g, const double* ap
         const double gn = sqrt(g2);
         if (!(gn > 0.0)) continue;
         const double pst = ps[c], ust = us[c];
+        const double jmp = adj_jump<D>(g, phi, i, j, kk);
         double pb = 0.0, ub = 0.0;
         for (int k = 0; k < 2; k++) {
             const double* lam = k == 0 ? lam0 : lam1;
             const double sg = k == 0 ? 1.0 : -1.0;
+            const double pk = k == 0 ? pst : pst - jmp;
             double dot = 0.0;
 #pragma unroll
             for (int d = 0; d < D; d++) dot += gv[d] * lam[(size_t)(1 + d) * g.nc + c];
             const double lE = lam[(size_t)(NV - 1) * g.nc + c];
             pb += sg * scale * (-dot - ust * gn * lE);
-            ub += sg * scale * (-pst * gn * lE);
+            ub += sg * scale * (-pk * gn * lE);
         }
         if (pb == 0.0 && ub == 0.0) continue;
         // (the wave functions depend on the normal velocities only through
         // u_R - u_L, whose partials are the sides' velocity adjoints below)
         const double r0 = W0[c], p0 = W0[(size_t)(NV - 1) * g.nc + c];
-        const double r1 = W1[c], p1 = W1[(size_t)(NV - 1) * g.nc + c];
+        const double r1 = W1[c], p1 = W1[(size_t)(NV - 1) * g.nc + c] + jmp;
+        const double pi1 = g.pinf[1] - jmp;
         double dfl, dfr, al4[4], ar4[4];
         wave_partials(r0, p0, g.gam[0], g.pinf[0], pst, &dfl, al4);
-        wave_partials(r1, p1, g.gam[1], g.pinf[1], pst, &dfr, ar4);
-        const double pfl = -(g.pinf[0] < g.pinf[1] ? g.pinf[0] : g.pinf[1]);
+        wave_partials(r1, p1, g.gam[1], pi1, pst, &dfr, ar4);
+        const double pfl = -(g.pinf[0] < pi1 ? g.pinf[0] : pi1);
         const double G = 0.5 * (dfr - dfl);
         const bool cav = !(pst > pfl);
         const double sig = cav ? 0.0 : (pb + ub * G) / (dfl + dfr);
@@ -610,13 +623,35 @@ __global__ void __launch_bounds__(ADJ_WG) k_adj2_riemann(Dev g, const double* ap
     block_add4(par, pacc);
 }
 
+// the Laplace jumps of every cut cell of the current geometry, from the
+// level set phi: what the interaction whose p*, u* a checkpoint restores
+// stored beside them (the jumps are not part of the checkpoint; the band
+// stages read them)
+template <int D>
+__global__ void __launch_bounds__(ADJ_WG) k_adj2_jump(Dev g, const double* phi)
+{
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x) {
+        int i, j, kk;
+        coords(g, c, i, j, kk);
+        double g2 = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            const double gd = (g.ap[d][fidx(g, i, j, kk)] - g.ap[d][fidx(g, i + (d == 0), j + (d == 1), kk + (d == 2))]) /
+                              g.h;
+            g2 += gd * gd;
+        }
+        g.pj[c] = g2 > 0.0 ? laplace_jump<D>(g, phi, i, j, kk) : 0.0;
+    }
+}
+
 // the exchange term's partials of one of its uses, accumulated per cut
-// cell: X_k = s_k (0, -p* g, -p* u* |g|) enters with weight `scale` against
-// the adjoint lam (a stage's (1 - a) dt, or a correction weight), s_0 = 1,
-// s_1 = -1; pb += dJ/dp*, ub += dJ/du*
+// cell: X_k = s_k (0, -p_k g, -p_k u* |g|) of fluid k (p_0 = p*, p_1 = p* -
+// j) enters with weight `scale` against the adjoint lam (a stage's (1 - a)
+// dt, or a correction weight), s_0 = 1, s_1 = -1; pb += dJ/dp*, ub += dJ/du*
 template <int D>
 __global__ void __launch_bounds__(ADJ_WG) k_adj2_xacc(Dev g, const double* ap, const double* ps, const double* us,
-                                                      const double* lam, double scale, double* pb, double* ub)
+                                                      const double* lam, double scale, double* pb, double* ub, int k,
+                                                      const double* phi)
 {
     constexpr int NV = D + 2;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < g.nc; c += gridDim.x * blockDim.x) {
@@ -635,8 +670,9 @@ __global__ void __launch_bounds__(ADJ_WG) k_adj2_xacc(Dev g, const double* ap, c
 #pragma unroll
         for (int d = 0; d < D; d++) dot += gv[d] * lam[(size_t)(1 + d) * g.nc + c];
         const double lE = lam[(size_t)(NV - 1) * g.nc + c];
+        const double pk = k == 0 ? ps[c] : ps[c] - adj_jump<D>(g, phi, i, j, kk);
         pb[c] += scale * (-dot - us[c] * gn * lE);
-        ub[c] += scale * (-ps[c] * gn * lE);
+        ub[c] += scale * (-pk * gn * lE);
     }
 }
 
@@ -645,7 +681,7 @@ __global__ void __launch_bounds__(ADJ_WG) k_adj2_xacc(Dev g, const double* ap, c
 template <int D>
 __global__ void __launch_bounds__(ADJ_WG) k_adj2_riemann2(Dev g, const double* ap, const double* W0, const double* W1,
                                                           const double* ps, const double* pbv, const double* ubv,
-                                                          double* Wb0, double* Wb1, double* pacc)
+                                                          double* Wb0, double* Wb1, double* pacc, const double* phi)
 {
     constexpr int NV = D + 2;
     double par[4] = {0.0, 0.0, 0.0, 0.0};
@@ -664,10 +700,11 @@ __global__ void __launch_bounds__(ADJ_WG) k_adj2_riemann2(Dev g, const double* a
         const double gn = sqrt(g2);
         if (!(gn > 0.0)) continue;
         const double pst = ps[c];
+        const double jmp = adj_jump<D>(g, phi, i, j, kk), pi1 = g.pinf[1] - jmp;
         double dfl, dfr, al4[4], ar4[4];
         wave_partials(W0[c], W0[(size_t)(NV - 1) * g.nc + c], g.gam[0], g.pinf[0], pst, &dfl, al4);
-        wave_partials(W1[c], W1[(size_t)(NV - 1) * g.nc + c], g.gam[1], g.pinf[1], pst, &dfr, ar4);
-        const double pfl = -(g.pinf[0] < g.pinf[1] ? g.pinf[0] : g.pinf[1]);
+        wave_partials(W1[c], W1[(size_t)(NV - 1) * g.nc + c] + jmp, g.gam[1], pi1, pst, &dfr, ar4);
+        const double pfl = -(g.pinf[0] < pi1 ? g.pinf[0] : pi1);
         const double G = 0.5 * (dfr - dfl);
         const double sig = !(pst > pfl) ? 0.0 : (pb + ub * G) / (dfl + dfr);
         const double uL = sig + 0.5 * ub, uR = -sig + 0.5 * ub;
@@ -1194,6 +1231,7 @@ struct Adjoint {
                                      s.stream));
             SHARP_HIP(hipMemcpyAsync(g.us, ck + 4 * nv + 2 * g.nc, sizeof(double) * g.nc, hipMemcpyDeviceToDevice,
                                      s.stream));
+            if (g.pj) k_adj2_jump<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, g.phiP);
             s.ls_pos = (size_t)s0 * ns;
             rec.base = store;
             rec.next = 0;
@@ -1223,7 +1261,7 @@ struct Adjoint {
                     // exchange term
                     k_adj2_riemann<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, R + rec.ap, R + rec.W[0], R + rec.W[1],
                                                                           R + rec.ps, R + rec.us, lam[0], lam[1],
-                                                                          w * dt, Wb[0][0], Wb[1][0], pacc);
+                                                                          w * dt, Wb[0][0], Wb[1][0], pacc, R + rec.phi);
                     const uint8_t* Mk = reinterpret_cast<const uint8_t*>(R + rec.M);
                     for (int k = 0; k < 2; k++) {
                         int cur = 0;
@@ -1428,6 +1466,7 @@ struct Adjoint {
             SHARP_HIP(hipMemcpyAsync(g.ps, ck + 4 * nv + nc, sizeof(double) * nc, hipMemcpyDeviceToDevice, s.stream));
             SHARP_HIP(hipMemcpyAsync(g.us, ck + 4 * nv + 2 * nc, sizeof(double) * nc, hipMemcpyDeviceToDevice,
                                      s.stream));
+            if (g.pj) k_adj2_jump<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, g.phiP);
             SHARP_HIP(hipMemsetAsync(g.corr, 0, sizeof(double) * nv, s.stream));
             s.ls_pos = s.tape_units[(size_t)u0].ls_block * ns;
             ops.clear();
@@ -1566,7 +1605,7 @@ struct Adjoint {
                     const double sg = o.k == 0 ? 1.0 : -1.0;
                     k_adj2_xacc<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, R + rec.ap, R + rec.ps, R + rec.us,
                                                                          lam[BCORR], sg * o.a, a + 2 * nv,
-                                                                         a + 2 * nv + nc);
+                                                                         a + 2 * nv + nc, o.k, R + rec.phi);
                     break;
                 }
                 case OP_STAGE: {
@@ -1585,7 +1624,8 @@ struct Adjoint {
                     k_adj_axpby<<<nb, ADJ_WG, 0, s.stream>>>((long long)nv, lam[o.in], 1.0, L, w);
                     k_adj_add<<<nb, ADJ_WG, 0, s.stream>>>((long long)nv, lam[o.in], v);
                     k_adj2_xacc<D><<<blocks(g.nc), ADJ_WG, 0, s.stream>>>(g, R + rec.ap, R + rec.ps, R + rec.us, L,
-                                                                         sg * w * o.dt, a + 2 * nv, a + 2 * nv + nc);
+                                                                         sg * w * o.dt, a + 2 * nv, a + 2 * nv + nc,
+                                                                         k, R + rec.phi);
                     break;
                 }
                 case OP_IX: {
@@ -1593,7 +1633,7 @@ struct Adjoint {
                     double* a = acc + (size_t)o.r * astride;
                     k_adj2_riemann2<D><<<ADJ_BLOCKS, ADJ_WG, 0, s.stream>>>(g, R + rec.ap, R + rec.W[0], R + rec.W[1],
                                                                            R + rec.ps, a + 2 * nv, a + 2 * nv + nc,
-                                                                           a, a + nv, pacc);
+                                                                           a, a + nv, pacc, R + rec.phi);
                     const uint8_t* Mk = reinterpret_cast<const uint8_t*>(R + rec.M);
                     const int ids[2] = {o.in, o.base};
                     for (int k = 0; k < 2; k++) {

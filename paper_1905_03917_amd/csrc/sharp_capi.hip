@@ -139,7 +139,6 @@ sim_status sim_create(const sim_grid* grid, const sim_eos eos[2], const sim_opts
     if (!(o.cfl > 0.0) || o.ext_iters < 0 || o.reinit_iters < 0) { set_error("invalid options"); return SIM_EINVAL; }
     if (o.tape && o.ckpt_every < 1) { set_error("ckpt_every must be >= 1"); return SIM_EINVAL; }
     if (!std::isfinite(o.sigma)) { set_error("sigma must be finite"); return SIM_EINVAL; }
-    if (o.tape && o.sigma != 0.0) { set_error("the adjoint does not cover surface tension (sigma != 0)"); return SIM_EINVAL; }
     {
         const double* f = o.dt_fixed_fluid;
         const bool none = f[0] == 0.0 && f[1] == 0.0;

@@ -414,6 +414,53 @@ __device__ inline void riemann(const Side& L, const Side& R, double p0, double* 
     out[3] = star_rho_w(wr, p, rzr);
 }
 
+// Laplace pressure jump sigma kappa of Eq. (surfacetension) at cut cell
+// (i, j, k): kappa = div(grad phi / |grad phi|) = (|G|^2 tr H - G.H.G) / |G|^3
+// with G and H from central differences of phi, positive where fluid 0 is
+// convex, moved from the cell centre to the nearest interface point as for
+// a circle or sphere (each principal curvature k at distance phi is
+// k / (1 + phi k)): kappa / (1 - phi kappa / (D - 1)), the denominator held
+// at >= 1/2; 0 in 1-D
+template <int D>
+__device__ __forceinline__ double laplace_jump(const Dev& g, const double* phi, int i, int j, int k)
+{
+    if constexpr (D < 2) {
+        return 0.0;
+    } else {
+        const double pc = phi[i + g.n[0] * (j + g.n[1] * k)];
+        const double h = g.h;
+        double G[D], H[D][D];
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            const int u = d == 0, v = d == 1, w = d == 2;
+            const double pp = phi[cidx(g, i + u, j + v, k + w)], pm = phi[cidx(g, i - u, j - v, k - w)];
+            G[d] = (pp - pm) / (2.0 * h);
+            H[d][d] = (pp - 2.0 * pc + pm) / (h * h);
+#pragma unroll
+            for (int e = d + 1; e < D; e++) {
+                const int a = e == 0, b = e == 1, f = e == 2;
+                const double q1 = phi[cidx(g, i + u + a, j + v + b, k + w + f)];
+                const double q2 = phi[cidx(g, i + u - a, j + v - b, k + w - f)];
+                const double q3 = phi[cidx(g, i - u + a, j - v + b, k - w + f)];
+                const double q4 = phi[cidx(g, i - u - a, j - v - b, k - w - f)];
+                H[d][e] = H[e][d] = (q1 - q2 - q3 + q4) / (4.0 * h * h);
+            }
+        }
+        double g2 = 0.0, tr = 0.0, ghg = 0.0;
+#pragma unroll
+        for (int d = 0; d < D; d++) {
+            g2 += G[d] * G[d];
+            tr += H[d][d];
+#pragma unroll
+            for (int e = 0; e < D; e++) ghg += G[d] * H[d][e] * G[e];
+        }
+        if (!(g2 > 1e-24)) return 0.0;
+        const double kap = (g2 * tr - ghg) / (g2 * sqrt(g2));
+        const double den = fmax(1.0 - pc * kap / (double)(D - 1), 0.5);
+        return g.sigma * (kap / den);
+    }
+}
+
 // ---------------------------------------------------------------------------
 // geometry of the level set (vertex = mean of the adjacent cell centres,
 // interface linear along every cell edge)

@@ -319,3 +319,76 @@ def test_accelerated_cycles_gradient_matches_oracle_finite_differences(ndim, n, 
         got = float(np.sum(gp * dirn))
         print("multi direction", seed, got, want, abs(got - want) / abs(want), flush=True)
         assert abs(got - want) <= 1e-6 * abs(want), (seed, got, want)
+
+
+def _with_sigma(c, sigma):
+    c = dict(c)
+    c["sigma"] = sigma
+    c["name"] = c["name"] + "_sigma"
+    return c
+
+
+@pytest.mark.parametrize("ndim,n", [(2, 24), (3, 12)])
+def test_gradient_with_surface_tension_matches_oracle_finite_differences(ndim, n):
+    """surface tension (Laplace jump sigma kappa in the interaction, Eq.
+    surfacetension; ~1e4 Pa on this column or droplet): with the geometry
+    frozen the jump of each cut cell is a constant of the recorded level set;
+    directions and both fluids' EOS parameters (the air's p_inf enters
+    through the jump-shifted wave curve) against central differences of the
+    oracle's replayed run"""
+    print("adjoint surface tension case ndim=%d n=%d" % (ndim, n), flush=True)
+    c = _with_sigma(AC.curved_case(n, ndim), 3.0e3)
+    steps = 6
+    r = _gradient(c, steps, ckpt=4)
+    log = _oracle_log(c, r["dt"], steps)
+    g0, p0 = list(c["gamma"]), list(c["pinf"])
+    for seed in (7, 11):
+        dirn = AC.interface_direction(c, seed=seed)
+        want = _richardson(lambda e: _oracle_J(c, c["prim"] + e * dirn, g0, p0, log, r["dt"], steps, r["probes"]),
+                           3e-3)
+        got = float(np.sum(r["gp"] * dirn))
+        print("sigma direction", seed, got, want, abs(got - want) / abs(want), flush=True)
+        assert abs(got - want) <= 1e-6 * abs(want), (seed, got, want)
+    # fluid 0 is the water (p_inf 6e8), fluid 1 the air (p_inf 0)
+    steps_eos = {(0, 0): 1e-6 * g0[0], (0, 1): 1e-6 * p0[0], (1, 0): 1e-3 * g0[1], (1, 1): 100.0}
+    for k in (0, 1):
+        rk_ = _gradient(c, steps, ckpt=4, fluid=k)
+        for j in (0, 1):
+            def Je(e, j=j):
+                g, p = list(g0), list(p0)
+                (g if j == 0 else p)[k] += e
+                return _oracle_J(c, c["prim"], g, p, log, r["dt"], steps, rk_["probes"])
+            want = _richardson(Je, steps_eos[(k, j)])
+            got = float(rk_["ge"][k, j])
+            print("sigma eos", k, j, got, want, abs(got - want) / abs(want), flush=True)
+            assert abs(got - want) <= 1e-6 * abs(want), (k, j, got, want)
+
+
+@pytest.mark.parametrize("ndim,n,ckpt", [(2, 24, 1), (3, 12, 2)])
+def test_accelerated_cycles_with_surface_tension_gradient(ndim, n, ckpt):
+    """accelerated cycles with surface tension: the correction books the slow
+    fluid's flux at its own interface pressure, reversed as such"""
+    import paper_1905_03917_amd as P
+    from oracle import oracle as O
+    print("adjoint multi_dt surface tension case ndim=%d n=%d" % (ndim, n), flush=True)
+    c = _with_sigma(AC.curved_case(n, ndim), 3.0e3)
+    cycles = 2
+    sim = P.Sim(c, tape=1, ckpt_every=ckpt)
+    st = sim.advance(1e30, mode=P.SIM_MULTI_DT, max_cycles=cycles)
+    assert st["steps"][0] != st["steps"][1]
+    _, cons, alpha = sim.state(device=False)
+    probes = AC.interface_probes(alpha)
+    J, gc, ge_loss = AC.interface_loss(cons, alpha, c["gamma"], c["pinf"], probes, ndim)
+    gp, ge = sim.backward(gc)
+    sim.close()
+    o = O.OracleSim(c, log_levelset=1)
+    ost = o.advance(1e30, mode=1, max_cycles=cycles)
+    assert ost["steps"] == st["steps"]
+    log, sched = o.levelset_log(), o.schedule()
+    for seed in (7, 11):
+        dirn = AC.interface_direction(c, seed=seed)
+        want = _richardson(lambda e: _oracle_J_multi(c, c["prim"] + e * dirn, c["gamma"], c["pinf"], log, sched,
+                                                     cycles, probes), 1e-3)
+        got = float(np.sum(gp * dirn))
+        print("sigma multi direction", seed, got, want, abs(got - want) / abs(want), flush=True)
+        assert abs(got - want) <= 1e-6 * abs(want), (seed, got, want)

@@ -3,8 +3,8 @@
 Sec. 4.3 static drop: relative L-infinity 1e-10 over a few steps or cycles in
 2-D and 3-D, both methods, with the tile-list grids capped so that every
 block walks several tiles; relative L1 1e-8 over longer runs, where the drop
-still holds the Laplace jump; and the refused combination with the adjoint's
-tape."""
+still holds the Laplace jump; the Sec. 4.5 drop's oscillation period (the
+adjoint with surface tension: tests/test_gpu_adjoint_interface.py)."""
 import numpy as np
 import pytest
 
@@ -49,13 +49,3 @@ def test_oscillating_drop_period(n, mode):
     T = drop_period(g, case, mode, lambda: g.state(device=False)[0])
     print("period %.5f (Rayleigh %.4f), relative %.2e" % (T, case["period"], T / case["period"] - 1.0))
     assert abs(T - case["period"]) <= 5e-3 * case["period"], T
-
-
-def test_surface_tension_refuses_the_tape():
-    import torch
-    import paper_1905_03917_amd as P
-    assert torch.cuda.is_available(), "GPU tests need a GPU"
-    case = WL.static_drop(32, 2)
-    with pytest.raises(P.SimError) as e:
-        P.Sim(case, tape=1)
-    assert e.value.status == -1
