@@ -49,3 +49,4 @@ def test_oscillating_drop_period(n, mode):
     T = drop_period(g, case, mode, lambda: g.state(device=False)[0])
     print("period %.5f (Rayleigh %.4f), relative %.2e" % (T, case["period"], T / case["period"] - 1.0))
     assert abs(T - case["period"]) <= 5e-3 * case["period"], T
+
