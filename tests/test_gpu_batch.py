@@ -22,6 +22,10 @@ def _cases():
     cs = WL.batch_cases(seed=3, n_tubes=3, n_bubbles=3, tube_n=(200, 700), bubble_n=(40, 96))
     cs.append(WL.shock_droplet_3d(n=20, seed=1))
     cs.append(WL.tube_1d(n=400, seed=2))
+    # instances with their own surface tension (each fused launch carries
+    # its instance's coefficient and jump buffer)
+    cs.append(WL.static_drop(40, 2, seed=1))
+    cs.append(WL.oscillating_drop(48, seed=2))
     return cs
 
 
