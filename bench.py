@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--paper-cases", action="store_true",
                     help="only the paper's own cases in its RK2 scheme: the Sec. 4.1 tubes and the Sec. 4.2 droplet "
                          "ladder (Table 1), a few minutes")
+    ap.add_argument("--paper-st", action="store_true",
+                    help="only the paper's surface-tension cases (static drop, drop oscillation) in RK2")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run a plain 1 GiB device copy (scale reference for HBM byte counters)")
     ap.add_argument("--reduce-valu", metavar="VALU_DIR",
@@ -703,6 +705,101 @@ def paper_cases(P, WL, ladder=(32, 64, 128, 256), n3=128, frac3=0.1, skip3=False
     return out
 
 
+def _drop_jump(case, cons, alpha):
+    """mean pressure of the drop's pure cells (more than 2 cells inside)
+    minus that of the pure gas cells from 2 cells outside to 3 radii"""
+    import numpy as np
+    D, n = case["ndim"], case["n"][0]
+    h = case["h"]
+    x = (np.arange(n) + 0.5) * h
+    grids = np.meshgrid(*([x] * D), indexing="ij")
+    r = np.sqrt(sum((grids[D - 1 - d] - case["centre"][d]) ** 2 for d in range(D))).reshape(-1)
+    R = case["radius"]
+    p = []
+    for k in range(2):
+        a = alpha if k == 0 else 1.0 - alpha
+        m = a > 0.5
+        U = cons[k][:, m] / a[m]
+        ke = 0.5 * sum(U[1 + d] ** 2 for d in range(D)) / U[0]
+        pk = np.full(alpha.shape, np.nan)
+        pk[m] = (case["gamma"][k] - 1.0) * (U[D + 1] - ke) - case["gamma"][k] * case["pinf"][k]
+        p.append(pk)
+    inner = (alpha > 1.0 - 1e-9) & (r < R - 2.0 * h)
+    outer = (alpha < 1e-9) & (r > R + 2.0 * h) & (r < 3.0 * R)
+    return float(p[0][inner].mean() - p[1][outer].mean())
+
+
+def paper_st_cases(P, WL, ladder=(32, 64, 128, 256), t_drop=0.05):
+    """The paper's surface-tension cases in its TVD-RK2 scheme: the Sec. 4.3
+    static drop (started at its Laplace equilibrium; the inviscid run from
+    the paper's uniform start does not settle) to t = t_drop on 32^2 ..
+    256^2, timed in both modes (r_s beside Table 2 as context), with the
+    relative error of the mean pressure jump against sigma/R = 360; and the
+    Sec. 4.5 drop oscillation at 128^2: its period (the extent along x
+    through the centre, first minimum, twice its time) against the 0.0878
+    of Eq. (oscillation), and r_s over one period."""
+    import numpy as np
+    import torch
+    out = dict(static_drop=[], oscillating_drop=None)
+    table2 = {32: 1.595, 64: 2.153, 128: 2.531, 256: 3.1048}
+    for n in ladder:
+        c = WL.static_drop(n, 2)
+        row = dict(grid="%dx%d" % (n, n), t_end=t_drop)
+        for mode in (0, 1):
+            s = P.Sim(c, rk=2)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            st = s.advance(t_drop, mode=mode)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            _, cons, alpha = s.state(device=False)
+            s.close()
+            key = "multi" if mode else "single"
+            row["seconds_" + key] = el
+            row["steps_" + key] = st["steps"]
+            row["jump_error_" + key] = abs(_drop_jump(c, cons, alpha) - 360.0) / 360.0
+        row["r_s"] = row["seconds_single"] / row["seconds_multi"]
+        row["paper_r_s"] = table2[n]
+        out["static_drop"].append(row)
+        print("bench: paper static drop %s: single %.2f s, multi %.2f s, r_s %.2f (paper, CPU: %.3f), "
+              "E(dp) %.2e / %.2e" % (row["grid"], row["seconds_single"], row["seconds_multi"], row["r_s"],
+                                     row["paper_r_s"], row["jump_error_single"], row["jump_error_multi"]), flush=True)
+    c = WL.oscillating_drop(128)
+    h = c["h"]
+    j0 = int(round(c["centre"][1] / h - 0.5))
+    row = dict(grid="128x128", paper_period=c["period"], paper_r_s=2.196)
+    for mode in (0, 1):
+        key = "multi" if mode else "single"
+        s = P.Sim(c, rk=2)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        s.advance(c["period"], mode=mode)
+        torch.cuda.synchronize()
+        row["seconds_" + key] = time.perf_counter() - t0
+        s.close()
+        s = P.Sim(c, rk=2)
+        ts, ext = [], []
+        while True:
+            st = s.advance(1e30, mode=mode, max_cycles=1)
+            rw = s.state(device=False)[0].reshape(128, 128)[j0]
+            i = np.where((rw[:-1] >= 0) != (rw[1:] >= 0))[0]
+            i = i[i >= 64][0]
+            ts.append(st["t"])
+            ext.append((i + 0.5 + rw[i] / (rw[i] - rw[i + 1])) * h - c["centre"][0])
+            if st["t"] > 0.055:
+                break
+        s.close()
+        k = int(np.argmin(ext))
+        A = np.polyfit(np.array(ts[k - 1:k + 2]) - ts[k], ext[k - 1:k + 2], 2)
+        row["period_" + key] = 2.0 * (ts[k] - A[1] / (2.0 * A[0]))
+    row["r_s"] = row["seconds_single"] / row["seconds_multi"]
+    out["oscillating_drop"] = row
+    print("bench: paper oscillating drop 128^2: period %.5f / %.5f (0.0878), single %.2f s, multi %.2f s, r_s %.2f "
+          "(paper, CPU: 2.196)" % (row["period_single"], row["period_multi"], row["seconds_single"],
+                                   row["seconds_multi"], row["r_s"]), flush=True)
+    return out
+
+
 def cpu_worker(case_name, n, seconds):
     """(child process) the oracle as it is, on one thread: accelerated cycles
     of the workload at n cells per direction for about `seconds`"""
@@ -883,6 +980,9 @@ def main():
         return
     if a.paper_cases:
         print(json.dumps({"paper_cases": paper_cases(P, WL)}), flush=True)
+        return
+    if a.paper_st:
+        print(json.dumps({"paper_st_cases": paper_st_cases(P, WL)}), flush=True)
         return
     if a.copy_probe:
         # a device-to-device copy of exactly 1 GiB read + 1 GiB written; a

@@ -50,3 +50,26 @@ def test_oscillating_drop_period(n, mode):
     print("period %.5f (Rayleigh %.4f), relative %.2e" % (T, case["period"], T / case["period"] - 1.0))
     assert abs(T - case["period"]) <= 5e-3 * case["period"], T
 
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_static_drop_jump_converges(mode):
+    """Sec. 4.3 in the paper's TVD-RK2: the relative error of the drop's
+    mean pressure jump against sigma/R = 360 after t = 0.05 (from the
+    Laplace equilibrium) falls under refinement at nearly second order, as
+    the paper reports for its runs"""
+    import paper_1905_03917_amd as P
+    errs = []
+    for n in (32, 64, 128, 256):
+        case = WL.static_drop(n, 2)
+        g = P.Sim(case, rk=2)
+        g.advance(0.05, mode=mode)
+        phi, cons, alpha = g.state(device=False)
+        g.close()
+        jump, vmax = drop_jump(case, phi, cons, alpha)
+        errs.append(abs(jump - 360.0) / 360.0)
+        print("n %d mode %d: jump %.5f E %.3e max speed %.2e" % (n, mode, jump, errs[-1], vmax), flush=True)
+    order = np.log2(errs[0] / errs[-1]) / 3.0
+    print("mean order %.2f" % order)
+    assert all(b < a for a, b in zip(errs, errs[1:])), errs
+    assert order > 1.3 and errs[-1] < 2e-4, (order, errs)
