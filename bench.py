@@ -579,7 +579,7 @@ def graph_cycle_timing(P, WL, cycles=40):
     """Captured accelerated cycles (opts dt_fixed_fluid: both fluids' steps
     prescribed, half their first CFL steps; graph=2) against the same cycles
     issued launch by launch: the 1-D water-air tube at 400 and 4000 cells and
-    the 2-D shock-bubble at 128^2 and 512^2.  Reports ms per cycle of each,
+    the 2-D shock-bubble at 128^2, 256^2 and 512^2.  Reports ms per cycle of each,
     the fast sub-steps per cycle, and whether both reach the same state bit
     for bit."""
     import torch
@@ -587,6 +587,7 @@ def graph_cycle_timing(P, WL, cycles=40):
     for name, case in (("tube_1d 400", WL.tube_1d(n=400, seed=0)),
                        ("tube_1d 4000", WL.tube_1d(n=4000, seed=0)),
                        ("shock_bubble_2d 128x128", WL.shock_bubble_2d(n=128, seed=0)),
+                       ("shock_bubble_2d 256x256", WL.shock_bubble_2d(n=256, seed=0)),
                        ("shock_bubble_2d 512x512", WL.shock_bubble_2d(n=512, seed=0))):
         s0 = P.Sim(case)
         dts = [0.5 * x for x in s0.advance(1.0, P.SIM_MULTI_DT, max_cycles=1)["last_dt"]]

@@ -47,6 +47,10 @@ extern "C" {
  * 512^2, where a captured step of the 2-D shock-bubble case still measured
  * 1.01x the launches it replaces (1.5x on a 400-cell tube). */
 #define SIM_GRAPH_MAX_CELLS 262144
+/* ... and accelerated cycles with prescribed steps (opts->dt_fixed_fluid):
+ * 256^2, where a captured cycle of the shock-bubble case measured 1.04x
+ * (0.95x at 512^2, 1.37x on a 400-cell tube). */
+#define SIM_GRAPH_MAX_CELLS_CYCLE 65536
 
 typedef struct sim sim_t;
 
@@ -127,7 +131,8 @@ typedef struct {
                             SIM_GRAPH_MAX_CELLS cells (measured faster up to
                             there; on larger grids the bulk stages overlapped
                             on side streams win and the steps are issued one
-                            by one); 2: capture at any size [0] */
+                            by one; SIM_GRAPH_MAX_CELLS_CYCLE cells for
+                            accelerated cycles); 2: capture at any size [0] */
     int no_rollback;     /* do not keep the state of the last cycle start: a
                             call that fails with SIM_ENONPHYS then leaves the
                             state of the failing step instead of rolling it

@@ -18,6 +18,7 @@ LIB_PATH = os.path.join(_HERE, "libsharp_hip.so")
 
 SIM_SINGLE_DT = 0
 SIM_GRAPH_MAX_CELLS = 262144     # largest grid opts graph=1 captures (graph=2: any size)
+SIM_GRAPH_MAX_CELLS_CYCLE = 65536    # ... for accelerated cycles with prescribed steps
 SIM_MULTI_DT = 1
 
 

@@ -3712,12 +3712,14 @@ struct Engine {
     // replaces).  A run of whole steps is enqueued without waiting for any of
     // them: the active-cell counts are summed on the device and read back,
     // with the error flags, once at the end of the run.  Under graph = 1
-    // only grids of at most SIM_GRAPH_MAX_CELLS cells are captured: above
+    // only grids of at most SIM_GRAPH_MAX_CELLS cells (accelerated cycles:
+    // SIM_GRAPH_MAX_CELLS_CYCLE) are captured: above
     // that the side-stream overlap of the bulk stages, which the graph gives
     // up, is worth more than the launch latency it saves.
     bool graph_run_ok(bool cycles = false) const
     {
-        const bool size_ok = s.o.graph == 2 || (s.o.graph == 1 && (long long)g.nc <= SIM_GRAPH_MAX_CELLS);
+        const long long cap = cycles ? SIM_GRAPH_MAX_CELLS_CYCLE : SIM_GRAPH_MAX_CELLS;
+        const bool size_ok = s.o.graph == 2 || (s.o.graph == 1 && (long long)g.nc <= cap);
         return size_ok && (cycles ? fixed_multi() : s.o.dt_fixed > 0.0) && !s.rec && !s.prof && !s.o.tape &&
                !replaying() && (!s.o.autotune || s.tune_cur >= Sim::NTUNE);
     }

@@ -241,3 +241,21 @@ def test_prescribed_steps_refused_combinations():
         with pytest.raises(P.SimError) as e:
             P.Sim(case, **bad)
         assert e.value.status == -1, bad
+
+
+def test_graph_cycle_size_gate():
+    """graph=1 captures accelerated cycles only on grids of at most
+    SIM_GRAPH_MAX_CELLS_CYCLE cells, graph=2 at any size; all give the
+    launches' state"""
+    torch, P = _mods()
+    case = WL.tube_1d(n=P.SIM_GRAPH_MAX_CELLS_CYCLE + 1, seed=2)
+    dts = [0.5 * x for x in _first_dts(P, case, 3)]
+    sims = [P.Sim(case, dt_fixed_fluid=dts, graph=g) for g in (0, 1, 2)]
+    for s in sims:
+        s.advance(1e9, P.SIM_MULTI_DT, max_cycles=3)
+    assert sims[1].graph_info()[0] == 0 and sims[2].graph_info()[0] >= 1
+    ref = sims[0].state()
+    for s in sims[1:]:
+        assert all(torch.equal(x, y) for x, y in zip(ref, s.state()))
+    for s in sims:
+        s.close()
