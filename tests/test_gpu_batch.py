@@ -201,3 +201,26 @@ def test_full_size_batch_samples():
     b.close()
     for s in sims:
         s.close()
+
+
+def test_batch_with_prescribed_steps():
+    """accelerated cycles with prescribed steps (dt_fixed_fluid: no CFL
+    steps, the cycle plan fixed) in a batch, against the same simulations
+    advanced alone"""
+    torch, P = _mods()
+    cases = [WL.tube_1d(n=500, seed=6), WL.shock_bubble_2d(n=56, seed=6), WL.static_drop(40, 2, seed=3)]
+    dts = []
+    for c in cases:
+        s = P.Sim(c)
+        dts.append([0.6 * x for x in s.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=1)["last_dt"]])
+        s.close()
+    alone = [P.Sim(c, dt_fixed_fluid=d) for c, d in zip(cases, dts)]
+    st_alone = [s.advance(1.0, mode=P.SIM_MULTI_DT, max_cycles=4) for s in alone]
+    sims = [P.Sim(c, dt_fixed_fluid=d) for c, d in zip(cases, dts)]
+    b = P.Batch(sims)
+    st_b = b.advance(np.ones(len(cases)), mode=P.SIM_MULTI_DT, max_cycles=4)
+    for i in range(len(cases)):
+        _stats_equal(st_b[i], st_alone[i], cases[i]["name"], alone[i].totals())
+        print("%s: batched vs alone with prescribed steps, worst relative difference %.2e"
+              % (cases[i]["name"], _same(sims[i], alone[i], cases[i]["name"])), flush=True)
+    b.close()
