@@ -101,7 +101,8 @@ typedef struct {
     int serial;          /* run every kernel on the simulation's stream instead of
                             overlapping the bulk-tile stages with the band work on
                             two library-owned streams; results are identical [0] */
-    int tape;            /* record single-dt steps for sim_backward [0] */
+    int tape;            /* record the run (single-dt steps and, with an
+                            interface, accelerated cycles) for sim_backward [0] */
     int ckpt_every;      /* taped steps between stored states (checkpoints) [20] */
     double dt_fixed;     /* > 0: single-dt steps of this length (the last one
                             clamped to t_end) instead of the CFL step, so that
@@ -309,7 +310,9 @@ sim_status sim_profile_read(sim_t* s, double* ms, int64_t* launches, int64_t* ce
  * frozen: every stage's level set is the recorded one (see
  * opts.ls_replay), so the derivative is that of the replayed run; the
  * exchange term's p*, u* are differentiated by the implicit function
- * theorem on the Riemann root; extension and mixing are linear maps with
+ * theorem on the Riemann root (with surface tension, opts.sigma, across the
+ * Laplace jump of the recorded level set, a constant of each cut cell);
+ * extension and mixing are linear maps with
  * their recorded coefficients, and the ghost values an extension starts
  * from (the previous extension's results; sim_set_state's primitives at
  * the first) are differentiated through.  A run in which one fluid fills
