@@ -41,7 +41,7 @@ def parse():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--n", type=int, default=None, help="cells per direction (default 256 in 3-D, 1024 in 2-D)")
-    ap.add_argument("--case", default="shock_droplet_3d", choices=["shock_bubble_2d", "shock_droplet_3d"],
+    ap.add_argument("--case", default="shock_droplet_3d", choices=["shock_bubble_2d", "shock_droplet_3d", "oscillating_drop", "static_drop"],
                     help="workload of the timed cycles (the headline line is shock_droplet_3d at 256^3)")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-2d", action="store_true", help="skip the 1024^2 shock-bubble leg")
