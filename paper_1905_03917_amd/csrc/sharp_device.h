@@ -392,6 +392,14 @@ __device__ inline void riemann(const Side& L, const Side& R, double p0, double* 
         if (f > 0.0) { if (p < hi) hi = p; }
         else { if (p > lo) lo = p; }
         double pn = p - f / (dfl + dfr);
+        if (fabs(pn - p) <= 1e-13 * (fabs(p) + scale)) {
+            // converged: a step this small can fall below the rounding of p
+            // (pn == p == lo), which the bracket test below would take for
+            // a step out of the bracket and answer with a bisection away
+            // from the root
+            if (pn > lo && pn < hi) p = pn;
+            break;
+        }
         if (!(pn > lo && pn < hi)) {
             if (!floor_known && !(pn > lo) && lo == pfloor) {
                 floor_known = true;
